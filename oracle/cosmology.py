@@ -1,0 +1,89 @@
+"""Background cosmology for the oracle (flat LambdaCDM, radiation neglected).
+
+Units: time in 1/H0, scale factor a (a=1 today), wavenumbers in h/Mpc where a power
+spectrum is involved.
+
+Sec. 2.1 sets the initial conditions from an analytic matter transfer function; the paper
+uses Eisenstein & Hu, the workloads here use the BBKS form with P(k) = A k^{n_s} T(q)^2,
+q = k / (Omega_m h), normalised to sigma_8 with a top-hat of radius 8 Mpc/h.  The linear
+growth factor is the Heath (1977) integral, valid for dust + Lambda.
+"""
+
+import math
+
+from scipy import integrate
+
+
+def hubble_e(a, om):
+    """E(a) = H(a)/H0 = sqrt(Om a^-3 + OL) for a flat universe."""
+    return math.sqrt(om / a ** 3 + (1.0 - om))
+
+
+def time_of_a(a, om):
+    """Cosmic time t(a) in 1/H0: the closed form of da/dt = a E(a) for flat dust + Lambda."""
+    ol = 1.0 - om
+    return 2.0 / (3.0 * math.sqrt(ol)) * math.asinh(math.sqrt(ol / om) * a ** 1.5)
+
+
+def a_of_time(t, om):
+    """Inverse of time_of_a: a(t) = (Om/OL)^(1/3) sinh^(2/3)(1.5 sqrt(OL) t)."""
+    ol = 1.0 - om
+    return (om / ol) ** (1.0 / 3.0) * math.sinh(1.5 * math.sqrt(ol) * t) ** (2.0 / 3.0)
+
+
+def _heath_integral(a, om):
+    f = lambda x: 1.0 / (x * hubble_e(x, om)) ** 3 if x > 0 else 0.0
+    val, _ = integrate.quad(f, 0.0, a, epsabs=0.0, epsrel=1e-13, limit=200)
+    return val
+
+
+def growth_unnormalised(a, om):
+    """D_u(a) = (5 Om / 2) E(a) int_0^a da' / (a' E(a'))^3; D_u -> a as a -> 0."""
+    return 2.5 * om * hubble_e(a, om) * _heath_integral(a, om)
+
+
+def growth(a, om):
+    """Linear growth factor normalised to D(1) = 1."""
+    return growth_unnormalised(a, om) / growth_unnormalised(1.0, om)
+
+
+def growth_rate(a, om):
+    """f = dlnD/dlna = -3 Om/(2 a^3 E^2) + 5 Om / (2 a^2 E^2 D_u)  (derivative of D_u above)."""
+    e2 = hubble_e(a, om) ** 2
+    return -1.5 * om / (a ** 3 * e2) + 2.5 * om / (a * a * e2 * growth_unnormalised(a, om))
+
+
+def bbks_transfer(q, log=math.log):
+    """BBKS (Bardeen et al. 1986) transfer function of q = k / (Om h) with k in h/Mpc.
+    Works on floats, or on tensors with log=torch.log (q > 0)."""
+    return (log(1.0 + 2.34 * q) / (2.34 * q)
+            * (1.0 + 3.89 * q + (16.1 * q) ** 2 + (5.46 * q) ** 3 + (6.71 * q) ** 4) ** -0.25)
+
+
+def _tophat(x):
+    if x < 1e-4:
+        return 1.0 - x * x / 10.0
+    return 3.0 * (math.sin(x) - x * math.cos(x)) / x ** 3
+
+
+def sigma_r(pk, radius):
+    """sigma(R)^2 = 1/(2 pi^2) int k^2 P(k) W(kR)^2 dk, integrated in ln k."""
+    f = lambda lnk: (math.exp(3 * lnk) * pk(math.exp(lnk)) * _tophat(math.exp(lnk) * radius) ** 2)
+    pts = [math.log(x) for x in (1e-3, 1e-2, 0.1, 1.0, 10.0)]
+    val, _ = integrate.quad(f, math.log(1e-7), math.log(1e4), points=pts, limit=2000,
+                            epsabs=0.0, epsrel=1e-11)
+    return math.sqrt(val / (2.0 * math.pi ** 2))
+
+
+def spectrum_amplitude(om, h, n_s, sigma8):
+    """A such that P(k) = A k^n_s T(k/(Om h))^2 has sigma(8 Mpc/h) = sigma8 today."""
+    shape = lambda k: k ** n_s * bbks_transfer(k / (om * h)) ** 2 if k > 0 else 0.0
+    s = sigma_r(shape, 8.0)
+    return (sigma8 / s) ** 2
+
+
+def linear_power(k, om, h, n_s, amp):
+    """P(k) [(Mpc/h)^3] at a = 1; k in h/Mpc; P(0) = 0."""
+    if k <= 0.0:
+        return 0.0
+    return amp * k ** n_s * bbks_transfer(k / (om * h)) ** 2

@@ -1,0 +1,115 @@
+"""Gas dynamics of the oracle: comoving Euler equations in conservation form, solved with
+the relaxing total-variation-diminishing scheme (Jin & Xin relaxation, Trac & Pen 2003) with
+a two-stage Runge-Kutta step and Strang dimensional splitting (Sec. 2.3, 2.3.1, 2.3.2).
+
+State vector per cell (eq. conservation):  Q = (rho, a rho U_x, a rho U_y, a rho U_z, a^2 rho E)
+with comoving gas density rho, peculiar velocity U and specific total energy E = e + U^2/2.
+Fluxes along direction d (eq. cont, eq. momentum, eq. ev with gamma = 5/3):
+    F_rho = rho U_d / a
+    F_mj  = rho U_d U_j + p delta_jd        (pressure in the momentum flux: conservative form)
+    F_E   = a U_d (rho E + p)
+The internal-energy source S_e is not applied: the energy variable is the total energy,
+whose flux already carries the pdV work (reading listed in the design doc).
+
+Units: length in cells (Delta x = 1), time in 1/H0, velocity in cells*H0.
+Arrays are indexed [component, z, y, x] (x fastest); axis d = 0, 1, 2 means x, y, z.
+"""
+
+import torch
+
+
+def shift(f, d, s):
+    """Value of f at cell j+s along axis d (periodic); f is [..., z, y, x]."""
+    return torch.roll(f, shifts=-s, dims=f.dim() - 1 - d)
+
+
+def primitives(q, a, gamma, e_floor):
+    """Velocity, pressure and sound speed from Q at scale factor a.
+
+    The specific internal energy e = E - U^2/2 is floored at e_floor only inside the
+    equation of state (pressure, sound speed); the stored total energy is never changed,
+    so the conservation form is untouched.  p = (gamma-1) rho e, c_s = sqrt(gamma p/rho).
+    """
+    rho = q[0]
+    u = q[1:4] / (a * rho)
+    e = q[4] / (a * a * rho) - 0.5 * (u * u).sum(0)
+    e_eff = torch.clamp(e, min=e_floor)
+    p = (gamma - 1.0) * rho * e_eff
+    cs = torch.sqrt(gamma * p / rho)
+    return u, p, cs
+
+
+def flux_and_speed(q, a, d, gamma, e_floor):
+    """Cell-centred flux F along d and the freezing speed c = (|U_d| + c_s)/a (Sec. 2.3.1).
+
+    The 1/a in c is the comoving signal speed in cells per unit time: the continuity flux is
+    rho U/a, so the characteristic speeds of this system are (U_d +- c_s)/a."""
+    rho = q[0]
+    u, p, cs = primitives(q, a, gamma, e_floor)
+    ud = u[d]
+    mom = [rho * ud * u[j] + (p if j == d else 0.0) for j in range(3)]
+    f = torch.stack([rho * ud / a] + mom + [a * ud * (q[4] / (a * a) + p)])
+    c = (ud.abs() + cs) / a
+    return f, c
+
+
+LIMITER_EPS = 1e-20
+
+
+def van_leer(x, y, eps=LIMITER_EPS):
+    """Harmonic-mean (van Leer) flux limiter with a small guard epsilon (Sec. 2.3.2).
+
+    phi(x, y) = (x y + |x y|) / (x + y + eps sgn(x+y)), sgn(0) = +1: equal to
+    2xy/(x+y+eps sgn) when x and y share a sign and 0 otherwise, so it is never 0/0
+    (reading listed in the design doc)."""
+    s = x + y
+    sg = torch.where(s >= 0, torch.ones_like(s), -torch.ones_like(s))
+    xy = x * y
+    return (xy + xy.abs()) / (s + eps * sg)
+
+
+def split_fluxes(q, a, d, gamma, e_floor):
+    """Right- and left-moving fluxes F^R = c Q^R, F^L = c Q^L of the relaxation system with
+    Q^R = (Q + F/c)/2 and Q^L = (Q - F/c)/2, so that F = F^R - F^L (Sec. 2.3.1)."""
+    f, c = flux_and_speed(q, a, d, gamma, e_floor)
+    return 0.5 * (c * q + f), 0.5 * (c * q - f)
+
+
+def sweep(q, d, dt, a_stage1, a_stage2, gamma, e_floor, eps=LIMITER_EPS):
+    """One dimensional relaxing-TVD sweep of the whole grid along axis d over a full dt.
+
+    Stage 1 (eq. TVD_halfstep): first-order upwind interface fluxes
+        F_{n+1/2} = F^R_n - F^L_{n+1},  Q^{1/2}_n = Q_n - dt/2 (F_{n+1/2} - F_{n-1/2}).
+    Stage 2 (eq. TVD_fullstep): second-order fluxes of Q^{1/2} with the limiter applied to
+    each wave and component,
+        F^R_{n+1/2} = F^R_n + phi((F^R_n - F^R_{n-1})/2, (F^R_{n+1} - F^R_n)/2)
+        F^L_{n+1/2} = F^L_{n+1} - phi((F^L_{n+1} - F^L_n)/2, (F^L_{n+2} - F^L_{n+1})/2)
+    and Q^{new}_n = Q_n - dt (F_{n+1/2} - F_{n-1/2}).  The freezing speed is recomputed at
+    each stage; stage 1 uses a(t_n), stage 2 a(t_n + dt/2).
+    """
+    fr, fl = split_fluxes(q, a_stage1, d, gamma, e_floor)
+    f1 = fr - shift(fl, d, 1)
+    qh = q - 0.5 * dt * (f1 - shift(f1, d, -1))
+
+    fr, fl = split_fluxes(qh, a_stage2, d, gamma, e_floor)
+    fr_m1, fr_p1 = shift(fr, d, -1), shift(fr, d, 1)
+    fl_p1, fl_p2 = shift(fl, d, 1), shift(fl, d, 2)
+    fr_face = fr + van_leer(0.5 * (fr - fr_m1), 0.5 * (fr_p1 - fr), eps)
+    fl_face = fl_p1 - van_leer(0.5 * (fl_p1 - fl), 0.5 * (fl_p2 - fl_p1), eps)
+    f2 = fr_face - fl_face
+    return q - dt * (f2 - shift(f2, d, -1))
+
+
+# Strang order (Sec. 2.3.2): the direction order is reversed on every other step and
+# rotated every two steps: XYZ ZYX | ZXY YXZ | YZX XZY, a cycle of six steps.
+STRANG_ORDER = ((0, 1, 2), (2, 1, 0), (2, 0, 1), (1, 0, 2), (1, 2, 0), (0, 2, 1))
+
+
+def strang_axes(step):
+    return STRANG_ORDER[step % 6]
+
+
+def max_signal_speed(q, a, gamma, e_floor):
+    """max over cells and axes of (|U_d| + c_s)/a, the speed in the CFL condition (eq. dt)."""
+    u, _, cs = primitives(q, a, gamma, e_floor)
+    return float(((u.abs() + cs) / a).max())

@@ -1,0 +1,75 @@
+"""Initial conditions of the oracle (Sec. 2.1): a Gaussian random field shaped by the linear
+power spectrum, Zel'dovich (first-order LPT) displacements of a particle lattice, and a gas
+state that tracks the dark matter.
+
+  delta_k  = FFT(w)_k sqrt(P(k) D(a_i)^2 / V_cell)      (FFT unnormalised, inverse 1/N^3)
+  Psi_k    = i k delta_k / k^2   (k in rad/cell, so div Psi = -delta; the derivative factor
+             is zero on the Nyquist plane of its own axis, k = 0 mode zero)
+  x        = q + Psi(q)  with q the cell centres;   p = a u = a_i^2 E(a_i) f(a_i) Psi(q)
+  gas      rho = f_b CIC(x), momentum a rho U = rho p(q) on the cells, T = T_init.
+The white noise w is an input, so the initial field is differentiable with respect to it.
+"""
+
+import math
+
+import torch
+
+from . import cosmology, gravity
+
+
+def lattice(n, dtype=torch.float64):
+    """Cell-centre positions q [3, n^3] in particle order id = (z n + y) n + x."""
+    r = torch.arange(n, dtype=dtype) + 0.5
+    z, y, x = torch.meshgrid(r, r, r, indexing="ij")
+    return torch.stack([x.reshape(-1), y.reshape(-1), z.reshape(-1)])
+
+
+def linear_density(white, cfg):
+    """delta_L at a_init from white noise [n, n, n] (torch float64)."""
+    n = cfg.n
+    kz, ky, kx = gravity.wavenumbers(n)
+    k2 = kx * kx + ky * ky + kz * kz
+    kphys = torch.sqrt(k2) * (n / cfg.box)          # rad/cell -> h/Mpc
+    pos = kphys > 0
+    ks = torch.where(pos, kphys, torch.ones_like(kphys))
+    pk = cfg.amp * ks ** cfg.n_s * cosmology.bbks_transfer(ks / (cfg.omega_m * cfg.h), log=torch.log) ** 2
+    pk = torch.where(pos, pk, torch.zeros_like(pk))
+    d = cosmology.growth(cfg.a_init, cfg.omega_m)
+    v_cell = (cfg.box / n) ** 3
+    dk = torch.fft.rfftn(white) * torch.sqrt(pk * d * d / v_cell)
+    return dk
+
+
+def za_displacement(dk, n):
+    """Psi [3, z, y, x] from the linear density spectrum (rfftn layout)."""
+    kz, ky, kx = gravity.wavenumbers(n)
+    k2 = kx * kx + ky * ky + kz * kz
+    inv_k2 = torch.where(k2 > 0, 1.0 / torch.where(k2 > 0, k2, torch.ones_like(k2)),
+                         torch.zeros_like(k2))
+    nyq = math.pi
+    out = []
+    for kj in (kx, ky, kz):
+        kj_eff = torch.where(kj.abs() == nyq, torch.zeros_like(kj), kj)
+        out.append(torch.fft.irfftn(1j * kj_eff * inv_k2 * dk, s=(n, n, n)))
+    return torch.stack(out)
+
+
+def state_from_displacement(psi, cfg):
+    """(Q, x, p) at a_init for a Zel'dovich displacement field psi [3, n, n, n] on the lattice."""
+    n = cfg.n
+    a = cfg.a_init
+    psi_p = psi.reshape(3, -1)
+    x = torch.remainder(lattice(n) + psi_p, float(n))
+    vfac = a * a * cosmology.hubble_e(a, cfg.omega_m) * cosmology.growth_rate(a, cfg.omega_m)
+    p = vfac * psi_p
+    rho = cfg.f_b * gravity.cic_deposit(x, 1.0, n)
+    mom = rho * (vfac * psi)
+    u = mom / (a * rho)
+    etot = a * a * rho * (cfg.e_init + 0.5 * (u * u).sum(0))
+    q = torch.cat([rho[None], mom, etot[None]])
+    return q, x, p
+
+
+def initial_state(white, cfg):
+    """Returns (Q, x, p) at a_init from white noise [n, n, n] (float64 tensor)."""
+    return state_from_displacement(za_displacement(linear_density(white, cfg), cfg.n), cfg)
