@@ -1,0 +1,168 @@
+"""Benchmark of the MI355X path: cell-updates/s of the full time step (forward with
+checkpoints plus the reverse pass) at 256^3 cells + 256^3 dark-matter particles, the
+forward-only rate, the HBM roofline fraction of the dominant kernel, and the FP64 CPU
+oracle timed on this host.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N = 256
+BOX = 40.0           # Mpc/h: cell size 0.156 Mpc/h, as the 128^3 / 20 Mpc/h box
+A_INIT = 0.01
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=8)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--n", type=int, default=N)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--kernel-reps", type=int, default=20)
+    return p.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_stage(torch, fn, reps):
+    """Average duration of one launch of fn() (HIP events on the current stream)."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def cpu_baseline(n, box):
+    """The FP64 oracle on this host's cores: one forward step at the same size."""
+    import torch
+    import synth_inputs as si
+    from oracle import sim as osim, subgrid
+    torch.set_default_dtype(torch.float64)
+    cfg = osim.default_config(n=n, box=box, a_init=A_INIT, subgrid=subgrid.MODE_RELAXED)
+    st = osim.initial_state(torch.from_numpy(si.white_noise(n, 6)).double(), cfg)
+    dt = osim.cfl_dt(st, cfg)
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        osim.step(st, cfg, osim.Params(), dt)
+    el = time.perf_counter() - t0
+    return {"value": n ** 3 / el, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"one forward step (relaxed star formation) of the FP64 oracle at {n}^3 "
+                      f"from the same initial conditions; {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the method is "
+              "benchmarked on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2502_02294_amd as dhp
+    import synth_inputs as si
+
+    n = args.n
+    nc = n ** 3
+    cfg = dhp.default_config(n=n, box=BOX * n / N, a_init=A_INIT, subgrid=2,
+                             ckpt_every=max(1, args.steps))
+    s = dhp.Sim(cfg)
+    white = torch.from_numpy(si.white_noise(n, 6)).cuda()
+    log(f"bench: n={n} steps={args.steps} warmup={args.warmup}")
+
+    # forward-only: warm up, then K steps
+    s.init_from_noise(white)
+    for _ in range(args.warmup):
+        s.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    log(f"bench: forward {args.steps} steps {t_fwd * 1e3:.1f} ms")
+
+    # forward with checkpoints + reverse pass over the same K-step schedule
+    s.init_from_noise(white)
+    for _ in range(args.steps):
+        s.step()
+    sched = s.get_schedule()
+    target = s.get("flux").clone()
+    s.set_schedule(sched)
+    s.forward(white, 1.0)                      # warm-up of the full path
+    s.loss(target)
+    s.backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_schedule(sched)
+    k = s.forward(white, 1.0)
+    s.loss(target)
+    gw, gp = s.backward()
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    assert k == args.steps
+    log(f"bench: forward+backward {k} steps {t_fb * 1e3:.1f} ms")
+
+    # dominant kernel: the hydro sweep (three per step), 40 algorithmic bytes per cell
+    q = s.get("q")
+    a, _, _ = s.time()
+    dts = []
+    sweep_t = {}
+    for axis in (0, 1, 2):
+        sweep_t[axis] = time_stage(torch, lambda: s.stage_sweep(q, axis, sched[0], a, a),
+                                   args.kernel_reps)
+    t_sweep = sum(sweep_t.values()) / 3.0
+    bytes_per_launch = 40.0 * nc
+    achieved = bytes_per_launch / t_sweep / 1e9
+
+    out = {
+        "metric": "cell-updates/s fwd+bwd at 256^3 (forward with checkpoints + reverse pass)",
+        "value": nc * args.steps / t_fb,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_fb / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{n}^3 cells + {n}^3 DM particles, {BOX * n / N:g} Mpc/h box, "
+                               "BBKS Gaussian random field at a=0.01, relaxed stochastic star "
+                               "formation, checkpointed forward + reverse pass",
+                   "n": n, "box_mpc_h": BOX * n / N, "ckpt_every": int(cfg.ckpt_every)},
+        "fwd_cell_updates_per_s": nc * args.steps / t_fwd,
+        "fwd_ms_per_step": t_fwd / args.steps * 1e3,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "hydro sweep (x, y, z mean)",
+                     "ms_per_launch": {str(k_): v * 1e3 for k_, v in sweep_t.items()}},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(n, BOX * n / N)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

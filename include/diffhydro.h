@@ -1,0 +1,172 @@
+/*
+ * diffhydro.h -- C ABI of the MI355X (gfx950) implementation of one time step of
+ * differentiable cosmological hydrodynamics (Horowitz & Lukic, arXiv:2502.02294), with its
+ * reverse-mode pass.
+ *
+ * The method (paper Sec. 2): gas obeys the comoving Euler equations in conservation form
+ * (eq. cont, eq. momentum, eq. ev, eq. conservation), solved with the relaxing TVD scheme,
+ * a two-stage Runge-Kutta step (eq. TVD_halfstep, eq. TVD_fullstep), the van Leer limiter
+ * and Strang dimensional splitting (Sec. 2.3.1-2.3.2); dark matter is evolved by a
+ * particle-mesh solver with kick-drift-kick leapfrog (Sec. 2.2, eq. dm_hamil); the global
+ * time step follows the CFL condition (eq. dt) or a predefined schedule (Sec. 2.3.3); a
+ * stochastic star-formation source term injects supernova energy, relaxed by the binary
+ * Gumbel-softmax for differentiation (Sec. 2.4, eq. gumbelsoftmax); the initial state is a
+ * Gaussian random field with Zel'dovich displacements (Sec. 2.1).
+ *
+ * Conventions
+ *  - Every call returns int: DH_OK (0) or a negative DH_E_* code; dh_last_error() then
+ *    holds a message.  No C++ exception crosses this boundary.
+ *  - Device pointers ("d_" prefix) are caller-owned, contiguous, on the handle's device,
+ *    and are only read or written during the call's stream work; host pointers likewise.
+ *    The library owns every internal buffer, the checkpoints and the reverse-mode tape.
+ *  - Grid fields are float32 arrays of n^3 values indexed (z*n + y)*n + x (x fastest).
+ *    Particle fields are float32 structure-of-arrays [3][n^3] (x, y, z components), in
+ *    particle order id = (z*n + y)*n + x of the initial lattice.
+ *  - Units: length in cells (comoving), time in 1/H0, velocities in cells*H0, i.e.
+ *    100*box/n km/s.  Gas state Q = (rho, a rho U_x, a rho U_y, a rho U_z, a^2 rho E) with
+ *    mean gas density Omega_b/Omega_m and mean total matter density 1 per cell.
+ *  - Work is enqueued on the handle's stream (dh_set_stream, default the null stream).
+ *    Calls that return host scalars synchronise that stream; others are asynchronous.
+ *  - A handle is not thread-safe; separate handles are independent.
+ */
+#ifndef DIFFHYDRO_H
+#define DIFFHYDRO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DH_OK = 0,
+    DH_E_INVAL = -1,      /* bad argument (size, null pointer, out-of-range option) */
+    DH_E_OOM = -2,        /* device or host allocation failed */
+    DH_E_HIP = -3,        /* a HIP runtime call failed */
+    DH_E_NONFINITE = -4,  /* non-finite or non-positive density found in the state */
+    DH_E_SCHEDULE = -5,   /* a replayed schedule is exhausted or violates the dt rule */
+    DH_E_STATE = -6       /* call out of order (e.g. backward before forward) */
+};
+
+enum { DH_SUBGRID_OFF = 0, DH_SUBGRID_HARD = 1, DH_SUBGRID_RELAXED = 2 };
+
+/* Run configuration.  dh_config_default() fills the values of the paper's workloads. */
+typedef struct dh_config {
+    int32_t n;           /* cells per side; power of two, 16..256                        */
+    double box;          /* comoving box side [Mpc/h]                                     */
+    double omega_m, omega_b, h, sigma8, n_s;   /* flat LambdaCDM, BBKS spectrum          */
+    double gamma;        /* adiabatic index (5/3)                                         */
+    double mu;           /* mean molecular weight used only for T <-> e                   */
+    double a_init;       /* initial scale factor                                          */
+    double t_init;       /* initial gas temperature [K]                                   */
+    double cfl;          /* Courant number C_max of eq. dt                                */
+    double dlna_max;     /* cap on dln a per step                                          */
+    double t_floor;      /* temperature floor [K] applied only inside the EOS              */
+    int32_t subgrid;     /* DH_SUBGRID_*                                                   */
+    double tau;          /* Gumbel-softmax temperature (Sec. 2.4.2; 0.1)                   */
+    uint64_t sf_seed;    /* key of the per-cell, per-step star-formation uniforms          */
+    int32_t ckpt_every;  /* checkpoint interval in steps for dh_forward/dh_backward (>=1)  */
+} dh_config;
+
+/* Model parameters (double).  A, beta: flux observable F = exp(-A Delta^beta) of the loss;
+ * eps_sf: star-formation efficiency per free-fall time; delta_c: gas overdensity
+ * threshold; t_c: temperature threshold [K]; e0: supernova specific energy
+ * [(1000 km/s)^2]; w_rho, w_t: widths of the relaxed thresholds relative to delta_c, t_c. */
+typedef struct dh_params {
+    double A, beta, eps_sf, delta_c, t_c, e0, w_rho, w_t;
+} dh_params;
+
+/* Fields for dh_get_field / dh_set_field.  Sizes in floats: Q = 5 n^3, POS and MOM = 3 n^3,
+ * the rest n^3.  TEMP (get only) is the gas temperature [K] from the floored energy. */
+typedef enum dh_field {
+    DH_FIELD_Q = 0, DH_FIELD_RHO = 1, DH_FIELD_POS = 2, DH_FIELD_MOM = 3,
+    DH_FIELD_STAR = 4, DH_FIELD_PHI = 5, DH_FIELD_TEMP = 6, DH_FIELD_FLUX = 7
+} dh_field;
+
+typedef struct dh_sim dh_sim;
+
+void dh_config_default(dh_config* cfg);
+void dh_params_default(dh_params* p);
+
+/* Allocates every device buffer on the current HIP device.  Errors: DH_E_INVAL for an
+ * unsupported n or non-physical cosmology, DH_E_OOM, DH_E_HIP. */
+int dh_create(const dh_config* cfg, dh_sim** out);
+int dh_destroy(dh_sim* sim);
+/* hip_stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) or NULL. */
+int dh_set_stream(dh_sim* sim, void* hip_stream);
+int dh_set_params(dh_sim* sim, const dh_params* p);
+
+/* Initial state (Sec. 2.1): white noise -> delta_k = FFT(w) sqrt(P(k) D(a_i)^2 / V_cell)
+ * -> Zel'dovich displacement Psi = IFFT(i k delta_k / k^2) -> particles x = q + Psi,
+ * p = a^2 E(a) f(a) Psi; gas rho = f_b CIC(x), velocity of the particles on the lattice,
+ * T = t_init; the potential of the initial state.  Resets time, step count and schedule.
+ * _from_seed draws the noise with the library's Philox-4x32-10 generator (one normal per
+ * cell by Box-Muller); _from_noise takes caller noise d_white[n^3] (device). */
+int dh_init_from_seed(dh_sim* sim, uint64_t seed);
+int dh_init_from_noise(dh_sim* sim, const float* d_white);
+
+/* One step (operator order: CFL dt or next schedule entry; opening half kicks of gas and
+ * dark matter with g_n; drift; three sweeps in the Strang order of this step; CIC deposit
+ * and Poisson solve; closing half kicks with g_{n+1}; source term).  dt_out, a_out may be
+ * NULL.  Returns DH_E_NONFINITE if the new state has a non-finite or non-positive density. */
+int dh_step(dh_sim* sim, double* dt_out, double* a_out);
+/* Steps until a >= a_final; the last step is clipped to land on a_final. */
+int dh_run_to(dh_sim* sim, double a_final, int32_t* nsteps_out);
+
+/* Predefined schedule (Sec. 2.3.3).  set: the next steps take dts[0..n) in order (then the
+ * CFL again); n = 0 clears it.  get: the dt of every step since the last init, at most
+ * cap values, total count in *n_out. */
+int dh_set_schedule(dh_sim* sim, const double* dts, int32_t n);
+int dh_get_schedule(const dh_sim* sim, double* dts, int32_t cap, int32_t* n_out);
+
+/* Copy a field to / from caller device memory (see dh_field).  set_field of Q, POS or RHO
+ * invalidates the potential; dh_refresh_potential() recomputes it from the current gas and
+ * particles at the current scale factor. */
+int dh_get_field(dh_sim* sim, dh_field f, float* d_out);
+int dh_set_field(dh_sim* sim, dh_field f, const float* d_in);
+int dh_refresh_potential(dh_sim* sim);
+/* Current time.  set_time sets a (and t = t(a)) and the step counter used for the Strang
+ * order and the random-number counters. */
+int dh_get_time(const dh_sim* sim, double* a, double* t, int32_t* step);
+int dh_set_time(dh_sim* sim, double a, int32_t step);
+
+/* Differentiable run: init from d_white, then step to a_final with checkpoints every
+ * cfg.ckpt_every steps (replaying the schedule if one was set, else recording it). */
+int dh_forward(dh_sim* sim, const float* d_white, double a_final, int32_t* nsteps_out);
+/* Loss L = mean over cells of (F - F_target)^2 with F = exp(-A (rho/rho_mean)^beta) on the
+ * current state; FP64 reduction.  d_target[n^3] device. */
+int dh_loss(dh_sim* sim, const float* d_target, double* loss_out);
+/* Reverse pass of the last dh_forward.  d_grad_rho: adjoint of the final gas density
+ * (device n^3) or NULL for the gradient of the last dh_loss.  Outputs: d_grad_white[n^3]
+ * (device) and grad_params[4] = dL/d(A, beta, eps_sf, delta_c) (host, FP64).  The time
+ * schedule is held fixed.  DH_E_STATE if no forward (or no loss, with NULL) precedes it. */
+int dh_backward(dh_sim* sim, const float* d_grad_rho, float* d_grad_white, double* grad_params);
+
+/* FP64 sums over the current state: out[0] gas mass, out[1..3] gas momentum a rho U,
+ * out[4] total gas energy a^2 rho E, out[5..7] dark-matter momentum (mass times p). */
+int dh_conservation(dh_sim* sim, double* out);
+
+/* Single stages on caller buffers, for verification of each kernel against a reference.
+ * They do not touch the handle's state.  All pointers are device float32.
+ *  sweep:    q_out = one relaxing-TVD sweep of q_in along axis (0 x, 1 y, 2 z) over dt,
+ *            with scale factors a_stage1, a_stage2 (Sec. 2.3.1-2.3.2).
+ *  sweep_vjp: lam_in = (d sweep / d q_in)^T lam_out at q_in.
+ *  poisson:  phi = solution of lap(phi) = (3 Om / 2a) delta (Green's function -1/k^2).
+ *  deposit:  delta = rho_gas + m_dm CIC(pos) - 1 (cell-sorted, deterministic).
+ *  readout:  out[3][np] = CIC interpolation of the central-difference g = -grad(phi).  */
+int dh_stage_sweep(dh_sim* sim, const float* d_q_in, float* d_q_out, int32_t axis, double dt,
+                   double a_stage1, double a_stage2);
+int dh_stage_sweep_vjp(dh_sim* sim, const float* d_q_in, const float* d_lam_out,
+                       float* d_lam_in, int32_t axis, double dt, double a_stage1,
+                       double a_stage2);
+int dh_stage_poisson(dh_sim* sim, const float* d_delta, float* d_phi, double a);
+int dh_stage_deposit(dh_sim* sim, const float* d_rho_gas, const float* d_pos, float* d_delta);
+int dh_stage_readout(dh_sim* sim, const float* d_phi, const float* d_pos, float* d_g);
+
+const char* dh_last_error(const dh_sim* sim);
+const char* dh_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

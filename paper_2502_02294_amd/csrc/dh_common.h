@@ -1,0 +1,201 @@
+// Internal definitions shared by the HIP translation units of libdiffhydro.
+// Device math follows the paper's method; see include/diffhydro.h for the conventions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#define DH_HIP(call)                                                                        \
+  do {                                                                                      \
+    hipError_t _e = (call);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      throw ::dh::HipError(std::string(#call) + ": " + hipGetErrorString(_e));              \
+  } while (0)
+
+#define DH_LAUNCH_CHECK() DH_HIP(hipGetLastError())
+
+namespace dh {
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct ArgError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+inline unsigned blocks_for(long long work, int threads) {
+  return static_cast<unsigned>((work + threads - 1) / threads);
+}
+
+// ---------------------------------------------------------------------------------------
+// Hydro: per-cell primitive recovery, flux along D and the relaxation split (Sec. 2.3.1).
+// Q = (rho, m_x, m_y, m_z, Et) with m = a rho U and Et = a^2 rho E.
+//   U = m/(a rho), e = Et/(a^2 rho) - U^2/2 floored at e_floor only inside the EOS,
+//   p = (gamma-1) rho e, c_s = sqrt(gamma (gamma-1) e), freezing speed c = (|U_d| + c_s)/a,
+//   F = (rho U_d / a, rho U_d U + p e_d, a U_d (Et/a^2 + p)),
+//   F^R = (c Q + F)/2, F^L = (c Q - F)/2.
+// ---------------------------------------------------------------------------------------
+struct HydroK {
+  float a, ia, ia2;   // scale factor, 1/a, 1/a^2
+  float gm1, gg1;     // gamma-1, gamma*(gamma-1)
+  float efloor;
+};
+
+__host__ __device__ inline HydroK make_hydro(float a, float gamma, float efloor) {
+  HydroK k;
+  k.a = a;
+  k.ia = 1.0f / a;
+  k.ia2 = k.ia * k.ia;
+  k.gm1 = gamma - 1.0f;
+  k.gg1 = gamma * (gamma - 1.0f);
+  k.efloor = efloor;
+  return k;
+}
+
+template <int D>
+__device__ __forceinline__ void split_flux(const float q[5], const HydroK& h, float fr[5],
+                                           float fl[5]) {
+  const float rho = q[0];
+  const float ir = 1.0f / rho;
+  const float u0 = q[1] * h.ia * ir, u1 = q[2] * h.ia * ir, u2 = q[3] * h.ia * ir;
+  const float ke = 0.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+  float e = q[4] * h.ia2 * ir - ke;
+  e = fmaxf(e, h.efloor);
+  const float p = h.gm1 * rho * e;
+  const float cs = sqrtf(h.gg1 * e);
+  const float ud = D == 0 ? u0 : (D == 1 ? u1 : u2);
+  const float c = (fabsf(ud) + cs) * h.ia;
+  float f[5];
+  f[0] = rho * ud * h.ia;
+  f[1] = rho * ud * u0 + (D == 0 ? p : 0.0f);
+  f[2] = rho * ud * u1 + (D == 1 ? p : 0.0f);
+  f[3] = rho * ud * u2 + (D == 2 ? p : 0.0f);
+  f[4] = h.a * ud * (q[4] * h.ia2 + p);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    fr[k] = 0.5f * (c * q[k] + f[k]);
+    fl[k] = 0.5f * (c * q[k] - f[k]);
+  }
+}
+
+// Vector-Jacobian product of the split fluxes at q: given the adjoints gR = dL/dF^R and
+// gL = dL/dF^L (5 each), returns dL/dq = (dF^R/dq)^T gR + (dF^L/dq)^T gL
+//   = 1/2 [ c s + (dc/dq)(q . s) + (dF/dq)^T d ],  s = gR + gL, d = gR - gL.
+// Derivatives are those of the floored EOS (zero through e where the floor is active) and
+// of |U_d| with sign(0) = 0.
+template <int D>
+__device__ __forceinline__ void split_flux_vjp(const float q[5], const HydroK& h,
+                                               const float s[5], const float dv[5],
+                                               float out[5]) {
+  const float rho = q[0];
+  const float ir = 1.0f / rho;
+  const float u[3] = {q[1] * h.ia * ir, q[2] * h.ia * ir, q[3] * h.ia * ir};
+  const float ke = 0.5f * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const float eraw = q[4] * h.ia2 * ir - ke;
+  const bool floored = eraw < h.efloor;
+  const float e = floored ? h.efloor : eraw;
+  const float p = h.gm1 * rho * e;
+  const float cs = sqrtf(h.gg1 * e);
+  const float ud = u[D];
+  const float md = q[1 + D];
+  const float sgn = md > 0.0f ? 1.0f : (md < 0.0f ? -1.0f : 0.0f);
+  const float c = (fabsf(ud) + cs) * h.ia;
+
+  // derivatives of e (zero when floored)
+  const float er = floored ? 0.0f : (ke - e) * ir;
+  float em[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) em[k] = floored ? 0.0f : -u[k] * h.ia * ir;
+  const float eE = floored ? 0.0f : h.ia2 * ir;
+  // pressure derivatives
+  const float pr = h.gm1 * (e + rho * er);
+  float pm[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) pm[k] = h.gm1 * rho * em[k];
+  const float pE = h.gm1 * rho * eE;
+  // freezing-speed derivatives
+  const float cse = floored ? 0.0f : 0.5f * h.gg1 / cs;
+  const float cr = h.ia * (-fabsf(ud) * ir + cse * er);
+  float cm[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) cm[k] = h.ia * ((k == D ? sgn * h.ia * ir : 0.0f) + cse * em[k]);
+  const float cE = h.ia * cse * eE;
+
+  const float qs = q[0] * s[0] + q[1] * s[1] + q[2] * s[2] + q[3] * s[3] + q[4] * s[4];
+  // (dF/dq)^T dv
+  const float H = (q[4] * h.ia2 + p) * ir;
+  const float vu = dv[1] * u[0] + dv[2] * u[1] + dv[3] * u[2];
+  const float W = dv[1 + D] + dv[4] * h.a * ud;
+  float jt[5];
+  jt[0] = -ud * vu + pr * W - dv[4] * h.a * ud * H;
+  const float diag = dv[0] * h.ia2 + h.ia * vu + dv[4] * H;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) jt[1 + k] = (k == D ? diag : 0.0f) + ud * h.ia * dv[1 + k] + pm[k] * W;
+  jt[4] = pE * W + dv[4] * h.a * ud * h.ia2;
+
+  const float dc[5] = {cr, cm[0], cm[1], cm[2], cE};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) out[k] = 0.5f * (c * s[k] + dc[k] * qs + jt[k]);
+}
+
+// van Leer limiter with guard epsilon (Sec. 2.3.2):
+//   phi(x, y) = (x y + |x y|) / (x + y + eps sgn(x+y)),  sgn(0) = +1.
+constexpr float kLimEps = 1e-20f;
+
+__device__ __forceinline__ float van_leer(float x, float y) {
+  const float s = x + y;
+  const float xy = x * y;
+  return (xy + fabsf(xy)) / (s + (s >= 0.0f ? kLimEps : -kLimEps));
+}
+
+// Partial derivatives of van_leer (for xy == 0 the one-sided average used by the
+// derivative of |xy| with sign(0) = 0).
+__device__ __forceinline__ void van_leer_d(float x, float y, float& dx, float& dy) {
+  const float s = x + y;
+  const float den = s + (s >= 0.0f ? kLimEps : -kLimEps);
+  const float xy = x * y;
+  const float sg = xy > 0.0f ? 1.0f : (xy < 0.0f ? -1.0f : 0.0f);
+  const float num = xy + fabsf(xy);
+  const float id = 1.0f / den;
+  const float q = num * id * id;   // num * id first: no 0 * inf when den is ~eps
+  dx = (y + sg * y) * id - q;
+  dy = (x + sg * x) * id - q;
+}
+
+// ---------------------------------------------------------------------------------------
+// Philox-4x32-10 (Salmon et al., SC'11): counter-based generator for the white noise and the
+// star-formation uniforms.  Counter (cell, step, tag, 0), key (seed lo, seed hi).
+// ---------------------------------------------------------------------------------------
+constexpr uint32_t kTagWhite = 0x574E0000u;
+constexpr uint32_t kTagStarform = 0x53460000u;
+
+__host__ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c[0];
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
+    const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+    const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// 24 random bits plus one half, times 2^-24: u in (0,1), exact in float and double.
+__host__ __device__ inline double uniform_open_d(uint32_t bits) {
+  return (static_cast<double>(bits >> 8) + 0.5) * (1.0 / 16777216.0);
+}
+__host__ __device__ inline float uniform_open_f(uint32_t bits) {
+  return (static_cast<float>(bits >> 8) + 0.5f) * (1.0f / 16777216.0f);
+}
+
+}  // namespace dh

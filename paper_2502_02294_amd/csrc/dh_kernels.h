@@ -1,0 +1,118 @@
+// Host-side launchers of the HIP kernels of libdiffhydro (one stream per call).
+#pragma once
+
+#include <vector>
+
+#include "dh_common.h"
+
+namespace dh {
+
+// ---- hydro (k_hydro.hip)
+void launch_sweep(hipStream_t st, const float* qin, float* qout, int n, int axis, float dt,
+                  const HydroK& h1, const HydroK& h2);
+// lam_h_scratch: 5 n^3 floats, used by the y/z adjoints
+void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
+                      float* lam_h_scratch, int n, int axis, float dt, const HydroK& h1,
+                      const HydroK& h2);
+
+// ---- particle mesh (k_pm.hip)
+struct Bins {          // counting sort of particles by CIC base cell
+  uint32_t* key;       // [np] base cell of each particle
+  uint32_t* rank;      // [np] scratch: arrival rank inside its bin
+  uint32_t* count;     // [nc]
+  uint32_t* start;     // [nc + 1] exclusive prefix sum of count
+  uint32_t* sorted;    // [np] particle ids, bins in cell order, ids ascending inside a bin
+  uint32_t* block_sums;  // [scan blocks]
+};
+size_t scan_block_count(long long nc);
+void launch_keys(hipStream_t st, const float* pos, uint32_t* key, int n);
+void launch_sort(hipStream_t st, const Bins& b, int n);
+// delta = rho_gas + m_dm * CIC(pos) - 1 ; rho_gas may be null (then 0), offset -1 optional
+void launch_deposit(hipStream_t st, const Bins& b, const float* pos, const float* rho_gas,
+                    float m_dm, float offset, float* out, int n);
+// deposit of a particle vector field v[3][np] with CIC weights: out[3][nc]
+void launch_deposit_vec(hipStream_t st, const Bins& b, const float* pos, const float* v,
+                        float scale, float* out_accum, int n);
+// g at particles: out[3][np] = CIC readout of -grad(phi) (central differences)
+void launch_readout_g(hipStream_t st, const float* phi, const float* pos, float* out, int n);
+// opening kick + drift (+ keys), closing kick
+void launch_kick_drift(hipStream_t st, const float* phi, float* pos, float* mom, uint32_t* key,
+                       float h_kick, float drift_fac, int n);
+void launch_kick(hipStream_t st, const float* phi, const float* pos, float* mom, float h_kick,
+                 int n);
+// adjoint of p' = p + h g(x): lam_x += h sum_c dw/dx (g_c . lam_p') ; (lam_g deposit separate)
+void launch_kick_vjp_pos(hipStream_t st, const float* phi, const float* pos,
+                         const float* lam_p, float h_kick, float* lam_x, int n);
+// adjoint of the deposit wrt positions: lam_x += mass sum_c lam_delta_c dw_c/dx
+void launch_deposit_vjp_pos(hipStream_t st, const float* lam_delta, const float* pos,
+                            float mass, float* lam_x, int n);
+// lam_x += lam_p * fac (drift adjoint), elementwise over 3 np
+void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long count);
+// lam_phi = div^T of lam_g (adjoint of the central-difference gradient) + lam_phi_in
+void launch_grad_vjp(hipStream_t st, const float* lam_g, const float* lam_phi_in, float* lam_phi,
+                     int n);
+
+// ---- FFT and spectral operators (k_fft.hip)
+enum SpecOp { kOpGreen = 0, kOpIcDisp = 1, kOpIcDispT = 2 };
+void fft_make_twiddles(int n, std::vector<float2>& tw);
+// real field -> half spectrum transformed along x and y (z pass separate)
+void fft_forward_xy(hipStream_t st, const float* in, float2* spec, const float2* tw, int n);
+// inverse along y, then c2r along x with a scale
+void fft_inverse_yx(hipStream_t st, float2* spec, float* out, const float2* tw, int n, float scale);
+// z pass: forward, Green's function (green = -(3 Om/2a)/N^3), inverse
+void fft_zpass_green(hipStream_t st, float2* spec, const float2* tw, int n, float green);
+void fft_zpass_forward(hipStream_t st, const float2* in, float2* out, const float2* tw, int n);
+void fft_zpass_inverse(hipStream_t st, float2* spec, const float2* tw, int n);
+// z pass with the initial-condition operator i k_axis T(k)/k^2 / N^3 (or its conjugate)
+void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* tw, int n,
+                  int axis, bool transpose, double amp, double om_h, double n_s, double kphys,
+                  bool forward_first, bool inverse_after, bool accumulate);
+
+// ---- pointwise / reductions (k_point.hip)
+void launch_gas_kick(hipStream_t st, float* q, const float* phi, float h, int n);
+void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float* phi, float h,
+                         float* lam_q, float* lam_g, int n);
+struct SourceArgs {
+  float a, dt, inv_rho_mean, omega_b, gm1, efloor, t_per_e, e0_code;
+  float eps_sf, delta_c, t_c, w_rho, w_t, tau;
+  int mode;
+  uint32_t seed_lo, seed_hi, step;
+};
+void launch_source(hipStream_t st, float* q, float* star, const SourceArgs& a, int n);
+// adjoint of the source term; accumulates dL/d(eps_sf, delta_c) partials per block
+void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, const SourceArgs& a,
+                       double* partials, int nblocks_out, int n);
+int source_vjp_blocks(int n);
+// FP64 block maxima of the CFL speed max_d (|U_d| + c_s)/a
+int cfl_blocks(int n);
+void launch_cfl_partial(hipStream_t st, const float* q, float a, float gamma, float efloor,
+                        double* block_max, int n);
+void launch_reduce_max(hipStream_t st, const double* in, int count, double* out);
+void launch_reduce_sum(hipStream_t st, const double* in, int count, int stride, int nvec,
+                       double* out);
+int sum_blocks(long long count);
+// FP64 block sums of several fields: partial[v * nblocks + b]
+void launch_conservation_partial(hipStream_t st, const float* q, const float* mom,
+                                 double* partial, int nblocks, long long nc);
+void launch_loss_partial(hipStream_t st, const float* rho, const float* target, double A,
+                         double beta, float inv_rho_mean, double* partial, int nblocks,
+                         long long nc);
+void launch_loss_vjp(hipStream_t st, const float* rho, const float* target, double A, double beta,
+                     float inv_rho_mean, float* lam_rho, double* partial, int nblocks, long long nc);
+void launch_flux_field(hipStream_t st, const float* rho, double A, double beta,
+                       float inv_rho_mean, float* out, long long nc);
+void launch_temperature(hipStream_t st, const float* q, float a, float efloor, float t_per_e,
+                        float* out, long long nc);
+void launch_white_noise(hipStream_t st, float* out, uint32_t seed_lo, uint32_t seed_hi, int n);
+// IC: particles from displacement and gas from the deposit
+void launch_ic_particles(hipStream_t st, const float* psi, float* pos, float* mom, float vfac,
+                         int n);
+void launch_ic_gas(hipStream_t st, const float* cic, const float* psi, float* q, float f_b,
+                   float vfac, float a, float e_init, int n);
+void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const float* lam_q,
+                       float f_b, float vfac, float a, float e_init, float* lam_cic,
+                       float* lam_psi, int n);
+void launch_fill(hipStream_t st, float* p, float v, long long count);
+void launch_check_finite(hipStream_t st, const float* q, long long nc, int* flag);
+
+}  // namespace dh

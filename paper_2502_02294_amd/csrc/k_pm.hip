@@ -1,0 +1,483 @@
+// Particle-mesh kernels (Sec. 2.2): cell keys, a stable counting sort of the particles by
+// their CIC base cell, the deterministic CIC deposit as a per-cell gather over the 8 bins
+// that can reach a cell, the CIC read-out of g = -grad(phi) (two-point central difference),
+// kick and drift (eq. dm_hamil: dx/dt = p/a^2, dp/dt = g), and the adjoints of all of them.
+//
+// CIC on cell centres: with s = x - 1/2, i0 = floor(s), w1 = s - i0, a particle puts
+// weight (1-w1) in cell i0 and w1 in i0+1 per axis.  Cell c receives from particles whose
+// base cell is c - o, o in {0,1}^3.  The deposit visits o in a fixed order and the bin
+// contents in ascending particle id, so every sum is reproducible bit for bit without float
+// atomics.
+#include "dh_kernels.h"
+
+namespace dh {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__device__ __forceinline__ int wrapi(int j, int n) { return j & (n - 1); }
+
+struct Cic {
+  int i0[3];
+  float w1[3];
+};
+
+__device__ __forceinline__ Cic cic_of(float x, float y, float z, int n) {
+  Cic c;
+  const float v[3] = {x, y, z};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float s = v[d] - 0.5f;
+    const float f = floorf(s);
+    c.w1[d] = s - f;
+    c.i0[d] = wrapi(static_cast<int>(f), n);
+  }
+  return c;
+}
+
+__device__ __forceinline__ float wsel(float w1, int o) { return o ? w1 : 1.0f - w1; }
+
+__global__ void keys_kernel(const float* __restrict__ pos, uint32_t* __restrict__ key, int n,
+                            long long np) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const Cic c = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
+  key[i] = static_cast<uint32_t>((c.i0[2] * n + c.i0[1]) * n + c.i0[0]);
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, long long count) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+__global__ void hist_kernel(const uint32_t* __restrict__ key, uint32_t* count,
+                            uint32_t* __restrict__ rank, long long np) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  rank[i] = atomicAdd(&count[key[i]], 1u);
+}
+
+// Block-local exclusive scan helper over kScanThreads values in LDS.
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t add = t >= off ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  total = sh[kScanThreads - 1];
+  const uint32_t incl = sh[t];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(
+    const uint32_t* __restrict__ in, uint32_t* __restrict__ block_sums, long long count) {
+  __shared__ uint32_t sh[kScanThreads];
+  const long long base = static_cast<long long>(blockIdx.x) * kScanTile + threadIdx.x * kScanPer;
+  uint32_t s = 0;
+  for (int k = 0; k < kScanPer; ++k)
+    if (base + k < count) s += in[base + k];
+  uint32_t total;
+  block_exclusive_scan(s, sh, total);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_block_sums_kernel(uint32_t* sums, int nb) {
+  __shared__ uint32_t sh[kScanThreads];
+  uint32_t carry = 0;
+  for (int b0 = 0; b0 < nb; b0 += kScanThreads) {
+    const int i = b0 + threadIdx.x;
+    const uint32_t v = i < nb ? sums[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, sh, total);
+    if (i < nb) sums[i] = carry + ex;
+    carry += total;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_final_kernel(
+    const uint32_t* __restrict__ in, const uint32_t* __restrict__ block_off,
+    uint32_t* __restrict__ out, long long count) {
+  __shared__ uint32_t sh[kScanThreads];
+  const long long base = static_cast<long long>(blockIdx.x) * kScanTile + threadIdx.x * kScanPer;
+  uint32_t v[kScanPer];
+  uint32_t s = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = base + k < count ? in[base + k] : 0u;
+    s += v[k];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(s, sh, total) + block_off[blockIdx.x];
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < count) out[base + k] = run;
+    run += v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[count] = block_off[blockIdx.x] + total;
+}
+
+__global__ void scatter_kernel(const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
+                               const uint32_t* __restrict__ start, uint32_t* __restrict__ sorted,
+                               long long np) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  sorted[start[key[i]] + rank[i]] = static_cast<uint32_t>(i);
+}
+
+// The atomics above fix each bin's size but not the order inside it; sorting each bin's ids
+// ascending makes the layout a pure function of the keys.
+__global__ void bin_sort_kernel(const uint32_t* __restrict__ start, uint32_t* sorted, long long nc) {
+  const long long b = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= nc) return;
+  const uint32_t lo = start[b], hi = start[b + 1];
+  for (uint32_t i = lo + 1; i < hi; ++i) {
+    const uint32_t v = sorted[i];
+    uint32_t j = i;
+    while (j > lo && sorted[j - 1] > v) {
+      sorted[j] = sorted[j - 1];
+      --j;
+    }
+    sorted[j] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------- deposit
+__global__ void __launch_bounds__(256) deposit_kernel(
+    const uint32_t* __restrict__ start, const uint32_t* __restrict__ sorted,
+    const float* __restrict__ pos, const float* __restrict__ rho_gas, float m_dm, float offset,
+    float* __restrict__ out, int n, long long np) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long nc = static_cast<long long>(n) * n * n;
+  if (c >= nc) return;
+  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
+            iz = static_cast<int>(c / (static_cast<long long>(n) * n));
+  float acc = 0.0f;
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        const long long b = (static_cast<long long>(wrapi(iz - oz, n)) * n + wrapi(iy - oy, n)) * n +
+                            wrapi(ix - ox, n);
+        const uint32_t lo = start[b], hi = start[b + 1];
+        for (uint32_t j = lo; j < hi; ++j) {
+          const uint32_t id = sorted[j];
+          const Cic w = cic_of(pos[id], pos[np + id], pos[2 * np + id], n);
+          acc += wsel(w.w1[0], ox) * wsel(w.w1[1], oy) * wsel(w.w1[2], oz);
+        }
+      }
+  const float g = rho_gas ? rho_gas[c] : 0.0f;
+  out[c] = g + m_dm * acc + offset;
+}
+
+__global__ void __launch_bounds__(256) deposit_vec_kernel(
+    const uint32_t* __restrict__ start, const uint32_t* __restrict__ sorted,
+    const float* __restrict__ pos, const float* __restrict__ v, float scale,
+    float* __restrict__ out, int n, long long np) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long nc = static_cast<long long>(n) * n * n;
+  if (c >= nc) return;
+  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
+            iz = static_cast<int>(c / (static_cast<long long>(n) * n));
+  float acc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        const long long b = (static_cast<long long>(wrapi(iz - oz, n)) * n + wrapi(iy - oy, n)) * n +
+                            wrapi(ix - ox, n);
+        const uint32_t lo = start[b], hi = start[b + 1];
+        for (uint32_t j = lo; j < hi; ++j) {
+          const uint32_t id = sorted[j];
+          const Cic w = cic_of(pos[id], pos[np + id], pos[2 * np + id], n);
+          const float ww = wsel(w.w1[0], ox) * wsel(w.w1[1], oy) * wsel(w.w1[2], oz);
+          acc[0] += ww * v[id];
+          acc[1] += ww * v[np + id];
+          acc[2] += ww * v[2 * np + id];
+        }
+      }
+  out[c] += scale * acc[0];
+  out[nc + c] += scale * acc[1];
+  out[2 * nc + c] += scale * acc[2];
+}
+
+// g_d at cell (ix, iy, iz) = -(phi[+e_d] - phi[-e_d]) / 2
+__device__ __forceinline__ void grid_g(const float* __restrict__ phi, int ix, int iy, int iz, int n,
+                                       float g[3]) {
+  const long long nn = static_cast<long long>(n) * n;
+  const long long zo = static_cast<long long>(iz) * nn, yo = static_cast<long long>(iy) * n;
+  g[0] = -0.5f * (phi[zo + yo + wrapi(ix + 1, n)] - phi[zo + yo + wrapi(ix - 1, n)]);
+  g[1] = -0.5f * (phi[zo + static_cast<long long>(wrapi(iy + 1, n)) * n + ix] -
+                  phi[zo + static_cast<long long>(wrapi(iy - 1, n)) * n + ix]);
+  g[2] = -0.5f * (phi[static_cast<long long>(wrapi(iz + 1, n)) * nn + yo + ix] -
+                  phi[static_cast<long long>(wrapi(iz - 1, n)) * nn + yo + ix]);
+}
+
+// CIC read-out of g at a particle, and optionally the position derivative of g . lam
+__device__ __forceinline__ void readout_g(const float* __restrict__ phi, const Cic& w, int n,
+                                          float out[3]) {
+  out[0] = out[1] = out[2] = 0.0f;
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        float g[3];
+        grid_g(phi, wrapi(w.i0[0] + ox, n), wrapi(w.i0[1] + oy, n), wrapi(w.i0[2] + oz, n), n, g);
+        const float ww = wsel(w.w1[0], ox) * wsel(w.w1[1], oy) * wsel(w.w1[2], oz);
+        out[0] += ww * g[0];
+        out[1] += ww * g[1];
+        out[2] += ww * g[2];
+      }
+}
+
+__global__ void __launch_bounds__(256) readout_g_kernel(const float* __restrict__ phi,
+                                                        const float* __restrict__ pos,
+                                                        float* __restrict__ out, int n,
+                                                        long long np) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
+  float g[3];
+  readout_g(phi, w, n, g);
+  out[i] = g[0];
+  out[np + i] = g[1];
+  out[2 * np + i] = g[2];
+}
+
+__device__ __forceinline__ float wrap_pos(float x, float fn) {
+  x -= fn * floorf(x / fn);
+  if (x >= fn) x -= fn;
+  return x;
+}
+
+__global__ void __launch_bounds__(256) kick_drift_kernel(const float* __restrict__ phi,
+                                                         float* __restrict__ pos,
+                                                         float* __restrict__ mom,
+                                                         uint32_t* __restrict__ key, float h,
+                                                         float drift_fac, int n, long long np) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  float x[3] = {pos[i], pos[np + i], pos[2 * np + i]};
+  const Cic w = cic_of(x[0], x[1], x[2], n);
+  float g[3];
+  readout_g(phi, w, n, g);
+  const float fn = static_cast<float>(n);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float p = mom[d * np + i] + h * g[d];
+    mom[d * np + i] = p;
+    x[d] = wrap_pos(x[d] + p * drift_fac, fn);
+    pos[d * np + i] = x[d];
+  }
+  const Cic w2 = cic_of(x[0], x[1], x[2], n);
+  key[i] = static_cast<uint32_t>((w2.i0[2] * n + w2.i0[1]) * n + w2.i0[0]);
+}
+
+__global__ void __launch_bounds__(256) kick_kernel(const float* __restrict__ phi,
+                                                   const float* __restrict__ pos,
+                                                   float* __restrict__ mom, float h, int n,
+                                                   long long np) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
+  float g[3];
+  readout_g(phi, w, n, g);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) mom[d * np + i] += h * g[d];
+}
+
+// lam_x += h * sum_corners (dw/dx) (g_corner . lam_p)
+__global__ void __launch_bounds__(256) kick_vjp_pos_kernel(const float* __restrict__ phi,
+                                                           const float* __restrict__ pos,
+                                                           const float* __restrict__ lam_p,
+                                                           float h, float* __restrict__ lam_x,
+                                                           int n, long long np) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
+  const float lp[3] = {lam_p[i], lam_p[np + i], lam_p[2 * np + i]};
+  float acc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        float g[3];
+        grid_g(phi, wrapi(w.i0[0] + ox, n), wrapi(w.i0[1] + oy, n), wrapi(w.i0[2] + oz, n), n, g);
+        const float gl = g[0] * lp[0] + g[1] * lp[1] + g[2] * lp[2];
+        const float wx = wsel(w.w1[0], ox), wy = wsel(w.w1[1], oy), wz = wsel(w.w1[2], oz);
+        acc[0] += (ox ? 1.0f : -1.0f) * wy * wz * gl;
+        acc[1] += wx * (oy ? 1.0f : -1.0f) * wz * gl;
+        acc[2] += wx * wy * (oz ? 1.0f : -1.0f) * gl;
+      }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) lam_x[d * np + i] += h * acc[d];
+}
+
+// lam_x += mass * sum_corners lam_delta[corner] dw/dx
+__global__ void __launch_bounds__(256) deposit_vjp_pos_kernel(const float* __restrict__ lam_delta,
+                                                              const float* __restrict__ pos,
+                                                              float mass, float* __restrict__ lam_x,
+                                                              int n, long long np) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
+  float acc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        const long long c = (static_cast<long long>(wrapi(w.i0[2] + oz, n)) * n +
+                             wrapi(w.i0[1] + oy, n)) * n + wrapi(w.i0[0] + ox, n);
+        const float l = lam_delta[c];
+        const float wx = wsel(w.w1[0], ox), wy = wsel(w.w1[1], oy), wz = wsel(w.w1[2], oz);
+        acc[0] += (ox ? 1.0f : -1.0f) * wy * wz * l;
+        acc[1] += wx * (oy ? 1.0f : -1.0f) * wz * l;
+        acc[2] += wx * wy * (oz ? 1.0f : -1.0f) * l;
+      }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) lam_x[d * np + i] += mass * acc[d];
+}
+
+__global__ void axpy_kernel(float* __restrict__ y, const float* __restrict__ x, float a,
+                            long long count) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) y[i] += a * x[i];
+}
+
+// lam_phi[c] = lam_phi_in[c] + sum_d (lam_g_d[c + e_d] - lam_g_d[c - e_d]) / 2
+__global__ void __launch_bounds__(256) grad_vjp_kernel(const float* __restrict__ lam_g,
+                                                       const float* __restrict__ lam_phi_in,
+                                                       float* __restrict__ lam_phi, int n) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long nn = static_cast<long long>(n) * n, nc = nn * n;
+  if (c >= nc) return;
+  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
+            iz = static_cast<int>(c / nn);
+  const long long zo = static_cast<long long>(iz) * nn, yo = static_cast<long long>(iy) * n;
+  float v = lam_phi_in ? lam_phi_in[c] : 0.0f;
+  v += 0.5f * (lam_g[zo + yo + wrapi(ix + 1, n)] - lam_g[zo + yo + wrapi(ix - 1, n)]);
+  v += 0.5f * (lam_g[nc + zo + static_cast<long long>(wrapi(iy + 1, n)) * n + ix] -
+               lam_g[nc + zo + static_cast<long long>(wrapi(iy - 1, n)) * n + ix]);
+  v += 0.5f * (lam_g[2 * nc + static_cast<long long>(wrapi(iz + 1, n)) * nn + yo + ix] -
+               lam_g[2 * nc + static_cast<long long>(wrapi(iz - 1, n)) * nn + yo + ix]);
+  lam_phi[c] = v;
+}
+
+}  // namespace
+
+size_t scan_block_count(long long nc) { return static_cast<size_t>((nc + kScanTile - 1) / kScanTile); }
+
+void launch_keys(hipStream_t st, const float* pos, uint32_t* key, int n) {
+  const long long np = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(keys_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, pos, key, n, np);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_sort(hipStream_t st, const Bins& b, int n) {
+  const long long nc = static_cast<long long>(n) * n * n, np = nc;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.count, 0u, nc);
+  DH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(hist_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, b.key, b.count,
+                     b.rank, np);
+  DH_LAUNCH_CHECK();
+  const int nb = static_cast<int>(scan_block_count(nc));
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kScanThreads), 0, st, b.count,
+                     b.block_sums, nc);
+  DH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(kScanThreads), 0, st, b.block_sums, nb);
+  DH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(scan_final_kernel, dim3(nb), dim3(kScanThreads), 0, st, b.count,
+                     b.block_sums, b.start, nc);
+  DH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, b.key, b.rank,
+                     b.start, b.sorted, np);
+  DH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(bin_sort_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.start,
+                     b.sorted, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_deposit(hipStream_t st, const Bins& b, const float* pos, const float* rho_gas,
+                    float m_dm, float offset, float* out, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(deposit_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.start,
+                     b.sorted, pos, rho_gas, m_dm, offset, out, n, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_deposit_vec(hipStream_t st, const Bins& b, const float* pos, const float* v,
+                        float scale, float* out_accum, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(deposit_vec_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.start,
+                     b.sorted, pos, v, scale, out_accum, n, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_readout_g(hipStream_t st, const float* phi, const float* pos, float* out, int n) {
+  const long long np = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(readout_g_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, phi, pos, out,
+                     n, np);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_kick_drift(hipStream_t st, const float* phi, float* pos, float* mom, uint32_t* key,
+                       float h_kick, float drift_fac, int n) {
+  const long long np = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(kick_drift_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, phi, pos, mom,
+                     key, h_kick, drift_fac, n, np);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_kick(hipStream_t st, const float* phi, const float* pos, float* mom, float h_kick,
+                 int n) {
+  const long long np = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(kick_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, phi, pos, mom,
+                     h_kick, n, np);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_kick_vjp_pos(hipStream_t st, const float* phi, const float* pos, const float* lam_p,
+                         float h_kick, float* lam_x, int n) {
+  const long long np = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(kick_vjp_pos_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, phi, pos,
+                     lam_p, h_kick, lam_x, n, np);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_deposit_vjp_pos(hipStream_t st, const float* lam_delta, const float* pos, float mass,
+                            float* lam_x, int n) {
+  const long long np = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(deposit_vjp_pos_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st,
+                     lam_delta, pos, mass, lam_x, n, np);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long count) {
+  hipLaunchKernelGGL(axpy_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, st, y, x, a, count);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_grad_vjp(hipStream_t st, const float* lam_g, const float* lam_phi_in, float* lam_phi,
+                     int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(grad_vjp_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, lam_g,
+                     lam_phi_in, lam_phi, n);
+  DH_LAUNCH_CHECK();
+}
+
+}  // namespace dh

@@ -1,0 +1,526 @@
+// Pointwise kernels and FP64 reductions: gravity source of the gas (operator-split kick),
+// stochastic star formation with supernova heating and its Gumbel-softmax relaxation
+// (Sec. 2.4), the CFL speed (eq. dt), conservation sums, the flux-field loss, and the
+// initial-condition helpers (Sec. 2.1); with the adjoints of the differentiable ones.
+// All reductions are two-pass with a fixed order, so results are reproducible bit for bit.
+#include <cmath>
+
+#include "dh_kernels.h"
+
+namespace dh {
+
+namespace {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedPer = 8;   // cells per thread in reduction kernels
+
+__device__ __forceinline__ int wrapi(int j, int n) { return j & (n - 1); }
+
+__device__ __forceinline__ void cell_g(const float* __restrict__ phi, long long c, int n, float g[3]) {
+  const long long nn = static_cast<long long>(n) * n;
+  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
+            iz = static_cast<int>(c / nn);
+  const long long zo = static_cast<long long>(iz) * nn, yo = static_cast<long long>(iy) * n;
+  g[0] = -0.5f * (phi[zo + yo + wrapi(ix + 1, n)] - phi[zo + yo + wrapi(ix - 1, n)]);
+  g[1] = -0.5f * (phi[zo + static_cast<long long>(wrapi(iy + 1, n)) * n + ix] -
+                  phi[zo + static_cast<long long>(wrapi(iy - 1, n)) * n + ix]);
+  g[2] = -0.5f * (phi[static_cast<long long>(wrapi(iz + 1, n)) * nn + yo + ix] -
+                  phi[static_cast<long long>(wrapi(iz - 1, n)) * nn + yo + ix]);
+}
+
+// block reduction of nv doubles per thread into out[v * gridDim.x + blockIdx.x]
+template <int NV, bool MAX>
+__device__ void block_reduce_store(double (&v)[NV], double* out) {
+  __shared__ double sh[NV][kRedThreads];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) sh[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+        sh[k][threadIdx.x] = MAX ? fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + off])
+                                 : sh[k][threadIdx.x] + sh[k][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k * gridDim.x + blockIdx.x] = sh[k][0];
+  }
+}
+
+// ------------------------------------------------------------------------- gas kick
+// m' = m + rho g h ; Et' = Et + h g . (m + m')/2   (internal energy unchanged)
+__global__ void __launch_bounds__(256) gas_kick_kernel(float* __restrict__ q,
+                                                       const float* __restrict__ phi, float h,
+                                                       int n, long long nc) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  float g[3];
+  cell_g(phi, c, n, g);
+  const float rho = q[c];
+  float de = 0.0f;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float m0 = q[(1 + d) * nc + c];
+    const float m1 = m0 + rho * g[d] * h;
+    q[(1 + d) * nc + c] = m1;
+    de += 0.5f * (m0 + m1) * g[d];
+  }
+  q[4 * nc + c] += de * h;
+}
+
+__global__ void __launch_bounds__(256) gas_kick_vjp_kernel(const float* __restrict__ q,
+                                                           const float* __restrict__ phi, float h,
+                                                           float* __restrict__ lam,
+                                                           float* __restrict__ lam_g, int n,
+                                                           long long nc) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  float g[3];
+  cell_g(phi, c, n, g);
+  const float rho = q[c];
+  const float le = lam[4 * nc + c];
+  float lr = lam[c];
+  float g2 = 0.0f;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float lm = lam[(1 + d) * nc + c];
+    const float m = q[(1 + d) * nc + c];
+    lr += h * lm * g[d];
+    g2 += g[d] * g[d];
+    lam[(1 + d) * nc + c] = lm + le * h * g[d];
+    lam_g[d * nc + c] = h * rho * lm + le * (h * m + h * h * rho * g[d]);
+  }
+  lam[c] = lr + le * 0.5f * h * h * g2;
+}
+
+// ------------------------------------------------------------------------- source term
+struct SrcCell {
+  float rho, delta, e, eraw, temp, x, psf, s1, s2, pi0, z, u;
+  bool floored;
+};
+
+__device__ __forceinline__ float sigmoidf_(float y) { return 1.0f / (1.0f + expf(-y)); }
+__device__ __forceinline__ float log_sigmoidf_(float y) {
+  return fminf(y, 0.0f) - log1pf(expf(-fabsf(y)));
+}
+
+__device__ SrcCell source_eval(const float* __restrict__ q, long long c, long long nc,
+                               const SourceArgs& a) {
+  SrcCell s;
+  s.rho = q[c];
+  const float ir = 1.0f / s.rho;
+  const float ia = 1.0f / a.a;
+  const float u0 = q[nc + c] * ia * ir, u1 = q[2 * nc + c] * ia * ir, u2 = q[3 * nc + c] * ia * ir;
+  s.eraw = q[4 * nc + c] * ia * ia * ir - 0.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+  s.floored = s.eraw < a.efloor;
+  s.e = s.floored ? a.efloor : s.eraw;
+  s.temp = s.e * a.t_per_e;
+  s.delta = s.rho * a.inv_rho_mean;
+  const float tff = 1.5707963267948966f * sqrtf(a.a * a.a * a.a / (a.omega_b * s.delta));
+  s.x = a.eps_sf * a.dt / tff;
+  s.psf = -expm1f(-s.x);
+  uint32_t ctr[4] = {static_cast<uint32_t>(c), a.step, kTagStarform, 0u};
+  philox4x32_10(ctr, a.seed_lo, a.seed_hi);
+  s.u = uniform_open_f(ctr[0]);
+  if (a.mode == 1) {
+    const float gate = (s.delta > a.delta_c && s.temp < a.t_c) ? 1.0f : 0.0f;
+    s.s1 = s.s2 = gate;
+    s.pi0 = s.psf * gate;
+    s.z = s.u > 1.0f - s.pi0 ? 1.0f : 0.0f;
+  } else {
+    const float y1 = (s.delta - a.delta_c) / (a.w_rho * a.delta_c);
+    const float y2 = (a.t_c - s.temp) / (a.w_t * a.t_c);
+    s.s1 = sigmoidf_(y1);
+    s.s2 = sigmoidf_(y2);
+    s.pi0 = s.psf * s.s1 * s.s2;
+    const float logpi = logf(s.psf) + log_sigmoidf_(y1) + log_sigmoidf_(y2);
+    const float logit = logpi - log1pf(-s.pi0);
+    const float noise = logf(s.u) - log1pf(-s.u);
+    s.z = sigmoidf_((logit + noise) / a.tau);
+  }
+  return s;
+}
+
+__global__ void __launch_bounds__(256) source_kernel(float* __restrict__ q, float* __restrict__ star,
+                                                     SourceArgs a, long long nc) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const SrcCell s = source_eval(q, c, nc, a);
+  q[4 * nc + c] += a.a * a.a * s.rho * s.z * a.e0_code;
+  star[c] += s.z;
+}
+
+// lam (in: adjoint after the source, out: before); partial[0|1][block] = dL/d(eps_sf|delta_c)
+__global__ void __launch_bounds__(kRedThreads) source_vjp_kernel(const float* __restrict__ q,
+                                                                 float* __restrict__ lam,
+                                                                 SourceArgs a, double* partial,
+                                                                 long long nc) {
+  double acc[2] = {0.0, 0.0};
+  const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
+  for (int r = 0; r < kRedPer; ++r) {
+    const long long c = base + r * kRedThreads + threadIdx.x;
+    if (c >= nc) break;
+    const SrcCell s = source_eval(q, c, nc, a);
+    const float le = lam[4 * nc + c];
+    const float K = a.a * a.a * a.e0_code;
+    // Et' = Et + K rho z
+    float lr = lam[c] + le * K * s.z;
+    if (a.mode != 1 && le != 0.0f) {
+      const float dz = s.z * (1.0f - s.z) / a.tau / (1.0f - s.pi0);   // dz / dln(pi0)
+      const float coef = le * K * s.rho * dz;
+      // dln p_sf / dx = 1 / expm1(x);  x ~ sqrt(rho)
+      const float dlp_dx = 1.0f / expm1f(s.x);
+      const float dlnpi_drho_sf = dlp_dx * s.x * 0.5f / s.rho;
+      const float dlnpi_drho_s1 = (1.0f - s.s1) * a.inv_rho_mean / (a.w_rho * a.delta_c);
+      // s2 through T(e)
+      const float dlnpi_dT = -(1.0f - s.s2) / (a.w_t * a.t_c);
+      const float dT = s.floored ? 0.0f : a.t_per_e;
+      const float ir = 1.0f / s.rho, ia = 1.0f / a.a;
+      float u[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) u[d] = q[(1 + d) * nc + c] * ia * ir;
+      const float ke = 0.5f * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      const float de_drho = (ke - s.eraw) * ir;
+      lr += coef * (dlnpi_drho_sf + dlnpi_drho_s1 + dlnpi_dT * dT * de_drho);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        lam[(1 + d) * nc + c] += coef * dlnpi_dT * dT * (-u[d] * ia * ir);
+      lam[4 * nc + c] = le + coef * dlnpi_dT * dT * (ia * ia * ir);
+      acc[0] += static_cast<double>(coef) * (dlp_dx * s.x / a.eps_sf);
+      acc[1] += static_cast<double>(coef) *
+                ((1.0f - s.s1) * (-s.delta / (a.w_rho * a.delta_c * a.delta_c)));
+    }
+    lam[c] = lr;
+  }
+  block_reduce_store<2, false>(acc, partial);
+}
+
+// ------------------------------------------------------------------------- CFL
+__global__ void __launch_bounds__(kRedThreads) cfl_partial_kernel(const float* __restrict__ q,
+                                                                  double a, double gg1,
+                                                                  double efloor, double* partial,
+                                                                  long long nc) {
+  double v[1] = {0.0};
+  const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
+  for (int r = 0; r < kRedPer; ++r) {
+    const long long c = base + r * kRedThreads + threadIdx.x;
+    if (c >= nc) break;
+    const double rho = q[c];
+    const double ia = 1.0 / a;
+    const double u0 = q[nc + c] * ia / rho, u1 = q[2 * nc + c] * ia / rho,
+                 u2 = q[3 * nc + c] * ia / rho;
+    double e = q[4 * nc + c] * ia * ia / rho - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+    e = fmax(e, efloor);
+    const double cs = sqrt(gg1 * e);
+    double s = (fmax(fabs(u0), fmax(fabs(u1), fabs(u2))) + cs) * ia;
+    if (!(rho > 0.0) || !isfinite(s)) s = INFINITY;   // flags a broken state
+    v[0] = fmax(v[0], s);
+  }
+  block_reduce_store<1, true>(v, partial);
+}
+
+// single block: out[v] = reduce over in[v * stride + 0..count)
+__global__ void __launch_bounds__(kRedThreads) reduce_kernel(const double* __restrict__ in,
+                                                             int count, int stride, int is_max,
+                                                             double* out) {
+  __shared__ double sh[kRedThreads];
+  const int v = blockIdx.x;
+  double acc = is_max ? -INFINITY : 0.0;
+  for (int i = threadIdx.x; i < count; i += kRedThreads) {
+    const double x = in[static_cast<long long>(v) * stride + i];
+    acc = is_max ? fmax(acc, x) : acc + x;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      sh[threadIdx.x] = is_max ? fmax(sh[threadIdx.x], sh[threadIdx.x + off])
+                               : sh[threadIdx.x] + sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = sh[0];
+}
+
+// ------------------------------------------------------------------------- sums
+__global__ void __launch_bounds__(kRedThreads) conservation_kernel(const float* __restrict__ q,
+                                                                   const float* __restrict__ mom,
+                                                                   double* partial, long long nc) {
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
+  for (int r = 0; r < kRedPer; ++r) {
+    const long long c = base + r * kRedThreads + threadIdx.x;
+    if (c >= nc) break;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] += q[k * nc + c];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[5 + k] += mom[k * nc + c];
+  }
+  block_reduce_store<8, false>(v, partial);
+}
+
+__global__ void __launch_bounds__(kRedThreads) loss_kernel(const float* __restrict__ rho,
+                                                           const float* __restrict__ target,
+                                                           double A, double beta, double irm,
+                                                           double* partial, long long nc) {
+  double v[1] = {0.0};
+  const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
+  for (int r = 0; r < kRedPer; ++r) {
+    const long long c = base + r * kRedThreads + threadIdx.x;
+    if (c >= nc) break;
+    const double f = exp(-A * pow(rho[c] * irm, beta));
+    const double d = f - target[c];
+    v[0] += d * d;
+  }
+  block_reduce_store<1, false>(v, partial);
+}
+
+// lam_rho = scale * 2 (F - F_t) dF/drho / nc ; partial[0|1] = dL/dA, dL/dbeta
+__global__ void __launch_bounds__(kRedThreads) loss_vjp_kernel(const float* __restrict__ rho,
+                                                               const float* __restrict__ target,
+                                                               double A, double beta, double irm,
+                                                               float* __restrict__ lam_rho,
+                                                               double* partial, long long nc) {
+  double v[2] = {0.0, 0.0};
+  const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
+  const double w = 2.0 / static_cast<double>(nc);
+  for (int r = 0; r < kRedPer; ++r) {
+    const long long c = base + r * kRedThreads + threadIdx.x;
+    if (c >= nc) break;
+    const double dl = rho[c] * irm;
+    const double db = pow(dl, beta);
+    const double f = exp(-A * db);
+    const double g = w * (f - target[c]) * f;
+    lam_rho[c] = static_cast<float>(g * (-A * beta * db / dl) * irm);
+    v[0] += g * (-db);
+    v[1] += g * (-A * db * log(dl));
+  }
+  block_reduce_store<2, false>(v, partial);
+}
+
+__global__ void flux_kernel(const float* __restrict__ rho, double A, double beta, double irm,
+                            float* __restrict__ out, long long nc) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  out[c] = static_cast<float>(exp(-A * pow(rho[c] * irm, beta)));
+}
+
+__global__ void temperature_kernel(const float* __restrict__ q, float a, float efloor,
+                                   float t_per_e, float* __restrict__ out, long long nc) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const float rho = q[c], ia = 1.0f / a;
+  const float u0 = q[nc + c] * ia / rho, u1 = q[2 * nc + c] * ia / rho, u2 = q[3 * nc + c] * ia / rho;
+  const float e = q[4 * nc + c] * ia * ia / rho - 0.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+  out[c] = fmaxf(e, efloor) * t_per_e;
+}
+
+// ------------------------------------------------------------------------- initial conditions
+__global__ void white_noise_kernel(float* __restrict__ out, uint32_t k0, uint32_t k1,
+                                   long long nc) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  uint32_t ctr[4] = {static_cast<uint32_t>(c), 0u, kTagWhite, 0u};
+  philox4x32_10(ctr, k0, k1);
+  const double u1 = uniform_open_d(ctr[0]), u2 = uniform_open_d(ctr[1]);
+  out[c] = static_cast<float>(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+}
+
+__global__ void ic_particles_kernel(const float* __restrict__ psi, float* __restrict__ pos,
+                                    float* __restrict__ mom, float vfac, int n, long long np) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const int l[3] = {static_cast<int>(i % n), static_cast<int>((i / n) % n),
+                    static_cast<int>(i / (static_cast<long long>(n) * n))};
+  const float fn = static_cast<float>(n);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float s = psi[d * np + i];
+    float x = static_cast<float>(l[d]) + 0.5f + s;
+    x -= fn * floorf(x / fn);
+    if (x >= fn) x -= fn;
+    pos[d * np + i] = x;
+    mom[d * np + i] = vfac * s;
+  }
+}
+
+__global__ void ic_gas_kernel(const float* __restrict__ cic, const float* __restrict__ psi,
+                              float* __restrict__ q, float f_b, float vfac, float a, float e_init,
+                              long long nc) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const float rho = f_b * cic[c];
+  q[c] = rho;
+  float u2 = 0.0f;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float p = vfac * psi[d * nc + c];
+    q[(1 + d) * nc + c] = rho * p;
+    const float u = p / a;
+    u2 += u * u;
+  }
+  q[4 * nc + c] = a * a * rho * (e_init + 0.5f * u2);
+}
+
+// adjoint of ic_gas: lam_cic = f_b * lam_rho_total ; lam_psi += contributions
+__global__ void ic_gas_vjp_kernel(const float* __restrict__ cic, const float* __restrict__ psi,
+                                  const float* __restrict__ lam, float f_b, float vfac, float a,
+                                  float e_init, float* __restrict__ lam_cic,
+                                  float* __restrict__ lam_psi, long long nc) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const float rho = f_b * cic[c];
+  const float le = lam[4 * nc + c];
+  float lr = lam[c];
+  float p2 = 0.0f;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float p = vfac * psi[d * nc + c];
+    const float lm = lam[(1 + d) * nc + c];
+    lr += lm * p;
+    p2 += p * p;
+    // Et = a^2 rho e_init + rho |p|^2 / 2
+    lam_psi[d * nc + c] += vfac * (lm * rho + le * rho * p);
+  }
+  lr += le * (a * a * e_init + 0.5f * p2);
+  lam_cic[c] = f_b * lr;
+}
+
+__global__ void fill_kernel(float* p, float v, long long count) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+}  // namespace
+
+void launch_gas_kick(hipStream_t st, float* q, const float* phi, float h, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(gas_kick_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, phi, h, n, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float* phi, float h,
+                         float* lam_q, float* lam_g, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(gas_kick_vjp_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q_before,
+                     phi, h, lam_q, lam_g, n, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_source(hipStream_t st, float* q, float* star, const SourceArgs& a, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(source_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, star, a, nc);
+  DH_LAUNCH_CHECK();
+}
+
+int sum_blocks(long long count) {
+  return static_cast<int>((count + kRedThreads * kRedPer - 1) / (kRedThreads * kRedPer));
+}
+int source_vjp_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n * n); }
+int cfl_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n * n); }
+
+void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, const SourceArgs& a,
+                       double* partials, int nblocks_out, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(source_vjp_kernel, dim3(nblocks_out), dim3(kRedThreads), 0, st, q_before,
+                     lam_q, a, partials, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_cfl_partial(hipStream_t st, const float* q, float a, float gamma, float efloor,
+                        double* block_max, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(cfl_partial_kernel, dim3(cfl_blocks(n)), dim3(kRedThreads), 0, st, q,
+                     static_cast<double>(a), static_cast<double>(gamma) * (gamma - 1.0),
+                     static_cast<double>(efloor), block_max, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_reduce_max(hipStream_t st, const double* in, int count, double* out) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kRedThreads), 0, st, in, count, count, 1, out);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_reduce_sum(hipStream_t st, const double* in, int count, int stride, int nvec,
+                       double* out) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(nvec), dim3(kRedThreads), 0, st, in, count, stride, 0, out);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_conservation_partial(hipStream_t st, const float* q, const float* mom,
+                                 double* partial, int nblocks, long long nc) {
+  hipLaunchKernelGGL(conservation_kernel, dim3(nblocks), dim3(kRedThreads), 0, st, q, mom,
+                     partial, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_loss_partial(hipStream_t st, const float* rho, const float* target, double A,
+                         double beta, float inv_rho_mean, double* partial, int nblocks,
+                         long long nc) {
+  hipLaunchKernelGGL(loss_kernel, dim3(nblocks), dim3(kRedThreads), 0, st, rho, target, A, beta,
+                     static_cast<double>(inv_rho_mean), partial, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_loss_vjp(hipStream_t st, const float* rho, const float* target, double A, double beta,
+                     float inv_rho_mean, float* lam_rho, double* partial, int nblocks,
+                     long long nc) {
+  hipLaunchKernelGGL(loss_vjp_kernel, dim3(nblocks), dim3(kRedThreads), 0, st, rho, target, A, beta,
+                     static_cast<double>(inv_rho_mean), lam_rho, partial, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_flux_field(hipStream_t st, const float* rho, double A, double beta, float inv_rho_mean,
+                       float* out, long long nc) {
+  hipLaunchKernelGGL(flux_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, rho, A, beta,
+                     static_cast<double>(inv_rho_mean), out, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_temperature(hipStream_t st, const float* q, float a, float efloor, float t_per_e,
+                        float* out, long long nc) {
+  hipLaunchKernelGGL(temperature_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, a, efloor,
+                     t_per_e, out, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_white_noise(hipStream_t st, float* out, uint32_t seed_lo, uint32_t seed_hi, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(white_noise_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, out, seed_lo,
+                     seed_hi, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_ic_particles(hipStream_t st, const float* psi, float* pos, float* mom, float vfac,
+                         int n) {
+  const long long np = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(ic_particles_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, psi, pos, mom,
+                     vfac, n, np);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_ic_gas(hipStream_t st, const float* cic, const float* psi, float* q, float f_b,
+                   float vfac, float a, float e_init, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(ic_gas_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, cic, psi, q, f_b,
+                     vfac, a, e_init, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const float* lam_q,
+                       float f_b, float vfac, float a, float e_init, float* lam_cic,
+                       float* lam_psi, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(ic_gas_vjp_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, cic, psi,
+                     lam_q, f_b, vfac, a, e_init, lam_cic, lam_psi, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_fill(hipStream_t st, float* p, float v, long long count) {
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, st, p, v, count);
+  DH_LAUNCH_CHECK();
+}
+
+}  // namespace dh

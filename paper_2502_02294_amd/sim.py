@@ -1,0 +1,187 @@
+"""Python face of libdiffhydro: a handle over the C ABI with PyTorch tensors for device
+memory.  Every computation runs in the library's HIP kernels; this module only checks
+shapes and passes pointers."""
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (FIELD_FLUX, FIELD_MOM, FIELD_PHI, FIELD_POS, FIELD_Q, FIELD_RHO, FIELD_STAR,
+                   FIELD_TEMP, Config, Params, check, lib)
+
+_FIELD_SHAPE = {FIELD_Q: (5,), FIELD_RHO: (), FIELD_POS: (3,), FIELD_MOM: (3,), FIELD_STAR: (),
+                FIELD_PHI: (), FIELD_TEMP: (), FIELD_FLUX: ()}
+FIELDS = {"q": FIELD_Q, "rho": FIELD_RHO, "pos": FIELD_POS, "mom": FIELD_MOM, "star": FIELD_STAR,
+          "phi": FIELD_PHI, "temp": FIELD_TEMP, "flux": FIELD_FLUX}
+
+
+def default_config(**kw):
+    c = Config()
+    lib().dh_config_default(ctypes.byref(c))
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+def default_params(**kw):
+    p = Params()
+    lib().dh_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t, dtype=torch.float32, numel=None):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Sim:
+    """One simulation handle on the current HIP device."""
+
+    def __init__(self, config=None, params=None, **cfg_kw):
+        self.cfg = config if config is not None else default_config(**cfg_kw)
+        self.n = int(self.cfg.n)
+        self.nc = self.n ** 3
+        self._h = ctypes.c_void_p()
+        torch.cuda.init()
+        check(lib().dh_create(ctypes.byref(self.cfg), ctypes.byref(self._h)))
+        stream = torch.cuda.current_stream().cuda_stream
+        check(lib().dh_set_stream(self._h, ctypes.c_void_p(stream)), self._h)
+        self.params = params if params is not None else default_params()
+        self.set_params(self.params)
+
+    def close(self):
+        if self._h:
+            lib().dh_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        check(rc, self._h)
+
+    def set_params(self, p=None, **kw):
+        if p is None:
+            p = self.params
+        for k, v in kw.items():
+            setattr(p, k, v)
+        self.params = p
+        self._check(lib().dh_set_params(self._h, ctypes.byref(p)))
+
+    def init_from_seed(self, seed):
+        self._check(lib().dh_init_from_seed(self._h, ctypes.c_uint64(seed)))
+
+    def init_from_noise(self, white):
+        self._check(lib().dh_init_from_noise(self._h, _ptr(white, numel=self.nc)))
+
+    def step(self):
+        dt, a = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().dh_step(self._h, ctypes.byref(dt), ctypes.byref(a)))
+        return dt.value, a.value
+
+    def run_to(self, a_final):
+        k = ctypes.c_int32()
+        self._check(lib().dh_run_to(self._h, a_final, ctypes.byref(k)))
+        return k.value
+
+    def set_schedule(self, dts):
+        arr = (ctypes.c_double * len(dts))(*[float(x) for x in dts])
+        self._check(lib().dh_set_schedule(self._h, arr, len(dts)))
+
+    def get_schedule(self):
+        n = ctypes.c_int32()
+        self._check(lib().dh_get_schedule(self._h, None, 0, ctypes.byref(n)))
+        arr = (ctypes.c_double * max(1, n.value))()
+        self._check(lib().dh_get_schedule(self._h, arr, n.value, ctypes.byref(n)))
+        return list(arr[:n.value])
+
+    def get(self, name):
+        f = FIELDS[name]
+        out = torch.empty(_FIELD_SHAPE[f] + (self.n, self.n, self.n), dtype=torch.float32,
+                          device="cuda")
+        self._check(lib().dh_get_field(self._h, f, _ptr(out)))
+        if f in (FIELD_POS, FIELD_MOM):
+            out = out.reshape(3, self.nc)
+        return out
+
+    def set(self, name, t):
+        f = FIELDS[name]
+        numel = self.nc * (5 if f == FIELD_Q else 3 if f in (FIELD_POS, FIELD_MOM) else 1)
+        self._check(lib().dh_set_field(self._h, f, _ptr(t.contiguous(), numel=numel)))
+
+    def refresh_potential(self):
+        self._check(lib().dh_refresh_potential(self._h))
+
+    def time(self):
+        a, t, s = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        self._check(lib().dh_get_time(self._h, ctypes.byref(a), ctypes.byref(t), ctypes.byref(s)))
+        return a.value, t.value, s.value
+
+    def set_time(self, a, step):
+        self._check(lib().dh_set_time(self._h, a, step))
+
+    def forward(self, white, a_final):
+        k = ctypes.c_int32()
+        self._check(lib().dh_forward(self._h, _ptr(white, numel=self.nc), a_final, ctypes.byref(k)))
+        return k.value
+
+    def loss(self, target):
+        v = ctypes.c_double()
+        self._check(lib().dh_loss(self._h, _ptr(target, numel=self.nc), ctypes.byref(v)))
+        return v.value
+
+    def backward(self, grad_rho=None):
+        gw = torch.empty(self.n, self.n, self.n, dtype=torch.float32, device="cuda")
+        gp = (ctypes.c_double * 4)()
+        gr = _ptr(grad_rho.contiguous(), numel=self.nc) if grad_rho is not None else None
+        self._check(lib().dh_backward(self._h, gr, _ptr(gw), gp))
+        return gw, list(gp)
+
+    def conservation(self):
+        out = (ctypes.c_double * 8)()
+        self._check(lib().dh_conservation(self._h, out))
+        return list(out)
+
+    # single stages on caller buffers
+    def stage_sweep(self, q, axis, dt, a1, a2):
+        out = torch.empty_like(q)
+        self._check(lib().dh_stage_sweep(self._h, _ptr(q, numel=5 * self.nc), _ptr(out), axis, dt,
+                                         a1, a2))
+        return out
+
+    def stage_sweep_vjp(self, q, lam_out, axis, dt, a1, a2):
+        out = torch.empty_like(q)
+        self._check(lib().dh_stage_sweep_vjp(self._h, _ptr(q, numel=5 * self.nc),
+                                             _ptr(lam_out, numel=5 * self.nc), _ptr(out), axis,
+                                             dt, a1, a2))
+        return out
+
+    def stage_poisson(self, delta, a):
+        out = torch.empty_like(delta)
+        self._check(lib().dh_stage_poisson(self._h, _ptr(delta, numel=self.nc), _ptr(out), a))
+        return out
+
+    def stage_deposit(self, rho_gas, pos):
+        out = torch.empty_like(rho_gas)
+        self._check(lib().dh_stage_deposit(self._h, _ptr(rho_gas, numel=self.nc),
+                                           _ptr(pos, numel=3 * self.nc), _ptr(out)))
+        return out
+
+    def stage_readout(self, phi, pos):
+        out = torch.empty_like(pos)
+        self._check(lib().dh_stage_readout(self._h, _ptr(phi, numel=self.nc),
+                                           _ptr(pos, numel=3 * self.nc), _ptr(out)))
+        return out
