@@ -142,27 +142,38 @@ __device__ __forceinline__ void split_flux_vjp(const float q[5], const HydroK& h
 }
 
 // van Leer limiter with guard epsilon (Sec. 2.3.2):
-//   phi(x, y) = (x y + |x y|) / (x + y + eps sgn(x+y)),  sgn(0) = +1.
+//   phi(x, y) = (x y + |x y|) / (x + y + eps sgn(x+y)),  sgn(0) = +1,
+// evaluated as 2xy / (x + y + eps sgn) when xy > 0 and 0 otherwise.  The branch is the same
+// function; it matters in floating point: with fused multiply-add contraction the sum
+// x*y + |x*y| is not exactly zero for xy < 0, and where x ~ -y the residue would be divided by
+// a denominator of order eps.
 constexpr float kLimEps = 1e-20f;
 
 __device__ __forceinline__ float van_leer(float x, float y) {
-  const float s = x + y;
   const float xy = x * y;
-  return (xy + fabsf(xy)) / (s + (s >= 0.0f ? kLimEps : -kLimEps));
+  if (!(xy > 0.0f)) return 0.0f;
+  const float s = x + y;
+  return (2.0f * xy) / (s + (s >= 0.0f ? kLimEps : -kLimEps));
 }
 
-// Partial derivatives of van_leer (for xy == 0 the one-sided average used by the
-// derivative of |xy| with sign(0) = 0).
+// Partial derivatives of van_leer; where xy == 0 the derivative of |xy| is taken with
+// sign(0) = 0 (half the one-sided slopes), where xy < 0 both are zero.
 __device__ __forceinline__ void van_leer_d(float x, float y, float& dx, float& dy) {
+  const float xy = x * y;
   const float s = x + y;
   const float den = s + (s >= 0.0f ? kLimEps : -kLimEps);
-  const float xy = x * y;
-  const float sg = xy > 0.0f ? 1.0f : (xy < 0.0f ? -1.0f : 0.0f);
-  const float num = xy + fabsf(xy);
   const float id = 1.0f / den;
-  const float q = num * id * id;   // num * id first: no 0 * inf when den is ~eps
-  dx = (y + sg * y) * id - q;
-  dy = (x + sg * x) * id - q;
+  if (xy > 0.0f) {
+    const float q = (2.0f * xy) * id * id;
+    dx = 2.0f * y * id - q;
+    dy = 2.0f * x * id - q;
+  } else if (xy < 0.0f) {
+    dx = 0.0f;
+    dy = 0.0f;
+  } else {
+    dx = y * id;
+    dy = x * id;
+  }
 }
 
 // ---------------------------------------------------------------------------------------

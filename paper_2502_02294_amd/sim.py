@@ -54,8 +54,8 @@ class Sim:
         self._h = ctypes.c_void_p()
         torch.cuda.init()
         check(lib().dh_create(ctypes.byref(self.cfg), ctypes.byref(self._h)))
-        stream = torch.cuda.current_stream().cuda_stream
-        check(lib().dh_set_stream(self._h, ctypes.c_void_p(stream)), self._h)
+        self._stream_handle = None
+        self._stream()
         self.params = params if params is not None else default_params()
         self.set_params(self.params)
 
@@ -73,7 +73,16 @@ class Sim:
     def _check(self, rc):
         check(rc, self._h)
 
+    def _stream(self):
+        """Enqueue the library's work on torch's current stream, so that it is ordered with
+        the tensors passed in and out (allocation, copies, reuse by the caching allocator)."""
+        stream = torch.cuda.current_stream().cuda_stream
+        if stream != self._stream_handle:
+            check(lib().dh_set_stream(self._h, ctypes.c_void_p(stream)), self._h)
+            self._stream_handle = stream
+
     def set_params(self, p=None, **kw):
+        self._stream()
         if p is None:
             p = self.params
         for k, v in kw.items():
@@ -82,26 +91,32 @@ class Sim:
         self._check(lib().dh_set_params(self._h, ctypes.byref(p)))
 
     def init_from_seed(self, seed):
+        self._stream()
         self._check(lib().dh_init_from_seed(self._h, ctypes.c_uint64(seed)))
 
     def init_from_noise(self, white):
+        self._stream()
         self._check(lib().dh_init_from_noise(self._h, _ptr(white, numel=self.nc)))
 
     def step(self):
+        self._stream()
         dt, a = ctypes.c_double(), ctypes.c_double()
         self._check(lib().dh_step(self._h, ctypes.byref(dt), ctypes.byref(a)))
         return dt.value, a.value
 
     def run_to(self, a_final):
+        self._stream()
         k = ctypes.c_int32()
         self._check(lib().dh_run_to(self._h, a_final, ctypes.byref(k)))
         return k.value
 
     def set_schedule(self, dts):
+        self._stream()
         arr = (ctypes.c_double * len(dts))(*[float(x) for x in dts])
         self._check(lib().dh_set_schedule(self._h, arr, len(dts)))
 
     def get_schedule(self):
+        self._stream()
         n = ctypes.c_int32()
         self._check(lib().dh_get_schedule(self._h, None, 0, ctypes.byref(n)))
         arr = (ctypes.c_double * max(1, n.value))()
@@ -109,6 +124,7 @@ class Sim:
         return list(arr[:n.value])
 
     def get(self, name):
+        self._stream()
         f = FIELDS[name]
         out = torch.empty(_FIELD_SHAPE[f] + (self.n, self.n, self.n), dtype=torch.float32,
                           device="cuda")
@@ -118,32 +134,39 @@ class Sim:
         return out
 
     def set(self, name, t):
+        self._stream()
         f = FIELDS[name]
         numel = self.nc * (5 if f == FIELD_Q else 3 if f in (FIELD_POS, FIELD_MOM) else 1)
         self._check(lib().dh_set_field(self._h, f, _ptr(t.contiguous(), numel=numel)))
 
     def refresh_potential(self):
+        self._stream()
         self._check(lib().dh_refresh_potential(self._h))
 
     def time(self):
+        self._stream()
         a, t, s = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
         self._check(lib().dh_get_time(self._h, ctypes.byref(a), ctypes.byref(t), ctypes.byref(s)))
         return a.value, t.value, s.value
 
     def set_time(self, a, step):
+        self._stream()
         self._check(lib().dh_set_time(self._h, a, step))
 
     def forward(self, white, a_final):
+        self._stream()
         k = ctypes.c_int32()
         self._check(lib().dh_forward(self._h, _ptr(white, numel=self.nc), a_final, ctypes.byref(k)))
         return k.value
 
     def loss(self, target):
+        self._stream()
         v = ctypes.c_double()
         self._check(lib().dh_loss(self._h, _ptr(target, numel=self.nc), ctypes.byref(v)))
         return v.value
 
     def backward(self, grad_rho=None):
+        self._stream()
         gw = torch.empty(self.n, self.n, self.n, dtype=torch.float32, device="cuda")
         gp = (ctypes.c_double * 4)()
         gr = _ptr(grad_rho.contiguous(), numel=self.nc) if grad_rho is not None else None
@@ -151,18 +174,21 @@ class Sim:
         return gw, list(gp)
 
     def conservation(self):
+        self._stream()
         out = (ctypes.c_double * 8)()
         self._check(lib().dh_conservation(self._h, out))
         return list(out)
 
     # single stages on caller buffers
     def stage_sweep(self, q, axis, dt, a1, a2):
+        self._stream()
         out = torch.empty_like(q)
         self._check(lib().dh_stage_sweep(self._h, _ptr(q, numel=5 * self.nc), _ptr(out), axis, dt,
                                          a1, a2))
         return out
 
     def stage_sweep_vjp(self, q, lam_out, axis, dt, a1, a2):
+        self._stream()
         out = torch.empty_like(q)
         self._check(lib().dh_stage_sweep_vjp(self._h, _ptr(q, numel=5 * self.nc),
                                              _ptr(lam_out, numel=5 * self.nc), _ptr(out), axis,
@@ -170,17 +196,20 @@ class Sim:
         return out
 
     def stage_poisson(self, delta, a):
+        self._stream()
         out = torch.empty_like(delta)
         self._check(lib().dh_stage_poisson(self._h, _ptr(delta, numel=self.nc), _ptr(out), a))
         return out
 
     def stage_deposit(self, rho_gas, pos):
+        self._stream()
         out = torch.empty_like(rho_gas)
         self._check(lib().dh_stage_deposit(self._h, _ptr(rho_gas, numel=self.nc),
                                            _ptr(pos, numel=3 * self.nc), _ptr(out)))
         return out
 
     def stage_readout(self, phi, pos):
+        self._stream()
         out = torch.empty_like(pos)
         self._check(lib().dh_stage_readout(self._h, _ptr(phi, numel=self.nc),
                                            _ptr(pos, numel=3 * self.nc), _ptr(out)))
