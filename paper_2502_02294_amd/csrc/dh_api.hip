@@ -183,20 +183,19 @@ double cfl_speed(dh_sim* s, const float* q, double a) {
 
 dh::SourceArgs source_args(const dh_sim* s, const Plan& pl) {
   dh::SourceArgs a{};
-  a.a = static_cast<float>(pl.a1);
-  a.dt = static_cast<float>(pl.dt);
-  a.inv_rho_mean = static_cast<float>(1.0 / s->f_b);
-  a.omega_b = static_cast<float>(s->cfg.omega_b);
-  a.gm1 = static_cast<float>(s->cfg.gamma - 1.0);
-  a.efloor = static_cast<float>(s->e_floor);
-  a.t_per_e = static_cast<float>(s->t_per_e);
-  a.e0_code = static_cast<float>(s->prm.e0 * 1e6 / (s->vel_unit * s->vel_unit));
-  a.eps_sf = static_cast<float>(s->prm.eps_sf);
-  a.delta_c = static_cast<float>(s->prm.delta_c);
-  a.t_c = static_cast<float>(s->prm.t_c);
-  a.w_rho = static_cast<float>(s->prm.w_rho);
-  a.w_t = static_cast<float>(s->prm.w_t);
-  a.tau = static_cast<float>(s->cfg.tau);
+  a.a = pl.a1;
+  a.dt = pl.dt;
+  a.inv_rho_mean = 1.0 / s->f_b;
+  a.omega_b = s->cfg.omega_b;
+  a.efloor = s->e_floor;
+  a.t_per_e = s->t_per_e;
+  a.e0_code = s->prm.e0 * 1e6 / (s->vel_unit * s->vel_unit);
+  a.eps_sf = s->prm.eps_sf;
+  a.delta_c = s->prm.delta_c;
+  a.t_c = s->prm.t_c;
+  a.w_rho = s->prm.w_rho;
+  a.w_t = s->prm.w_t;
+  a.tau = s->cfg.tau;
   a.mode = s->cfg.subgrid;
   a.seed_lo = static_cast<uint32_t>(s->cfg.sf_seed & 0xFFFFFFFFull);
   a.seed_hi = static_cast<uint32_t>(s->cfg.sf_seed >> 32);

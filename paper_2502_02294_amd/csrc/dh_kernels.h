@@ -72,9 +72,9 @@ void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* t
 void launch_gas_kick(hipStream_t st, float* q, const float* phi, float h, int n);
 void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float* phi, float h,
                          float* lam_q, float* lam_g, int n);
-struct SourceArgs {
-  float a, dt, inv_rho_mean, omega_b, gm1, efloor, t_per_e, e0_code;
-  float eps_sf, delta_c, t_c, w_rho, w_t, tau;
+struct SourceArgs {   // FP64: the source term is evaluated in double precision
+  double a, dt, inv_rho_mean, omega_b, efloor, t_per_e, e0_code;
+  double eps_sf, delta_c, t_c, w_rho, w_t, tau;
   int mode;
   uint32_t seed_lo, seed_hi, step;
 };

@@ -97,49 +97,51 @@ __global__ void __launch_bounds__(256) gas_kick_vjp_kernel(const float* __restri
 }
 
 // ------------------------------------------------------------------------- source term
+// Evaluated in FP64 from the FP32 state (the kernel is memory bound, and the relaxed draw
+// sigma(x / tau) amplifies rounding of its argument by 1/tau).
 struct SrcCell {
-  float rho, delta, e, eraw, temp, x, psf, s1, s2, pi0, z, u;
+  double rho, delta, e, eraw, temp, x, psf, s1, s2, pi0, z, u;
   bool floored;
 };
 
-__device__ __forceinline__ float sigmoidf_(float y) { return 1.0f / (1.0f + expf(-y)); }
-__device__ __forceinline__ float log_sigmoidf_(float y) {
-  return fminf(y, 0.0f) - log1pf(expf(-fabsf(y)));
+__device__ __forceinline__ double sigmoid_(double y) { return 1.0 / (1.0 + exp(-y)); }
+__device__ __forceinline__ double log_sigmoid_(double y) {
+  return fmin(y, 0.0) - log1p(exp(-fabs(y)));
 }
 
 __device__ SrcCell source_eval(const float* __restrict__ q, long long c, long long nc,
                                const SourceArgs& a) {
   SrcCell s;
   s.rho = q[c];
-  const float ir = 1.0f / s.rho;
-  const float ia = 1.0f / a.a;
-  const float u0 = q[nc + c] * ia * ir, u1 = q[2 * nc + c] * ia * ir, u2 = q[3 * nc + c] * ia * ir;
-  s.eraw = q[4 * nc + c] * ia * ia * ir - 0.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+  const double ir = 1.0 / s.rho;
+  const double ia = 1.0 / a.a;
+  const double u0 = q[nc + c] * ia * ir, u1 = q[2 * nc + c] * ia * ir, u2 = q[3 * nc + c] * ia * ir;
+  s.eraw = q[4 * nc + c] * ia * ia * ir - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
   s.floored = s.eraw < a.efloor;
   s.e = s.floored ? a.efloor : s.eraw;
   s.temp = s.e * a.t_per_e;
   s.delta = s.rho * a.inv_rho_mean;
-  const float tff = 1.5707963267948966f * sqrtf(a.a * a.a * a.a / (a.omega_b * s.delta));
+  const double tff = 1.5707963267948966 * sqrt(a.a * a.a * a.a / (a.omega_b * s.delta));
   s.x = a.eps_sf * a.dt / tff;
-  s.psf = -expm1f(-s.x);
+  s.psf = -expm1(-s.x);
   uint32_t ctr[4] = {static_cast<uint32_t>(c), a.step, kTagStarform, 0u};
   philox4x32_10(ctr, a.seed_lo, a.seed_hi);
-  s.u = uniform_open_f(ctr[0]);
+  s.u = uniform_open_d(ctr[0]);
   if (a.mode == 1) {
-    const float gate = (s.delta > a.delta_c && s.temp < a.t_c) ? 1.0f : 0.0f;
+    const double gate = (s.delta > a.delta_c && s.temp < a.t_c) ? 1.0 : 0.0;
     s.s1 = s.s2 = gate;
     s.pi0 = s.psf * gate;
-    s.z = s.u > 1.0f - s.pi0 ? 1.0f : 0.0f;
+    s.z = s.u > 1.0 - s.pi0 ? 1.0 : 0.0;
   } else {
-    const float y1 = (s.delta - a.delta_c) / (a.w_rho * a.delta_c);
-    const float y2 = (a.t_c - s.temp) / (a.w_t * a.t_c);
-    s.s1 = sigmoidf_(y1);
-    s.s2 = sigmoidf_(y2);
+    const double y1 = (s.delta - a.delta_c) / (a.w_rho * a.delta_c);
+    const double y2 = (a.t_c - s.temp) / (a.w_t * a.t_c);
+    s.s1 = sigmoid_(y1);
+    s.s2 = sigmoid_(y2);
     s.pi0 = s.psf * s.s1 * s.s2;
-    const float logpi = logf(s.psf) + log_sigmoidf_(y1) + log_sigmoidf_(y2);
-    const float logit = logpi - log1pf(-s.pi0);
-    const float noise = logf(s.u) - log1pf(-s.u);
-    s.z = sigmoidf_((logit + noise) / a.tau);
+    const double logpi = log(s.psf) + log_sigmoid_(y1) + log_sigmoid_(y2);
+    const double logit = logpi - log1p(-s.pi0);
+    const double noise = log(s.u) - log1p(-s.u);
+    s.z = sigmoid_((logit + noise) / a.tau);
   }
   return s;
 }
@@ -149,8 +151,8 @@ __global__ void __launch_bounds__(256) source_kernel(float* __restrict__ q, floa
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   const SrcCell s = source_eval(q, c, nc, a);
-  q[4 * nc + c] += a.a * a.a * s.rho * s.z * a.e0_code;
-  star[c] += s.z;
+  q[4 * nc + c] = static_cast<float>(q[4 * nc + c] + a.a * a.a * s.rho * s.z * a.e0_code);
+  star[c] = static_cast<float>(star[c] + s.z);
 }
 
 // lam (in: adjoint after the source, out: before); partial[0|1][block] = dL/d(eps_sf|delta_c)
@@ -164,36 +166,36 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_kernel(const float* __
     const long long c = base + r * kRedThreads + threadIdx.x;
     if (c >= nc) break;
     const SrcCell s = source_eval(q, c, nc, a);
-    const float le = lam[4 * nc + c];
-    const float K = a.a * a.a * a.e0_code;
+    const double le = lam[4 * nc + c];
+    const double K = a.a * a.a * a.e0_code;
     // Et' = Et + K rho z
-    float lr = lam[c] + le * K * s.z;
-    if (a.mode != 1 && le != 0.0f) {
-      const float dz = s.z * (1.0f - s.z) / a.tau / (1.0f - s.pi0);   // dz / dln(pi0)
-      const float coef = le * K * s.rho * dz;
+    double lr = lam[c] + le * K * s.z;
+    if (a.mode != 1 && le != 0.0) {
+      const double dz = s.z * (1.0 - s.z) / a.tau / (1.0 - s.pi0);   // dz / dln(pi0)
+      const double coef = le * K * s.rho * dz;
       // dln p_sf / dx = 1 / expm1(x);  x ~ sqrt(rho)
-      const float dlp_dx = 1.0f / expm1f(s.x);
-      const float dlnpi_drho_sf = dlp_dx * s.x * 0.5f / s.rho;
-      const float dlnpi_drho_s1 = (1.0f - s.s1) * a.inv_rho_mean / (a.w_rho * a.delta_c);
+      const double dlp_dx = 1.0 / expm1(s.x);
+      const double dlnpi_drho_sf = dlp_dx * s.x * 0.5 / s.rho;
+      const double dlnpi_drho_s1 = (1.0 - s.s1) * a.inv_rho_mean / (a.w_rho * a.delta_c);
       // s2 through T(e)
-      const float dlnpi_dT = -(1.0f - s.s2) / (a.w_t * a.t_c);
-      const float dT = s.floored ? 0.0f : a.t_per_e;
-      const float ir = 1.0f / s.rho, ia = 1.0f / a.a;
-      float u[3];
+      const double dlnpi_dT = -(1.0 - s.s2) / (a.w_t * a.t_c);
+      const double dT = s.floored ? 0.0 : a.t_per_e;
+      const double ir = 1.0 / s.rho, ia = 1.0 / a.a;
+      double u[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) u[d] = q[(1 + d) * nc + c] * ia * ir;
-      const float ke = 0.5f * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-      const float de_drho = (ke - s.eraw) * ir;
+      const double ke = 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      const double de_drho = (ke - s.eraw) * ir;
       lr += coef * (dlnpi_drho_sf + dlnpi_drho_s1 + dlnpi_dT * dT * de_drho);
 #pragma unroll
       for (int d = 0; d < 3; ++d)
-        lam[(1 + d) * nc + c] += coef * dlnpi_dT * dT * (-u[d] * ia * ir);
-      lam[4 * nc + c] = le + coef * dlnpi_dT * dT * (ia * ia * ir);
-      acc[0] += static_cast<double>(coef) * (dlp_dx * s.x / a.eps_sf);
-      acc[1] += static_cast<double>(coef) *
-                ((1.0f - s.s1) * (-s.delta / (a.w_rho * a.delta_c * a.delta_c)));
+        lam[(1 + d) * nc + c] =
+            static_cast<float>(lam[(1 + d) * nc + c] + coef * dlnpi_dT * dT * (-u[d] * ia * ir));
+      lam[4 * nc + c] = static_cast<float>(le + coef * dlnpi_dT * dT * (ia * ia * ir));
+      acc[0] += coef * (dlp_dx * s.x / a.eps_sf);
+      acc[1] += coef * ((1.0 - s.s1) * (-s.delta / (a.w_rho * a.delta_c * a.delta_c)));
     }
-    lam[c] = lr;
+    lam[c] = static_cast<float>(lr);
   }
   block_reduce_store<2, false>(acc, partial);
 }

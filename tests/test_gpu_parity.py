@@ -46,6 +46,28 @@ def test_sweep_matches_oracle(dhp, n, axis):
         assert rel_l2(out[c], ref[c]) < STEP_TOL, (c, rel_l2(out[c], ref[c]))
 
 
+def _nonsmooth_cells(q, axis, dt, a0, ah, ocfg, rel=1e-5, reach=4):
+    """Cells whose adjoint depends on a non-smooth point that float32 rounding can move:
+    a limiter slope of a stage-2 split flux, or a sweep-direction momentum, within `rel` of
+    zero relative to its neighbours.  FP32 and FP64 may take different branches there."""
+    with torch.no_grad():
+        qt = torch.from_numpy(q).double()
+        fr, fl = hydro.split_fluxes(qt, a0, axis, ocfg.gamma, ocfg.e_floor)
+        f1 = fr - hydro.shift(fl, axis, 1)
+        qh = qt - 0.5 * dt * (f1 - hydro.shift(f1, axis, -1))
+        fr, fl = hydro.split_fluxes(qh, ah, axis, ocfg.gamma, ocfg.e_floor)
+        frm, flp = hydro.shift(fr, axis, -1), hydro.shift(fl, axis, 1)
+        amb = ((fr - frm).abs() <= rel * (fr.abs() + frm.abs())).any(0)
+        amb |= ((flp - fl).abs() <= rel * (fl.abs() + flp.abs())).any(0)
+        for st in (qt, qh):
+            m = st[1 + axis].abs()
+            amb |= m <= rel * st[1:4].abs().sum(0)
+        mask = amb.clone()
+        for k in range(1, reach + 1):
+            mask |= hydro.shift(amb, axis, k) | hydro.shift(amb, axis, -k)
+    return mask.numpy()
+
+
 @pytest.mark.parametrize("n", [32, 128])
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_sweep_vjp_matches_oracle_autograd(dhp, n, axis):
@@ -59,8 +81,15 @@ def test_sweep_vjp_matches_oracle_autograd(dhp, n, axis):
     y = hydro.sweep(q64, axis, dt, a0, ah, ocfg.gamma, ocfg.e_floor)
     (ref,) = torch.autograd.grad(y, q64, torch.from_numpy(lam).double())
     ref = ref.numpy()
+    skip = _nonsmooth_cells(q, axis, dt, a0, ah, ocfg)
+    assert skip.mean() < 0.03
+    keep = ~skip
     for c in range(5):
-        assert rel_l2(out[c], ref[c]) < STEP_TOL, (c, rel_l2(out[c], ref[c]))
+        err = rel_l2(out[c][keep], ref[c][keep])
+        assert err < STEP_TOL, (c, err, skip.mean())
+    # where a branch may differ, the adjoint is still finite and of the same scale
+    assert np.isfinite(out).all()
+    assert np.abs(out[:, skip]).max(initial=0.0) <= 10 * np.abs(ref).max()
 
 
 def test_sweep_handles_cold_gas_floor(dhp):
@@ -224,6 +253,8 @@ def test_single_step_with_star_formation(dhp, mode):
     if mode == subgrid.MODE_RELAXED:
         _compare_state(s, ref, n, STEP_TOL)
         assert rel_l2(star, ref.star.numpy()) < STEP_TOL
+        assert rel_l2(to_np(s.get("temp")), subgrid.temperature(ref.q, ref.a, ocfg.gamma,
+                                                                ocfg.e_floor, ocfg.t_per_e).numpy()) < STEP_TOL
     else:
         # hard draws: identical except where the uniform sits within float32 rounding of
         # the threshold 1 - pi0
