@@ -71,7 +71,13 @@ struct dh_sim {
   // scratch
   float *q2 = nullptr, *delta = nullptr, *cic = nullptr, *psi = nullptr, *fscratch = nullptr;
   float2 *spec = nullptr, *spec2 = nullptr, *tw = nullptr;
+  float4* g4 = nullptr;        // (-grad phi, 0) of the current potential
+  float4* g4b = nullptr;       // scratch acceleration field for the reverse pass and stages
   dh::Bins bins{};
+  double* cfl_red = nullptr;   // CFL block maxima of the current state (from the closing pass)
+  bool cfl_partials = false;   // cfl_red holds the maxima of the current state
+  bool speed_known = false;    // speed holds the CFL speed of the current state
+  double speed = 0.0;
   double* red = nullptr;       // block partials
   double* red_out = nullptr;   // reduced values
   double* host_out = nullptr;  // pinned
@@ -152,7 +158,7 @@ void sync(dh_sim* s) { DH_HIP(hipStreamSynchronize(s->st)); }
 // bins of the particle positions pos
 void sort_particles(dh_sim* s, const float* pos) {
   dh::launch_keys(s->st, pos, s->bins.key, s->n);
-  dh::launch_sort(s->st, s->bins, s->n);
+  dh::launch_sort(s->st, s->bins, pos, s->n);
 }
 
 // phi_out = Poisson solve of delta at scale factor a; uses spec
@@ -164,21 +170,32 @@ void poisson(dh_sim* s, const float* delta, float* phi_out, double a) {
   dh::fft_inverse_yx(s->st, s->spec, phi_out, s->tw, s->n, 1.0f);
 }
 
-// phi = Poisson(rho_gas + m_dm CIC(pos) - 1) with the bins of pos already built
-void potential_from_bins(dh_sim* s, const float* rho_gas, const float* pos, float* phi_out,
+// phi = Poisson(rho_gas + m_dm CIC(pos) - 1) and g4 = -grad(phi), with the bins of the
+// particle positions already built
+void potential_from_bins(dh_sim* s, const float* rho_gas, float* phi_out, float4* g4_out,
                          double a) {
-  dh::launch_deposit(s->st, s->bins, pos, rho_gas, static_cast<float>(s->m_dm), -1.0f, s->delta,
-                     s->n);
+  dh::launch_deposit(s->st, s->bins, rho_gas, static_cast<float>(s->m_dm), -1.0f, s->delta, s->n);
   poisson(s, s->delta, phi_out, a);
+  dh::launch_grad(s->st, phi_out, g4_out, s->n);
 }
 
-double cfl_speed(dh_sim* s, const float* q, double a) {
-  dh::launch_cfl_partial(s->st, q, static_cast<float>(a), static_cast<float>(s->cfg.gamma),
-                         static_cast<float>(s->e_floor), s->red, s->n);
-  dh::launch_reduce_max(s->st, s->red, dh::cfl_blocks(s->n), s->red_out);
+void state_changed(dh_sim* s) {
+  s->cfl_partials = false;
+  s->speed_known = false;
+}
+
+// CFL speed max over cells and axes of (|U_d| + c_s)/a of the current state (FP64 on the
+// device); +inf when the state holds a non-finite value or a non-positive density
+double current_speed(dh_sim* s) {
+  if (s->speed_known) return s->speed;
+  if (!s->cfl_partials)
+    dh::launch_cfl_partial(s->st, s->q, s->a, s->cfg.gamma, s->e_floor, s->cfl_red, s->n);
+  dh::launch_reduce_max(s->st, s->cfl_red, dh::cfl_blocks(s->n), s->red_out);
   DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, sizeof(double), hipMemcpyDeviceToHost, s->st));
   sync(s);
-  return s->host_out[0];
+  s->speed = s->host_out[0];
+  s->speed_known = true;
+  return s->speed;
 }
 
 dh::SourceArgs source_args(const dh_sim* s, const Plan& pl) {
@@ -228,8 +245,8 @@ void do_step(dh_sim* s, const Plan& pl, TapeStep* tp) {
     copy_d2d(s, tp->phi0, s->phi, nc);
   }
   // opening half kicks with g_n, drift with a(t + dt/2)
-  dh::launch_gas_kick(s->st, s->q, s->phi, h, n);
-  dh::launch_kick_drift(s->st, s->phi, s->pos, s->mom, s->bins.key, h,
+  dh::launch_gas_kick(s->st, s->q, s->g4, h, n);
+  dh::launch_kick_drift(s->st, s->g4, s->pos, s->mom, s->bins.key, h,
                         static_cast<float>(pl.dt / (pl.ah * pl.ah)), n);
   if (tp) {
     copy_d2d(s, tp->ph, s->mom, 3 * np);
@@ -244,24 +261,25 @@ void do_step(dh_sim* s, const Plan& pl, TapeStep* tp) {
   }
   if (tp) copy_d2d(s, tp->q[4], s->q, 5 * nc);
   // Poisson at a(t + dt) from gas + DM (keys were written by the drift)
-  dh::launch_sort(s->st, s->bins, n);
-  potential_from_bins(s, s->q, s->pos, s->phi, pl.a1);
+  dh::launch_sort(s->st, s->bins, s->pos, n);
+  potential_from_bins(s, s->q, s->phi, s->g4, pl.a1);
   if (tp) copy_d2d(s, tp->phi1, s->phi, nc);
-  // closing half kicks with g_{n+1}
-  dh::launch_gas_kick(s->st, s->q, s->phi, h, n);
-  dh::launch_kick(s->st, s->phi, s->pos, s->mom, h, n);
-  if (tp) copy_d2d(s, tp->q[5], s->q, 5 * nc);
-  // source term
-  if (s->cfg.subgrid != DH_SUBGRID_OFF) dh::launch_source(s->st, s->q, s->star, source_args(s, pl), n);
+  // closing half kicks with g_{n+1}; the gas kick, the source term and the CFL maxima of the
+  // new state are one pass over the cells
+  dh::launch_close_step(s->st, s->q, s->g4, h, s->star, source_args(s, pl),
+                        tp ? tp->q[5] : nullptr, s->cfg.gamma, s->cfl_red, n);
+  dh::launch_kick(s->st, s->g4, s->pos, s->mom, h, n);
   DH_LAUNCH_CHECK();
   s->t = pl.t0 + pl.dt;
   s->a = pl.a1;
   s->step = pl.step + 1;
+  s->speed_known = false;
+  s->cfl_partials = true;
 }
 
 void refresh_potential(dh_sim* s) {
   sort_particles(s, s->pos);
-  potential_from_bins(s, s->q, s->pos, s->phi, s->a);
+  potential_from_bins(s, s->q, s->phi, s->g4, s->a);
   s->phi_valid = true;
 }
 
@@ -281,7 +299,7 @@ void initial_conditions(dh_sim* s, const float* d_white) {
   const double vfac = ai * ai * s->cosmo.E(ai) * s->cosmo.growth_rate(ai);
   dh::launch_ic_particles(s->st, s->psi, s->pos, s->mom, static_cast<float>(vfac), n);
   sort_particles(s, s->pos);
-  dh::launch_deposit(s->st, s->bins, s->pos, nullptr, 1.0f, 0.0f, s->cic, n);
+  dh::launch_deposit(s->st, s->bins, nullptr, 1.0f, 0.0f, s->cic, n);
   dh::launch_ic_gas(s->st, s->cic, s->psi, s->q, static_cast<float>(s->f_b),
                     static_cast<float>(vfac), static_cast<float>(ai), static_cast<float>(s->e_init),
                     n);
@@ -289,8 +307,9 @@ void initial_conditions(dh_sim* s, const float* d_white) {
   s->t = s->cosmo.t_of_a(ai);
   s->a = ai;
   s->step = 0;
-  potential_from_bins(s, s->q, s->pos, s->phi, ai);
+  potential_from_bins(s, s->q, s->phi, s->g4, ai);
   s->phi_valid = true;
+  state_changed(s);
   s->initialised = true;
   s->recorded.clear();
   s->replay_pos = 0;
@@ -303,7 +322,7 @@ int next_dt(dh_sim* s, double t_end, double* dt_out) {
     dt = s->replay[s->replay_pos++];
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(s, DH_E_SCHEDULE, "schedule entry is not a positive finite dt");
   } else {
-    const double v = cfl_speed(s, s->q, s->a);
+    const double v = current_speed(s);
     if (!std::isfinite(v) || !(v > 0.0))
       return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
     dt = std::min(s->cfg.cfl / v, s->cfg.dlna_max / s->cosmo.E(s->a));
@@ -362,7 +381,9 @@ void load_ckpt(dh_sim* s, const Ckpt& c) {
   s->t = c.t;
   s->a = c.a;
   s->step = c.step;
+  dh::launch_grad(s->st, s->phi, s->g4, s->n);
   s->phi_valid = true;
+  state_changed(s);
 }
 
 // Adjoint of one step.  In: lq, lx, lp, lphi = adjoints of the state after the step (lphi is
@@ -381,10 +402,12 @@ void step_vjp(dh_sim* s, const TapeStep& T, int param_slot) {
     dh::launch_reduce_sum(st, s->red, nb, nb, 2, s->param_steps + 2 * param_slot);
   }
   // closing kicks (gas from Q4, DM at x1) -> lambda_g -> lambda_phi_{n+1}
-  dh::launch_gas_kick_vjp(st, T.q[4], T.phi1, h, s->lq, s->lg, n);
+  dh::launch_grad(st, T.phi1, s->g4b, n);
+  dh::launch_gas_kick_vjp(st, T.q[4], s->g4b, h, s->lq, s->lg, n);
   sort_particles(s, T.x1);
-  dh::launch_deposit_vec(st, s->bins, T.x1, s->lp, h, s->lg, n);
-  dh::launch_kick_vjp_pos(st, T.phi1, T.x1, s->lp, h, s->lx, n);
+  dh::launch_gather_sorted(st, s->bins, s->lp, n);
+  dh::launch_deposit_vec(st, s->bins, h, s->lg, n);
+  dh::launch_kick_vjp_pos(st, s->g4b, T.x1, s->lp, h, s->lx, n);
   dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi2, n);
   // Poisson (symmetric operator) and deposit at x1
   poisson(s, s->lphi2, s->ldelta, pl.a1);
@@ -400,10 +423,12 @@ void step_vjp(dh_sim* s, const TapeStep& T, int param_slot) {
   // drift: x1 = x0 + p_half dt / a_h^2
   dh::launch_axpy(st, s->lp, s->lx, static_cast<float>(pl.dt / (pl.ah * pl.ah)), 3 * np);
   // opening kicks with phi_n at x0
-  dh::launch_gas_kick_vjp(st, T.q[0], T.phi0, h, s->lq, s->lg, n);
+  dh::launch_grad(st, T.phi0, s->g4b, n);
+  dh::launch_gas_kick_vjp(st, T.q[0], s->g4b, h, s->lq, s->lg, n);
   sort_particles(s, T.x0);
-  dh::launch_deposit_vec(st, s->bins, T.x0, s->lp, h, s->lg, n);
-  dh::launch_kick_vjp_pos(st, T.phi0, T.x0, s->lp, h, s->lx, n);
+  dh::launch_gather_sorted(st, s->bins, s->lp, n);
+  dh::launch_deposit_vec(st, s->bins, h, s->lg, n);
+  dh::launch_kick_vjp_pos(st, s->g4b, T.x0, s->lp, h, s->lx, n);
   dh::launch_grad_vjp(st, s->lg, nullptr, s->lphi, n);
 }
 
@@ -530,6 +555,11 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
     s->bins.start = s->alloc<uint32_t>(nc + 1);
     s->bins.sorted = s->alloc<uint32_t>(np);
     s->bins.block_sums = s->alloc<uint32_t>(static_cast<long long>(dh::scan_block_count(nc)) + 1);
+    s->bins.spos = s->alloc<float4>(np);
+    s->bins.sval = s->alloc<float4>(np);
+    s->g4 = s->alloc<float4>(nc);
+    s->g4b = s->alloc<float4>(nc);
+    s->cfl_red = s->alloc<double>(dh::cfl_blocks(n) + 1);
     s->red_blocks = dh::sum_blocks(nc);
     s->red = s->alloc<double>(8LL * s->red_blocks + 8);
     s->red_out = s->alloc<double>(16);
@@ -600,7 +630,7 @@ int dh_step(dh_sim* s, double* dt_out, double* a_out) {
     int rc = step_once(s, -1.0, nullptr, &dt);
     if (rc) return rc;
     s->have_forward = false;
-    const double v = cfl_speed(s, s->q, s->a);   // also validates the new state
+    const double v = current_speed(s);   // also validates the new state
     if (!std::isfinite(v)) return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
     if (dt_out) *dt_out = dt;
     if (a_out) *a_out = s->a;
@@ -675,11 +705,16 @@ int dh_set_field(dh_sim* s, dh_field f, const float* d_in) {
       case DH_FIELD_POS: copy_d2d(s, s->pos, d_in, 3 * s->np); s->phi_valid = false; break;
       case DH_FIELD_MOM: copy_d2d(s, s->mom, d_in, 3 * s->np); break;
       case DH_FIELD_STAR: copy_d2d(s, s->star, d_in, s->nc); break;
-      case DH_FIELD_PHI: copy_d2d(s, s->phi, d_in, s->nc); s->phi_valid = true; break;
+      case DH_FIELD_PHI:
+        copy_d2d(s, s->phi, d_in, s->nc);
+        dh::launch_grad(s->st, s->phi, s->g4, s->n);
+        s->phi_valid = true;
+        break;
       default: return fail(s, DH_E_INVAL, "field cannot be set");
     }
     s->initialised = true;
     s->have_forward = false;
+    state_changed(s);
     return DH_OK;
   });
 }
@@ -706,6 +741,7 @@ int dh_set_time(dh_sim* s, double a, int32_t step) {
   s->t = s->cosmo.t_of_a(a);
   s->step = step;
   s->phi_valid = false;
+  state_changed(s);
   return DH_OK;
 }
 
@@ -729,7 +765,7 @@ int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_
       if (rc) return rc;
       ++count;
     }
-    const double v = cfl_speed(s, s->q, s->a);
+    const double v = current_speed(s);
     if (!std::isfinite(v)) return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
     s->fwd_steps = count;
     s->have_forward = true;
@@ -895,8 +931,7 @@ int dh_stage_deposit(dh_sim* s, const float* d_rho_gas, const float* d_pos, floa
   if (!s || !d_rho_gas || !d_pos || !d_delta) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
     sort_particles(s, d_pos);
-    dh::launch_deposit(s->st, s->bins, d_pos, d_rho_gas, static_cast<float>(s->m_dm), -1.0f, d_delta,
-                       s->n);
+    dh::launch_deposit(s->st, s->bins, d_rho_gas, static_cast<float>(s->m_dm), -1.0f, d_delta, s->n);
     return DH_OK;
   });
 }
@@ -904,7 +939,8 @@ int dh_stage_deposit(dh_sim* s, const float* d_rho_gas, const float* d_pos, floa
 int dh_stage_readout(dh_sim* s, const float* d_phi, const float* d_pos, float* d_g) {
   if (!s || !d_phi || !d_pos || !d_g) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
-    dh::launch_readout_g(s->st, d_phi, d_pos, d_g, s->n);
+    dh::launch_grad(s->st, d_phi, s->g4b, s->n);
+    dh::launch_readout_g(s->st, s->g4b, d_pos, d_g, s->n);
     return DH_OK;
   });
 }

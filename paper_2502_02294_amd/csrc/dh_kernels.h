@@ -23,32 +23,38 @@ struct Bins {          // counting sort of particles by CIC base cell
   uint32_t* start;     // [nc + 1] exclusive prefix sum of count
   uint32_t* sorted;    // [np] particle ids, bins in cell order, ids ascending inside a bin
   uint32_t* block_sums;  // [scan blocks]
+  float4* spos;        // [np] positions in bin order
+  float4* sval;        // [np] a particle vector field in bin order (adjoint deposits)
 };
 size_t scan_block_count(long long nc);
 void launch_keys(hipStream_t st, const float* pos, uint32_t* key, int n);
-void launch_sort(hipStream_t st, const Bins& b, int n);
-// delta = rho_gas + m_dm * CIC(pos) - 1 ; rho_gas may be null (then 0), offset -1 optional
-void launch_deposit(hipStream_t st, const Bins& b, const float* pos, const float* rho_gas,
-                    float m_dm, float offset, float* out, int n);
-// deposit of a particle vector field v[3][np] with CIC weights: out[3][nc]
-void launch_deposit_vec(hipStream_t st, const Bins& b, const float* pos, const float* v,
-                        float scale, float* out_accum, int n);
-// g at particles: out[3][np] = CIC readout of -grad(phi) (central differences)
-void launch_readout_g(hipStream_t st, const float* phi, const float* pos, float* out, int n);
+// sort by b.key (already computed for pos) and gather pos into bin order
+void launch_sort(hipStream_t st, const Bins& b, const float* pos, int n);
+// b.sval = v[3][np] in bin order
+void launch_gather_sorted(hipStream_t st, const Bins& b, const float* v, int n);
+// out = rho_gas + m_dm * CIC(sorted positions) + offset; rho_gas may be null (then 0)
+void launch_deposit(hipStream_t st, const Bins& b, const float* rho_gas, float m_dm, float offset,
+                    float* out, int n);
+// out_accum[3][nc] += scale * CIC deposit of b.sval
+void launch_deposit_vec(hipStream_t st, const Bins& b, float scale, float* out_accum, int n);
+// g4 = (-grad phi, 0) by two-point central differences
+void launch_grad(hipStream_t st, const float* phi, float4* g4, int n);
+// g at particles: out[3][np] = CIC read-out of g4
+void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float* out, int n);
 // opening kick + drift (+ keys), closing kick
-void launch_kick_drift(hipStream_t st, const float* phi, float* pos, float* mom, uint32_t* key,
+void launch_kick_drift(hipStream_t st, const float4* g4, float* pos, float* mom, uint32_t* key,
                        float h_kick, float drift_fac, int n);
-void launch_kick(hipStream_t st, const float* phi, const float* pos, float* mom, float h_kick,
+void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom, float h_kick,
                  int n);
-// adjoint of p' = p + h g(x): lam_x += h sum_c dw/dx (g_c . lam_p') ; (lam_g deposit separate)
-void launch_kick_vjp_pos(hipStream_t st, const float* phi, const float* pos,
+// adjoint of p' = p + h g(x) with respect to x: lam_x += h sum_c dw/dx (g_c . lam_p')
+void launch_kick_vjp_pos(hipStream_t st, const float4* g4, const float* pos,
                          const float* lam_p, float h_kick, float* lam_x, int n);
 // adjoint of the deposit wrt positions: lam_x += mass sum_c lam_delta_c dw_c/dx
 void launch_deposit_vjp_pos(hipStream_t st, const float* lam_delta, const float* pos,
                             float mass, float* lam_x, int n);
-// lam_x += lam_p * fac (drift adjoint), elementwise over 3 np
+// y += a x, elementwise
 void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long count);
-// lam_phi = div^T of lam_g (adjoint of the central-difference gradient) + lam_phi_in
+// lam_phi = (adjoint of the central-difference gradient) lam_g + lam_phi_in
 void launch_grad_vjp(hipStream_t st, const float* lam_g, const float* lam_phi_in, float* lam_phi,
                      int n);
 
@@ -69,8 +75,8 @@ void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* t
                   bool forward_first, bool inverse_after, bool accumulate);
 
 // ---- pointwise / reductions (k_point.hip)
-void launch_gas_kick(hipStream_t st, float* q, const float* phi, float h, int n);
-void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float* phi, float h,
+void launch_gas_kick(hipStream_t st, float* q, const float4* g4, float h, int n);
+void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4, float h,
                          float* lam_q, float* lam_g, int n);
 struct SourceArgs {   // FP64: the source term is evaluated in double precision
   double a, dt, inv_rho_mean, omega_b, efloor, t_per_e, e0_code;
@@ -79,13 +85,19 @@ struct SourceArgs {   // FP64: the source term is evaluated in double precision
   uint32_t seed_lo, seed_hi, step;
 };
 void launch_source(hipStream_t st, float* q, float* star, const SourceArgs& a, int n);
+// closing pass of a step: gas half kick with g4, optional copy of the kicked state to
+// q_kicked (tape), source term (if a.mode != 0), FP64 block maxima of the CFL speed of the
+// result at scale factor a.a into block_max[cfl_blocks(n)]
+void launch_close_step(hipStream_t st, float* q, const float4* g4, float h, float* star,
+                       const SourceArgs& a, float* q_kicked, double gamma, double* block_max,
+                       int n);
 // adjoint of the source term; accumulates dL/d(eps_sf, delta_c) partials per block
 void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, const SourceArgs& a,
                        double* partials, int nblocks_out, int n);
 int source_vjp_blocks(int n);
 // FP64 block maxima of the CFL speed max_d (|U_d| + c_s)/a
 int cfl_blocks(int n);
-void launch_cfl_partial(hipStream_t st, const float* q, float a, float gamma, float efloor,
+void launch_cfl_partial(hipStream_t st, const float* q, double a, double gamma, double efloor,
                         double* block_max, int n);
 void launch_reduce_max(hipStream_t st, const double* in, int count, double* out);
 void launch_reduce_sum(hipStream_t st, const double* in, int count, int stride, int nvec,

@@ -1,12 +1,15 @@
 // Particle-mesh kernels (Sec. 2.2): cell keys, a stable counting sort of the particles by
-// their CIC base cell, the deterministic CIC deposit as a per-cell gather over the 8 bins
-// that can reach a cell, the CIC read-out of g = -grad(phi) (two-point central difference),
-// kick and drift (eq. dm_hamil: dx/dt = p/a^2, dp/dt = g), and the adjoints of all of them.
+// their CIC base cell, the deterministic CIC deposit as a per-cell gather over the bins
+// that can reach a cell, the mesh acceleration g = -grad(phi) (two-point central
+// difference) and its CIC read-out, kick and drift (eq. dm_hamil: dx/dt = p/a^2,
+// dp/dt = g), and the adjoints of all of them.
 //
 // CIC on cell centres: with s = x - 1/2, i0 = floor(s), w1 = s - i0, a particle puts
 // weight (1-w1) in cell i0 and w1 in i0+1 per axis.  Cell c receives from particles whose
-// base cell is c - o, o in {0,1}^3.  The deposit visits o in a fixed order and the bin
-// contents in ascending particle id, so every sum is reproducible bit for bit without float
+// base cell is c - o, o in {0,1}^3.  After the sort, the positions are gathered into bin
+// order (float4 per particle), so a cell reads, for each (oz, oy), the two x-adjacent bins
+// c - (1, oy, oz) and c - (0, oy, oz) as one contiguous range, in a fixed order and with
+// ascending particle id inside a bin: every sum is reproducible bit for bit without float
 // atomics.
 #include "dh_kernels.h"
 
@@ -38,6 +41,11 @@ __device__ __forceinline__ Cic cic_of(float x, float y, float z, int n) {
   return c;
 }
 
+__device__ __forceinline__ float w1_of(float x) {
+  const float s = x - 0.5f;
+  return s - floorf(s);
+}
+
 __device__ __forceinline__ float wsel(float w1, int o) { return o ? w1 : 1.0f - w1; }
 
 __global__ void keys_kernel(const float* __restrict__ pos, uint32_t* __restrict__ key, int n,
@@ -60,7 +68,7 @@ __global__ void hist_kernel(const uint32_t* __restrict__ key, uint32_t* count,
   rank[i] = atomicAdd(&count[key[i]], 1u);
 }
 
-// Block-local exclusive scan helper over kScanThreads values in LDS.
+// Block-local exclusive scan over kScanThreads values in LDS.
 __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
   const int t = threadIdx.x;
   sh[t] = v;
@@ -77,13 +85,18 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& tot
   return incl - v;
 }
 
+// tile element e lives at LDS word e + e / kScanPer (padding breaks the 16-word stride)
+__device__ __forceinline__ int tile_slot(int e) { return e + e / kScanPer; }
+
 __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ block_sums, long long count) {
   __shared__ uint32_t sh[kScanThreads];
-  const long long base = static_cast<long long>(blockIdx.x) * kScanTile + threadIdx.x * kScanPer;
+  const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
   uint32_t s = 0;
-  for (int k = 0; k < kScanPer; ++k)
-    if (base + k < count) s += in[base + k];
+  for (int k = 0; k < kScanPer; ++k) {   // coalesced: consecutive threads, consecutive words
+    const long long e = base + k * kScanThreads + threadIdx.x;
+    if (e < count) s += in[e];
+  }
   uint32_t total;
   block_exclusive_scan(s, sh, total);
   if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
@@ -105,19 +118,28 @@ __global__ void __launch_bounds__(kScanThreads) scan_block_sums_kernel(uint32_t*
 __global__ void __launch_bounds__(kScanThreads) scan_final_kernel(
     const uint32_t* __restrict__ in, const uint32_t* __restrict__ block_off,
     uint32_t* __restrict__ out, long long count) {
+  __shared__ uint32_t tile[kScanTile + kScanTile / kScanPer];
   __shared__ uint32_t sh[kScanThreads];
-  const long long base = static_cast<long long>(blockIdx.x) * kScanTile + threadIdx.x * kScanPer;
-  uint32_t v[kScanPer];
-  uint32_t s = 0;
+  const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
   for (int k = 0; k < kScanPer; ++k) {
-    v[k] = base + k < count ? in[base + k] : 0u;
-    s += v[k];
+    const int e = k * kScanThreads + threadIdx.x;
+    tile[tile_slot(e)] = base + e < count ? in[base + e] : 0u;
   }
+  __syncthreads();
+  uint32_t s = 0;
+  for (int k = 0; k < kScanPer; ++k) s += tile[tile_slot(threadIdx.x * kScanPer + k)];
   uint32_t total;
   uint32_t run = block_exclusive_scan(s, sh, total) + block_off[blockIdx.x];
   for (int k = 0; k < kScanPer; ++k) {
-    if (base + k < count) out[base + k] = run;
-    run += v[k];
+    const int sl = tile_slot(threadIdx.x * kScanPer + k);
+    const uint32_t v = tile[sl];
+    tile[sl] = run;
+    run += v;
+  }
+  __syncthreads();
+  for (int k = 0; k < kScanPer; ++k) {
+    const int e = k * kScanThreads + threadIdx.x;
+    if (base + e < count) out[base + e] = tile[tile_slot(e)];
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[count] = block_off[blockIdx.x] + total;
 }
@@ -147,83 +169,125 @@ __global__ void bin_sort_kernel(const uint32_t* __restrict__ start, uint32_t* so
   }
 }
 
+// out[j] = (v[0][id], v[1][id], v[2][id], 0) for id = sorted[j]
+__global__ void gather_sorted_kernel(const uint32_t* __restrict__ sorted,
+                                     const float* __restrict__ v, float4* __restrict__ out,
+                                     long long np) {
+  const long long j = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= np) return;
+  const uint32_t id = sorted[j];
+  out[j] = make_float4(v[id], v[np + id], v[2 * np + id], 0.0f);
+}
+
 // ---------------------------------------------------------------------------- deposit
-__global__ void __launch_bounds__(256) deposit_kernel(
-    const uint32_t* __restrict__ start, const uint32_t* __restrict__ sorted,
-    const float* __restrict__ pos, const float* __restrict__ rho_gas, float m_dm, float offset,
-    float* __restrict__ out, int n, long long np) {
-  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const long long nc = static_cast<long long>(n) * n * n;
-  if (c >= nc) return;
-  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
-            iz = static_cast<int>(c / (static_cast<long long>(n) * n));
-  float acc = 0.0f;
+// For cell (ix, iy, iz) and each (oz, oy): the bin with x index ix-1 (weight w1 in x) is
+// visited before the bin ix (weight 1-w1); when ix = 0 the first bin wraps to n-1.
+template <bool VEC>
+__device__ __forceinline__ void deposit_cell(const uint32_t* __restrict__ start,
+                                             const float4* __restrict__ spos,
+                                             const float4* __restrict__ sval, int ix, int iy,
+                                             int iz, int n, float acc[3]) {
 #pragma unroll
   for (int oz = 0; oz < 2; ++oz)
 #pragma unroll
-    for (int oy = 0; oy < 2; ++oy)
-#pragma unroll
-      for (int ox = 0; ox < 2; ++ox) {
-        const long long b = (static_cast<long long>(wrapi(iz - oz, n)) * n + wrapi(iy - oy, n)) * n +
-                            wrapi(ix - ox, n);
-        const uint32_t lo = start[b], hi = start[b + 1];
-        for (uint32_t j = lo; j < hi; ++j) {
-          const uint32_t id = sorted[j];
-          const Cic w = cic_of(pos[id], pos[np + id], pos[2 * np + id], n);
-          acc += wsel(w.w1[0], ox) * wsel(w.w1[1], oy) * wsel(w.w1[2], oz);
+    for (int oy = 0; oy < 2; ++oy) {
+      const long long row = (static_cast<long long>(wrapi(iz - oz, n)) * n + wrapi(iy - oy, n)) * n;
+      uint32_t a0, a1, b0, b1;
+      if (ix > 0) {
+        a0 = start[row + ix - 1];
+        a1 = start[row + ix];
+        b0 = a1;
+        b1 = start[row + ix + 1];
+      } else {
+        a0 = start[row + n - 1];
+        a1 = start[row + n];
+        b0 = start[row];
+        b1 = start[row + 1];
+      }
+      for (uint32_t j = a0; j < a1; ++j) {   // bin ix-1: weight w1 in x
+        const float4 p = spos[j];
+        const float w = w1_of(p.x) * wsel(w1_of(p.y), oy) * wsel(w1_of(p.z), oz);
+        if (VEC) {
+          const float4 v = sval[j];
+          acc[0] += w * v.x;
+          acc[1] += w * v.y;
+          acc[2] += w * v.z;
+        } else {
+          acc[0] += w;
         }
       }
-  const float g = rho_gas ? rho_gas[c] : 0.0f;
-  out[c] = g + m_dm * acc + offset;
+      for (uint32_t j = b0; j < b1; ++j) {   // bin ix: weight 1-w1 in x
+        const float4 p = spos[j];
+        const float w = (1.0f - w1_of(p.x)) * wsel(w1_of(p.y), oy) * wsel(w1_of(p.z), oz);
+        if (VEC) {
+          const float4 v = sval[j];
+          acc[0] += w * v.x;
+          acc[1] += w * v.y;
+          acc[2] += w * v.z;
+        } else {
+          acc[0] += w;
+        }
+      }
+    }
 }
 
-__global__ void __launch_bounds__(256) deposit_vec_kernel(
-    const uint32_t* __restrict__ start, const uint32_t* __restrict__ sorted,
-    const float* __restrict__ pos, const float* __restrict__ v, float scale,
-    float* __restrict__ out, int n, long long np) {
+__global__ void __launch_bounds__(256) deposit_kernel(const uint32_t* __restrict__ start,
+                                                      const float4* __restrict__ spos,
+                                                      const float* __restrict__ rho_gas,
+                                                      float m_dm, float offset,
+                                                      float* __restrict__ out, int n) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const long long nc = static_cast<long long>(n) * n * n;
   if (c >= nc) return;
   const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
             iz = static_cast<int>(c / (static_cast<long long>(n) * n));
   float acc[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int oz = 0; oz < 2; ++oz)
-#pragma unroll
-    for (int oy = 0; oy < 2; ++oy)
-#pragma unroll
-      for (int ox = 0; ox < 2; ++ox) {
-        const long long b = (static_cast<long long>(wrapi(iz - oz, n)) * n + wrapi(iy - oy, n)) * n +
-                            wrapi(ix - ox, n);
-        const uint32_t lo = start[b], hi = start[b + 1];
-        for (uint32_t j = lo; j < hi; ++j) {
-          const uint32_t id = sorted[j];
-          const Cic w = cic_of(pos[id], pos[np + id], pos[2 * np + id], n);
-          const float ww = wsel(w.w1[0], ox) * wsel(w.w1[1], oy) * wsel(w.w1[2], oz);
-          acc[0] += ww * v[id];
-          acc[1] += ww * v[np + id];
-          acc[2] += ww * v[2 * np + id];
-        }
-      }
+  deposit_cell<false>(start, spos, nullptr, ix, iy, iz, n, acc);
+  const float g = rho_gas ? rho_gas[c] : 0.0f;
+  out[c] = g + m_dm * acc[0] + offset;
+}
+
+__global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __restrict__ start,
+                                                          const float4* __restrict__ spos,
+                                                          const float4* __restrict__ sval,
+                                                          float scale, float* __restrict__ out,
+                                                          int n) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long nc = static_cast<long long>(n) * n * n;
+  if (c >= nc) return;
+  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
+            iz = static_cast<int>(c / (static_cast<long long>(n) * n));
+  float acc[3] = {0.0f, 0.0f, 0.0f};
+  deposit_cell<true>(start, spos, sval, ix, iy, iz, n, acc);
   out[c] += scale * acc[0];
   out[nc + c] += scale * acc[1];
   out[2 * nc + c] += scale * acc[2];
 }
 
-// g_d at cell (ix, iy, iz) = -(phi[+e_d] - phi[-e_d]) / 2
-__device__ __forceinline__ void grid_g(const float* __restrict__ phi, int ix, int iy, int iz, int n,
-                                       float g[3]) {
-  const long long nn = static_cast<long long>(n) * n;
+// g4[c] = (g_x, g_y, g_z, 0),  g_d = -(phi[c + e_d] - phi[c - e_d]) / 2
+__global__ void __launch_bounds__(256) grad_kernel(const float* __restrict__ phi,
+                                                   float4* __restrict__ g4, int n) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long nn = static_cast<long long>(n) * n, nc = nn * n;
+  if (c >= nc) return;
+  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
+            iz = static_cast<int>(c / nn);
   const long long zo = static_cast<long long>(iz) * nn, yo = static_cast<long long>(iy) * n;
-  g[0] = -0.5f * (phi[zo + yo + wrapi(ix + 1, n)] - phi[zo + yo + wrapi(ix - 1, n)]);
-  g[1] = -0.5f * (phi[zo + static_cast<long long>(wrapi(iy + 1, n)) * n + ix] -
-                  phi[zo + static_cast<long long>(wrapi(iy - 1, n)) * n + ix]);
-  g[2] = -0.5f * (phi[static_cast<long long>(wrapi(iz + 1, n)) * nn + yo + ix] -
-                  phi[static_cast<long long>(wrapi(iz - 1, n)) * nn + yo + ix]);
+  const float gx = -0.5f * (phi[zo + yo + wrapi(ix + 1, n)] - phi[zo + yo + wrapi(ix - 1, n)]);
+  const float gy = -0.5f * (phi[zo + static_cast<long long>(wrapi(iy + 1, n)) * n + ix] -
+                            phi[zo + static_cast<long long>(wrapi(iy - 1, n)) * n + ix]);
+  const float gz = -0.5f * (phi[static_cast<long long>(wrapi(iz + 1, n)) * nn + yo + ix] -
+                            phi[static_cast<long long>(wrapi(iz - 1, n)) * nn + yo + ix]);
+  g4[c] = make_float4(gx, gy, gz, 0.0f);
 }
 
-// CIC read-out of g at a particle, and optionally the position derivative of g . lam
-__device__ __forceinline__ void readout_g(const float* __restrict__ phi, const Cic& w, int n,
+__device__ __forceinline__ long long corner(const Cic& w, int ox, int oy, int oz, int n) {
+  return (static_cast<long long>(wrapi(w.i0[2] + oz, n)) * n + wrapi(w.i0[1] + oy, n)) * n +
+         wrapi(w.i0[0] + ox, n);
+}
+
+// CIC read-out of g at a particle
+__device__ __forceinline__ void readout_g(const float4* __restrict__ g4, const Cic& w, int n,
                                           float out[3]) {
   out[0] = out[1] = out[2] = 0.0f;
 #pragma unroll
@@ -232,16 +296,15 @@ __device__ __forceinline__ void readout_g(const float* __restrict__ phi, const C
     for (int oy = 0; oy < 2; ++oy)
 #pragma unroll
       for (int ox = 0; ox < 2; ++ox) {
-        float g[3];
-        grid_g(phi, wrapi(w.i0[0] + ox, n), wrapi(w.i0[1] + oy, n), wrapi(w.i0[2] + oz, n), n, g);
+        const float4 g = g4[corner(w, ox, oy, oz, n)];
         const float ww = wsel(w.w1[0], ox) * wsel(w.w1[1], oy) * wsel(w.w1[2], oz);
-        out[0] += ww * g[0];
-        out[1] += ww * g[1];
-        out[2] += ww * g[2];
+        out[0] += ww * g.x;
+        out[1] += ww * g.y;
+        out[2] += ww * g.z;
       }
 }
 
-__global__ void __launch_bounds__(256) readout_g_kernel(const float* __restrict__ phi,
+__global__ void __launch_bounds__(256) readout_g_kernel(const float4* __restrict__ g4,
                                                         const float* __restrict__ pos,
                                                         float* __restrict__ out, int n,
                                                         long long np) {
@@ -249,7 +312,7 @@ __global__ void __launch_bounds__(256) readout_g_kernel(const float* __restrict_
   if (i >= np) return;
   const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
   float g[3];
-  readout_g(phi, w, n, g);
+  readout_g(g4, w, n, g);
   out[i] = g[0];
   out[np + i] = g[1];
   out[2 * np + i] = g[2];
@@ -261,7 +324,7 @@ __device__ __forceinline__ float wrap_pos(float x, float fn) {
   return x;
 }
 
-__global__ void __launch_bounds__(256) kick_drift_kernel(const float* __restrict__ phi,
+__global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restrict__ g4,
                                                          float* __restrict__ pos,
                                                          float* __restrict__ mom,
                                                          uint32_t* __restrict__ key, float h,
@@ -271,7 +334,7 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float* __restrict
   float x[3] = {pos[i], pos[np + i], pos[2 * np + i]};
   const Cic w = cic_of(x[0], x[1], x[2], n);
   float g[3];
-  readout_g(phi, w, n, g);
+  readout_g(g4, w, n, g);
   const float fn = static_cast<float>(n);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -284,7 +347,7 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float* __restrict
   key[i] = static_cast<uint32_t>((w2.i0[2] * n + w2.i0[1]) * n + w2.i0[0]);
 }
 
-__global__ void __launch_bounds__(256) kick_kernel(const float* __restrict__ phi,
+__global__ void __launch_bounds__(256) kick_kernel(const float4* __restrict__ g4,
                                                    const float* __restrict__ pos,
                                                    float* __restrict__ mom, float h, int n,
                                                    long long np) {
@@ -292,13 +355,13 @@ __global__ void __launch_bounds__(256) kick_kernel(const float* __restrict__ phi
   if (i >= np) return;
   const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
   float g[3];
-  readout_g(phi, w, n, g);
+  readout_g(g4, w, n, g);
 #pragma unroll
   for (int d = 0; d < 3; ++d) mom[d * np + i] += h * g[d];
 }
 
 // lam_x += h * sum_corners (dw/dx) (g_corner . lam_p)
-__global__ void __launch_bounds__(256) kick_vjp_pos_kernel(const float* __restrict__ phi,
+__global__ void __launch_bounds__(256) kick_vjp_pos_kernel(const float4* __restrict__ g4,
                                                            const float* __restrict__ pos,
                                                            const float* __restrict__ lam_p,
                                                            float h, float* __restrict__ lam_x,
@@ -314,9 +377,8 @@ __global__ void __launch_bounds__(256) kick_vjp_pos_kernel(const float* __restri
     for (int oy = 0; oy < 2; ++oy)
 #pragma unroll
       for (int ox = 0; ox < 2; ++ox) {
-        float g[3];
-        grid_g(phi, wrapi(w.i0[0] + ox, n), wrapi(w.i0[1] + oy, n), wrapi(w.i0[2] + oz, n), n, g);
-        const float gl = g[0] * lp[0] + g[1] * lp[1] + g[2] * lp[2];
+        const float4 g = g4[corner(w, ox, oy, oz, n)];
+        const float gl = g.x * lp[0] + g.y * lp[1] + g.z * lp[2];
         const float wx = wsel(w.w1[0], ox), wy = wsel(w.w1[1], oy), wz = wsel(w.w1[2], oz);
         acc[0] += (ox ? 1.0f : -1.0f) * wy * wz * gl;
         acc[1] += wx * (oy ? 1.0f : -1.0f) * wz * gl;
@@ -341,9 +403,7 @@ __global__ void __launch_bounds__(256) deposit_vjp_pos_kernel(const float* __res
     for (int oy = 0; oy < 2; ++oy)
 #pragma unroll
       for (int ox = 0; ox < 2; ++ox) {
-        const long long c = (static_cast<long long>(wrapi(w.i0[2] + oz, n)) * n +
-                             wrapi(w.i0[1] + oy, n)) * n + wrapi(w.i0[0] + ox, n);
-        const float l = lam_delta[c];
+        const float l = lam_delta[corner(w, ox, oy, oz, n)];
         const float wx = wsel(w.w1[0], ox), wy = wsel(w.w1[1], oy), wz = wsel(w.w1[2], oz);
         acc[0] += (ox ? 1.0f : -1.0f) * wy * wz * l;
         acc[1] += wx * (oy ? 1.0f : -1.0f) * wz * l;
@@ -388,7 +448,7 @@ void launch_keys(hipStream_t st, const float* pos, uint32_t* key, int n) {
   DH_LAUNCH_CHECK();
 }
 
-void launch_sort(hipStream_t st, const Bins& b, int n) {
+void launch_sort(hipStream_t st, const Bins& b, const float* pos, int n) {
   const long long nc = static_cast<long long>(n) * n * n, np = nc;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.count, 0u, nc);
   DH_LAUNCH_CHECK();
@@ -410,51 +470,66 @@ void launch_sort(hipStream_t st, const Bins& b, int n) {
   hipLaunchKernelGGL(bin_sort_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.start,
                      b.sorted, nc);
   DH_LAUNCH_CHECK();
-}
-
-void launch_deposit(hipStream_t st, const Bins& b, const float* pos, const float* rho_gas,
-                    float m_dm, float offset, float* out, int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(deposit_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.start,
-                     b.sorted, pos, rho_gas, m_dm, offset, out, n, nc);
+  hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, b.sorted,
+                     pos, b.spos, np);
   DH_LAUNCH_CHECK();
 }
 
-void launch_deposit_vec(hipStream_t st, const Bins& b, const float* pos, const float* v,
-                        float scale, float* out_accum, int n) {
+void launch_gather_sorted(hipStream_t st, const Bins& b, const float* v, int n) {
+  const long long np = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, b.sorted,
+                     v, b.sval, np);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_deposit(hipStream_t st, const Bins& b, const float* rho_gas, float m_dm, float offset,
+                    float* out, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(deposit_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.start, b.spos,
+                     rho_gas, m_dm, offset, out, n);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_deposit_vec(hipStream_t st, const Bins& b, float scale, float* out_accum, int n) {
   const long long nc = static_cast<long long>(n) * n * n;
   hipLaunchKernelGGL(deposit_vec_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.start,
-                     b.sorted, pos, v, scale, out_accum, n, nc);
+                     b.spos, b.sval, scale, out_accum, n);
   DH_LAUNCH_CHECK();
 }
 
-void launch_readout_g(hipStream_t st, const float* phi, const float* pos, float* out, int n) {
+void launch_grad(hipStream_t st, const float* phi, float4* g4, int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(grad_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, phi, g4, n);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float* out, int n) {
   const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(readout_g_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, phi, pos, out,
+  hipLaunchKernelGGL(readout_g_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, g4, pos, out,
                      n, np);
   DH_LAUNCH_CHECK();
 }
 
-void launch_kick_drift(hipStream_t st, const float* phi, float* pos, float* mom, uint32_t* key,
+void launch_kick_drift(hipStream_t st, const float4* g4, float* pos, float* mom, uint32_t* key,
                        float h_kick, float drift_fac, int n) {
   const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(kick_drift_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, phi, pos, mom,
+  hipLaunchKernelGGL(kick_drift_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, g4, pos, mom,
                      key, h_kick, drift_fac, n, np);
   DH_LAUNCH_CHECK();
 }
 
-void launch_kick(hipStream_t st, const float* phi, const float* pos, float* mom, float h_kick,
+void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom, float h_kick,
                  int n) {
   const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(kick_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, phi, pos, mom,
+  hipLaunchKernelGGL(kick_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, g4, pos, mom,
                      h_kick, n, np);
   DH_LAUNCH_CHECK();
 }
 
-void launch_kick_vjp_pos(hipStream_t st, const float* phi, const float* pos, const float* lam_p,
+void launch_kick_vjp_pos(hipStream_t st, const float4* g4, const float* pos, const float* lam_p,
                          float h_kick, float* lam_x, int n) {
   const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(kick_vjp_pos_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, phi, pos,
+  hipLaunchKernelGGL(kick_vjp_pos_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, g4, pos,
                      lam_p, h_kick, lam_x, n, np);
   DH_LAUNCH_CHECK();
 }

@@ -16,18 +16,6 @@ constexpr int kRedPer = 8;   // cells per thread in reduction kernels
 
 __device__ __forceinline__ int wrapi(int j, int n) { return j & (n - 1); }
 
-__device__ __forceinline__ void cell_g(const float* __restrict__ phi, long long c, int n, float g[3]) {
-  const long long nn = static_cast<long long>(n) * n;
-  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
-            iz = static_cast<int>(c / nn);
-  const long long zo = static_cast<long long>(iz) * nn, yo = static_cast<long long>(iy) * n;
-  g[0] = -0.5f * (phi[zo + yo + wrapi(ix + 1, n)] - phi[zo + yo + wrapi(ix - 1, n)]);
-  g[1] = -0.5f * (phi[zo + static_cast<long long>(wrapi(iy + 1, n)) * n + ix] -
-                  phi[zo + static_cast<long long>(wrapi(iy - 1, n)) * n + ix]);
-  g[2] = -0.5f * (phi[static_cast<long long>(wrapi(iz + 1, n)) * nn + yo + ix] -
-                  phi[static_cast<long long>(wrapi(iz - 1, n)) * nn + yo + ix]);
-}
-
 // block reduction of nv doubles per thread into out[v * gridDim.x + blockIdx.x]
 template <int NV, bool MAX>
 __device__ void block_reduce_store(double (&v)[NV], double* out) {
@@ -52,34 +40,42 @@ __device__ void block_reduce_store(double (&v)[NV], double* out) {
 
 // ------------------------------------------------------------------------- gas kick
 // m' = m + rho g h ; Et' = Et + h g . (m + m')/2   (internal energy unchanged)
-__global__ void __launch_bounds__(256) gas_kick_kernel(float* __restrict__ q,
-                                                       const float* __restrict__ phi, float h,
-                                                       int n, long long nc) {
-  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  float g[3];
-  cell_g(phi, c, n, g);
-  const float rho = q[c];
+__device__ __forceinline__ void kick_cell(float rho, const float4 g4, float h, float m[3],
+                                          float& et) {
+  const float g[3] = {g4.x, g4.y, g4.z};
   float de = 0.0f;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const float m0 = q[(1 + d) * nc + c];
+    const float m0 = m[d];
     const float m1 = m0 + rho * g[d] * h;
-    q[(1 + d) * nc + c] = m1;
+    m[d] = m1;
     de += 0.5f * (m0 + m1) * g[d];
   }
-  q[4 * nc + c] += de * h;
+  et += de * h;
+}
+
+__global__ void __launch_bounds__(256) gas_kick_kernel(float* __restrict__ q,
+                                                       const float4* __restrict__ g4, float h,
+                                                       long long nc) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  float m[3] = {q[nc + c], q[2 * nc + c], q[3 * nc + c]};
+  float et = q[4 * nc + c];
+  kick_cell(q[c], g4[c], h, m, et);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) q[(1 + d) * nc + c] = m[d];
+  q[4 * nc + c] = et;
 }
 
 __global__ void __launch_bounds__(256) gas_kick_vjp_kernel(const float* __restrict__ q,
-                                                           const float* __restrict__ phi, float h,
+                                                           const float4* __restrict__ g4, float h,
                                                            float* __restrict__ lam,
-                                                           float* __restrict__ lam_g, int n,
+                                                           float* __restrict__ lam_g,
                                                            long long nc) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nc) return;
-  float g[3];
-  cell_g(phi, c, n, g);
+  const float4 gv = g4[c];
+  const float g[3] = {gv.x, gv.y, gv.z};
   const float rho = q[c];
   const float le = lam[4 * nc + c];
   float lr = lam[c];
@@ -109,50 +105,154 @@ __device__ __forceinline__ double log_sigmoid_(double y) {
   return fmin(y, 0.0) - log1p(exp(-fabs(y)));
 }
 
-__device__ SrcCell source_eval(const float* __restrict__ q, long long c, long long nc,
-                               const SourceArgs& a) {
+__device__ __forceinline__ float log_sigmoidf_(float y) {
+  return fminf(y, 0.0f) - log1pf(expf(-fabsf(y)));
+}
+
+// The uniform of cell c for the draw of the given step.
+__device__ __forceinline__ double starform_uniform(long long c, const SourceArgs& a) {
+  uint32_t ctr[4] = {static_cast<uint32_t>(c), a.step, kTagStarform, 0u};
+  philox4x32_10(ctr, a.seed_lo, a.seed_hi);
+  return uniform_open_d(ctr[0]);
+}
+
+// True when the relaxed draw is certainly below e^-109 (zero in float, and no change of the
+// energy in float): a float32 estimate of its argument is below -110.  Not used where the
+// float32 probability nears underflow, since there the estimate is not accurate enough.
+__device__ bool draw_negligible(const float q5[5], double u, const SourceArgs& a) {
+  if (a.mode != 2) return false;
+  const float rho = q5[0];
+  const float ir = 1.0f / rho, ia = static_cast<float>(1.0 / a.a);
+  const float u0 = q5[1] * ia * ir, u1 = q5[2] * ia * ir, u2 = q5[3] * ia * ir;
+  const float e = fmaxf(q5[4] * ia * ia * ir - 0.5f * (u0 * u0 + u1 * u1 + u2 * u2),
+                        static_cast<float>(a.efloor));
+  const float temp = e * static_cast<float>(a.t_per_e);
+  const float delta = rho * static_cast<float>(a.inv_rho_mean);
+  const float a3 = static_cast<float>(a.a * a.a * a.a);
+  const float tff = 1.5707963f * sqrtf(a3 / (static_cast<float>(a.omega_b) * delta));
+  const float psf = -expm1f(-static_cast<float>(a.eps_sf * a.dt) / tff);
+  if (!(psf > 1e-30f)) return false;
+  const float y1 = (delta - static_cast<float>(a.delta_c)) / static_cast<float>(a.w_rho * a.delta_c);
+  const float y2 = (static_cast<float>(a.t_c) - temp) / static_cast<float>(a.w_t * a.t_c);
+  const float logpi = logf(psf) + log_sigmoidf_(y1) + log_sigmoidf_(y2);
+  const float uf = static_cast<float>(u);
+  const float arg = (logpi - log1pf(-expf(logpi)) + logf(uf) - log1pf(-uf)) /
+                    static_cast<float>(a.tau);
+  return arg < -110.0f;
+}
+
+__device__ SrcCell source_eval(const float q5[5], double u, const SourceArgs& a) {
   SrcCell s;
-  s.rho = q[c];
+  s.rho = q5[0];
   const double ir = 1.0 / s.rho;
   const double ia = 1.0 / a.a;
-  const double u0 = q[nc + c] * ia * ir, u1 = q[2 * nc + c] * ia * ir, u2 = q[3 * nc + c] * ia * ir;
-  s.eraw = q[4 * nc + c] * ia * ia * ir - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+  const double u0 = q5[1] * ia * ir, u1 = q5[2] * ia * ir, u2 = q5[3] * ia * ir;
+  s.eraw = q5[4] * ia * ia * ir - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
   s.floored = s.eraw < a.efloor;
   s.e = s.floored ? a.efloor : s.eraw;
   s.temp = s.e * a.t_per_e;
   s.delta = s.rho * a.inv_rho_mean;
+  s.u = u;
+  if (a.mode == 1) {
+    s.x = 0.0;
+    s.psf = 0.0;
+    const double gate = (s.delta > a.delta_c && s.temp < a.t_c) ? 1.0 : 0.0;
+    s.s1 = s.s2 = gate;
+    s.pi0 = 0.0;
+    s.z = 0.0;
+    if (gate > 0.0) {   // the draw matters only where the thresholds are passed
+      const double tff = 1.5707963267948966 * sqrt(a.a * a.a * a.a / (a.omega_b * s.delta));
+      s.x = a.eps_sf * a.dt / tff;
+      s.psf = -expm1(-s.x);
+      s.pi0 = s.psf;
+      s.z = s.u > 1.0 - s.pi0 ? 1.0 : 0.0;
+    }
+    return s;
+  }
   const double tff = 1.5707963267948966 * sqrt(a.a * a.a * a.a / (a.omega_b * s.delta));
   s.x = a.eps_sf * a.dt / tff;
   s.psf = -expm1(-s.x);
-  uint32_t ctr[4] = {static_cast<uint32_t>(c), a.step, kTagStarform, 0u};
-  philox4x32_10(ctr, a.seed_lo, a.seed_hi);
-  s.u = uniform_open_d(ctr[0]);
-  if (a.mode == 1) {
-    const double gate = (s.delta > a.delta_c && s.temp < a.t_c) ? 1.0 : 0.0;
-    s.s1 = s.s2 = gate;
-    s.pi0 = s.psf * gate;
-    s.z = s.u > 1.0 - s.pi0 ? 1.0 : 0.0;
-  } else {
-    const double y1 = (s.delta - a.delta_c) / (a.w_rho * a.delta_c);
-    const double y2 = (a.t_c - s.temp) / (a.w_t * a.t_c);
-    s.s1 = sigmoid_(y1);
-    s.s2 = sigmoid_(y2);
-    s.pi0 = s.psf * s.s1 * s.s2;
-    const double logpi = log(s.psf) + log_sigmoid_(y1) + log_sigmoid_(y2);
-    const double logit = logpi - log1p(-s.pi0);
-    const double noise = log(s.u) - log1p(-s.u);
-    s.z = sigmoid_((logit + noise) / a.tau);
-  }
+  const double y1 = (s.delta - a.delta_c) / (a.w_rho * a.delta_c);
+  const double y2 = (a.t_c - s.temp) / (a.w_t * a.t_c);
+  s.s1 = sigmoid_(y1);
+  s.s2 = sigmoid_(y2);
+  s.pi0 = s.psf * s.s1 * s.s2;
+  const double logpi = log(s.psf) + log_sigmoid_(y1) + log_sigmoid_(y2);
+  const double logit = logpi - log1p(-s.pi0);
+  const double noise = log(s.u) - log1p(-s.u);
+  s.z = sigmoid_((logit + noise) / a.tau);
   return s;
+}
+
+__device__ __forceinline__ void load_q(const float* __restrict__ q, long long c, long long nc,
+                                       float q5[5]) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) q5[k] = q[k * nc + c];
+}
+
+// FP64 CFL speed of one cell: max_d (|U_d| + c_s) / a; +inf flags a broken state
+__device__ __forceinline__ double cell_speed(const float q5[5], double a, double gg1,
+                                             double efloor) {
+  const double rho = q5[0];
+  const double ia = 1.0 / a;
+  const double u0 = q5[1] * ia / rho, u1 = q5[2] * ia / rho, u2 = q5[3] * ia / rho;
+  double e = q5[4] * ia * ia / rho - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+  e = fmax(e, efloor);
+  const double cs = sqrt(gg1 * e);
+  double sp = (fmax(fabs(u0), fmax(fabs(u1), fabs(u2))) + cs) * ia;
+  if (!(rho > 0.0) || !isfinite(sp)) sp = INFINITY;
+  return sp;
 }
 
 __global__ void __launch_bounds__(256) source_kernel(float* __restrict__ q, float* __restrict__ star,
                                                      SourceArgs a, long long nc) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nc) return;
-  const SrcCell s = source_eval(q, c, nc, a);
-  q[4 * nc + c] = static_cast<float>(q[4 * nc + c] + a.a * a.a * s.rho * s.z * a.e0_code);
+  float q5[5];
+  load_q(q, c, nc, q5);
+  const double u = starform_uniform(c, a);
+  if (draw_negligible(q5, u, a)) return;
+  const SrcCell s = source_eval(q5, u, a);
+  q[4 * nc + c] = static_cast<float>(q5[4] + a.a * a.a * s.rho * s.z * a.e0_code);
   star[c] = static_cast<float>(star[c] + s.z);
+}
+
+// Closing pass of a step over kRedPer cells per thread: gas half kick, optional tape copy,
+// source term, CFL block maximum of the result.
+__global__ void __launch_bounds__(kRedThreads) close_step_kernel(
+    float* __restrict__ q, const float4* __restrict__ g4, float h, float* __restrict__ star,
+    SourceArgs a, float* __restrict__ q_kicked, double gg1, double* partial, long long nc) {
+  double vmax[1] = {0.0};
+  const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
+  for (int r = 0; r < kRedPer; ++r) {
+    const long long c = base + r * kRedThreads + threadIdx.x;
+    if (c >= nc) break;
+    float q5[5];
+    load_q(q, c, nc, q5);
+    float m[3] = {q5[1], q5[2], q5[3]};
+    kick_cell(q5[0], g4[c], h, m, q5[4]);
+    q5[1] = m[0];
+    q5[2] = m[1];
+    q5[3] = m[2];
+    if (q_kicked) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) q_kicked[k * nc + c] = q5[k];
+    }
+    if (a.mode != 0) {
+      const double u = starform_uniform(c, a);
+      if (!draw_negligible(q5, u, a)) {
+        const SrcCell s = source_eval(q5, u, a);
+        if (s.z != 0.0) {
+          q5[4] = static_cast<float>(q5[4] + a.a * a.a * s.rho * s.z * a.e0_code);
+          star[c] = static_cast<float>(star[c] + s.z);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 1; k < 5; ++k) q[k * nc + c] = q5[k];
+    vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
+  }
+  block_reduce_store<1, true>(vmax, partial);
 }
 
 // lam (in: adjoint after the source, out: before); partial[0|1][block] = dL/d(eps_sf|delta_c)
@@ -165,7 +265,11 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_kernel(const float* __
   for (int r = 0; r < kRedPer; ++r) {
     const long long c = base + r * kRedThreads + threadIdx.x;
     if (c >= nc) break;
-    const SrcCell s = source_eval(q, c, nc, a);
+    float q5[5];
+    load_q(q, c, nc, q5);
+    const double u = starform_uniform(c, a);
+    if (draw_negligible(q5, u, a)) continue;   // z and its derivatives are below 1e-47
+    const SrcCell s = source_eval(q5, u, a);
     const double le = lam[4 * nc + c];
     const double K = a.a * a.a * a.e0_code;
     // Et' = Et + K rho z
@@ -183,7 +287,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_kernel(const float* __
       const double ir = 1.0 / s.rho, ia = 1.0 / a.a;
       double u[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) u[d] = q[(1 + d) * nc + c] * ia * ir;
+      for (int d = 0; d < 3; ++d) u[d] = q5[1 + d] * ia * ir;
       const double ke = 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
       const double de_drho = (ke - s.eraw) * ir;
       lr += coef * (dlnpi_drho_sf + dlnpi_drho_s1 + dlnpi_dT * dT * de_drho);
@@ -210,16 +314,9 @@ __global__ void __launch_bounds__(kRedThreads) cfl_partial_kernel(const float* _
   for (int r = 0; r < kRedPer; ++r) {
     const long long c = base + r * kRedThreads + threadIdx.x;
     if (c >= nc) break;
-    const double rho = q[c];
-    const double ia = 1.0 / a;
-    const double u0 = q[nc + c] * ia / rho, u1 = q[2 * nc + c] * ia / rho,
-                 u2 = q[3 * nc + c] * ia / rho;
-    double e = q[4 * nc + c] * ia * ia / rho - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
-    e = fmax(e, efloor);
-    const double cs = sqrt(gg1 * e);
-    double s = (fmax(fabs(u0), fmax(fabs(u1), fabs(u2))) + cs) * ia;
-    if (!(rho > 0.0) || !isfinite(s)) s = INFINITY;   // flags a broken state
-    v[0] = fmax(v[0], s);
+    float q5[5];
+    load_q(q, c, nc, q5);
+    v[0] = fmax(v[0], cell_speed(q5, a, gg1, efloor));
   }
   block_reduce_store<1, true>(v, partial);
 }
@@ -397,17 +494,26 @@ __global__ void fill_kernel(float* p, float v, long long count) {
 
 }  // namespace
 
-void launch_gas_kick(hipStream_t st, float* q, const float* phi, float h, int n) {
+void launch_gas_kick(hipStream_t st, float* q, const float4* g4, float h, int n) {
   const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(gas_kick_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, phi, h, n, nc);
+  hipLaunchKernelGGL(gas_kick_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, g4, h, nc);
   DH_LAUNCH_CHECK();
 }
 
-void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float* phi, float h,
+void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4, float h,
                          float* lam_q, float* lam_g, int n) {
   const long long nc = static_cast<long long>(n) * n * n;
   hipLaunchKernelGGL(gas_kick_vjp_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q_before,
-                     phi, h, lam_q, lam_g, n, nc);
+                     g4, h, lam_q, lam_g, nc);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_close_step(hipStream_t st, float* q, const float4* g4, float h, float* star,
+                       const SourceArgs& a, float* q_kicked, double gamma, double* block_max,
+                       int n) {
+  const long long nc = static_cast<long long>(n) * n * n;
+  hipLaunchKernelGGL(close_step_kernel, dim3(sum_blocks(nc)), dim3(kRedThreads), 0, st, q, g4, h,
+                     star, a, q_kicked, gamma * (gamma - 1.0), block_max, nc);
   DH_LAUNCH_CHECK();
 }
 
@@ -431,12 +537,11 @@ void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, cons
   DH_LAUNCH_CHECK();
 }
 
-void launch_cfl_partial(hipStream_t st, const float* q, float a, float gamma, float efloor,
+void launch_cfl_partial(hipStream_t st, const float* q, double a, double gamma, double efloor,
                         double* block_max, int n) {
   const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(cfl_partial_kernel, dim3(cfl_blocks(n)), dim3(kRedThreads), 0, st, q,
-                     static_cast<double>(a), static_cast<double>(gamma) * (gamma - 1.0),
-                     static_cast<double>(efloor), block_max, nc);
+  hipLaunchKernelGGL(cfl_partial_kernel, dim3(cfl_blocks(n)), dim3(kRedThreads), 0, st, q, a,
+                     gamma * (gamma - 1.0), efloor, block_max, nc);
   DH_LAUNCH_CHECK();
 }
 
