@@ -40,7 +40,7 @@ const int kStrang[6][3] = {{0, 1, 2}, {2, 1, 0}, {2, 0, 1}, {1, 0, 2}, {1, 2, 0}
 struct TapeStep {
   float* q[6];      // Q0 start, Q1 after opening kick (sweep-1 input), Q2, Q3 sweep inputs,
                     // Q4 after sweeps, Q5 after closing kick (source input)
-  float *x0, *p0, *x1, *ph;   // positions/momenta at start, after drift, momenta after kick
+  float *x0, *x1;             // particle positions at the start and after the drift
   float *phi0, *phi1;
   Plan plan;
 };
@@ -241,33 +241,38 @@ void do_step(dh_sim* s, const Plan& pl, TapeStep* tp) {
     tp->plan = pl;
     copy_d2d(s, tp->q[0], s->q, 5 * nc);
     copy_d2d(s, tp->x0, s->pos, 3 * np);
-    copy_d2d(s, tp->p0, s->mom, 3 * np);
     copy_d2d(s, tp->phi0, s->phi, nc);
   }
-  // opening half kicks with g_n, drift with a(t + dt/2)
-  dh::launch_gas_kick(s->st, s->q, s->g4, h, n);
-  dh::launch_kick_drift(s->st, s->g4, s->pos, s->mom, s->bins.key, h,
-                        static_cast<float>(pl.dt / (pl.ah * pl.ah)), n);
-  if (tp) {
-    copy_d2d(s, tp->ph, s->mom, 3 * np);
-    copy_d2d(s, tp->x1, s->pos, 3 * np);
-  }
-  // sweeps
   const dh::HydroK h1 = hydro_at(s, pl.a0), h2 = hydro_at(s, pl.ah);
-  for (int k = 0; k < 3; ++k) {
-    if (tp) copy_d2d(s, tp->q[1 + k], s->q, 5 * nc);
-    dh::launch_sweep(s->st, s->q, s->q2, n, pl.axes[k], static_cast<float>(pl.dt), h1, h2);
-    std::swap(s->q, s->q2);
+  const float dtf = static_cast<float>(pl.dt);
+  const float drift = static_cast<float>(pl.dt / (pl.ah * pl.ah));
+  if (tp) {
+    // the kick, the sweeps and the closing pass write their results straight into the tape
+    dh::launch_gas_kick(s->st, s->q, tp->q[1], s->g4, h, n);
+    dh::launch_kick_drift(s->st, s->g4, s->pos, s->mom, s->bins.key, h, drift, nullptr, tp->x1, n);
+    for (int k = 0; k < 3; ++k)
+      dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], n, pl.axes[k], dtf, h1, h2);
+    dh::launch_sort(s->st, s->bins, s->pos, n);
+    potential_from_bins(s, tp->q[4], s->phi, s->g4, pl.a1);
+    copy_d2d(s, tp->phi1, s->phi, nc);
+    dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, h, s->star, source_args(s, pl), tp->q[5],
+                          s->cfg.gamma, s->cfl_red, n);
+  } else {
+    // opening half kicks with g_n, drift with a(t + dt/2)
+    dh::launch_gas_kick(s->st, s->q, s->q, s->g4, h, n);
+    dh::launch_kick_drift(s->st, s->g4, s->pos, s->mom, s->bins.key, h, drift, nullptr, nullptr, n);
+    // sweeps in the Strang order of the step
+    for (int k = 0; k < 3; ++k) {
+      dh::launch_sweep(s->st, s->q, s->q2, n, pl.axes[k], dtf, h1, h2);
+      std::swap(s->q, s->q2);
+    }
+    // Poisson at a(t + dt) from gas + DM (keys were written by the drift)
+    dh::launch_sort(s->st, s->bins, s->pos, n);
+    potential_from_bins(s, s->q, s->phi, s->g4, pl.a1);
+    // closing gas half kick with g_{n+1}, source term and the CFL maxima: one pass
+    dh::launch_close_step(s->st, s->q, s->q, s->g4, h, s->star, source_args(s, pl), nullptr,
+                          s->cfg.gamma, s->cfl_red, n);
   }
-  if (tp) copy_d2d(s, tp->q[4], s->q, 5 * nc);
-  // Poisson at a(t + dt) from gas + DM (keys were written by the drift)
-  dh::launch_sort(s->st, s->bins, s->pos, n);
-  potential_from_bins(s, s->q, s->phi, s->g4, pl.a1);
-  if (tp) copy_d2d(s, tp->phi1, s->phi, nc);
-  // closing half kicks with g_{n+1}; the gas kick, the source term and the CFL maxima of the
-  // new state are one pass over the cells
-  dh::launch_close_step(s->st, s->q, s->g4, h, s->star, source_args(s, pl),
-                        tp ? tp->q[5] : nullptr, s->cfg.gamma, s->cfl_red, n);
   dh::launch_kick(s->st, s->g4, s->pos, s->mom, h, n);
   DH_LAUNCH_CHECK();
   s->t = pl.t0 + pl.dt;
@@ -347,9 +352,7 @@ int step_once(dh_sim* s, double t_end, TapeStep* tp, double* dt_used) {
 void alloc_tape_entry(dh_sim* s, TapeStep& t) {
   for (int k = 0; k < 6; ++k) t.q[k] = s->alloc<float>(5 * s->nc);
   t.x0 = s->alloc<float>(3 * s->np);
-  t.p0 = s->alloc<float>(3 * s->np);
   t.x1 = s->alloc<float>(3 * s->np);
-  t.ph = s->alloc<float>(3 * s->np);
   t.phi0 = s->alloc<float>(s->nc);
   t.phi1 = s->alloc<float>(s->nc);
 }
@@ -389,7 +392,11 @@ void load_ckpt(dh_sim* s, const Ckpt& c) {
 // Adjoint of one step.  In: lq, lx, lp, lphi = adjoints of the state after the step (lphi is
 // the adjoint of phi_{n+1} from the following step).  Out: the same buffers hold the
 // adjoints of the state at the start of the step.
-void step_vjp(dh_sim* s, const TapeStep& T, int param_slot) {
+// The opening dark-matter kick of the following step acts at the same positions, with the
+// same g and the same adjoint momentum as this step's closing kick, so its adjoint is merged
+// here with factor h_next (0 for the last step); this step's own opening kick is left to the
+// previous step, or to finish_first_kick after the first step.
+void step_vjp(dh_sim* s, const TapeStep& T, int param_slot, float h_next) {
   const int n = s->n;
   const long long nc = s->nc, np = s->np;
   const Plan& pl = T.plan;
@@ -406,8 +413,8 @@ void step_vjp(dh_sim* s, const TapeStep& T, int param_slot) {
   dh::launch_gas_kick_vjp(st, T.q[4], s->g4b, h, s->lq, s->lg, n);
   sort_particles(s, T.x1);
   dh::launch_gather_sorted(st, s->bins, s->lp, n);
-  dh::launch_deposit_vec(st, s->bins, h, s->lg, n);
-  dh::launch_kick_vjp_pos(st, s->g4b, T.x1, s->lp, h, s->lx, n);
+  dh::launch_deposit_vec(st, s->bins, h + h_next, s->lg, n);
+  dh::launch_kick_vjp_pos(st, s->g4b, T.x1, s->lp, h + h_next, s->lx, n);
   dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi2, n);
   // Poisson (symmetric operator) and deposit at x1
   poisson(s, s->lphi2, s->ldelta, pl.a1);
@@ -422,14 +429,24 @@ void step_vjp(dh_sim* s, const TapeStep& T, int param_slot) {
   }
   // drift: x1 = x0 + p_half dt / a_h^2
   dh::launch_axpy(st, s->lp, s->lx, static_cast<float>(pl.dt / (pl.ah * pl.ah)), 3 * np);
-  // opening kicks with phi_n at x0
+  // opening gas kick with phi_n
   dh::launch_grad(st, T.phi0, s->g4b, n);
   dh::launch_gas_kick_vjp(st, T.q[0], s->g4b, h, s->lq, s->lg, n);
+  dh::launch_grad_vjp(st, s->lg, nullptr, s->lphi, n);
+}
+
+// Adjoint of the opening dark-matter kick of the first step (x0, phi0 of its tape entry)
+void finish_first_kick(dh_sim* s, const TapeStep& T) {
+  const int n = s->n;
+  const float h = static_cast<float>(0.5 * T.plan.dt);
+  hipStream_t st = s->st;
+  dh::launch_grad(st, T.phi0, s->g4b, n);
+  dh::launch_fill(st, s->lg, 0.0f, 3 * s->nc);
   sort_particles(s, T.x0);
   dh::launch_gather_sorted(st, s->bins, s->lp, n);
   dh::launch_deposit_vec(st, s->bins, h, s->lg, n);
   dh::launch_kick_vjp_pos(st, s->g4b, T.x0, s->lp, h, s->lx, n);
-  dh::launch_grad_vjp(st, s->lg, nullptr, s->lphi, n);
+  dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi, n);
 }
 
 // Adjoint of the initial conditions: lq, lx, lp, lphi at a_init -> d_grad_white
@@ -851,12 +868,17 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     save_ckpt(s, final_state);
     const std::vector<double> sched = s->recorded;
     dh::launch_fill(s->st, reinterpret_cast<float*>(s->param_steps), 0.0f, 4LL * s->param_cap);
+    float h_next = 0.0f;
     for (int g = nseg - 1; g >= 0; --g) {
       load_ckpt(s, s->ckpts[g]);
       const int s0 = g * K, s1 = std::min(nsteps, s0 + K);
       for (int k = s0; k < s1; ++k) do_step(s, make_plan(s, sched[k]), &s->tape[k - s0]);
-      for (int k = s1 - 1; k >= s0; --k) step_vjp(s, s->tape[k - s0], k);
+      for (int k = s1 - 1; k >= s0; --k) {
+        step_vjp(s, s->tape[k - s0], k, h_next);
+        h_next = static_cast<float>(0.5 * sched[k]);
+      }
     }
+    if (nsteps > 0) finish_first_kick(s, s->tape[0]);
     ic_vjp(s, d_grad_white);
     // restore the final state of the forward run
     load_ckpt(s, final_state);

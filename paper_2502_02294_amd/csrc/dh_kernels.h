@@ -41,9 +41,9 @@ void launch_deposit_vec(hipStream_t st, const Bins& b, float scale, float* out_a
 void launch_grad(hipStream_t st, const float* phi, float4* g4, int n);
 // g at particles: out[3][np] = CIC read-out of g4
 void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float* out, int n);
-// opening kick + drift (+ keys), closing kick
+// opening kick + drift (+ keys; optional copies of the new momenta and positions), closing kick
 void launch_kick_drift(hipStream_t st, const float4* g4, float* pos, float* mom, uint32_t* key,
-                       float h_kick, float drift_fac, int n);
+                       float h_kick, float drift_fac, float* mom_copy, float* pos_copy, int n);
 void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom, float h_kick,
                  int n);
 // adjoint of p' = p + h g(x) with respect to x: lam_x += h sum_c dw/dx (g_c . lam_p')
@@ -75,7 +75,9 @@ void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* t
                   bool forward_first, bool inverse_after, bool accumulate);
 
 // ---- pointwise / reductions (k_point.hip)
-void launch_gas_kick(hipStream_t st, float* q, const float4* g4, float h, int n);
+// q_out = q_in after the half kick (q_out may equal q_in)
+void launch_gas_kick(hipStream_t st, const float* q_in, float* q_out, const float4* g4, float h,
+                     int n);
 void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4, float h,
                          float* lam_q, float* lam_g, int n);
 struct SourceArgs {   // FP64: the source term is evaluated in double precision
@@ -85,12 +87,12 @@ struct SourceArgs {   // FP64: the source term is evaluated in double precision
   uint32_t seed_lo, seed_hi, step;
 };
 void launch_source(hipStream_t st, float* q, float* star, const SourceArgs& a, int n);
-// closing pass of a step: gas half kick with g4, optional copy of the kicked state to
+// closing pass of a step, from q_in (may equal q) into q: gas half kick with g4, optional copy of the kicked state to
 // q_kicked (tape), source term (if a.mode != 0), FP64 block maxima of the CFL speed of the
 // result at scale factor a.a into block_max[cfl_blocks(n)]
-void launch_close_step(hipStream_t st, float* q, const float4* g4, float h, float* star,
-                       const SourceArgs& a, float* q_kicked, double gamma, double* block_max,
-                       int n);
+void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4* g4, float h,
+                       float* star, const SourceArgs& a, float* q_kicked, double gamma,
+                       double* block_max, int n);
 // adjoint of the source term; accumulates dL/d(eps_sf, delta_c) partials per block
 void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, const SourceArgs& a,
                        double* partials, int nblocks_out, int n);

@@ -180,55 +180,54 @@ __global__ void gather_sorted_kernel(const uint32_t* __restrict__ sorted,
 }
 
 // ---------------------------------------------------------------------------- deposit
-// For cell (ix, iy, iz) and each (oz, oy): the bin with x index ix-1 (weight w1 in x) is
-// visited before the bin ix (weight 1-w1); when ix = 0 the first bin wraps to n-1.
+// For cell (ix, iy, iz) and each (oz, oy) in the order (0,0), (0,1), (1,0), (1,1): the bin
+// with x index ix-1 (weight w1 in x) is visited before the bin ix (weight 1-w1); when ix = 0
+// the first bin wraps to n-1.
 template <bool VEC>
 __device__ __forceinline__ void deposit_cell(const uint32_t* __restrict__ start,
                                              const float4* __restrict__ spos,
                                              const float4* __restrict__ sval, int ix, int iy,
                                              int iz, int n, float acc[3]) {
+  // all bin bounds first (independent loads), then the particle ranges
+  uint32_t a0[4], a1[4], b0[4], b1[4];
+  const int xm = wrapi(ix - 1, n);
 #pragma unroll
-  for (int oz = 0; oz < 2; ++oz)
+  for (int r = 0; r < 4; ++r) {
+    const int oz = r >> 1, oy = r & 1;
+    const long long row = (static_cast<long long>(wrapi(iz - oz, n)) * n + wrapi(iy - oy, n)) * n;
+    a0[r] = start[row + xm];
+    a1[r] = start[row + xm + 1];
+    b0[r] = start[row + ix];
+    b1[r] = start[row + ix + 1];
+  }
 #pragma unroll
-    for (int oy = 0; oy < 2; ++oy) {
-      const long long row = (static_cast<long long>(wrapi(iz - oz, n)) * n + wrapi(iy - oy, n)) * n;
-      uint32_t a0, a1, b0, b1;
-      if (ix > 0) {
-        a0 = start[row + ix - 1];
-        a1 = start[row + ix];
-        b0 = a1;
-        b1 = start[row + ix + 1];
+  for (int r = 0; r < 4; ++r) {
+    const int oz = r >> 1, oy = r & 1;
+    for (uint32_t j = a0[r]; j < a1[r]; ++j) {   // bin ix-1: weight w1 in x
+      const float4 p = spos[j];
+      const float w = w1_of(p.x) * wsel(w1_of(p.y), oy) * wsel(w1_of(p.z), oz);
+      if (VEC) {
+        const float4 v = sval[j];
+        acc[0] += w * v.x;
+        acc[1] += w * v.y;
+        acc[2] += w * v.z;
       } else {
-        a0 = start[row + n - 1];
-        a1 = start[row + n];
-        b0 = start[row];
-        b1 = start[row + 1];
-      }
-      for (uint32_t j = a0; j < a1; ++j) {   // bin ix-1: weight w1 in x
-        const float4 p = spos[j];
-        const float w = w1_of(p.x) * wsel(w1_of(p.y), oy) * wsel(w1_of(p.z), oz);
-        if (VEC) {
-          const float4 v = sval[j];
-          acc[0] += w * v.x;
-          acc[1] += w * v.y;
-          acc[2] += w * v.z;
-        } else {
-          acc[0] += w;
-        }
-      }
-      for (uint32_t j = b0; j < b1; ++j) {   // bin ix: weight 1-w1 in x
-        const float4 p = spos[j];
-        const float w = (1.0f - w1_of(p.x)) * wsel(w1_of(p.y), oy) * wsel(w1_of(p.z), oz);
-        if (VEC) {
-          const float4 v = sval[j];
-          acc[0] += w * v.x;
-          acc[1] += w * v.y;
-          acc[2] += w * v.z;
-        } else {
-          acc[0] += w;
-        }
+        acc[0] += w;
       }
     }
+    for (uint32_t j = b0[r]; j < b1[r]; ++j) {   // bin ix: weight 1-w1 in x
+      const float4 p = spos[j];
+      const float w = (1.0f - w1_of(p.x)) * wsel(w1_of(p.y), oy) * wsel(w1_of(p.z), oz);
+      if (VEC) {
+        const float4 v = sval[j];
+        acc[0] += w * v.x;
+        acc[1] += w * v.y;
+        acc[2] += w * v.z;
+      } else {
+        acc[0] += w;
+      }
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256) deposit_kernel(const uint32_t* __restrict__ start,
@@ -328,7 +327,9 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
                                                          float* __restrict__ pos,
                                                          float* __restrict__ mom,
                                                          uint32_t* __restrict__ key, float h,
-                                                         float drift_fac, int n, long long np) {
+                                                         float drift_fac, float* __restrict__ mom_copy,
+                                                         float* __restrict__ pos_copy, int n,
+                                                         long long np) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= np) return;
   float x[3] = {pos[i], pos[np + i], pos[2 * np + i]};
@@ -342,6 +343,8 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
     mom[d * np + i] = p;
     x[d] = wrap_pos(x[d] + p * drift_fac, fn);
     pos[d * np + i] = x[d];
+    if (mom_copy) mom_copy[d * np + i] = p;
+    if (pos_copy) pos_copy[d * np + i] = x[d];
   }
   const Cic w2 = cic_of(x[0], x[1], x[2], n);
   key[i] = static_cast<uint32_t>((w2.i0[2] * n + w2.i0[1]) * n + w2.i0[0]);
@@ -511,10 +514,10 @@ void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float*
 }
 
 void launch_kick_drift(hipStream_t st, const float4* g4, float* pos, float* mom, uint32_t* key,
-                       float h_kick, float drift_fac, int n) {
+                       float h_kick, float drift_fac, float* mom_copy, float* pos_copy, int n) {
   const long long np = static_cast<long long>(n) * n * n;
   hipLaunchKernelGGL(kick_drift_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, g4, pos, mom,
-                     key, h_kick, drift_fac, n, np);
+                     key, h_kick, drift_fac, mom_copy, pos_copy, n, np);
   DH_LAUNCH_CHECK();
 }
 

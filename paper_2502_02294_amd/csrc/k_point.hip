@@ -54,14 +54,16 @@ __device__ __forceinline__ void kick_cell(float rho, const float4 g4, float h, f
   et += de * h;
 }
 
-__global__ void __launch_bounds__(256) gas_kick_kernel(float* __restrict__ q,
+__global__ void __launch_bounds__(256) gas_kick_kernel(const float* q_in, float* q,
                                                        const float4* __restrict__ g4, float h,
                                                        long long nc) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nc) return;
-  float m[3] = {q[nc + c], q[2 * nc + c], q[3 * nc + c]};
-  float et = q[4 * nc + c];
-  kick_cell(q[c], g4[c], h, m, et);
+  float m[3] = {q_in[nc + c], q_in[2 * nc + c], q_in[3 * nc + c]};
+  float et = q_in[4 * nc + c];
+  const float rho = q_in[c];
+  kick_cell(rho, g4[c], h, m, et);
+  if (q != q_in) q[c] = rho;
 #pragma unroll
   for (int d = 0; d < 3; ++d) q[(1 + d) * nc + c] = m[d];
   q[4 * nc + c] = et;
@@ -220,7 +222,7 @@ __global__ void __launch_bounds__(256) source_kernel(float* __restrict__ q, floa
 // Closing pass of a step over kRedPer cells per thread: gas half kick, optional tape copy,
 // source term, CFL block maximum of the result.
 __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
-    float* __restrict__ q, const float4* __restrict__ g4, float h, float* __restrict__ star,
+    const float* q_in, float* q, const float4* __restrict__ g4, float h, float* __restrict__ star,
     SourceArgs a, float* __restrict__ q_kicked, double gg1, double* partial, long long nc) {
   double vmax[1] = {0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
@@ -228,7 +230,7 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
     const long long c = base + r * kRedThreads + threadIdx.x;
     if (c >= nc) break;
     float q5[5];
-    load_q(q, c, nc, q5);
+    load_q(q_in, c, nc, q5);
     float m[3] = {q5[1], q5[2], q5[3]};
     kick_cell(q5[0], g4[c], h, m, q5[4]);
     q5[1] = m[0];
@@ -249,7 +251,7 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
       }
     }
 #pragma unroll
-    for (int k = 1; k < 5; ++k) q[k * nc + c] = q5[k];
+    for (int k = (q == q_in ? 1 : 0); k < 5; ++k) q[k * nc + c] = q5[k];
     vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
   }
   block_reduce_store<1, true>(vmax, partial);
@@ -494,9 +496,11 @@ __global__ void fill_kernel(float* p, float v, long long count) {
 
 }  // namespace
 
-void launch_gas_kick(hipStream_t st, float* q, const float4* g4, float h, int n) {
+void launch_gas_kick(hipStream_t st, const float* q_in, float* q_out, const float4* g4, float h,
+                     int n) {
   const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(gas_kick_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, g4, h, nc);
+  hipLaunchKernelGGL(gas_kick_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q_in, q_out, g4,
+                     h, nc);
   DH_LAUNCH_CHECK();
 }
 
@@ -508,12 +512,12 @@ void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4
   DH_LAUNCH_CHECK();
 }
 
-void launch_close_step(hipStream_t st, float* q, const float4* g4, float h, float* star,
-                       const SourceArgs& a, float* q_kicked, double gamma, double* block_max,
-                       int n) {
+void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4* g4, float h,
+                       float* star, const SourceArgs& a, float* q_kicked, double gamma,
+                       double* block_max, int n) {
   const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(close_step_kernel, dim3(sum_blocks(nc)), dim3(kRedThreads), 0, st, q, g4, h,
-                     star, a, q_kicked, gamma * (gamma - 1.0), block_max, nc);
+  hipLaunchKernelGGL(close_step_kernel, dim3(sum_blocks(nc)), dim3(kRedThreads), 0, st, q_in, q,
+                     g4, h, star, a, q_kicked, gamma * (gamma - 1.0), block_max, nc);
   DH_LAUNCH_CHECK();
 }
 
