@@ -8,7 +8,8 @@ One step from t_n to t_n + dt (operator order; readings listed in the design doc):
   4. three relaxing-TVD sweeps in the Strang order of this step;
   5. CIC deposit of gas + dark matter and the FFT Poisson solve at a(t_n+dt) -> phi_{n+1};
   6. closing half kicks with g_{n+1}: gas and dark matter;
-  7. the star-formation source term with a(t_n+dt).
+  7. the star-formation source term with a(t_n+dt), or the learned closure standing in for
+     its probability (oracle.mlp) when the configuration carries network weights.
 The state carries phi so that each step solves Poisson once; phi of the initial state is
 solved from the initial particles and gas.
 """
@@ -19,7 +20,7 @@ from dataclasses import dataclass, replace
 import numpy as np
 import torch
 
-from . import cosmology, gravity, hydro, ics, philox, subgrid
+from . import cosmology, gravity, hydro, ics, mlp, philox, subgrid
 
 
 @dataclass
@@ -41,6 +42,8 @@ class Config:
     subgrid: int = subgrid.MODE_OFF
     tau: float = 0.1
     sf_seed: int = 102
+    closure_theta: object = None  # flat network parameters (oracle.mlp), None: plain source
+    closure_bf16: bool = True     # round the network's product operands to bfloat16
 
     # derived quantities (filled by finish())
     amp: float = 0.0
@@ -137,6 +140,15 @@ def step(state, cfg, prm, dt):
     star = state.star
     if cfg.subgrid != subgrid.MODE_OFF:
         u = torch.from_numpy(philox.starform_uniform(cfg.sf_seed, state.step, n))
+        if cfg.closure_theta is not None:
+            theta = torch.as_tensor(cfg.closure_theta, dtype=torch.float64)
+            q, star = mlp.apply_closure(
+                q, star, a1, dt, u, theta, rho_mean_gas=cfg.f_b, gamma=cfg.gamma,
+                e_floor=cfg.e_floor, t_per_e=cfg.t_per_e,
+                e0_code=prm.e0 * 1e6 / cfg.vel_unit ** 2, eps_sf=prm.eps_sf,
+                delta_c=prm.delta_c, tau=cfg.tau, mode=cfg.subgrid, bf16=cfg.closure_bf16)
+            return State(q=q, x=x, p=p, star=star, phi=phi, t=state.t + dt, a=a1,
+                         step=state.step + 1)
         q, star = subgrid.apply_source(
             q, star, a1, dt, u, rho_mean_gas=cfg.f_b, omega_b=cfg.omega_b, gamma=cfg.gamma,
             e_floor=cfg.e_floor, t_per_e=cfg.t_per_e, e0_code=prm.e0 * 1e6 / cfg.vel_unit ** 2,
