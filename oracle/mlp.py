@@ -58,23 +58,77 @@ def silu(z):
     return z * torch.sigmoid(z)
 
 
+def _to_bf16(t):
+    return t.detach().to(torch.bfloat16).to(torch.float64)
+
+
+class _Bf16Round(torch.autograd.Function):
+    """Rounding to bfloat16 whose backward passes the gradient unchanged (a cast's own
+    backward would round the gradient too)."""
+
+    @staticmethod
+    def forward(ctx, t):
+        return _to_bf16(t)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
 def bf16_round(t):
     """Round to the nearest bfloat16 value (ties to even), returned in float64.  Autograd
     passes gradients through the rounding unchanged."""
-    return t.to(torch.bfloat16).to(torch.float64)
+    return _Bf16Round.apply(t) if t.requires_grad else _to_bf16(t)
+
+
+class _RoundGrad(torch.autograd.Function):
+    """Identity whose backward rounds the incoming gradient to bfloat16."""
+
+    @staticmethod
+    def forward(ctx, t):
+        return t.view_as(t)
+
+    @staticmethod
+    def backward(ctx, g):
+        return _to_bf16(g)
+
+
+class _SiluBf16Grad(torch.autograd.Function):
+    """SiLU whose backward multiplies by the derivative rounded to bfloat16."""
+
+    @staticmethod
+    def forward(ctx, z):
+        ctx.save_for_backward(z)
+        return silu(z)
+
+    @staticmethod
+    def backward(ctx, g):
+        z, = ctx.saved_tensors
+        s = torch.sigmoid(z)
+        return g * _to_bf16(s * (1.0 + z * (1.0 - s)))
 
 
 def forward(theta, x, bf16=False):
-    """Network outputs [2, ...] for inputs x [5, ...].  With bf16, every operand of the four
-    matrix products (weights, inputs, hidden activations) is rounded to bfloat16, as on a
-    matrix core; sums, biases and activations stay in float64."""
+    """Network outputs [2, ...] for inputs x [5, ...].
+
+    With bf16, the arithmetic is that of a matrix-core evaluation: every operand of the four
+    matrix products is rounded to bfloat16 (weights, inputs, hidden activations), and so are
+    the operands of the products of the backward pass (the gradient with respect to each
+    layer's pre-activation, the SiLU derivative it is formed with, and the gradient of the
+    output layer's sum); sums, biases and activations stay in float64."""
     W1, b1, W2, b2, W3, b3, W4, b4 = unpack(theta)
-    r = bf16_round if bf16 else (lambda t: t)
     shape = x.shape[1:]
+    if not bf16:
+        h = x.reshape(N_IN, -1)
+        for W, b in ((W1, b1), (W2, b2), (W3, b3)):
+            h = silu(W @ h + b[:, None])
+        o = OUT_SCALE * (W4 @ h + b4[:, None])
+        return o.reshape((N_OUT,) + shape)
+    r = bf16_round
     h = r(x.reshape(N_IN, -1))
     for W, b in ((W1, b1), (W2, b2), (W3, b3)):
-        h = r(silu(r(W) @ h + b[:, None]))
-    o = OUT_SCALE * (r(W4) @ h + b4[:, None])
+        h = r(_SiluBf16Grad.apply(_RoundGrad.apply(r(W) @ h + b[:, None])))
+    o = OUT_SCALE * _RoundGrad.apply(r(W4) @ h + b4[:, None])
     return o.reshape((N_OUT,) + shape)
 
 

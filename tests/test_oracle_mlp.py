@@ -77,6 +77,15 @@ def test_bf16_rounding_known_values():
     assert torch.equal(mlp.bf16_round(x), want)
 
 
+def test_bf16_rounding_passes_gradients_unchanged():
+    t = torch.tensor([1.0 + 2.0 ** -9, -0.3, 7.7], requires_grad=True)
+    g = torch.tensor([1.0 + 2.0 ** -10, 0.123456789, -5.0])
+    out = mlp.bf16_round(t)
+    assert torch.equal(out.detach(), mlp.bf16_round(t.detach()))
+    gt, = torch.autograd.grad(out, t, grad_outputs=g)
+    assert torch.equal(gt, g)
+
+
 def test_bf16_forward_differs_from_fp64_by_rounding_only():
     th = _theta()
     x = _inputs(256)
@@ -86,8 +95,7 @@ def test_bf16_forward_differs_from_fp64_by_rounding_only():
     assert 1e-5 < rel < 2e-2
 
 
-@pytest.mark.parametrize("bf16", [False, True])
-def test_objective_gradient_by_finite_differences(bf16):
+def test_objective_gradient_by_finite_differences():
     th = _theta().requires_grad_(True)
     x = _inputs(16).requires_grad_(True)
     t = torch.from_numpy(np.random.default_rng(9).normal(size=(2, 16)))
@@ -103,6 +111,33 @@ def test_objective_gradient_by_finite_differences(bf16):
             fd_x = (mlp.loss(th, x + h * w, t) - mlp.loss(th, x - h * w, t)) / (2 * h)
         assert float(gth @ v) == pytest.approx(float(fd_t), rel=1e-7)
         assert float((gx * w).sum()) == pytest.approx(float(fd_x), rel=1e-7)
+
+
+def test_backward_rounding_operators():
+    g = torch.tensor([1.0 + 2.0 ** -8, -3.0 - 2.0 ** -7, 0.1])
+    z = torch.tensor([0.3, -2.0, 5.0], requires_grad=True)
+    out = mlp._RoundGrad.apply(z)
+    assert torch.equal(out, z)
+    gz, = torch.autograd.grad(out, z, grad_outputs=g)
+    assert torch.equal(gz, mlp.bf16_round(g))
+    out = mlp._SiluBf16Grad.apply(z)
+    assert torch.allclose(out, z * torch.sigmoid(z), rtol=1e-15)
+    gz, = torch.autograd.grad(out, z, grad_outputs=torch.ones(3))
+    with torch.no_grad():
+        h = 1e-6
+        fd = (mlp.silu(z + h) - mlp.silu(z - h)) / (2 * h)
+    assert torch.allclose(gz, fd, rtol=2.0 ** -8)           # within one bfloat16 rounding
+    assert torch.equal(gz, mlp.bf16_round(gz))              # and exactly a bfloat16 value
+
+
+def test_bf16_gradient_differs_from_fp64_by_rounding_only():
+    th = _theta().requires_grad_(True)
+    x = _inputs(64)
+    t = torch.from_numpy(np.random.default_rng(9).normal(size=(2, 64)))
+    g64, = torch.autograd.grad(mlp.loss(th, x, t), th)
+    g16, = torch.autograd.grad(mlp.loss(th, x, t, bf16=True), th)
+    rel = float((g16 - g64).norm() / g64.norm())
+    assert 1e-5 < rel < 3e-2
 
 
 def test_output_bias_gradient_closed_form():
