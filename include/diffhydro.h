@@ -50,6 +50,12 @@ enum {
 
 enum { DH_SUBGRID_OFF = 0, DH_SUBGRID_HARD = 1, DH_SUBGRID_RELAXED = 2 };
 
+/* Star-formation probability of the source term: the plain formula (Sec. 2.4.1) or the
+ * learned closure (a small network standing in for it, in the spirit of the learned
+ * sub-grid models of Sec. 4; see dh_mlp_* below).  The draw and the supernova energy are
+ * the same in both. */
+enum { DH_CLOSURE_PLAIN = 0, DH_CLOSURE_MLP = 1 };
+
 /* Run configuration.  dh_config_default() fills the values of the paper's workloads. */
 typedef struct dh_config {
     int32_t n;           /* cells per side; power of two, 16..256                        */
@@ -66,6 +72,7 @@ typedef struct dh_config {
     double tau;          /* Gumbel-softmax temperature (Sec. 2.4.2; 0.1)                   */
     uint64_t sf_seed;    /* key of the per-cell, per-step star-formation uniforms          */
     int32_t ckpt_every;  /* checkpoint interval in steps for dh_forward/dh_backward (>=1)  */
+    int32_t closure;     /* DH_CLOSURE_*; MLP needs subgrid != OFF and dh_set_closure()    */
 } dh_config;
 
 /* Model parameters (double).  A, beta: flux observable F = exp(-A Delta^beta) of the loss;
@@ -165,6 +172,82 @@ int dh_stage_readout(dh_sim* sim, const float* d_phi, const float* d_pos, float*
 
 const char* dh_last_error(const dh_sim* sim);
 const char* dh_strerror(int code);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned star-formation closure.
+ *
+ * Network: inputs x = ((ln Delta - 4.6)/5, (ln T - 10.4)/5, (ln a + 3)/1.5, eps_sf/0.02 - 1,
+ * Delta_c/100 - 1) with Delta the gas overdensity and T [K] the temperature; three hidden
+ * layers of 64 with SiLU; outputs o = 10 (W4 h3 + b4).  In the simulation the outputs give
+ * the star-formation probability of a step, pi0 = (1 - exp(-exp(o0) dt)) exp(min(o1, 0)):
+ * o0 stands for ln(eps_sf / t_ff) and o1 for the log of the two threshold gates of the
+ * relaxed model (Sec. 2.4), clipped at -30.  Inference and training run on the matrix
+ * cores in bfloat16 with float32 accumulation.
+ *
+ * Parameters: DH_MLP_NPARAMS floats, W1[64][5], b1[64], W2[64][64], b2[64], W3[64][64],
+ * b3[64], W4[2][64], b4[2] (W[out][in]), in host memory for set/get.
+ * Arrays of samples are device float32 structure-of-arrays: x[5][count], outputs and
+ * targets [2][count].
+ * ------------------------------------------------------------------------------------- */
+#define DH_MLP_NPARAMS 8834
+
+/* Network weights for DH_CLOSURE_MLP runs of this simulation (host h_theta, copied). */
+int dh_set_closure(dh_sim* sim, const float* h_theta);
+
+typedef struct dh_mlp dh_mlp;
+
+/* Training options: Adam (beta1, beta2, eps) with a cosine learning-rate decay from lr to
+ * lr_final over `steps` steps of `batch` samples; batch k takes samples
+ * [(k batch) mod count, ...) cyclically. */
+typedef struct dh_mlp_train_opts {
+    int64_t batch;
+    int32_t steps;
+    double lr, lr_final, beta1, beta2, eps;
+} dh_mlp_train_opts;
+
+/* Ranges of the training states: ln Delta, ln T [K], ln a uniform over [lo, hi], except
+ * that with probability 1/2 each, ln Delta (ln T) is drawn within +-1.5 of ln Delta_c
+ * (ln T_c); eps_sf and Delta_c uniform over [lo, hi].  Defaults (dh_mlp_sample_defaults):
+ * Delta in [1e-2, 3e4], T in [1, 3e8] K, a in [0.008, 0.32], eps_sf and Delta_c within
+ * +-50% of 0.02 and 100. */
+typedef struct dh_mlp_sample_opts {
+    double lnd_lo, lnd_hi, lnt_lo, lnt_hi, lna_lo, lna_hi;
+    double eps_lo, eps_hi, dc_lo, dc_hi;
+} dh_mlp_sample_opts;
+
+void dh_mlp_train_defaults(dh_mlp_train_opts* opts);
+void dh_mlp_sample_defaults(dh_mlp_sample_opts* opts);
+
+/* A network with its training state on the current HIP device. */
+int dh_mlp_create(dh_mlp** out);
+int dh_mlp_destroy(dh_mlp* net);
+int dh_mlp_set_stream(dh_mlp* net, void* hip_stream);
+/* Uniform(+-1/sqrt(fan_in)) weights from the library's Philox generator. */
+int dh_mlp_init_weights(dh_mlp* net, uint64_t seed);
+int dh_mlp_set_weights(dh_mlp* net, const float* h_theta);
+int dh_mlp_get_weights(dh_mlp* net, float* h_theta);
+/* Training set of the closure: states drawn over the ranges of opts, samples first ..
+ * first + count - 1 of the stream of `seed` (so that sets can be made in pieces); inputs
+ * d_x[5][count] and targets d_y[2][count] = (ln(eps_sf/t_ff), clipped log gate) of the plain
+ * relaxed source term, computed in FP64; omega_b and p (t_c, w_rho, w_t) as in dh_config and
+ * dh_params.  opts NULL: defaults. */
+int dh_mlp_sample(dh_mlp* net, const dh_mlp_sample_opts* opts, double omega_b,
+                  const dh_params* p, uint64_t seed, int64_t first, int64_t count, float* d_x,
+                  float* d_y);
+/* d_out[2][count] = network(d_x). */
+int dh_mlp_eval(dh_mlp* net, const float* d_x, int64_t count, float* d_out);
+/* d_gx[5][count] = (d out / d x)^T d_gout[2][count] (BF16 rounding passed as identity). */
+int dh_mlp_vjp(dh_mlp* net, const float* d_x, const float* d_gout, int64_t count, float* d_gx);
+/* Objective L = mean over samples of sum_k (o_k - y_k)^2 and its gradient in the weights
+ * (host h_grad[DH_MLP_NPARAMS], FP64), summed in a fixed order. */
+int dh_mlp_grad(dh_mlp* net, const float* d_x, const float* d_y, int64_t count, double* h_grad,
+                double* loss_out);
+/* Adam on the objective over the set (d_x, d_y); h_loss (host, opts.steps values, or NULL)
+ * receives the batch objective before each step.  The optimiser state restarts with each
+ * call. */
+int dh_mlp_train(dh_mlp* net, const float* d_x, const float* d_y, int64_t count,
+                 const dh_mlp_train_opts* opts, double* h_loss);
+const char* dh_mlp_last_error(const dh_mlp* net);
 
 #ifdef __cplusplus
 }

@@ -11,5 +11,6 @@ _load()
 
 from .sim import Sim, default_config, default_params  # noqa: E402
 from .autograd import DiffHydroFn  # noqa: E402
+from .mlp import Mlp  # noqa: E402
 
 __all__ = ["Sim", "default_config", "default_params", "DiffHydroFn"]

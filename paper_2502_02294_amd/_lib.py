@@ -15,6 +15,8 @@ ERRORS = {-1: "DH_E_INVAL", -2: "DH_E_OOM", -3: "DH_E_HIP", -4: "DH_E_NONFINITE"
           -5: "DH_E_SCHEDULE", -6: "DH_E_STATE"}
 
 SUBGRID_OFF, SUBGRID_HARD, SUBGRID_RELAXED = 0, 1, 2
+CLOSURE_PLAIN, CLOSURE_MLP = 0, 1
+MLP_NPARAMS = 8834
 FIELD_Q, FIELD_RHO, FIELD_POS, FIELD_MOM, FIELD_STAR, FIELD_PHI, FIELD_TEMP, FIELD_FLUX = range(8)
 
 
@@ -25,12 +27,23 @@ class Config(ctypes.Structure):
                 ("a_init", ctypes.c_double), ("t_init", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("dlna_max", ctypes.c_double), ("t_floor", ctypes.c_double),
                 ("subgrid", ctypes.c_int32), ("tau", ctypes.c_double), ("sf_seed", ctypes.c_uint64),
-                ("ckpt_every", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("closure", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in ("A", "beta", "eps_sf", "delta_c", "t_c", "e0",
                                                 "w_rho", "w_t")]
+
+
+class MlpTrainOpts(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int64), ("steps", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("lr_final", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
+class MlpSampleOpts(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("lnd_lo", "lnd_hi", "lnt_lo", "lnt_hi", "lna_lo",
+                                                "lna_hi", "eps_lo", "eps_hi", "dc_lo", "dc_hi")]
 
 
 class DiffHydroError(RuntimeError):
@@ -74,6 +87,23 @@ _SIGNATURES = {
     "dh_stage_readout": (I, [P, P, P, P]),
     "dh_last_error": (ctypes.c_char_p, [P]),
     "dh_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "dh_set_closure": (I, [P, P]),
+    "dh_mlp_train_defaults": (None, [ctypes.POINTER(MlpTrainOpts)]),
+    "dh_mlp_sample_defaults": (None, [ctypes.POINTER(MlpSampleOpts)]),
+    "dh_mlp_create": (I, [ctypes.POINTER(P)]),
+    "dh_mlp_destroy": (I, [P]),
+    "dh_mlp_set_stream": (I, [P, P]),
+    "dh_mlp_init_weights": (I, [P, ctypes.c_uint64]),
+    "dh_mlp_set_weights": (I, [P, P]),
+    "dh_mlp_get_weights": (I, [P, P]),
+    "dh_mlp_sample": (I, [P, ctypes.POINTER(MlpSampleOpts), D, ctypes.POINTER(Params),
+                          ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, P, P]),
+    "dh_mlp_eval": (I, [P, P, ctypes.c_int64, P]),
+    "dh_mlp_vjp": (I, [P, P, P, ctypes.c_int64, P]),
+    "dh_mlp_grad": (I, [P, P, P, ctypes.c_int64, ctypes.POINTER(D), ctypes.POINTER(D)]),
+    "dh_mlp_train": (I, [P, P, P, ctypes.c_int64, ctypes.POINTER(MlpTrainOpts),
+                         ctypes.POINTER(D)]),
+    "dh_mlp_last_error": (ctypes.c_char_p, [P]),
 }
 
 EXPORTED = tuple(_SIGNATURES)
@@ -95,7 +125,10 @@ def lib():
     return _lib
 
 
-def check(rc, handle=None):
+def check(rc, handle=None, last_error=None):
     if rc != DH_OK:
-        msg = lib().dh_last_error(handle).decode() if handle else lib().dh_strerror(rc).decode()
+        if handle:
+            msg = (last_error or lib().dh_last_error)(handle).decode()
+        else:
+            msg = lib().dh_strerror(rc).decode()
         raise DiffHydroError(rc, msg)

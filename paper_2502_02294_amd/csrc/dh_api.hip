@@ -20,6 +20,7 @@
 #include "../../include/diffhydro.h"
 #include "dh_cosmo.h"
 #include "dh_kernels.h"
+#include "dh_mlp.h"
 
 namespace {
 
@@ -89,6 +90,11 @@ struct dh_sim {
         *lcic = nullptr;
   double* param_steps = nullptr;   // [2 * cap] per-step dL/d(eps_sf, delta_c)
   int param_cap = 0;
+
+  // learned closure: flat weights and their packed matrix-core form
+  float* mlp_theta = nullptr;
+  uint4* mlp_packed = nullptr;
+  bool mlp_ready = false;
 
   // schedule
   std::vector<double> recorded;
@@ -217,6 +223,7 @@ dh::SourceArgs source_args(const dh_sim* s, const Plan& pl) {
   a.seed_lo = static_cast<uint32_t>(s->cfg.sf_seed & 0xFFFFFFFFull);
   a.seed_hi = static_cast<uint32_t>(s->cfg.sf_seed >> 32);
   a.step = static_cast<uint32_t>(pl.step);
+  a.mlp = s->cfg.closure == DH_CLOSURE_MLP ? s->mlp_packed : nullptr;
   return a;
 }
 
@@ -339,6 +346,8 @@ int next_dt(dh_sim* s, double t_end, double* dt_out) {
 
 int step_once(dh_sim* s, double t_end, TapeStep* tp, double* dt_used) {
   if (!s->initialised) return fail(s, DH_E_STATE, "no initial state");
+  if (s->cfg.closure == DH_CLOSURE_MLP && !s->mlp_ready)
+    return fail(s, DH_E_STATE, "closure network weights not set (dh_set_closure)");
   if (!s->phi_valid) refresh_potential(s);
   double dt;
   int rc = next_dt(s, t_end, &dt);
@@ -532,7 +541,9 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
   if (!(cfg->omega_m > 0 && cfg->omega_m < 1 && cfg->omega_b > 0 && cfg->omega_b < cfg->omega_m &&
         cfg->box > 0 && cfg->a_init > 0 && cfg->a_init < 1 && cfg->cfl > 0 && cfg->dlna_max > 0 &&
         cfg->gamma > 1 && cfg->tau > 0 && cfg->ckpt_every >= 1 && cfg->subgrid >= 0 &&
-        cfg->subgrid <= 2 && cfg->t_floor > 0 && cfg->t_init > 0 && cfg->sigma8 > 0))
+        cfg->subgrid <= 2 && cfg->t_floor > 0 && cfg->t_init > 0 && cfg->sigma8 > 0 &&
+        (cfg->closure == DH_CLOSURE_PLAIN ||
+         (cfg->closure == DH_CLOSURE_MLP && cfg->subgrid != DH_SUBGRID_OFF))))
     return DH_E_INVAL;
   auto s = std::make_unique<dh_sim>();
   int rc = guarded(s.get(), [&]() -> int {
@@ -580,6 +591,10 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
     s->red_blocks = dh::sum_blocks(nc);
     s->red = s->alloc<double>(8LL * s->red_blocks + 8);
     s->red_out = s->alloc<double>(16);
+    if (cfg->closure == DH_CLOSURE_MLP) {
+      s->mlp_theta = s->alloc<float>(dh::mlp::kParams);
+      s->mlp_packed = s->alloc<uint4>(static_cast<long long>(dh::mlp::kPackedBytes / sizeof(uint4)));
+    }
     void* hp = nullptr;
     DH_HIP(hipHostMalloc(&hp, 16 * sizeof(double), hipHostMallocDefault));
     s->host_out = static_cast<double*>(hp);
@@ -617,6 +632,20 @@ int dh_set_params(dh_sim* s, const dh_params* p) {
     return fail(s, DH_E_INVAL, "non-physical parameters");
   s->prm = *p;
   return DH_OK;
+}
+
+int dh_set_closure(dh_sim* s, const float* h_theta) {
+  if (!s || !h_theta) return DH_E_INVAL;
+  if (s->cfg.closure != DH_CLOSURE_MLP)
+    return fail(s, DH_E_STATE, "simulation was created without the learned closure");
+  return guarded(s, [&]() -> int {
+    DH_HIP(hipMemcpyAsync(s->mlp_theta, h_theta, dh::mlp::kParams * sizeof(float),
+                          hipMemcpyHostToDevice, s->st));
+    dh::launch_mlp_pack(s->st, s->mlp_theta, s->mlp_packed);
+    sync(s);
+    s->mlp_ready = true;
+    return DH_OK;
+  });
 }
 
 int dh_init_from_seed(dh_sim* s, uint64_t seed) {

@@ -182,6 +182,7 @@ __device__ __forceinline__ void van_leer_d(float x, float y, float& dx, float& d
 // ---------------------------------------------------------------------------------------
 constexpr uint32_t kTagWhite = 0x574E0000u;
 constexpr uint32_t kTagStarform = 0x53460000u;
+constexpr uint32_t kTagMlpSample = 0x4D4C0000u;   // training states of the learned closure
 
 __host__ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
   for (int r = 0; r < 10; ++r) {

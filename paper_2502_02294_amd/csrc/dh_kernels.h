@@ -85,8 +85,8 @@ struct SourceArgs {   // FP64: the source term is evaluated in double precision
   double eps_sf, delta_c, t_c, w_rho, w_t, tau;
   int mode;
   uint32_t seed_lo, seed_hi, step;
+  const uint4* mlp;   // packed closure network (dh_mlp.h): pi0 from the network; null: plain
 };
-void launch_source(hipStream_t st, float* q, float* star, const SourceArgs& a, int n);
 // closing pass of a step, from q_in (may equal q) into q: gas half kick with g4, optional copy of the kicked state to
 // q_kicked (tape), source term (if a.mode != 0), FP64 block maxima of the CFL speed of the
 // result at scale factor a.a into block_max[cfl_blocks(n)]
@@ -128,5 +128,40 @@ void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const
                        float* lam_psi, int n);
 void launch_fill(hipStream_t st, float* p, float v, long long count);
 void launch_check_finite(hipStream_t st, const float* q, long long nc, int* flag);
+
+// ---- learned closure network (k_mlp.hip; layout in dh_mlp.h)
+struct MlpSampleArgs {   // ranges of the training states (natural logs where named ln)
+  long long first;       // index of the first sample (Philox counter)
+  uint32_t seed_lo, seed_hi;
+  double lnd_lo, lnd_hi, lnt_lo, lnt_hi, lna_lo, lna_hi, eps_lo, eps_hi, dc_lo, dc_hi;
+  double t_c, omega_b, w_rho, w_t;
+};
+struct AdamArgs {
+  float lr, beta1, beta2, eps;
+  float corr1, corr2;    // 1 / (1 - beta^t)
+  int step;
+};
+// packed[kFrAll * 64 fragments + biases] from the flat parameter vector
+void launch_mlp_pack(hipStream_t st, const float* theta, uint4* packed);
+// x[5][count] network inputs and y[2][count] targets of the plain source term
+void launch_mlp_sample(hipStream_t st, const MlpSampleArgs& p, float* x, float* y, long long count);
+// out[2][count] = network(x[5][count])
+void launch_mlp_eval(hipStream_t st, const uint4* packed, const float* x, float* out,
+                     long long count);
+// gx[5][count] = (d out / d x)^T gout[2][count]
+void launch_mlp_vjp(hipStream_t st, const uint4* packed, const float* x, const float* gout,
+                    float* gx, long long count);
+// per-wave partial gradients partial[mlp_train_parts(batch)][kParams] and loss sums of the
+// objective mean_s sum_k (o_k - y_k)^2 over samples (start + i) mod n_data, i < batch
+int mlp_train_parts(long long batch);
+void launch_mlp_train_grad(hipStream_t st, const uint4* packed, const float* x, const float* y,
+                           long long n_data, long long start, long long batch, float* partial,
+                           double* loss_part);
+void launch_mlp_reduce_grad(hipStream_t st, const float* partial, int nparts,
+                            const double* loss_part, double loss_scale, double* grad,
+                            double* loss_out);
+void launch_mlp_adam(hipStream_t st, const float* partial, int nparts, const double* loss_part,
+                     double loss_scale, float* theta, float* m, float* v, const AdamArgs& a,
+                     double* loss_hist);
 
 }  // namespace dh

@@ -6,6 +6,7 @@
 #include <cmath>
 
 #include "dh_kernels.h"
+#include "dh_mlp.h"
 
 namespace dh {
 
@@ -206,19 +207,6 @@ __device__ __forceinline__ double cell_speed(const float q5[5], double a, double
   return sp;
 }
 
-__global__ void __launch_bounds__(256) source_kernel(float* __restrict__ q, float* __restrict__ star,
-                                                     SourceArgs a, long long nc) {
-  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  float q5[5];
-  load_q(q, c, nc, q5);
-  const double u = starform_uniform(c, a);
-  if (draw_negligible(q5, u, a)) return;
-  const SrcCell s = source_eval(q5, u, a);
-  q[4 * nc + c] = static_cast<float>(q5[4] + a.a * a.a * s.rho * s.z * a.e0_code);
-  star[c] = static_cast<float>(star[c] + s.z);
-}
-
 // Closing pass of a step over kRedPer cells per thread: gas half kick, optional tape copy,
 // source term, CFL block maximum of the result.
 __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
@@ -302,6 +290,257 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_kernel(const float* __
       acc[1] += coef * ((1.0 - s.s1) * (-s.delta / (a.w_rho * a.delta_c * a.delta_c)));
     }
     lam[c] = static_cast<float>(lr);
+  }
+  block_reduce_store<2, false>(acc, partial);
+}
+
+// ------------------------------------------------------------------------- learned closure
+// The closure replaces the star-formation probability of the source term by the network of
+// dh_mlp.h: o = net(x(Q)), pi0 = (1 - exp(-exp(o0) dt)) exp(min(o1, 0)); the draw and the
+// supernova energy are those of the plain term.  Each wave evaluates the network on its 64
+// consecutive cells; the per-cell inputs and outputs pass through LDS.
+constexpr int kStage = 8;   // floats per cell in the LDS stage
+
+// network inputs of one cell (FP64 from the FP32 state, then FP32)
+__device__ __forceinline__ void closure_inputs(const float q5[5], const SourceArgs& a,
+                                               float x[5], double& e_raw, bool& floored) {
+  const double rho = q5[0];
+  const double ir = 1.0 / rho, ia = 1.0 / a.a;
+  const double u0 = q5[1] * ia * ir, u1 = q5[2] * ia * ir, u2 = q5[3] * ia * ir;
+  e_raw = q5[4] * ia * ia * ir - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+  floored = e_raw < a.efloor;
+  const double e = floored ? a.efloor : e_raw;
+  x[0] = static_cast<float>((log(rho * a.inv_rho_mean) - 4.6) / 5.0);
+  x[1] = static_cast<float>((log(e * a.t_per_e) - 10.4) / 5.0);
+  x[2] = static_cast<float>((log(a.a) + 3.0) / 1.5);
+  x[3] = static_cast<float>(a.eps_sf / 0.02 - 1.0);
+  x[4] = static_cast<float>(a.delta_c / 100.0 - 1.0);
+}
+
+// input operands of 16 NCT cells from the stage (slots 0..4 of each cell)
+template <int NCT>
+__device__ __forceinline__ mlp::Act<NCT> stage_operands(const float (*stage)[kStage], int lane) {
+  const int g = lane >> 4, c = lane & 15;
+  mlp::Act<NCT> in;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    mlp::f4 lo = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (g == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) lo[r] = stage[16 * ct + c][r];
+    } else if (g == 1) {
+      lo[0] = stage[16 * ct + c][4];
+    }
+    mlp::set_half(in.v[0][ct], 0, lo);
+    mlp::set_half(in.v[0][ct], 1, mlp::f4{0.0f, 0.0f, 0.0f, 0.0f});
+  }
+  return in;
+}
+
+struct ClosureDraw {
+  double x, psf, pi0, z, lgate;
+};
+
+// pi0 from the outputs and the draw with uniform u (FP64, as the plain term)
+__device__ __forceinline__ ClosureDraw closure_draw(float o0, float o1, double u,
+                                                    const SourceArgs& a) {
+  ClosureDraw d;
+  d.x = exp(static_cast<double>(o0)) * a.dt;
+  d.psf = -expm1(-d.x);
+  d.lgate = fmin(static_cast<double>(o1), 0.0);
+  d.pi0 = d.psf * exp(d.lgate);
+  if (a.mode == 1) {
+    d.z = u > 1.0 - d.pi0 ? 1.0 : 0.0;
+  } else {
+    const double logit = log(d.psf) + d.lgate - log1p(-d.pi0);
+    d.z = sigmoid_((logit + log(u) - log1p(-u)) / a.tau);
+  }
+  return d;
+}
+
+// True when the relaxed draw is certainly below e^-109 (FP32 screen, as draw_negligible).
+__device__ __forceinline__ bool closure_negligible(float o0, float o1, double u,
+                                                   const SourceArgs& a) {
+  if (a.mode != 2) return false;
+  const float psf = -expm1f(-expf(o0) * static_cast<float>(a.dt));
+  if (!(psf > 1e-30f)) return false;
+  const float logpi = logf(psf) + fminf(o1, 0.0f);
+  const float uf = static_cast<float>(u);
+  const float arg = (logpi - log1pf(-expf(logpi)) + logf(uf) - log1pf(-uf)) /
+                    static_cast<float>(a.tau);
+  return arg < -110.0f;
+}
+
+// Closing pass with the learned closure (same cells per block as close_step_kernel).
+__global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
+    const float* q_in, float* q, const float4* __restrict__ g4, float h, float* __restrict__ star,
+    SourceArgs a, float* __restrict__ q_kicked, double gg1, double* partial, long long nc) {
+  __shared__ uint4 fr[mlp::kFrFwd * 64];
+  __shared__ __attribute__((aligned(16))) float bias[mlp::kBias];
+  __shared__ float stage[kRedThreads / 64][64][kStage];
+  mlp::load_packed(a.mlp, mlp::kFrFwd, fr, bias);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, cl = lane & 15;
+  double vmax[1] = {0.0};
+  const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
+  for (int r = 0; r < kRedPer; ++r) {
+    const long long c = base + r * kRedThreads + threadIdx.x;
+    const bool valid = c < nc;
+    float q5[5] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+    if (valid) {
+      load_q(q_in, c, nc, q5);
+      float m[3] = {q5[1], q5[2], q5[3]};
+      kick_cell(q5[0], g4[c], h, m, q5[4]);
+      q5[1] = m[0];
+      q5[2] = m[1];
+      q5[3] = m[2];
+      if (q_kicked) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) q_kicked[k * nc + c] = q5[k];
+      }
+    }
+    float xin[5];
+    double e_raw;
+    bool floored;
+    closure_inputs(q5, a, xin, e_raw, floored);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) stage[wave][lane][k] = valid ? xin[k] : 0.0f;
+    __syncthreads();
+    mlp::f4 o[4];
+    mlp::forward<4>(fr, bias, stage_operands<4>(stage[wave], lane), o, nullptr, nullptr, lane);
+    if (g == 0) {
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        stage[wave][16 * ct + cl][5] = o[ct][0];
+        stage[wave][16 * ct + cl][6] = o[ct][1];
+      }
+    }
+    __syncthreads();
+    if (valid) {
+      const float o0 = stage[wave][lane][5], o1 = stage[wave][lane][6];
+      const double u = starform_uniform(c, a);
+      if (!closure_negligible(o0, o1, u, a)) {
+        const ClosureDraw d = closure_draw(o0, o1, u, a);
+        if (d.z != 0.0) {
+          q5[4] = static_cast<float>(q5[4] + a.a * a.a * static_cast<double>(q5[0]) * d.z * a.e0_code);
+          star[c] = static_cast<float>(star[c] + d.z);
+        }
+      }
+#pragma unroll
+      for (int k = (q == q_in ? 1 : 0); k < 5; ++k) q[k * nc + c] = q5[k];
+      vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
+    }
+    __syncthreads();
+  }
+  block_reduce_store<1, true>(vmax, partial);
+}
+
+// Adjoint of the closure's source update at the kicked state q: lam (in: after, out:
+// before); partial[0|1][block] = dL/d(eps_sf | delta_c), which enter through the inputs.
+__global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(const float* __restrict__ q,
+                                                                     float* __restrict__ lam,
+                                                                     SourceArgs a, double* partial,
+                                                                     long long nc) {
+  __shared__ uint4 fr[mlp::kFrAll * 64];
+  __shared__ __attribute__((aligned(16))) float bias[mlp::kBias];
+  __shared__ float stage[kRedThreads / 64][64][kStage];
+  mlp::load_packed(a.mlp, mlp::kFrAll, fr, bias);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, cl = lane & 15;
+  const double K = a.a * a.a * a.e0_code;
+  double acc[2] = {0.0, 0.0};
+  const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
+  for (int r = 0; r < kRedPer; ++r) {
+    const long long c = base + r * kRedThreads + threadIdx.x;
+    const bool valid = c < nc;
+    float q5[5] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+    if (valid) load_q(q, c, nc, q5);
+    float xin[5];
+    double e_raw;
+    bool floored;
+    closure_inputs(q5, a, xin, e_raw, floored);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) stage[wave][lane][k] = valid ? xin[k] : 0.0f;
+    __syncthreads();
+    mlp::f4 o[4];
+    mlp::forward<4>(fr, bias, stage_operands<4>(stage[wave], lane), o, nullptr, nullptr, lane);
+    if (g == 0) {
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        stage[wave][16 * ct + cl][5] = o[ct][0];
+        stage[wave][16 * ct + cl][6] = o[ct][1];
+      }
+    }
+    __syncthreads();
+    // dL/do of this cell
+    double le = 0.0, z = 0.0, go0 = 0.0, go1 = 0.0;
+    if (valid) {
+      const float o0 = stage[wave][lane][5], o1 = stage[wave][lane][6];
+      const double u = starform_uniform(c, a);
+      le = lam[4 * nc + c];
+      if (!closure_negligible(o0, o1, u, a)) {
+        const ClosureDraw d = closure_draw(o0, o1, u, a);
+        z = d.z;
+        if (a.mode != 1 && le != 0.0) {
+          const double dz = d.z * (1.0 - d.z) / a.tau / (1.0 - d.pi0);   // dz / dln(pi0)
+          const double coef = le * K * q5[0] * dz;
+          go0 = coef * d.x / expm1(d.x);                // dln p_sf / do0
+          go1 = o1 < 0.0f ? coef : 0.0;                  // dln gate / do1
+        }
+      }
+    }
+    __syncthreads();
+    stage[wave][lane][5] = static_cast<float>(go0);
+    stage[wave][lane][6] = static_cast<float>(go1);
+    __syncthreads();
+    // backward in two halves of 32 cells (the forward is recomputed with its derivatives)
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const float (*sh)[kStage] = stage[wave] + 32 * half;
+      mlp::f4 oh[2], go[2], dx[2];
+      mlp::Act<2> sd[3];
+      mlp::forward<2>(fr, bias, stage_operands<2>(sh, lane), oh, sd, nullptr, lane);
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        go[ct] = mlp::f4{0.0f, 0.0f, 0.0f, 0.0f};
+        if (g == 0) {
+          go[ct][0] = sh[16 * ct + cl][5];
+          go[ct][1] = sh[16 * ct + cl][6];
+        }
+      }
+      mlp::backward<2>(fr, sd, go, dx, nullptr, lane);
+      __syncthreads();
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        float* cellst = stage[wave][32 * half + 16 * ct + cl];
+        if (g == 0) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) cellst[k] = dx[ct][k];
+        } else if (g == 1) {
+          cellst[4] = dx[ct][0];
+        }
+      }
+      __syncthreads();
+    }
+    if (valid) {
+      // Et' = Et + K rho z; inputs x0 = (ln Delta - 4.6)/5, x1 = (ln T - 10.4)/5 with T ~ e
+      const double rho = q5[0];
+      const double gx0 = stage[wave][lane][0], gx1 = stage[wave][lane][1];
+      const double ir = 1.0 / rho, ia = 1.0 / a.a;
+      double u[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) u[d] = q5[1 + d] * ia * ir;
+      const double ke = 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      const double ge = floored ? 0.0 : gx1 / (5.0 * e_raw);   // dL/de
+      lam[c] = static_cast<float>(lam[c] + le * K * z + gx0 / (5.0 * rho) + ge * (ke - e_raw) * ir);
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        lam[(1 + d) * nc + c] = static_cast<float>(lam[(1 + d) * nc + c] + ge * (-u[d] * ia * ir));
+      lam[4 * nc + c] = static_cast<float>(le + ge * (ia * ia * ir));
+      acc[0] += stage[wave][lane][3] / 0.02;
+      acc[1] += stage[wave][lane][4] / 100.0;
+    }
+    __syncthreads();
   }
   block_reduce_store<2, false>(acc, partial);
 }
@@ -516,14 +755,12 @@ void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4
                        float* star, const SourceArgs& a, float* q_kicked, double gamma,
                        double* block_max, int n) {
   const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(close_step_kernel, dim3(sum_blocks(nc)), dim3(kRedThreads), 0, st, q_in, q,
-                     g4, h, star, a, q_kicked, gamma * (gamma - 1.0), block_max, nc);
-  DH_LAUNCH_CHECK();
-}
-
-void launch_source(hipStream_t st, float* q, float* star, const SourceArgs& a, int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(source_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, star, a, nc);
+  if (a.mlp && a.mode != 0)
+    hipLaunchKernelGGL(close_step_mlp_kernel, dim3(sum_blocks(nc)), dim3(kRedThreads), 0, st, q_in,
+                       q, g4, h, star, a, q_kicked, gamma * (gamma - 1.0), block_max, nc);
+  else
+    hipLaunchKernelGGL(close_step_kernel, dim3(sum_blocks(nc)), dim3(kRedThreads), 0, st, q_in, q,
+                       g4, h, star, a, q_kicked, gamma * (gamma - 1.0), block_max, nc);
   DH_LAUNCH_CHECK();
 }
 
@@ -536,8 +773,12 @@ int cfl_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n * n); }
 void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, const SourceArgs& a,
                        double* partials, int nblocks_out, int n) {
   const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(source_vjp_kernel, dim3(nblocks_out), dim3(kRedThreads), 0, st, q_before,
-                     lam_q, a, partials, nc);
+  if (a.mlp)
+    hipLaunchKernelGGL(source_vjp_mlp_kernel, dim3(nblocks_out), dim3(kRedThreads), 0, st,
+                       q_before, lam_q, a, partials, nc);
+  else
+    hipLaunchKernelGGL(source_vjp_kernel, dim3(nblocks_out), dim3(kRedThreads), 0, st, q_before,
+                       lam_q, a, partials, nc);
   DH_LAUNCH_CHECK();
 }
 

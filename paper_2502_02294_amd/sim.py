@@ -44,6 +44,14 @@ def _ptr(t, dtype=torch.float32, numel=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _host_floats(values, count):
+    """ctypes float array of exactly `count` values (from a sequence, numpy or CPU tensor)."""
+    vals = [float(v) for v in (values.tolist() if hasattr(values, "tolist") else values)]
+    if len(vals) != count:
+        raise ValueError(f"expected {count} values, got {len(vals)}")
+    return (ctypes.c_float * count)(*vals)
+
+
 class Sim:
     """One simulation handle on the current HIP device."""
 
@@ -89,6 +97,13 @@ class Sim:
             setattr(p, k, v)
         self.params = p
         self._check(lib().dh_set_params(self._h, ctypes.byref(p)))
+
+    def set_closure(self, theta):
+        """Weights of the learned closure (flat float vector of DH_MLP_NPARAMS values; a
+        simulation created with closure=CLOSURE_MLP needs them before its first step)."""
+        self._stream()
+        arr = _host_floats(theta, _lib.MLP_NPARAMS)
+        self._check(lib().dh_set_closure(self._h, arr))
 
     def init_from_seed(self, seed):
         self._stream()

@@ -47,9 +47,12 @@ def test_struct_layouts_match_c(tmp_path):
 #include <stddef.h>
 #include "{HEADER}"
 int main(void) {{
-  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dh_config), sizeof(dh_params),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dh_config), sizeof(dh_params),
          offsetof(dh_config, subgrid), offsetof(dh_config, sf_seed),
-         offsetof(dh_config, ckpt_every), offsetof(dh_params, w_t));
+         offsetof(dh_config, ckpt_every), offsetof(dh_params, w_t),
+         offsetof(dh_config, closure), sizeof(dh_mlp_train_opts),
+         offsetof(dh_mlp_train_opts, lr), sizeof(dh_mlp_sample_opts),
+         offsetof(dh_mlp_sample_opts, dc_hi));
   return 0;
 }}
 """)
@@ -57,9 +60,10 @@ int main(void) {{
     subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
-    C, P = _lib.Config, _lib.Params
+    C, P, T, S = _lib.Config, _lib.Params, _lib.MlpTrainOpts, _lib.MlpSampleOpts
     want = [ctypes.sizeof(C), ctypes.sizeof(P), C.subgrid.offset, C.sf_seed.offset,
-            C.ckpt_every.offset, P.w_t.offset]
+            C.ckpt_every.offset, P.w_t.offset, C.closure.offset, ctypes.sizeof(T), T.lr.offset,
+            ctypes.sizeof(S), S.dc_hi.offset]
     assert got == want
 
 
