@@ -1,7 +1,8 @@
 """Benchmark of the MI355X path: cell-updates/s of the full time step (forward with
 checkpoints plus the reverse pass) at 256^3 cells + 256^3 dark-matter particles, the
-forward-only rate, the HBM roofline fraction of the dominant kernel, and the FP64 CPU
-oracle timed on this host.
+forward-only rate, the HBM roofline fraction of the dominant kernel, the FP64 CPU oracle
+timed on this host, and the learned star-formation closure against the plain source term
+(its training, its step rates, and the distance of its final fields from the plain run's).
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -31,6 +32,8 @@ def parse():
     p.add_argument("--n", type=int, default=N)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--kernel-reps", type=int, default=20)
+    p.add_argument("--no-mlp", action="store_true", help="skip the learned-closure comparison")
+    p.add_argument("--mlp-samples", type=int, default=1 << 24)
     return p.parse_args()
 
 
@@ -50,6 +53,105 @@ def time_stage(torch, fn, reps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps / 1e3
+
+
+def time_steps(torch, s, white, steps, warmup):
+    """(forward-only seconds, forward-with-checkpoints + loss + reverse seconds) of `steps`
+    steps from the initial conditions of `white`, after `warmup` untimed steps / one untimed
+    pass of the full path."""
+    s.init_from_noise(white)
+    for _ in range(warmup):
+        s.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    s.init_from_noise(white)
+    for _ in range(steps):
+        s.step()
+    sched = s.get_schedule()
+    target = s.get("flux").clone()
+    s.set_schedule(sched)
+    s.forward(white, 1.0)
+    s.loss(target)
+    s.backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_schedule(sched)
+    k = s.forward(white, 1.0)
+    s.loss(target)
+    s.backward()
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    assert k == steps
+    return t_fwd, t_fb, sched
+
+
+def mlp_comparison(torch, dhp, white, n, box, steps, warmup, samples):
+    """Learned closure vs the plain source term at the same size.  Without cooling the gas
+    denser than the default threshold is hot at this resolution and forms almost no stars,
+    so the comparison uses thresholds under which stars form (Delta_c = 10, T_c = 1e7 K,
+    eps_sf = 0.03); the network is trained for them on `samples` states of the plain term."""
+    prm = dhp.default_params(eps_sf=0.03, delta_c=10.0, t_c=1e7)
+    net = dhp.Mlp(seed=1)
+    x, y = net.sample(samples, seed=7, params=prm,
+                      opts=dhp.mlp.sample_defaults(dc_lo=5.0, dc_hi=20.0))
+    opts = dhp.mlp.train_defaults()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = net.train(x, y, opts)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del x, y
+    theta = net.weights()
+    log(f"bench: closure trained in {t_train:.2f} s, objective {hist[-100:].mean():.4g}")
+    rates = {}
+    for name, clo in (("plain", 0), ("mlp", 1)):
+        cfg = dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=2, closure=clo,
+                                 ckpt_every=max(1, steps))
+        s = dhp.Sim(cfg, prm)
+        if clo:
+            s.set_closure(theta)
+        t_fwd, t_fb, _ = time_steps(torch, s, white, steps, warmup)
+        rates[name] = (n ** 3 * steps / t_fwd, n ** 3 * steps / t_fb)
+        s.close()
+        log(f"bench: {name} source term: forward {t_fwd * 1e3 / steps:.2f} ms/step, "
+            f"fwd+bwd {t_fb * 1e3 / steps:.2f} ms/step")
+    finals = {}
+    for name, sub, clo in (("plain", 2, 0), ("mlp", 2, 1), ("off", 0, 0)):
+        s = dhp.Sim(dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=sub, closure=clo), prm)
+        if clo:
+            s.set_closure(theta)
+        s.init_from_noise(white)
+        k = s.run_to(0.29)
+        finals[name] = (s.get("rho").double(), s.get("temp").double().log(),
+                        float(s.get("star").double().sum()), k)
+        s.close()
+
+    def rel(a, b):
+        return float((a - b).norm() / b.norm())
+
+    p = finals["plain"]
+    return {
+        "fwd_cell_updates_per_s": rates["mlp"][0],
+        "fwd_bwd_cell_updates_per_s": rates["mlp"][1],
+        "plain_fwd_cell_updates_per_s": rates["plain"][0],
+        "plain_fwd_bwd_cell_updates_per_s": rates["plain"][1],
+        "fwd_time_ratio_vs_plain": rates["plain"][0] / rates["mlp"][0],
+        "fwd_bwd_time_ratio_vs_plain": rates["plain"][1] / rates["mlp"][1],
+        "train": {"samples": samples, "steps": int(opts.steps), "batch": int(opts.batch),
+                  "seconds": t_train, "objective_start": float(np.mean(hist[:10])),
+                  "objective_end": float(np.mean(hist[-100:]))},
+        "accuracy": {"run": f"a = {A_INIT} -> 0.29, {p[3]} steps, relaxed star formation, "
+                            "Delta_c = 10, T_c = 1e7 K, eps_sf = 0.03",
+                     "rel_l2_rho_vs_plain": rel(finals["mlp"][0], p[0]),
+                     "rel_l2_lnT_vs_plain": rel(finals["mlp"][1], p[1]),
+                     "no_source_rel_l2_rho_vs_plain": rel(finals["off"][0], p[0]),
+                     "no_source_rel_l2_lnT_vs_plain": rel(finals["off"][1], p[1]),
+                     "stars_plain": p[2], "stars_mlp": finals["mlp"][2]},
+    }
 
 
 def cpu_baseline(n, box):
@@ -89,43 +191,13 @@ def main():
     white = torch.from_numpy(si.white_noise(n, 6)).cuda()
     log(f"bench: n={n} steps={args.steps} warmup={args.warmup}")
 
-    # forward-only: warm up, then K steps
-    s.init_from_noise(white)
-    for _ in range(args.warmup):
-        s.step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.step()
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
+    t_fwd, t_fb, sched = time_steps(torch, s, white, args.steps, args.warmup)
     log(f"bench: forward {args.steps} steps {t_fwd * 1e3:.1f} ms")
-
-    # forward with checkpoints + reverse pass over the same K-step schedule
-    s.init_from_noise(white)
-    for _ in range(args.steps):
-        s.step()
-    sched = s.get_schedule()
-    target = s.get("flux").clone()
-    s.set_schedule(sched)
-    s.forward(white, 1.0)                      # warm-up of the full path
-    s.loss(target)
-    s.backward()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.set_schedule(sched)
-    k = s.forward(white, 1.0)
-    s.loss(target)
-    gw, gp = s.backward()
-    torch.cuda.synchronize()
-    t_fb = time.perf_counter() - t0
-    assert k == args.steps
-    log(f"bench: forward+backward {k} steps {t_fb * 1e3:.1f} ms")
+    log(f"bench: forward+backward {args.steps} steps {t_fb * 1e3:.1f} ms")
 
     # dominant kernel: the hydro sweep (three per step), 40 algorithmic bytes per cell
     q = s.get("q")
     a, _, _ = s.time()
-    dts = []
     sweep_t = {}
     for axis in (0, 1, 2):
         sweep_t[axis] = time_stage(torch, lambda: s.stage_sweep(q, axis, sched[0], a, a),
@@ -158,6 +230,11 @@ def main():
                      "kernel": "hydro sweep (x, y, z mean)",
                      "ms_per_launch": {str(k_): v * 1e3 for k_, v in sweep_t.items()}},
     }
+    s.close()
+    if not args.no_mlp:
+        log("bench: learned closure vs plain source term")
+        out["mlp_closure"] = mlp_comparison(torch, dhp, white, n, BOX * n / N, args.steps,
+                                            args.warmup, args.mlp_samples)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(n, BOX * n / N)

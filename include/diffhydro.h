@@ -28,6 +28,13 @@
  *  - Work is enqueued on the handle's stream (dh_set_stream, default the null stream).
  *    Calls that return host scalars synchronise that stream; others are asynchronous.
  *  - A handle is not thread-safe; separate handles are independent.
+ *  - Batches: a handle created with cfg.batch = S > 1 holds S independent samples of the
+ *    same size and cosmology (the parameter sampler).  Every device array exchanged with
+ *    the handle then holds S consecutive single-sample arrays, every per-sample host output
+ *    S values (documented per call), and every kernel launch covers all samples at once.
+ *    Sample s uses white-noise seed (seed + s) in dh_init_from_seed and star-formation key
+ *    (sf_seed + s).  The samples step in lockstep: each has its own dt (its own CFL or
+ *    schedule); one that has reached its end sits out the remaining steps unchanged.
  */
 #ifndef DIFFHYDRO_H
 #define DIFFHYDRO_H
@@ -73,6 +80,7 @@ typedef struct dh_config {
     uint64_t sf_seed;    /* key of the per-cell, per-step star-formation uniforms          */
     int32_t ckpt_every;  /* checkpoint interval in steps for dh_forward/dh_backward (>=1)  */
     int32_t closure;     /* DH_CLOSURE_*; MLP needs subgrid != OFF and dh_set_closure()    */
+    int32_t batch;       /* samples in the handle (>= 1); n^3 * batch <= 2^31              */
 } dh_config;
 
 /* Model parameters (double).  A, beta: flux observable F = exp(-A Delta^beta) of the loss;
@@ -102,6 +110,9 @@ int dh_destroy(dh_sim* sim);
 /* hip_stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) or NULL. */
 int dh_set_stream(dh_sim* sim, void* hip_stream);
 int dh_set_params(dh_sim* sim, const dh_params* p);
+/* Star-formation parameters of one sample of a batch (eps_sf, delta_c, t_c, e0, w_rho, w_t
+ * of p; the loss parameters A, beta stay those of dh_set_params, shared by all samples). */
+int dh_set_sample_params(dh_sim* sim, int32_t sample, const dh_params* p);
 
 /* Initial state (Sec. 2.1): white noise -> delta_k = FFT(w) sqrt(P(k) D(a_i)^2 / V_cell)
  * -> Zel'dovich displacement Psi = IFFT(i k delta_k / k^2) -> particles x = q + Psi,
@@ -114,10 +125,12 @@ int dh_init_from_noise(dh_sim* sim, const float* d_white);
 
 /* One step (operator order: CFL dt or next schedule entry; opening half kicks of gas and
  * dark matter with g_n; drift; three sweeps in the Strang order of this step; CIC deposit
- * and Poisson solve; closing half kicks with g_{n+1}; source term).  dt_out, a_out may be
- * NULL.  Returns DH_E_NONFINITE if the new state has a non-finite or non-positive density. */
+ * and Poisson solve; closing half kicks with g_{n+1}; source term).  dt_out, a_out (of
+ * sample 0) may be NULL.  Returns DH_E_NONFINITE if the new state has a non-finite or
+ * non-positive density. */
 int dh_step(dh_sim* sim, double* dt_out, double* a_out);
-/* Steps until a >= a_final; the last step is clipped to land on a_final. */
+/* Steps until a >= a_final for every sample (the last step of each is clipped to land on
+ * a_final); *nsteps_out = number of lockstep steps taken. */
 int dh_run_to(dh_sim* sim, double a_final, int32_t* nsteps_out);
 
 /* Predefined schedule (Sec. 2.3.3).  set: the next steps take dts[0..n) in order (then the
@@ -125,6 +138,11 @@ int dh_run_to(dh_sim* sim, double a_final, int32_t* nsteps_out);
  * cap values, total count in *n_out. */
 int dh_set_schedule(dh_sim* sim, const double* dts, int32_t n);
 int dh_get_schedule(const dh_sim* sim, double* dts, int32_t cap, int32_t* n_out);
+/* The same for one sample of a batch (dh_set_schedule sets every sample's; dh_get_schedule
+ * returns sample 0's). */
+int dh_set_sample_schedule(dh_sim* sim, int32_t sample, const double* dts, int32_t n);
+int dh_get_sample_schedule(const dh_sim* sim, int32_t sample, double* dts, int32_t cap,
+                           int32_t* n_out);
 
 /* Copy a field to / from caller device memory (see dh_field).  set_field of Q, POS or RHO
  * invalidates the potential; dh_refresh_potential() recomputes it from the current gas and
@@ -136,25 +154,32 @@ int dh_refresh_potential(dh_sim* sim);
  * order and the random-number counters. */
 int dh_get_time(const dh_sim* sim, double* a, double* t, int32_t* step);
 int dh_set_time(dh_sim* sim, double a, int32_t step);
+/* Scale factor and time of every sample (host arrays of batch values; either may be NULL). */
+int dh_get_sample_times(const dh_sim* sim, double* a, double* t);
 
 /* Differentiable run: init from d_white, then step to a_final with checkpoints every
- * cfg.ckpt_every steps (replaying the schedule if one was set, else recording it). */
+ * cfg.ckpt_every steps (replaying each sample's schedule if one was set, else recording
+ * it); *nsteps_out = number of lockstep steps. */
 int dh_forward(dh_sim* sim, const float* d_white, double a_final, int32_t* nsteps_out);
 /* Loss L = mean over cells of (F - F_target)^2 with F = exp(-A (rho/rho_mean)^beta) on the
- * current state; FP64 reduction.  d_target[n^3] device. */
+ * current state; FP64 reduction.  d_target[n^3] device (per sample); loss_out: one value
+ * per sample. */
 int dh_loss(dh_sim* sim, const float* d_target, double* loss_out);
 /* Reverse pass of the last dh_forward.  d_grad_rho: adjoint of the final gas density
- * (device n^3) or NULL for the gradient of the last dh_loss.  Outputs: d_grad_white[n^3]
- * (device) and grad_params[4] = dL/d(A, beta, eps_sf, delta_c) (host, FP64).  The time
+ * (device n^3 per sample) or NULL for the gradient of the last dh_loss (each sample's own
+ * loss).  Outputs: d_grad_white[n^3] per sample (device) and grad_params[4] per sample =
+ * dL/d(A, beta, eps_sf, delta_c) (host, FP64, summed over steps in a fixed order).  The time
  * schedule is held fixed.  DH_E_STATE if no forward (or no loss, with NULL) precedes it. */
 int dh_backward(dh_sim* sim, const float* d_grad_rho, float* d_grad_white, double* grad_params);
 
-/* FP64 sums over the current state: out[0] gas mass, out[1..3] gas momentum a rho U,
- * out[4] total gas energy a^2 rho E, out[5..7] dark-matter momentum (mass times p). */
+/* FP64 sums over the current state, 8 values per sample: out[0] gas mass, out[1..3] gas
+ * momentum a rho U, out[4] total gas energy a^2 rho E, out[5..7] dark-matter momentum (mass
+ * times p). */
 int dh_conservation(dh_sim* sim, double* out);
 
-/* Single stages on caller buffers, for verification of each kernel against a reference.
- * They do not touch the handle's state.  All pointers are device float32.
+/* Single stages on caller buffers (one sample's size), for verification of each kernel
+ * against a reference.  They do not touch the handle's state.  All pointers are device
+ * float32.
  *  sweep:    q_out = one relaxing-TVD sweep of q_in along axis (0 x, 1 y, 2 z) over dt,
  *            with scale factors a_stage1, a_stage2 (Sec. 2.3.1-2.3.2).
  *  sweep_vjp: lam_in = (d sweep / d q_in)^T lam_out at q_in.

@@ -27,7 +27,8 @@ class Config(ctypes.Structure):
                 ("a_init", ctypes.c_double), ("t_init", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("dlna_max", ctypes.c_double), ("t_floor", ctypes.c_double),
                 ("subgrid", ctypes.c_int32), ("tau", ctypes.c_double), ("sf_seed", ctypes.c_uint64),
-                ("ckpt_every", ctypes.c_int32), ("closure", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("closure", ctypes.c_int32),
+                ("batch", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -65,17 +66,21 @@ _SIGNATURES = {
     "dh_destroy": (I, [P]),
     "dh_set_stream": (I, [P, P]),
     "dh_set_params": (I, [P, ctypes.POINTER(Params)]),
+    "dh_set_sample_params": (I, [P, I, ctypes.POINTER(Params)]),
     "dh_init_from_seed": (I, [P, ctypes.c_uint64]),
     "dh_init_from_noise": (I, [P, P]),
     "dh_step": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
     "dh_run_to": (I, [P, D, ctypes.POINTER(I)]),
     "dh_set_schedule": (I, [P, ctypes.POINTER(D), I]),
     "dh_get_schedule": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
+    "dh_set_sample_schedule": (I, [P, I, ctypes.POINTER(D), I]),
+    "dh_get_sample_schedule": (I, [P, I, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
     "dh_get_field": (I, [P, I, P]),
     "dh_set_field": (I, [P, I, P]),
     "dh_refresh_potential": (I, [P]),
     "dh_get_time": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I)]),
     "dh_set_time": (I, [P, D, I]),
+    "dh_get_sample_times": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
     "dh_forward": (I, [P, P, D, ctypes.POINTER(I)]),
     "dh_loss": (I, [P, P, ctypes.POINTER(D)]),
     "dh_backward": (I, [P, P, P, ctypes.POINTER(D)]),

@@ -6,6 +6,10 @@
 //   -> three sweeps in the Strang order of the step (Sec. 2.3.2)
 //   -> counting sort -> CIC deposit of gas + DM -> FFT Poisson at a(t+dt) -> phi_{n+1}
 //   -> gas and DM closing half kicks with g_{n+1} -> star-formation source term.
+// A handle holds S independent samples (S = 1 for a single simulation): every launch covers
+// all of them, each with its own dt, scale factors and parameters from a per-step device
+// table; the samples advance in lockstep by global step, and a sample that has reached its
+// end (or the end of its replayed schedule) sits out the remaining steps.
 // Reverse mode: the forward keeps a checkpoint of the state every ckpt_every steps; the
 // backward re-runs each segment from its checkpoint, keeping every intermediate the
 // adjoint kernels need (the tape of that segment), then applies the adjoint of each step
@@ -25,15 +29,23 @@
 namespace {
 
 using dh::ArgError;
+using dh::Batch;
 using dh::HipError;
+using dh::StepScal;
 
 constexpr double kBoltzmann = 1.380649e-23;       // J/K
 constexpr double kProtonMass = 1.67262192369e-27;  // kg
 
-struct Plan {
+struct Plan {        // one sample's part of a step
   double t0, dt, a0, ah, a1;
-  int step;
+  bool active;
+};
+
+struct StepPlan {    // one global step of all samples
+  int step;          // global step counter (Strang order, random-number counter)
+  int slot;          // index of its table in the handle's table store
   int axes[3];
+  std::vector<Plan> smp;
 };
 
 const int kStrang[6][3] = {{0, 1, 2}, {2, 1, 0}, {2, 0, 1}, {1, 0, 2}, {1, 2, 0}, {0, 2, 1}};
@@ -43,12 +55,12 @@ struct TapeStep {
                     // Q4 after sweeps, Q5 after closing kick (source input)
   float *x0, *x1;             // particle positions at the start and after the drift
   float *phi0, *phi1;
-  Plan plan;
+  StepPlan plan;
 };
 
 struct Ckpt {
   float *q, *pos, *mom, *star, *phi;
-  double t, a;
+  std::vector<double> t, a;
   int step;
 };
 
@@ -56,17 +68,18 @@ struct Ckpt {
 
 struct dh_sim {
   dh_config cfg;
-  dh_params prm;
-  int n = 0;
+  dh_params prm;                    // shared parameters (loss: A, beta)
+  std::vector<dh_params> sprm;      // per-sample parameters of the source term
+  int n = 0, S = 1;
   long long nc = 0, np = 0, nck = 0;
   hipStream_t st = nullptr;
   dh::Cosmo cosmo{};
   double amp = 0, f_b = 0, vel_unit = 0, t_per_e = 0, e_init = 0, e_floor = 0, m_dm = 0;
 
-  // state
+  // state (S samples stacked)
   float *q = nullptr, *pos = nullptr, *mom = nullptr, *star = nullptr, *phi = nullptr;
-  double t = 0, a = 0;
-  int step = 0;
+  std::vector<double> t, a;         // per sample
+  int step = 0;                     // global step counter
   bool phi_valid = false, initialised = false;
 
   // scratch
@@ -77,18 +90,28 @@ struct dh_sim {
   dh::Bins bins{};
   double* cfl_red = nullptr;   // CFL block maxima of the current state (from the closing pass)
   bool cfl_partials = false;   // cfl_red holds the maxima of the current state
-  bool speed_known = false;    // speed holds the CFL speed of the current state
-  double speed = 0.0;
+  bool speed_known = false;    // speed holds the CFL speeds of the current state
+  std::vector<double> speed;
   double* red = nullptr;       // block partials
   double* red_out = nullptr;   // reduced values
   double* host_out = nullptr;  // pinned
+  double* d_acur = nullptr;    // scale factor of each sample (CFL recomputation)
   int red_blocks = 0;
+
+  // per-step tables: slot k holds the S entries of the k-th step since the last init
+  StepScal* tabs = nullptr;
+  StepScal* htabs = nullptr;   // pinned mirror
+  int tab_cap = 0;
+  int nslots = 0;
+  StepScal* cur_tab = nullptr;    // state table: every sample active at its current a
+  StepScal* stage_tab = nullptr;  // single entry for the stage calls
+  StepScal* hstage = nullptr;     // pinned staging of cur_tab / stage_tab
 
   // adjoint buffers
   float *lq = nullptr, *lq2 = nullptr, *lh = nullptr, *lx = nullptr, *lp = nullptr,
         *lphi = nullptr, *lphi2 = nullptr, *lg = nullptr, *ldelta = nullptr, *lpsi = nullptr,
         *lcic = nullptr;
-  double* param_steps = nullptr;   // [2 * cap] per-step dL/d(eps_sf, delta_c)
+  double* param_steps = nullptr;   // [cap][2 S] per-step dL/d(eps_sf, delta_c)
   int param_cap = 0;
 
   // learned closure: flat weights and their packed matrix-core form
@@ -96,14 +119,14 @@ struct dh_sim {
   uint4* mlp_packed = nullptr;
   bool mlp_ready = false;
 
-  // schedule
-  std::vector<double> recorded;
-  std::vector<double> replay;
-  size_t replay_pos = 0;
+  // schedules (per sample)
+  std::vector<std::vector<double>> recorded, replay;
+  std::vector<size_t> replay_pos;
 
   // reverse mode
   std::vector<Ckpt> ckpts;
   std::vector<TapeStep> tape;
+  std::vector<StepPlan> fwd_plans;   // plans of the last dh_forward, in order
   bool have_forward = false, have_loss = false;
   int fwd_steps = 0;
   float* loss_target = nullptr;
@@ -161,28 +184,135 @@ dh::HydroK hydro_at(const dh_sim* s, double a) {
 
 void sync(dh_sim* s) { DH_HIP(hipStreamSynchronize(s->st)); }
 
-// bins of the particle positions pos
-void sort_particles(dh_sim* s, const float* pos) {
-  dh::launch_keys(s->st, pos, s->bins.key, s->n);
-  dh::launch_sort(s->st, s->bins, pos, s->n);
+Batch batch(const dh_sim* s, const StepScal* tab) { return Batch{s->n, s->S, tab}; }
+
+float green_at(const dh_sim* s, double a) {
+  return static_cast<float>(-(1.5 * s->cfg.omega_m / a) / static_cast<double>(s->nc));
 }
 
-// phi_out = Poisson solve of delta at scale factor a; uses spec
-void poisson(dh_sim* s, const float* delta, float* phi_out, double a) {
-  dh::fft_forward_xy(s->st, delta, s->spec, s->tw, s->n);
-  const double n3 = static_cast<double>(s->nc);
-  dh::fft_zpass_green(s->st, s->spec, s->tw, s->n,
-                      static_cast<float>(-(1.5 * s->cfg.omega_m / a) / n3));
-  dh::fft_inverse_yx(s->st, s->spec, phi_out, s->tw, s->n, 1.0f);
+dh::SourceArgs source_args(const dh_sim* s, int smp, double a1, double dt, int step) {
+  const dh_params& p = s->sprm[smp];
+  dh::SourceArgs a{};
+  a.a = a1;
+  a.dt = dt;
+  a.inv_rho_mean = 1.0 / s->f_b;
+  a.omega_b = s->cfg.omega_b;
+  a.efloor = s->e_floor;
+  a.t_per_e = s->t_per_e;
+  a.e0_code = p.e0 * 1e6 / (s->vel_unit * s->vel_unit);
+  a.eps_sf = p.eps_sf;
+  a.delta_c = p.delta_c;
+  a.t_c = p.t_c;
+  a.w_rho = p.w_rho;
+  a.w_t = p.w_t;
+  a.tau = s->cfg.tau;
+  a.mode = s->cfg.subgrid;
+  const uint64_t seed = s->cfg.sf_seed + static_cast<uint64_t>(smp);   // sample s: key + s
+  a.seed_lo = static_cast<uint32_t>(seed & 0xFFFFFFFFull);
+  a.seed_hi = static_cast<uint32_t>(seed >> 32);
+  a.step = static_cast<uint32_t>(step);
+  a.mlp = s->cfg.closure == DH_CLOSURE_MLP ? s->mlp_packed : nullptr;
+  return a;
+}
+
+StepScal entry_of(const dh_sim* s, int smp, const Plan& p, int step) {
+  StepScal e{};
+  e.src = source_args(s, smp, p.active ? p.a1 : p.a0, p.active ? p.dt : 0.0, step);
+  e.active = p.active ? 1 : 0;
+  if (!p.active) return e;
+  e.dt = static_cast<float>(p.dt);
+  e.h = static_cast<float>(0.5 * p.dt);
+  e.drift = static_cast<float>(p.dt / (p.ah * p.ah));
+  e.h1 = hydro_at(s, p.a0);
+  e.h2 = hydro_at(s, p.ah);
+  e.green = green_at(s, p.a1);
+  e.h_dm = e.h;
+  return e;
+}
+
+// Grows the table store to hold `slots` steps (keeping the tables written so far).
+void ensure_tab_slots(dh_sim* s, int slots) {
+  if (slots <= s->tab_cap) return;
+  const int cap = std::max(slots, 2 * s->tab_cap + 64);
+  sync(s);
+  StepScal* d = s->alloc<StepScal>(static_cast<long long>(cap) * s->S);
+  void* hp = nullptr;
+  DH_HIP(hipHostMalloc(&hp, static_cast<size_t>(cap) * s->S * sizeof(StepScal),
+                       hipHostMallocDefault));
+  StepScal* h = static_cast<StepScal*>(hp);
+  if (s->tabs) {
+    const size_t bytes = static_cast<size_t>(s->tab_cap) * s->S * sizeof(StepScal);
+    DH_HIP(hipMemcpy(d, s->tabs, bytes, hipMemcpyDeviceToDevice));
+    std::memcpy(h, s->htabs, bytes);
+    s->release(s->tabs);
+    (void)hipHostFree(s->htabs);
+  }
+  s->tabs = d;
+  s->htabs = h;
+  s->tab_cap = cap;
+}
+
+// Writes the table of a planned step into its slot (host mirror and device).  Each slot
+// has its own pinned host memory, so no copy in flight is ever overwritten.
+void upload_plan(dh_sim* s, const StepPlan& sp) {
+  ensure_tab_slots(s, sp.slot + 1);
+  StepScal* h = s->htabs + static_cast<size_t>(sp.slot) * s->S;
+  for (int i = 0; i < s->S; ++i) h[i] = entry_of(s, i, sp.smp[i], sp.step);
+  DH_HIP(hipMemcpyAsync(s->tabs + static_cast<size_t>(sp.slot) * s->S, h,
+                        static_cast<size_t>(s->S) * sizeof(StepScal), hipMemcpyHostToDevice,
+                        s->st));
+}
+
+const StepScal* tab_of(const dh_sim* s, const StepPlan& sp) {
+  return s->tabs + static_cast<size_t>(sp.slot) * s->S;
+}
+
+// Table of the current state: every sample active at its own scale factor (Poisson green).
+// The staging buffer is reused only after the stream has drained.
+const StepScal* state_table(dh_sim* s) {
+  sync(s);
+  for (int i = 0; i < s->S; ++i) {
+    StepScal e{};
+    e.active = 1;
+    e.green = green_at(s, s->a[i]);
+    e.h1 = e.h2 = hydro_at(s, s->a[i]);
+    e.src = source_args(s, i, s->a[i], 0.0, s->step);
+    s->hstage[i] = e;
+  }
+  DH_HIP(hipMemcpyAsync(s->cur_tab, s->hstage, static_cast<size_t>(s->S) * sizeof(StepScal),
+                        hipMemcpyHostToDevice, s->st));
+  return s->cur_tab;
+}
+
+// Single entry for the stage calls (layout of one sample).
+const StepScal* stage_table(dh_sim* s, const StepScal& e) {
+  sync(s);
+  s->hstage[0] = e;
+  DH_HIP(hipMemcpyAsync(s->stage_tab, s->hstage, sizeof(StepScal), hipMemcpyHostToDevice, s->st));
+  return s->stage_tab;
+}
+
+// bins of the particle positions pos (all samples of b)
+void sort_particles(dh_sim* s, const float* pos, const Batch& b) {
+  dh::launch_keys(s->st, pos, s->bins.key, b);
+  dh::launch_sort(s->st, s->bins, pos, b);
+}
+
+// phi_out = Poisson solve of delta with the Green's factor of each sample's table entry
+void poisson(dh_sim* s, const float* delta, float* phi_out, const Batch& b) {
+  dh::fft_forward_xy(s->st, delta, s->spec, s->tw, b);
+  dh::fft_zpass_green(s->st, s->spec, s->tw, b);
+  dh::fft_inverse_yx(s->st, s->spec, phi_out, s->tw, 1.0f, b);
 }
 
 // phi = Poisson(rho_gas + m_dm CIC(pos) - 1) and g4 = -grad(phi), with the bins of the
 // particle positions already built
 void potential_from_bins(dh_sim* s, const float* rho_gas, float* phi_out, float4* g4_out,
-                         double a) {
-  dh::launch_deposit(s->st, s->bins, rho_gas, static_cast<float>(s->m_dm), -1.0f, s->delta, s->n);
-  poisson(s, s->delta, phi_out, a);
-  dh::launch_grad(s->st, phi_out, g4_out, s->n);
+                         const Batch& b) {
+  dh::launch_deposit(s->st, s->bins, rho_gas, 5 * s->nc, static_cast<float>(s->m_dm), -1.0f,
+                     s->delta, b);
+  poisson(s, s->delta, phi_out, b);
+  dh::launch_grad(s->st, phi_out, g4_out, b);
 }
 
 void state_changed(dh_sim* s) {
@@ -190,109 +320,105 @@ void state_changed(dh_sim* s) {
   s->speed_known = false;
 }
 
-// CFL speed max over cells and axes of (|U_d| + c_s)/a of the current state (FP64 on the
-// device); +inf when the state holds a non-finite value or a non-positive density
-double current_speed(dh_sim* s) {
+// CFL speeds, max over cells and axes of (|U_d| + c_s)/a, of each sample's current state
+// (FP64 on the device); +inf when a state holds a non-finite value or a non-positive density
+const std::vector<double>& current_speed(dh_sim* s) {
   if (s->speed_known) return s->speed;
-  if (!s->cfl_partials)
-    dh::launch_cfl_partial(s->st, s->q, s->a, s->cfg.gamma, s->e_floor, s->cfl_red, s->n);
-  dh::launch_reduce_max(s->st, s->cfl_red, dh::cfl_blocks(s->n), s->red_out);
-  DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, sizeof(double), hipMemcpyDeviceToHost, s->st));
+  const int nb = dh::cfl_blocks(s->n);
+  if (!s->cfl_partials) {
+    sync(s);
+    std::memcpy(s->host_out, s->a.data(), s->S * sizeof(double));
+    DH_HIP(hipMemcpyAsync(s->d_acur, s->host_out, s->S * sizeof(double), hipMemcpyHostToDevice,
+                          s->st));
+    dh::launch_cfl_partial(s->st, s->q, s->d_acur, s->cfg.gamma, s->e_floor, s->cfl_red,
+                           batch(s, nullptr));
+  }
+  dh::launch_reduce_max(s->st, s->cfl_red, nb, nb, s->S, s->red_out);
+  DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, s->S * sizeof(double), hipMemcpyDeviceToHost,
+                        s->st));
   sync(s);
-  s->speed = s->host_out[0];
+  s->speed.assign(s->host_out, s->host_out + s->S);
   s->speed_known = true;
+  s->cfl_partials = true;
   return s->speed;
 }
 
-dh::SourceArgs source_args(const dh_sim* s, const Plan& pl) {
-  dh::SourceArgs a{};
-  a.a = pl.a1;
-  a.dt = pl.dt;
-  a.inv_rho_mean = 1.0 / s->f_b;
-  a.omega_b = s->cfg.omega_b;
-  a.efloor = s->e_floor;
-  a.t_per_e = s->t_per_e;
-  a.e0_code = s->prm.e0 * 1e6 / (s->vel_unit * s->vel_unit);
-  a.eps_sf = s->prm.eps_sf;
-  a.delta_c = s->prm.delta_c;
-  a.t_c = s->prm.t_c;
-  a.w_rho = s->prm.w_rho;
-  a.w_t = s->prm.w_t;
-  a.tau = s->cfg.tau;
-  a.mode = s->cfg.subgrid;
-  a.seed_lo = static_cast<uint32_t>(s->cfg.sf_seed & 0xFFFFFFFFull);
-  a.seed_hi = static_cast<uint32_t>(s->cfg.sf_seed >> 32);
-  a.step = static_cast<uint32_t>(pl.step);
-  a.mlp = s->cfg.closure == DH_CLOSURE_MLP ? s->mlp_packed : nullptr;
-  return a;
-}
-
-Plan make_plan(const dh_sim* s, double dt) {
-  Plan p{};
-  p.t0 = s->t;
-  p.dt = dt;
-  p.a0 = s->a;
-  p.ah = s->cosmo.a_of_t(s->t + 0.5 * dt);
-  p.a1 = s->cosmo.a_of_t(s->t + dt);
-  p.step = s->step;
-  for (int k = 0; k < 3; ++k) p.axes[k] = kStrang[s->step % 6][k];
-  return p;
+bool all_finite(const std::vector<double>& v) {
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return true;
 }
 
 // One step of the method on the handle state.  With a tape entry, keeps its intermediates.
-void do_step(dh_sim* s, const Plan& pl, TapeStep* tp) {
-  const int n = s->n;
+void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp) {
   const long long nc = s->nc, np = s->np;
-  const float h = static_cast<float>(0.5 * pl.dt);
+  const Batch b = batch(s, tab_of(s, sp));
   if (tp) {
-    tp->plan = pl;
-    copy_d2d(s, tp->q[0], s->q, 5 * nc);
-    copy_d2d(s, tp->x0, s->pos, 3 * np);
-    copy_d2d(s, tp->phi0, s->phi, nc);
+    tp->plan = sp;
+    copy_d2d(s, tp->q[0], s->q, 5 * nc * s->S);
+    copy_d2d(s, tp->x0, s->pos, 3 * np * s->S);
+    copy_d2d(s, tp->phi0, s->phi, nc * s->S);
   }
-  const dh::HydroK h1 = hydro_at(s, pl.a0), h2 = hydro_at(s, pl.ah);
-  const float dtf = static_cast<float>(pl.dt);
-  const float drift = static_cast<float>(pl.dt / (pl.ah * pl.ah));
+  const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
   if (tp) {
     // the kick, the sweeps and the closing pass write their results straight into the tape
-    dh::launch_gas_kick(s->st, s->q, tp->q[1], s->g4, h, n);
-    dh::launch_kick_drift(s->st, s->g4, s->pos, s->mom, s->bins.key, h, drift, nullptr, tp->x1, n);
-    for (int k = 0; k < 3; ++k)
-      dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], n, pl.axes[k], dtf, h1, h2);
-    dh::launch_sort(s->st, s->bins, s->pos, n);
-    potential_from_bins(s, tp->q[4], s->phi, s->g4, pl.a1);
-    copy_d2d(s, tp->phi1, s->phi, nc);
-    dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, h, s->star, source_args(s, pl), tp->q[5],
-                          s->cfg.gamma, s->cfl_red, n);
+    dh::launch_gas_kick(s->st, s->q, tp->q[1], s->g4, b);
+    dh::launch_kick_drift(s->st, s->g4, s->pos, s->mom, s->bins.key, nullptr, tp->x1, b);
+    for (int k = 0; k < 3; ++k) dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
+    dh::launch_sort(s->st, s->bins, s->pos, b);
+    potential_from_bins(s, tp->q[4], s->phi, s->g4, b);
+    copy_d2d(s, tp->phi1, s->phi, nc * s->S);
+    dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, s->star, tp->q[5], s->cfg.gamma,
+                          s->cfl_red, b, closure);
   } else {
     // opening half kicks with g_n, drift with a(t + dt/2)
-    dh::launch_gas_kick(s->st, s->q, s->q, s->g4, h, n);
-    dh::launch_kick_drift(s->st, s->g4, s->pos, s->mom, s->bins.key, h, drift, nullptr, nullptr, n);
-    // sweeps in the Strang order of the step
+    dh::launch_gas_kick(s->st, s->q, s->q, s->g4, b);
+    dh::launch_kick_drift(s->st, s->g4, s->pos, s->mom, s->bins.key, nullptr, nullptr, b);
+    // sweeps in the Strang order of the step (a sample that sits out is copied along)
     for (int k = 0; k < 3; ++k) {
-      dh::launch_sweep(s->st, s->q, s->q2, n, pl.axes[k], dtf, h1, h2);
+      dh::launch_sweep(s->st, s->q, s->q2, b, sp.axes[k]);
       std::swap(s->q, s->q2);
     }
     // Poisson at a(t + dt) from gas + DM (keys were written by the drift)
-    dh::launch_sort(s->st, s->bins, s->pos, n);
-    potential_from_bins(s, s->q, s->phi, s->g4, pl.a1);
+    dh::launch_sort(s->st, s->bins, s->pos, b);
+    potential_from_bins(s, s->q, s->phi, s->g4, b);
     // closing gas half kick with g_{n+1}, source term and the CFL maxima: one pass
-    dh::launch_close_step(s->st, s->q, s->q, s->g4, h, s->star, source_args(s, pl), nullptr,
-                          s->cfg.gamma, s->cfl_red, n);
+    dh::launch_close_step(s->st, s->q, s->q, s->g4, s->star, nullptr, s->cfg.gamma, s->cfl_red, b,
+                          closure);
   }
-  dh::launch_kick(s->st, s->g4, s->pos, s->mom, h, n);
+  dh::launch_kick(s->st, s->g4, s->pos, s->mom, b);
   DH_LAUNCH_CHECK();
-  s->t = pl.t0 + pl.dt;
-  s->a = pl.a1;
-  s->step = pl.step + 1;
+  bool all = true;
+  for (int i = 0; i < s->S; ++i) {
+    const Plan& p = sp.smp[i];
+    if (!p.active) {
+      all = false;
+      continue;
+    }
+    s->t[i] = p.t0 + p.dt;
+    s->a[i] = p.a1;
+  }
+  s->step = sp.step + 1;
   s->speed_known = false;
-  s->cfl_partials = true;
+  // the closing pass left the CFL maxima of every sample that moved (zeros for the others)
+  s->cfl_partials = all;
 }
 
 void refresh_potential(dh_sim* s) {
-  sort_particles(s, s->pos);
-  potential_from_bins(s, s->q, s->phi, s->g4, s->a);
+  const Batch b = batch(s, state_table(s));
+  sort_particles(s, s->pos, b);
+  potential_from_bins(s, s->q, s->phi, s->g4, b);
   s->phi_valid = true;
+}
+
+void reset_clock(dh_sim* s) {
+  const double ai = s->cfg.a_init;
+  std::fill(s->t.begin(), s->t.end(), s->cosmo.t_of_a(ai));
+  std::fill(s->a.begin(), s->a.end(), ai);
+  s->step = 0;
+  s->nslots = 0;
+  for (auto& r : s->recorded) r.clear();
+  std::fill(s->replay_pos.begin(), s->replay_pos.end(), 0);
 }
 
 void initial_conditions(dh_sim* s, const float* d_white) {
@@ -301,101 +427,145 @@ void initial_conditions(dh_sim* s, const float* d_white) {
   const double d = s->cosmo.growth(ai);
   const double vcell = std::pow(s->cfg.box / n, 3.0);
   const double amp = s->amp * d * d / vcell;
-  dh::fft_forward_xy(s->st, d_white, s->spec2, s->tw, n);
-  dh::fft_zpass_forward(s->st, s->spec2, s->spec2, s->tw, n);
+  const Batch all = batch(s, nullptr);
+  dh::fft_forward_xy(s->st, d_white, s->spec2, s->tw, all);
+  dh::fft_zpass_forward(s->st, s->spec2, s->spec2, s->tw, all);
   for (int j = 0; j < 3; ++j) {
-    dh::fft_zpass_ic(s->st, s->spec2, s->spec, s->tw, n, j, false, amp, s->cfg.omega_m * s->cfg.h,
-                     s->cfg.n_s, n / s->cfg.box, false, true, false);
-    dh::fft_inverse_yx(s->st, s->spec, s->psi + j * s->nc, s->tw, n, 1.0f);
+    dh::fft_zpass_ic(s->st, s->spec2, s->spec, s->tw, j, false, amp, s->cfg.omega_m * s->cfg.h,
+                     s->cfg.n_s, n / s->cfg.box, false, true, false, all);
+    dh::fft_inverse_yx(s->st, s->spec, s->psi + j * s->nc, s->tw, 1.0f, all, 3 * s->nc);
   }
   const double vfac = ai * ai * s->cosmo.E(ai) * s->cosmo.growth_rate(ai);
-  dh::launch_ic_particles(s->st, s->psi, s->pos, s->mom, static_cast<float>(vfac), n);
-  sort_particles(s, s->pos);
-  dh::launch_deposit(s->st, s->bins, nullptr, 1.0f, 0.0f, s->cic, n);
+  dh::launch_ic_particles(s->st, s->psi, s->pos, s->mom, static_cast<float>(vfac), all);
+  sort_particles(s, s->pos, all);
+  dh::launch_deposit(s->st, s->bins, nullptr, 0, 1.0f, 0.0f, s->cic, all);
   dh::launch_ic_gas(s->st, s->cic, s->psi, s->q, static_cast<float>(s->f_b),
                     static_cast<float>(vfac), static_cast<float>(ai), static_cast<float>(s->e_init),
-                    n);
-  dh::launch_fill(s->st, s->star, 0.0f, s->nc);
-  s->t = s->cosmo.t_of_a(ai);
-  s->a = ai;
-  s->step = 0;
-  potential_from_bins(s, s->q, s->phi, s->g4, ai);
+                    all);
+  dh::launch_fill(s->st, s->star, 0.0f, s->nc * s->S);
+  reset_clock(s);
+  potential_from_bins(s, s->q, s->phi, s->g4, batch(s, state_table(s)));
   s->phi_valid = true;
   state_changed(s);
   s->initialised = true;
-  s->recorded.clear();
-  s->replay_pos = 0;
 }
 
-// next dt: schedule entry or CFL (eq. dt) with the dln a cap, clipped to t_end (< 0: none)
-int next_dt(dh_sim* s, double t_end, double* dt_out) {
-  double dt;
-  if (s->replay_pos < s->replay.size()) {
-    dt = s->replay[s->replay_pos++];
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(s, DH_E_SCHEDULE, "schedule entry is not a positive finite dt");
-  } else {
-    const double v = current_speed(s);
-    if (!std::isfinite(v) || !(v > 0.0))
-      return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
-    dt = std::min(s->cfg.cfl / v, s->cfg.dlna_max / s->cosmo.E(s->a));
-    if (t_end > 0.0 && s->t + dt > t_end) dt = t_end - s->t;
+// Plans the next step of every sample: the next schedule entry, or the CFL dt (eq. dt) with
+// the dln a cap, clipped to land on t_end (< 0: none).  A sample at t_end, or whose replayed
+// schedule is used up (with stop_at_replay_end), sits out.  *any = whether a sample moves.
+int plan_step(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan& sp, bool* any) {
+  sp.step = s->step;
+  for (int k = 0; k < 3; ++k) sp.axes[k] = kStrang[s->step % 6][k];
+  sp.smp.assign(s->S, Plan{});
+  *any = false;
+  const std::vector<double>* speeds = nullptr;
+  for (int i = 0; i < s->S; ++i) {
+    Plan& p = sp.smp[i];
+    p.t0 = s->t[i];
+    p.a0 = s->a[i];
+    p.active = false;
+    if (t_end > 0.0 && s->t[i] >= t_end * (1.0 - 1e-12)) continue;
+    double dt;
+    if (s->replay_pos[i] < s->replay[i].size()) {
+      dt = s->replay[i][s->replay_pos[i]];
+      if (!(dt > 0.0) || !std::isfinite(dt))
+        return fail(s, DH_E_SCHEDULE, "schedule entry is not a positive finite dt");
+    } else {
+      if (stop_at_replay_end && !s->replay[i].empty()) continue;
+      if (!speeds) speeds = &current_speed(s);
+      const double v = (*speeds)[i];
+      if (!std::isfinite(v) || !(v > 0.0))
+        return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
+      dt = std::min(s->cfg.cfl / v, s->cfg.dlna_max / s->cosmo.E(s->a[i]));
+      if (t_end > 0.0 && s->t[i] + dt > t_end) dt = t_end - s->t[i];
+    }
+    p.dt = dt;
+    p.ah = s->cosmo.a_of_t(p.t0 + 0.5 * dt);
+    p.a1 = s->cosmo.a_of_t(p.t0 + dt);
+    p.active = true;
+    *any = true;
   }
-  *dt_out = dt;
   return DH_OK;
 }
 
-int step_once(dh_sim* s, double t_end, TapeStep* tp, double* dt_used) {
+void commit_plan(dh_sim* s, const StepPlan& sp) {
+  for (int i = 0; i < s->S; ++i) {
+    if (!sp.smp[i].active) continue;
+    if (s->replay_pos[i] < s->replay[i].size()) ++s->replay_pos[i];
+    s->recorded[i].push_back(sp.smp[i].dt);
+  }
+}
+
+// Plans and takes one step of all samples; *moved = false when no sample had a step left.
+int step_once(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan* out, bool* moved) {
   if (!s->initialised) return fail(s, DH_E_STATE, "no initial state");
   if (s->cfg.closure == DH_CLOSURE_MLP && !s->mlp_ready)
     return fail(s, DH_E_STATE, "closure network weights not set (dh_set_closure)");
   if (!s->phi_valid) refresh_potential(s);
-  double dt;
-  int rc = next_dt(s, t_end, &dt);
+  StepPlan sp;
+  bool any = false;
+  int rc = plan_step(s, t_end, stop_at_replay_end, sp, &any);
   if (rc) return rc;
-  do_step(s, make_plan(s, dt), tp);
-  s->recorded.push_back(dt);
-  if (dt_used) *dt_used = dt;
+  *moved = any;
+  if (!any) return DH_OK;
+  sp.slot = s->nslots++;
+  upload_plan(s, sp);
+  do_step(s, sp, nullptr);
+  commit_plan(s, sp);
+  if (out) *out = sp;
   return DH_OK;
 }
 
 void alloc_tape_entry(dh_sim* s, TapeStep& t) {
-  for (int k = 0; k < 6; ++k) t.q[k] = s->alloc<float>(5 * s->nc);
-  t.x0 = s->alloc<float>(3 * s->np);
-  t.x1 = s->alloc<float>(3 * s->np);
-  t.phi0 = s->alloc<float>(s->nc);
-  t.phi1 = s->alloc<float>(s->nc);
+  const long long S = s->S;
+  for (int k = 0; k < 6; ++k) t.q[k] = s->alloc<float>(5 * s->nc * S);
+  t.x0 = s->alloc<float>(3 * s->np * S);
+  t.x1 = s->alloc<float>(3 * s->np * S);
+  t.phi0 = s->alloc<float>(s->nc * S);
+  t.phi1 = s->alloc<float>(s->nc * S);
 }
 
 void save_ckpt(dh_sim* s, Ckpt& c) {
+  const long long S = s->S;
   if (!c.q) {
-    c.q = s->alloc<float>(5 * s->nc);
-    c.pos = s->alloc<float>(3 * s->np);
-    c.mom = s->alloc<float>(3 * s->np);
-    c.star = s->alloc<float>(s->nc);
-    c.phi = s->alloc<float>(s->nc);
+    c.q = s->alloc<float>(5 * s->nc * S);
+    c.pos = s->alloc<float>(3 * s->np * S);
+    c.mom = s->alloc<float>(3 * s->np * S);
+    c.star = s->alloc<float>(s->nc * S);
+    c.phi = s->alloc<float>(s->nc * S);
   }
-  copy_d2d(s, c.q, s->q, 5 * s->nc);
-  copy_d2d(s, c.pos, s->pos, 3 * s->np);
-  copy_d2d(s, c.mom, s->mom, 3 * s->np);
-  copy_d2d(s, c.star, s->star, s->nc);
-  copy_d2d(s, c.phi, s->phi, s->nc);
+  copy_d2d(s, c.q, s->q, 5 * s->nc * S);
+  copy_d2d(s, c.pos, s->pos, 3 * s->np * S);
+  copy_d2d(s, c.mom, s->mom, 3 * s->np * S);
+  copy_d2d(s, c.star, s->star, s->nc * S);
+  copy_d2d(s, c.phi, s->phi, s->nc * S);
   c.t = s->t;
   c.a = s->a;
   c.step = s->step;
 }
 
 void load_ckpt(dh_sim* s, const Ckpt& c) {
-  copy_d2d(s, s->q, c.q, 5 * s->nc);
-  copy_d2d(s, s->pos, c.pos, 3 * s->np);
-  copy_d2d(s, s->mom, c.mom, 3 * s->np);
-  copy_d2d(s, s->star, c.star, s->nc);
-  copy_d2d(s, s->phi, c.phi, s->nc);
+  const long long S = s->S;
+  copy_d2d(s, s->q, c.q, 5 * s->nc * S);
+  copy_d2d(s, s->pos, c.pos, 3 * s->np * S);
+  copy_d2d(s, s->mom, c.mom, 3 * s->np * S);
+  copy_d2d(s, s->star, c.star, s->nc * S);
+  copy_d2d(s, s->phi, c.phi, s->nc * S);
   s->t = c.t;
   s->a = c.a;
   s->step = c.step;
-  dh::launch_grad(s->st, s->phi, s->g4, s->n);
+  dh::launch_grad(s->st, s->phi, s->g4, batch(s, nullptr));
   s->phi_valid = true;
   state_changed(s);
+}
+
+void release_ckpt(dh_sim* s, Ckpt& c) {
+  s->release(c.q);
+  s->release(c.pos);
+  s->release(c.mom);
+  s->release(c.star);
+  s->release(c.phi);
+  c.q = c.pos = c.mom = c.star = c.phi = nullptr;
 }
 
 // Adjoint of one step.  In: lq, lx, lp, lphi = adjoints of the state after the step (lphi is
@@ -403,59 +573,57 @@ void load_ckpt(dh_sim* s, const Ckpt& c) {
 // adjoints of the state at the start of the step.
 // The opening dark-matter kick of the following step acts at the same positions, with the
 // same g and the same adjoint momentum as this step's closing kick, so its adjoint is merged
-// here with factor h_next (0 for the last step); this step's own opening kick is left to the
-// previous step, or to finish_first_kick after the first step.
-void step_vjp(dh_sim* s, const TapeStep& T, int param_slot, float h_next) {
-  const int n = s->n;
+// here (factor h_dm = h of this step + h of the next, the latter 0 after a sample's last
+// step); this step's own opening kick is left to the previous step, or to
+// finish_first_kick after the first step.  A sample that sat the step out keeps its adjoints.
+void step_vjp(dh_sim* s, const TapeStep& T) {
   const long long nc = s->nc, np = s->np;
-  const Plan& pl = T.plan;
-  const float h = static_cast<float>(0.5 * pl.dt);
+  const StepPlan& sp = T.plan;
+  const Batch b = batch(s, tab_of(s, sp));
   hipStream_t st = s->st;
+  const bool closure = s->cfg.closure == DH_CLOSURE_MLP;
   // source term
   if (s->cfg.subgrid != DH_SUBGRID_OFF) {
-    const int nb = dh::source_vjp_blocks(n);
-    dh::launch_source_vjp(st, T.q[5], s->lq, source_args(s, pl), s->red, nb, n);
-    dh::launch_reduce_sum(st, s->red, nb, nb, 2, s->param_steps + 2 * param_slot);
+    const int nb = dh::source_vjp_blocks(s->n);
+    dh::launch_source_vjp(st, T.q[5], s->lq, s->red, b, closure);
+    dh::launch_reduce_sum(st, s->red, nb, nb, 2 * s->S, s->param_steps + 2LL * s->S * sp.slot);
   }
   // closing kicks (gas from Q4, DM at x1) -> lambda_g -> lambda_phi_{n+1}
-  dh::launch_grad(st, T.phi1, s->g4b, n);
-  dh::launch_gas_kick_vjp(st, T.q[4], s->g4b, h, s->lq, s->lg, n);
-  sort_particles(s, T.x1);
-  dh::launch_gather_sorted(st, s->bins, s->lp, n);
-  dh::launch_deposit_vec(st, s->bins, h + h_next, s->lg, n);
-  dh::launch_kick_vjp_pos(st, s->g4b, T.x1, s->lp, h + h_next, s->lx, n);
-  dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi2, n);
+  dh::launch_grad(st, T.phi1, s->g4b, b);
+  dh::launch_gas_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, b);
+  sort_particles(s, T.x1, b);
+  dh::launch_gather_sorted(st, s->bins, s->lp, b);
+  dh::launch_deposit_vec(st, s->bins, true, s->lg, b);
+  dh::launch_kick_vjp_pos(st, s->g4b, T.x1, s->lp, true, s->lx, b);
+  dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi2, b);
   // Poisson (symmetric operator) and deposit at x1
-  poisson(s, s->lphi2, s->ldelta, pl.a1);
-  dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc);
-  dh::launch_deposit_vjp_pos(st, s->ldelta, T.x1, static_cast<float>(s->m_dm), s->lx, n);
+  poisson(s, s->lphi2, s->ldelta, b);
+  dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc, 5 * nc, nc, false, b);
+  dh::launch_deposit_vjp_pos(st, s->ldelta, T.x1, static_cast<float>(s->m_dm), s->lx, b);
   // sweeps in reverse
-  const dh::HydroK h1 = hydro_at(s, pl.a0), h2 = hydro_at(s, pl.ah);
   for (int k = 2; k >= 0; --k) {
-    dh::launch_sweep_vjp(st, T.q[1 + k], s->lq, s->lq2, s->lh, n, pl.axes[k],
-                         static_cast<float>(pl.dt), h1, h2);
+    dh::launch_sweep_vjp(st, T.q[1 + k], s->lq, s->lq2, s->lh, b, sp.axes[k]);
     std::swap(s->lq, s->lq2);
   }
   // drift: x1 = x0 + p_half dt / a_h^2
-  dh::launch_axpy(st, s->lp, s->lx, static_cast<float>(pl.dt / (pl.ah * pl.ah)), 3 * np);
+  dh::launch_axpy(st, s->lp, s->lx, 1.0f, 3 * np, 3 * np, 3 * np, true, b);
   // opening gas kick with phi_n
-  dh::launch_grad(st, T.phi0, s->g4b, n);
-  dh::launch_gas_kick_vjp(st, T.q[0], s->g4b, h, s->lq, s->lg, n);
-  dh::launch_grad_vjp(st, s->lg, nullptr, s->lphi, n);
+  dh::launch_grad(st, T.phi0, s->g4b, b);
+  dh::launch_gas_kick_vjp(st, T.q[0], s->g4b, s->lq, s->lg, b);
+  dh::launch_grad_vjp(st, s->lg, nullptr, s->lphi, b);
 }
 
 // Adjoint of the opening dark-matter kick of the first step (x0, phi0 of its tape entry)
 void finish_first_kick(dh_sim* s, const TapeStep& T) {
-  const int n = s->n;
-  const float h = static_cast<float>(0.5 * T.plan.dt);
+  const Batch b = batch(s, tab_of(s, T.plan));
   hipStream_t st = s->st;
-  dh::launch_grad(st, T.phi0, s->g4b, n);
-  dh::launch_fill(st, s->lg, 0.0f, 3 * s->nc);
-  sort_particles(s, T.x0);
-  dh::launch_gather_sorted(st, s->bins, s->lp, n);
-  dh::launch_deposit_vec(st, s->bins, h, s->lg, n);
-  dh::launch_kick_vjp_pos(st, s->g4b, T.x0, s->lp, h, s->lx, n);
-  dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi, n);
+  dh::launch_grad(st, T.phi0, s->g4b, b);
+  dh::launch_fill(st, s->lg, 0.0f, 3 * s->nc * s->S);
+  sort_particles(s, T.x0, b);
+  dh::launch_gather_sorted(st, s->bins, s->lp, b);
+  dh::launch_deposit_vec(st, s->bins, false, s->lg, b);
+  dh::launch_kick_vjp_pos(st, s->g4b, T.x0, s->lp, false, s->lx, b);
+  dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi, b);
 }
 
 // Adjoint of the initial conditions: lq, lx, lp, lphi at a_init -> d_grad_white
@@ -464,35 +632,44 @@ void ic_vjp(dh_sim* s, float* d_grad_white) {
   const long long nc = s->nc;
   hipStream_t st = s->st;
   const double ai = s->cfg.a_init;
+  const Batch all = batch(s, nullptr);
+  std::fill(s->a.begin(), s->a.end(), ai);
+  const Batch b0 = batch(s, state_table(s));
   // phi_0 = Poisson(rho_gas + m_dm CIC(x) - 1)
-  poisson(s, s->lphi, s->ldelta, ai);
-  dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc);
+  poisson(s, s->lphi, s->ldelta, b0);
+  dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc, 5 * nc, nc, false, all);
   // positions of the initial particles are recomputed from psi
   const double vfac = ai * ai * s->cosmo.E(ai) * s->cosmo.growth_rate(ai);
-  dh::launch_ic_particles(st, s->psi, s->pos, s->fscratch, static_cast<float>(vfac), n);
-  dh::launch_deposit_vjp_pos(st, s->ldelta, s->pos, static_cast<float>(s->m_dm), s->lx, n);
+  dh::launch_ic_particles(st, s->psi, s->pos, s->fscratch, static_cast<float>(vfac), all);
+  dh::launch_deposit_vjp_pos(st, s->ldelta, s->pos, static_cast<float>(s->m_dm), s->lx, all);
   // gas: rho = f_b CIC(x), m = rho p(q), Et = a^2 rho (e_init + |p/a|^2/2)
-  dh::launch_fill(st, s->lpsi, 0.0f, 3 * nc);
+  dh::launch_fill(st, s->lpsi, 0.0f, 3 * nc * s->S);
   dh::launch_ic_gas_vjp(st, s->cic, s->psi, s->lq, static_cast<float>(s->f_b),
                         static_cast<float>(vfac), static_cast<float>(ai),
-                        static_cast<float>(s->e_init), s->lcic, s->lpsi, n);
-  dh::launch_deposit_vjp_pos(st, s->lcic, s->pos, 1.0f, s->lx, n);
+                        static_cast<float>(s->e_init), s->lcic, s->lpsi, all);
+  dh::launch_deposit_vjp_pos(st, s->lcic, s->pos, 1.0f, s->lx, all);
   // x = q + psi, p = vfac psi
-  dh::launch_axpy(st, s->lpsi, s->lx, 1.0f, 3 * nc);
-  dh::launch_axpy(st, s->lpsi, s->lp, static_cast<float>(vfac), 3 * nc);
+  dh::launch_axpy(st, s->lpsi, s->lx, 1.0f, 3 * nc, 3 * nc, 3 * nc, false, all);
+  dh::launch_axpy(st, s->lpsi, s->lp, static_cast<float>(vfac), 3 * nc, 3 * nc, 3 * nc, false,
+                  all);
   // psi_j = IFFT(i k_j T(k)/k^2 FFT(w)) -> lambda_w = sum_j IFFT(-i k_j T/k^2 FFT(lambda_psi_j))
   const double d = s->cosmo.growth(ai);
   const double amp = s->amp * d * d / std::pow(s->cfg.box / n, 3.0);
   for (int j = 0; j < 3; ++j) {
-    dh::fft_forward_xy(st, s->lpsi + j * nc, s->spec, s->tw, n);
-    dh::fft_zpass_ic(st, s->spec, s->spec2, s->tw, n, j, true, amp, s->cfg.omega_m * s->cfg.h,
-                     s->cfg.n_s, n / s->cfg.box, true, false, j > 0);
+    dh::fft_forward_xy(st, s->lpsi + j * nc, s->spec, s->tw, all, 3 * nc);
+    dh::fft_zpass_ic(st, s->spec, s->spec2, s->tw, j, true, amp, s->cfg.omega_m * s->cfg.h,
+                     s->cfg.n_s, n / s->cfg.box, true, false, j > 0, all);
   }
-  dh::fft_zpass_inverse(st, s->spec2, s->tw, n);
-  dh::fft_inverse_yx(st, s->spec2, d_grad_white, s->tw, n, 1.0f);
+  dh::fft_zpass_inverse(st, s->spec2, s->tw, all);
+  dh::fft_inverse_yx(st, s->spec2, d_grad_white, s->tw, 1.0f, all);
 }
 
 bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+bool params_ok(const dh_params* p) {
+  return p->eps_sf >= 0 && p->delta_c > 0 && p->t_c > 0 && p->w_rho > 0 && p->w_t > 0 &&
+         p->e0 >= 0;
+}
 
 }  // namespace
 
@@ -519,6 +696,8 @@ void dh_config_default(dh_config* c) {
   c->tau = 0.1;
   c->sf_seed = 102;
   c->ckpt_every = 16;
+  c->closure = DH_CLOSURE_PLAIN;
+  c->batch = 1;
 }
 
 void dh_params_default(dh_params* p) {
@@ -537,7 +716,9 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
   if (!cfg || !out) return DH_E_INVAL;
   *out = nullptr;
   const int n = cfg->n;
-  if (!pow2(n) || n < 16 || n > 256) return DH_E_INVAL;
+  if (!pow2(n) || n < 16 || n > 256 || cfg->batch < 1 || cfg->batch > 4096) return DH_E_INVAL;
+  const int S = cfg->batch;
+  if (static_cast<long long>(n) * n * n * S > (1LL << 31)) return DH_E_INVAL;
   if (!(cfg->omega_m > 0 && cfg->omega_m < 1 && cfg->omega_b > 0 && cfg->omega_b < cfg->omega_m &&
         cfg->box > 0 && cfg->a_init > 0 && cfg->a_init < 1 && cfg->cfl > 0 && cfg->dlna_max > 0 &&
         cfg->gamma > 1 && cfg->tau > 0 && cfg->ckpt_every >= 1 && cfg->subgrid >= 0 &&
@@ -549,7 +730,9 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
   int rc = guarded(s.get(), [&]() -> int {
     s->cfg = *cfg;
     dh_params_default(&s->prm);
+    s->sprm.assign(S, s->prm);
     s->n = n;
+    s->S = S;
     s->nc = static_cast<long long>(n) * n * n;
     s->np = s->nc;
     s->nck = static_cast<long long>(n) * n * (n / 2 + 1);
@@ -563,7 +746,12 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
                  (s->vel_unit * 1e3) * (s->vel_unit * 1e3);
     s->e_init = cfg->t_init / s->t_per_e;
     s->e_floor = cfg->t_floor / s->t_per_e;
-    const long long nc = s->nc, np = s->np;
+    s->t.assign(S, 0.0);
+    s->a.assign(S, cfg->a_init);
+    s->recorded.assign(S, {});
+    s->replay.assign(S, {});
+    s->replay_pos.assign(S, 0);
+    const long long nc = s->nc * S, np = s->np * S;
     s->q = s->alloc<float>(5 * nc);
     s->q2 = s->alloc<float>(5 * nc);
     s->pos = s->alloc<float>(3 * np);
@@ -574,8 +762,8 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
     s->cic = s->alloc<float>(nc);
     s->psi = s->alloc<float>(3 * nc);
     s->fscratch = s->alloc<float>(3 * np);
-    s->spec = s->alloc<float2>(s->nck);
-    s->spec2 = s->alloc<float2>(s->nck);
+    s->spec = s->alloc<float2>(s->nck * S);
+    s->spec2 = s->alloc<float2>(s->nck * S);
     s->tw = s->alloc<float2>(n / 2);
     s->bins.key = s->alloc<uint32_t>(np);
     s->bins.rank = s->alloc<uint32_t>(np);
@@ -587,17 +775,22 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
     s->bins.sval = s->alloc<float4>(np);
     s->g4 = s->alloc<float4>(nc);
     s->g4b = s->alloc<float4>(nc);
-    s->cfl_red = s->alloc<double>(dh::cfl_blocks(n) + 1);
-    s->red_blocks = dh::sum_blocks(nc);
-    s->red = s->alloc<double>(8LL * s->red_blocks + 8);
-    s->red_out = s->alloc<double>(16);
+    s->cfl_red = s->alloc<double>(static_cast<long long>(dh::cfl_blocks(n)) * S + 1);
+    s->red_blocks = dh::sum_blocks(s->nc);
+    s->red = s->alloc<double>(8LL * s->red_blocks * S + 8);
+    s->red_out = s->alloc<double>(8LL * S + 16);
+    s->d_acur = s->alloc<double>(S);
+    s->cur_tab = s->alloc<StepScal>(S);
+    s->stage_tab = s->alloc<StepScal>(1);
     if (cfg->closure == DH_CLOSURE_MLP) {
       s->mlp_theta = s->alloc<float>(dh::mlp::kParams);
       s->mlp_packed = s->alloc<uint4>(static_cast<long long>(dh::mlp::kPackedBytes / sizeof(uint4)));
     }
     void* hp = nullptr;
-    DH_HIP(hipHostMalloc(&hp, 16 * sizeof(double), hipHostMallocDefault));
+    DH_HIP(hipHostMalloc(&hp, (8 * S + 16) * sizeof(double), hipHostMallocDefault));
     s->host_out = static_cast<double*>(hp);
+    DH_HIP(hipHostMalloc(&hp, S * sizeof(StepScal), hipHostMallocDefault));
+    s->hstage = static_cast<StepScal*>(hp);
     std::vector<float2> tw;
     dh::fft_make_twiddles(n, tw);
     DH_HIP(hipMemcpy(s->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
@@ -616,6 +809,8 @@ int dh_destroy(dh_sim* s) {
   (void)hipDeviceSynchronize();
   for (void* p : s->allocs) (void)hipFree(p);
   if (s->host_out) (void)hipHostFree(s->host_out);
+  if (s->hstage) (void)hipHostFree(s->hstage);
+  if (s->htabs) (void)hipHostFree(s->htabs);
   delete s;
   return DH_OK;
 }
@@ -628,9 +823,16 @@ int dh_set_stream(dh_sim* s, void* stream) {
 
 int dh_set_params(dh_sim* s, const dh_params* p) {
   if (!s || !p) return DH_E_INVAL;
-  if (!(p->eps_sf >= 0 && p->delta_c > 0 && p->t_c > 0 && p->w_rho > 0 && p->w_t > 0 && p->e0 >= 0))
-    return fail(s, DH_E_INVAL, "non-physical parameters");
+  if (!params_ok(p)) return fail(s, DH_E_INVAL, "non-physical parameters");
   s->prm = *p;
+  s->sprm.assign(s->S, *p);
+  return DH_OK;
+}
+
+int dh_set_sample_params(dh_sim* s, int32_t sample, const dh_params* p) {
+  if (!s || !p || sample < 0 || sample >= s->S) return DH_E_INVAL;
+  if (!params_ok(p)) return fail(s, DH_E_INVAL, "non-physical parameters");
+  s->sprm[sample] = *p;
   return DH_OK;
 }
 
@@ -651,9 +853,12 @@ int dh_set_closure(dh_sim* s, const float* h_theta) {
 int dh_init_from_seed(dh_sim* s, uint64_t seed) {
   if (!s) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
-    dh::launch_white_noise(s->st, s->delta, static_cast<uint32_t>(seed & 0xFFFFFFFFull),
-                           static_cast<uint32_t>(seed >> 32), s->n);
-    copy_d2d(s, s->fscratch, s->delta, s->nc);
+    for (int i = 0; i < s->S; ++i) {
+      const uint64_t k = seed + static_cast<uint64_t>(i);
+      dh::launch_white_noise(s->st, s->fscratch + s->nc * i,
+                             static_cast<uint32_t>(k & 0xFFFFFFFFull),
+                             static_cast<uint32_t>(k >> 32), s->n);
+    }
     initial_conditions(s, s->fscratch);
     s->have_forward = false;
     return DH_OK;
@@ -672,14 +877,15 @@ int dh_init_from_noise(dh_sim* s, const float* d_white) {
 int dh_step(dh_sim* s, double* dt_out, double* a_out) {
   if (!s) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
-    double dt = 0;
-    int rc = step_once(s, -1.0, nullptr, &dt);
+    StepPlan sp;
+    bool moved = false;
+    int rc = step_once(s, -1.0, false, &sp, &moved);
     if (rc) return rc;
     s->have_forward = false;
-    const double v = current_speed(s);   // also validates the new state
-    if (!std::isfinite(v)) return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
-    if (dt_out) *dt_out = dt;
-    if (a_out) *a_out = s->a;
+    if (!all_finite(current_speed(s)))   // also validates the new state
+      return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
+    if (dt_out) *dt_out = moved ? sp.smp[0].dt : 0.0;
+    if (a_out) *a_out = s->a[0];
     return DH_OK;
   });
 }
@@ -689,9 +895,11 @@ int dh_run_to(dh_sim* s, double a_final, int32_t* nsteps_out) {
   return guarded(s, [&]() -> int {
     const double t_end = s->cosmo.t_of_a(a_final);
     int count = 0;
-    while (s->t < t_end * (1.0 - 1e-12)) {
-      int rc = step_once(s, t_end, nullptr, nullptr);
+    for (;;) {
+      bool moved = false;
+      int rc = step_once(s, t_end, false, nullptr, &moved);
       if (rc) return rc;
+      if (!moved) break;
       ++count;
     }
     s->have_forward = false;
@@ -702,39 +910,60 @@ int dh_run_to(dh_sim* s, double a_final, int32_t* nsteps_out) {
 
 int dh_set_schedule(dh_sim* s, const double* dts, int32_t n) {
   if (!s || n < 0 || (n > 0 && !dts)) return DH_E_INVAL;
-  s->replay.assign(dts, dts + n);
-  s->replay_pos = 0;
+  for (int i = 0; i < s->S; ++i) {
+    s->replay[i].assign(dts, dts + n);
+    s->replay_pos[i] = 0;
+  }
+  return DH_OK;
+}
+
+int dh_set_sample_schedule(dh_sim* s, int32_t sample, const double* dts, int32_t n) {
+  if (!s || sample < 0 || sample >= s->S || n < 0 || (n > 0 && !dts)) return DH_E_INVAL;
+  s->replay[sample].assign(dts, dts + n);
+  s->replay_pos[sample] = 0;
+  return DH_OK;
+}
+
+int dh_get_sample_schedule(const dh_sim* s, int32_t sample, double* dts, int32_t cap,
+                           int32_t* n_out) {
+  if (!s || sample < 0 || sample >= s->S || cap < 0 || (cap > 0 && !dts)) return DH_E_INVAL;
+  const std::vector<double>& r = s->recorded[sample];
+  const int32_t n = static_cast<int32_t>(r.size());
+  for (int32_t i = 0; i < std::min(n, cap); ++i) dts[i] = r[i];
+  if (n_out) *n_out = n;
   return DH_OK;
 }
 
 int dh_get_schedule(const dh_sim* s, double* dts, int32_t cap, int32_t* n_out) {
-  if (!s) return DH_E_INVAL;
-  const int32_t n = static_cast<int32_t>(s->recorded.size());
-  for (int32_t i = 0; i < std::min(n, cap); ++i) dts[i] = s->recorded[i];
-  if (n_out) *n_out = n;
-  return DH_OK;
+  return dh_get_sample_schedule(s, 0, dts, cap, n_out);
 }
 
 int dh_get_field(dh_sim* s, dh_field f, float* d_out) {
   if (!s || !d_out) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
+    const long long nc = s->nc, S = s->S;
     switch (f) {
-      case DH_FIELD_Q: copy_d2d(s, d_out, s->q, 5 * s->nc); break;
-      case DH_FIELD_RHO: copy_d2d(s, d_out, s->q, s->nc); break;
-      case DH_FIELD_POS: copy_d2d(s, d_out, s->pos, 3 * s->np); break;
-      case DH_FIELD_MOM: copy_d2d(s, d_out, s->mom, 3 * s->np); break;
-      case DH_FIELD_STAR: copy_d2d(s, d_out, s->star, s->nc); break;
+      case DH_FIELD_Q: copy_d2d(s, d_out, s->q, 5 * nc * S); break;
+      case DH_FIELD_RHO:
+        for (int i = 0; i < S; ++i) copy_d2d(s, d_out + nc * i, s->q + 5 * nc * i, nc);
+        break;
+      case DH_FIELD_POS: copy_d2d(s, d_out, s->pos, 3 * s->np * S); break;
+      case DH_FIELD_MOM: copy_d2d(s, d_out, s->mom, 3 * s->np * S); break;
+      case DH_FIELD_STAR: copy_d2d(s, d_out, s->star, nc * S); break;
       case DH_FIELD_PHI:
         if (!s->phi_valid) refresh_potential(s);
-        copy_d2d(s, d_out, s->phi, s->nc);
+        copy_d2d(s, d_out, s->phi, nc * S);
         break;
       case DH_FIELD_TEMP:
-        dh::launch_temperature(s->st, s->q, static_cast<float>(s->a), static_cast<float>(s->e_floor),
-                               static_cast<float>(s->t_per_e), d_out, s->nc);
+        for (int i = 0; i < S; ++i)
+          dh::launch_temperature(s->st, s->q + 5 * nc * i, static_cast<float>(s->a[i]),
+                                 static_cast<float>(s->e_floor), static_cast<float>(s->t_per_e),
+                                 d_out + nc * i, nc);
         break;
       case DH_FIELD_FLUX:
-        dh::launch_flux_field(s->st, s->q, s->prm.A, s->prm.beta, static_cast<float>(1.0 / s->f_b),
-                              d_out, s->nc);
+        for (int i = 0; i < S; ++i)
+          dh::launch_flux_field(s->st, s->q + 5 * nc * i, s->prm.A, s->prm.beta,
+                                static_cast<float>(1.0 / s->f_b), d_out + nc * i, nc);
         break;
       default: return fail(s, DH_E_INVAL, "unknown field");
     }
@@ -745,15 +974,19 @@ int dh_get_field(dh_sim* s, dh_field f, float* d_out) {
 int dh_set_field(dh_sim* s, dh_field f, const float* d_in) {
   if (!s || !d_in) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
+    const long long nc = s->nc, S = s->S;
     switch (f) {
-      case DH_FIELD_Q: copy_d2d(s, s->q, d_in, 5 * s->nc); s->phi_valid = false; break;
-      case DH_FIELD_RHO: copy_d2d(s, s->q, d_in, s->nc); s->phi_valid = false; break;
-      case DH_FIELD_POS: copy_d2d(s, s->pos, d_in, 3 * s->np); s->phi_valid = false; break;
-      case DH_FIELD_MOM: copy_d2d(s, s->mom, d_in, 3 * s->np); break;
-      case DH_FIELD_STAR: copy_d2d(s, s->star, d_in, s->nc); break;
+      case DH_FIELD_Q: copy_d2d(s, s->q, d_in, 5 * nc * S); s->phi_valid = false; break;
+      case DH_FIELD_RHO:
+        for (int i = 0; i < S; ++i) copy_d2d(s, s->q + 5 * nc * i, d_in + nc * i, nc);
+        s->phi_valid = false;
+        break;
+      case DH_FIELD_POS: copy_d2d(s, s->pos, d_in, 3 * s->np * S); s->phi_valid = false; break;
+      case DH_FIELD_MOM: copy_d2d(s, s->mom, d_in, 3 * s->np * S); break;
+      case DH_FIELD_STAR: copy_d2d(s, s->star, d_in, nc * S); break;
       case DH_FIELD_PHI:
-        copy_d2d(s, s->phi, d_in, s->nc);
-        dh::launch_grad(s->st, s->phi, s->g4, s->n);
+        copy_d2d(s, s->phi, d_in, nc * S);
+        dh::launch_grad(s->st, s->phi, s->g4, batch(s, nullptr));
         s->phi_valid = true;
         break;
       default: return fail(s, DH_E_INVAL, "field cannot be set");
@@ -775,16 +1008,25 @@ int dh_refresh_potential(dh_sim* s) {
 
 int dh_get_time(const dh_sim* s, double* a, double* t, int32_t* step) {
   if (!s) return DH_E_INVAL;
-  if (a) *a = s->a;
-  if (t) *t = s->t;
+  if (a) *a = s->a[0];
+  if (t) *t = s->t[0];
   if (step) *step = s->step;
+  return DH_OK;
+}
+
+int dh_get_sample_times(const dh_sim* s, double* a, double* t) {
+  if (!s) return DH_E_INVAL;
+  for (int i = 0; i < s->S; ++i) {
+    if (a) a[i] = s->a[i];
+    if (t) t[i] = s->t[i];
+  }
   return DH_OK;
 }
 
 int dh_set_time(dh_sim* s, double a, int32_t step) {
   if (!s || !(a > 0) || step < 0) return DH_E_INVAL;
-  s->a = a;
-  s->t = s->cosmo.t_of_a(a);
+  std::fill(s->a.begin(), s->a.end(), a);
+  std::fill(s->t.begin(), s->t.end(), s->cosmo.t_of_a(a));
   s->step = step;
   s->phi_valid = false;
   state_changed(s);
@@ -795,24 +1037,26 @@ int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_
   if (!s || !d_white || !(a_final > s->cfg.a_init)) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
     initial_conditions(s, d_white);
-    s->replay_pos = 0;
     const double t_end = s->cosmo.t_of_a(a_final);
     const int K = s->cfg.ckpt_every;
     size_t nck = 0;
     int count = 0;
-    const bool replaying = !s->replay.empty();
-    while (s->t < t_end * (1.0 - 1e-12)) {
-      if (replaying && s->replay_pos >= s->replay.size()) break;   // schedule fully replayed
+    s->fwd_plans.clear();
+    for (;;) {
       if (count % K == 0) {
         if (nck == s->ckpts.size()) s->ckpts.push_back(Ckpt{});
         save_ckpt(s, s->ckpts[nck++]);
       }
-      int rc = step_once(s, t_end, nullptr, nullptr);
+      StepPlan sp;
+      bool moved = false;
+      int rc = step_once(s, t_end, true, &sp, &moved);
       if (rc) return rc;
+      if (!moved) break;
+      s->fwd_plans.push_back(sp);
       ++count;
     }
-    const double v = current_speed(s);
-    if (!std::isfinite(v)) return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
+    if (!all_finite(current_speed(s)))
+      return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
     s->fwd_steps = count;
     s->have_forward = true;
     s->have_loss = false;
@@ -826,13 +1070,14 @@ int dh_loss(dh_sim* s, const float* d_target, double* loss_out) {
   return guarded(s, [&]() -> int {
     const int nb = s->red_blocks;
     dh::launch_loss_partial(s->st, s->q, d_target, s->prm.A, s->prm.beta,
-                            static_cast<float>(1.0 / s->f_b), s->red, nb, s->nc);
-    dh::launch_reduce_sum(s->st, s->red, nb, nb, 1, s->red_out);
-    DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, sizeof(double), hipMemcpyDeviceToHost, s->st));
+                            static_cast<float>(1.0 / s->f_b), s->red, batch(s, nullptr));
+    dh::launch_reduce_sum(s->st, s->red, nb, nb, s->S, s->red_out);
+    DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, s->S * sizeof(double), hipMemcpyDeviceToHost,
+                          s->st));
     sync(s);
-    *loss_out = s->host_out[0] / static_cast<double>(s->nc);
-    if (!s->loss_target) s->loss_target = s->alloc<float>(s->nc);
-    copy_d2d(s, s->loss_target, d_target, s->nc);
+    for (int i = 0; i < s->S; ++i) loss_out[i] = s->host_out[i] / static_cast<double>(s->nc);
+    if (!s->loss_target) s->loss_target = s->alloc<float>(s->nc * s->S);
+    copy_d2d(s, s->loss_target, d_target, s->nc * s->S);
     s->have_loss = s->have_forward;
     return DH_OK;
   });
@@ -843,94 +1088,110 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
   if (!s->have_forward) return fail(s, DH_E_STATE, "dh_backward needs a preceding dh_forward");
   if (!d_grad_rho && !s->have_loss) return fail(s, DH_E_STATE, "dh_backward without d_grad_rho needs dh_loss");
   return guarded(s, [&]() -> int {
-    const int n = s->n;
+    const int S = s->S;
     const long long nc = s->nc, np = s->np;
     const int nsteps = s->fwd_steps;
     const int K = s->cfg.ckpt_every;
     if (!s->lq) {
-      s->lq = s->alloc<float>(5 * nc);
-      s->lq2 = s->alloc<float>(5 * nc);
-      s->lh = s->alloc<float>(5 * nc);
-      s->lx = s->alloc<float>(3 * np);
-      s->lp = s->alloc<float>(3 * np);
-      s->lphi = s->alloc<float>(nc);
-      s->lphi2 = s->alloc<float>(nc);
-      s->lg = s->alloc<float>(3 * nc);
-      s->ldelta = s->alloc<float>(nc);
-      s->lpsi = s->alloc<float>(3 * nc);
-      s->lcic = s->alloc<float>(nc);
+      s->lq = s->alloc<float>(5 * nc * S);
+      s->lq2 = s->alloc<float>(5 * nc * S);
+      s->lh = s->alloc<float>(5 * nc * S);
+      s->lx = s->alloc<float>(3 * np * S);
+      s->lp = s->alloc<float>(3 * np * S);
+      s->lphi = s->alloc<float>(nc * S);
+      s->lphi2 = s->alloc<float>(nc * S);
+      s->lg = s->alloc<float>(3 * nc * S);
+      s->ldelta = s->alloc<float>(nc * S);
+      s->lpsi = s->alloc<float>(3 * nc * S);
+      s->lcic = s->alloc<float>(nc * S);
+    } else if (s->lh == nullptr) {
+      s->lh = s->alloc<float>(5 * nc * S);
     }
     if (s->param_cap < nsteps + 2) {
       if (s->param_steps) s->release(s->param_steps);
+      s->param_steps = nullptr;
       s->param_cap = nsteps + 2;
-      s->param_steps = s->alloc<double>(2LL * s->param_cap);
+      s->param_steps = s->alloc<double>(2LL * S * s->param_cap);
     }
+    // dark-matter kick factors of the reverse pass: h of the step plus h of the same
+    // sample's next step (0 after its last)
+    for (int k = 0; k < nsteps; ++k) {
+      const StepPlan& sp = s->fwd_plans[k];
+      StepScal* h = s->htabs + static_cast<size_t>(sp.slot) * S;
+      for (int i = 0; i < S; ++i) {
+        if (!sp.smp[i].active) continue;
+        const bool next = k + 1 < nsteps && s->fwd_plans[k + 1].smp[i].active;
+        const double hn = next ? 0.5 * s->fwd_plans[k + 1].smp[i].dt : 0.0;
+        h[i].h_dm = static_cast<float>(0.5 * sp.smp[i].dt + hn);
+      }
+    }
+    if (nsteps > 0)
+      DH_HIP(hipMemcpyAsync(s->tabs, s->htabs,
+                            static_cast<size_t>(s->fwd_plans.back().slot + 1) * S * sizeof(StepScal),
+                            hipMemcpyHostToDevice, s->st));
     // final state adjoint
-    dh::launch_fill(s->st, s->lq, 0.0f, 5 * nc);
-    dh::launch_fill(s->st, s->lx, 0.0f, 3 * np);
-    dh::launch_fill(s->st, s->lp, 0.0f, 3 * np);
-    dh::launch_fill(s->st, s->lphi, 0.0f, nc);
-    double gA = 0.0, gB = 0.0;
+    dh::launch_fill(s->st, s->lq, 0.0f, 5 * nc * S);
+    dh::launch_fill(s->st, s->lx, 0.0f, 3 * np * S);
+    dh::launch_fill(s->st, s->lp, 0.0f, 3 * np * S);
+    dh::launch_fill(s->st, s->lphi, 0.0f, nc * S);
+    std::vector<double> gA(S, 0.0), gB(S, 0.0);
     if (d_grad_rho) {
-      copy_d2d(s, s->lq, d_grad_rho, nc);
+      for (int i = 0; i < S; ++i) copy_d2d(s, s->lq + 5 * nc * i, d_grad_rho + nc * i, nc);
     } else {
       const int nb = s->red_blocks;
       dh::launch_loss_vjp(s->st, s->q, s->loss_target, s->prm.A, s->prm.beta,
-                          static_cast<float>(1.0 / s->f_b), s->lq, s->red, nb, nc);
-      dh::launch_reduce_sum(s->st, s->red, nb, nb, 2, s->red_out);
-      DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+                          static_cast<float>(1.0 / s->f_b), s->lq, s->red, batch(s, nullptr));
+      dh::launch_reduce_sum(s->st, s->red, nb, nb, 2 * S, s->red_out);
+      DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, 2 * S * sizeof(double),
+                            hipMemcpyDeviceToHost, s->st));
       sync(s);
-      gA = s->host_out[0];
-      gB = s->host_out[1];
+      for (int i = 0; i < S; ++i) {
+        gA[i] = s->host_out[i];
+        gB[i] = s->host_out[S + i];
+      }
     }
     // segments in reverse
     const int nseg = (nsteps + K - 1) / K;
-    if (s->tape.size() < static_cast<size_t>(std::min(K, nsteps))) {
-      const size_t want = static_cast<size_t>(std::min(K, nsteps));
-      while (s->tape.size() < want) {
-        s->tape.push_back(TapeStep{});
-        alloc_tape_entry(s, s->tape.back());
-      }
+    const size_t want = static_cast<size_t>(std::min(K, nsteps));
+    while (s->tape.size() < want) {
+      s->tape.push_back(TapeStep{});
+      alloc_tape_entry(s, s->tape.back());
     }
     // keep the forward's final state to restore it afterwards
     Ckpt final_state{};
     save_ckpt(s, final_state);
-    const std::vector<double> sched = s->recorded;
-    dh::launch_fill(s->st, reinterpret_cast<float*>(s->param_steps), 0.0f, 4LL * s->param_cap);
-    float h_next = 0.0f;
+    dh::launch_fill(s->st, reinterpret_cast<float*>(s->param_steps), 0.0f,
+                    4LL * S * s->param_cap);
     for (int g = nseg - 1; g >= 0; --g) {
       load_ckpt(s, s->ckpts[g]);
       const int s0 = g * K, s1 = std::min(nsteps, s0 + K);
-      for (int k = s0; k < s1; ++k) do_step(s, make_plan(s, sched[k]), &s->tape[k - s0]);
-      for (int k = s1 - 1; k >= s0; --k) {
-        step_vjp(s, s->tape[k - s0], k, h_next);
-        h_next = static_cast<float>(0.5 * sched[k]);
-      }
+      for (int k = s0; k < s1; ++k) do_step(s, s->fwd_plans[k], &s->tape[k - s0]);
+      for (int k = s1 - 1; k >= s0; --k) step_vjp(s, s->tape[k - s0]);
     }
     if (nsteps > 0) finish_first_kick(s, s->tape[0]);
     ic_vjp(s, d_grad_white);
     // restore the final state of the forward run
     load_ckpt(s, final_state);
-    s->release(final_state.q);
-    s->release(final_state.pos);
-    s->release(final_state.mom);
-    s->release(final_state.star);
-    s->release(final_state.phi);
+    release_ckpt(s, final_state);
     // parameter gradients: fixed-order host sum of the per-step FP64 partials
-    std::vector<double> ps(2 * static_cast<size_t>(nsteps));
+    std::vector<double> ps(2 * static_cast<size_t>(S) * (nsteps > 0 ? nsteps : 1));
     if (nsteps > 0)
-      DH_HIP(hipMemcpyAsync(ps.data(), s->param_steps, ps.size() * sizeof(double),
+      DH_HIP(hipMemcpyAsync(ps.data(), s->param_steps, 2 * static_cast<size_t>(S) * nsteps *
+                                                           sizeof(double),
                             hipMemcpyDeviceToHost, s->st));
     sync(s);
-    double ge = 0.0, gd = 0.0;
-    for (int k = 0; k < nsteps; ++k) {
-      ge += ps[2 * k];
-      gd += ps[2 * k + 1];
+    for (int i = 0; i < S; ++i) {
+      double ge = 0.0, gd = 0.0;
+      for (int k = 0; k < nsteps; ++k) {
+        const size_t slot = static_cast<size_t>(s->fwd_plans[k].slot);
+        ge += ps[2 * S * slot + i];
+        gd += ps[2 * S * slot + S + i];
+      }
+      grad_params[4 * i + 0] = gA[i];
+      grad_params[4 * i + 1] = gB[i];
+      grad_params[4 * i + 2] = ge;
+      grad_params[4 * i + 3] = gd;
     }
-    grad_params[0] = gA;
-    grad_params[1] = gB;
-    grad_params[2] = ge;
-    grad_params[3] = gd;
     return DH_OK;
   });
 }
@@ -939,12 +1200,16 @@ int dh_conservation(dh_sim* s, double* out) {
   if (!s || !out) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
     const int nb = s->red_blocks;
-    dh::launch_conservation_partial(s->st, s->q, s->mom, s->red, nb, s->nc);
-    dh::launch_reduce_sum(s->st, s->red, nb, nb, 8, s->red_out);
-    DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s->st));
-    sync(s);
-    for (int k = 0; k < 8; ++k) out[k] = s->host_out[k];
-    for (int k = 5; k < 8; ++k) out[k] *= s->m_dm;
+    for (int i = 0; i < s->S; ++i) {
+      dh::launch_conservation_partial(s->st, s->q + 5 * s->nc * i, s->mom + 3 * s->np * i, s->red,
+                                      nb, s->nc);
+      dh::launch_reduce_sum(s->st, s->red, nb, nb, 8, s->red_out);
+      DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                            s->st));
+      sync(s);
+      for (int k = 0; k < 8; ++k) out[8 * i + k] = s->host_out[k];
+      for (int k = 5; k < 8; ++k) out[8 * i + k] *= s->m_dm;
+    }
     return DH_OK;
   });
 }
@@ -953,8 +1218,12 @@ int dh_stage_sweep(dh_sim* s, const float* d_q_in, float* d_q_out, int32_t axis,
                    double a1, double a2) {
   if (!s || !d_q_in || !d_q_out || axis < 0 || axis > 2 || d_q_in == d_q_out) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
-    dh::launch_sweep(s->st, d_q_in, d_q_out, s->n, axis, static_cast<float>(dt), hydro_at(s, a1),
-                     hydro_at(s, a2));
+    StepScal e{};
+    e.active = 1;
+    e.dt = static_cast<float>(dt);
+    e.h1 = hydro_at(s, a1);
+    e.h2 = hydro_at(s, a2);
+    dh::launch_sweep(s->st, d_q_in, d_q_out, Batch{s->n, 1, stage_table(s, e)}, axis);
     return DH_OK;
   });
 }
@@ -963,9 +1232,14 @@ int dh_stage_sweep_vjp(dh_sim* s, const float* d_q_in, const float* d_lam_out, f
                        int32_t axis, double dt, double a1, double a2) {
   if (!s || !d_q_in || !d_lam_out || !d_lam_in || axis < 0 || axis > 2) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
-    if (!s->lh) s->lh = s->alloc<float>(5 * s->nc);
-    dh::launch_sweep_vjp(s->st, d_q_in, d_lam_out, d_lam_in, s->lh, s->n, axis,
-                         static_cast<float>(dt), hydro_at(s, a1), hydro_at(s, a2));
+    if (!s->lh) s->lh = s->alloc<float>(5 * s->nc * s->S);
+    StepScal e{};
+    e.active = 1;
+    e.dt = static_cast<float>(dt);
+    e.h1 = hydro_at(s, a1);
+    e.h2 = hydro_at(s, a2);
+    dh::launch_sweep_vjp(s->st, d_q_in, d_lam_out, d_lam_in, s->lh,
+                         Batch{s->n, 1, stage_table(s, e)}, axis);
     return DH_OK;
   });
 }
@@ -973,7 +1247,10 @@ int dh_stage_sweep_vjp(dh_sim* s, const float* d_q_in, const float* d_lam_out, f
 int dh_stage_poisson(dh_sim* s, const float* d_delta, float* d_phi, double a) {
   if (!s || !d_delta || !d_phi || !(a > 0)) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
-    poisson(s, d_delta, d_phi, a);
+    StepScal e{};
+    e.active = 1;
+    e.green = green_at(s, a);
+    poisson(s, d_delta, d_phi, Batch{s->n, 1, stage_table(s, e)});
     return DH_OK;
   });
 }
@@ -981,8 +1258,10 @@ int dh_stage_poisson(dh_sim* s, const float* d_delta, float* d_phi, double a) {
 int dh_stage_deposit(dh_sim* s, const float* d_rho_gas, const float* d_pos, float* d_delta) {
   if (!s || !d_rho_gas || !d_pos || !d_delta) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
-    sort_particles(s, d_pos);
-    dh::launch_deposit(s->st, s->bins, d_rho_gas, static_cast<float>(s->m_dm), -1.0f, d_delta, s->n);
+    const Batch one{s->n, 1, nullptr};
+    sort_particles(s, d_pos, one);
+    dh::launch_deposit(s->st, s->bins, d_rho_gas, s->nc, static_cast<float>(s->m_dm), -1.0f,
+                       d_delta, one);
     return DH_OK;
   });
 }
@@ -990,14 +1269,14 @@ int dh_stage_deposit(dh_sim* s, const float* d_rho_gas, const float* d_pos, floa
 int dh_stage_readout(dh_sim* s, const float* d_phi, const float* d_pos, float* d_g) {
   if (!s || !d_phi || !d_pos || !d_g) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
-    dh::launch_grad(s->st, d_phi, s->g4b, s->n);
-    dh::launch_readout_g(s->st, s->g4b, d_pos, d_g, s->n);
+    const Batch one{s->n, 1, nullptr};
+    dh::launch_grad(s->st, d_phi, s->g4b, one);
+    dh::launch_readout_g(s->st, s->g4b, d_pos, d_g, one);
     return DH_OK;
   });
 }
 
 const char* dh_last_error(const dh_sim* s) { return s ? s->err.c_str() : "null handle"; }
-
 const char* dh_strerror(int code) {
   switch (code) {
     case DH_OK: return "ok";

@@ -7,79 +7,13 @@
 
 namespace dh {
 
-// ---- hydro (k_hydro.hip)
-void launch_sweep(hipStream_t st, const float* qin, float* qout, int n, int axis, float dt,
-                  const HydroK& h1, const HydroK& h2);
-// lam_h_scratch: 5 n^3 floats, used by the y/z adjoints
-void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
-                      float* lam_h_scratch, int n, int axis, float dt, const HydroK& h1,
-                      const HydroK& h2);
-
-// ---- particle mesh (k_pm.hip)
-struct Bins {          // counting sort of particles by CIC base cell
-  uint32_t* key;       // [np] base cell of each particle
-  uint32_t* rank;      // [np] scratch: arrival rank inside its bin
-  uint32_t* count;     // [nc]
-  uint32_t* start;     // [nc + 1] exclusive prefix sum of count
-  uint32_t* sorted;    // [np] particle ids, bins in cell order, ids ascending inside a bin
-  uint32_t* block_sums;  // [scan blocks]
-  float4* spos;        // [np] positions in bin order
-  float4* sval;        // [np] a particle vector field in bin order (adjoint deposits)
-};
-size_t scan_block_count(long long nc);
-void launch_keys(hipStream_t st, const float* pos, uint32_t* key, int n);
-// sort by b.key (already computed for pos) and gather pos into bin order
-void launch_sort(hipStream_t st, const Bins& b, const float* pos, int n);
-// b.sval = v[3][np] in bin order
-void launch_gather_sorted(hipStream_t st, const Bins& b, const float* v, int n);
-// out = rho_gas + m_dm * CIC(sorted positions) + offset; rho_gas may be null (then 0)
-void launch_deposit(hipStream_t st, const Bins& b, const float* rho_gas, float m_dm, float offset,
-                    float* out, int n);
-// out_accum[3][nc] += scale * CIC deposit of b.sval
-void launch_deposit_vec(hipStream_t st, const Bins& b, float scale, float* out_accum, int n);
-// g4 = (-grad phi, 0) by two-point central differences
-void launch_grad(hipStream_t st, const float* phi, float4* g4, int n);
-// g at particles: out[3][np] = CIC read-out of g4
-void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float* out, int n);
-// opening kick + drift (+ keys; optional copies of the new momenta and positions), closing kick
-void launch_kick_drift(hipStream_t st, const float4* g4, float* pos, float* mom, uint32_t* key,
-                       float h_kick, float drift_fac, float* mom_copy, float* pos_copy, int n);
-void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom, float h_kick,
-                 int n);
-// adjoint of p' = p + h g(x) with respect to x: lam_x += h sum_c dw/dx (g_c . lam_p')
-void launch_kick_vjp_pos(hipStream_t st, const float4* g4, const float* pos,
-                         const float* lam_p, float h_kick, float* lam_x, int n);
-// adjoint of the deposit wrt positions: lam_x += mass sum_c lam_delta_c dw_c/dx
-void launch_deposit_vjp_pos(hipStream_t st, const float* lam_delta, const float* pos,
-                            float mass, float* lam_x, int n);
-// y += a x, elementwise
-void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long count);
-// lam_phi = (adjoint of the central-difference gradient) lam_g + lam_phi_in
-void launch_grad_vjp(hipStream_t st, const float* lam_g, const float* lam_phi_in, float* lam_phi,
-                     int n);
-
-// ---- FFT and spectral operators (k_fft.hip)
-enum SpecOp { kOpGreen = 0, kOpIcDisp = 1, kOpIcDispT = 2 };
-void fft_make_twiddles(int n, std::vector<float2>& tw);
-// real field -> half spectrum transformed along x and y (z pass separate)
-void fft_forward_xy(hipStream_t st, const float* in, float2* spec, const float2* tw, int n);
-// inverse along y, then c2r along x with a scale
-void fft_inverse_yx(hipStream_t st, float2* spec, float* out, const float2* tw, int n, float scale);
-// z pass: forward, Green's function (green = -(3 Om/2a)/N^3), inverse
-void fft_zpass_green(hipStream_t st, float2* spec, const float2* tw, int n, float green);
-void fft_zpass_forward(hipStream_t st, const float2* in, float2* out, const float2* tw, int n);
-void fft_zpass_inverse(hipStream_t st, float2* spec, const float2* tw, int n);
-// z pass with the initial-condition operator i k_axis T(k)/k^2 / N^3 (or its conjugate)
-void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* tw, int n,
-                  int axis, bool transpose, double amp, double om_h, double n_s, double kphys,
-                  bool forward_first, bool inverse_after, bool accumulate);
-
-// ---- pointwise / reductions (k_point.hip)
-// q_out = q_in after the half kick (q_out may equal q_in)
-void launch_gas_kick(hipStream_t st, const float* q_in, float* q_out, const float4* g4, float h,
-                     int n);
-void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4, float h,
-                         float* lam_q, float* lam_g, int n);
+// ---- batches
+// A handle holds S independent samples of n^3 cells and n^3 particles, stacked: every array
+// is S consecutive copies of its single-sample layout.  A launch covers all samples (the
+// sample is blockIdx.y, blockIdx.z in the pencil passes).  The per-sample scalars of a step
+// come from a device table of S entries; a sample whose entry is not active is left as it
+// is (kernels that write a separate output copy their input there, the identity of the
+// step).  tab == nullptr: every sample active, no step scalars used.
 struct SourceArgs {   // FP64: the source term is evaluated in double precision
   double a, dt, inv_rho_mean, omega_b, efloor, t_per_e, e0_code;
   double eps_sf, delta_c, t_c, w_rho, w_t, tau;
@@ -87,32 +21,142 @@ struct SourceArgs {   // FP64: the source term is evaluated in double precision
   uint32_t seed_lo, seed_hi, step;
   const uint4* mlp;   // packed closure network (dh_mlp.h): pi0 from the network; null: plain
 };
-// closing pass of a step, from q_in (may equal q) into q: gas half kick with g4, optional copy of the kicked state to
-// q_kicked (tape), source term (if a.mode != 0), FP64 block maxima of the CFL speed of the
-// result at scale factor a.a into block_max[cfl_blocks(n)]
-void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4* g4, float h,
-                       float* star, const SourceArgs& a, float* q_kicked, double gamma,
-                       double* block_max, int n);
-// adjoint of the source term; accumulates dL/d(eps_sf, delta_c) partials per block
-void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, const SourceArgs& a,
-                       double* partials, int nblocks_out, int n);
+struct StepScal {
+  SourceArgs src;     // source term at a(t+dt)
+  HydroK h1, h2;      // sweep stages at a(t) and a(t+dt/2)
+  float dt, h;        // step length, half kick
+  float drift;        // dt / a(t+dt/2)^2
+  float green;        // Poisson: -(3 Om / 2 a(t+dt)) / N^3
+  float h_dm;         // reverse pass: dark-matter kick factor of this step and the next
+  int active;
+};
+struct Batch {
+  int n;                 // cells per side of one sample
+  int S;                 // samples
+  const StepScal* tab;   // device table [S] or null
+  long long nc() const { return static_cast<long long>(n) * n * n; }
+};
+
+__device__ __forceinline__ bool sample_active(const StepScal* tab, int smp) {
+  return tab == nullptr || tab[smp].active != 0;
+}
+
+// ---- hydro (k_hydro.hip): one sweep with dt, h1, h2 of the table (tab required)
+void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis);
+// lam_h_scratch: 5 n^3 floats per sample, used by the y/z adjoints
+void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
+                      float* lam_h_scratch, const Batch& b, int axis);
+
+// ---- particle mesh (k_pm.hip)
+// Keys are global bins: sample * n^3 + CIC base cell, so one counting sort orders the
+// particles of every sample.
+struct Bins {          // counting sort of particles by CIC base cell
+  uint32_t* key;       // [S np] bin of each particle
+  uint32_t* rank;      // [S np] scratch: arrival rank inside its bin
+  uint32_t* count;     // [S nc]
+  uint32_t* start;     // [S nc + 1] exclusive prefix sum of count
+  uint32_t* sorted;    // [S np] particle ids, bins in order, ids ascending inside a bin
+  uint32_t* block_sums;  // [scan blocks]
+  float4* spos;        // [S np] positions in bin order
+  float4* sval;        // [S np] a particle vector field in bin order (adjoint deposits)
+};
+size_t scan_block_count(long long nbins);
+void launch_keys(hipStream_t st, const float* pos, uint32_t* key, const Batch& b);
+// sort by bins.key (already computed for pos) and gather pos into bin order
+void launch_sort(hipStream_t st, const Bins& bins, const float* pos, const Batch& b);
+// bins.sval = v[3][np] (per sample) in bin order
+void launch_gather_sorted(hipStream_t st, const Bins& bins, const float* v, const Batch& b);
+// out = rho_gas + m_dm * CIC(sorted positions) + offset; rho_gas (sample s at
+// rho_gas + s * rho_stride: 5 n^3 for the density row of Q) may be null (then 0)
+void launch_deposit(hipStream_t st, const Bins& bins, const float* rho_gas,
+                    long long rho_stride, float m_dm, float offset, float* out, const Batch& b);
+// out_accum[3][nc] += scale * CIC deposit of bins.sval, scale = h (merged: h_dm) of the table
+void launch_deposit_vec(hipStream_t st, const Bins& bins, bool merged, float* out_accum,
+                        const Batch& b);
+// g4 = (-grad phi, 0) by two-point central differences
+void launch_grad(hipStream_t st, const float* phi, float4* g4, const Batch& b);
+// g at particles: out[3][np] = CIC read-out of g4
+void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float* out,
+                      const Batch& b);
+// opening kick (h) + drift (drift) + keys; optional copies of the new momenta and positions
+void launch_kick_drift(hipStream_t st, const float4* g4, float* pos, float* mom, uint32_t* key,
+                       float* mom_copy, float* pos_copy, const Batch& b);
+// closing kick p += h g(x)
+void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom, const Batch& b);
+// adjoint of p' = p + k g(x) with respect to x: lam_x += k sum_c dw/dx (g_c . lam_p'), with
+// k = h (merged: h_dm) of the table
+void launch_kick_vjp_pos(hipStream_t st, const float4* g4, const float* pos,
+                         const float* lam_p, bool merged, float* lam_x, const Batch& b);
+// adjoint of the deposit wrt positions: lam_x += mass sum_c lam_delta_c dw_c/dx
+void launch_deposit_vjp_pos(hipStream_t st, const float* lam_delta, const float* pos,
+                            float mass, float* lam_x, const Batch& b);
+// y[s] += a x[s] over `count` values per sample (strides ys, xs); a times the table's drift
+// factor if by_drift
+void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long count,
+                 long long ys, long long xs, bool by_drift, const Batch& b);
+// lam_phi = (adjoint of the central-difference gradient) lam_g + lam_phi_in
+void launch_grad_vjp(hipStream_t st, const float* lam_g, const float* lam_phi_in, float* lam_phi,
+                     const Batch& b);
+
+// ---- FFT and spectral operators (k_fft.hip)
+enum SpecOp { kOpGreen = 0, kOpIcDisp = 1, kOpIcDispT = 2 };
+void fft_make_twiddles(int n, std::vector<float2>& tw);
+// real field -> half spectrum transformed along x and y (z pass separate); sample s of the
+// input starts at in + s * in_stride (default n^3)
+void fft_forward_xy(hipStream_t st, const float* in, float2* spec, const float2* tw,
+                    const Batch& b, long long in_stride = -1);
+// inverse along y, then c2r along x with a scale; sample s of the output at out + s out_stride
+void fft_inverse_yx(hipStream_t st, float2* spec, float* out, const float2* tw, float scale,
+                    const Batch& b, long long out_stride = -1);
+// z pass: forward, Green's function (the table's green), inverse
+void fft_zpass_green(hipStream_t st, float2* spec, const float2* tw, const Batch& b);
+void fft_zpass_forward(hipStream_t st, const float2* in, float2* out, const float2* tw,
+                       const Batch& b);
+void fft_zpass_inverse(hipStream_t st, float2* spec, const float2* tw, const Batch& b);
+// z pass with the initial-condition operator i k_axis T(k)/k^2 / N^3 (or its conjugate)
+void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* tw, int axis,
+                  bool transpose, double amp, double om_h, double n_s, double kphys,
+                  bool forward_first, bool inverse_after, bool accumulate, const Batch& b);
+
+// ---- pointwise / reductions (k_point.hip)
+// q_out = q_in after the half kick h (q_out may equal q_in)
+void launch_gas_kick(hipStream_t st, const float* q_in, float* q_out, const float4* g4,
+                     const Batch& b);
+void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4, float* lam_q,
+                         float* lam_g, const Batch& b);
+// closing pass of a step, from q_in (may equal q) into q: gas half kick with g4, optional
+// copy of the kicked state to q_kicked (tape), source term (if src.mode != 0; with the
+// learned closure if `closure`), FP64 block maxima of the CFL speed of the result at src.a
+// into block_max[S][cfl_blocks(n)]
+void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4* g4,
+                       float* star, float* q_kicked, double gamma, double* block_max,
+                       const Batch& b, bool closure);
+// adjoint of the source term; dL/d(eps_sf, delta_c) partials per block:
+// partials[(v S + s) nb + block], nb = source_vjp_blocks(n)
+void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, double* partials,
+                       const Batch& b, bool closure);
 int source_vjp_blocks(int n);
-// FP64 block maxima of the CFL speed max_d (|U_d| + c_s)/a
+// FP64 block maxima of the CFL speed max_d (|U_d| + c_s)/a with a = a_cur[s]:
+// block_max[s][cfl_blocks(n)]
 int cfl_blocks(int n);
-void launch_cfl_partial(hipStream_t st, const float* q, double a, double gamma, double efloor,
-                        double* block_max, int n);
-void launch_reduce_max(hipStream_t st, const double* in, int count, double* out);
+void launch_cfl_partial(hipStream_t st, const float* q, const double* a_cur, double gamma,
+                        double efloor, double* block_max, const Batch& b);
+// out[v] = max (or sum) of in[v * stride + 0..count), v < nvec
+void launch_reduce_max(hipStream_t st, const double* in, int count, int stride, int nvec,
+                       double* out);
 void launch_reduce_sum(hipStream_t st, const double* in, int count, int stride, int nvec,
                        double* out);
 int sum_blocks(long long count);
-// FP64 block sums of several fields: partial[v * nblocks + b]
+// FP64 block sums of several fields of one sample: partial[v * nblocks + b]
 void launch_conservation_partial(hipStream_t st, const float* q, const float* mom,
                                  double* partial, int nblocks, long long nc);
+// flux-field loss: partial[s nb + block], nb = sum_blocks(nc)
 void launch_loss_partial(hipStream_t st, const float* rho, const float* target, double A,
-                         double beta, float inv_rho_mean, double* partial, int nblocks,
-                         long long nc);
+                         double beta, float inv_rho_mean, double* partial, const Batch& b);
+// lam_rho = dL/drho (per sample, mean over the sample's cells); dL/d(A, beta) partials
+// [(v S + s) nb + block]
 void launch_loss_vjp(hipStream_t st, const float* rho, const float* target, double A, double beta,
-                     float inv_rho_mean, float* lam_rho, double* partial, int nblocks, long long nc);
+                     float inv_rho_mean, float* lam_rho, double* partial, const Batch& b);
 void launch_flux_field(hipStream_t st, const float* rho, double A, double beta,
                        float inv_rho_mean, float* out, long long nc);
 void launch_temperature(hipStream_t st, const float* q, float a, float efloor, float t_per_e,
@@ -120,14 +164,13 @@ void launch_temperature(hipStream_t st, const float* q, float a, float efloor, f
 void launch_white_noise(hipStream_t st, float* out, uint32_t seed_lo, uint32_t seed_hi, int n);
 // IC: particles from displacement and gas from the deposit
 void launch_ic_particles(hipStream_t st, const float* psi, float* pos, float* mom, float vfac,
-                         int n);
+                         const Batch& b);
 void launch_ic_gas(hipStream_t st, const float* cic, const float* psi, float* q, float f_b,
-                   float vfac, float a, float e_init, int n);
+                   float vfac, float a, float e_init, const Batch& b);
 void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const float* lam_q,
                        float f_b, float vfac, float a, float e_init, float* lam_cic,
-                       float* lam_psi, int n);
+                       float* lam_psi, const Batch& b);
 void launch_fill(hipStream_t st, float* p, float v, long long count);
-void launch_check_finite(hipStream_t st, const float* q, long long nc, int* flag);
 
 // ---- learned closure network (k_mlp.hip; layout in dh_mlp.h)
 struct MlpSampleArgs {   // ranges of the training states (natural logs where named ln)

@@ -58,18 +58,24 @@ __device__ __forceinline__ void load_tw(float2* sh_tw, const float2* tw, int n) 
   for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) sh_tw[i] = tw[i];
 }
 
+// Rows of all samples are consecutive (n^2 per sample); a block's rows lie in one sample.
 __global__ void __launch_bounds__(kFftThreads) x_r2c_kernel(const float* __restrict__ in,
                                                             float2* __restrict__ spec,
                                                             const float2* __restrict__ tw, int n,
-                                                            int logn) {
+                                                            int logn,
+                                                            const StepScal* __restrict__ tab,
+                                                            long long in_stride) {
   __shared__ float2 A[kRowTile], B[kRowTile];
   __shared__ float2 TW[128];
   const int rows = kRowTile / n;
   const int nh = n / 2 + 1;
   const long long row0 = static_cast<long long>(blockIdx.x) * rows;
+  const long long nn = static_cast<long long>(n) * n;
+  const int smp = static_cast<int>(row0 / nn);
+  if (!sample_active(tab, smp)) return;
+  const float* src = in + smp * in_stride + (row0 - smp * nn) * n;
   load_tw(TW, tw, n);
-  for (int t = threadIdx.x; t < rows * n; t += blockDim.x)
-    A[t] = make_float2(in[row0 * n + t], 0.0f);
+  for (int t = threadIdx.x; t < rows * n; t += blockDim.x) A[t] = make_float2(src[t], 0.0f);
   __syncthreads();
   float2* r = lds_fft<false>(A, B, n, logn, rows, n, TW);
   for (int t = threadIdx.x; t < rows * nh; t += blockDim.x) {
@@ -81,12 +87,18 @@ __global__ void __launch_bounds__(kFftThreads) x_r2c_kernel(const float* __restr
 __global__ void __launch_bounds__(kFftThreads) x_c2r_kernel(const float2* __restrict__ spec,
                                                             float* __restrict__ out,
                                                             const float2* __restrict__ tw, int n,
-                                                            int logn, float scale) {
+                                                            int logn, float scale,
+                                                            const StepScal* __restrict__ tab,
+                                                            long long out_stride) {
   __shared__ float2 A[kRowTile], B[kRowTile];
   __shared__ float2 TW[128];
   const int rows = kRowTile / n;
   const int nh = n / 2 + 1;
   const long long row0 = static_cast<long long>(blockIdx.x) * rows;
+  const long long nn = static_cast<long long>(n) * n;
+  const int smp = static_cast<int>(row0 / nn);
+  if (!sample_active(tab, smp)) return;
+  float* dst = out + smp * out_stride + (row0 - smp * nn) * n;
   load_tw(TW, tw, n);
   for (int t = threadIdx.x; t < rows * nh; t += blockDim.x) {
     const int rr = t / nh, k = t - rr * nh;
@@ -100,7 +112,7 @@ __global__ void __launch_bounds__(kFftThreads) x_c2r_kernel(const float2* __rest
   }
   __syncthreads();
   float2* r = lds_fft<true>(A, B, n, logn, rows, n, TW);
-  for (int t = threadIdx.x; t < rows * n; t += blockDim.x) out[row0 * n + t] = r[t].x * scale;
+  for (int t = threadIdx.x; t < rows * n; t += blockDim.x) dst[t] = r[t].x * scale;
 }
 
 struct OpArgs {
@@ -143,20 +155,27 @@ __device__ float2 apply_op(const OpArgs& o, int kx, int ky, int kz, int n, float
   return make_float2(-v.y * ff, v.x * ff);
 }
 
-// Pencil pass along AX (1 = y, 2 = z) over a tile of tk consecutive kx.
-// flags: 1 forward, 2 operator, 4 inverse, 8 accumulate into out.
+// Pencil pass along AX (1 = y, 2 = z) over a tile of tk consecutive kx of sample blockIdx.z.
+// flags: 1 forward, 2 operator, 4 inverse, 8 accumulate into out.  The Green's function
+// factor comes from the sample's step table when there is one.
 template <int AX>
 // in and out may alias (in-place passes): no __restrict__ on them
 __global__ void __launch_bounds__(kFftThreads) pencil_kernel(const float2* in, float2* out,
                                                              const float2* __restrict__ tw, int n,
                                                              int logn, int kTK, int flags,
-                                                             OpArgs op) {
+                                                             OpArgs op,
+                                                             const StepScal* __restrict__ tab) {
   extern __shared__ float2 sh[];
+  if (!sample_active(tab, blockIdx.z)) return;
+  if (tab && op.op == kOpGreen) op.green = tab[blockIdx.z].green;
   const int ps = n + 1;
   float2* A = sh;
   float2* B = sh + kTK * ps;
   float2* TW = sh + 2 * kTK * ps;
   const int nh = n / 2 + 1;
+  const long long slab = static_cast<long long>(n) * n * nh;
+  in += blockIdx.z * slab;
+  out += blockIdx.z * slab;
   const int kx0 = blockIdx.x * kTK;
   const int fixed = blockIdx.y;   // z for AX = 1, ky for AX = 2
   const long long line_stride = AX == 1 ? nh : static_cast<long long>(n) * nh;
@@ -214,19 +233,24 @@ size_t pencil_smem(int n, int tk) { return (2 * tk * (n + 1) + n / 2) * sizeof(f
 // kx columns per pencil block: 16 (128-byte rows) while the tile fits in 64 KB of LDS
 int pencil_tile(int n) { return pencil_smem(n, 16) <= 65536 ? 16 : 8; }
 
-void pencil(hipStream_t st, int ax, const float2* in, float2* out, const float2* tw, int n,
-            int flags, const OpArgs& op) {
+void pencil(hipStream_t st, int ax, const float2* in, float2* out, const float2* tw, int flags,
+            const OpArgs& op, const Batch& b) {
+  const int n = b.n;
   const int nh = n / 2 + 1;
   const int tk = pencil_tile(n);
-  dim3 grid((nh + tk - 1) / tk, n);
+  dim3 grid((nh + tk - 1) / tk, n, b.S);
   const size_t smem = pencil_smem(n, tk);
   if (ax == 1)
     hipLaunchKernelGGL(pencil_kernel<1>, grid, dim3(kFftThreads), smem, st, in, out, tw, n,
-                       ilog2(n), tk, flags, op);
+                       ilog2(n), tk, flags, op, b.tab);
   else
     hipLaunchKernelGGL(pencil_kernel<2>, grid, dim3(kFftThreads), smem, st, in, out, tw, n,
-                       ilog2(n), tk, flags, op);
+                       ilog2(n), tk, flags, op, b.tab);
   DH_LAUNCH_CHECK();
+}
+
+unsigned row_blocks(const Batch& b) {
+  return static_cast<unsigned>(static_cast<long long>(b.n) * b.n * b.S / (kRowTile / b.n));
 }
 
 }  // namespace
@@ -239,49 +263,51 @@ void fft_make_twiddles(int n, std::vector<float2>& tw) {
   }
 }
 
-void fft_forward_xy(hipStream_t st, const float* in, float2* spec, const float2* tw, int n) {
-  const long long rows = static_cast<long long>(n) * n;
-  hipLaunchKernelGGL(x_r2c_kernel, dim3(static_cast<unsigned>(rows / (kRowTile / n))),
-                     dim3(kFftThreads), 0, st, in, spec, tw, n, ilog2(n));
+void fft_forward_xy(hipStream_t st, const float* in, float2* spec, const float2* tw,
+                    const Batch& b, long long in_stride) {
+  hipLaunchKernelGGL(x_r2c_kernel, dim3(row_blocks(b)), dim3(kFftThreads), 0, st, in, spec, tw,
+                     b.n, ilog2(b.n), b.tab, in_stride < 0 ? b.nc() : in_stride);
   DH_LAUNCH_CHECK();
   OpArgs none{};
   none.op = -1;
-  pencil(st, 1, spec, spec, tw, n, 1, none);
+  pencil(st, 1, spec, spec, tw, 1, none, b);
 }
 
-void fft_inverse_yx(hipStream_t st, float2* spec, float* out, const float2* tw, int n, float scale) {
+void fft_inverse_yx(hipStream_t st, float2* spec, float* out, const float2* tw, float scale,
+                    const Batch& b, long long out_stride) {
   OpArgs none{};
   none.op = -1;
-  pencil(st, 1, spec, spec, tw, n, 4, none);
-  const long long rows = static_cast<long long>(n) * n;
-  hipLaunchKernelGGL(x_c2r_kernel, dim3(static_cast<unsigned>(rows / (kRowTile / n))),
-                     dim3(kFftThreads), 0, st, spec, out, tw, n, ilog2(n), scale);
+  pencil(st, 1, spec, spec, tw, 4, none, b);
+  hipLaunchKernelGGL(x_c2r_kernel, dim3(row_blocks(b)), dim3(kFftThreads), 0, st, spec, out, tw,
+                     b.n, ilog2(b.n), scale, b.tab, out_stride < 0 ? b.nc() : out_stride);
   DH_LAUNCH_CHECK();
 }
 
-void fft_zpass_green(hipStream_t st, float2* spec, const float2* tw, int n, float green) {
+void fft_zpass_green(hipStream_t st, float2* spec, const float2* tw, const Batch& b) {
+  if (!b.tab) throw ArgError("Poisson pass: step table required");
   OpArgs o{};
   o.op = kOpGreen;
-  o.green = green;
-  pencil(st, 2, spec, spec, tw, n, 1 | 2 | 4, o);
+  pencil(st, 2, spec, spec, tw, 1 | 2 | 4, o, b);
 }
 
-void fft_zpass_forward(hipStream_t st, const float2* in, float2* out, const float2* tw, int n) {
+void fft_zpass_forward(hipStream_t st, const float2* in, float2* out, const float2* tw,
+                       const Batch& b) {
   OpArgs none{};
   none.op = -1;
-  pencil(st, 2, in, out, tw, n, 1, none);
+  pencil(st, 2, in, out, tw, 1, none, b);
 }
 
-void fft_zpass_inverse(hipStream_t st, float2* spec, const float2* tw, int n) {
+void fft_zpass_inverse(hipStream_t st, float2* spec, const float2* tw, const Batch& b) {
   OpArgs none{};
   none.op = -1;
-  pencil(st, 2, spec, spec, tw, n, 4, none);
+  pencil(st, 2, spec, spec, tw, 4, none, b);
 }
 
 // IC displacement: out = op_axis(in) then inverse along z (in already transformed in x, y, z)
-void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* tw, int n,
-                  int axis, bool transpose, double amp, double om_h, double n_s, double kphys,
-                  bool forward_first, bool inverse_after, bool accumulate) {
+void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* tw, int axis,
+                  bool transpose, double amp, double om_h, double n_s, double kphys,
+                  bool forward_first, bool inverse_after, bool accumulate, const Batch& b) {
+  const int n = b.n;
   OpArgs o{};
   o.op = transpose ? kOpIcDispT : kOpIcDisp;
   o.axis = axis;
@@ -291,7 +317,7 @@ void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* t
   o.kphys = kphys;
   o.inv_n3 = 1.0 / (static_cast<double>(n) * n * n);
   const int flags = (forward_first ? 1 : 0) | 2 | (inverse_after ? 4 : 0) | (accumulate ? 8 : 0);
-  pencil(st, 2, in, out, tw, n, flags, o);
+  pencil(st, 2, in, out, tw, flags, o, b);
 }
 
 }  // namespace dh

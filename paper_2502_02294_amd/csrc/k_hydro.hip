@@ -31,6 +31,15 @@ constexpr int kRowThreads = 256;
 
 __device__ __forceinline__ int wrap(int j, int n) { return j & (n - 1); }
 
+// out = in over the cells [base, base + count) of all five components (inactive samples)
+__device__ __forceinline__ void copy_block(const float* __restrict__ in, float* __restrict__ out,
+                                           long long nc, long long base, int count, int tid,
+                                           int threads) {
+  for (int i = tid; i < count; i += threads)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c * nc + base + i] = in[c * nc + base + i];
+}
+
 // coefficients of the limited right-moving face flux FRf_m with respect to F^R at m-1, m, m+1
 __device__ __forceinline__ void face_r_coef(float fm1, float f0, float fp1, float& cm1, float& c0,
                                             float& cp1) {
@@ -59,13 +68,22 @@ __device__ __forceinline__ void call_split(int d, const float* q, const HydroK& 
 // ------------------------------------------------------------------------------- forward x
 __global__ void __launch_bounds__(kRowThreads) sweep_x_kernel(const float* __restrict__ qin,
                                                               float* __restrict__ qout, int n,
-                                                              long long nc, float dt, HydroK h1,
-                                                              HydroK h2) {
+                                                              long long nc,
+                                                              const StepScal* __restrict__ tab) {
   __shared__ float U[5][kRowCells];
   __shared__ float FR[5][kRowCells];
   __shared__ float FL[5][kRowCells];
   const long long base = static_cast<long long>(blockIdx.x) * kRowCells;
   const int tid = threadIdx.x;
+  const StepScal& sc = tab[blockIdx.y];
+  qin += blockIdx.y * 5 * nc;
+  qout += blockIdx.y * 5 * nc;
+  if (!sc.active) {
+    copy_block(qin, qout, nc, base, kRowCells, tid, kRowThreads);
+    return;
+  }
+  const float dt = sc.dt;
+  const HydroK h1 = sc.h1, h2 = sc.h2;
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
     U[c][tid] = qin[c * nc + base + tid];
@@ -143,7 +161,7 @@ template <int D>
 __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict__ qin,
                                                          float* __restrict__ qout, int n,
                                                          long long nc, int seg_len, int nseg,
-                                                         float dt, HydroK h1, HydroK h2) {
+                                                         const StepScal* __restrict__ tab) {
   const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<long long>(n) * n * nseg) return;
   const int x = static_cast<int>(t % n);
@@ -153,6 +171,19 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
                                 : static_cast<long long>(other) * n + x;
   const long long stride = D == 1 ? n : static_cast<long long>(n) * n;
   const int s = seg * seg_len;
+  const StepScal& sc = tab[blockIdx.y];
+  qin += blockIdx.y * 5 * nc;
+  qout += blockIdx.y * 5 * nc;
+  if (!sc.active) {
+    for (int i = 0; i < seg_len; ++i) {
+      const long long off = base + static_cast<long long>(s + i) * stride;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) qout[c * nc + off] = qin[c * nc + off];
+    }
+    return;
+  }
+  const float dt = sc.dt;
+  const HydroK h1 = sc.h1, h2 = sc.h2;
   const float hdt = 0.5f * dt;
 
   float ut[4][5];          // U at k-3 .. k
@@ -230,7 +261,7 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
 // --------------------------------------------------------------------------- adjoint x
 __global__ void __launch_bounds__(kRowThreads) sweep_x_vjp_kernel(
     const float* __restrict__ qin, const float* __restrict__ lam_out, float* __restrict__ lam_in,
-    int n, long long nc, float dt, HydroK h1, HydroK h2) {
+    int n, long long nc, const StepScal* __restrict__ tab) {
   __shared__ float U[5][kRowCells];
   __shared__ float L[5][kRowCells];
   __shared__ float FR[5][kRowCells];
@@ -238,6 +269,16 @@ __global__ void __launch_bounds__(kRowThreads) sweep_x_vjp_kernel(
   __shared__ float LH[5][kRowCells];
   const long long base = static_cast<long long>(blockIdx.x) * kRowCells;
   const int tid = threadIdx.x;
+  const StepScal& sc = tab[blockIdx.y];
+  qin += blockIdx.y * 5 * nc;
+  lam_out += blockIdx.y * 5 * nc;
+  lam_in += blockIdx.y * 5 * nc;
+  if (!sc.active) {
+    copy_block(lam_out, lam_in, nc, base, kRowCells, tid, kRowThreads);
+    return;
+  }
+  const float dt = sc.dt;
+  const HydroK h1 = sc.h1, h2 = sc.h2;
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
     U[c][tid] = qin[c * nc + base + tid];
@@ -367,9 +408,16 @@ __global__ void __launch_bounds__(256) vjp_walk_h_kernel(const float* __restrict
                                                          const float* __restrict__ lam_out,
                                                          float* __restrict__ lam_h, int n,
                                                          long long nc, int seg_len, int nseg,
-                                                         float dt, HydroK h1, HydroK h2) {
+                                                         const StepScal* __restrict__ tab) {
   const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<long long>(n) * n * nseg) return;
+  const StepScal& sc = tab[blockIdx.y];
+  if (!sc.active) return;
+  qin += blockIdx.y * 5 * nc;
+  lam_out += blockIdx.y * 5 * nc;
+  lam_h += blockIdx.y * 5 * nc;
+  const float dt = sc.dt;
+  const HydroK h1 = sc.h1, h2 = sc.h2;
   const int x = static_cast<int>(t % n);
   const int other = static_cast<int>((t / n) % n);
   const int seg = static_cast<int>(t / (static_cast<long long>(n) * n));
@@ -477,9 +525,22 @@ __global__ void __launch_bounds__(256) vjp_finish_kernel(const float* __restrict
                                                          const float* __restrict__ lam_out,
                                                          const float* __restrict__ lam_h,
                                                          float* __restrict__ lam_in, int n,
-                                                         long long nc, float dt, HydroK h1) {
+                                                         long long nc,
+                                                         const StepScal* __restrict__ tab) {
   const long long cell = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (cell >= nc) return;
+  const StepScal& sc = tab[blockIdx.y];
+  qin += blockIdx.y * 5 * nc;
+  lam_out += blockIdx.y * 5 * nc;
+  lam_h += blockIdx.y * 5 * nc;
+  lam_in += blockIdx.y * 5 * nc;
+  if (!sc.active) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) lam_in[c * nc + cell] = lam_out[c * nc + cell];
+    return;
+  }
+  const float dt = sc.dt;
+  const HydroK h1 = sc.h1;
   const int x = static_cast<int>(cell % n);
   const int y = static_cast<int>((cell / n) % n);
   const int z = static_cast<int>(cell / (static_cast<long long>(n) * n));
@@ -515,50 +576,54 @@ int pick_segment(int n) { return n >= 64 ? 64 : n; }
 
 }  // namespace
 
-void launch_sweep(hipStream_t st, const float* qin, float* qout, int n, int axis, float dt,
-                  const HydroK& h1, const HydroK& h2) {
-  const long long nc = static_cast<long long>(n) * n * n;
+void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis) {
+  const int n = b.n;
+  const long long nc = b.nc();
+  if (!b.tab) throw ArgError("sweep: step table required");
   if (axis == 0) {
     if (qin == qout) throw ArgError("sweep_x: in-place not supported");
-    hipLaunchKernelGGL(sweep_x_kernel, dim3(static_cast<unsigned>(nc / kRowCells)),
-                       dim3(kRowThreads), 0, st, qin, qout, n, nc, dt, h1, h2);
+    hipLaunchKernelGGL(sweep_x_kernel, dim3(static_cast<unsigned>(nc / kRowCells), b.S),
+                       dim3(kRowThreads), 0, st, qin, qout, n, nc, b.tab);
   } else {
     const int seg = pick_segment(n);
     const int nseg = n / seg;
     const long long threads = static_cast<long long>(n) * n * nseg;
+    const dim3 grid(blocks_for(threads, 256), b.S);
     if (axis == 1)
-      hipLaunchKernelGGL(sweep_walk_kernel<1>, dim3(blocks_for(threads, 256)), dim3(256), 0, st,
-                         qin, qout, n, nc, seg, nseg, dt, h1, h2);
+      hipLaunchKernelGGL(sweep_walk_kernel<1>, grid, dim3(256), 0, st, qin, qout, n, nc, seg,
+                         nseg, b.tab);
     else
-      hipLaunchKernelGGL(sweep_walk_kernel<2>, dim3(blocks_for(threads, 256)), dim3(256), 0, st,
-                         qin, qout, n, nc, seg, nseg, dt, h1, h2);
+      hipLaunchKernelGGL(sweep_walk_kernel<2>, grid, dim3(256), 0, st, qin, qout, n, nc, seg,
+                         nseg, b.tab);
   }
   DH_LAUNCH_CHECK();
 }
 
 void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
-                      float* lam_h_scratch, int n, int axis, float dt, const HydroK& h1,
-                      const HydroK& h2) {
-  const long long nc = static_cast<long long>(n) * n * n;
+                      float* lam_h_scratch, const Batch& b, int axis) {
+  const int n = b.n;
+  const long long nc = b.nc();
+  if (!b.tab) throw ArgError("sweep adjoint: step table required");
   if (axis == 0) {
-    hipLaunchKernelGGL(sweep_x_vjp_kernel, dim3(static_cast<unsigned>(nc / kRowCells)),
-                       dim3(kRowThreads), 0, st, qin, lam_out, lam_in, n, nc, dt, h1, h2);
+    hipLaunchKernelGGL(sweep_x_vjp_kernel, dim3(static_cast<unsigned>(nc / kRowCells), b.S),
+                       dim3(kRowThreads), 0, st, qin, lam_out, lam_in, n, nc, b.tab);
   } else {
     const int seg = pick_segment(n);
     const int nseg = n / seg;
     const long long threads = static_cast<long long>(n) * n * nseg;
+    const dim3 grid(blocks_for(threads, 256), b.S), grid2(blocks_for(nc, 256), b.S);
     if (axis == 1) {
-      hipLaunchKernelGGL(vjp_walk_h_kernel<1>, dim3(blocks_for(threads, 256)), dim3(256), 0, st,
-                         qin, lam_out, lam_h_scratch, n, nc, seg, nseg, dt, h1, h2);
+      hipLaunchKernelGGL(vjp_walk_h_kernel<1>, grid, dim3(256), 0, st, qin, lam_out,
+                         lam_h_scratch, n, nc, seg, nseg, b.tab);
       DH_LAUNCH_CHECK();
-      hipLaunchKernelGGL(vjp_finish_kernel<1>, dim3(blocks_for(nc, 256)), dim3(256), 0, st, qin,
-                         lam_out, lam_h_scratch, lam_in, n, nc, dt, h1);
+      hipLaunchKernelGGL(vjp_finish_kernel<1>, grid2, dim3(256), 0, st, qin, lam_out,
+                         lam_h_scratch, lam_in, n, nc, b.tab);
     } else {
-      hipLaunchKernelGGL(vjp_walk_h_kernel<2>, dim3(blocks_for(threads, 256)), dim3(256), 0, st,
-                         qin, lam_out, lam_h_scratch, n, nc, seg, nseg, dt, h1, h2);
+      hipLaunchKernelGGL(vjp_walk_h_kernel<2>, grid, dim3(256), 0, st, qin, lam_out,
+                         lam_h_scratch, n, nc, seg, nseg, b.tab);
       DH_LAUNCH_CHECK();
-      hipLaunchKernelGGL(vjp_finish_kernel<2>, dim3(blocks_for(nc, 256)), dim3(256), 0, st, qin,
-                         lam_out, lam_h_scratch, lam_in, n, nc, dt, h1);
+      hipLaunchKernelGGL(vjp_finish_kernel<2>, grid2, dim3(256), 0, st, qin, lam_out,
+                         lam_h_scratch, lam_in, n, nc, b.tab);
     }
   }
   DH_LAUNCH_CHECK();

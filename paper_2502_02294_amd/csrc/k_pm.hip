@@ -48,12 +48,18 @@ __device__ __forceinline__ float w1_of(float x) {
 
 __device__ __forceinline__ float wsel(float w1, int o) { return o ? w1 : 1.0f - w1; }
 
+// bin of particle i of sample s: s n^3 + CIC base cell
+__device__ __forceinline__ uint32_t bin_of(const Cic& c, int n, int smp, long long nc) {
+  return static_cast<uint32_t>(smp * nc + (c.i0[2] * n + c.i0[1]) * n + c.i0[0]);
+}
+
 __global__ void keys_kernel(const float* __restrict__ pos, uint32_t* __restrict__ key, int n,
                             long long np) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= np) return;
+  pos += blockIdx.y * 3 * np;
   const Cic c = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
-  key[i] = static_cast<uint32_t>((c.i0[2] * n + c.i0[1]) * n + c.i0[0]);
+  key[blockIdx.y * np + i] = bin_of(c, n, blockIdx.y, np);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, long long count) {
@@ -169,14 +175,18 @@ __global__ void bin_sort_kernel(const uint32_t* __restrict__ start, uint32_t* so
   }
 }
 
-// out[j] = (v[0][id], v[1][id], v[2][id], 0) for id = sorted[j]
+// out[j] = (v[0][id], v[1][id], v[2][id], 0) for id = sorted[j] (global particle index: sample
+// id >> lnp, particle id & (np - 1) of a per-sample [3][np] array)
 __global__ void gather_sorted_kernel(const uint32_t* __restrict__ sorted,
                                      const float* __restrict__ v, float4* __restrict__ out,
-                                     long long np) {
+                                     long long total, int lnp) {
   const long long j = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= np) return;
+  if (j >= total) return;
   const uint32_t id = sorted[j];
-  out[j] = make_float4(v[id], v[np + id], v[2 * np + id], 0.0f);
+  const long long np = 1LL << lnp;
+  const long long smp = id >> lnp, loc = id & (np - 1);
+  const float* vs = v + smp * 3 * np;
+  out[j] = make_float4(vs[loc], vs[np + loc], vs[2 * np + loc], 0.0f);
 }
 
 // ---------------------------------------------------------------------------- deposit
@@ -233,11 +243,15 @@ __device__ __forceinline__ void deposit_cell(const uint32_t* __restrict__ start,
 __global__ void __launch_bounds__(256) deposit_kernel(const uint32_t* __restrict__ start,
                                                       const float4* __restrict__ spos,
                                                       const float* __restrict__ rho_gas,
-                                                      float m_dm, float offset,
-                                                      float* __restrict__ out, int n) {
+                                                      long long rho_stride, float m_dm,
+                                                      float offset, float* __restrict__ out,
+                                                      int n, const StepScal* __restrict__ tab) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const long long nc = static_cast<long long>(n) * n * n;
-  if (c >= nc) return;
+  if (c >= nc || !sample_active(tab, blockIdx.y)) return;
+  start += blockIdx.y * nc;
+  if (rho_gas) rho_gas += blockIdx.y * rho_stride;
+  out += blockIdx.y * nc;
   const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
             iz = static_cast<int>(c / (static_cast<long long>(n) * n));
   float acc[3] = {0.0f, 0.0f, 0.0f};
@@ -249,11 +263,15 @@ __global__ void __launch_bounds__(256) deposit_kernel(const uint32_t* __restrict
 __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __restrict__ start,
                                                           const float4* __restrict__ spos,
                                                           const float4* __restrict__ sval,
-                                                          float scale, float* __restrict__ out,
-                                                          int n) {
+                                                          bool merged, float* __restrict__ out,
+                                                          int n, const StepScal* __restrict__ tab) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const long long nc = static_cast<long long>(n) * n * n;
-  if (c >= nc) return;
+  const StepScal& sc = tab[blockIdx.y];
+  if (c >= nc || !sc.active) return;
+  const float scale = merged ? sc.h_dm : sc.h;
+  start += blockIdx.y * nc;
+  out += blockIdx.y * 3 * nc;
   const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
             iz = static_cast<int>(c / (static_cast<long long>(n) * n));
   float acc[3] = {0.0f, 0.0f, 0.0f};
@@ -265,10 +283,13 @@ __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __rest
 
 // g4[c] = (g_x, g_y, g_z, 0),  g_d = -(phi[c + e_d] - phi[c - e_d]) / 2
 __global__ void __launch_bounds__(256) grad_kernel(const float* __restrict__ phi,
-                                                   float4* __restrict__ g4, int n) {
+                                                   float4* __restrict__ g4, int n,
+                                                   const StepScal* __restrict__ tab) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const long long nn = static_cast<long long>(n) * n, nc = nn * n;
-  if (c >= nc) return;
+  if (c >= nc || !sample_active(tab, blockIdx.y)) return;
+  phi += blockIdx.y * nc;
+  g4 += blockIdx.y * nc;
   const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
             iz = static_cast<int>(c / nn);
   const long long zo = static_cast<long long>(iz) * nn, yo = static_cast<long long>(iy) * n;
@@ -309,6 +330,9 @@ __global__ void __launch_bounds__(256) readout_g_kernel(const float4* __restrict
                                                         long long np) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= np) return;
+  g4 += blockIdx.y * np;
+  pos += blockIdx.y * 3 * np;
+  out += blockIdx.y * 3 * np;
   const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
   float g[3];
   readout_g(g4, w, n, g);
@@ -326,12 +350,22 @@ __device__ __forceinline__ float wrap_pos(float x, float fn) {
 __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restrict__ g4,
                                                          float* __restrict__ pos,
                                                          float* __restrict__ mom,
-                                                         uint32_t* __restrict__ key, float h,
-                                                         float drift_fac, float* __restrict__ mom_copy,
+                                                         uint32_t* __restrict__ key,
+                                                         float* __restrict__ mom_copy,
                                                          float* __restrict__ pos_copy, int n,
-                                                         long long np) {
+                                                         long long np,
+                                                         const StepScal* __restrict__ tab) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= np) return;
+  const StepScal& sc = tab[blockIdx.y];
+  if (i >= np || !sc.active) return;
+  const float h = sc.h, drift_fac = sc.drift;
+  const int smp = blockIdx.y;
+  g4 += smp * np;
+  pos += smp * 3 * np;
+  mom += smp * 3 * np;
+  key += smp * np;
+  if (mom_copy) mom_copy += smp * 3 * np;
+  if (pos_copy) pos_copy += smp * 3 * np;
   float x[3] = {pos[i], pos[np + i], pos[2 * np + i]};
   const Cic w = cic_of(x[0], x[1], x[2], n);
   float g[3];
@@ -347,15 +381,20 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
     if (pos_copy) pos_copy[d * np + i] = x[d];
   }
   const Cic w2 = cic_of(x[0], x[1], x[2], n);
-  key[i] = static_cast<uint32_t>((w2.i0[2] * n + w2.i0[1]) * n + w2.i0[0]);
+  key[i] = bin_of(w2, n, smp, np);
 }
 
 __global__ void __launch_bounds__(256) kick_kernel(const float4* __restrict__ g4,
                                                    const float* __restrict__ pos,
-                                                   float* __restrict__ mom, float h, int n,
-                                                   long long np) {
+                                                   float* __restrict__ mom, int n, long long np,
+                                                   const StepScal* __restrict__ tab) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= np) return;
+  const StepScal& sc = tab[blockIdx.y];
+  if (i >= np || !sc.active) return;
+  const float h = sc.h;
+  g4 += blockIdx.y * np;
+  pos += blockIdx.y * 3 * np;
+  mom += blockIdx.y * 3 * np;
   const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
   float g[3];
   readout_g(g4, w, n, g);
@@ -367,10 +406,17 @@ __global__ void __launch_bounds__(256) kick_kernel(const float4* __restrict__ g4
 __global__ void __launch_bounds__(256) kick_vjp_pos_kernel(const float4* __restrict__ g4,
                                                            const float* __restrict__ pos,
                                                            const float* __restrict__ lam_p,
-                                                           float h, float* __restrict__ lam_x,
-                                                           int n, long long np) {
+                                                           bool merged, float* __restrict__ lam_x,
+                                                           int n, long long np,
+                                                           const StepScal* __restrict__ tab) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= np) return;
+  const StepScal& sc = tab[blockIdx.y];
+  if (i >= np || !sc.active) return;
+  const float h = merged ? sc.h_dm : sc.h;
+  g4 += blockIdx.y * np;
+  pos += blockIdx.y * 3 * np;
+  lam_p += blockIdx.y * 3 * np;
+  lam_x += blockIdx.y * 3 * np;
   const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
   const float lp[3] = {lam_p[i], lam_p[np + i], lam_p[2 * np + i]};
   float acc[3] = {0.0f, 0.0f, 0.0f};
@@ -395,9 +441,13 @@ __global__ void __launch_bounds__(256) kick_vjp_pos_kernel(const float4* __restr
 __global__ void __launch_bounds__(256) deposit_vjp_pos_kernel(const float* __restrict__ lam_delta,
                                                               const float* __restrict__ pos,
                                                               float mass, float* __restrict__ lam_x,
-                                                              int n, long long np) {
+                                                              int n, long long np,
+                                                              const StepScal* __restrict__ tab) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= np) return;
+  if (i >= np || !sample_active(tab, blockIdx.y)) return;
+  lam_delta += blockIdx.y * np;
+  pos += blockIdx.y * 3 * np;
+  lam_x += blockIdx.y * 3 * np;
   const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
   float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -417,18 +467,25 @@ __global__ void __launch_bounds__(256) deposit_vjp_pos_kernel(const float* __res
 }
 
 __global__ void axpy_kernel(float* __restrict__ y, const float* __restrict__ x, float a,
-                            long long count) {
+                            long long count, long long ys, long long xs, bool by_drift,
+                            const StepScal* __restrict__ tab) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < count) y[i] += a * x[i];
+  if (i >= count || !sample_active(tab, blockIdx.y)) return;
+  const float f = by_drift ? a * tab[blockIdx.y].drift : a;
+  y[blockIdx.y * ys + i] += f * x[blockIdx.y * xs + i];
 }
 
 // lam_phi[c] = lam_phi_in[c] + sum_d (lam_g_d[c + e_d] - lam_g_d[c - e_d]) / 2
 __global__ void __launch_bounds__(256) grad_vjp_kernel(const float* __restrict__ lam_g,
                                                        const float* __restrict__ lam_phi_in,
-                                                       float* __restrict__ lam_phi, int n) {
+                                                       float* __restrict__ lam_phi, int n,
+                                                       const StepScal* __restrict__ tab) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const long long nn = static_cast<long long>(n) * n, nc = nn * n;
-  if (c >= nc) return;
+  if (c >= nc || !sample_active(tab, blockIdx.y)) return;
+  lam_g += blockIdx.y * 3 * nc;
+  if (lam_phi_in) lam_phi_in += blockIdx.y * nc;
+  lam_phi += blockIdx.y * nc;
   const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
             iz = static_cast<int>(c / nn);
   const long long zo = static_cast<long long>(iz) * nn, yo = static_cast<long long>(iy) * n;
@@ -443,118 +500,130 @@ __global__ void __launch_bounds__(256) grad_vjp_kernel(const float* __restrict__
 
 }  // namespace
 
-size_t scan_block_count(long long nc) { return static_cast<size_t>((nc + kScanTile - 1) / kScanTile); }
+size_t scan_block_count(long long nbins) {
+  return static_cast<size_t>((nbins + kScanTile - 1) / kScanTile);
+}
 
-void launch_keys(hipStream_t st, const float* pos, uint32_t* key, int n) {
-  const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(keys_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, pos, key, n, np);
+namespace {
+int log2_ll(long long v) {
+  int l = 0;
+  while ((1LL << l) < v) ++l;
+  return l;
+}
+dim3 per_sample(long long work, const Batch& b) { return dim3(blocks_for(work, 256), b.S); }
+}  // namespace
+
+void launch_keys(hipStream_t st, const float* pos, uint32_t* key, const Batch& b) {
+  const long long np = b.nc();
+  hipLaunchKernelGGL(keys_kernel, per_sample(np, b), dim3(256), 0, st, pos, key, b.n, np);
   DH_LAUNCH_CHECK();
 }
 
-void launch_sort(hipStream_t st, const Bins& b, const float* pos, int n) {
-  const long long nc = static_cast<long long>(n) * n * n, np = nc;
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.count, 0u, nc);
+void launch_sort(hipStream_t st, const Bins& bins, const float* pos, const Batch& b) {
+  const long long nbins = b.nc() * b.S, total = nbins;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(nbins, 256)), dim3(256), 0, st, bins.count,
+                     0u, nbins);
   DH_LAUNCH_CHECK();
-  hipLaunchKernelGGL(hist_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, b.key, b.count,
-                     b.rank, np);
+  hipLaunchKernelGGL(hist_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, st, bins.key,
+                     bins.count, bins.rank, total);
   DH_LAUNCH_CHECK();
-  const int nb = static_cast<int>(scan_block_count(nc));
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kScanThreads), 0, st, b.count,
-                     b.block_sums, nc);
+  const int nb = static_cast<int>(scan_block_count(nbins));
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kScanThreads), 0, st, bins.count,
+                     bins.block_sums, nbins);
   DH_LAUNCH_CHECK();
-  hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(kScanThreads), 0, st, b.block_sums, nb);
+  hipLaunchKernelGGL(scan_block_sums_kernel, dim3(1), dim3(kScanThreads), 0, st, bins.block_sums,
+                     nb);
   DH_LAUNCH_CHECK();
-  hipLaunchKernelGGL(scan_final_kernel, dim3(nb), dim3(kScanThreads), 0, st, b.count,
-                     b.block_sums, b.start, nc);
+  hipLaunchKernelGGL(scan_final_kernel, dim3(nb), dim3(kScanThreads), 0, st, bins.count,
+                     bins.block_sums, bins.start, nbins);
   DH_LAUNCH_CHECK();
-  hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, b.key, b.rank,
-                     b.start, b.sorted, np);
+  hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, st, bins.key,
+                     bins.rank, bins.start, bins.sorted, total);
   DH_LAUNCH_CHECK();
-  hipLaunchKernelGGL(bin_sort_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.start,
-                     b.sorted, nc);
+  hipLaunchKernelGGL(bin_sort_kernel, dim3(blocks_for(nbins, 256)), dim3(256), 0, st, bins.start,
+                     bins.sorted, nbins);
   DH_LAUNCH_CHECK();
-  hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, b.sorted,
-                     pos, b.spos, np);
-  DH_LAUNCH_CHECK();
-}
-
-void launch_gather_sorted(hipStream_t st, const Bins& b, const float* v, int n) {
-  const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, b.sorted,
-                     v, b.sval, np);
+  hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, st,
+                     bins.sorted, pos, bins.spos, total, log2_ll(b.nc()));
   DH_LAUNCH_CHECK();
 }
 
-void launch_deposit(hipStream_t st, const Bins& b, const float* rho_gas, float m_dm, float offset,
-                    float* out, int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(deposit_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.start, b.spos,
-                     rho_gas, m_dm, offset, out, n);
+void launch_gather_sorted(hipStream_t st, const Bins& bins, const float* v, const Batch& b) {
+  const long long total = b.nc() * b.S;
+  hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, st,
+                     bins.sorted, v, bins.sval, total, log2_ll(b.nc()));
   DH_LAUNCH_CHECK();
 }
 
-void launch_deposit_vec(hipStream_t st, const Bins& b, float scale, float* out_accum, int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(deposit_vec_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, b.start,
-                     b.spos, b.sval, scale, out_accum, n);
+void launch_deposit(hipStream_t st, const Bins& bins, const float* rho_gas,
+                    long long rho_stride, float m_dm, float offset, float* out, const Batch& b) {
+  hipLaunchKernelGGL(deposit_kernel, per_sample(b.nc(), b), dim3(256), 0, st, bins.start,
+                     bins.spos, rho_gas, rho_stride, m_dm, offset, out, b.n, b.tab);
   DH_LAUNCH_CHECK();
 }
 
-void launch_grad(hipStream_t st, const float* phi, float4* g4, int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(grad_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, phi, g4, n);
+void launch_deposit_vec(hipStream_t st, const Bins& bins, bool merged, float* out_accum,
+                        const Batch& b) {
+  if (!b.tab) throw ArgError("deposit_vec: step table required");
+  hipLaunchKernelGGL(deposit_vec_kernel, per_sample(b.nc(), b), dim3(256), 0, st, bins.start,
+                     bins.spos, bins.sval, merged, out_accum, b.n, b.tab);
   DH_LAUNCH_CHECK();
 }
 
-void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float* out, int n) {
-  const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(readout_g_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, g4, pos, out,
-                     n, np);
+void launch_grad(hipStream_t st, const float* phi, float4* g4, const Batch& b) {
+  hipLaunchKernelGGL(grad_kernel, per_sample(b.nc(), b), dim3(256), 0, st, phi, g4, b.n, b.tab);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float* out,
+                      const Batch& b) {
+  hipLaunchKernelGGL(readout_g_kernel, per_sample(b.nc(), b), dim3(256), 0, st, g4, pos, out, b.n,
+                     b.nc());
   DH_LAUNCH_CHECK();
 }
 
 void launch_kick_drift(hipStream_t st, const float4* g4, float* pos, float* mom, uint32_t* key,
-                       float h_kick, float drift_fac, float* mom_copy, float* pos_copy, int n) {
-  const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(kick_drift_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, g4, pos, mom,
-                     key, h_kick, drift_fac, mom_copy, pos_copy, n, np);
+                       float* mom_copy, float* pos_copy, const Batch& b) {
+  if (!b.tab) throw ArgError("kick_drift: step table required");
+  hipLaunchKernelGGL(kick_drift_kernel, per_sample(b.nc(), b), dim3(256), 0, st, g4, pos, mom, key,
+                     mom_copy, pos_copy, b.n, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
-void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom, float h_kick,
-                 int n) {
-  const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(kick_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, g4, pos, mom,
-                     h_kick, n, np);
+void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom, const Batch& b) {
+  if (!b.tab) throw ArgError("kick: step table required");
+  hipLaunchKernelGGL(kick_kernel, per_sample(b.nc(), b), dim3(256), 0, st, g4, pos, mom, b.n,
+                     b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
 void launch_kick_vjp_pos(hipStream_t st, const float4* g4, const float* pos, const float* lam_p,
-                         float h_kick, float* lam_x, int n) {
-  const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(kick_vjp_pos_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, g4, pos,
-                     lam_p, h_kick, lam_x, n, np);
+                         bool merged, float* lam_x, const Batch& b) {
+  if (!b.tab) throw ArgError("kick adjoint: step table required");
+  hipLaunchKernelGGL(kick_vjp_pos_kernel, per_sample(b.nc(), b), dim3(256), 0, st, g4, pos, lam_p,
+                     merged, lam_x, b.n, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
 void launch_deposit_vjp_pos(hipStream_t st, const float* lam_delta, const float* pos, float mass,
-                            float* lam_x, int n) {
-  const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(deposit_vjp_pos_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st,
-                     lam_delta, pos, mass, lam_x, n, np);
+                            float* lam_x, const Batch& b) {
+  hipLaunchKernelGGL(deposit_vjp_pos_kernel, per_sample(b.nc(), b), dim3(256), 0, st, lam_delta,
+                     pos, mass, lam_x, b.n, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
-void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long count) {
-  hipLaunchKernelGGL(axpy_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, st, y, x, a, count);
+void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long count, long long ys,
+                 long long xs, bool by_drift, const Batch& b) {
+  if (by_drift && !b.tab) throw ArgError("axpy: step table required");
+  hipLaunchKernelGGL(axpy_kernel, per_sample(count, b), dim3(256), 0, st, y, x, a, count, ys, xs,
+                     by_drift, b.tab);
   DH_LAUNCH_CHECK();
 }
 
 void launch_grad_vjp(hipStream_t st, const float* lam_g, const float* lam_phi_in, float* lam_phi,
-                     int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(grad_vjp_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, lam_g,
-                     lam_phi_in, lam_phi, n);
+                     const Batch& b) {
+  hipLaunchKernelGGL(grad_vjp_kernel, per_sample(b.nc(), b), dim3(256), 0, st, lam_g, lam_phi_in,
+                     lam_phi, b.n, b.tab);
   DH_LAUNCH_CHECK();
 }
 

@@ -17,9 +17,9 @@ constexpr int kRedPer = 8;   // cells per thread in reduction kernels
 
 __device__ __forceinline__ int wrapi(int j, int n) { return j & (n - 1); }
 
-// block reduction of nv doubles per thread into out[v * gridDim.x + blockIdx.x]
+// block reduction of nv doubles per thread into out[v * stride + blockIdx.x]
 template <int NV, bool MAX>
-__device__ void block_reduce_store(double (&v)[NV], double* out) {
+__device__ void block_reduce_store(double (&v)[NV], double* out, long long stride) {
   __shared__ double sh[NV][kRedThreads];
 #pragma unroll
   for (int k = 0; k < NV; ++k) sh[k][threadIdx.x] = v[k];
@@ -35,8 +35,24 @@ __device__ void block_reduce_store(double (&v)[NV], double* out) {
   }
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) out[k * gridDim.x + blockIdx.x] = sh[k][0];
+    for (int k = 0; k < NV; ++k) out[k * stride + blockIdx.x] = sh[k][0];
   }
+}
+
+// Partials of a batched reduction: value v of block b of sample s at [(v S + s) nb + b]
+// (nb = gridDim.x, S = gridDim.y); returns the base for block_reduce_store's stride S nb.
+__device__ __forceinline__ double* sample_partials(double* partial) {
+  return partial + static_cast<long long>(blockIdx.y) * gridDim.x;
+}
+__device__ __forceinline__ long long partial_stride() {
+  return static_cast<long long>(gridDim.y) * gridDim.x;
+}
+// zero partials of an inactive sample's block
+template <int NV>
+__device__ __forceinline__ void zero_partials(double* partial) {
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sample_partials(partial)[k * partial_stride() + blockIdx.x] = 0.0;
 }
 
 // ------------------------------------------------------------------------- gas kick
@@ -56,10 +72,16 @@ __device__ __forceinline__ void kick_cell(float rho, const float4 g4, float h, f
 }
 
 __global__ void __launch_bounds__(256) gas_kick_kernel(const float* q_in, float* q,
-                                                       const float4* __restrict__ g4, float h,
-                                                       long long nc) {
+                                                       const float4* __restrict__ g4,
+                                                       long long nc,
+                                                       const StepScal* __restrict__ tab) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
+  const StepScal& sc = tab[blockIdx.y];
+  if (c >= nc || !sc.active) return;
+  const float h = sc.h;
+  q_in += blockIdx.y * 5 * nc;
+  q += blockIdx.y * 5 * nc;
+  g4 += blockIdx.y * nc;
   float m[3] = {q_in[nc + c], q_in[2 * nc + c], q_in[3 * nc + c]};
   float et = q_in[4 * nc + c];
   const float rho = q_in[c];
@@ -71,12 +93,19 @@ __global__ void __launch_bounds__(256) gas_kick_kernel(const float* q_in, float*
 }
 
 __global__ void __launch_bounds__(256) gas_kick_vjp_kernel(const float* __restrict__ q,
-                                                           const float4* __restrict__ g4, float h,
+                                                           const float4* __restrict__ g4,
                                                            float* __restrict__ lam,
                                                            float* __restrict__ lam_g,
-                                                           long long nc) {
+                                                           long long nc,
+                                                           const StepScal* __restrict__ tab) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
+  const StepScal& sc = tab[blockIdx.y];
+  if (c >= nc || !sc.active) return;
+  const float h = sc.h;
+  q += blockIdx.y * 5 * nc;
+  lam += blockIdx.y * 5 * nc;
+  lam_g += blockIdx.y * 3 * nc;
+  g4 += blockIdx.y * nc;
   const float4 gv = g4[c];
   const float g[3] = {gv.x, gv.y, gv.z};
   const float rho = q[c];
@@ -210,8 +239,21 @@ __device__ __forceinline__ double cell_speed(const float q5[5], double a, double
 // Closing pass of a step over kRedPer cells per thread: gas half kick, optional tape copy,
 // source term, CFL block maximum of the result.
 __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
-    const float* q_in, float* q, const float4* __restrict__ g4, float h, float* __restrict__ star,
-    SourceArgs a, float* __restrict__ q_kicked, double gg1, double* partial, long long nc) {
+    const float* q_in, float* q, const float4* __restrict__ g4, float* __restrict__ star,
+    float* __restrict__ q_kicked, double gg1, double* partial, long long nc,
+    const StepScal* __restrict__ tab) {
+  const StepScal& sc = tab[blockIdx.y];
+  if (!sc.active) {
+    zero_partials<1>(partial);
+    return;
+  }
+  const float h = sc.h;
+  const SourceArgs& a = sc.src;
+  q_in += blockIdx.y * 5 * nc;
+  q += blockIdx.y * 5 * nc;
+  if (q_kicked) q_kicked += blockIdx.y * 5 * nc;
+  g4 += blockIdx.y * nc;
+  star += blockIdx.y * nc;
   double vmax[1] = {0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   for (int r = 0; r < kRedPer; ++r) {
@@ -242,14 +284,22 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
     for (int k = (q == q_in ? 1 : 0); k < 5; ++k) q[k * nc + c] = q5[k];
     vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
   }
-  block_reduce_store<1, true>(vmax, partial);
+  block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
 }
 
-// lam (in: adjoint after the source, out: before); partial[0|1][block] = dL/d(eps_sf|delta_c)
+// lam (in: adjoint after the source, out: before); partials of dL/d(eps_sf|delta_c)
 __global__ void __launch_bounds__(kRedThreads) source_vjp_kernel(const float* __restrict__ q,
                                                                  float* __restrict__ lam,
-                                                                 SourceArgs a, double* partial,
-                                                                 long long nc) {
+                                                                 double* partial, long long nc,
+                                                                 const StepScal* __restrict__ tab) {
+  const StepScal& sc = tab[blockIdx.y];
+  if (!sc.active) {
+    zero_partials<2>(partial);
+    return;
+  }
+  const SourceArgs& a = sc.src;
+  q += blockIdx.y * 5 * nc;
+  lam += blockIdx.y * 5 * nc;
   double acc[2] = {0.0, 0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   for (int r = 0; r < kRedPer; ++r) {
@@ -291,7 +341,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_kernel(const float* __
     }
     lam[c] = static_cast<float>(lr);
   }
-  block_reduce_store<2, false>(acc, partial);
+  block_reduce_store<2, false>(acc, sample_partials(partial), partial_stride());
 }
 
 // ------------------------------------------------------------------------- learned closure
@@ -373,8 +423,21 @@ __device__ __forceinline__ bool closure_negligible(float o0, float o1, double u,
 
 // Closing pass with the learned closure (same cells per block as close_step_kernel).
 __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
-    const float* q_in, float* q, const float4* __restrict__ g4, float h, float* __restrict__ star,
-    SourceArgs a, float* __restrict__ q_kicked, double gg1, double* partial, long long nc) {
+    const float* q_in, float* q, const float4* __restrict__ g4, float* __restrict__ star,
+    float* __restrict__ q_kicked, double gg1, double* partial, long long nc,
+    const StepScal* __restrict__ tab) {
+  const StepScal& sc = tab[blockIdx.y];
+  if (!sc.active) {
+    zero_partials<1>(partial);
+    return;
+  }
+  const float h = sc.h;
+  const SourceArgs& a = sc.src;
+  q_in += blockIdx.y * 5 * nc;
+  q += blockIdx.y * 5 * nc;
+  if (q_kicked) q_kicked += blockIdx.y * 5 * nc;
+  g4 += blockIdx.y * nc;
+  star += blockIdx.y * nc;
   __shared__ uint4 fr[mlp::kFrFwd * 64];
   __shared__ __attribute__((aligned(16))) float bias[mlp::kBias];
   __shared__ float stage[kRedThreads / 64][64][kStage];
@@ -432,15 +495,22 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
     }
     __syncthreads();
   }
-  block_reduce_store<1, true>(vmax, partial);
+  block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
 }
 
 // Adjoint of the closure's source update at the kicked state q: lam (in: after, out:
 // before); partial[0|1][block] = dL/d(eps_sf | delta_c), which enter through the inputs.
-__global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(const float* __restrict__ q,
-                                                                     float* __restrict__ lam,
-                                                                     SourceArgs a, double* partial,
-                                                                     long long nc) {
+__global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
+    const float* __restrict__ q, float* __restrict__ lam, double* partial, long long nc,
+    const StepScal* __restrict__ tab) {
+  const StepScal& sc = tab[blockIdx.y];
+  if (!sc.active) {
+    zero_partials<2>(partial);
+    return;
+  }
+  const SourceArgs& a = sc.src;
+  q += blockIdx.y * 5 * nc;
+  lam += blockIdx.y * 5 * nc;
   __shared__ uint4 fr[mlp::kFrAll * 64];
   __shared__ __attribute__((aligned(16))) float bias[mlp::kBias];
   __shared__ float stage[kRedThreads / 64][64][kStage];
@@ -542,14 +612,16 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(const float
     }
     __syncthreads();
   }
-  block_reduce_store<2, false>(acc, partial);
+  block_reduce_store<2, false>(acc, sample_partials(partial), partial_stride());
 }
 
 // ------------------------------------------------------------------------- CFL
 __global__ void __launch_bounds__(kRedThreads) cfl_partial_kernel(const float* __restrict__ q,
-                                                                  double a, double gg1,
-                                                                  double efloor, double* partial,
-                                                                  long long nc) {
+                                                                  const double* __restrict__ a_cur,
+                                                                  double gg1, double efloor,
+                                                                  double* partial, long long nc) {
+  const double a = a_cur[blockIdx.y];
+  q += blockIdx.y * 5 * nc;
   double v[1] = {0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   for (int r = 0; r < kRedPer; ++r) {
@@ -559,7 +631,7 @@ __global__ void __launch_bounds__(kRedThreads) cfl_partial_kernel(const float* _
     load_q(q, c, nc, q5);
     v[0] = fmax(v[0], cell_speed(q5, a, gg1, efloor));
   }
-  block_reduce_store<1, true>(v, partial);
+  block_reduce_store<1, true>(v, sample_partials(partial), partial_stride());
 }
 
 // single block: out[v] = reduce over in[v * stride + 0..count)
@@ -598,13 +670,15 @@ __global__ void __launch_bounds__(kRedThreads) conservation_kernel(const float* 
 #pragma unroll
     for (int k = 0; k < 3; ++k) v[5 + k] += mom[k * nc + c];
   }
-  block_reduce_store<8, false>(v, partial);
+  block_reduce_store<8, false>(v, partial, gridDim.x);
 }
 
 __global__ void __launch_bounds__(kRedThreads) loss_kernel(const float* __restrict__ rho,
                                                            const float* __restrict__ target,
                                                            double A, double beta, double irm,
                                                            double* partial, long long nc) {
+  rho += blockIdx.y * 5 * nc;   // density row of the sample's Q
+  target += blockIdx.y * nc;
   double v[1] = {0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   for (int r = 0; r < kRedPer; ++r) {
@@ -614,7 +688,7 @@ __global__ void __launch_bounds__(kRedThreads) loss_kernel(const float* __restri
     const double d = f - target[c];
     v[0] += d * d;
   }
-  block_reduce_store<1, false>(v, partial);
+  block_reduce_store<1, false>(v, sample_partials(partial), partial_stride());
 }
 
 // lam_rho = scale * 2 (F - F_t) dF/drho / nc ; partial[0|1] = dL/dA, dL/dbeta
@@ -623,6 +697,9 @@ __global__ void __launch_bounds__(kRedThreads) loss_vjp_kernel(const float* __re
                                                                double A, double beta, double irm,
                                                                float* __restrict__ lam_rho,
                                                                double* partial, long long nc) {
+  rho += blockIdx.y * 5 * nc;
+  target += blockIdx.y * nc;
+  lam_rho += blockIdx.y * 5 * nc;
   double v[2] = {0.0, 0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   const double w = 2.0 / static_cast<double>(nc);
@@ -637,7 +714,7 @@ __global__ void __launch_bounds__(kRedThreads) loss_vjp_kernel(const float* __re
     v[0] += g * (-db);
     v[1] += g * (-A * db * log(dl));
   }
-  block_reduce_store<2, false>(v, partial);
+  block_reduce_store<2, false>(v, sample_partials(partial), partial_stride());
 }
 
 __global__ void flux_kernel(const float* __restrict__ rho, double A, double beta, double irm,
@@ -672,6 +749,9 @@ __global__ void ic_particles_kernel(const float* __restrict__ psi, float* __rest
                                     float* __restrict__ mom, float vfac, int n, long long np) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= np) return;
+  psi += blockIdx.y * 3 * np;
+  pos += blockIdx.y * 3 * np;
+  mom += blockIdx.y * 3 * np;
   const int l[3] = {static_cast<int>(i % n), static_cast<int>((i / n) % n),
                     static_cast<int>(i / (static_cast<long long>(n) * n))};
   const float fn = static_cast<float>(n);
@@ -691,6 +771,9 @@ __global__ void ic_gas_kernel(const float* __restrict__ cic, const float* __rest
                               long long nc) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nc) return;
+  cic += blockIdx.y * nc;
+  psi += blockIdx.y * 3 * nc;
+  q += blockIdx.y * 5 * nc;
   const float rho = f_b * cic[c];
   q[c] = rho;
   float u2 = 0.0f;
@@ -711,6 +794,11 @@ __global__ void ic_gas_vjp_kernel(const float* __restrict__ cic, const float* __
                                   float* __restrict__ lam_psi, long long nc) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nc) return;
+  cic += blockIdx.y * nc;
+  psi += blockIdx.y * 3 * nc;
+  lam += blockIdx.y * 5 * nc;
+  lam_cic += blockIdx.y * nc;
+  lam_psi += blockIdx.y * 3 * nc;
   const float rho = f_b * cic[c];
   const float le = lam[4 * nc + c];
   float lr = lam[c];
@@ -735,32 +823,34 @@ __global__ void fill_kernel(float* p, float v, long long count) {
 
 }  // namespace
 
-void launch_gas_kick(hipStream_t st, const float* q_in, float* q_out, const float4* g4, float h,
-                     int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(gas_kick_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q_in, q_out, g4,
-                     h, nc);
+void launch_gas_kick(hipStream_t st, const float* q_in, float* q_out, const float4* g4,
+                     const Batch& b) {
+  if (!b.tab) throw ArgError("gas kick: step table required");
+  hipLaunchKernelGGL(gas_kick_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st, q_in,
+                     q_out, g4, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
-void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4, float h,
-                         float* lam_q, float* lam_g, int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(gas_kick_vjp_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q_before,
-                     g4, h, lam_q, lam_g, nc);
+void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4, float* lam_q,
+                         float* lam_g, const Batch& b) {
+  if (!b.tab) throw ArgError("gas kick adjoint: step table required");
+  hipLaunchKernelGGL(gas_kick_vjp_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st,
+                     q_before, g4, lam_q, lam_g, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
-void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4* g4, float h,
-                       float* star, const SourceArgs& a, float* q_kicked, double gamma,
-                       double* block_max, int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  if (a.mlp && a.mode != 0)
-    hipLaunchKernelGGL(close_step_mlp_kernel, dim3(sum_blocks(nc)), dim3(kRedThreads), 0, st, q_in,
-                       q, g4, h, star, a, q_kicked, gamma * (gamma - 1.0), block_max, nc);
+// The closure kernels are chosen per launch: every sample of a batch has the same closure.
+void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4* g4,
+                       float* star, float* q_kicked, double gamma, double* block_max,
+                       const Batch& b, bool closure) {
+  if (!b.tab) throw ArgError("closing pass: step table required");
+  const dim3 grid(sum_blocks(b.nc()), b.S);
+  if (closure)
+    hipLaunchKernelGGL(close_step_mlp_kernel, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
+                       q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab);
   else
-    hipLaunchKernelGGL(close_step_kernel, dim3(sum_blocks(nc)), dim3(kRedThreads), 0, st, q_in, q,
-                       g4, h, star, a, q_kicked, gamma * (gamma - 1.0), block_max, nc);
+    hipLaunchKernelGGL(close_step_kernel, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
+                       q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
@@ -770,28 +860,30 @@ int sum_blocks(long long count) {
 int source_vjp_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n * n); }
 int cfl_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n * n); }
 
-void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, const SourceArgs& a,
-                       double* partials, int nblocks_out, int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  if (a.mlp)
-    hipLaunchKernelGGL(source_vjp_mlp_kernel, dim3(nblocks_out), dim3(kRedThreads), 0, st,
-                       q_before, lam_q, a, partials, nc);
+void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, double* partials,
+                       const Batch& b, bool closure) {
+  if (!b.tab) throw ArgError("source adjoint: step table required");
+  const dim3 grid(source_vjp_blocks(b.n), b.S);
+  if (closure)
+    hipLaunchKernelGGL(source_vjp_mlp_kernel, grid, dim3(kRedThreads), 0, st, q_before, lam_q,
+                       partials, b.nc(), b.tab);
   else
-    hipLaunchKernelGGL(source_vjp_kernel, dim3(nblocks_out), dim3(kRedThreads), 0, st, q_before,
-                       lam_q, a, partials, nc);
+    hipLaunchKernelGGL(source_vjp_kernel, grid, dim3(kRedThreads), 0, st, q_before, lam_q,
+                       partials, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
-void launch_cfl_partial(hipStream_t st, const float* q, double a, double gamma, double efloor,
-                        double* block_max, int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(cfl_partial_kernel, dim3(cfl_blocks(n)), dim3(kRedThreads), 0, st, q, a,
-                     gamma * (gamma - 1.0), efloor, block_max, nc);
+void launch_cfl_partial(hipStream_t st, const float* q, const double* a_cur, double gamma,
+                        double efloor, double* block_max, const Batch& b) {
+  hipLaunchKernelGGL(cfl_partial_kernel, dim3(cfl_blocks(b.n), b.S), dim3(kRedThreads), 0, st, q,
+                     a_cur, gamma * (gamma - 1.0), efloor, block_max, b.nc());
   DH_LAUNCH_CHECK();
 }
 
-void launch_reduce_max(hipStream_t st, const double* in, int count, double* out) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kRedThreads), 0, st, in, count, count, 1, out);
+void launch_reduce_max(hipStream_t st, const double* in, int count, int stride, int nvec,
+                       double* out) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(nvec), dim3(kRedThreads), 0, st, in, count, stride, 1,
+                     out);
   DH_LAUNCH_CHECK();
 }
 
@@ -809,18 +901,16 @@ void launch_conservation_partial(hipStream_t st, const float* q, const float* mo
 }
 
 void launch_loss_partial(hipStream_t st, const float* rho, const float* target, double A,
-                         double beta, float inv_rho_mean, double* partial, int nblocks,
-                         long long nc) {
-  hipLaunchKernelGGL(loss_kernel, dim3(nblocks), dim3(kRedThreads), 0, st, rho, target, A, beta,
-                     static_cast<double>(inv_rho_mean), partial, nc);
+                         double beta, float inv_rho_mean, double* partial, const Batch& b) {
+  hipLaunchKernelGGL(loss_kernel, dim3(sum_blocks(b.nc()), b.S), dim3(kRedThreads), 0, st, rho,
+                     target, A, beta, static_cast<double>(inv_rho_mean), partial, b.nc());
   DH_LAUNCH_CHECK();
 }
 
 void launch_loss_vjp(hipStream_t st, const float* rho, const float* target, double A, double beta,
-                     float inv_rho_mean, float* lam_rho, double* partial, int nblocks,
-                     long long nc) {
-  hipLaunchKernelGGL(loss_vjp_kernel, dim3(nblocks), dim3(kRedThreads), 0, st, rho, target, A, beta,
-                     static_cast<double>(inv_rho_mean), lam_rho, partial, nc);
+                     float inv_rho_mean, float* lam_rho, double* partial, const Batch& b) {
+  hipLaunchKernelGGL(loss_vjp_kernel, dim3(sum_blocks(b.nc()), b.S), dim3(kRedThreads), 0, st, rho,
+                     target, A, beta, static_cast<double>(inv_rho_mean), lam_rho, partial, b.nc());
   DH_LAUNCH_CHECK();
 }
 
@@ -846,27 +936,24 @@ void launch_white_noise(hipStream_t st, float* out, uint32_t seed_lo, uint32_t s
 }
 
 void launch_ic_particles(hipStream_t st, const float* psi, float* pos, float* mom, float vfac,
-                         int n) {
-  const long long np = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(ic_particles_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, psi, pos, mom,
-                     vfac, n, np);
+                         const Batch& b) {
+  hipLaunchKernelGGL(ic_particles_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st, psi,
+                     pos, mom, vfac, b.n, b.nc());
   DH_LAUNCH_CHECK();
 }
 
 void launch_ic_gas(hipStream_t st, const float* cic, const float* psi, float* q, float f_b,
-                   float vfac, float a, float e_init, int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(ic_gas_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, cic, psi, q, f_b,
-                     vfac, a, e_init, nc);
+                   float vfac, float a, float e_init, const Batch& b) {
+  hipLaunchKernelGGL(ic_gas_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st, cic, psi,
+                     q, f_b, vfac, a, e_init, b.nc());
   DH_LAUNCH_CHECK();
 }
 
 void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const float* lam_q,
                        float f_b, float vfac, float a, float e_init, float* lam_cic,
-                       float* lam_psi, int n) {
-  const long long nc = static_cast<long long>(n) * n * n;
-  hipLaunchKernelGGL(ic_gas_vjp_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, cic, psi,
-                     lam_q, f_b, vfac, a, e_init, lam_cic, lam_psi, nc);
+                       float* lam_psi, const Batch& b) {
+  hipLaunchKernelGGL(ic_gas_vjp_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st, cic,
+                     psi, lam_q, f_b, vfac, a, e_init, lam_cic, lam_psi, b.nc());
   DH_LAUNCH_CHECK();
 }
 

@@ -53,11 +53,14 @@ def _host_floats(values, count):
 
 
 class Sim:
-    """One simulation handle on the current HIP device."""
+    """One simulation handle on the current HIP device.  With config.batch = S > 1 it holds
+    S independent samples: fields, white noise, targets and gradients then carry a leading
+    sample dimension, and losses and parameter gradients are per sample."""
 
     def __init__(self, config=None, params=None, **cfg_kw):
         self.cfg = config if config is not None else default_config(**cfg_kw)
         self.n = int(self.cfg.n)
+        self.S = max(1, int(self.cfg.batch))
         self.nc = self.n ** 3
         self._h = ctypes.c_void_p()
         torch.cuda.init()
@@ -98,6 +101,41 @@ class Sim:
         self.params = p
         self._check(lib().dh_set_params(self._h, ctypes.byref(p)))
 
+    def _lead(self):
+        return (self.S,) if self.S > 1 else ()
+
+    def set_sample_params(self, sample, p=None, **kw):
+        """Star-formation parameters of one sample (A, beta stay the shared ones)."""
+        self._stream()
+        if p is None:
+            p = default_params()
+            for f, _ in type(p)._fields_:
+                setattr(p, f, getattr(self.params, f))
+        for k, v in kw.items():
+            setattr(p, k, v)
+        self._check(lib().dh_set_sample_params(self._h, sample, ctypes.byref(p)))
+
+    def set_sample_schedule(self, sample, dts):
+        self._stream()
+        arr = (ctypes.c_double * max(1, len(dts)))(*[float(x) for x in dts])
+        self._check(lib().dh_set_sample_schedule(self._h, sample, arr, len(dts)))
+
+    def get_sample_schedule(self, sample):
+        self._stream()
+        n = ctypes.c_int32()
+        self._check(lib().dh_get_sample_schedule(self._h, sample, None, 0, ctypes.byref(n)))
+        arr = (ctypes.c_double * max(1, n.value))()
+        self._check(lib().dh_get_sample_schedule(self._h, sample, arr, n.value, ctypes.byref(n)))
+        return list(arr[:n.value])
+
+    def sample_times(self):
+        """(a, t) of every sample."""
+        self._stream()
+        a = (ctypes.c_double * self.S)()
+        t = (ctypes.c_double * self.S)()
+        self._check(lib().dh_get_sample_times(self._h, a, t))
+        return list(a), list(t)
+
     def set_closure(self, theta):
         """Weights of the learned closure (flat float vector of DH_MLP_NPARAMS values; a
         simulation created with closure=CLOSURE_MLP needs them before its first step)."""
@@ -111,7 +149,7 @@ class Sim:
 
     def init_from_noise(self, white):
         self._stream()
-        self._check(lib().dh_init_from_noise(self._h, _ptr(white, numel=self.nc)))
+        self._check(lib().dh_init_from_noise(self._h, _ptr(white, numel=self.S * self.nc)))
 
     def step(self):
         self._stream()
@@ -141,17 +179,17 @@ class Sim:
     def get(self, name):
         self._stream()
         f = FIELDS[name]
-        out = torch.empty(_FIELD_SHAPE[f] + (self.n, self.n, self.n), dtype=torch.float32,
-                          device="cuda")
+        out = torch.empty(self._lead() + _FIELD_SHAPE[f] + (self.n, self.n, self.n),
+                          dtype=torch.float32, device="cuda")
         self._check(lib().dh_get_field(self._h, f, _ptr(out)))
         if f in (FIELD_POS, FIELD_MOM):
-            out = out.reshape(3, self.nc)
+            out = out.reshape(self._lead() + (3, self.nc))
         return out
 
     def set(self, name, t):
         self._stream()
         f = FIELDS[name]
-        numel = self.nc * (5 if f == FIELD_Q else 3 if f in (FIELD_POS, FIELD_MOM) else 1)
+        numel = self.S * self.nc * (5 if f == FIELD_Q else 3 if f in (FIELD_POS, FIELD_MOM) else 1)
         self._check(lib().dh_set_field(self._h, f, _ptr(t.contiguous(), numel=numel)))
 
     def refresh_potential(self):
@@ -171,28 +209,35 @@ class Sim:
     def forward(self, white, a_final):
         self._stream()
         k = ctypes.c_int32()
-        self._check(lib().dh_forward(self._h, _ptr(white, numel=self.nc), a_final, ctypes.byref(k)))
+        self._check(lib().dh_forward(self._h, _ptr(white, numel=self.S * self.nc), a_final,
+                                     ctypes.byref(k)))
         return k.value
 
     def loss(self, target):
+        """The flux-field loss (a list of per-sample values for a batch)."""
         self._stream()
-        v = ctypes.c_double()
-        self._check(lib().dh_loss(self._h, _ptr(target, numel=self.nc), ctypes.byref(v)))
-        return v.value
+        v = (ctypes.c_double * self.S)()
+        self._check(lib().dh_loss(self._h, _ptr(target, numel=self.S * self.nc), v))
+        return v[0] if self.S == 1 else list(v)
 
     def backward(self, grad_rho=None):
+        """(dL/dwhite, dL/d(A, beta, eps_sf, delta_c)); per sample for a batch."""
         self._stream()
-        gw = torch.empty(self.n, self.n, self.n, dtype=torch.float32, device="cuda")
-        gp = (ctypes.c_double * 4)()
-        gr = _ptr(grad_rho.contiguous(), numel=self.nc) if grad_rho is not None else None
+        gw = torch.empty(self._lead() + (self.n, self.n, self.n), dtype=torch.float32,
+                         device="cuda")
+        gp = (ctypes.c_double * (4 * self.S))()
+        gr = (_ptr(grad_rho.contiguous(), numel=self.S * self.nc) if grad_rho is not None
+              else None)
         self._check(lib().dh_backward(self._h, gr, _ptr(gw), gp))
-        return gw, list(gp)
+        vals = list(gp)
+        return gw, (vals if self.S == 1 else [vals[4 * i:4 * i + 4] for i in range(self.S)])
 
     def conservation(self):
         self._stream()
-        out = (ctypes.c_double * 8)()
+        out = (ctypes.c_double * (8 * self.S))()
         self._check(lib().dh_conservation(self._h, out))
-        return list(out)
+        vals = list(out)
+        return vals if self.S == 1 else [vals[8 * i:8 * i + 8] for i in range(self.S)]
 
     # single stages on caller buffers
     def stage_sweep(self, q, axis, dt, a1, a2):
