@@ -1,8 +1,11 @@
 """Benchmark of the MI355X path: cell-updates/s of the full time step (forward with
 checkpoints plus the reverse pass) at 256^3 cells + 256^3 dark-matter particles, the
 forward-only rate, the HBM roofline fraction of the dominant kernel, the FP64 CPU oracle
-timed on this host, and the learned star-formation closure against the plain source term
-(its training, its step rates, and the distance of its final fields from the plain run's).
+timed on this host, the learned star-formation closure against the plain source term
+(its training, its step rates, and the distance of its final fields from the plain run's),
+and the batched parameter sampler (64 samples of 64^3 with their own seeds, star-formation
+parameters and step counts, forward + reverse in shared launches) against running the same
+samples one after another.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -34,6 +37,8 @@ def parse():
     p.add_argument("--kernel-reps", type=int, default=20)
     p.add_argument("--no-mlp", action="store_true", help="skip the learned-closure comparison")
     p.add_argument("--mlp-samples", type=int, default=1 << 24)
+    p.add_argument("--no-batch", action="store_true", help="skip the batched-sampler comparison")
+    p.add_argument("--batch-samples", type=int, default=64)
     return p.parse_args()
 
 
@@ -154,6 +159,85 @@ def mlp_comparison(torch, dhp, white, n, box, steps, warmup, samples):
     }
 
 
+def batch_comparison(torch, dhp, si, samples):
+    """Batched parameter sampler: `samples` samples of 64^3 cells + particles in 10 Mpc/h
+    boxes, white noise from seeds 1000 + s, (eps_sf, Delta_c) drawn uniformly within +-50% of
+    (0.02, 100) (seed 8), relaxed star formation, each stepping by its own CFL from a = 0.01
+    to 0.29; forward with checkpoints, per-sample loss against the flux field of seeds 2000 + s,
+    reverse pass.  Timed as one batch and as the same samples run one after another."""
+    n, box, a_final, K = 64, 10.0, 0.29, 16
+    rng = np.random.default_rng(8)
+    eps = 0.02 * rng.uniform(0.5, 1.5, samples)
+    dcs = 100.0 * rng.uniform(0.5, 1.5, samples)
+    white = torch.from_numpy(np.stack([si.white_noise(n, 1000 + i) for i in range(samples)])).cuda()
+    white_t = torch.from_numpy(np.stack([si.white_noise(n, 2000 + i)
+                                         for i in range(samples)])).cuda()
+    b = dhp.Sim(dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=2, batch=samples,
+                                   ckpt_every=K))
+    for i in range(samples):
+        b.set_sample_params(i, eps_sf=float(eps[i]), delta_c=float(dcs[i]))
+    t0 = time.perf_counter()
+    kt = b.forward(white_t, a_final)
+    target = b.get("flux").clone()
+    torch.cuda.synchronize()
+    log(f"bench: batch target run: {kt} lockstep steps, {time.perf_counter() - t0:.2f} s")
+    b.forward(white, a_final)                  # warm-up of the full path
+    b.loss(target)
+    b.backward()
+    torch.cuda.synchronize()
+    log(f"bench: batch warm-up done, {time.perf_counter() - t0:.2f} s")
+    t0 = time.perf_counter()
+    k = b.forward(white, a_final)
+    losses = b.loss(target)
+    gw, gp = b.backward()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    steps = [len(b.get_sample_schedule(i)) for i in range(samples)]
+    b.close()
+    log(f"bench: batch of {samples}: {k} lockstep steps, per-sample {min(steps)}..{max(steps)}, "
+        f"fwd+bwd {t_batch:.2f} s")
+    # the same samples one at a time
+    t_seq = 0.0
+    seq_steps = []
+    for i in range(-1, samples):               # i = -1: untimed warm-up of sample 0
+        j = max(i, 0)
+        s = dhp.Sim(dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=2, ckpt_every=K,
+                                       sf_seed=102 + j),
+                    dhp.default_params(eps_sf=float(eps[j]), delta_c=float(dcs[j])))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.forward(white[j].contiguous(), a_final)
+        s.loss(target[j].contiguous())
+        s.backward()
+        torch.cuda.synchronize()
+        if i >= 0:
+            t_seq += time.perf_counter() - t0
+            seq_steps.append(len(s.get_schedule()))
+            if i % 8 == 7:
+                log(f"bench: sequential samples {i + 1}/{samples}, {t_seq:.2f} s")
+        s.close()
+    assert seq_steps == steps
+    log(f"bench: the same {samples} samples one after another: {t_seq:.2f} s")
+    cells = float(n ** 3) * sum(steps)
+    return {
+        "workload": f"{samples} samples x (64^3 cells + 64^3 DM particles), 10 Mpc/h boxes, "
+                    "white-noise seeds 1000+s, eps_sf and Delta_c uniform within +-50% of "
+                    "(0.02, 100) (seed 8), relaxed star formation, own CFL steps a = 0.01 -> "
+                    "0.29, checkpointed forward + per-sample flux loss + reverse pass",
+        "fwd_bwd_cell_updates_per_s": cells / t_batch,
+        "sequential_fwd_bwd_cell_updates_per_s": cells / t_seq,
+        "speedup_vs_sequential": t_seq / t_batch,
+        "seconds": t_batch,
+        "sequential_seconds": t_seq,
+        "lockstep_steps": k,
+        "steps_min": min(steps), "steps_max": max(steps), "steps_total": sum(steps),
+        "ckpt_every": K,
+        "mean_abs_dL_deps_sf": float(np.mean([abs(g[2]) for g in gp])),
+        "mean_abs_dL_ddelta_c": float(np.mean([abs(g[3]) for g in gp])),
+        "mean_loss": float(np.mean(losses)),
+    }
+
+
 def cpu_baseline(n, box):
     """The FP64 oracle on this host's cores: one forward step at the same size."""
     import torch
@@ -235,6 +319,9 @@ def main():
         log("bench: learned closure vs plain source term")
         out["mlp_closure"] = mlp_comparison(torch, dhp, white, n, BOX * n / N, args.steps,
                                             args.warmup, args.mlp_samples)
+    if not args.no_batch:
+        log("bench: batched parameter sampler vs one sample at a time")
+        out["batched_sampler"] = batch_comparison(torch, dhp, si, args.batch_samples)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(n, BOX * n / N)

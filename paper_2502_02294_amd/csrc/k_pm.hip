@@ -357,8 +357,7 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
                                                          const StepScal* __restrict__ tab) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const StepScal& sc = tab[blockIdx.y];
-  if (i >= np || !sc.active) return;
-  const float h = sc.h, drift_fac = sc.drift;
+  if (i >= np) return;
   const int smp = blockIdx.y;
   g4 += smp * np;
   pos += smp * 3 * np;
@@ -366,6 +365,17 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
   key += smp * np;
   if (mom_copy) mom_copy += smp * 3 * np;
   if (pos_copy) pos_copy += smp * 3 * np;
+  if (!sc.active) {
+    // a sample that sits the step out keeps its particles; the copies (the tape of the
+    // reverse pass, which sorts them again) receive them unchanged
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (mom_copy) mom_copy[d * np + i] = mom[d * np + i];
+      if (pos_copy) pos_copy[d * np + i] = pos[d * np + i];
+    }
+    return;
+  }
+  const float h = sc.h, drift_fac = sc.drift;
   float x[3] = {pos[i], pos[np + i], pos[2 * np + i]};
   const Cic w = cic_of(x[0], x[1], x[2], n);
   float g[3];
