@@ -771,6 +771,7 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
     s->bins.start = s->alloc<uint32_t>(nc + 1);
     s->bins.sorted = s->alloc<uint32_t>(np);
     s->bins.block_sums = s->alloc<uint32_t>(static_cast<long long>(dh::scan_block_count(nc)) + 1);
+    s->bins.large = s->alloc<uint32_t>(1 + dh::large_bin_capacity(np));
     s->bins.spos = s->alloc<float4>(np);
     s->bins.sval = s->alloc<float4>(np);
     s->g4 = s->alloc<float4>(nc);

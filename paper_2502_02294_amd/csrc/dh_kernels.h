@@ -57,10 +57,13 @@ struct Bins {          // counting sort of particles by CIC base cell
   uint32_t* start;     // [S nc + 1] exclusive prefix sum of count
   uint32_t* sorted;    // [S np] particle ids, bins in order, ids ascending inside a bin
   uint32_t* block_sums;  // [scan blocks]
+  uint32_t* large;     // [1 + large_bin_capacity(total)]: count, then bins of many particles
   float4* spos;        // [S np] positions in bin order
   float4* sval;        // [S np] a particle vector field in bin order (adjoint deposits)
 };
 size_t scan_block_count(long long nbins);
+// entries of Bins::large for `total` particles (bins of more than 32 particles)
+long long large_bin_capacity(long long total);
 void launch_keys(hipStream_t st, const float* pos, uint32_t* key, const Batch& b);
 // sort by bins.key (already computed for pos) and gather pos into bin order
 void launch_sort(hipStream_t st, const Bins& bins, const float* pos, const Batch& b);

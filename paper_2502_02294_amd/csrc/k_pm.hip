@@ -18,6 +18,7 @@ namespace dh {
 namespace {
 
 constexpr int kScanThreads = 256;
+constexpr int kLargeSortBlocks = 1024;
 constexpr int kScanPer = 16;
 constexpr int kScanTile = kScanThreads * kScanPer;
 
@@ -159,11 +160,22 @@ __global__ void scatter_kernel(const uint32_t* __restrict__ key, const uint32_t*
 }
 
 // The atomics above fix each bin's size but not the order inside it; sorting each bin's ids
-// ascending makes the layout a pure function of the keys.
-__global__ void bin_sort_kernel(const uint32_t* __restrict__ start, uint32_t* sorted, long long nc) {
+// ascending makes the layout a pure function of the keys.  A thread sorts a bin of up to
+// kSmallBin ids by insertion; larger bins (dense halos gather thousands of particles in a
+// cell) go to a list that bin_sort_large_kernel sorts one workgroup per bin.
+constexpr uint32_t kSmallBin = 32;
+constexpr int kLdsSort = 16384;   // ids a workgroup sorts in LDS (64 KB)
+
+__global__ void bin_sort_kernel(const uint32_t* __restrict__ start, uint32_t* sorted,
+                                long long nbins, uint32_t* __restrict__ large) {
   const long long b = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (b >= nc) return;
+  if (b >= nbins) return;
   const uint32_t lo = start[b], hi = start[b + 1];
+  if (hi - lo > kSmallBin) {
+    // large[0] counts the entries large[1..]; the list order does not affect the result
+    large[1 + atomicAdd(&large[0], 1u)] = static_cast<uint32_t>(b);
+    return;
+  }
   for (uint32_t i = lo + 1; i < hi; ++i) {
     const uint32_t v = sorted[i];
     uint32_t j = i;
@@ -172,6 +184,53 @@ __global__ void bin_sort_kernel(const uint32_t* __restrict__ start, uint32_t* so
       --j;
     }
     sorted[j] = v;
+  }
+}
+
+// Ascending bitonic network over p = 2^m slots of which the first k hold data and the rest
+// count as +infinity: every compare-exchange orders a lower index before a higher one (the
+// first stage of each merge pairs i with its mirror), so a slot >= k is never written.
+template <typename Get, typename Put>
+__device__ void bitonic_ascending(uint32_t k, uint32_t p, Get get, Put put) {
+  for (uint32_t size = 2; size <= p; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = threadIdx.x; i < p; i += blockDim.x) {
+        const uint32_t j = stride == (size >> 1) ? (i ^ (size - 1)) : (i ^ stride);
+        if (j > i && j < k) {
+          const uint32_t a = get(i), c = get(j);
+          if (a > c) {
+            put(i, c);
+            put(j, a);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) bin_sort_large_kernel(const uint32_t* __restrict__ start,
+                                                             uint32_t* sorted,
+                                                             const uint32_t* __restrict__ large) {
+  __shared__ uint32_t sh[kLdsSort];
+  const uint32_t count = large[0];
+  for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {
+    const uint32_t b = large[1 + e];
+    const uint32_t lo = start[b], k = start[b + 1] - lo;
+    uint32_t p = 1;
+    while (p < k) p <<= 1;
+    uint32_t* g = sorted + lo;
+    if (k <= static_cast<uint32_t>(kLdsSort)) {
+      for (uint32_t i = threadIdx.x; i < k; i += blockDim.x) sh[i] = g[i];
+      __syncthreads();
+      bitonic_ascending(k, p, [&](uint32_t i) { return sh[i]; },
+                        [&](uint32_t i, uint32_t v) { sh[i] = v; });
+      for (uint32_t i = threadIdx.x; i < k; i += blockDim.x) g[i] = sh[i];
+    } else {
+      bitonic_ascending(k, p, [&](uint32_t i) { return g[i]; },
+                        [&](uint32_t i, uint32_t v) { g[i] = v; });
+    }
+    __syncthreads();
   }
 }
 
@@ -510,6 +569,8 @@ __global__ void __launch_bounds__(256) grad_vjp_kernel(const float* __restrict__
 
 }  // namespace
 
+long long large_bin_capacity(long long total) { return total / (kSmallBin + 1) + 1; }
+
 size_t scan_block_count(long long nbins) {
   return static_cast<size_t>((nbins + kScanTile - 1) / kScanTile);
 }
@@ -550,8 +611,13 @@ void launch_sort(hipStream_t st, const Bins& bins, const float* pos, const Batch
   hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, st, bins.key,
                      bins.rank, bins.start, bins.sorted, total);
   DH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, st, bins.large, 0u, 1LL);
+  DH_LAUNCH_CHECK();
   hipLaunchKernelGGL(bin_sort_kernel, dim3(blocks_for(nbins, 256)), dim3(256), 0, st, bins.start,
-                     bins.sorted, nbins);
+                     bins.sorted, nbins, bins.large);
+  DH_LAUNCH_CHECK();
+  hipLaunchKernelGGL(bin_sort_large_kernel, dim3(kLargeSortBlocks), dim3(256), 0, st, bins.start,
+                     bins.sorted, bins.large);
   DH_LAUNCH_CHECK();
   hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, st,
                      bins.sorted, pos, bins.spos, total, log2_ll(b.nc()));

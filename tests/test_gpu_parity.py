@@ -160,6 +160,23 @@ def test_deposit_dense_bins(dhp):
     assert rel_l2(a + 1.0, ref + 1.0) < STEP_TOL
 
 
+@pytest.mark.parametrize("width", [0.3, 2.0])
+def test_deposit_crowded_bins(dhp, width):
+    # every particle of a 32^3 set in one bin (32768 ids: the global-memory sort) or spread
+    # over a few bins of thousands (the LDS sort); two deposits agree bit for bit
+    n = 32
+    ocfg = osim.default_config(n=n)
+    s = _sim(dhp, ocfg)
+    pos = (np.float32(5.55) + width * si.random_positions(n, seed=9) / n).astype(np.float32)
+    rho = np.zeros((n, n, n), dtype=np.float32)
+    a = s.stage_deposit(to_gpu(rho), to_gpu(pos))
+    b = s.stage_deposit(to_gpu(rho), to_gpu(pos))
+    assert torch.equal(a, b)
+    ref = gravity.total_overdensity(torch.from_numpy(rho).double(), torch.from_numpy(pos).double(),
+                                    1.0 - ocfg.f_b, n).numpy()
+    assert rel_l2(to_np(a) + 1.0, ref + 1.0) < STEP_TOL
+
+
 def test_readout_matches_oracle(dhp):
     n = 32
     ocfg = osim.default_config(n=n)
