@@ -60,6 +60,24 @@ def time_stage(torch, fn, reps):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
+def sweep_traffic_bytes():
+    """Measured HBM bytes per sweep launch at 256^3 (two rocprofv3 counter passes, calibrated
+    by streaming kernels of known size; profiles/sweep_256_traffic.json), or None when the
+    sweep sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sweep_256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        doc = json.load(fh)
+    for name, digest in doc.get("sources_sha256", {}).items():
+        src = os.path.join(ROOT, "paper_2502_02294_amd", "csrc", name)
+        with open(src, "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != digest:
+                return None
+    return float(doc["traffic_bytes_per_launch"])
+
+
 def time_steps(torch, s, white, steps, warmup):
     """(forward-only seconds, forward-with-checkpoints + loss + reverse seconds) of `steps`
     steps from the initial conditions of `white`, after `warmup` untimed steps / one untimed
@@ -289,6 +307,8 @@ def main():
     t_sweep = sum(sweep_t.values()) / 3.0
     bytes_per_launch = 40.0 * nc
     achieved = bytes_per_launch / t_sweep / 1e9
+    measured = sweep_traffic_bytes() if n == N else None
+    traffic = measured / t_sweep / 1e9 if measured else None
 
     out = {
         "metric": "cell-updates/s fwd+bwd at 256^3 (forward with checkpoints + reverse pass)",
@@ -310,7 +330,9 @@ def main():
         "fwd_cell_updates_per_s": nc * args.steps / t_fwd,
         "fwd_ms_per_step": t_fwd / args.steps * 1e3,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_bytes_per_launch": measured,
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
                      "kernel": "hydro sweep (x, y, z mean)",
                      "ms_per_launch": {str(k_): v * 1e3 for k_, v in sweep_t.items()}},
     }
