@@ -392,21 +392,54 @@ __global__ void __launch_bounds__(64 * kTrainWaves) train_grad_kernel(
   }
 }
 
+// Sum of the per-wave partial gradients of kRedParams parameters per block: thread
+// (stripe, j) adds partials stripe, stripe + kStripes, ... of parameter base + j, then the
+// stripes are added in order; the result does not depend on the launch.
+constexpr int kRedParams = 16;
+constexpr int kStripes = 16;   // kRedParams * kStripes = 256 threads
+
+__device__ __forceinline__ double sum_partials(const float* __restrict__ partial, int nparts,
+                                               int p) {
+  __shared__ double sh[kStripes][kRedParams];
+  const int j = threadIdx.x % kRedParams, stripe = threadIdx.x / kRedParams;
+  double acc = 0.0;
+  if (p < kParams)
+    for (int w = stripe; w < nparts; w += kStripes)
+      acc += partial[static_cast<long long>(w) * kParams + p];
+  sh[stripe][j] = acc;
+  __syncthreads();
+  double s = 0.0;
+  if (stripe == 0)
+    for (int k = 0; k < kStripes; ++k) s += sh[k][j];
+  return s;   // valid in stripe 0
+}
+
+// Block-wide sum of the loss partials in a fixed order (valid in thread 0); every thread of
+// the block calls it.
+__device__ __forceinline__ double sum_loss(const double* __restrict__ loss_part, int nparts) {
+  __shared__ double sh[256];
+  double l = 0.0;
+  for (int w = threadIdx.x; w < nparts; w += 256) l += loss_part[w];
+  sh[threadIdx.x] = l;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
 // grad[p] = sum over partials (fixed order, FP64); loss = sum of loss partials * scale
 __global__ void __launch_bounds__(256) reduce_grad_kernel(const float* __restrict__ partial,
                                                           int nparts, const double* __restrict__ loss_part,
                                                           double loss_scale, double* __restrict__ grad,
                                                           double* __restrict__ loss_out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < kParams) {
-    double s = 0.0;
-    for (int w = 0; w < nparts; ++w) s += partial[static_cast<long long>(w) * kParams + p];
-    grad[p] = s;
-  }
-  if (p == 0) {
-    double l = 0.0;
-    for (int w = 0; w < nparts; ++w) l += loss_part[w];
-    *loss_out = l * loss_scale;
+  const int p = blockIdx.x * kRedParams + threadIdx.x % kRedParams;
+  const double s = sum_partials(partial, nparts, p);
+  if (threadIdx.x < kRedParams && p < kParams) grad[p] = s;
+  if (blockIdx.x == 0) {
+    const double l = sum_loss(loss_part, nparts);
+    if (threadIdx.x == 0) *loss_out = l * loss_scale;
   }
 }
 
@@ -416,10 +449,9 @@ __global__ void __launch_bounds__(256) adam_kernel(const float* __restrict__ par
                                                    double loss_scale, float* __restrict__ th,
                                                    float* __restrict__ m, float* __restrict__ v,
                                                    AdamArgs a, double* __restrict__ loss_hist) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < kParams) {
-    double s = 0.0;
-    for (int w = 0; w < nparts; ++w) s += partial[static_cast<long long>(w) * kParams + p];
+  const int p = blockIdx.x * kRedParams + threadIdx.x % kRedParams;
+  const double s = sum_partials(partial, nparts, p);
+  if (threadIdx.x < kRedParams && p < kParams) {
     const float gr = static_cast<float>(s);
     const float mm = a.beta1 * m[p] + (1.0f - a.beta1) * gr;
     const float vv = a.beta2 * v[p] + (1.0f - a.beta2) * gr * gr;
@@ -427,10 +459,9 @@ __global__ void __launch_bounds__(256) adam_kernel(const float* __restrict__ par
     v[p] = vv;
     th[p] -= a.lr * (mm * a.corr1) / (sqrtf(vv * a.corr2) + a.eps);
   }
-  if (p == 0 && loss_hist) {
-    double l = 0.0;
-    for (int w = 0; w < nparts; ++w) l += loss_part[w];
-    loss_hist[a.step] = l * loss_scale;
+  if (loss_hist && blockIdx.x == 0) {
+    const double l = sum_loss(loss_part, nparts);
+    if (threadIdx.x == 0) loss_hist[a.step] = l * loss_scale;
   }
 }
 
@@ -486,16 +517,16 @@ void launch_mlp_train_grad(hipStream_t st, const uint4* packed, const float* x, 
 void launch_mlp_reduce_grad(hipStream_t st, const float* partial, int nparts,
                             const double* loss_part, double loss_scale, double* grad,
                             double* loss_out) {
-  hipLaunchKernelGGL(reduce_grad_kernel, dim3(blocks_for(kParams, 256)), dim3(256), 0, st, partial,
-                     nparts, loss_part, loss_scale, grad, loss_out);
+  hipLaunchKernelGGL(reduce_grad_kernel, dim3(blocks_for(kParams, kRedParams)), dim3(256), 0, st,
+                     partial, nparts, loss_part, loss_scale, grad, loss_out);
   DH_LAUNCH_CHECK();
 }
 
 void launch_mlp_adam(hipStream_t st, const float* partial, int nparts, const double* loss_part,
                      double loss_scale, float* theta, float* m, float* v, const AdamArgs& a,
                      double* loss_hist) {
-  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(kParams, 256)), dim3(256), 0, st, partial, nparts,
-                     loss_part, loss_scale, theta, m, v, a, loss_hist);
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(kParams, kRedParams)), dim3(256), 0, st, partial,
+                     nparts, loss_part, loss_scale, theta, m, v, a, loss_hist);
   DH_LAUNCH_CHECK();
 }
 
