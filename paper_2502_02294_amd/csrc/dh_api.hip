@@ -108,7 +108,7 @@ struct dh_sim {
   StepScal* hstage = nullptr;     // pinned staging of cur_tab / stage_tab
 
   // adjoint buffers
-  float *lq = nullptr, *lq2 = nullptr, *lh = nullptr, *lx = nullptr, *lp = nullptr,
+  float *lq = nullptr, *lq2 = nullptr, *lx = nullptr, *lp = nullptr,
         *lphi = nullptr, *lphi2 = nullptr, *lg = nullptr, *ldelta = nullptr, *lpsi = nullptr,
         *lcic = nullptr;
   double* param_steps = nullptr;   // [cap][2 S] per-step dL/d(eps_sf, delta_c)
@@ -602,7 +602,7 @@ void step_vjp(dh_sim* s, const TapeStep& T) {
   dh::launch_deposit_vjp_pos(st, s->ldelta, T.x1, static_cast<float>(s->m_dm), s->lx, b);
   // sweeps in reverse
   for (int k = 2; k >= 0; --k) {
-    dh::launch_sweep_vjp(st, T.q[1 + k], s->lq, s->lq2, s->lh, b, sp.axes[k]);
+    dh::launch_sweep_vjp(st, T.q[1 + k], s->lq, s->lq2, b, sp.axes[k]);
     std::swap(s->lq, s->lq2);
   }
   // drift: x1 = x0 + p_half dt / a_h^2
@@ -1096,7 +1096,6 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     if (!s->lq) {
       s->lq = s->alloc<float>(5 * nc * S);
       s->lq2 = s->alloc<float>(5 * nc * S);
-      s->lh = s->alloc<float>(5 * nc * S);
       s->lx = s->alloc<float>(3 * np * S);
       s->lp = s->alloc<float>(3 * np * S);
       s->lphi = s->alloc<float>(nc * S);
@@ -1105,8 +1104,6 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
       s->ldelta = s->alloc<float>(nc * S);
       s->lpsi = s->alloc<float>(3 * nc * S);
       s->lcic = s->alloc<float>(nc * S);
-    } else if (s->lh == nullptr) {
-      s->lh = s->alloc<float>(5 * nc * S);
     }
     if (s->param_cap < nsteps + 2) {
       if (s->param_steps) s->release(s->param_steps);
@@ -1233,14 +1230,13 @@ int dh_stage_sweep_vjp(dh_sim* s, const float* d_q_in, const float* d_lam_out, f
                        int32_t axis, double dt, double a1, double a2) {
   if (!s || !d_q_in || !d_lam_out || !d_lam_in || axis < 0 || axis > 2) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
-    if (!s->lh) s->lh = s->alloc<float>(5 * s->nc * s->S);
     StepScal e{};
     e.active = 1;
     e.dt = static_cast<float>(dt);
     e.h1 = hydro_at(s, a1);
     e.h2 = hydro_at(s, a2);
-    dh::launch_sweep_vjp(s->st, d_q_in, d_lam_out, d_lam_in, s->lh,
-                         Batch{s->n, 1, stage_table(s, e)}, axis);
+    dh::launch_sweep_vjp(s->st, d_q_in, d_lam_out, d_lam_in, Batch{s->n, 1, stage_table(s, e)},
+                         axis);
     return DH_OK;
   });
 }

@@ -38,6 +38,14 @@ inline unsigned blocks_for(long long work, int threads) {
 //   F = (rho U_d / a, rho U_d U + p e_d, a U_d (Et/a^2 + p)),
 //   F^R = (c Q + F)/2, F^L = (c Q - F)/2.
 // ---------------------------------------------------------------------------------------
+// Reciprocal and square root on the hardware's approximate units (v_rcp_f32, v_sqrt_f32:
+// within 1 ulp).  The hydro kernels take these in place of the correctly rounded division
+// and square root, which expand to about ten instructions each; every operand here is a
+// normal positive number (density, floored energy) or bounded away from zero (limiter
+// denominator), and the error stays at the level of one FP32 rounding.
+__device__ __forceinline__ float rcp_approx(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt_approx(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 struct HydroK {
   float a, ia, ia2;   // scale factor, 1/a, 1/a^2
   float gm1, gg1;     // gamma-1, gamma*(gamma-1)
@@ -59,13 +67,13 @@ template <int D>
 __device__ __forceinline__ void split_flux(const float q[5], const HydroK& h, float fr[5],
                                            float fl[5]) {
   const float rho = q[0];
-  const float ir = 1.0f / rho;
+  const float ir = rcp_approx(rho);
   const float u0 = q[1] * h.ia * ir, u1 = q[2] * h.ia * ir, u2 = q[3] * h.ia * ir;
   const float ke = 0.5f * (u0 * u0 + u1 * u1 + u2 * u2);
   float e = q[4] * h.ia2 * ir - ke;
   e = fmaxf(e, h.efloor);
   const float p = h.gm1 * rho * e;
-  const float cs = sqrtf(h.gg1 * e);
+  const float cs = sqrt_approx(h.gg1 * e);
   const float ud = D == 0 ? u0 : (D == 1 ? u1 : u2);
   const float c = (fabsf(ud) + cs) * h.ia;
   float f[5];
@@ -91,25 +99,29 @@ __device__ __forceinline__ void split_flux_vjp(const float q[5], const HydroK& h
                                                const float s[5], const float dv[5],
                                                float out[5]) {
   const float rho = q[0];
-  const float ir = 1.0f / rho;
-  const float u[3] = {q[1] * h.ia * ir, q[2] * h.ia * ir, q[3] * h.ia * ir};
+  const float ir = rcp_approx(rho);
+  const float iar = h.ia * ir;
+  const float u[3] = {q[1] * iar, q[2] * iar, q[3] * iar};
   const float ke = 0.5f * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   const float eraw = q[4] * h.ia2 * ir - ke;
-  const bool floored = eraw < h.efloor;
-  const float e = floored ? h.efloor : eraw;
+  // 0 where the floor is active (its derivative), 1 elsewhere; every term is computed and
+  // masked, so the function has no branches
+  const float live = eraw < h.efloor ? 0.0f : 1.0f;
+  const float e = fmaxf(eraw, h.efloor);
   const float p = h.gm1 * rho * e;
-  const float cs = sqrtf(h.gg1 * e);
+  const float cs = sqrt_approx(h.gg1 * e);
   const float ud = u[D];
   const float md = q[1 + D];
   const float sgn = md > 0.0f ? 1.0f : (md < 0.0f ? -1.0f : 0.0f);
   const float c = (fabsf(ud) + cs) * h.ia;
 
   // derivatives of e (zero when floored)
-  const float er = floored ? 0.0f : (ke - e) * ir;
+  const float er = live * (ke - e) * ir;
+  const float liar = -live * iar;
   float em[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) em[k] = floored ? 0.0f : -u[k] * h.ia * ir;
-  const float eE = floored ? 0.0f : h.ia2 * ir;
+  for (int k = 0; k < 3; ++k) em[k] = liar * u[k];
+  const float eE = live * h.ia2 * ir;
   // pressure derivatives
   const float pr = h.gm1 * (e + rho * er);
   float pm[3];
@@ -117,11 +129,11 @@ __device__ __forceinline__ void split_flux_vjp(const float q[5], const HydroK& h
   for (int k = 0; k < 3; ++k) pm[k] = h.gm1 * rho * em[k];
   const float pE = h.gm1 * rho * eE;
   // freezing-speed derivatives
-  const float cse = floored ? 0.0f : 0.5f * h.gg1 / cs;
+  const float cse = live > 0.0f ? 0.5f * h.gg1 * rcp_approx(cs) : 0.0f;   // cs may be 0 if floored
   const float cr = h.ia * (-fabsf(ud) * ir + cse * er);
   float cm[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) cm[k] = h.ia * ((k == D ? sgn * h.ia * ir : 0.0f) + cse * em[k]);
+  for (int k = 0; k < 3; ++k) cm[k] = h.ia * ((k == D ? sgn * iar : 0.0f) + cse * em[k]);
   const float cE = h.ia * cse * eE;
 
   const float qs = q[0] * s[0] + q[1] * s[1] + q[2] * s[2] + q[3] * s[3] + q[4] * s[4];
@@ -143,17 +155,41 @@ __device__ __forceinline__ void split_flux_vjp(const float q[5], const HydroK& h
 
 // van Leer limiter with guard epsilon (Sec. 2.3.2):
 //   phi(x, y) = (x y + |x y|) / (x + y + eps sgn(x+y)),  sgn(0) = +1,
-// evaluated as 2xy / (x + y + eps sgn) when xy > 0 and 0 otherwise.  The branch is the same
-// function; it matters in floating point: with fused multiply-add contraction the sum
+// evaluated as 2xy / (x + y + eps sgn) when xy > 0 and 0 otherwise.  The selection is the
+// same function; it matters in floating point: with fused multiply-add contraction the sum
 // x*y + |x*y| is not exactly zero for xy < 0, and where x ~ -y the residue would be divided by
-// a denominator of order eps.
+// a denominator of order eps.  Both sides of the selection are computed (no branch); the
+// discarded one is finite or an infinity, never read.
 constexpr float kLimEps = 1e-20f;
 
 __device__ __forceinline__ float van_leer(float x, float y) {
   const float xy = x * y;
-  if (!(xy > 0.0f)) return 0.0f;
   const float s = x + y;
-  return (2.0f * xy) / (s + (s >= 0.0f ? kLimEps : -kLimEps));
+  const float r = (2.0f * xy) * rcp_approx(s + (s >= 0.0f ? kLimEps : -kLimEps));
+  return xy > 0.0f ? r : 0.0f;
+}
+
+// van_leer(a/2, b/2) of two undivided differences, written as a b / (a + b + 2 eps sgn(a+b)).
+// The sign of a zero sum is immaterial: it only occurs where a b <= 0.
+__device__ __forceinline__ float van_leer_half(float a, float b) {
+  const float ab = a * b;
+  const float s = a + b;
+  const float r = ab * rcp_approx(s + __builtin_copysignf(2.0f * kLimEps, s));
+  return ab > 0.0f ? r : 0.0f;
+}
+
+// Partial derivatives of van_leer_half with respect to a and b.  Where a b == 0 the derivative
+// of |a b| is taken with sign(0) = 0 (half the one-sided slopes), where a b < 0 both are zero.
+__device__ __forceinline__ void van_leer_half_d(float a, float b, float& da, float& db) {
+  const float ab = a * b;
+  const float s = a + b;
+  const float id = rcp_approx(s + __builtin_copysignf(2.0f * kLimEps, s));
+  const float q = ab * id * id;
+  const float hb = b * id, ha = a * id;
+  const float pa = hb - q, pb = ha - q;
+  const float za = ab < 0.0f ? 0.0f : 0.5f * hb, zb = ab < 0.0f ? 0.0f : 0.5f * ha;
+  da = ab > 0.0f ? pa : za;
+  db = ab > 0.0f ? pb : zb;
 }
 
 // Partial derivatives of van_leer; where xy == 0 the derivative of |xy| is taken with
@@ -162,18 +198,13 @@ __device__ __forceinline__ void van_leer_d(float x, float y, float& dx, float& d
   const float xy = x * y;
   const float s = x + y;
   const float den = s + (s >= 0.0f ? kLimEps : -kLimEps);
-  const float id = 1.0f / den;
-  if (xy > 0.0f) {
-    const float q = (2.0f * xy) * id * id;
-    dx = 2.0f * y * id - q;
-    dy = 2.0f * x * id - q;
-  } else if (xy < 0.0f) {
-    dx = 0.0f;
-    dy = 0.0f;
-  } else {
-    dx = y * id;
-    dy = x * id;
-  }
+  const float id = rcp_approx(den);
+  const float q = (2.0f * xy) * id * id;
+  const float hy = y * id, hx = x * id;
+  const float px = 2.0f * hy - q, py = 2.0f * hx - q;
+  const float zx = xy < 0.0f ? 0.0f : hy, zy = xy < 0.0f ? 0.0f : hx;
+  dx = xy > 0.0f ? px : zx;
+  dy = xy > 0.0f ? py : zy;
 }
 
 // ---------------------------------------------------------------------------------------

@@ -43,9 +43,9 @@ __device__ __forceinline__ bool sample_active(const StepScal* tab, int smp) {
 
 // ---- hydro (k_hydro.hip): one sweep with dt, h1, h2 of the table (tab required)
 void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis);
-// lam_h_scratch: 5 n^3 floats per sample, used by the y/z adjoints
+// adjoint of one sweep: lam_in = (dU'/dU)^T lam_out at U = qin (not in place)
 void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
-                      float* lam_h_scratch, const Batch& b, int axis);
+                      const Batch& b, int axis);
 
 // ---- particle mesh (k_pm.hip)
 // Keys are global bins: sample * n^3 + CIC base cell, so one counting sort orders the

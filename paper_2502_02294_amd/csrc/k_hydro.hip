@@ -11,11 +11,11 @@
 // Stencil: U' at j depends on U at j-3..j+3 (periodic).
 //
 // Kernels
-//   sweep_x      x is contiguous: a block stages whole rows (512 cells) in LDS, two cells
+//   sweep_x      x is contiguous: a block stages whole rows (512 cells) in LDS, one cell
 //                per thread, so the periodic wrap stays inside the block.
 //   sweep_walk   y and z: each thread owns one (x, other) column and walks a segment of S
 //                cells along the pencil with a register pipeline (loads coalesced across x,
-//                3-cell halos re-read from cache).
+//                two cells prefetched, 3-cell halos re-read from cache).
 //   sweep_x_vjp  adjoint along x in LDS.
 //   vjp_walk_h + vjp_finish   adjoint along y/z in two passes: the first walks the pencil
 //                and writes lambda_h = dL/dUh, the second applies the stage-1 transpose
@@ -26,8 +26,8 @@ namespace dh {
 
 namespace {
 
-constexpr int kRowCells = 512;   // cells per x-sweep block (whole rows)
-constexpr int kRowThreads = 256;
+constexpr int kRowCells = 512;   // cells per x-sweep block (whole rows), one per thread
+constexpr int kRowThreads = kRowCells;
 
 __device__ __forceinline__ int wrap(int j, int n) { return j & (n - 1); }
 
@@ -40,123 +40,162 @@ __device__ __forceinline__ void copy_block(const float* __restrict__ in, float* 
     for (int c = 0; c < 5; ++c) out[c * nc + base + i] = in[c * nc + base + i];
 }
 
-// coefficients of the limited right-moving face flux FRf_m with respect to F^R at m-1, m, m+1
+// coefficients of the limited right-moving face flux FRf_m = F_m + phi((F_m - F_{m-1})/2,
+// (F_{m+1} - F_m)/2) with respect to F^R at m-1, m, m+1
 __device__ __forceinline__ void face_r_coef(float fm1, float f0, float fp1, float& cm1, float& c0,
                                             float& cp1) {
   float da, db;
-  van_leer_d(0.5f * (f0 - fm1), 0.5f * (fp1 - f0), da, db);
-  cm1 = -0.5f * da;
-  c0 = 1.0f + 0.5f * da - 0.5f * db;
-  cp1 = 0.5f * db;
+  van_leer_half_d(f0 - fm1, fp1 - f0, da, db);
+  cm1 = -da;
+  c0 = 1.0f + da - db;
+  cp1 = db;
 }
-// coefficients of the limited left-moving face flux FLf_m with respect to F^L at m, m+1, m+2
+// coefficients of the limited left-moving face flux FLf_m = F_{m+1} - phi((F_{m+1} - F_m)/2,
+// (F_{m+2} - F_{m+1})/2) with respect to F^L at m, m+1, m+2
 __device__ __forceinline__ void face_l_coef(float f0, float fp1, float fp2, float& c0, float& cp1,
                                             float& cp2) {
   float da, db;
-  van_leer_d(0.5f * (fp1 - f0), 0.5f * (fp2 - fp1), da, db);
-  c0 = 0.5f * da;
-  cp1 = 1.0f - 0.5f * da + 0.5f * db;
-  cp2 = -0.5f * db;
-}
-
-template <int D>
-__device__ __forceinline__ void call_split(int d, const float* q, const HydroK& h, float* fr,
-                                           float* fl) {
-  split_flux<D>(q, h, fr, fl);
+  van_leer_half_d(fp1 - f0, fp2 - fp1, da, db);
+  c0 = da;
+  cp1 = 1.0f - da + db;
+  cp2 = -db;
 }
 
 // ------------------------------------------------------------------------------- forward x
+// Whole rows in LDS, one cell per thread; the limited stage-2 flux is formed once per face.
 __global__ void __launch_bounds__(kRowThreads) sweep_x_kernel(const float* __restrict__ qin,
                                                               float* __restrict__ qout, int n,
                                                               long long nc,
                                                               const StepScal* __restrict__ tab) {
-  __shared__ float U[5][kRowCells];
   __shared__ float FR[5][kRowCells];
   __shared__ float FL[5][kRowCells];
   const long long base = static_cast<long long>(blockIdx.x) * kRowCells;
-  const int tid = threadIdx.x;
+  const int j = threadIdx.x;
   const StepScal& sc = tab[blockIdx.y];
   qin += blockIdx.y * 5 * nc;
   qout += blockIdx.y * 5 * nc;
   if (!sc.active) {
-    copy_block(qin, qout, nc, base, kRowCells, tid, kRowThreads);
+    copy_block(qin, qout, nc, base, kRowCells, j, kRowThreads);
     return;
   }
   const float dt = sc.dt;
   const HydroK h1 = sc.h1, h2 = sc.h2;
+  const float hdt = 0.5f * dt;
+  const int row0 = j - (j & (n - 1)), col = j & (n - 1);
+  const int jm = row0 + wrap(col - 1, n), jp = row0 + wrap(col + 1, n);
+  const int jpp = row0 + wrap(col + 2, n);
+  float u[5], fr[5], fl[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) u[c] = qin[c * nc + base + j];
+  split_flux<0>(u, h1, fr, fl);
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
-    U[c][tid] = qin[c * nc + base + tid];
-    U[c][tid + kRowThreads] = qin[c * nc + base + tid + kRowThreads];
+    FR[c][j] = fr[c];
+    FL[c][j] = fl[c];
   }
   __syncthreads();
-  const float hdt = 0.5f * dt;
+  float qh[5];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int j = tid + r * kRowThreads;
-    float q[5], fr[5], fl[5];
+  for (int c = 0; c < 5; ++c)
+    qh[c] = u[c] - hdt * ((fr[c] - FL[c][jp]) - (FR[c][jm] - fl[c]));
+  split_flux<0>(qh, h2, fr, fl);
+  __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 5; ++c) q[c] = U[c][j];
-    split_flux<0>(q, h1, fr, fl);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      FR[c][j] = fr[c];
-      FL[c][j] = fl[c];
-    }
+  for (int c = 0; c < 5; ++c) {
+    FR[c][j] = fr[c];
+    FL[c][j] = fl[c];
   }
   __syncthreads();
-  float r2[2][5], l2[2][5];
+  float f2[5];   // limited stage-2 flux of face j+1/2
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int j = tid + r * kRowThreads;
-    const int row0 = j - (j & (n - 1));
-    const int col = j & (n - 1);
-    const int jp = row0 + wrap(col + 1, n), jm = row0 + wrap(col - 1, n);
-    float qh[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      const float fp = FR[c][j] - FL[c][jp];
-      const float fm = FR[c][jm] - FL[c][j];
-      qh[c] = U[c][j] - hdt * (fp - fm);
-    }
-    split_flux<0>(qh, h2, r2[r], l2[r]);
+  for (int c = 0; c < 5; ++c) {
+    const float rm1 = FR[c][jm], r0 = fr[c], rp1 = FR[c][jp];
+    const float l0 = fl[c], lp1 = FL[c][jp], lp2 = FL[c][jpp];
+    f2[c] = (r0 + van_leer_half(r0 - rm1, rp1 - r0)) - (lp1 - van_leer_half(lp1 - l0, lp2 - lp1));
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int j = tid + r * kRowThreads;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      FR[c][j] = r2[r][c];
-      FL[c][j] = l2[r][c];
-    }
-  }
+  for (int c = 0; c < 5; ++c) FR[c][j] = f2[c];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int j = tid + r * kRowThreads;
-    const int row0 = j - (j & (n - 1));
-    const int col = j & (n - 1);
-    const int jm2 = row0 + wrap(col - 2, n), jm1 = row0 + wrap(col - 1, n);
-    const int jp1 = row0 + wrap(col + 1, n), jp2 = row0 + wrap(col + 2, n);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      const float rm2 = FR[c][jm2], rm1 = FR[c][jm1], r0 = FR[c][j], rp1 = FR[c][jp1];
-      const float lm1 = FL[c][jm1], l0 = FL[c][j], lp1 = FL[c][jp1], lp2 = FL[c][jp2];
-      // face j+1/2
-      const float frp = r0 + van_leer(0.5f * (r0 - rm1), 0.5f * (rp1 - r0));
-      const float flp = lp1 - van_leer(0.5f * (lp1 - l0), 0.5f * (lp2 - lp1));
-      // face j-1/2
-      const float frm = rm1 + van_leer(0.5f * (rm1 - rm2), 0.5f * (r0 - rm1));
-      const float flm = l0 - van_leer(0.5f * (l0 - lm1), 0.5f * (lp1 - l0));
-      qout[c * nc + base + j] = U[c][j] - dt * ((frp - flp) - (frm - flm));
-    }
-  }
+  for (int c = 0; c < 5; ++c) qout[c * nc + base + j] = u[c] - dt * (f2[c] - FR[c][jm]);
 }
 
 // ---------------------------------------------------------------------- forward y / z walk
 // Thread t: x = t % n, other = (t / n) % n, segment = t / n^2.  Column base and stride:
 //   D = 1 (y): base = other*n*n + x, stride n;   D = 2 (z): base = other*n + x, stride n*n.
+// The thread visits cells k = s-3 .. s+seg+2; at visit i (cell k = s-3+i) it loads cell
+// k+kAhead, splits U_k, forms the stage-1 face k-1/2, the half step and stage-2 split of cell
+// k-1, the limited stage-2 face (k-3)+1/2 and the update of cell k-3.  Every carried quantity
+// sits in a ring indexed by the visit number, so with the visits unrolled eight at a time all
+// ring slots are compile-time registers and nothing is shifted.  Offsets within one sample are
+// 32-bit (at most 5 * 256^3 floats).
+constexpr int kAhead = 4;   // cells loaded ahead of the one being split
+
+template <int D>
+struct WalkFwd {
+  float u[8][5];             // U of cell k - j in slot (i - j) & 7 (j = -kAhead .. 3)
+  float r1[2][5];            // stage-1 F^R of cell k - j in slot (i - j) & 1
+  float f1[2][5];            // stage-1 face flux (k - j) - 1/2 in slot (i - j) & 1
+  float r2[4][5], l2[4][5];  // stage-2 split of cell k - 1 - j in slot (i - j) & 3
+  float f2[2][5];            // limited stage-2 face (k - 3 - j) + 1/2 in slot (i - j) & 1
+};
+
+struct WalkPtr {
+  const float* __restrict__ q[5];
+  float* __restrict__ o[5];
+  unsigned base, stride;   // in bytes
+  int n;
+  // byte offset of cell k of the column (periodic)
+  __device__ __forceinline__ unsigned at(int k) const {
+    return base + static_cast<unsigned>(k & (n - 1)) * stride;
+  }
+  __device__ __forceinline__ float ld(int c, unsigned off) const {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(q[c]) + off);
+  }
+  __device__ __forceinline__ void st(int c, unsigned off, float v) const {
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(o[c]) + off) = v;
+  }
+};
+
+template <int D, int I, int STAGE>
+__device__ __forceinline__ void walk_fwd_visit(WalkFwd<D>& w, const WalkPtr& p, int k,
+                                               const HydroK& h1, const HydroK& h2, float dt,
+                                               float hdt) {
+  constexpr int s0 = I & 7, s1 = (I + 7) & 7, s3 = (I + 5) & 7, sa = (I + kAhead) & 7;
+  constexpr int t0 = I & 3, t1 = (I + 3) & 3, t2 = (I + 2) & 3, t3 = (I + 1) & 3;
+  constexpr int p0 = I & 1, p1 = (I + 1) & 1;
+  {
+    const unsigned off = p.at(k + kAhead);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) w.u[sa][c] = p.ld(c, off);
+  }
+  float l1[5];
+  split_flux<D>(w.u[s0], h1, w.r1[p0], l1);
+  if (STAGE < 1) return;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) w.f1[p0][c] = w.r1[p1][c] - l1[c];   // face k-1/2
+  if (STAGE < 2) return;
+  float qh[5];   // half step of cell k-1 from faces (k-1) -+ 1/2
+#pragma unroll
+  for (int c = 0; c < 5; ++c) qh[c] = w.u[s1][c] - hdt * (w.f1[p0][c] - w.f1[p1][c]);
+  split_flux<D>(qh, h2, w.r2[t0], w.l2[t0]);
+  if (STAGE < 3) return;
+  // face (k-3)+1/2: F^R at cells k-4, k-3, k-2 (slots t3, t2, t1), F^L at k-3, k-2, k-1
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const float rm = w.r2[t3][c], r0 = w.r2[t2][c], rp = w.r2[t1][c];
+    const float l0 = w.l2[t2][c], lp = w.l2[t1][c], lpp = w.l2[t0][c];
+    const float fr = r0 + van_leer_half(r0 - rm, rp - r0);
+    const float fl = lp - van_leer_half(lp - l0, lpp - lp);
+    w.f2[p0][c] = fr - fl;
+  }
+  if (STAGE < 4) return;
+  const unsigned off = p.at(k - 3);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) p.st(c, off, w.u[s3][c] - dt * (w.f2[p0][c] - w.f2[p1][c]));
+}
+
 template <int D>
 __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict__ qin,
                                                          float* __restrict__ qout, int n,
@@ -167,409 +206,369 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
   const int x = static_cast<int>(t % n);
   const int other = static_cast<int>((t / n) % n);
   const int seg = static_cast<int>(t / (static_cast<long long>(n) * n));
-  const long long base = D == 1 ? static_cast<long long>(other) * n * n + x
-                                : static_cast<long long>(other) * n + x;
-  const long long stride = D == 1 ? n : static_cast<long long>(n) * n;
+  WalkPtr p;
+  p.n = n;
+  p.base = 4u * (D == 1 ? static_cast<unsigned>(other) * n * n + x
+                        : static_cast<unsigned>(other) * n + x);
+  p.stride = 4u * (D == 1 ? n : static_cast<unsigned>(n) * n);
   const int s = seg * seg_len;
   const StepScal& sc = tab[blockIdx.y];
-  qin += blockIdx.y * 5 * nc;
-  qout += blockIdx.y * 5 * nc;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    p.q[c] = qin + (blockIdx.y * 5 + c) * nc;
+    p.o[c] = qout + (blockIdx.y * 5 + c) * nc;
+  }
   if (!sc.active) {
     for (int i = 0; i < seg_len; ++i) {
-      const long long off = base + static_cast<long long>(s + i) * stride;
+      const unsigned off = p.at(s + i);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) qout[c * nc + off] = qin[c * nc + off];
+      for (int c = 0; c < 5; ++c) p.st(c, off, p.ld(c, off));
     }
     return;
   }
   const float dt = sc.dt;
   const HydroK h1 = sc.h1, h2 = sc.h2;
   const float hdt = 0.5f * dt;
-
-  float ut[4][5];          // U at k-3 .. k
-  float r1[2][5], l1[2][5];  // stage-1 split fluxes at k-1, k
-  float f1prev[5];         // F1 at (k-1)-1/2
-  float r2[4][5], l2[4][5];  // stage-2 split fluxes at k-4 .. k-1
-  float f2prev[5];         // F2 at (k-3)-1/2
-  float nxt[5];
-  {
-    const long long off = base + static_cast<long long>(wrap(s - 3, n)) * stride;
+  WalkFwd<D> w;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) nxt[c] = qin[c * nc + off];
+  for (int j = 0; j < kAhead; ++j) {
+    const unsigned off = p.at(s - 3 + j);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) w.u[j][c] = p.ld(c, off);
   }
-  const int iters = seg_len + 6;
-  for (int i = 0; i < iters; ++i) {
-    const int k = s - 3 + i;
-#pragma unroll
-    for (int w = 0; w < 3; ++w)
-#pragma unroll
-      for (int c = 0; c < 5; ++c) ut[w][c] = ut[w + 1][c];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) ut[3][c] = nxt[c];
-    if (i + 1 < iters) {
-      const long long off = base + static_cast<long long>(wrap(k + 1, n)) * stride;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) nxt[c] = qin[c * nc + off];
-    }
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      r1[0][c] = r1[1][c];
-      l1[0][c] = l1[1][c];
-    }
-    split_flux<D>(ut[3], h1, r1[1], l1[1]);
-    if (i >= 1) {
-      float f1[5];
-#pragma unroll
-      for (int c = 0; c < 5; ++c) f1[c] = r1[0][c] - l1[1][c];   // face k-1/2
-      if (i >= 2) {
-        float qh[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) qh[c] = ut[2][c] - hdt * (f1[c] - f1prev[c]);  // cell k-1
-#pragma unroll
-        for (int w = 0; w < 3; ++w)
-#pragma unroll
-          for (int c = 0; c < 5; ++c) {
-            r2[w][c] = r2[w + 1][c];
-            l2[w][c] = l2[w + 1][c];
-          }
-        split_flux<D>(qh, h2, r2[3], l2[3]);
-        if (i >= 5) {
-          float f2[5];   // face (k-3)+1/2
-#pragma unroll
-          for (int c = 0; c < 5; ++c) {
-            const float fr = r2[1][c] + van_leer(0.5f * (r2[1][c] - r2[0][c]),
-                                                 0.5f * (r2[2][c] - r2[1][c]));
-            const float fl = l2[2][c] - van_leer(0.5f * (l2[2][c] - l2[1][c]),
-                                                 0.5f * (l2[3][c] - l2[2][c]));
-            f2[c] = fr - fl;
-          }
-          if (i >= 6) {
-            const long long off = base + static_cast<long long>(wrap(k - 3, n)) * stride;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) qout[c * nc + off] = ut[0][c] - dt * (f2[c] - f2prev[c]);
-          }
-#pragma unroll
-          for (int c = 0; c < 5; ++c) f2prev[c] = f2[c];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 5; ++c) f1prev[c] = f1[c];
-    }
+  // visits 0..5 fill the pipeline; from visit 6 on every visit writes a cell
+  walk_fwd_visit<D, 0, 0>(w, p, s - 3, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 1, 1>(w, p, s - 2, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 2, 2>(w, p, s - 1, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 3, 2>(w, p, s, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 4, 2>(w, p, s + 1, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 5, 3>(w, p, s + 2, h1, h2, dt, hdt);
+  // seg_len is a multiple of 8: visits 6 + 8m .. 13 + 8m have ring phases 6, 7, 0, .., 5
+  for (int k = s + 3; k < s + 3 + seg_len; k += 8) {
+    walk_fwd_visit<D, 6, 4>(w, p, k, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 7, 4>(w, p, k + 1, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 0, 4>(w, p, k + 2, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 1, 4>(w, p, k + 3, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 2, 4>(w, p, k + 4, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 3, 4>(w, p, k + 5, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 4, 4>(w, p, k + 6, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 5, 4>(w, p, k + 7, h1, h2, dt, hdt);
   }
 }
 
 // --------------------------------------------------------------------------- adjoint x
+// Whole rows in LDS, one cell per thread, each face handled once:
+//   1. U, lambda' from memory; stage-1 split of the own cell into LDS.
+//   2. half step Uh and its stage-2 split into LDS.
+//   3. per face m: G2_m = -dt (lambda'_m - lambda'_{m+1}) times the limiter coefficients gives
+//      the adjoints of F^R at m-1, m, m+1 and of F^L at m, m+1, m+2; the own-cell terms stay in
+//      registers, the four that belong to neighbours go through LDS.
+//   4. lambda_h = split VJP at Uh of the gathered adjoints.
+//   5. stage-1 transpose: lambda = lambda' + lambda_h + split VJP at U of (G1_j, -G1_{j-1}),
+//      G1_m = -dt/2 (lambda_h_m - lambda_h_{m+1}).
 __global__ void __launch_bounds__(kRowThreads) sweep_x_vjp_kernel(
     const float* __restrict__ qin, const float* __restrict__ lam_out, float* __restrict__ lam_in,
     int n, long long nc, const StepScal* __restrict__ tab) {
-  __shared__ float U[5][kRowCells];
-  __shared__ float L[5][kRowCells];
-  __shared__ float FR[5][kRowCells];
-  __shared__ float FL[5][kRowCells];
-  __shared__ float LH[5][kRowCells];
+  __shared__ float S[5][5][kRowCells];
   const long long base = static_cast<long long>(blockIdx.x) * kRowCells;
-  const int tid = threadIdx.x;
+  const int j = threadIdx.x;
   const StepScal& sc = tab[blockIdx.y];
   qin += blockIdx.y * 5 * nc;
   lam_out += blockIdx.y * 5 * nc;
   lam_in += blockIdx.y * 5 * nc;
   if (!sc.active) {
-    copy_block(lam_out, lam_in, nc, base, kRowCells, tid, kRowThreads);
+    copy_block(lam_out, lam_in, nc, base, kRowCells, j, kRowThreads);
     return;
   }
   const float dt = sc.dt;
   const HydroK h1 = sc.h1, h2 = sc.h2;
-#pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    U[c][tid] = qin[c * nc + base + tid];
-    U[c][tid + kRowThreads] = qin[c * nc + base + tid + kRowThreads];
-    L[c][tid] = lam_out[c * nc + base + tid];
-    L[c][tid + kRowThreads] = lam_out[c * nc + base + tid + kRowThreads];
-  }
-  __syncthreads();
   const float hdt = 0.5f * dt;
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int j = tid + r * kRowThreads;
-    float q[5], fr[5], fl[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) q[c] = U[c][j];
-    split_flux<0>(q, h1, fr, fl);
+  const int row0 = j - (j & (n - 1)), col = j & (n - 1);
+  const int jm = row0 + wrap(col - 1, n), jmm = row0 + wrap(col - 2, n);
+  const int jp = row0 + wrap(col + 1, n), jpp = row0 + wrap(col + 2, n);
+  float u[5], lm[5];
+  {  // 1. S[0] = lambda', S[1] = F^R(U), S[2] = F^L(U)
+    float fr[5], fl[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      FR[c][j] = fr[c];
-      FL[c][j] = fl[c];
+      u[c] = qin[c * nc + base + j];
+      lm[c] = lam_out[c * nc + base + j];
+    }
+    split_flux<0>(u, h1, fr, fl);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      S[0][c][j] = lm[c];
+      S[1][c][j] = fr[c];
+      S[2][c][j] = fl[c];
     }
   }
   __syncthreads();
-  float qh[2][5], r2[2][5], l2[2][5];
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int j = tid + r * kRowThreads;
-    const int row0 = j - (j & (n - 1));
-    const int col = j & (n - 1);
-    const int jp = row0 + wrap(col + 1, n), jm = row0 + wrap(col - 1, n);
+  float qh[5];
+  {  // 2. S[3] = F^R(Uh), S[4] = F^L(Uh)
+    float fr[5], fl[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c)
-      qh[r][c] = U[c][j] - hdt * ((FR[c][j] - FL[c][jp]) - (FR[c][jm] - FL[c][j]));
-    split_flux<0>(qh[r], h2, r2[r], l2[r]);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int j = tid + r * kRowThreads;
+      qh[c] = u[c] - hdt * ((S[1][c][j] - S[2][c][jp]) - (S[1][c][jm] - S[2][c][j]));
+    split_flux<0>(qh, h2, fr, fl);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      FR[c][j] = r2[r][c];
-      FL[c][j] = l2[r][c];
+      S[3][c][j] = fr[c];
+      S[4][c][j] = fl[c];
     }
   }
   __syncthreads();
-  // lambda_h_j = VJP of the split at Uh_j with gR_j, gL_j gathered from the faces around j.
+  // 3. face m = j; S[1], S[2] are free since step 2
+  float gr[5], gl[5], xl1[5], xl2[5];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int j = tid + r * kRowThreads;
-    const int row0 = j - (j & (n - 1));
-    const int col = j & (n - 1);
-    int idx[7];
+  for (int c = 0; c < 5; ++c) {
+    const float g = -dt * (S[0][c][j] - S[0][c][jp]);
+    float a0, a1, a2, b0, b1, b2;
+    face_r_coef(S[3][c][jm], S[3][c][j], S[3][c][jp], a0, a1, a2);
+    face_l_coef(S[4][c][j], S[4][c][jp], S[4][c][jpp], b0, b1, b2);
+    S[1][c][j] = g * a0;   // F^R at m-1
+    gr[c] = g * a1;        // F^R at m
+    S[2][c][j] = g * a2;   // F^R at m+1
+    gl[c] = -g * b0;       // F^L at m
+    xl1[c] = -g * b1;      // F^L at m+1
+    xl2[c] = -g * b2;      // F^L at m+2
+  }
+  __syncthreads();
 #pragma unroll
-    for (int o = -3; o <= 3; ++o) idx[o + 3] = row0 + wrap(col + o, n);
-    float gR[5], gL[5];
+  for (int c = 0; c < 5; ++c) {
+    S[3][c][j] = xl1[c];
+    S[4][c][j] = xl2[c];
+  }
+  __syncthreads();
+  {  // 4. lambda_h into S[0]
+    float sv[5], dv[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      float fr[5], fl[5], lm[5];
-#pragma unroll
-      for (int o = -2; o <= 2; ++o) {
-        fr[o + 2] = FR[c][idx[o + 3]];
-        fl[o + 2] = FL[c][idx[o + 3]];
-      }
-#pragma unroll
-      for (int o = -2; o <= 2; ++o) lm[o + 2] = L[c][idx[o + 3]];
-      // G2_m = dL/dF2_{m+1/2} = -dt (lambda_m - lambda_{m+1}); fr/fl/lm index o+2 <-> j+o
-      float acc = 0.0f;
-      {  // R faces m = j-1, j, j+1
-        float a0, a1, a2;
-        face_r_coef(fr[0], fr[1], fr[2], a0, a1, a2);   // m = j-1: coefficient of j is a2
-        acc += -dt * (lm[1] - lm[2]) * a2;
-        face_r_coef(fr[1], fr[2], fr[3], a0, a1, a2);   // m = j: coefficient of j is a1
-        acc += -dt * (lm[2] - lm[3]) * a1;
-        face_r_coef(fr[2], fr[3], fr[4], a0, a1, a2);   // m = j+1: coefficient of j is a0
-        acc += -dt * (lm[3] - lm[4]) * a0;
-      }
-      gR[c] = acc;
-      acc = 0.0f;
-      {  // L faces m = j-2, j-1, j; dL/dFLf = -G2
-        float b0, b1, b2;
-        face_l_coef(fl[0], fl[1], fl[2], b0, b1, b2);   // m = j-2: coefficient of j is b2
-        acc += dt * (lm[0] - lm[1]) * b2;
-        face_l_coef(fl[1], fl[2], fl[3], b0, b1, b2);   // m = j-1: coefficient of j is b1
-        acc += dt * (lm[1] - lm[2]) * b1;
-        face_l_coef(fl[2], fl[3], fl[4], b0, b1, b2);   // m = j: coefficient of j is b0
-        acc += dt * (lm[2] - lm[3]) * b0;
-      }
-      gL[c] = acc;
+      const float gR = gr[c] + S[2][c][jm] + S[1][c][jp];
+      const float gL = gl[c] + S[3][c][jm] + S[4][c][jmm];
+      sv[c] = gR + gL;
+      dv[c] = gR - gL;
     }
+    split_flux_vjp<0>(qh, h2, sv, dv, gr);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) S[0][c][j] = gr[c];
+  }
+  __syncthreads();
+  {  // 5. stage-1 transpose
     float sv[5], dv[5], out[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      sv[c] = gR[c] + gL[c];
-      dv[c] = gR[c] - gL[c];
-    }
-    split_flux_vjp<0>(qh[r], h2, sv, dv, out);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) LH[c][j] = out[c];
-  }
-  __syncthreads();
-  // stage-1 transpose: gR1_j = G1_{j+1/2}, gL1_j = -G1_{j-1/2}, G1_m = -dt/2 (lh_m - lh_{m+1})
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int j = tid + r * kRowThreads;
-    const int row0 = j - (j & (n - 1));
-    const int col = j & (n - 1);
-    const int jp = row0 + wrap(col + 1, n), jm = row0 + wrap(col - 1, n);
-    float q[5], sv[5], dv[5], out[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      q[c] = U[c][j];
-      const float gp = -hdt * (LH[c][j] - LH[c][jp]);
-      const float gm = -hdt * (LH[c][jm] - LH[c][j]);
+      const float gp = -hdt * (gr[c] - S[0][c][jp]);
+      const float gm = -hdt * (S[0][c][jm] - gr[c]);
       sv[c] = gp - gm;
       dv[c] = gp + gm;
     }
-    split_flux_vjp<0>(q, h1, sv, dv, out);
+    split_flux_vjp<0>(u, h1, sv, dv, out);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) lam_in[c * nc + base + j] = L[c][j] + LH[c][j] + out[c];
+    for (int c = 0; c < 5; ++c) lam_in[c * nc + base + j] = lm[c] + gr[c] + out[c];
   }
 }
 
-// ----------------------------------------------------------------- adjoint y / z, pass 1
+// ------------------------------------------------------------------------ adjoint y / z walk
+// One pass per column segment.  At visit i the thread holds cell k = s-4+i as the newest U and
+// lambda' and, with the rings of the forward walk:
+//   splits U_k at a1, forms F1_{k-1/2}, the half step Uh_{k-1} and its split at a2;
+//   pushes G2 of R face k-2 and L face k-3 (G2_m = -dt (lambda'_m - lambda'_{m+1})) through the
+//   limiter coefficients into the adjoints gR, gL of cells k-3 .. k-1 (cell k-3 is then
+//   complete);
+//   lambda_h_{k-3} = split VJP at Uh_{k-3}; G1_{k-4} = -dt/2 (lambda_h_{k-4} - lambda_h_{k-3});
+//   lambda_{k-4} = lambda'_{k-4} + lambda_h_{k-4} + split VJP at U_{k-4} of (G1_{k-4}, -G1_{k-5}).
+// Output cell c needs U at c-4 .. c+4 and lambda' at c-3 .. c+3, so a segment of seg cells
+// takes seg + 8 visits.
+constexpr int kAheadU = 2;   // U loaded this many cells ahead of the newest one
+constexpr int kAheadL = 1;   // lambda' likewise
+
+struct WalkVjp {
+  float u[8][5];             // U of cell k - j in slot (i - j) & 7
+  float lm[8][5];            // lambda' of cell k - j in slot (i - j) & 7
+  float r1[2][5];            // stage-1 F^R of cell k - j in slot (i - j) & 1
+  float f1[2][5];            // F1 of face (k - j) - 1/2 in slot (i - j) & 1
+  float uh[4][5];            // Uh of cell k - 1 - j in slot (i - j) & 3
+  float r2[4][5], l2[4][5];  // stage-2 split of cell k - 1 - j in slot (i - j) & 3
+  float gr[4][5], gl[4][5];  // adjoints of F^R, F^L of cell k - 1 - j in slot (i - j) & 3
+  float lh[2][5];            // lambda_h of cell k - 3 - j in slot (i - j) & 1
+  float g1[2][5];            // G1 of face (k - 4 - j) + 1/2 in slot (i - j) & 1
+};
+
+// Returns x unchanged through an empty asm statement, so that the compiler cannot reuse
+// values it derived from x visits earlier (it would keep them in registers that long).
+__device__ __forceinline__ float opaque(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+struct WalkVjpPtr {
+  const float* __restrict__ q[5];
+  const float* __restrict__ l[5];
+  float* __restrict__ o[5];
+  unsigned base, stride;   // in bytes
+  int n;
+  __device__ __forceinline__ unsigned at(int k) const {
+    return base + static_cast<unsigned>(k & (n - 1)) * stride;
+  }
+  __device__ __forceinline__ static float ld(const float* p, unsigned off) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(p) + off);
+  }
+  __device__ __forceinline__ void st(int c, unsigned off, float v) const {
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(o[c]) + off) = v;
+  }
+};
+
+// STAGE: 0 split only, 1 + F1, 2 + half step and stage-2 split, 3 + first faces (every
+// adjoint assigned), 4 + faces, 5 + lambda_h, 6 + G1, 7 + output
+template <int D, int I, int STAGE>
+__device__ __forceinline__ void walk_vjp_visit(WalkVjp& w, const WalkVjpPtr& p, int k,
+                                               const HydroK& h1, const HydroK& h2, float dt,
+                                               float hdt) {
+  constexpr int u0 = I & 7, u1 = (I + 7) & 7, u4 = (I + 4) & 7;
+  constexpr int ua = (I + kAheadU) & 7, la = (I + kAheadL) & 7;
+  constexpr int l1s = (I + 7) & 7, l2s = (I + 6) & 7, l3s = (I + 5) & 7;
+  constexpr int t0 = I & 3, t1 = (I + 3) & 3, t2 = (I + 2) & 3;
+  constexpr int p0 = I & 1, p1 = (I + 1) & 1;
+  // keep the scheduler from hoisting the loads of later visits (and their registers) up here
+  __builtin_amdgcn_sched_barrier(0);
+  {
+    const unsigned offu = p.at(k + kAheadU), offl = p.at(k + kAheadL);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      w.u[ua][c] = WalkVjpPtr::ld(p.q[c], offu);
+      w.lm[la][c] = WalkVjpPtr::ld(p.l[c], offl);
+    }
+  }
+  float l1[5];
+  split_flux<D>(w.u[u0], h1, w.r1[p0], l1);
+  if (STAGE < 1) return;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) w.f1[p0][c] = w.r1[p1][c] - l1[c];
+  if (STAGE < 2) return;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) w.uh[t0][c] = w.u[u1][c] - hdt * (w.f1[p0][c] - w.f1[p1][c]);
+  split_flux<D>(w.uh[t0], h2, w.r2[t0], w.l2[t0]);
+  if (STAGE < 3) return;
+  // R face k-2 (F^R at k-3, k-2, k-1), L face k-3 (F^L at k-3, k-2, k-1)
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    float a0, a1, a2;
+    face_r_coef(w.r2[t2][c], w.r2[t1][c], w.r2[t0][c], a0, a1, a2);
+    const float gR = -dt * (w.lm[l2s][c] - w.lm[l1s][c]);
+    float b0, b1, b2;
+    face_l_coef(w.l2[t2][c], w.l2[t1][c], w.l2[t0][c], b0, b1, b2);
+    const float gL = dt * (w.lm[l3s][c] - w.lm[l2s][c]);
+    if (STAGE == 3) {
+      w.gr[t2][c] = gR * a0;
+      w.gr[t1][c] = gR * a1;
+      w.gl[t2][c] = gL * b0;
+      w.gl[t1][c] = gL * b1;
+    } else {
+      w.gr[t2][c] += gR * a0;
+      w.gr[t1][c] += gR * a1;
+      w.gl[t2][c] += gL * b0;
+      w.gl[t1][c] += gL * b1;
+    }
+    w.gr[t0][c] = gR * a2;
+    w.gl[t0][c] = gL * b2;
+  }
+  if (STAGE < 5) return;
+  {  // lambda_h of cell k-3
+    float sv[5], dv[5], q[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      sv[c] = w.gr[t2][c] + w.gl[t2][c];
+      dv[c] = w.gr[t2][c] - w.gl[t2][c];
+      q[c] = opaque(w.uh[t2][c]);
+    }
+    split_flux_vjp<D>(q, h2, sv, dv, w.lh[p0]);
+  }
+  if (STAGE < 6) return;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) w.g1[p0][c] = -hdt * (w.lh[p1][c] - w.lh[p0][c]);   // face k-4+1/2
+  if (STAGE < 7) return;
+  {  // lambda of cell k-4
+    float sv[5], dv[5], out[5], q[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      sv[c] = w.g1[p0][c] - w.g1[p1][c];
+      dv[c] = w.g1[p0][c] + w.g1[p1][c];
+      q[c] = opaque(w.u[u4][c]);
+    }
+    split_flux_vjp<D>(q, h1, sv, dv, out);
+    const unsigned off = p.at(k - 4);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) p.st(c, off, w.lm[u4][c] + w.lh[p1][c] + out[c]);
+  }
+}
+
 template <int D>
-__global__ void __launch_bounds__(256) vjp_walk_h_kernel(const float* __restrict__ qin,
-                                                         const float* __restrict__ lam_out,
-                                                         float* __restrict__ lam_h, int n,
-                                                         long long nc, int seg_len, int nseg,
-                                                         const StepScal* __restrict__ tab) {
+__global__ void __launch_bounds__(256) sweep_walk_vjp_kernel(const float* __restrict__ qin,
+                                                             const float* __restrict__ lam_out,
+                                                             float* __restrict__ lam_in, int n,
+                                                             long long nc, int seg_len, int nseg,
+                                                             const StepScal* __restrict__ tab) {
   const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<long long>(n) * n * nseg) return;
-  const StepScal& sc = tab[blockIdx.y];
-  if (!sc.active) return;
-  qin += blockIdx.y * 5 * nc;
-  lam_out += blockIdx.y * 5 * nc;
-  lam_h += blockIdx.y * 5 * nc;
-  const float dt = sc.dt;
-  const HydroK h1 = sc.h1, h2 = sc.h2;
   const int x = static_cast<int>(t % n);
   const int other = static_cast<int>((t / n) % n);
   const int seg = static_cast<int>(t / (static_cast<long long>(n) * n));
-  const long long base = D == 1 ? static_cast<long long>(other) * n * n + x
-                                : static_cast<long long>(other) * n + x;
-  const long long stride = D == 1 ? n : static_cast<long long>(n) * n;
+  WalkVjpPtr p;
+  p.n = n;
+  p.base = 4u * (D == 1 ? static_cast<unsigned>(other) * n * n + x
+                        : static_cast<unsigned>(other) * n + x);
+  p.stride = 4u * (D == 1 ? n : static_cast<unsigned>(n) * n);
   const int s = seg * seg_len;
-  const float hdt = 0.5f * dt;
-
-  float ut[2][5];              // U at k-1, k
-  float r1[2][5], l1[2][5];    // stage-1 split at k-1, k
-  float f1prev[5];
-  float uh[3][5];              // Uh at k-3 .. k-1
-  float r2[3][5], l2[3][5];    // stage-2 split at k-3 .. k-1
-  float lm[4][5];              // lambda at k-3 .. k
-  float gR[3][5], gL[3][5];    // accumulators for cells k-3 .. k-1
-#pragma unroll
-  for (int w = 0; w < 3; ++w)
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      gR[w][c] = 0.0f;
-      gL[w][c] = 0.0f;
-    }
-  const int iters = seg_len + 6;
-  for (int i = 0; i < iters; ++i) {
-    const int k = s - 3 + i;
-    const long long off = base + static_cast<long long>(wrap(k, n)) * stride;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      ut[0][c] = ut[1][c];
-      ut[1][c] = qin[c * nc + off];
-      lm[0][c] = lm[1][c];
-      lm[1][c] = lm[2][c];
-      lm[2][c] = lm[3][c];
-      lm[3][c] = lam_out[c * nc + off];
-      r1[0][c] = r1[1][c];
-      l1[0][c] = l1[1][c];
-    }
-    split_flux<D>(ut[1], h1, r1[1], l1[1]);
-    if (i >= 1) {
-      float f1[5];
-#pragma unroll
-      for (int c = 0; c < 5; ++c) f1[c] = r1[0][c] - l1[1][c];
-      if (i >= 2) {
-#pragma unroll
-        for (int w = 0; w < 2; ++w)
-#pragma unroll
-          for (int c = 0; c < 5; ++c) {
-            uh[w][c] = uh[w + 1][c];
-            r2[w][c] = r2[w + 1][c];
-            l2[w][c] = l2[w + 1][c];
-          }
-#pragma unroll
-        for (int c = 0; c < 5; ++c) uh[2][c] = ut[0][c] - hdt * (f1[c] - f1prev[c]);
-        split_flux<D>(uh[2], h2, r2[2], l2[2]);
-        if (i >= 4) {
-          // R face m = k-2 (F^R at k-3, k-2, k-1 = r2[0..2]); G2_m = -dt (lam[k-2] - lam[k-1])
-          // L face m = k-3 (F^L at k-3, k-2, k-1 = l2[0..2]); dL/dFLf = dt (lam[k-3] - lam[k-2])
-#pragma unroll
-          for (int c = 0; c < 5; ++c) {
-            float a0, a1, a2;
-            face_r_coef(r2[0][c], r2[1][c], r2[2][c], a0, a1, a2);
-            const float gr = -dt * (lm[1][c] - lm[2][c]);
-            gR[0][c] += gr * a0;
-            gR[1][c] += gr * a1;
-            gR[2][c] += gr * a2;
-            face_l_coef(l2[0][c], l2[1][c], l2[2][c], a0, a1, a2);
-            const float gl = dt * (lm[0][c] - lm[1][c]);
-            gL[0][c] += gl * a0;
-            gL[1][c] += gl * a1;
-            gL[2][c] += gl * a2;
-          }
-          if (i >= 6) {   // cell k-3 is complete
-            float sv[5], dv[5], out[5];
-#pragma unroll
-            for (int c = 0; c < 5; ++c) {
-              sv[c] = gR[0][c] + gL[0][c];
-              dv[c] = gR[0][c] - gL[0][c];
-            }
-            split_flux_vjp<D>(uh[0], h2, sv, dv, out);
-            const long long o3 = base + static_cast<long long>(wrap(k - 3, n)) * stride;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) lam_h[c * nc + o3] = out[c];
-          }
-#pragma unroll
-          for (int c = 0; c < 5; ++c) {
-            gR[0][c] = gR[1][c];
-            gR[1][c] = gR[2][c];
-            gR[2][c] = 0.0f;
-            gL[0][c] = gL[1][c];
-            gL[1][c] = gL[2][c];
-            gL[2][c] = 0.0f;
-          }
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 5; ++c) f1prev[c] = f1[c];
-    }
-  }
-}
-
-// ----------------------------------------------------------------- adjoint, pass 2 (any D)
-template <int D>
-__global__ void __launch_bounds__(256) vjp_finish_kernel(const float* __restrict__ qin,
-                                                         const float* __restrict__ lam_out,
-                                                         const float* __restrict__ lam_h,
-                                                         float* __restrict__ lam_in, int n,
-                                                         long long nc,
-                                                         const StepScal* __restrict__ tab) {
-  const long long cell = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (cell >= nc) return;
   const StepScal& sc = tab[blockIdx.y];
-  qin += blockIdx.y * 5 * nc;
-  lam_out += blockIdx.y * 5 * nc;
-  lam_h += blockIdx.y * 5 * nc;
-  lam_in += blockIdx.y * 5 * nc;
-  if (!sc.active) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) lam_in[c * nc + cell] = lam_out[c * nc + cell];
+  for (int c = 0; c < 5; ++c) {
+    p.q[c] = qin + (blockIdx.y * 5 + c) * nc;
+    p.l[c] = lam_out + (blockIdx.y * 5 + c) * nc;
+    p.o[c] = lam_in + (blockIdx.y * 5 + c) * nc;
+  }
+  if (!sc.active) {
+    for (int i = 0; i < seg_len; ++i) {
+      const unsigned off = p.at(s + i);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) p.st(c, off, WalkVjpPtr::ld(p.l[c], off));
+    }
     return;
   }
   const float dt = sc.dt;
-  const HydroK h1 = sc.h1;
-  const int x = static_cast<int>(cell % n);
-  const int y = static_cast<int>((cell / n) % n);
-  const int z = static_cast<int>(cell / (static_cast<long long>(n) * n));
-  long long cp, cm;
-  if (D == 0) {
-    cp = cell - x + wrap(x + 1, n);
-    cm = cell - x + wrap(x - 1, n);
-  } else if (D == 1) {
-    cp = cell + static_cast<long long>(wrap(y + 1, n) - y) * n;
-    cm = cell + static_cast<long long>(wrap(y - 1, n) - y) * n;
-  } else {
-    cp = cell + static_cast<long long>(wrap(z + 1, n) - z) * n * n;
-    cm = cell + static_cast<long long>(wrap(z - 1, n) - z) * n * n;
-  }
+  const HydroK h1 = sc.h1, h2 = sc.h2;
   const float hdt = 0.5f * dt;
-  float q[5], sv[5], dv[5], out[5];
+  WalkVjp w;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    q[c] = qin[c * nc + cell];
-    const float h0 = lam_h[c * nc + cell];
-    const float gp = -hdt * (h0 - lam_h[c * nc + cp]);
-    const float gm = -hdt * (lam_h[c * nc + cm] - h0);
-    sv[c] = gp - gm;
-    dv[c] = gp + gm;
+  for (int j = 0; j < kAheadU; ++j) {
+    const unsigned off = p.at(s - 4 + j);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) w.u[j][c] = WalkVjpPtr::ld(p.q[c], off);
   }
-  split_flux_vjp<D>(q, h1, sv, dv, out);
 #pragma unroll
-  for (int c = 0; c < 5; ++c)
-    lam_in[c * nc + cell] = lam_out[c * nc + cell] + lam_h[c * nc + cell] + out[c];
+  for (int j = 0; j < kAheadL; ++j) {
+    const unsigned off = p.at(s - 4 + j);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) w.lm[j][c] = WalkVjpPtr::ld(p.l[c], off);
+  }
+  walk_vjp_visit<D, 0, 0>(w, p, s - 4, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 1, 1>(w, p, s - 3, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 2, 2>(w, p, s - 2, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 3, 2>(w, p, s - 1, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 4, 3>(w, p, s, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 5, 4>(w, p, s + 1, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 6, 5>(w, p, s + 2, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 7, 6>(w, p, s + 3, h1, h2, dt, hdt);
+  // seg_len is a multiple of 8: visits 8 + 8m .. 15 + 8m have ring phases 0 .. 7
+  for (int k = s + 4; k < s + 4 + seg_len; k += 8) {
+    walk_vjp_visit<D, 0, 7>(w, p, k, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 1, 7>(w, p, k + 1, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 2, 7>(w, p, k + 2, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 3, 7>(w, p, k + 3, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 4, 7>(w, p, k + 4, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 5, 7>(w, p, k + 5, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 6, 7>(w, p, k + 6, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 7, 7>(w, p, k + 7, h1, h2, dt, hdt);
+  }
 }
 
 int pick_segment(int n) { return n >= 64 ? 64 : n; }
@@ -600,10 +599,11 @@ void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b,
 }
 
 void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
-                      float* lam_h_scratch, const Batch& b, int axis) {
+                      const Batch& b, int axis) {
   const int n = b.n;
   const long long nc = b.nc();
   if (!b.tab) throw ArgError("sweep adjoint: step table required");
+  if (qin == lam_in || lam_out == lam_in) throw ArgError("sweep adjoint: in-place not supported");
   if (axis == 0) {
     hipLaunchKernelGGL(sweep_x_vjp_kernel, dim3(static_cast<unsigned>(nc / kRowCells), b.S),
                        dim3(kRowThreads), 0, st, qin, lam_out, lam_in, n, nc, b.tab);
@@ -611,20 +611,13 @@ void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, fl
     const int seg = pick_segment(n);
     const int nseg = n / seg;
     const long long threads = static_cast<long long>(n) * n * nseg;
-    const dim3 grid(blocks_for(threads, 256), b.S), grid2(blocks_for(nc, 256), b.S);
-    if (axis == 1) {
-      hipLaunchKernelGGL(vjp_walk_h_kernel<1>, grid, dim3(256), 0, st, qin, lam_out,
-                         lam_h_scratch, n, nc, seg, nseg, b.tab);
-      DH_LAUNCH_CHECK();
-      hipLaunchKernelGGL(vjp_finish_kernel<1>, grid2, dim3(256), 0, st, qin, lam_out,
-                         lam_h_scratch, lam_in, n, nc, b.tab);
-    } else {
-      hipLaunchKernelGGL(vjp_walk_h_kernel<2>, grid, dim3(256), 0, st, qin, lam_out,
-                         lam_h_scratch, n, nc, seg, nseg, b.tab);
-      DH_LAUNCH_CHECK();
-      hipLaunchKernelGGL(vjp_finish_kernel<2>, grid2, dim3(256), 0, st, qin, lam_out,
-                         lam_h_scratch, lam_in, n, nc, b.tab);
-    }
+    const dim3 grid(blocks_for(threads, 256), b.S);
+    if (axis == 1)
+      hipLaunchKernelGGL(sweep_walk_vjp_kernel<1>, grid, dim3(256), 0, st, qin, lam_out, lam_in,
+                         n, nc, seg, nseg, b.tab);
+    else
+      hipLaunchKernelGGL(sweep_walk_vjp_kernel<2>, grid, dim3(256), 0, st, qin, lam_out, lam_in,
+                         n, nc, seg, nseg, b.tab);
   }
   DH_LAUNCH_CHECK();
 }
