@@ -1,16 +1,22 @@
-// Radix-2 Stockham FFTs in LDS for the particle-mesh Poisson solve and the initial
-// conditions (Sec. 2.1, 2.2), with the spectral operators fused into the z pass.
+// FFTs for the particle-mesh Poisson solve and the initial conditions (Sec. 2.1, 2.2), with
+// the spectral operators fused into the z pass.
 //
 // Half spectrum layout: spec[(kz * n + ky) * nh + kx], nh = n/2 + 1, kx = 0..n/2.
 // Forward transforms are unnormalised; every spectral operator carries the 1/N^3 of the
 // inverse.  Passes:
-//   x_r2c     rows of n reals -> n/2+1 complex (full complex FFT of the row in LDS)
-//   pencil<1> y pencils (one z plane, tk consecutive kx per block)
-//   pencil<2> z pencils (one ky line, tk consecutive kx per block): forward, spectral
-//             operator, inverse, each optional, and optional accumulation into the output
+//   x_r2c     rows of n reals -> n/2+1 complex
+//   pencil<1> y lines (all (z, kx) lines of a sample, tk consecutive ones per block)
+//   pencil<2> z lines ((ky, kx) lines): forward, spectral operator, inverse, each optional,
+//             and optional accumulation into the output
 //   x_c2r     Hermitian extension of each row, inverse FFT, real part times a scale.
-// Stockham step for sub-transform size p: for butterfly i < n/2, k = i mod p,
-//   u0 = a[i], u1 = a[i + n/2] * exp(-i pi k / p),  b[2i - k] = u0 + u1, b[2i - k + p] = u0 - u1.
+//
+// Each n-point line transform is the four-step factorisation n = N1 * N2 with both factors
+// done in registers and one transpose through LDS:
+//   X[k1 + N1 k2] = sum_j2 W_N2^(j2 k2) W_n^(j2 k1) sum_j1 x[j2 + N2 j1] W_N1^(j1 k1).
+// Natural order "D_x": N2 threads per line, thread q holds x[q + N2 r], r < N1.
+// Spectral order "D_k": N1 threads per line, thread q holds X[q + N1 r], r < N2.
+// The forward transform maps D_x to D_k, the inverse D_k to D_x:
+//   x[a + N2 b] = sum_k1 W_N1^(-b k1) W_n^(-a k1) sum_k2 X[k1 + N1 k2] W_N2^(-a k2).
 #include <cmath>
 #include <vector>
 
@@ -21,100 +27,198 @@ namespace dh {
 namespace {
 
 constexpr int kFftThreads = 256;
-constexpr int kRowTile = 1024;   // complex elements per x-pass block
+constexpr int kMaxR = 16;
 
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// cos and sin of 2 pi e / 16, e = 0..7
+__device__ constexpr float kCos16[8] = {1.0f, 0.92387953251128674f, 0.70710678118654752f,
+                                        0.38268343236508977f, 0.0f, -0.38268343236508977f,
+                                        -0.70710678118654752f, -0.92387953251128674f};
+__device__ constexpr float kSin16[8] = {0.0f, 0.38268343236508977f, 0.70710678118654752f,
+                                        0.92387953251128674f, 1.0f, 0.92387953251128674f,
+                                        0.70710678118654752f, 0.38268343236508977f};
+
+// x * W_16^(+-e): forward exp(-2 pi i e / 16), inverse exp(+2 pi i e / 16); e is a constant
 template <bool INV>
-__device__ float2* lds_fft(float2* a, float2* b, int n, int logn, int npen, int ps,
-                           const float2* tw) {
-  const int half = n >> 1;
-  const int total = npen * half;
-  for (int p = 1, s = 0; p < n; p <<= 1, ++s) {
-    const int tws = n >> (s + 1);
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-      const int pen = t >> (logn - 1);
-      const int i = t - pen * half;
-      const int k = i & (p - 1);
-      const float2 u0 = a[pen * ps + i];
-      float2 w = tw[k * tws];
-      if (INV) w.y = -w.y;
-      const float2 v = cmul(a[pen * ps + i + half], w);
-      const int j = (i << 1) - k;
-      b[pen * ps + j] = make_float2(u0.x + v.x, u0.y + v.y);
-      b[pen * ps + j + p] = make_float2(u0.x - v.x, u0.y - v.y);
+__device__ __forceinline__ float2 rot16(float2 x, int e) {
+  if (e == 0) return x;
+  if (e == 4) return INV ? make_float2(-x.y, x.x) : make_float2(x.y, -x.x);
+  const float c = kCos16[e], s = INV ? kSin16[e] : -kSin16[e];
+  return make_float2(x.x * c - x.y * s, x.x * s + x.y * c);
+}
+
+constexpr int bit_reverse(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+constexpr int log2c(int r) { return r <= 1 ? 0 : 1 + log2c(r / 2); }
+
+// In-register R-point DFT (R = 2, 4, 8, 16) of v[0..R-1], natural order in and out: radix-2
+// decimation in time after a bit-reversal permutation, twiddles as constants.
+template <int R, bool INV>
+__device__ __forceinline__ void dft_reg(float2 (&v)[kMaxR]) {
+  constexpr int bits = log2c(R);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int j = bit_reverse(i, bits);
+    if (j > i) {
+      const float2 t = v[i];
+      v[i] = v[j];
+      v[j] = t;
     }
-    __syncthreads();
-    float2* tmp = a;
-    a = b;
-    b = tmp;
   }
-  return a;
+#pragma unroll
+  for (int m = 2; m <= R; m <<= 1) {
+#pragma unroll
+    for (int k = 0; k < R; k += m)
+#pragma unroll
+      for (int j = 0; j < m / 2; ++j) {
+        const float2 t = rot16<INV>(v[k + j + m / 2], j * (16 / m));
+        const float2 u = v[k + j];
+        v[k + j] = cadd(u, t);
+        v[k + j + m / 2] = csub(u, t);
+      }
+  }
+}
+
+// W_n^m (forward sign) from the half table tw[m] = exp(-2 pi i m / n), m < n/2
+__device__ __forceinline__ float2 tw_full(const float2* tw, int m, int n) {
+  const int h = n >> 1;
+  const float2 w = tw[m & (h - 1)];
+  return m < h ? w : make_float2(-w.x, -w.y);
+}
+
+// Forward line transform: D_x (thread q < N2 of the line) -> D_k (thread q < N1).
+// ex: this line's exchange buffer (n complex), tw: twiddle half table in LDS.
+template <int N1, int N2>
+__device__ __forceinline__ void line_forward(float2 (&v)[kMaxR], float2* ex, const float2* tw,
+                                             int q, bool in_x, bool in_k) {
+  constexpr int n = N1 * N2;
+  if (in_x) {   // q = j2: DFT over j1, then W_n^(j2 k1), store at [k1 * N2 + j2]
+    dft_reg<N1, false>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) ex[k1 * N2 + q] = cmul(v[k1], tw_full(tw, q * k1, n));
+  }
+  __syncthreads();
+  if (in_k) {   // q = k1: DFT over j2 gives X[k1 + N1 k2]
+#pragma unroll
+    for (int j2 = 0; j2 < N2; ++j2) v[j2] = ex[q * N2 + j2];
+    dft_reg<N2, false>(v);
+  }
+}
+
+// Inverse line transform: D_k (thread q < N1) -> D_x (thread q < N2), unnormalised.
+template <int N1, int N2>
+__device__ __forceinline__ void line_inverse(float2 (&v)[kMaxR], float2* ex, const float2* tw,
+                                             int q, bool in_x, bool in_k) {
+  constexpr int n = N1 * N2;
+  if (in_k) {   // q = k1: inverse DFT over k2 gives index a; times W_n^(-a k1); store [a * N1 + k1]
+    dft_reg<N2, true>(v);
+#pragma unroll
+    for (int a = 0; a < N2; ++a) {
+      const float2 w = tw_full(tw, a * q, n);
+      ex[a * N1 + q] = cmul(v[a], make_float2(w.x, -w.y));
+    }
+  }
+  __syncthreads();
+  if (in_x) {   // q = a: inverse DFT over k1 gives x[a + N2 b]
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = ex[q * N1 + k1];
+    dft_reg<N1, true>(v);
+  }
 }
 
 __device__ __forceinline__ void load_tw(float2* sh_tw, const float2* tw, int n) {
   for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) sh_tw[i] = tw[i];
 }
 
+template <int N1, int N2>
+struct Lines {
+  static constexpr int n = N1 * N2;
+  static constexpr int R = N1 > N2 ? N1 : N2;
+  static constexpr int tk = kFftThreads / R;   // lines per block
+  static constexpr int ps = n + 1;             // padded exchange stride
+};
+
+// ------------------------------------------------------------------------------- x passes
 // Rows of all samples are consecutive (n^2 per sample); a block's rows lie in one sample.
+// Thread t: q = t % R, row = t / R (consecutive lanes walk along the row).
+template <int N1, int N2>
 __global__ void __launch_bounds__(kFftThreads) x_r2c_kernel(const float* __restrict__ in,
                                                             float2* __restrict__ spec,
-                                                            const float2* __restrict__ tw, int n,
-                                                            int logn,
+                                                            const float2* __restrict__ tw,
                                                             const StepScal* __restrict__ tab,
                                                             long long in_stride) {
-  __shared__ float2 A[kRowTile], B[kRowTile];
-  __shared__ float2 TW[128];
-  const int rows = kRowTile / n;
-  const int nh = n / 2 + 1;
-  const long long row0 = static_cast<long long>(blockIdx.x) * rows;
+  using L = Lines<N1, N2>;
+  constexpr int n = L::n, nh = n / 2 + 1;
+  __shared__ float2 EX[L::tk * L::ps];
+  __shared__ float2 TW[n / 2];
+  const long long row0 = static_cast<long long>(blockIdx.x) * L::tk;
   const long long nn = static_cast<long long>(n) * n;
   const int smp = static_cast<int>(row0 / nn);
   if (!sample_active(tab, smp)) return;
-  const float* src = in + smp * in_stride + (row0 - smp * nn) * n;
   load_tw(TW, tw, n);
-  for (int t = threadIdx.x; t < rows * n; t += blockDim.x) A[t] = make_float2(src[t], 0.0f);
+  const int q = threadIdx.x % L::R, r = threadIdx.x / L::R;
+  const long long row = row0 + r;
+  const float* src = in + smp * in_stride + (row - smp * nn) * n;
+  float2 v[kMaxR];
+  const bool in_x = q < N2, in_k = q < N1;
+  if (in_x)
+#pragma unroll
+    for (int j1 = 0; j1 < N1; ++j1) v[j1] = make_float2(src[q + N2 * j1], 0.0f);
   __syncthreads();
-  float2* r = lds_fft<false>(A, B, n, logn, rows, n, TW);
-  for (int t = threadIdx.x; t < rows * nh; t += blockDim.x) {
-    const int rr = t / nh, k = t - rr * nh;
-    spec[(row0 + rr) * nh + k] = r[rr * n + k];
-  }
+  line_forward<N1, N2>(v, EX + r * L::ps, TW, q, in_x, in_k);
+  if (in_k)
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int k = q + N1 * k2;
+      if (k < nh) spec[row * nh + k] = v[k2];
+    }
 }
 
+template <int N1, int N2>
 __global__ void __launch_bounds__(kFftThreads) x_c2r_kernel(const float2* __restrict__ spec,
                                                             float* __restrict__ out,
-                                                            const float2* __restrict__ tw, int n,
-                                                            int logn, float scale,
+                                                            const float2* __restrict__ tw,
+                                                            float scale,
                                                             const StepScal* __restrict__ tab,
                                                             long long out_stride) {
-  __shared__ float2 A[kRowTile], B[kRowTile];
-  __shared__ float2 TW[128];
-  const int rows = kRowTile / n;
-  const int nh = n / 2 + 1;
-  const long long row0 = static_cast<long long>(blockIdx.x) * rows;
+  using L = Lines<N1, N2>;
+  constexpr int n = L::n, nh = n / 2 + 1;
+  __shared__ float2 EX[L::tk * L::ps];
+  __shared__ float2 TW[n / 2];
+  const long long row0 = static_cast<long long>(blockIdx.x) * L::tk;
   const long long nn = static_cast<long long>(n) * n;
   const int smp = static_cast<int>(row0 / nn);
   if (!sample_active(tab, smp)) return;
-  float* dst = out + smp * out_stride + (row0 - smp * nn) * n;
   load_tw(TW, tw, n);
-  for (int t = threadIdx.x; t < rows * nh; t += blockDim.x) {
-    const int rr = t / nh, k = t - rr * nh;
-    A[rr * n + k] = spec[(row0 + rr) * nh + k];
-  }
+  const int q = threadIdx.x % L::R, r = threadIdx.x / L::R;
+  const long long row = row0 + r;
+  float2 v[kMaxR];
+  const bool in_x = q < N2, in_k = q < N1;
+  if (in_k)
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {   // Hermitian extension X[n - k] = conj(X[k])
+      const int k = q + N1 * k2;
+      const float2 w = spec[row * nh + (k < nh ? k : n - k)];
+      v[k2] = k < nh ? w : make_float2(w.x, -w.y);
+    }
   __syncthreads();
-  for (int t = threadIdx.x; t < rows * (n - nh); t += blockDim.x) {
-    const int rr = t / (n - nh), k = nh + (t - rr * (n - nh));
-    const float2 v = A[rr * n + (n - k)];
-    A[rr * n + k] = make_float2(v.x, -v.y);
+  line_inverse<N1, N2>(v, EX + r * L::ps, TW, q, in_x, in_k);
+  if (in_x) {
+    float* dst = out + smp * out_stride + (row - smp * nn) * n;
+#pragma unroll
+    for (int b = 0; b < N1; ++b) dst[q + N2 * b] = v[b].x * scale;
   }
-  __syncthreads();
-  float2* r = lds_fft<true>(A, B, n, logn, rows, n, TW);
-  for (int t = threadIdx.x; t < rows * n; t += blockDim.x) dst[t] = r[t].x * scale;
 }
 
+// ---------------------------------------------------------------------------- line passes
 struct OpArgs {
   int op;          // -1 none, kOpGreen, kOpIcDisp, kOpIcDispT
   float green;     // -(3 Om / 2a) / N^3
@@ -126,9 +230,13 @@ struct OpArgs {
 
 __device__ __forceinline__ int signed_freq(int k, int n) { return k <= n / 2 ? k : k - n; }
 
-__device__ float2 apply_op(const OpArgs& o, int kx, int ky, int kz, int n, float2 v) {
+// OPK: 0 none, 1 Green's function, 2 initial-condition displacement (o.op says which sign)
+template <int OPK>
+__device__ __forceinline__ float2 apply_op(const OpArgs& o, int kx, int ky, int kz, int n,
+                                           float2 v) {
   const int fx = kx, fy = signed_freq(ky, n), fz = signed_freq(kz, n);
-  if (o.op == kOpGreen) {
+  if (OPK == 0) return v;
+  if (OPK == 1) {
     const float c = 6.283185307179586f / static_cast<float>(n);
     const float ax = c * fx, ay = c * fy, az = c * fz;
     const float k2 = ax * ax + ay * ay + az * az;
@@ -155,102 +263,137 @@ __device__ float2 apply_op(const OpArgs& o, int kx, int ky, int kz, int n, float
   return make_float2(-v.y * ff, v.x * ff);
 }
 
-// Pencil pass along AX (1 = y, 2 = z) over a tile of tk consecutive kx of sample blockIdx.z.
-// flags: 1 forward, 2 operator, 4 inverse, 8 accumulate into out.  The Green's function
-// factor comes from the sample's step table when there is one.
-template <int AX>
+// Line pass along AX (1 = y, 2 = z) over tk consecutive lines of sample blockIdx.y.  Line
+// l = fixed * nh + kx (fixed = z for AX = 1, ky for AX = 2); thread t: line t % tk, q = t / tk,
+// so consecutive lanes take consecutive kx.  flags: 1 forward, 2 operator, 4 inverse, 8
+// accumulate into out.  Input in D_x unless the pass starts with the inverse (D_k).  The
+// Green's function factor comes from the sample's step table when there is one.
+template <int AX, int N1, int N2, int OPK>
 // in and out may alias (in-place passes): no __restrict__ on them
 __global__ void __launch_bounds__(kFftThreads) pencil_kernel(const float2* in, float2* out,
-                                                             const float2* __restrict__ tw, int n,
-                                                             int logn, int kTK, int flags,
-                                                             OpArgs op,
+                                                             const float2* __restrict__ tw,
+                                                             int flags, OpArgs op,
                                                              const StepScal* __restrict__ tab) {
-  extern __shared__ float2 sh[];
-  if (!sample_active(tab, blockIdx.z)) return;
-  if (tab && op.op == kOpGreen) op.green = tab[blockIdx.z].green;
-  const int ps = n + 1;
-  float2* A = sh;
-  float2* B = sh + kTK * ps;
-  float2* TW = sh + 2 * kTK * ps;
-  const int nh = n / 2 + 1;
+  using L = Lines<N1, N2>;
+  constexpr int n = L::n, nh = n / 2 + 1;
+  __shared__ float2 EX[L::tk * L::ps];
+  __shared__ float2 TW[n / 2];
+  if (!sample_active(tab, blockIdx.y)) return;
+  if (tab && op.op == kOpGreen) op.green = tab[blockIdx.y].green;
   const long long slab = static_cast<long long>(n) * n * nh;
-  in += blockIdx.z * slab;
-  out += blockIdx.z * slab;
-  const int kx0 = blockIdx.x * kTK;
-  const int fixed = blockIdx.y;   // z for AX = 1, ky for AX = 2
-  const long long line_stride = AX == 1 ? nh : static_cast<long long>(n) * nh;
-  const long long base = AX == 1 ? static_cast<long long>(fixed) * n * nh
-                                 : static_cast<long long>(fixed) * nh;
+  in += blockIdx.y * slab;
+  out += blockIdx.y * slab;
   load_tw(TW, tw, n);
-  for (int t = threadIdx.x; t < kTK * n; t += blockDim.x) {
-    const int pen = t % kTK, j = t / kTK;
-    const int kx = kx0 + pen;
-    A[pen * ps + j] = kx < nh ? in[base + j * line_stride + kx] : make_float2(0.0f, 0.0f);
-  }
-  __syncthreads();
-  float2* cur = A;
-  float2* oth = B;
+  const int li = threadIdx.x % L::tk, q = threadIdx.x / L::tk;
+  const int line = blockIdx.x * L::tk + li;
+  const bool valid = line < n * nh;
+  const int fixed = line / nh, kx = line - fixed * nh;
+  const long long stride = AX == 1 ? nh : static_cast<long long>(n) * nh;
+  const long long base = AX == 1 ? static_cast<long long>(fixed) * n * nh + kx
+                                 : static_cast<long long>(fixed) * nh + kx;
+  float2* ex = EX + li * L::ps;
+  float2 v[kMaxR];
+  const bool in_x = valid && q < N2, in_k = valid && q < N1;
   if (flags & 1) {
-    cur = lds_fft<false>(A, B, n, logn, kTK, ps, TW);
-    oth = cur == A ? B : A;
-  }
-  if (flags & 2) {
-    for (int t = threadIdx.x; t < kTK * n; t += blockDim.x) {
-      const int pen = t / n, j = t - pen * n;
-      const int kx = kx0 + pen;
-      if (kx < nh) {
-        const int ky = AX == 1 ? j : fixed;
-        const int kz = AX == 1 ? fixed : j;
-        cur[pen * ps + j] = apply_op(op, kx, ky, kz, n, cur[pen * ps + j]);
-      }
-    }
+    if (in_x)
+#pragma unroll
+      for (int r = 0; r < N1; ++r) v[r] = in[base + (q + N2 * r) * stride];
     __syncthreads();
+    line_forward<N1, N2>(v, ex, TW, q, in_x, in_k);
+  } else {
+    if (in_k)
+#pragma unroll
+      for (int r = 0; r < N2; ++r) v[r] = in[base + (q + N1 * r) * stride];
   }
-  if (flags & 4) cur = lds_fft<true>(cur, oth, n, logn, kTK, ps, TW);
-  for (int t = threadIdx.x; t < kTK * n; t += blockDim.x) {
-    const int pen = t % kTK, j = t / kTK;
-    const int kx = kx0 + pen;
-    if (kx < nh) {
-      const long long g = base + j * line_stride + kx;
-      float2 v = cur[pen * ps + j];
-      if (flags & 8) {
-        const float2 o = out[g];
-        v = make_float2(v.x + o.x, v.y + o.y);
+  if ((flags & 2) && in_k) {
+#pragma unroll
+    for (int r = 0; r < N2; ++r) {
+      const int k = q + N1 * r;
+      v[r] = apply_op<OPK>(op, kx, AX == 1 ? k : fixed, AX == 1 ? fixed : k, n, v[r]);
+    }
+  }
+  if (flags & 4) {
+    __syncthreads();   // the forward pass may still read the exchange buffer
+    line_inverse<N1, N2>(v, ex, TW, q, in_x, in_k);
+    if (in_x)
+#pragma unroll
+      for (int r = 0; r < N1; ++r) {
+        const long long g = base + (q + N2 * r) * stride;
+        float2 w = v[r];
+        if (flags & 8) w = cadd(w, out[g]);
+        out[g] = w;
       }
-      out[g] = v;
+  } else if (in_k) {
+#pragma unroll
+    for (int r = 0; r < N2; ++r) {
+      const long long g = base + (q + N1 * r) * stride;
+      float2 w = v[r];
+      if (flags & 8) w = cadd(w, out[g]);
+      out[g] = w;
     }
   }
 }
 
-int ilog2(int n) {
-  int l = 0;
-  while ((1 << l) < n) ++l;
-  return l;
+template <int N1, int N2, int OPK>
+void pencil_op(hipStream_t st, int ax, const float2* in, float2* out, const float2* tw,
+               int flags, const OpArgs& op, const Batch& b) {
+  using L = Lines<N1, N2>;
+  constexpr int n = L::n, nh = n / 2 + 1;
+  const dim3 grid((n * nh + L::tk - 1) / L::tk, b.S);
+  if (ax == 1)
+    hipLaunchKernelGGL((pencil_kernel<1, N1, N2, OPK>), grid, dim3(kFftThreads), 0, st, in, out,
+                       tw, flags, op, b.tab);
+  else
+    hipLaunchKernelGGL((pencil_kernel<2, N1, N2, OPK>), grid, dim3(kFftThreads), 0, st, in, out,
+                       tw, flags, op, b.tab);
 }
 
-size_t pencil_smem(int n, int tk) { return (2 * tk * (n + 1) + n / 2) * sizeof(float2); }
+template <int N1, int N2>
+void pencil_n(hipStream_t st, int ax, const float2* in, float2* out, const float2* tw, int flags,
+              const OpArgs& op, const Batch& b) {
+  if (!(flags & 2) || op.op < 0)
+    pencil_op<N1, N2, 0>(st, ax, in, out, tw, flags & ~2, op, b);
+  else if (op.op == kOpGreen)
+    pencil_op<N1, N2, 1>(st, ax, in, out, tw, flags, op, b);
+  else
+    pencil_op<N1, N2, 2>(st, ax, in, out, tw, flags, op, b);
+}
 
-// kx columns per pencil block: 16 (128-byte rows) while the tile fits in 64 KB of LDS
-int pencil_tile(int n) { return pencil_smem(n, 16) <= 65536 ? 16 : 8; }
+template <int N1, int N2>
+void r2c_n(hipStream_t st, const float* in, float2* spec, const float2* tw, const Batch& b,
+           long long in_stride) {
+  using L = Lines<N1, N2>;
+  const long long rows = static_cast<long long>(L::n) * L::n * b.S;
+  hipLaunchKernelGGL((x_r2c_kernel<N1, N2>), dim3(static_cast<unsigned>(rows / L::tk)),
+                     dim3(kFftThreads), 0, st, in, spec, tw, b.tab, in_stride);
+}
+
+template <int N1, int N2>
+void c2r_n(hipStream_t st, const float2* spec, float* out, const float2* tw, float scale,
+           const Batch& b, long long out_stride) {
+  using L = Lines<N1, N2>;
+  const long long rows = static_cast<long long>(L::n) * L::n * b.S;
+  hipLaunchKernelGGL((x_c2r_kernel<N1, N2>), dim3(static_cast<unsigned>(rows / L::tk)),
+                     dim3(kFftThreads), 0, st, spec, out, tw, scale, b.tab, out_stride);
+}
+
+// n = N1 * N2 with N1 >= N2, both at most 16
+#define DH_FFT_DISPATCH(n, CALL)                                  \
+  switch (n) {                                                    \
+    case 16: CALL(4, 4); break;                                   \
+    case 32: CALL(8, 4); break;                                   \
+    case 64: CALL(8, 8); break;                                   \
+    case 128: CALL(16, 8); break;                                 \
+    case 256: CALL(16, 16); break;                                \
+    default: throw ArgError("fft: n must be a power of two in [16, 256]"); \
+  }
 
 void pencil(hipStream_t st, int ax, const float2* in, float2* out, const float2* tw, int flags,
             const OpArgs& op, const Batch& b) {
-  const int n = b.n;
-  const int nh = n / 2 + 1;
-  const int tk = pencil_tile(n);
-  dim3 grid((nh + tk - 1) / tk, n, b.S);
-  const size_t smem = pencil_smem(n, tk);
-  if (ax == 1)
-    hipLaunchKernelGGL(pencil_kernel<1>, grid, dim3(kFftThreads), smem, st, in, out, tw, n,
-                       ilog2(n), tk, flags, op, b.tab);
-  else
-    hipLaunchKernelGGL(pencil_kernel<2>, grid, dim3(kFftThreads), smem, st, in, out, tw, n,
-                       ilog2(n), tk, flags, op, b.tab);
+#define DH_CALL(a, c) pencil_n<a, c>(st, ax, in, out, tw, flags, op, b)
+  DH_FFT_DISPATCH(b.n, DH_CALL)
+#undef DH_CALL
   DH_LAUNCH_CHECK();
-}
-
-unsigned row_blocks(const Batch& b) {
-  return static_cast<unsigned>(static_cast<long long>(b.n) * b.n * b.S / (kRowTile / b.n));
 }
 
 }  // namespace
@@ -265,8 +408,10 @@ void fft_make_twiddles(int n, std::vector<float2>& tw) {
 
 void fft_forward_xy(hipStream_t st, const float* in, float2* spec, const float2* tw,
                     const Batch& b, long long in_stride) {
-  hipLaunchKernelGGL(x_r2c_kernel, dim3(row_blocks(b)), dim3(kFftThreads), 0, st, in, spec, tw,
-                     b.n, ilog2(b.n), b.tab, in_stride < 0 ? b.nc() : in_stride);
+  const long long is = in_stride < 0 ? b.nc() : in_stride;
+#define DH_CALL(a, c) r2c_n<a, c>(st, in, spec, tw, b, is)
+  DH_FFT_DISPATCH(b.n, DH_CALL)
+#undef DH_CALL
   DH_LAUNCH_CHECK();
   OpArgs none{};
   none.op = -1;
@@ -278,8 +423,10 @@ void fft_inverse_yx(hipStream_t st, float2* spec, float* out, const float2* tw, 
   OpArgs none{};
   none.op = -1;
   pencil(st, 1, spec, spec, tw, 4, none, b);
-  hipLaunchKernelGGL(x_c2r_kernel, dim3(row_blocks(b)), dim3(kFftThreads), 0, st, spec, out, tw,
-                     b.n, ilog2(b.n), scale, b.tab, out_stride < 0 ? b.nc() : out_stride);
+  const long long os = out_stride < 0 ? b.nc() : out_stride;
+#define DH_CALL(a, c) c2r_n<a, c>(st, spec, out, tw, scale, b, os)
+  DH_FFT_DISPATCH(b.n, DH_CALL)
+#undef DH_CALL
   DH_LAUNCH_CHECK();
 }
 
