@@ -223,9 +223,11 @@ struct OpArgs {
   int op;          // -1 none, kOpGreen, kOpIcDisp, kOpIcDispT
   float green;     // -(3 Om / 2a) / N^3
   int axis;
-  double amp;      // A D^2 / V_cell
-  double om_h, n_s, kphys;   // Omega_m h, spectral index, (n / box): rad/cell -> h/Mpc
-  double inv_n3;
+  float sqrt_amp;  // sqrt(A D^2 / V_cell)
+  float half_ns;   // spectral index / 2
+  float om_h;      // Omega_m h
+  float kphys;     // n / box: rad/cell -> h/Mpc
+  float inv_n3;
 };
 
 __device__ __forceinline__ int signed_freq(int k, int n) { return k <= n / 2 ? k : k - n; }
@@ -244,21 +246,21 @@ __device__ __forceinline__ float2 apply_op(const OpArgs& o, int kx, int ky, int 
     const float f = o.green / k2;
     return make_float2(v.x * f, v.y * f);
   }
-  // initial-condition displacement operators, evaluated in double precision
-  const double c = 6.283185307179586 / n;
-  const double ax = c * fx, ay = c * fy, az = c * fz;
-  const double k2 = ax * ax + ay * ay + az * az;
+  // initial-condition displacement operators: i k_axis sqrt(P(k)) / k^2 / N^3 (or its
+  // conjugate), with the BBKS transfer function
+  const float c = 6.283185307179586f / static_cast<float>(n);
+  const float ax = c * fx, ay = c * fy, az = c * fz;
+  const float k2 = ax * ax + ay * ay + az * az;
   const int f_axis = o.axis == 0 ? fx : (o.axis == 1 ? fy : fz);
-  if (k2 == 0.0 || (f_axis == n / 2 || f_axis == -n / 2)) return make_float2(0.0f, 0.0f);
-  const double kj = o.axis == 0 ? ax : (o.axis == 1 ? ay : az);
-  const double kp = sqrt(k2) * o.kphys;
-  const double q = kp / o.om_h;
-  const double tq = log(1.0 + 2.34 * q) / (2.34 * q) *
-                    pow(1.0 + 3.89 * q + pow(16.1 * q, 2.0) + pow(5.46 * q, 3.0) + pow(6.71 * q, 4.0),
-                        -0.25);
-  const double pk = o.amp * pow(kp, o.n_s) * tq * tq;
-  const double f = kj * sqrt(pk) / k2 * o.inv_n3;
-  const float ff = static_cast<float>(o.op == kOpIcDisp ? f : -f);
+  if (k2 == 0.0f || (f_axis == n / 2 || f_axis == -n / 2)) return make_float2(0.0f, 0.0f);
+  const float kj = o.axis == 0 ? ax : (o.axis == 1 ? ay : az);
+  const float kp = sqrtf(k2) * o.kphys;
+  const float q = kp / o.om_h;
+  const float q2 = 16.1f * q, q3 = 5.46f * q, q4 = 6.71f * q;
+  const float tq = logf(1.0f + 2.34f * q) / (2.34f * q) *
+                   powf(1.0f + 3.89f * q + q2 * q2 + q3 * q3 * q3 + (q4 * q4) * (q4 * q4), -0.25f);
+  const float f = kj * (o.sqrt_amp * powf(kp, o.half_ns) * tq) / k2 * o.inv_n3;
+  const float ff = o.op == kOpIcDisp ? f : -f;
   // multiply by i * ff
   return make_float2(-v.y * ff, v.x * ff);
 }
@@ -458,11 +460,11 @@ void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* t
   OpArgs o{};
   o.op = transpose ? kOpIcDispT : kOpIcDisp;
   o.axis = axis;
-  o.amp = amp;
-  o.om_h = om_h;
-  o.n_s = n_s;
-  o.kphys = kphys;
-  o.inv_n3 = 1.0 / (static_cast<double>(n) * n * n);
+  o.sqrt_amp = static_cast<float>(std::sqrt(amp));
+  o.half_ns = static_cast<float>(0.5 * n_s);
+  o.om_h = static_cast<float>(om_h);
+  o.kphys = static_cast<float>(kphys);
+  o.inv_n3 = static_cast<float>(1.0 / (static_cast<double>(n) * n * n));
   const int flags = (forward_first ? 1 : 0) | 2 | (inverse_after ? 4 : 0) | (accumulate ? 8 : 0);
   pencil(st, 2, in, out, tw, flags, o, b);
 }

@@ -251,50 +251,62 @@ __global__ void gather_sorted_kernel(const uint32_t* __restrict__ sorted,
 // ---------------------------------------------------------------------------- deposit
 // For cell (ix, iy, iz) and each (oz, oy) in the order (0,0), (0,1), (1,0), (1,1): the bin
 // with x index ix-1 (weight w1 in x) is visited before the bin ix (weight 1-w1); when ix = 0
-// the first bin wraps to n-1.
+// the first bin wraps to n-1.  Inside a bin the particles are summed in ascending order.
+template <bool VEC>
+__device__ __forceinline__ void deposit_particle(const float4& p, const float4& v, int ox, int oy,
+                                                 int oz, float acc[3]) {
+  const float w = wsel(w1_of(p.x), ox) * wsel(w1_of(p.y), oy) * wsel(w1_of(p.z), oz);
+  if (VEC) {
+    acc[0] += w * v.x;
+    acc[1] += w * v.y;
+    acc[2] += w * v.z;
+  } else {
+    acc[0] += w;
+  }
+}
+
+// All 16 bin bounds are loaded first.  For the density (VEC = false) the first particle of
+// each of the 8 bins is loaded next, before any sum, so a cell waits for two rounds of loads
+// when bins hold at most one particle (further particles of a bin follow in its loop); the
+// vector deposit, which would hold twice as many registers, reads bin by bin.  `last` is the
+// last valid index of spos.
 template <bool VEC>
 __device__ __forceinline__ void deposit_cell(const uint32_t* __restrict__ start,
                                              const float4* __restrict__ spos,
                                              const float4* __restrict__ sval, int ix, int iy,
-                                             int iz, int n, float acc[3]) {
-  // all bin bounds first (independent loads), then the particle ranges
-  uint32_t a0[4], a1[4], b0[4], b1[4];
+                                             int iz, int n, uint32_t last, float acc[3]) {
+  uint32_t lo[8], hi[8];   // bin 2r: x index ix-1 of row r, bin 2r+1: x index ix
   const int xm = wrapi(ix - 1, n);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int oz = r >> 1, oy = r & 1;
     const long long row = (static_cast<long long>(wrapi(iz - oz, n)) * n + wrapi(iy - oy, n)) * n;
-    a0[r] = start[row + xm];
-    a1[r] = start[row + xm + 1];
-    b0[r] = start[row + ix];
-    b1[r] = start[row + ix + 1];
+    lo[2 * r] = start[row + xm];
+    hi[2 * r] = start[row + xm + 1];
+    lo[2 * r + 1] = start[row + ix];
+    hi[2 * r + 1] = start[row + ix + 1];
   }
+  if (VEC) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int oz = r >> 1, oy = r & 1;
-    for (uint32_t j = a0[r]; j < a1[r]; ++j) {   // bin ix-1: weight w1 in x
-      const float4 p = spos[j];
-      const float w = w1_of(p.x) * wsel(w1_of(p.y), oy) * wsel(w1_of(p.z), oz);
-      if (VEC) {
-        const float4 v = sval[j];
-        acc[0] += w * v.x;
-        acc[1] += w * v.y;
-        acc[2] += w * v.z;
-      } else {
-        acc[0] += w;
-      }
+    for (int k = 0; k < 8; ++k) {
+      const int r = k >> 1, oz = r >> 1, oy = r & 1;
+      const int ox = (k & 1) ? 0 : 1;   // bin ix-1 carries w1 in x, bin ix 1 - w1
+      for (uint32_t j = lo[k]; j < hi[k]; ++j)
+        deposit_particle<VEC>(spos[j], sval[j], ox, oy, oz, acc);
     }
-    for (uint32_t j = b0[r]; j < b1[r]; ++j) {   // bin ix: weight 1-w1 in x
-      const float4 p = spos[j];
-      const float w = (1.0f - w1_of(p.x)) * wsel(w1_of(p.y), oy) * wsel(w1_of(p.z), oz);
-      if (VEC) {
-        const float4 v = sval[j];
-        acc[0] += w * v.x;
-        acc[1] += w * v.y;
-        acc[2] += w * v.z;
-      } else {
-        acc[0] += w;
-      }
+    return;
+  }
+  float4 p[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) p[k] = spos[lo[k] < last ? lo[k] : last];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int r = k >> 1, oz = r >> 1, oy = r & 1;
+    const int ox = (k & 1) ? 0 : 1;
+    if (lo[k] < hi[k]) {
+      deposit_particle<VEC>(p[k], p[k], ox, oy, oz, acc);
+      for (uint32_t j = lo[k] + 1; j < hi[k]; ++j)
+        deposit_particle<VEC>(spos[j], p[k], ox, oy, oz, acc);
     }
   }
 }
@@ -314,7 +326,8 @@ __global__ void __launch_bounds__(256) deposit_kernel(const uint32_t* __restrict
   const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
             iz = static_cast<int>(c / (static_cast<long long>(n) * n));
   float acc[3] = {0.0f, 0.0f, 0.0f};
-  deposit_cell<false>(start, spos, nullptr, ix, iy, iz, n, acc);
+  deposit_cell<false>(start, spos, nullptr, ix, iy, iz, n,
+                      static_cast<uint32_t>(gridDim.y * nc - 1), acc);
   const float g = rho_gas ? rho_gas[c] : 0.0f;
   out[c] = g + m_dm * acc[0] + offset;
 }
@@ -334,7 +347,8 @@ __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __rest
   const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
             iz = static_cast<int>(c / (static_cast<long long>(n) * n));
   float acc[3] = {0.0f, 0.0f, 0.0f};
-  deposit_cell<true>(start, spos, sval, ix, iy, iz, n, acc);
+  deposit_cell<true>(start, spos, sval, ix, iy, iz, n, static_cast<uint32_t>(gridDim.y * nc - 1),
+                     acc);
   out[c] += scale * acc[0];
   out[nc + c] += scale * acc[1];
   out[2 * nc + c] += scale * acc[2];

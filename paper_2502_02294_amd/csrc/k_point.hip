@@ -137,10 +137,6 @@ __device__ __forceinline__ double log_sigmoid_(double y) {
   return fmin(y, 0.0) - log1p(exp(-fabs(y)));
 }
 
-__device__ __forceinline__ float log_sigmoidf_(float y) {
-  return fminf(y, 0.0f) - log1pf(expf(-fabsf(y)));
-}
-
 // The uniform of cell c for the draw of the given step.
 __device__ __forceinline__ double starform_uniform(long long c, const SourceArgs& a) {
   uint32_t ctr[4] = {static_cast<uint32_t>(c), a.step, kTagStarform, 0u};
@@ -148,29 +144,57 @@ __device__ __forceinline__ double starform_uniform(long long c, const SourceArgs
   return uniform_open_d(ctr[0]);
 }
 
-// True when the relaxed draw is certainly below e^-109 (zero in float, and no change of the
-// energy in float): a float32 estimate of its argument is below -110.  Not used where the
-// float32 probability nears underflow, since there the estimate is not accurate enough.
-__device__ bool draw_negligible(const float q5[5], double u, const SourceArgs& a) {
-  if (a.mode != 2) return false;
+// Screening of the relaxed draw z = sigmoid((logit pi0 + logit u) / tau): z is certainly
+// below e^-109 (zero in float, and no change of the energy in float) when an FP32 estimate of
+// its argument is below -110.  logit u of the 24-bit uniforms is at most
+// log((1 - 2^-25) / 2^-25) < 17.33, so a cell whose estimate stays below -110 with that
+// bound needs no uniform at all.  The estimate uses the hardware exp2/log2/rcp/sqrt (absolute
+// error of the logit near 1e-6, against the margin of tau between -110 and -109); it is +inf
+// (no screening) where the float32 probability nears underflow.
+constexpr float kMaxLogitU = 17.5f;
+
+__device__ __forceinline__ float fast_exp(float x) { return __expf(x); }
+__device__ __forceinline__ float fast_log(float x) { return __logf(x); }
+// 1 - exp(-x) for x >= 0, relative error below 1e-4
+__device__ __forceinline__ float one_minus_exp_neg(float x) {
+  return x < 1e-3f ? x * (1.0f - 0.5f * x) : 1.0f - fast_exp(-x);
+}
+__device__ __forceinline__ float fast_log_sigmoid(float y) {
+  return fminf(y, 0.0f) - fast_log(1.0f + fast_exp(-fabsf(y)));
+}
+// log p - log(1 - p) from log p
+__device__ __forceinline__ float fast_logit_of_log(float logp) {
+  return logp - fast_log(1.0f - fast_exp(logp));
+}
+
+__device__ __forceinline__ bool screened_out(float logit_pi, float logit_u, const SourceArgs& a) {
+  return (logit_pi + logit_u) / static_cast<float>(a.tau) < -110.0f;
+}
+__device__ __forceinline__ float logit_u_of(double u) {
+  const float uf = static_cast<float>(u);
+  return fast_log(uf) - fast_log(1.0f - uf);
+}
+
+// FP32 estimate of log pi0 - log(1 - pi0) of the plain source term (relaxed mode only)
+__device__ __forceinline__ float draw_logit_estimate(const float q5[5], const SourceArgs& a) {
+  if (a.mode != 2) return INFINITY;
   const float rho = q5[0];
-  const float ir = 1.0f / rho, ia = static_cast<float>(1.0 / a.a);
-  const float u0 = q5[1] * ia * ir, u1 = q5[2] * ia * ir, u2 = q5[3] * ia * ir;
-  const float e = fmaxf(q5[4] * ia * ia * ir - 0.5f * (u0 * u0 + u1 * u1 + u2 * u2),
+  const float ir = rcp_approx(rho), ia = static_cast<float>(1.0 / a.a);
+  const float iar = ia * ir;
+  const float u0 = q5[1] * iar, u1 = q5[2] * iar, u2 = q5[3] * iar;
+  const float e = fmaxf(q5[4] * ia * iar - 0.5f * (u0 * u0 + u1 * u1 + u2 * u2),
                         static_cast<float>(a.efloor));
   const float temp = e * static_cast<float>(a.t_per_e);
   const float delta = rho * static_cast<float>(a.inv_rho_mean);
-  const float a3 = static_cast<float>(a.a * a.a * a.a);
-  const float tff = 1.5707963f * sqrtf(a3 / (static_cast<float>(a.omega_b) * delta));
-  const float psf = -expm1f(-static_cast<float>(a.eps_sf * a.dt) / tff);
-  if (!(psf > 1e-30f)) return false;
-  const float y1 = (delta - static_cast<float>(a.delta_c)) / static_cast<float>(a.w_rho * a.delta_c);
-  const float y2 = (static_cast<float>(a.t_c) - temp) / static_cast<float>(a.w_t * a.t_c);
-  const float logpi = logf(psf) + log_sigmoidf_(y1) + log_sigmoidf_(y2);
-  const float uf = static_cast<float>(u);
-  const float arg = (logpi - log1pf(-expf(logpi)) + logf(uf) - log1pf(-uf)) /
-                    static_cast<float>(a.tau);
-  return arg < -110.0f;
+  // t_ff = pi/2 sqrt(a^3 / (Omega_b delta)); x = eps dt / t_ff
+  const float c_ff = static_cast<float>(a.eps_sf * a.dt / 1.5707963267948966 *
+                                        sqrt(a.omega_b / (a.a * a.a * a.a)));
+  const float psf = one_minus_exp_neg(c_ff * sqrt_approx(delta));
+  if (!(psf > 1e-30f)) return INFINITY;
+  const float y1 = (delta - static_cast<float>(a.delta_c)) *
+                   static_cast<float>(1.0 / (a.w_rho * a.delta_c));
+  const float y2 = (static_cast<float>(a.t_c) - temp) * static_cast<float>(1.0 / (a.w_t * a.t_c));
+  return fast_logit_of_log(fast_log(psf) + fast_log_sigmoid(y1) + fast_log_sigmoid(y2));
 }
 
 __device__ SrcCell source_eval(const float q5[5], double u, const SourceArgs& a) {
@@ -227,8 +251,9 @@ __device__ __forceinline__ double cell_speed(const float q5[5], double a, double
                                              double efloor) {
   const double rho = q5[0];
   const double ia = 1.0 / a;
-  const double u0 = q5[1] * ia / rho, u1 = q5[2] * ia / rho, u2 = q5[3] * ia / rho;
-  double e = q5[4] * ia * ia / rho - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+  const double iar = ia / rho;
+  const double u0 = q5[1] * iar, u1 = q5[2] * iar, u2 = q5[3] * iar;
+  double e = q5[4] * ia * iar - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
   e = fmax(e, efloor);
   const double cs = sqrt(gg1 * e);
   double sp = (fmax(fabs(u0), fmax(fabs(u1), fabs(u2))) + cs) * ia;
@@ -270,9 +295,10 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
 #pragma unroll
       for (int k = 0; k < 5; ++k) q_kicked[k * nc + c] = q5[k];
     }
-    if (a.mode != 0) {
+    const float lg = a.mode != 0 ? draw_logit_estimate(q5, a) : 0.0f;
+    if (a.mode != 0 && !screened_out(lg, kMaxLogitU, a)) {
       const double u = starform_uniform(c, a);
-      if (!draw_negligible(q5, u, a)) {
+      if (!screened_out(lg, logit_u_of(u), a)) {
         const SrcCell s = source_eval(q5, u, a);
         if (s.z != 0.0) {
           q5[4] = static_cast<float>(q5[4] + a.a * a.a * s.rho * s.z * a.e0_code);
@@ -307,8 +333,11 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_kernel(const float* __
     if (c >= nc) break;
     float q5[5];
     load_q(q, c, nc, q5);
+    // z and its derivatives are below 1e-47 where the draw is screened out
+    const float lg = draw_logit_estimate(q5, a);
+    if (screened_out(lg, kMaxLogitU, a)) continue;
     const double u = starform_uniform(c, a);
-    if (draw_negligible(q5, u, a)) continue;   // z and its derivatives are below 1e-47
+    if (screened_out(lg, logit_u_of(u), a)) continue;
     const SrcCell s = source_eval(q5, u, a);
     const double le = lam[4 * nc + c];
     const double K = a.a * a.a * a.e0_code;
@@ -408,17 +437,12 @@ __device__ __forceinline__ ClosureDraw closure_draw(float o0, float o1, double u
   return d;
 }
 
-// True when the relaxed draw is certainly below e^-109 (FP32 screen, as draw_negligible).
-__device__ __forceinline__ bool closure_negligible(float o0, float o1, double u,
-                                                   const SourceArgs& a) {
-  if (a.mode != 2) return false;
-  const float psf = -expm1f(-expf(o0) * static_cast<float>(a.dt));
-  if (!(psf > 1e-30f)) return false;
-  const float logpi = logf(psf) + fminf(o1, 0.0f);
-  const float uf = static_cast<float>(u);
-  const float arg = (logpi - log1pf(-expf(logpi)) + logf(uf) - log1pf(-uf)) /
-                    static_cast<float>(a.tau);
-  return arg < -110.0f;
+// FP32 estimate of log pi0 - log(1 - pi0) of the learned closure (relaxed mode only)
+__device__ __forceinline__ float closure_logit_estimate(float o0, float o1, const SourceArgs& a) {
+  if (a.mode != 2) return INFINITY;
+  const float psf = one_minus_exp_neg(fast_exp(o0) * static_cast<float>(a.dt));
+  if (!(psf > 1e-30f)) return INFINITY;
+  return fast_logit_of_log(fast_log(psf) + fminf(o1, 0.0f));
 }
 
 // Closing pass with the learned closure (same cells per block as close_step_kernel).
@@ -481,8 +505,9 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
     __syncthreads();
     if (valid) {
       const float o0 = stage[wave][lane][5], o1 = stage[wave][lane][6];
-      const double u = starform_uniform(c, a);
-      if (!closure_negligible(o0, o1, u, a)) {
+      const float lg = closure_logit_estimate(o0, o1, a);
+      const double u = screened_out(lg, kMaxLogitU, a) ? 0.5 : starform_uniform(c, a);
+      if (!screened_out(lg, kMaxLogitU, a) && !screened_out(lg, logit_u_of(u), a)) {
         const ClosureDraw d = closure_draw(o0, o1, u, a);
         if (d.z != 0.0) {
           q5[4] = static_cast<float>(q5[4] + a.a * a.a * static_cast<double>(q5[0]) * d.z * a.e0_code);
@@ -546,9 +571,10 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
     double le = 0.0, z = 0.0, go0 = 0.0, go1 = 0.0;
     if (valid) {
       const float o0 = stage[wave][lane][5], o1 = stage[wave][lane][6];
-      const double u = starform_uniform(c, a);
+      const float lg = closure_logit_estimate(o0, o1, a);
+      const double u = screened_out(lg, kMaxLogitU, a) ? 0.5 : starform_uniform(c, a);
       le = lam[4 * nc + c];
-      if (!closure_negligible(o0, o1, u, a)) {
+      if (!screened_out(lg, kMaxLogitU, a) && !screened_out(lg, logit_u_of(u), a)) {
         const ClosureDraw d = closure_draw(o0, o1, u, a);
         z = d.z;
         if (a.mode != 1 && le != 0.0) {
