@@ -7,10 +7,9 @@
 // CIC on cell centres: with s = x - 1/2, i0 = floor(s), w1 = s - i0, a particle puts
 // weight (1-w1) in cell i0 and w1 in i0+1 per axis.  Cell c receives from particles whose
 // base cell is c - o, o in {0,1}^3.  After the sort, the positions are gathered into bin
-// order (float4 per particle), so a cell reads, for each (oz, oy), the two x-adjacent bins
-// c - (1, oy, oz) and c - (0, oy, oz) as one contiguous range, in a fixed order and with
-// ascending particle id inside a bin: every sum is reproducible bit for bit without float
-// atomics.
+// order (float4 per particle); the deposit sums each bin's 8 corner weights in LDS and each
+// cell adds its 8 corners, in a fixed order and with ascending particle id inside a bin:
+// every sum is reproducible bit for bit without float atomics.
 #include "dh_kernels.h"
 
 namespace dh {
@@ -249,109 +248,199 @@ __global__ void gather_sorted_kernel(const uint32_t* __restrict__ sorted,
 }
 
 // ---------------------------------------------------------------------------- deposit
-// For cell (ix, iy, iz) and each (oz, oy) in the order (0,0), (0,1), (1,0), (1,1): the bin
-// with x index ix-1 (weight w1 in x) is visited before the bin ix (weight 1-w1); when ix = 0
-// the first bin wraps to n-1.  Inside a bin the particles are summed in ascending order.
-template <bool VEC>
-__device__ __forceinline__ void deposit_particle(const float4& p, const float4& v, int ox, int oy,
-                                                 int oz, float acc[3]) {
-  const float w = wsel(w1_of(p.x), ox) * wsel(w1_of(p.y), oy) * wsel(w1_of(p.z), oz);
-  if (VEC) {
-    acc[0] += w * v.x;
-    acc[1] += w * v.y;
-    acc[2] += w * v.z;
-  } else {
-    acc[0] += w;
+// A block owns a tile of TX x TY x TZ cells.  Pass 1: for every bin of the tile and of its
+// low halo (the bins that reach the tile), one thread sums over the bin's particles, in
+// ascending order, the 8 CIC corner weights (times one component of the particle's vector
+// for the vector deposit) into LDS:
+//   W[o][b] = sum_{p in b} prod_d (o_d ? w1_d : 1 - w1_d),  o in {0,1}^3.
+// Pass 2: cell c adds W[o][c - o] over o in a fixed order.  Each particle's weights are
+// formed once per tile that sees its bin (about 1.5 times) instead of once per cell, and the
+// sums are reproducible bit for bit.
+template <int TX, int TY, int TZ>
+struct DepTile {
+  static constexpr int BX = TX + 1, BY = TY + 1, BZ = TZ + 1;
+  static constexpr int NB = BX * BY * BZ;           // bins read by a tile
+  static constexpr int NC = TX * TY * TZ;           // cells of a tile
+  static constexpr int PER = (NB + 255) / 256;      // bins per thread
+};
+
+// Pass 1 of the density deposit: W[o][b] for the bins of the tile and its halo.
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void deposit_tile(const uint32_t* __restrict__ start,
+                                             const float4* __restrict__ spos, int n, int x0,
+                                             int y0, int z0, float* W) {
+  using T = DepTile<TX, TY, TZ>;
+  // bounds of this thread's bins first (independent loads), then their particles
+  uint32_t lo[T::PER], hi[T::PER];
+#pragma unroll
+  for (int k = 0; k < T::PER; ++k) {
+    const int b = threadIdx.x + 256 * k;
+    lo[k] = hi[k] = 0;
+    if (b < T::NB) {
+      const int bx = b % T::BX, by = (b / T::BX) % T::BY, bz = b / (T::BX * T::BY);
+      const long long cell = (static_cast<long long>(wrapi(z0 - 1 + bz, n)) * n +
+                              wrapi(y0 - 1 + by, n)) * n + wrapi(x0 - 1 + bx, n);
+      lo[k] = start[cell];
+      hi[k] = start[cell + 1];
+    }
+  }
+  // the first particle of every bin of this thread (one round of independent loads; bins
+  // seldom hold more than one particle before clustering)
+  float4 p0[T::PER];
+#pragma unroll
+  for (int k = 0; k < T::PER; ++k) p0[k] = spos[lo[k] < hi[k] ? lo[k] : 0u];
+#pragma unroll
+  for (int k = 0; k < T::PER; ++k) {
+    const int b = threadIdx.x + 256 * k;
+    if (b >= T::NB) continue;
+    float acc[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) acc[o] = 0.0f;
+    for (uint32_t j = lo[k]; j < hi[k]; ++j) {
+      const float4 p = j == lo[k] ? p0[k] : spos[j];
+      const float wx = w1_of(p.x), wy = w1_of(p.y), wz = w1_of(p.z);
+#pragma unroll
+      for (int o = 0; o < 8; ++o)
+        acc[o] += wsel(wx, o & 1) * wsel(wy, (o >> 1) & 1) * wsel(wz, o >> 2);
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) W[o * T::NB + b] = acc[o];
   }
 }
 
-// All 16 bin bounds are loaded first.  For the density (VEC = false) the first particle of
-// each of the 8 bins is loaded next, before any sum, so a cell waits for two rounds of loads
-// when bins hold at most one particle (further particles of a bin follow in its loop); the
-// vector deposit, which would hold twice as many registers, reads bin by bin.  `last` is the
-// last valid index of spos.
-template <bool VEC>
-__device__ __forceinline__ void deposit_cell(const uint32_t* __restrict__ start,
-                                             const float4* __restrict__ spos,
-                                             const float4* __restrict__ sval, int ix, int iy,
-                                             int iz, int n, uint32_t last, float acc[3]) {
-  uint32_t lo[8], hi[8];   // bin 2r: x index ix-1 of row r, bin 2r+1: x index ix
-  const int xm = wrapi(ix - 1, n);
+// sum over the 8 corners of cell (cx, cy, cz) of the tile
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ float tile_cell_sum(const float* W, int cx, int cy, int cz) {
+  using T = DepTile<TX, TY, TZ>;
+  float s = 0.0f;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int oz = r >> 1, oy = r & 1;
-    const long long row = (static_cast<long long>(wrapi(iz - oz, n)) * n + wrapi(iy - oy, n)) * n;
-    lo[2 * r] = start[row + xm];
-    hi[2 * r] = start[row + xm + 1];
-    lo[2 * r + 1] = start[row + ix];
-    hi[2 * r + 1] = start[row + ix + 1];
+  for (int o = 0; o < 8; ++o) {
+    const int b = ((cz + 1 - (o >> 2)) * T::BY + (cy + 1 - ((o >> 1) & 1))) * T::BX +
+                  (cx + 1 - (o & 1));
+    s += W[o * T::NB + b];
   }
-  if (VEC) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int r = k >> 1, oz = r >> 1, oy = r & 1;
-      const int ox = (k & 1) ? 0 : 1;   // bin ix-1 carries w1 in x, bin ix 1 - w1
-      for (uint32_t j = lo[k]; j < hi[k]; ++j)
-        deposit_particle<VEC>(spos[j], sval[j], ox, oy, oz, acc);
-    }
-    return;
-  }
-  float4 p[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) p[k] = spos[lo[k] < last ? lo[k] : last];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int r = k >> 1, oz = r >> 1, oy = r & 1;
-    const int ox = (k & 1) ? 0 : 1;
-    if (lo[k] < hi[k]) {
-      deposit_particle<VEC>(p[k], p[k], ox, oy, oz, acc);
-      for (uint32_t j = lo[k] + 1; j < hi[k]; ++j)
-        deposit_particle<VEC>(spos[j], p[k], ox, oy, oz, acc);
-    }
-  }
+  return s;
 }
 
+// tile t of a sample: x fastest
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void tile_origin(int n, int& x0, int& y0, int& z0) {
+  const int tx = n / TX, ty = n / TY;
+  const int t = blockIdx.x;
+  x0 = (t % tx) * TX;
+  y0 = ((t / tx) % ty) * TY;
+  z0 = (t / (tx * ty)) * TZ;
+}
+
+template <int TX, int TY, int TZ>
 __global__ void __launch_bounds__(256) deposit_kernel(const uint32_t* __restrict__ start,
                                                       const float4* __restrict__ spos,
                                                       const float* __restrict__ rho_gas,
                                                       long long rho_stride, float m_dm,
                                                       float offset, float* __restrict__ out,
                                                       int n, const StepScal* __restrict__ tab) {
-  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  using T = DepTile<TX, TY, TZ>;
+  __shared__ float W[8 * T::NB];
+  if (!sample_active(tab, blockIdx.y)) return;
   const long long nc = static_cast<long long>(n) * n * n;
-  if (c >= nc || !sample_active(tab, blockIdx.y)) return;
   start += blockIdx.y * nc;
   if (rho_gas) rho_gas += blockIdx.y * rho_stride;
   out += blockIdx.y * nc;
-  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
-            iz = static_cast<int>(c / (static_cast<long long>(n) * n));
-  float acc[3] = {0.0f, 0.0f, 0.0f};
-  deposit_cell<false>(start, spos, nullptr, ix, iy, iz, n,
-                      static_cast<uint32_t>(gridDim.y * nc - 1), acc);
-  const float g = rho_gas ? rho_gas[c] : 0.0f;
-  out[c] = g + m_dm * acc[0] + offset;
+  int x0, y0, z0;
+  tile_origin<TX, TY, TZ>(n, x0, y0, z0);
+  deposit_tile<TX, TY, TZ>(start, spos, n, x0, y0, z0, W);
+  __syncthreads();
+  for (int t = threadIdx.x; t < T::NC; t += 256) {
+    const int cx = t % TX, cy = (t / TX) % TY, cz = t / (TX * TY);
+    const long long c = (static_cast<long long>(z0 + cz) * n + (y0 + cy)) * n + (x0 + cx);
+    const float g = rho_gas ? rho_gas[c] : 0.0f;
+    out[c] = g + m_dm * tile_cell_sum<TX, TY, TZ>(W, cx, cy, cz) + offset;
+  }
 }
 
+// Vector deposit: the three components go through the same 8-corner LDS table one after the
+// other (a third of the LDS of a 24-sum table, so twice as many blocks per CU); the first
+// particle of each bin stays in registers across the three passes.
+template <int TX, int TY, int TZ>
 __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __restrict__ start,
                                                           const float4* __restrict__ spos,
                                                           const float4* __restrict__ sval,
                                                           bool merged, float* __restrict__ out,
                                                           int n, const StepScal* __restrict__ tab) {
-  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const long long nc = static_cast<long long>(n) * n * n;
+  using T = DepTile<TX, TY, TZ>;
+  constexpr int CPT = (T::NC + 255) / 256;   // cells per thread
+  __shared__ float W[8 * T::NB];
   const StepScal& sc = tab[blockIdx.y];
-  if (c >= nc || !sc.active) return;
+  if (!sc.active) return;
   const float scale = merged ? sc.h_dm : sc.h;
+  const long long nc = static_cast<long long>(n) * n * n;
   start += blockIdx.y * nc;
   out += blockIdx.y * 3 * nc;
-  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
-            iz = static_cast<int>(c / (static_cast<long long>(n) * n));
-  float acc[3] = {0.0f, 0.0f, 0.0f};
-  deposit_cell<true>(start, spos, sval, ix, iy, iz, n, static_cast<uint32_t>(gridDim.y * nc - 1),
-                     acc);
-  out[c] += scale * acc[0];
-  out[nc + c] += scale * acc[1];
-  out[2 * nc + c] += scale * acc[2];
+  int x0, y0, z0;
+  tile_origin<TX, TY, TZ>(n, x0, y0, z0);
+  uint32_t lo[T::PER], hi[T::PER];
+#pragma unroll
+  for (int k = 0; k < T::PER; ++k) {
+    const int b = threadIdx.x + 256 * k;
+    lo[k] = hi[k] = 0;
+    if (b < T::NB) {
+      const int bx = b % T::BX, by = (b / T::BX) % T::BY, bz = b / (T::BX * T::BY);
+      const long long cell = (static_cast<long long>(wrapi(z0 - 1 + bz, n)) * n +
+                              wrapi(y0 - 1 + by, n)) * n + wrapi(x0 - 1 + bx, n);
+      lo[k] = start[cell];
+      hi[k] = start[cell + 1];
+    }
+  }
+  float4 p0[T::PER], v0[T::PER];
+#pragma unroll
+  for (int k = 0; k < T::PER; ++k) {
+    const uint32_t j = lo[k] < hi[k] ? lo[k] : 0u;
+    p0[k] = spos[j];
+    v0[k] = sval[j];
+  }
+  float sum[3][CPT];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+#pragma unroll
+    for (int k = 0; k < T::PER; ++k) {
+      const int b = threadIdx.x + 256 * k;
+      if (b >= T::NB) continue;
+      float acc[8];
+#pragma unroll
+      for (int o = 0; o < 8; ++o) acc[o] = 0.0f;
+      for (uint32_t j = lo[k]; j < hi[k]; ++j) {
+        const float4 p = j == lo[k] ? p0[k] : spos[j];
+        const float4 q = j == lo[k] ? v0[k] : sval[j];
+        const float val = v == 0 ? q.x : (v == 1 ? q.y : q.z);
+        const float wx = w1_of(p.x), wy = w1_of(p.y), wz = w1_of(p.z);
+#pragma unroll
+        for (int o = 0; o < 8; ++o)
+          acc[o] += wsel(wx, o & 1) * wsel(wy, (o >> 1) & 1) * wsel(wz, o >> 2) * val;
+      }
+#pragma unroll
+      for (int o = 0; o < 8; ++o) W[o * T::NB + b] = acc[o];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int t = threadIdx.x + 256 * i;
+      sum[v][i] = 0.0f;
+      if (t < T::NC) {
+        const int cx = t % TX, cy = (t / TX) % TY, cz = t / (TX * TY);
+        sum[v][i] = tile_cell_sum<TX, TY, TZ>(W, cx, cy, cz);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int t = threadIdx.x + 256 * i;
+    if (t >= T::NC) continue;
+    const int cx = t % TX, cy = (t / TX) % TY, cz = t / (TX * TY);
+    const long long c = (static_cast<long long>(z0 + cz) * n + (y0 + cy)) * n + (x0 + cx);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) out[v * nc + c] += scale * sum[v][i];
+  }
 }
 
 // g4[c] = (g_x, g_y, g_z, 0),  g_d = -(phi[c + e_d] - phi[c - e_d]) / 2
@@ -647,16 +736,32 @@ void launch_gather_sorted(hipStream_t st, const Bins& bins, const float* v, cons
 
 void launch_deposit(hipStream_t st, const Bins& bins, const float* rho_gas,
                     long long rho_stride, float m_dm, float offset, float* out, const Batch& b) {
-  hipLaunchKernelGGL(deposit_kernel, per_sample(b.nc(), b), dim3(256), 0, st, bins.start,
-                     bins.spos, rho_gas, rho_stride, m_dm, offset, out, b.n, b.tab);
+  // tiles of 32 x 4 x 4 cells (16 x 4 x 4 at n = 16): 26 KB of LDS, six blocks per CU
+  if (b.n >= 32) {
+    const unsigned tiles = static_cast<unsigned>(b.nc() / (32 * 4 * 4));
+    hipLaunchKernelGGL((deposit_kernel<32, 4, 4>), dim3(tiles, b.S), dim3(256), 0, st,
+                       bins.start, bins.spos, rho_gas, rho_stride, m_dm, offset, out, b.n, b.tab);
+  } else {
+    const unsigned tiles = static_cast<unsigned>(b.nc() / (16 * 4 * 4));
+    hipLaunchKernelGGL((deposit_kernel<16, 4, 4>), dim3(tiles, b.S), dim3(256), 0, st,
+                       bins.start, bins.spos, rho_gas, rho_stride, m_dm, offset, out, b.n, b.tab);
+  }
   DH_LAUNCH_CHECK();
 }
 
 void launch_deposit_vec(hipStream_t st, const Bins& bins, bool merged, float* out_accum,
                         const Batch& b) {
   if (!b.tab) throw ArgError("deposit_vec: step table required");
-  hipLaunchKernelGGL(deposit_vec_kernel, per_sample(b.nc(), b), dim3(256), 0, st, bins.start,
-                     bins.spos, bins.sval, merged, out_accum, b.n, b.tab);
+  // tiles of 32 x 4 x 4 cells (16 x 4 x 4 at n = 16)
+  if (b.n >= 32) {
+    const unsigned tiles = static_cast<unsigned>(b.nc() / (32 * 4 * 4));
+    hipLaunchKernelGGL((deposit_vec_kernel<32, 4, 4>), dim3(tiles, b.S), dim3(256), 0, st,
+                       bins.start, bins.spos, bins.sval, merged, out_accum, b.n, b.tab);
+  } else {
+    const unsigned tiles = static_cast<unsigned>(b.nc() / (16 * 4 * 4));
+    hipLaunchKernelGGL((deposit_vec_kernel<16, 4, 4>), dim3(tiles, b.S), dim3(256), 0, st,
+                       bins.start, bins.spos, bins.sval, merged, out_accum, b.n, b.tab);
+  }
   DH_LAUNCH_CHECK();
 }
 
