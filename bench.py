@@ -1,6 +1,7 @@
 """Benchmark of the MI355X path: cell-updates/s of the full time step (forward with
 checkpoints plus the reverse pass) at 256^3 cells + 256^3 dark-matter particles, the
-forward-only rate, the HBM roofline fraction of the dominant kernel, the FP64 CPU oracle
+forward-only rate, the roofline of the dominant kernel (the hydro sweep, bound by vector ALU
+issue; its HBM fraction beside it), the FP64 CPU oracle
 timed on this host, the learned star-formation closure against the plain source term
 (its training, its step rates, and the distance of its final fields from the plain run's),
 and the batched parameter sampler (64 samples of 64^3 with their own seeds, star-formation
@@ -22,6 +23,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed FP32 instructions (this build emits none): 256 CUs x 4 SIMDs
+# x 16 lanes x 2 flops (FMA) x 2.4 GHz
+VALU_FP32_PEAK_TFLOPS = 78.6432
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4   # wave64 VALU instructions per second (4 cycles each)
+SWEEP_FLOPS_PER_CELL = 236           # FP32 operations of one sweep per cell (FMA = 2)
+SWEEP_BYTES_PER_CELL = 40            # read Q, write Q
 N = 256
 BOX = 40.0           # Mpc/h: cell size 0.156 Mpc/h, as the 128^3 / 20 Mpc/h box
 A_INIT = 0.01
@@ -47,11 +54,14 @@ def log(msg):
 
 
 def time_stage(torch, fn, reps):
-    """Average duration of one launch of fn() (HIP events on the current stream)."""
+    """Average duration of one launch of fn() (HIP events on the current stream).  One
+    untimed launch is queued before the start event, so the timed launches follow each other
+    without the idle gap of the first launch after a synchronisation."""
     fn()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    fn()
     e0.record()
     for _ in range(reps):
         fn()
@@ -60,22 +70,36 @@ def time_stage(torch, fn, reps):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
-def sweep_traffic_bytes():
-    """Measured HBM bytes per sweep launch at 256^3 (two rocprofv3 counter passes, calibrated
-    by streaming kernels of known size; profiles/sweep_256_traffic.json), or None when the
-    sweep sources have changed since the counters were taken."""
+def sweep_counter_record(name):
+    """A record of rocprofv3 counters of the 256^3 sweep launches (profiles/<name>), or None
+    when the sweep sources have changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "sweep_256_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         doc = json.load(fh)
-    for name, digest in doc.get("sources_sha256", {}).items():
-        src = os.path.join(ROOT, "paper_2502_02294_amd", "csrc", name)
+    for src_name, digest in doc.get("sources_sha256", {}).items():
+        src = os.path.join(ROOT, "paper_2502_02294_amd", "csrc", src_name)
         with open(src, "rb") as fh:
             if hashlib.sha256(fh.read()).hexdigest() != digest:
                 return None
-    return float(doc["traffic_bytes_per_launch"])
+    return doc
+
+
+def sweep_traffic_bytes():
+    """Measured HBM bytes per sweep launch at 256^3 (two counter passes, calibrated by
+    streaming kernels of known size), or None."""
+    doc = sweep_counter_record("sweep_256_traffic.json")
+    return float(doc["traffic_bytes_per_launch"]) if doc else None
+
+
+def sweep_valu_insts():
+    """Measured VALU wave instructions per sweep launch at 256^3 by axis, or None."""
+    doc = sweep_counter_record("sweep_256_valu.json")
+    if not doc:
+        return None
+    return {ax: float(v["valu_insts_per_launch"]) for ax, v in doc["per_axis"].items()}
 
 
 def time_steps(torch, s, white, steps, warmup):
@@ -297,7 +321,8 @@ def main():
     log(f"bench: forward {args.steps} steps {t_fwd * 1e3:.1f} ms")
     log(f"bench: forward+backward {args.steps} steps {t_fb * 1e3:.1f} ms")
 
-    # dominant kernel: the hydro sweep (three per step), 40 algorithmic bytes per cell
+    # dominant kernel: the hydro sweep (three per step, three adjoint sweeps in the reverse
+    # pass), bound by vector ALU issue: 236 FP32 operations and 40 bytes per cell and launch
     q = s.get("q")
     a, _, _ = s.time()
     sweep_t = {}
@@ -305,10 +330,15 @@ def main():
         sweep_t[axis] = time_stage(torch, lambda: s.stage_sweep(q, axis, sched[0], a, a),
                                    args.kernel_reps)
     t_sweep = sum(sweep_t.values()) / 3.0
-    bytes_per_launch = 40.0 * nc
-    achieved = bytes_per_launch / t_sweep / 1e9
+    flops_per_launch = SWEEP_FLOPS_PER_CELL * nc
+    achieved = flops_per_launch / t_sweep / 1e12
+    bytes_per_launch = SWEEP_BYTES_PER_CELL * nc
+    hbm_achieved = bytes_per_launch / t_sweep / 1e9
     measured = sweep_traffic_bytes() if n == N else None
     traffic = measured / t_sweep / 1e9 if measured else None
+    valu = sweep_valu_insts() if n == N else None
+    issue_frac = (sum(valu[ax] / sweep_t[i] for i, ax in enumerate("xyz")) / 3.0 / VALU_ISSUE_PEAK
+                  if valu else None)
 
     out = {
         "metric": "cell-updates/s fwd+bwd at 256^3 (forward with checkpoints + reverse pass)",
@@ -329,11 +359,16 @@ def main():
                    "n": n, "box_mpc_h": BOX * n / N, "ckpt_every": int(cfg.ckpt_every)},
         "fwd_cell_updates_per_s": nc * args.steps / t_fwd,
         "fwd_ms_per_step": t_fwd / args.steps * 1e3,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_bytes_per_launch": measured,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS,
+                     "traffic": traffic, "traffic_unit": "GB/s",
                      "kernel": "hydro sweep (x, y, z mean)",
+                     "algorithmic_flops_per_launch": flops_per_launch,
+                     "valu_issue_frac": issue_frac,
+                     "hbm": {"achieved": hbm_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": hbm_achieved / HBM_PEAK_GBS,
+                             "algorithmic_bytes_per_launch": bytes_per_launch,
+                             "traffic_bytes_per_launch": measured},
                      "ms_per_launch": {str(k_): v * 1e3 for k_, v in sweep_t.items()}},
     }
     s.close()
