@@ -360,17 +360,30 @@ bool all_finite(const std::vector<double>& v) {
 void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp) {
   const long long nc = s->nc, np = s->np;
   const Batch b = batch(s, tab_of(s, sp));
+  const float* pos_in = s->pos;
   if (tp) {
     tp->plan = sp;
-    copy_d2d(s, tp->q[0], s->q, 5 * nc * s->S);
-    copy_d2d(s, tp->x0, s->pos, 3 * np * s->S);
-    copy_d2d(s, tp->phi0, s->phi, nc * s->S);
+    bool all = true;
+    for (int i = 0; i < s->S; ++i) all = all && sp.smp[i].active;
+    if (all) {
+      // every sample moves: the state buffers become the tape's step-start entries and the
+      // step writes the new state into the tape's former buffers (every pass below writes
+      // all of its output), so nothing is copied
+      std::swap(s->q, tp->q[0]);
+      std::swap(s->pos, tp->x0);
+      std::swap(s->phi, tp->phi0);
+      pos_in = tp->x0;
+    } else {
+      copy_d2d(s, tp->q[0], s->q, 5 * nc * s->S);
+      copy_d2d(s, tp->x0, s->pos, 3 * np * s->S);
+      copy_d2d(s, tp->phi0, s->phi, nc * s->S);
+    }
   }
   const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
   if (tp) {
     // the kick, the sweeps and the closing pass write their results straight into the tape
-    dh::launch_gas_kick(s->st, s->q, tp->q[1], s->g4, b);
-    dh::launch_kick_drift(s->st, s->g4, s->pos, s->mom, s->bins.key, nullptr, tp->x1, b);
+    dh::launch_gas_kick(s->st, tp->q[0], tp->q[1], s->g4, b);
+    dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, tp->x1, b);
     for (int k = 0; k < 3; ++k) dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
     dh::launch_sort(s->st, s->bins, s->pos, b);
     potential_from_bins(s, tp->q[4], s->phi, s->g4, b);
@@ -380,7 +393,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp) {
   } else {
     // opening half kicks with g_n, drift with a(t + dt/2)
     dh::launch_gas_kick(s->st, s->q, s->q, s->g4, b);
-    dh::launch_kick_drift(s->st, s->g4, s->pos, s->mom, s->bins.key, nullptr, nullptr, b);
+    dh::launch_kick_drift(s->st, s->g4, s->pos, s->pos, s->mom, s->bins.key, nullptr, nullptr, b);
     // sweeps in the Strang order of the step (a sample that sits out is copied along)
     for (int k = 0; k < 3; ++k) {
       dh::launch_sweep(s->st, s->q, s->q2, b, sp.axes[k]);

@@ -153,58 +153,35 @@ __device__ __forceinline__ void split_flux_vjp(const float q[5], const HydroK& h
   for (int k = 0; k < 5; ++k) out[k] = 0.5f * (c * s[k] + dc[k] * qs + jt[k]);
 }
 
-// van Leer limiter with guard epsilon (Sec. 2.3.2):
-//   phi(x, y) = (x y + |x y|) / (x + y + eps sgn(x+y)),  sgn(0) = +1,
-// evaluated as 2xy / (x + y + eps sgn) when xy > 0 and 0 otherwise.  The selection is the
-// same function; it matters in floating point: with fused multiply-add contraction the sum
-// x*y + |x*y| is not exactly zero for xy < 0, and where x ~ -y the residue would be divided by
-// a denominator of order eps.  Both sides of the selection are computed (no branch); the
-// discarded one is finite or an infinity, never read.
+// van Leer limiter (Sec. 2.3.2): phi(x, y) = (x y + |x y|) / (x + y + eps sgn(x+y)),
+// eps = 1e-20, sgn(0) = +1.  The sweeps call it on half differences, phi(a/2, b/2), written
+// here on the undivided differences a, b:
+//   van_leer_half(a, b) = a b / (a + b + 2 eps sgn(a+b))  where a b > 0,  0 otherwise.
+// Where a b > 0, |a + b| >= 2 sqrt(a b) > 0: the guard only moves the value by at most eps/2
+// in absolute terms, below any FP32 flux, and is left out.  The selection on a b > 0 is the
+// function itself (an FMA-contracted x y + |x y| is not exactly zero for x y < 0); both
+// sides are computed and the discarded one is never read.
 constexpr float kLimEps = 1e-20f;
 
-__device__ __forceinline__ float van_leer(float x, float y) {
-  const float xy = x * y;
-  const float s = x + y;
-  const float r = (2.0f * xy) * rcp_approx(s + (s >= 0.0f ? kLimEps : -kLimEps));
-  return xy > 0.0f ? r : 0.0f;
-}
-
-// van_leer(a/2, b/2) of two undivided differences, written as a b / (a + b + 2 eps sgn(a+b)).
-// The sign of a zero sum is immaterial: it only occurs where a b <= 0.
 __device__ __forceinline__ float van_leer_half(float a, float b) {
   const float ab = a * b;
-  const float s = a + b;
-  const float r = ab * rcp_approx(s + __builtin_copysignf(2.0f * kLimEps, s));
+  const float r = ab * rcp_approx(a + b);
   return ab > 0.0f ? r : 0.0f;
 }
 
-// Partial derivatives of van_leer_half with respect to a and b.  Where a b == 0 the derivative
-// of |a b| is taken with sign(0) = 0 (half the one-sided slopes), where a b < 0 both are zero.
+// Partial derivatives of van_leer_half: (b/(a+b))^2 and (a/(a+b))^2 where a b > 0; where
+// a b == 0 the derivative of |a b| is taken with sign(0) = 0, which gives half the one-sided
+// slopes b/(2(a+b)) and a/(2(a+b)) (the guard keeps them finite at a = b = 0); zero where
+// a b < 0.
 __device__ __forceinline__ void van_leer_half_d(float a, float b, float& da, float& db) {
   const float ab = a * b;
   const float s = a + b;
   const float id = rcp_approx(s + __builtin_copysignf(2.0f * kLimEps, s));
-  const float q = ab * id * id;
   const float hb = b * id, ha = a * id;
-  const float pa = hb - q, pb = ha - q;
+  const float pa = hb * hb, pb = ha * ha;
   const float za = ab < 0.0f ? 0.0f : 0.5f * hb, zb = ab < 0.0f ? 0.0f : 0.5f * ha;
   da = ab > 0.0f ? pa : za;
   db = ab > 0.0f ? pb : zb;
-}
-
-// Partial derivatives of van_leer; where xy == 0 the derivative of |xy| is taken with
-// sign(0) = 0 (half the one-sided slopes), where xy < 0 both are zero.
-__device__ __forceinline__ void van_leer_d(float x, float y, float& dx, float& dy) {
-  const float xy = x * y;
-  const float s = x + y;
-  const float den = s + (s >= 0.0f ? kLimEps : -kLimEps);
-  const float id = rcp_approx(den);
-  const float q = (2.0f * xy) * id * id;
-  const float hy = y * id, hx = x * id;
-  const float px = 2.0f * hy - q, py = 2.0f * hx - q;
-  const float zx = xy < 0.0f ? 0.0f : hy, zy = xy < 0.0f ? 0.0f : hx;
-  dx = xy > 0.0f ? px : zx;
-  dy = xy > 0.0f ? py : zy;
 }
 
 // ---------------------------------------------------------------------------------------

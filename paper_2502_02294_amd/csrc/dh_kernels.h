@@ -81,9 +81,11 @@ void launch_grad(hipStream_t st, const float* phi, float4* g4, const Batch& b);
 // g at particles: out[3][np] = CIC read-out of g4
 void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float* out,
                       const Batch& b);
-// opening kick (h) + drift (drift) + keys; optional copies of the new momenta and positions
-void launch_kick_drift(hipStream_t st, const float4* g4, float* pos, float* mom, uint32_t* key,
-                       float* mom_copy, float* pos_copy, const Batch& b);
+// opening kick (h) + drift (drift) + keys: positions read from pos_in and written to pos
+// (the same array for an update in place); optional copies of the new momenta and positions
+void launch_kick_drift(hipStream_t st, const float4* g4, const float* pos_in, float* pos,
+                       float* mom, uint32_t* key, float* mom_copy, float* pos_copy,
+                       const Batch& b);
 // closing kick p += h g(x)
 void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom, const Batch& b);
 // adjoint of p' = p + k g(x) with respect to x: lam_x += k sum_c dw/dx (g_c . lam_p'), with

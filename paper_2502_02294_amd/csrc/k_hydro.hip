@@ -139,6 +139,8 @@ struct WalkFwd {
   float f1[2][5];            // stage-1 face flux (k - j) - 1/2 in slot (i - j) & 1
   float r2[4][5], l2[4][5];  // stage-2 split of cell k - 1 - j in slot (i - j) & 3
   float f2[2][5];            // limited stage-2 face (k - 3 - j) + 1/2 in slot (i - j) & 1
+  float dr[2][5], dl[2][5];  // upper slopes of face (k - 3 - j) + 1/2 in slot (i - j) & 1: the
+                             // lower slopes of the next face
 };
 
 struct WalkPtr {
@@ -181,13 +183,17 @@ __device__ __forceinline__ void walk_fwd_visit(WalkFwd<D>& w, const WalkPtr& p, 
   for (int c = 0; c < 5; ++c) qh[c] = w.u[s1][c] - hdt * (w.f1[p0][c] - w.f1[p1][c]);
   split_flux<D>(qh, h2, w.r2[t0], w.l2[t0]);
   if (STAGE < 3) return;
-  // face (k-3)+1/2: F^R at cells k-4, k-3, k-2 (slots t3, t2, t1), F^L at k-3, k-2, k-1
+  // face (k-3)+1/2: F^R at cells k-4, k-3, k-2 (slots t3, t2, t1), F^L at k-3, k-2, k-1; the
+  // lower slopes are the previous face's upper ones
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
-    const float rm = w.r2[t3][c], r0 = w.r2[t2][c], rp = w.r2[t1][c];
-    const float l0 = w.l2[t2][c], lp = w.l2[t1][c], lpp = w.l2[t0][c];
-    const float fr = r0 + van_leer_half(r0 - rm, rp - r0);
-    const float fl = lp - van_leer_half(lp - l0, lpp - lp);
+    const float r0 = w.r2[t2][c], lp = w.l2[t1][c];
+    const float sr = STAGE == 3 ? r0 - w.r2[t3][c] : w.dr[p1][c];
+    const float sl = STAGE == 3 ? lp - w.l2[t2][c] : w.dl[p1][c];
+    w.dr[p0][c] = w.r2[t1][c] - r0;
+    w.dl[p0][c] = w.l2[t0][c] - lp;
+    const float fr = r0 + van_leer_half(sr, w.dr[p0][c]);
+    const float fl = lp - van_leer_half(sl, w.dl[p0][c]);
     w.f2[p0][c] = fr - fl;
   }
   if (STAGE < 4) return;

@@ -509,8 +509,9 @@ __device__ __forceinline__ float wrap_pos(float x, float fn) {
   return x;
 }
 
+// pos_in and pos may be the same array (in place): no __restrict__ on them
 __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restrict__ g4,
-                                                         float* __restrict__ pos,
+                                                         const float* pos_in, float* pos,
                                                          float* __restrict__ mom,
                                                          uint32_t* __restrict__ key,
                                                          float* __restrict__ mom_copy,
@@ -522,6 +523,7 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
   if (i >= np) return;
   const int smp = blockIdx.y;
   g4 += smp * np;
+  pos_in += smp * 3 * np;
   pos += smp * 3 * np;
   mom += smp * 3 * np;
   key += smp * np;
@@ -532,13 +534,15 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
     // reverse pass, which sorts them again) receive them unchanged
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
+      const float xd = pos_in[d * np + i];
+      if (pos != pos_in) pos[d * np + i] = xd;
       if (mom_copy) mom_copy[d * np + i] = mom[d * np + i];
-      if (pos_copy) pos_copy[d * np + i] = pos[d * np + i];
+      if (pos_copy) pos_copy[d * np + i] = xd;
     }
     return;
   }
   const float h = sc.h, drift_fac = sc.drift;
-  float x[3] = {pos[i], pos[np + i], pos[2 * np + i]};
+  float x[3] = {pos_in[i], pos_in[np + i], pos_in[2 * np + i]};
   const Cic w = cic_of(x[0], x[1], x[2], n);
   float g[3];
   readout_g(g4, w, n, g);
@@ -777,11 +781,12 @@ void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float*
   DH_LAUNCH_CHECK();
 }
 
-void launch_kick_drift(hipStream_t st, const float4* g4, float* pos, float* mom, uint32_t* key,
-                       float* mom_copy, float* pos_copy, const Batch& b) {
+void launch_kick_drift(hipStream_t st, const float4* g4, const float* pos_in, float* pos,
+                       float* mom, uint32_t* key, float* mom_copy, float* pos_copy,
+                       const Batch& b) {
   if (!b.tab) throw ArgError("kick_drift: step table required");
-  hipLaunchKernelGGL(kick_drift_kernel, per_sample(b.nc(), b), dim3(256), 0, st, g4, pos, mom, key,
-                     mom_copy, pos_copy, b.n, b.nc(), b.tab);
+  hipLaunchKernelGGL(kick_drift_kernel, per_sample(b.nc(), b), dim3(256), 0, st, g4, pos_in, pos,
+                     mom, key, mom_copy, pos_copy, b.n, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
