@@ -12,7 +12,7 @@ import torch
 import synth_inputs as si
 from gpu_helpers import (displacement_err, gpu_config, gpu_params, load_state, rel_l2,
                          round32, rounded_state, to_gpu, to_np)
-from oracle import gravity, hydro, ics, sim as osim, subgrid
+from oracle import cosmology, gravity, hydro, ics, sim as osim, subgrid
 
 pytestmark = pytest.mark.gpu
 torch.set_default_dtype(torch.float64)
@@ -327,26 +327,49 @@ def test_conservation_sums(dhp):
 
 # ---------------------------------------------------------------- gradients
 
-def test_gradient_matches_oracle_autograd(dhp):
-    n = 16
-    ocfg = osim.default_config(n=n, box=4.0, subgrid=subgrid.MODE_RELAXED, a_init=0.05,
-                               )
+def _initial_state_fp32_cells(white, ocfg):
+    """The oracle's initial state with the CIC cell of every particle decided on its float32
+    position, as the GPU decides it: the values of x are rounded to float32, the gradient
+    passes through the rounding.  The lattice puts every particle on a CIC kink (a cell
+    centre), so a displacement within float32 rounding of zero picks the neighbouring cell
+    differently in float32 and float64; a 64^3 field has a few such particles, and each moves
+    the exact gradient by ~1e-3."""
+    n = ocfg.n
+    a = ocfg.a_init
+    psi = ics.za_displacement(ics.linear_density(white, ocfg), n)
+    psi_p = psi.reshape(3, -1)
+    x = torch.remainder(ics.lattice(n) + psi_p, float(n))
+    x = x + (round32(x) - x).detach()
+    vfac = a * a * cosmology.hubble_e(a, ocfg.omega_m) * cosmology.growth_rate(a, ocfg.omega_m)
+    p = vfac * psi_p
+    rho = ocfg.f_b * gravity.cic_deposit(x, 1.0, n)
+    mom = rho * (vfac * psi)
+    u = mom / (a * rho)
+    etot = a * a * rho * (ocfg.e_init + 0.5 * (u * u).sum(0))
+    return osim.state_from_qxp(torch.cat([rho[None], mom, etot[None]]), x, p, ocfg)
+
+
+@pytest.mark.parametrize("n,box,a_init,nsteps,ckpt", [(16, 4.0, 0.05, 4, 3), (64, 10.0, 0.01, 2, 1)])
+def test_gradient_matches_oracle_autograd(dhp, n, box, a_init, nsteps, ckpt):
+    # 16^3: star formation active in most cells; 64^3: the launch shapes of larger grids
+    # (whole-segment walks, 8 x 8 FFT lines, tiled deposits), two checkpoint segments
+    print(f"gradient vs oracle autograd, {n}^3, {nsteps} steps", flush=True)
+    ocfg = osim.default_config(n=n, box=box, subgrid=subgrid.MODE_RELAXED, a_init=a_init)
     prm = osim.Params(delta_c=1.05, t_c=1e6, eps_sf=0.5)
     w = si.white_noise(n, seed=21)
     target = (0.2 + 0.7 * np.random.default_rng(1).random((n, n, n))).astype(np.float32)
-    nsteps = 4
     # oracle schedule and autograd gradient
     st0 = osim.initial_state(torch.from_numpy(w).double(), ocfg)
     _, sched = osim.run(st0, ocfg, prm, nsteps=nsteps)
     w64 = torch.from_numpy(w).double().requires_grad_(True)
     th = torch.tensor([prm.A, prm.beta, prm.eps_sf, prm.delta_c], requires_grad=True)
     p2 = osim.Params(A=th[0], beta=th[1], eps_sf=th[2], delta_c=th[3], t_c=prm.t_c)
-    st = osim.initial_state(w64, ocfg)
+    st = _initial_state_fp32_cells(w64, ocfg)
     st, _ = osim.run(st, ocfg, p2, schedule=sched)
     loss = osim.loss(st, torch.from_numpy(target).double(), ocfg, th[0], th[1])
     gw_ref, gp_ref = torch.autograd.grad(loss, (w64, th))
     # GPU
-    s = _sim(dhp, ocfg, prm, ckpt_every=3)
+    s = _sim(dhp, ocfg, prm, ckpt_every=ckpt)
     s.set_schedule(sched)
     k = s.forward(to_gpu(w), 1.0)
     assert k == nsteps
