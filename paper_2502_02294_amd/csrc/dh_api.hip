@@ -55,6 +55,7 @@ struct TapeStep {
                     // Q4 after sweeps, Q5 after closing kick (source input)
   float *x0, *x1;             // particle positions at the start and after the drift
   float *phi0, *phi1;
+  uint32_t *start, *sorted;   // the step's sort of x1 (bin starts, ids in bin order)
   StepPlan plan;
 };
 
@@ -388,6 +389,10 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp) {
     dh::launch_sort(s->st, s->bins, s->pos, b);
     potential_from_bins(s, tp->q[4], s->phi, s->g4, b);
     copy_d2d(s, tp->phi1, s->phi, nc * s->S);
+    // the tape keeps this sort of x1 for the reverse pass; the next sort writes the tape's
+    // former buffers
+    std::swap(s->bins.start, tp->start);
+    std::swap(s->bins.sorted, tp->sorted);
     dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, s->star, tp->q[5], s->cfg.gamma,
                           s->cfl_red, b, closure);
   } else {
@@ -543,6 +548,8 @@ void alloc_tape_entry(dh_sim* s, TapeStep& t) {
   t.x1 = s->alloc<float>(3 * s->np * S);
   t.phi0 = s->alloc<float>(s->nc * S);
   t.phi1 = s->alloc<float>(s->nc * S);
+  t.start = s->alloc<uint32_t>(s->nc * S + 1);
+  t.sorted = s->alloc<uint32_t>(s->np * S);
 }
 
 void save_ckpt(dh_sim* s, Ckpt& c) {
@@ -611,9 +618,15 @@ void step_vjp(dh_sim* s, const TapeStep& T) {
   // closing kicks (gas from Q4, DM at x1) -> lambda_g -> lambda_phi_{n+1}
   dh::launch_grad(st, T.phi1, s->g4b, b);
   dh::launch_gas_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, b);
-  sort_particles(s, T.x1, b);
-  dh::launch_gather_sorted(st, s->bins, s->lp, b);
-  dh::launch_deposit_vec(st, s->bins, true, s->lg, b);
+  // x1 in bin order from the sort the recomputed step kept, then lambda_p in the same order
+  dh::Bins tb = s->bins;
+  tb.start = T.start;
+  tb.sorted = T.sorted;
+  tb.sval = tb.spos;
+  dh::launch_gather_sorted(st, tb, T.x1, b);
+  tb.sval = s->bins.sval;
+  dh::launch_gather_sorted(st, tb, s->lp, b);
+  dh::launch_deposit_vec(st, tb, true, s->lg, b);
   dh::launch_kick_vjp_pos(st, s->g4b, T.x1, s->lp, true, s->lx, b);
   dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi2, b);
   // Poisson (symmetric operator) and deposit at x1
