@@ -88,6 +88,7 @@ struct dh_sim {
   float2 *spec = nullptr, *spec2 = nullptr, *tw = nullptr;
   float4* g4 = nullptr;        // (-grad phi, 0) of the current potential
   float4* g4b = nullptr;       // scratch acceleration field for the reverse pass and stages
+  int g4b_phi0_of = -1;         // g4b holds -grad of this step's phi0 (every sample moved), or -1
   dh::Bins bins{};
   double* cfl_red = nullptr;   // CFL block maxima of the current state (from the closing pass)
   bool cfl_partials = false;   // cfl_red holds the maxima of the current state
@@ -616,7 +617,11 @@ void step_vjp(dh_sim* s, const TapeStep& T) {
     dh::launch_reduce_sum(st, s->red, nb, nb, 2 * s->S, s->param_steps + 2LL * s->S * sp.slot);
   }
   // closing kicks (gas from Q4, DM at x1) -> lambda_g -> lambda_phi_{n+1}
-  dh::launch_grad(st, T.phi1, s->g4b, b);
+  // phi1 of this step is phi0 of the next one (bit for bit, also across a checkpoint), whose
+  // gradient the previous call left in g4b when every sample moved in both steps
+  bool all = true;
+  for (int i = 0; i < s->S; ++i) all = all && sp.smp[i].active;
+  if (!(all && s->g4b_phi0_of == sp.step + 1)) dh::launch_grad(st, T.phi1, s->g4b, b);
   dh::launch_gas_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, b);
   // x1 in bin order from the sort the recomputed step kept, then lambda_p in the same order
   dh::Bins tb = s->bins;
@@ -642,6 +647,7 @@ void step_vjp(dh_sim* s, const TapeStep& T) {
   dh::launch_axpy(st, s->lp, s->lx, 1.0f, 3 * np, 3 * np, 3 * np, true, b);
   // opening gas kick with phi_n
   dh::launch_grad(st, T.phi0, s->g4b, b);
+  s->g4b_phi0_of = all ? sp.step : -1;
   dh::launch_gas_kick_vjp(st, T.q[0], s->g4b, s->lq, s->lg, b);
   dh::launch_grad_vjp(st, s->lg, nullptr, s->lphi, b);
 }
@@ -651,6 +657,7 @@ void finish_first_kick(dh_sim* s, const TapeStep& T) {
   const Batch b = batch(s, tab_of(s, T.plan));
   hipStream_t st = s->st;
   dh::launch_grad(st, T.phi0, s->g4b, b);
+  s->g4b_phi0_of = -1;
   dh::launch_fill(st, s->lg, 0.0f, 3 * s->nc * s->S);
   sort_particles(s, T.x0, b);
   dh::launch_gather_sorted(st, s->bins, s->lp, b);
@@ -1125,6 +1132,7 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     const int S = s->S;
     const long long nc = s->nc, np = s->np;
     const int nsteps = s->fwd_steps;
+    s->g4b_phi0_of = -1;
     const int K = s->cfg.ckpt_every;
     if (!s->lq) {
       s->lq = s->alloc<float>(5 * nc * S);
@@ -1301,6 +1309,7 @@ int dh_stage_readout(dh_sim* s, const float* d_phi, const float* d_pos, float* d
   return guarded(s, [&]() -> int {
     const Batch one{s->n, 1, nullptr};
     dh::launch_grad(s->st, d_phi, s->g4b, one);
+    s->g4b_phi0_of = -1;
     dh::launch_readout_g(s->st, s->g4b, d_pos, d_g, one);
     return DH_OK;
   });
