@@ -443,23 +443,28 @@ __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __rest
   }
 }
 
+// Cell c of one sample (at most 256^3, so 32-bit) from its x, y, z: n is a power of two.
+struct GridIdx {
+  unsigned n1, lg;   // n - 1, log2 n
+  __device__ __forceinline__ unsigned at(unsigned x, unsigned y, unsigned z) const {
+    return (((z & n1) << lg | (y & n1)) << lg) | (x & n1);
+  }
+};
+
 // g4[c] = (g_x, g_y, g_z, 0),  g_d = -(phi[c + e_d] - phi[c - e_d]) / 2
 __global__ void __launch_bounds__(256) grad_kernel(const float* __restrict__ phi,
-                                                   float4* __restrict__ g4, int n,
+                                                   float4* __restrict__ g4, int n, int lgn,
                                                    const StepScal* __restrict__ tab) {
-  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const long long nn = static_cast<long long>(n) * n, nc = nn * n;
+  const unsigned c = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nc = 1u << (3 * lgn);
   if (c >= nc || !sample_active(tab, blockIdx.y)) return;
-  phi += blockIdx.y * nc;
-  g4 += blockIdx.y * nc;
-  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
-            iz = static_cast<int>(c / nn);
-  const long long zo = static_cast<long long>(iz) * nn, yo = static_cast<long long>(iy) * n;
-  const float gx = -0.5f * (phi[zo + yo + wrapi(ix + 1, n)] - phi[zo + yo + wrapi(ix - 1, n)]);
-  const float gy = -0.5f * (phi[zo + static_cast<long long>(wrapi(iy + 1, n)) * n + ix] -
-                            phi[zo + static_cast<long long>(wrapi(iy - 1, n)) * n + ix]);
-  const float gz = -0.5f * (phi[static_cast<long long>(wrapi(iz + 1, n)) * nn + yo + ix] -
-                            phi[static_cast<long long>(wrapi(iz - 1, n)) * nn + yo + ix]);
+  phi += static_cast<long long>(blockIdx.y) * nc;
+  g4 += static_cast<long long>(blockIdx.y) * nc;
+  const GridIdx gi{static_cast<unsigned>(n - 1), static_cast<unsigned>(lgn)};
+  const unsigned ix = c & gi.n1, iy = (c >> lgn) & gi.n1, iz = c >> (2 * lgn);
+  const float gx = -0.5f * (phi[gi.at(ix + 1, iy, iz)] - phi[gi.at(ix - 1, iy, iz)]);
+  const float gy = -0.5f * (phi[gi.at(ix, iy + 1, iz)] - phi[gi.at(ix, iy - 1, iz)]);
+  const float gz = -0.5f * (phi[gi.at(ix, iy, iz + 1)] - phi[gi.at(ix, iy, iz - 1)]);
   g4[c] = make_float4(gx, gy, gz, 0.0f);
 }
 
@@ -654,23 +659,23 @@ __global__ void axpy_kernel(float* __restrict__ y, const float* __restrict__ x, 
 // lam_phi[c] = lam_phi_in[c] + sum_d (lam_g_d[c + e_d] - lam_g_d[c - e_d]) / 2
 __global__ void __launch_bounds__(256) grad_vjp_kernel(const float* __restrict__ lam_g,
                                                        const float* __restrict__ lam_phi_in,
-                                                       float* __restrict__ lam_phi, int n,
+                                                       float* __restrict__ lam_phi, int n, int lgn,
                                                        const StepScal* __restrict__ tab) {
-  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const long long nn = static_cast<long long>(n) * n, nc = nn * n;
+  const unsigned c = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nc = 1u << (3 * lgn);
   if (c >= nc || !sample_active(tab, blockIdx.y)) return;
-  lam_g += blockIdx.y * 3 * nc;
-  if (lam_phi_in) lam_phi_in += blockIdx.y * nc;
-  lam_phi += blockIdx.y * nc;
-  const int ix = static_cast<int>(c % n), iy = static_cast<int>((c / n) % n),
-            iz = static_cast<int>(c / nn);
-  const long long zo = static_cast<long long>(iz) * nn, yo = static_cast<long long>(iy) * n;
+  lam_g += static_cast<long long>(blockIdx.y) * 3 * nc;
+  if (lam_phi_in) lam_phi_in += static_cast<long long>(blockIdx.y) * nc;
+  lam_phi += static_cast<long long>(blockIdx.y) * nc;
+  const GridIdx gi{static_cast<unsigned>(n - 1), static_cast<unsigned>(lgn)};
+  const unsigned ix = c & gi.n1, iy = (c >> lgn) & gi.n1, iz = c >> (2 * lgn);
+  const float* lx = lam_g;
+  const float* ly = lam_g + nc;
+  const float* lz = lam_g + 2 * static_cast<long long>(nc);
   float v = lam_phi_in ? lam_phi_in[c] : 0.0f;
-  v += 0.5f * (lam_g[zo + yo + wrapi(ix + 1, n)] - lam_g[zo + yo + wrapi(ix - 1, n)]);
-  v += 0.5f * (lam_g[nc + zo + static_cast<long long>(wrapi(iy + 1, n)) * n + ix] -
-               lam_g[nc + zo + static_cast<long long>(wrapi(iy - 1, n)) * n + ix]);
-  v += 0.5f * (lam_g[2 * nc + static_cast<long long>(wrapi(iz + 1, n)) * nn + yo + ix] -
-               lam_g[2 * nc + static_cast<long long>(wrapi(iz - 1, n)) * nn + yo + ix]);
+  v += 0.5f * (lx[gi.at(ix + 1, iy, iz)] - lx[gi.at(ix - 1, iy, iz)]);
+  v += 0.5f * (ly[gi.at(ix, iy + 1, iz)] - ly[gi.at(ix, iy - 1, iz)]);
+  v += 0.5f * (lz[gi.at(ix, iy, iz + 1)] - lz[gi.at(ix, iy, iz - 1)]);
   lam_phi[c] = v;
 }
 
@@ -770,7 +775,8 @@ void launch_deposit_vec(hipStream_t st, const Bins& bins, bool merged, float* ou
 }
 
 void launch_grad(hipStream_t st, const float* phi, float4* g4, const Batch& b) {
-  hipLaunchKernelGGL(grad_kernel, per_sample(b.nc(), b), dim3(256), 0, st, phi, g4, b.n, b.tab);
+  hipLaunchKernelGGL(grad_kernel, per_sample(b.nc(), b), dim3(256), 0, st, phi, g4, b.n,
+                     log2_ll(b.n), b.tab);
   DH_LAUNCH_CHECK();
 }
 
@@ -823,7 +829,7 @@ void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long co
 void launch_grad_vjp(hipStream_t st, const float* lam_g, const float* lam_phi_in, float* lam_phi,
                      const Batch& b) {
   hipLaunchKernelGGL(grad_vjp_kernel, per_sample(b.nc(), b), dim3(256), 0, st, lam_g, lam_phi_in,
-                     lam_phi, b.n, b.tab);
+                     lam_phi, b.n, log2_ll(b.n), b.tab);
   DH_LAUNCH_CHECK();
 }
 
