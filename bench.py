@@ -107,17 +107,14 @@ def time_steps(torch, s, white, steps, warmup):
     steps from the initial conditions of `white`, after `warmup` untimed steps / one untimed
     pass of the full path."""
     s.init_from_noise(white)
-    for _ in range(warmup):
-        s.step()
+    s.run_steps(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        s.step()
+    assert s.run_steps(steps) == steps
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     s.init_from_noise(white)
-    for _ in range(steps):
-        s.step()
+    s.run_steps(steps)
     sched = s.get_schedule()
     target = s.get("flux").clone()
     s.set_schedule(sched)

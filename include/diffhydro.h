@@ -130,8 +130,15 @@ int dh_init_from_noise(dh_sim* sim, const float* d_white);
  * non-positive density. */
 int dh_step(dh_sim* sim, double* dt_out, double* a_out);
 /* Steps until a >= a_final for every sample (the last step of each is clipped to land on
- * a_final); *nsteps_out = number of lockstep steps taken. */
+ * a_final); *nsteps_out = number of lockstep steps taken.  Inside the loop the closing
+ * dark-matter half kick of a step is applied together with the next step's opening kick
+ * (one pass over the particles, the same roundings as dh_step's separate kicks); the state
+ * is complete again when the call returns. */
 int dh_run_to(dh_sim* sim, double a_final, int32_t* nsteps_out);
+/* nsteps steps as dh_step would take them one by one (same results bit for bit), in one
+ * call, with the kick fusion of dh_run_to; *nsteps_out (may be NULL) = steps taken (fewer
+ * only on error).  nsteps < 0: DH_E_INVAL; DH_E_NONFINITE as dh_step. */
+int dh_run_steps(dh_sim* sim, int32_t nsteps, int32_t* nsteps_out);
 
 /* Predefined schedule (Sec. 2.3.3).  set: the next steps take dts[0..n) in order (then the
  * CFL again); n = 0 clears it.  get: the dt of every step since the last init, at most

@@ -71,6 +71,7 @@ _SIGNATURES = {
     "dh_init_from_noise": (I, [P, P]),
     "dh_step": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
     "dh_run_to": (I, [P, D, ctypes.POINTER(I)]),
+    "dh_run_steps": (I, [P, I, ctypes.POINTER(I)]),
     "dh_set_schedule": (I, [P, ctypes.POINTER(D), I]),
     "dh_get_schedule": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
     "dh_set_sample_schedule": (I, [P, I, ctypes.POINTER(D), I]),

@@ -89,6 +89,12 @@ struct dh_sim {
   float4* g4 = nullptr;        // (-grad phi, 0) of the current potential
   float4* g4b = nullptr;       // scratch acceleration field for the reverse pass and stages
   int g4b_phi0_of = -1;         // g4b holds -grad of this step's phi0 (every sample moved), or -1
+  // Closing dark-matter half kicks left to the next step's kick-drift pass (one pass over the
+  // particles instead of two): factor per sample, 0 when none.  Only the step loops of
+  // run_to / forward / run_steps defer, and they apply what is left before returning, so
+  // outside them the state is always complete.
+  std::vector<float> kick_due;
+  bool kick_pending = false;
   dh::Bins bins{};
   double* cfl_red = nullptr;   // CFL block maxima of the current state (from the closing pass)
   bool cfl_partials = false;   // cfl_red holds the maxima of the current state
@@ -231,6 +237,7 @@ StepScal entry_of(const dh_sim* s, int smp, const Plan& p, int step) {
   e.h2 = hydro_at(s, p.ah);
   e.green = green_at(s, p.a1);
   e.h_dm = e.h;
+  e.h_prev = s->kick_due[smp];
   return e;
 }
 
@@ -301,6 +308,29 @@ const StepScal* stage_table(dh_sim* s, const StepScal& e) {
   return s->stage_tab;
 }
 
+// Applies the deferred closing kicks (same arithmetic as the kick at the end of a step).
+void flush_kick(dh_sim* s) {
+  if (!s->kick_pending) return;
+  sync(s);
+  for (int i = 0; i < s->S; ++i) {
+    StepScal e{};
+    e.active = s->kick_due[i] != 0.0f ? 1 : 0;
+    e.h = s->kick_due[i];
+    s->hstage[i] = e;
+  }
+  DH_HIP(hipMemcpyAsync(s->cur_tab, s->hstage, static_cast<size_t>(s->S) * sizeof(StepScal),
+                        hipMemcpyHostToDevice, s->st));
+  dh::launch_kick(s->st, s->g4, s->pos, s->mom, Batch{s->n, s->S, s->cur_tab});
+  std::fill(s->kick_due.begin(), s->kick_due.end(), 0.0f);
+  s->kick_pending = false;
+}
+
+// drops deferred kicks that a new state replaces
+void drop_kick(dh_sim* s) {
+  std::fill(s->kick_due.begin(), s->kick_due.end(), 0.0f);
+  s->kick_pending = false;
+}
+
 // bins of the particle positions pos (all samples of b)
 void sort_particles(dh_sim* s, const float* pos, const Batch& b) {
   dh::launch_keys(s->st, pos, s->bins.key, b);
@@ -359,8 +389,11 @@ bool all_finite(const std::vector<double>& v) {
 }
 
 // One step of the method on the handle state.  With a tape entry, keeps its intermediates.
-void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp) {
+// defer (no tape only): leave the closing dark-matter kick to the next step's kick-drift pass.
+void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
   const long long nc = s->nc, np = s->np;
+  if (tp || !defer) flush_kick(s);
+  const bool prev = s->kick_pending;
   const Batch b = batch(s, tab_of(s, sp));
   const float* pos_in = s->pos;
   if (tp) {
@@ -385,7 +418,8 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp) {
   if (tp) {
     // the kick, the sweeps and the closing pass write their results straight into the tape
     dh::launch_gas_kick(s->st, tp->q[0], tp->q[1], s->g4, b);
-    dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, tp->x1, b);
+    dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, tp->x1,
+                          false, b);
     for (int k = 0; k < 3; ++k) dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
     dh::launch_sort(s->st, s->bins, s->pos, b);
     potential_from_bins(s, tp->q[4], s->phi, s->g4, b);
@@ -399,7 +433,8 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp) {
   } else {
     // opening half kicks with g_n, drift with a(t + dt/2)
     dh::launch_gas_kick(s->st, s->q, s->q, s->g4, b);
-    dh::launch_kick_drift(s->st, s->g4, s->pos, s->pos, s->mom, s->bins.key, nullptr, nullptr, b);
+    dh::launch_kick_drift(s->st, s->g4, s->pos, s->pos, s->mom, s->bins.key, nullptr, nullptr,
+                          prev, b);
     // sweeps in the Strang order of the step (a sample that sits out is copied along)
     for (int k = 0; k < 3; ++k) {
       dh::launch_sweep(s->st, s->q, s->q2, b, sp.axes[k]);
@@ -412,7 +447,8 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp) {
     dh::launch_close_step(s->st, s->q, s->q, s->g4, s->star, nullptr, s->cfg.gamma, s->cfl_red, b,
                           closure);
   }
-  dh::launch_kick(s->st, s->g4, s->pos, s->mom, b);
+  // closing dark-matter half kick with g_{n+1} (deferred: the factor the table holds)
+  if (tp || !defer) dh::launch_kick(s->st, s->g4, s->pos, s->mom, b);
   DH_LAUNCH_CHECK();
   bool all = true;
   for (int i = 0; i < s->S; ++i) {
@@ -420,6 +456,10 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp) {
     if (!p.active) {
       all = false;
       continue;
+    }
+    if (!tp && defer) {
+      s->kick_due[i] = static_cast<float>(0.5 * p.dt);
+      s->kick_pending = true;
     }
     s->t[i] = p.t0 + p.dt;
     s->a[i] = p.a1;
@@ -462,6 +502,7 @@ void initial_conditions(dh_sim* s, const float* d_white) {
     dh::fft_inverse_yx(s->st, s->spec, s->psi + j * s->nc, s->tw, 1.0f, all, 3 * s->nc);
   }
   const double vfac = ai * ai * s->cosmo.E(ai) * s->cosmo.growth_rate(ai);
+  drop_kick(s);
   dh::launch_ic_particles(s->st, s->psi, s->pos, s->mom, static_cast<float>(vfac), all);
   sort_particles(s, s->pos, all);
   dh::launch_deposit(s->st, s->bins, nullptr, 0, 1.0f, 0.0f, s->cic, all);
@@ -523,7 +564,8 @@ void commit_plan(dh_sim* s, const StepPlan& sp) {
 }
 
 // Plans and takes one step of all samples; *moved = false when no sample had a step left.
-int step_once(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan* out, bool* moved) {
+int step_once(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan* out, bool* moved,
+              bool defer) {
   if (!s->initialised) return fail(s, DH_E_STATE, "no initial state");
   if (s->cfg.closure == DH_CLOSURE_MLP && !s->mlp_ready)
     return fail(s, DH_E_STATE, "closure network weights not set (dh_set_closure)");
@@ -536,7 +578,7 @@ int step_once(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan* out, b
   if (!any) return DH_OK;
   sp.slot = s->nslots++;
   upload_plan(s, sp);
-  do_step(s, sp, nullptr);
+  do_step(s, sp, nullptr, defer);
   commit_plan(s, sp);
   if (out) *out = sp;
   return DH_OK;
@@ -555,6 +597,7 @@ void alloc_tape_entry(dh_sim* s, TapeStep& t) {
 
 void save_ckpt(dh_sim* s, Ckpt& c) {
   const long long S = s->S;
+  flush_kick(s);
   if (!c.q) {
     c.q = s->alloc<float>(5 * s->nc * S);
     c.pos = s->alloc<float>(3 * s->np * S);
@@ -574,6 +617,7 @@ void save_ckpt(dh_sim* s, Ckpt& c) {
 
 void load_ckpt(dh_sim* s, const Ckpt& c) {
   const long long S = s->S;
+  drop_kick(s);
   copy_d2d(s, s->q, c.q, 5 * s->nc * S);
   copy_d2d(s, s->pos, c.pos, 3 * s->np * S);
   copy_d2d(s, s->mom, c.mom, 3 * s->np * S);
@@ -791,6 +835,7 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
     s->recorded.assign(S, {});
     s->replay.assign(S, {});
     s->replay_pos.assign(S, 0);
+    s->kick_due.assign(S, 0.0f);
     const long long nc = s->nc * S, np = s->np * S;
     s->q = s->alloc<float>(5 * nc);
     s->q2 = s->alloc<float>(5 * nc);
@@ -920,7 +965,7 @@ int dh_step(dh_sim* s, double* dt_out, double* a_out) {
   return guarded(s, [&]() -> int {
     StepPlan sp;
     bool moved = false;
-    int rc = step_once(s, -1.0, false, &sp, &moved);
+    int rc = step_once(s, -1.0, false, &sp, &moved, false);
     if (rc) return rc;
     s->have_forward = false;
     if (!all_finite(current_speed(s)))   // also validates the new state
@@ -936,15 +981,37 @@ int dh_run_to(dh_sim* s, double a_final, int32_t* nsteps_out) {
   return guarded(s, [&]() -> int {
     const double t_end = s->cosmo.t_of_a(a_final);
     int count = 0;
+    int rc = DH_OK;
     for (;;) {
       bool moved = false;
-      int rc = step_once(s, t_end, false, nullptr, &moved);
-      if (rc) return rc;
-      if (!moved) break;
+      rc = step_once(s, t_end, false, nullptr, &moved, true);
+      if (rc || !moved) break;
       ++count;
     }
+    flush_kick(s);
     s->have_forward = false;
     if (nsteps_out) *nsteps_out = count;
+    return rc;
+  });
+}
+
+int dh_run_steps(dh_sim* s, int32_t nsteps, int32_t* nsteps_out) {
+  if (!s || nsteps < 0) return DH_E_INVAL;
+  return guarded(s, [&]() -> int {
+    int count = 0;
+    int rc = DH_OK;
+    while (count < nsteps) {
+      bool moved = false;
+      rc = step_once(s, -1.0, false, nullptr, &moved, true);
+      if (rc || !moved) break;
+      ++count;
+    }
+    flush_kick(s);
+    s->have_forward = false;
+    if (nsteps_out) *nsteps_out = count;
+    if (rc) return rc;
+    if (!all_finite(current_speed(s)))   // also validates the new state
+      return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
     return DH_OK;
   });
 }
@@ -1090,12 +1157,16 @@ int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_
       }
       StepPlan sp;
       bool moved = false;
-      int rc = step_once(s, t_end, true, &sp, &moved);
-      if (rc) return rc;
+      int rc = step_once(s, t_end, true, &sp, &moved, true);
+      if (rc) {
+        flush_kick(s);
+        return rc;
+      }
       if (!moved) break;
       s->fwd_plans.push_back(sp);
       ++count;
     }
+    flush_kick(s);
     if (!all_finite(current_speed(s)))
       return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
     s->fwd_steps = count;
@@ -1204,7 +1275,7 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     for (int g = nseg - 1; g >= 0; --g) {
       load_ckpt(s, s->ckpts[g]);
       const int s0 = g * K, s1 = std::min(nsteps, s0 + K);
-      for (int k = s0; k < s1; ++k) do_step(s, s->fwd_plans[k], &s->tape[k - s0]);
+      for (int k = s0; k < s1; ++k) do_step(s, s->fwd_plans[k], &s->tape[k - s0], false);
       for (int k = s1 - 1; k >= s0; --k) step_vjp(s, s->tape[k - s0]);
     }
     if (nsteps > 0) finish_first_kick(s, s->tape[0]);

@@ -28,6 +28,7 @@ struct StepScal {
   float drift;        // dt / a(t+dt/2)^2
   float green;        // Poisson: -(3 Om / 2 a(t+dt)) / N^3
   float h_dm;         // reverse pass: dark-matter kick factor of this step and the next
+  float h_prev;       // closing dark-matter kick of the sample's previous step, when deferred
   int active;
 };
 struct Batch {
@@ -82,9 +83,10 @@ void launch_grad(hipStream_t st, const float* phi, float4* g4, const Batch& b);
 void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float* out,
                       const Batch& b);
 // opening kick (h) + drift (drift) + keys: positions read from pos_in and written to pos
-// (the same array for an update in place); optional copies of the new momenta and positions
+// (the same array for an update in place); optional copies of the new momenta and positions.
+// prev: first the previous step's closing kick (h_prev of the table), as launch_kick would
 void launch_kick_drift(hipStream_t st, const float4* g4, const float* pos_in, float* pos,
-                       float* mom, uint32_t* key, float* mom_copy, float* pos_copy,
+                       float* mom, uint32_t* key, float* mom_copy, float* pos_copy, bool prev,
                        const Batch& b);
 // closing kick p += h g(x)
 void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom, const Batch& b);

@@ -485,9 +485,9 @@ __device__ __forceinline__ void readout_g(const float4* __restrict__ g4, const C
       for (int ox = 0; ox < 2; ++ox) {
         const float4 g = g4[corner(w, ox, oy, oz, n)];
         const float ww = wsel(w.w1[0], ox) * wsel(w.w1[1], oy) * wsel(w.w1[2], oz);
-        out[0] += ww * g.x;
-        out[1] += ww * g.y;
-        out[2] += ww * g.z;
+        out[0] = fmaf(ww, g.x, out[0]);
+        out[1] = fmaf(ww, g.y, out[1]);
+        out[2] = fmaf(ww, g.z, out[2]);
       }
 }
 
@@ -514,6 +514,10 @@ __device__ __forceinline__ float wrap_pos(float x, float fn) {
   return x;
 }
 
+// Opening half kick and drift of the dark matter, with the keys of the new positions.  With
+// `prev`, the closing half kick of the sample's previous step (factor h_prev, same field and
+// positions) is applied first: the two kicks are the separate roundings of kick_kernel
+// followed by this kernel, fused into one pass over the particles.
 // pos_in and pos may be the same array (in place): no __restrict__ on them
 __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restrict__ g4,
                                                          const float* pos_in, float* pos,
@@ -521,7 +525,7 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
                                                          uint32_t* __restrict__ key,
                                                          float* __restrict__ mom_copy,
                                                          float* __restrict__ pos_copy, int n,
-                                                         long long np,
+                                                         long long np, int prev,
                                                          const StepScal* __restrict__ tab) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const StepScal& sc = tab[blockIdx.y];
@@ -546,7 +550,7 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
     }
     return;
   }
-  const float h = sc.h, drift_fac = sc.drift;
+  const float h = sc.h, drift_fac = sc.drift, hp = prev ? sc.h_prev : 0.0f;
   float x[3] = {pos_in[i], pos_in[np + i], pos_in[2 * np + i]};
   const Cic w = cic_of(x[0], x[1], x[2], n);
   float g[3];
@@ -554,7 +558,9 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
   const float fn = static_cast<float>(n);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const float p = mom[d * np + i] + h * g[d];
+    float p = mom[d * np + i];
+    if (prev) p = fmaf(hp, g[d], p);
+    p = fmaf(h, g[d], p);
     mom[d * np + i] = p;
     x[d] = wrap_pos(x[d] + p * drift_fac, fn);
     pos[d * np + i] = x[d];
@@ -580,7 +586,7 @@ __global__ void __launch_bounds__(256) kick_kernel(const float4* __restrict__ g4
   float g[3];
   readout_g(g4, w, n, g);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) mom[d * np + i] += h * g[d];
+  for (int d = 0; d < 3; ++d) mom[d * np + i] = fmaf(h, g[d], mom[d * np + i]);
 }
 
 // lam_x += h * sum_corners (dw/dx) (g_corner . lam_p)
@@ -788,11 +794,11 @@ void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float*
 }
 
 void launch_kick_drift(hipStream_t st, const float4* g4, const float* pos_in, float* pos,
-                       float* mom, uint32_t* key, float* mom_copy, float* pos_copy,
+                       float* mom, uint32_t* key, float* mom_copy, float* pos_copy, bool prev,
                        const Batch& b) {
   if (!b.tab) throw ArgError("kick_drift: step table required");
   hipLaunchKernelGGL(kick_drift_kernel, per_sample(b.nc(), b), dim3(256), 0, st, g4, pos_in, pos,
-                     mom, key, mom_copy, pos_copy, b.n, b.nc(), b.tab);
+                     mom, key, mom_copy, pos_copy, b.n, b.nc(), prev ? 1 : 0, b.tab);
   DH_LAUNCH_CHECK();
 }
 

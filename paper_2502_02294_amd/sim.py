@@ -163,6 +163,13 @@ class Sim:
         self._check(lib().dh_run_to(self._h, a_final, ctypes.byref(k)))
         return k.value
 
+    def run_steps(self, nsteps):
+        """nsteps steps in one call (the same results as that many step() calls)."""
+        self._stream()
+        k = ctypes.c_int32()
+        self._check(lib().dh_run_steps(self._h, int(nsteps), ctypes.byref(k)))
+        return k.value
+
     def set_schedule(self, dts):
         self._stream()
         arr = (ctypes.c_double * len(dts))(*[float(x) for x in dts])

@@ -71,6 +71,46 @@ def test_batch_samples_equal_single_runs(dhp):
             assert torch.equal(b.get(f)[i], s.get(f)), (i, f)
 
 
+def test_run_loops_equal_single_steps(dhp):
+    """run_to and run_steps leave each closing dark-matter kick to the next step's kick-drift
+    pass (a sample that has finished keeps its last one pending until the loop ends); the
+    states are those of separate steps, bit for bit."""
+    n, box, S = 32, 10.0, 3
+    white = np.stack([si.white_noise(n, seed=80 + i) for i in range(S)])
+    print("run_to of a batch with uneven step counts against single steps", flush=True)
+    b = _batch(dhp, n, box, S)
+    for i, dts in FIRST_STEPS.items():
+        b.set_sample_schedule(i, dts)
+    b.init_from_noise(to_gpu(white))
+    b.run_to(0.03)
+    counts = [len(b.get_sample_schedule(i)) for i in range(S)]
+    assert len(set(counts)) > 1, counts
+    for i in range(S):
+        s = _single(dhp, n, box, i)
+        s.set_schedule(b.get_sample_schedule(i))
+        s.init_from_noise(to_gpu(white[i]))
+        for _ in range(counts[i]):
+            s.step()
+        for f in ("q", "pos", "mom", "star", "phi"):
+            assert torch.equal(b.get(f)[i], s.get(f)), (i, f)
+    print("run_steps against step", flush=True)
+    runs = []
+    for fused in (True, False):
+        r = _batch(dhp, n, box, S)
+        for i, dts in FIRST_STEPS.items():
+            r.set_sample_schedule(i, dts)
+        r.init_from_noise(to_gpu(white))
+        if fused:
+            assert r.run_steps(5) == 5
+        else:
+            for _ in range(5):
+                r.step()
+        runs.append({f: r.get(f) for f in ("q", "pos", "mom", "star", "phi")})
+        assert r.get_sample_schedule(1)[:3] == FIRST_STEPS[1]
+    for f in runs[0]:
+        assert torch.equal(runs[0][f], runs[1][f]), f
+
+
 # samples 1 and 2 replay schedules that stop before a = 0.08 (a forward run ends a sample at
 # the end of its schedule); sample 0 steps by the CFL
 REPLAY = {1: [7e-4] * 4, 2: [6e-4] * 6}
