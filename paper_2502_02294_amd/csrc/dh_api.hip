@@ -91,8 +91,9 @@ struct dh_sim {
   int g4b_phi0_of = -1;         // g4b holds -grad of this step's phi0 (every sample moved), or -1
   // Closing dark-matter half kicks left to the next step's kick-drift pass (one pass over the
   // particles instead of two): factor per sample, 0 when none.  Only the step loops of
-  // run_to / forward / run_steps defer, and they apply what is left before returning, so
-  // outside them the state is always complete.
+  // run_to / forward / run_steps and the recomputation of the reverse pass defer, and they
+  // apply (or, for a discarded state, drop) what is left before returning, so outside them
+  // the state is always complete.
   std::vector<float> kick_due;
   bool kick_pending = false;
   dh::Bins bins{};
@@ -389,10 +390,10 @@ bool all_finite(const std::vector<double>& v) {
 }
 
 // One step of the method on the handle state.  With a tape entry, keeps its intermediates.
-// defer (no tape only): leave the closing dark-matter kick to the next step's kick-drift pass.
+// defer: leave the closing dark-matter kick to the next step's kick-drift pass.
 void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
   const long long nc = s->nc, np = s->np;
-  if (tp || !defer) flush_kick(s);
+  if (!defer) flush_kick(s);
   const bool prev = s->kick_pending;
   const Batch b = batch(s, tab_of(s, sp));
   const float* pos_in = s->pos;
@@ -419,7 +420,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
     // the kick, the sweeps and the closing pass write their results straight into the tape
     dh::launch_gas_kick(s->st, tp->q[0], tp->q[1], s->g4, b);
     dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, tp->x1,
-                          false, b);
+                          prev, b);
     for (int k = 0; k < 3; ++k) dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
     dh::launch_sort(s->st, s->bins, s->pos, b);
     potential_from_bins(s, tp->q[4], s->phi, s->g4, b);
@@ -448,7 +449,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
                           closure);
   }
   // closing dark-matter half kick with g_{n+1} (deferred: the factor the table holds)
-  if (tp || !defer) dh::launch_kick(s->st, s->g4, s->pos, s->mom, b);
+  if (!defer) dh::launch_kick(s->st, s->g4, s->pos, s->mom, b);
   DH_LAUNCH_CHECK();
   bool all = true;
   for (int i = 0; i < s->S; ++i) {
@@ -457,7 +458,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
       all = false;
       continue;
     }
-    if (!tp && defer) {
+    if (defer) {
       s->kick_due[i] = static_cast<float>(0.5 * p.dt);
       s->kick_pending = true;
     }
@@ -649,24 +650,27 @@ void release_ckpt(dh_sim* s, Ckpt& c) {
 // step); this step's own opening kick is left to the previous step, or to
 // finish_first_kick after the first step.  A sample that sat the step out keeps its adjoints.
 void step_vjp(dh_sim* s, const TapeStep& T) {
-  const long long nc = s->nc, np = s->np;
+  const long long nc = s->nc;
   const StepPlan& sp = T.plan;
   const Batch b = batch(s, tab_of(s, sp));
   hipStream_t st = s->st;
-  const bool closure = s->cfg.closure == DH_CLOSURE_MLP;
-  // source term
-  if (s->cfg.subgrid != DH_SUBGRID_OFF) {
-    const int nb = dh::source_vjp_blocks(s->n);
-    dh::launch_source_vjp(st, T.q[5], s->lq, s->red, b, closure);
-    dh::launch_reduce_sum(st, s->red, nb, nb, 2 * s->S, s->param_steps + 2LL * s->S * sp.slot);
-  }
-  // closing kicks (gas from Q4, DM at x1) -> lambda_g -> lambda_phi_{n+1}
+  const bool source = s->cfg.subgrid != DH_SUBGRID_OFF;
+  const bool closure = source && s->cfg.closure == DH_CLOSURE_MLP;
+  // source term and closing kicks (gas from Q4, DM at x1) -> lambda_g -> lambda_phi_{n+1}.
   // phi1 of this step is phi0 of the next one (bit for bit, also across a checkpoint), whose
   // gradient the previous call left in g4b when every sample moved in both steps
   bool all = true;
   for (int i = 0; i < s->S; ++i) all = all && sp.smp[i].active;
   if (!(all && s->g4b_phi0_of == sp.step + 1)) dh::launch_grad(st, T.phi1, s->g4b, b);
-  dh::launch_gas_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, b);
+  const int nb = dh::source_vjp_blocks(s->n);
+  if (closure) {
+    dh::launch_source_vjp(st, T.q[5], s->lq, s->red, b);
+    dh::launch_gas_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, b);
+  } else {
+    dh::launch_source_kick_vjp(st, T.q[5], T.q[4], s->g4b, s->lq, s->lg, s->red, b);
+  }
+  if (source)
+    dh::launch_reduce_sum(st, s->red, nb, nb, 2 * s->S, s->param_steps + 2LL * s->S * sp.slot);
   // x1 in bin order from the sort the recomputed step kept, then lambda_p in the same order
   dh::Bins tb = s->bins;
   tb.start = T.start;
@@ -681,14 +685,13 @@ void step_vjp(dh_sim* s, const TapeStep& T) {
   // Poisson (symmetric operator) and deposit at x1
   poisson(s, s->lphi2, s->ldelta, b);
   dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc, 5 * nc, nc, false, b);
-  dh::launch_deposit_vjp_pos(st, s->ldelta, T.x1, static_cast<float>(s->m_dm), s->lx, b);
+  // with the drift x1 = x0 + p_half dt / a_h^2: lambda_p += (dt / a_h^2) lambda_x
+  dh::launch_deposit_vjp_pos(st, s->ldelta, T.x1, static_cast<float>(s->m_dm), s->lx, s->lp, b);
   // sweeps in reverse
   for (int k = 2; k >= 0; --k) {
     dh::launch_sweep_vjp(st, T.q[1 + k], s->lq, s->lq2, b, sp.axes[k]);
     std::swap(s->lq, s->lq2);
   }
-  // drift: x1 = x0 + p_half dt / a_h^2
-  dh::launch_axpy(st, s->lp, s->lx, 1.0f, 3 * np, 3 * np, 3 * np, true, b);
   // opening gas kick with phi_n
   dh::launch_grad(st, T.phi0, s->g4b, b);
   s->g4b_phi0_of = all ? sp.step : -1;
@@ -725,13 +728,14 @@ void ic_vjp(dh_sim* s, float* d_grad_white) {
   // positions of the initial particles are recomputed from psi
   const double vfac = ai * ai * s->cosmo.E(ai) * s->cosmo.growth_rate(ai);
   dh::launch_ic_particles(st, s->psi, s->pos, s->fscratch, static_cast<float>(vfac), all);
-  dh::launch_deposit_vjp_pos(st, s->ldelta, s->pos, static_cast<float>(s->m_dm), s->lx, all);
+  dh::launch_deposit_vjp_pos(st, s->ldelta, s->pos, static_cast<float>(s->m_dm), s->lx, nullptr,
+                             all);
   // gas: rho = f_b CIC(x), m = rho p(q), Et = a^2 rho (e_init + |p/a|^2/2)
   dh::launch_fill(st, s->lpsi, 0.0f, 3 * nc * s->S);
   dh::launch_ic_gas_vjp(st, s->cic, s->psi, s->lq, static_cast<float>(s->f_b),
                         static_cast<float>(vfac), static_cast<float>(ai),
                         static_cast<float>(s->e_init), s->lcic, s->lpsi, all);
-  dh::launch_deposit_vjp_pos(st, s->lcic, s->pos, 1.0f, s->lx, all);
+  dh::launch_deposit_vjp_pos(st, s->lcic, s->pos, 1.0f, s->lx, nullptr, all);
   // x = q + psi, p = vfac psi
   dh::launch_axpy(st, s->lpsi, s->lx, 1.0f, 3 * nc, 3 * nc, 3 * nc, false, all);
   dh::launch_axpy(st, s->lpsi, s->lp, static_cast<float>(vfac), 3 * nc, 3 * nc, 3 * nc, false,
@@ -1275,7 +1279,11 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     for (int g = nseg - 1; g >= 0; --g) {
       load_ckpt(s, s->ckpts[g]);
       const int s0 = g * K, s1 = std::min(nsteps, s0 + K);
-      for (int k = s0; k < s1; ++k) do_step(s, s->fwd_plans[k], &s->tape[k - s0], false);
+      // the recomputed trajectory is the forward's bit for bit (the forward also deferred
+      // its kicks and applied them before each checkpoint); the momenta after the last
+      // step of the segment are not needed, so its pending kick is dropped
+      for (int k = s0; k < s1; ++k) do_step(s, s->fwd_plans[k], &s->tape[k - s0], true);
+      drop_kick(s);
       for (int k = s1 - 1; k >= s0; --k) step_vjp(s, s->tape[k - s0]);
     }
     if (nsteps > 0) finish_first_kick(s, s->tape[0]);

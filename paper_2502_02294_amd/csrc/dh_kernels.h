@@ -94,9 +94,10 @@ void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom,
 // k = h (merged: h_dm) of the table
 void launch_kick_vjp_pos(hipStream_t st, const float4* g4, const float* pos,
                          const float* lam_p, bool merged, float* lam_x, const Batch& b);
-// adjoint of the deposit wrt positions: lam_x += mass sum_c lam_delta_c dw_c/dx
+// adjoint of the deposit wrt positions: lam_x += mass sum_c lam_delta_c dw_c/dx; with lam_p
+// (table required), then the drift's adjoint lam_p += drift lam_x
 void launch_deposit_vjp_pos(hipStream_t st, const float* lam_delta, const float* pos,
-                            float mass, float* lam_x, const Batch& b);
+                            float mass, float* lam_x, float* lam_p, const Batch& b);
 // y[s] += a x[s] over `count` values per sample (strides ys, xs); a times the table's drift
 // factor if by_drift
 void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long count,
@@ -138,10 +139,16 @@ void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4
 void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4* g4,
                        float* star, float* q_kicked, double gamma, double* block_max,
                        const Batch& b, bool closure);
-// adjoint of the source term; dL/d(eps_sf, delta_c) partials per block:
-// partials[(v S + s) nb + block], nb = source_vjp_blocks(n)
+// adjoint of the source term with the learned closure; dL/d(eps_sf, delta_c) partials per
+// block: partials[(v S + s) nb + block], nb = source_vjp_blocks(n)
 void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, double* partials,
-                       const Batch& b, bool closure);
+                       const Batch& b);
+// adjoint of the closing pass with the plain source term (or none, src.mode 0): the source
+// at q_src, then the gas half kick at q_kick with g4 (lam_g = adjoint of g), in one pass;
+// partials as launch_source_vjp (zeros without source)
+void launch_source_kick_vjp(hipStream_t st, const float* q_src, const float* q_kick,
+                            const float4* g4, float* lam_q, float* lam_g, double* partials,
+                            const Batch& b);
 int source_vjp_blocks(int n);
 // FP64 block maxima of the CFL speed max_d (|U_d| + c_s)/a with a = a_cur[s]:
 // block_max[s][cfl_blocks(n)]

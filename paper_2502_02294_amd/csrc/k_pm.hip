@@ -625,9 +625,12 @@ __global__ void __launch_bounds__(256) kick_vjp_pos_kernel(const float4* __restr
 }
 
 // lam_x += mass * sum_corners lam_delta[corner] dw/dx
+// With lam_p: then lam_p += drift lam_x (the drift's adjoint, x1 = x0 + drift p), in the
+// same pass.
 __global__ void __launch_bounds__(256) deposit_vjp_pos_kernel(const float* __restrict__ lam_delta,
                                                               const float* __restrict__ pos,
                                                               float mass, float* __restrict__ lam_x,
+                                                              float* __restrict__ lam_p,
                                                               int n, long long np,
                                                               const StepScal* __restrict__ tab) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -635,6 +638,7 @@ __global__ void __launch_bounds__(256) deposit_vjp_pos_kernel(const float* __res
   lam_delta += blockIdx.y * np;
   pos += blockIdx.y * 3 * np;
   lam_x += blockIdx.y * 3 * np;
+  if (lam_p) lam_p += blockIdx.y * 3 * np;
   const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
   float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -650,7 +654,11 @@ __global__ void __launch_bounds__(256) deposit_vjp_pos_kernel(const float* __res
         acc[2] += wx * wy * (oz ? 1.0f : -1.0f) * l;
       }
 #pragma unroll
-  for (int d = 0; d < 3; ++d) lam_x[d * np + i] += mass * acc[d];
+  for (int d = 0; d < 3; ++d) {
+    const float lx = fmaf(mass, acc[d], lam_x[d * np + i]);
+    lam_x[d * np + i] = lx;
+    if (lam_p) lam_p[d * np + i] = fmaf(tab[blockIdx.y].drift, lx, lam_p[d * np + i]);
+  }
 }
 
 __global__ void axpy_kernel(float* __restrict__ y, const float* __restrict__ x, float a,
@@ -659,7 +667,7 @@ __global__ void axpy_kernel(float* __restrict__ y, const float* __restrict__ x, 
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= count || !sample_active(tab, blockIdx.y)) return;
   const float f = by_drift ? a * tab[blockIdx.y].drift : a;
-  y[blockIdx.y * ys + i] += f * x[blockIdx.y * xs + i];
+  y[blockIdx.y * ys + i] = fmaf(f, x[blockIdx.y * xs + i], y[blockIdx.y * ys + i]);
 }
 
 // lam_phi[c] = lam_phi_in[c] + sum_d (lam_g_d[c + e_d] - lam_g_d[c - e_d]) / 2
@@ -818,9 +826,10 @@ void launch_kick_vjp_pos(hipStream_t st, const float4* g4, const float* pos, con
 }
 
 void launch_deposit_vjp_pos(hipStream_t st, const float* lam_delta, const float* pos, float mass,
-                            float* lam_x, const Batch& b) {
+                            float* lam_x, float* lam_p, const Batch& b) {
+  if (lam_p && !b.tab) throw ArgError("deposit adjoint: step table required for the drift");
   hipLaunchKernelGGL(deposit_vjp_pos_kernel, per_sample(b.nc(), b), dim3(256), 0, st, lam_delta,
-                     pos, mass, lam_x, b.n, b.nc(), b.tab);
+                     pos, mass, lam_x, lam_p, b.n, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 

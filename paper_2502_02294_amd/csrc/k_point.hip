@@ -92,6 +92,25 @@ __global__ void __launch_bounds__(256) gas_kick_kernel(const float* q_in, float*
   q[4 * nc + c] = et;
 }
 
+// adjoint of kick_cell at one cell: l5 (adjoint after the kick) becomes the adjoint before
+// it (the energy component is unchanged); lg = adjoint of g
+__device__ __forceinline__ void kick_cell_vjp(float rho, const float m[3], const float4 gv,
+                                              float h, float l5[5], float lg[3]) {
+  const float g[3] = {gv.x, gv.y, gv.z};
+  const float le = l5[4];
+  float lr = l5[0];
+  float g2 = 0.0f;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float lm = l5[1 + d];
+    lr += h * lm * g[d];
+    g2 += g[d] * g[d];
+    l5[1 + d] = lm + le * h * g[d];
+    lg[d] = h * rho * lm + le * (h * m[d] + h * h * rho * g[d]);
+  }
+  l5[0] = lr + le * 0.5f * h * h * g2;
+}
+
 __global__ void __launch_bounds__(256) gas_kick_vjp_kernel(const float* __restrict__ q,
                                                            const float4* __restrict__ g4,
                                                            float* __restrict__ lam,
@@ -101,27 +120,20 @@ __global__ void __launch_bounds__(256) gas_kick_vjp_kernel(const float* __restri
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const StepScal& sc = tab[blockIdx.y];
   if (c >= nc || !sc.active) return;
-  const float h = sc.h;
   q += blockIdx.y * 5 * nc;
   lam += blockIdx.y * 5 * nc;
   lam_g += blockIdx.y * 3 * nc;
   g4 += blockIdx.y * nc;
-  const float4 gv = g4[c];
-  const float g[3] = {gv.x, gv.y, gv.z};
-  const float rho = q[c];
-  const float le = lam[4 * nc + c];
-  float lr = lam[c];
-  float g2 = 0.0f;
+  const float m[3] = {q[nc + c], q[2 * nc + c], q[3 * nc + c]};
+  float l5[5];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const float lm = lam[(1 + d) * nc + c];
-    const float m = q[(1 + d) * nc + c];
-    lr += h * lm * g[d];
-    g2 += g[d] * g[d];
-    lam[(1 + d) * nc + c] = lm + le * h * g[d];
-    lam_g[d * nc + c] = h * rho * lm + le * (h * m + h * h * rho * g[d]);
-  }
-  lam[c] = lr + le * 0.5f * h * h * g2;
+  for (int k = 0; k < 5; ++k) l5[k] = lam[k * nc + c];
+  float lg[3];
+  kick_cell_vjp(q[c], m, g4[c], sc.h, l5, lg);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) lam[k * nc + c] = l5[k];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) lam_g[d * nc + c] = lg[d];
 }
 
 // ------------------------------------------------------------------------- source term
@@ -313,62 +325,84 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
   block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
 }
 
-// lam (in: adjoint after the source, out: before); partials of dL/d(eps_sf|delta_c)
-__global__ void __launch_bounds__(kRedThreads) source_vjp_kernel(const float* __restrict__ q,
-                                                                 float* __restrict__ lam,
-                                                                 double* partial, long long nc,
-                                                                 const StepScal* __restrict__ tab) {
+// Adjoint of the source term at one cell (state q5 before it): l5 from the adjoint after the
+// source to the adjoint before; acc += dL/d(eps_sf, delta_c).  z and its derivatives are
+// below 1e-47 where the draw is screened out.
+__device__ __forceinline__ void source_cell_vjp(const float q5[5], long long c,
+                                                const SourceArgs& a, float l5[5],
+                                                double acc[2]) {
+  const float lg = draw_logit_estimate(q5, a);
+  if (screened_out(lg, kMaxLogitU, a)) return;
+  const double u = starform_uniform(c, a);
+  if (screened_out(lg, logit_u_of(u), a)) return;
+  const SrcCell s = source_eval(q5, u, a);
+  const double le = l5[4];
+  const double K = a.a * a.a * a.e0_code;
+  // Et' = Et + K rho z
+  double lr = l5[0] + le * K * s.z;
+  if (a.mode != 1 && le != 0.0) {
+    const double dz = s.z * (1.0 - s.z) / a.tau / (1.0 - s.pi0);   // dz / dln(pi0)
+    const double coef = le * K * s.rho * dz;
+    // dln p_sf / dx = 1 / expm1(x);  x ~ sqrt(rho)
+    const double dlp_dx = 1.0 / expm1(s.x);
+    const double dlnpi_drho_sf = dlp_dx * s.x * 0.5 / s.rho;
+    const double dlnpi_drho_s1 = (1.0 - s.s1) * a.inv_rho_mean / (a.w_rho * a.delta_c);
+    // s2 through T(e)
+    const double dlnpi_dT = -(1.0 - s.s2) / (a.w_t * a.t_c);
+    const double dT = s.floored ? 0.0 : a.t_per_e;
+    const double ir = 1.0 / s.rho, ia = 1.0 / a.a;
+    double u[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) u[d] = q5[1 + d] * ia * ir;
+    const double ke = 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const double de_drho = (ke - s.eraw) * ir;
+    lr += coef * (dlnpi_drho_sf + dlnpi_drho_s1 + dlnpi_dT * dT * de_drho);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      l5[1 + d] = static_cast<float>(l5[1 + d] + coef * dlnpi_dT * dT * (-u[d] * ia * ir));
+    l5[4] = static_cast<float>(le + coef * dlnpi_dT * dT * (ia * ia * ir));
+    acc[0] += coef * (dlp_dx * s.x / a.eps_sf);
+    acc[1] += coef * ((1.0 - s.s1) * (-s.delta / (a.w_rho * a.delta_c * a.delta_c)));
+  }
+  l5[0] = static_cast<float>(lr);
+}
+
+// Adjoint of the closing pass of a step (plain source term): lam (in: adjoint after the
+// source, out: before the closing gas kick), with the state q_src before the source and
+// q_kick before the kick; lam_g = adjoint of the kick's g; partials of dL/d(eps_sf|delta_c).
+// One pass over the cells for the two pointwise operators.
+__global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
+    const float* __restrict__ q_src, const float* __restrict__ q_kick,
+    const float4* __restrict__ g4, float* __restrict__ lam, float* __restrict__ lam_g,
+    double* partial, long long nc, const StepScal* __restrict__ tab) {
   const StepScal& sc = tab[blockIdx.y];
   if (!sc.active) {
     zero_partials<2>(partial);
     return;
   }
   const SourceArgs& a = sc.src;
-  q += blockIdx.y * 5 * nc;
+  const float h = sc.h;
+  q_src += blockIdx.y * 5 * nc;
+  q_kick += blockIdx.y * 5 * nc;
+  g4 += blockIdx.y * nc;
   lam += blockIdx.y * 5 * nc;
+  lam_g += blockIdx.y * 3 * nc;
   double acc[2] = {0.0, 0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   for (int r = 0; r < kRedPer; ++r) {
     const long long c = base + r * kRedThreads + threadIdx.x;
     if (c >= nc) break;
-    float q5[5];
-    load_q(q, c, nc, q5);
-    // z and its derivatives are below 1e-47 where the draw is screened out
-    const float lg = draw_logit_estimate(q5, a);
-    if (screened_out(lg, kMaxLogitU, a)) continue;
-    const double u = starform_uniform(c, a);
-    if (screened_out(lg, logit_u_of(u), a)) continue;
-    const SrcCell s = source_eval(q5, u, a);
-    const double le = lam[4 * nc + c];
-    const double K = a.a * a.a * a.e0_code;
-    // Et' = Et + K rho z
-    double lr = lam[c] + le * K * s.z;
-    if (a.mode != 1 && le != 0.0) {
-      const double dz = s.z * (1.0 - s.z) / a.tau / (1.0 - s.pi0);   // dz / dln(pi0)
-      const double coef = le * K * s.rho * dz;
-      // dln p_sf / dx = 1 / expm1(x);  x ~ sqrt(rho)
-      const double dlp_dx = 1.0 / expm1(s.x);
-      const double dlnpi_drho_sf = dlp_dx * s.x * 0.5 / s.rho;
-      const double dlnpi_drho_s1 = (1.0 - s.s1) * a.inv_rho_mean / (a.w_rho * a.delta_c);
-      // s2 through T(e)
-      const double dlnpi_dT = -(1.0 - s.s2) / (a.w_t * a.t_c);
-      const double dT = s.floored ? 0.0 : a.t_per_e;
-      const double ir = 1.0 / s.rho, ia = 1.0 / a.a;
-      double u[3];
+    float q5[5], l5[5];
+    load_q(q_src, c, nc, q5);
+    load_q(lam, c, nc, l5);
+    if (a.mode != 0) source_cell_vjp(q5, c, a, l5, acc);
+    const float m[3] = {q_kick[nc + c], q_kick[2 * nc + c], q_kick[3 * nc + c]};
+    float lg[3];
+    kick_cell_vjp(q_kick[c], m, g4[c], h, l5, lg);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) u[d] = q5[1 + d] * ia * ir;
-      const double ke = 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-      const double de_drho = (ke - s.eraw) * ir;
-      lr += coef * (dlnpi_drho_sf + dlnpi_drho_s1 + dlnpi_dT * dT * de_drho);
+    for (int k = 0; k < 5; ++k) lam[k * nc + c] = l5[k];
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        lam[(1 + d) * nc + c] =
-            static_cast<float>(lam[(1 + d) * nc + c] + coef * dlnpi_dT * dT * (-u[d] * ia * ir));
-      lam[4 * nc + c] = static_cast<float>(le + coef * dlnpi_dT * dT * (ia * ia * ir));
-      acc[0] += coef * (dlp_dx * s.x / a.eps_sf);
-      acc[1] += coef * ((1.0 - s.s1) * (-s.delta / (a.w_rho * a.delta_c * a.delta_c)));
-    }
-    lam[c] = static_cast<float>(lr);
+    for (int d = 0; d < 3; ++d) lam_g[d * nc + c] = lg[d];
   }
   block_reduce_store<2, false>(acc, sample_partials(partial), partial_stride());
 }
@@ -887,15 +921,21 @@ int source_vjp_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n *
 int cfl_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n * n); }
 
 void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, double* partials,
-                       const Batch& b, bool closure) {
+                       const Batch& b) {
   if (!b.tab) throw ArgError("source adjoint: step table required");
   const dim3 grid(source_vjp_blocks(b.n), b.S);
-  if (closure)
-    hipLaunchKernelGGL(source_vjp_mlp_kernel, grid, dim3(kRedThreads), 0, st, q_before, lam_q,
-                       partials, b.nc(), b.tab);
-  else
-    hipLaunchKernelGGL(source_vjp_kernel, grid, dim3(kRedThreads), 0, st, q_before, lam_q,
-                       partials, b.nc(), b.tab);
+  hipLaunchKernelGGL(source_vjp_mlp_kernel, grid, dim3(kRedThreads), 0, st, q_before, lam_q,
+                     partials, b.nc(), b.tab);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_source_kick_vjp(hipStream_t st, const float* q_src, const float* q_kick,
+                            const float4* g4, float* lam_q, float* lam_g, double* partials,
+                            const Batch& b) {
+  if (!b.tab) throw ArgError("closing pass adjoint: step table required");
+  const dim3 grid(source_vjp_blocks(b.n), b.S);
+  hipLaunchKernelGGL(source_kick_vjp_kernel, grid, dim3(kRedThreads), 0, st, q_src, q_kick, g4,
+                     lam_q, lam_g, partials, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
