@@ -52,7 +52,8 @@ const int kStrang[6][3] = {{0, 1, 2}, {2, 1, 0}, {2, 0, 1}, {1, 0, 2}, {1, 2, 0}
 
 struct TapeStep {
   float* q[6];      // Q0 start, Q1 after opening kick (sweep-1 input), Q2, Q3 sweep inputs,
-                    // Q4 after sweeps, Q5 after closing kick (source input)
+                    // Q4 after sweeps, Q5 after closing kick (source input; kept only for
+                    // the learned closure, the plain source's adjoint recomputes it)
   float *x0, *x1;             // particle positions at the start and after the drift
   float *phi0, *phi1;
   uint32_t *start, *sorted;   // the step's sort of x1 (bin starts, ids in bin order)
@@ -217,6 +218,10 @@ dh::SourceArgs source_args(const dh_sim* s, int smp, double a1, double dt, int s
   a.w_rho = p.w_rho;
   a.w_t = p.w_t;
   a.tau = s->cfg.tau;
+  a.c_x = p.eps_sf * dt * std::sqrt(a.omega_b / (a1 * a1 * a1)) / 1.5707963267948966;
+  a.k_rho = 1.0 / (p.w_rho * p.delta_c);
+  a.k_t = 1.0 / (p.w_t * p.t_c);
+  a.inv_tau = 1.0 / a.tau;
   a.mode = s->cfg.subgrid;
   const uint64_t seed = s->cfg.sf_seed + static_cast<uint64_t>(smp);   // sample s: key + s
   a.seed_lo = static_cast<uint32_t>(seed & 0xFFFFFFFFull);
@@ -429,8 +434,8 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
     // former buffers
     std::swap(s->bins.start, tp->start);
     std::swap(s->bins.sorted, tp->sorted);
-    dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, s->star, tp->q[5], s->cfg.gamma,
-                          s->cfl_red, b, closure);
+    dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, s->star, closure ? tp->q[5] : nullptr,
+                          s->cfg.gamma, s->cfl_red, b, closure);
   } else {
     // opening half kicks with g_n, drift with a(t + dt/2)
     dh::launch_gas_kick(s->st, s->q, s->q, s->g4, b);
@@ -587,7 +592,9 @@ int step_once(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan* out, b
 
 void alloc_tape_entry(dh_sim* s, TapeStep& t) {
   const long long S = s->S;
-  for (int k = 0; k < 6; ++k) t.q[k] = s->alloc<float>(5 * s->nc * S);
+  const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
+  for (int k = 0; k < 6; ++k)
+    t.q[k] = k < 5 || closure ? s->alloc<float>(5 * s->nc * S) : nullptr;
   t.x0 = s->alloc<float>(3 * s->np * S);
   t.x1 = s->alloc<float>(3 * s->np * S);
   t.phi0 = s->alloc<float>(s->nc * S);
@@ -667,7 +674,7 @@ void step_vjp(dh_sim* s, const TapeStep& T) {
     dh::launch_source_vjp(st, T.q[5], s->lq, s->red, b);
     dh::launch_gas_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, b);
   } else {
-    dh::launch_source_kick_vjp(st, T.q[5], T.q[4], s->g4b, s->lq, s->lg, s->red, b);
+    dh::launch_source_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, s->red, b);
   }
   if (source)
     dh::launch_reduce_sum(st, s->red, nb, nb, 2 * s->S, s->param_steps + 2LL * s->S * sp.slot);

@@ -17,6 +17,10 @@ namespace dh {
 struct SourceArgs {   // FP64: the source term is evaluated in double precision
   double a, dt, inv_rho_mean, omega_b, efloor, t_per_e, e0_code;
   double eps_sf, delta_c, t_c, w_rho, w_t, tau;
+  // per-step constants: x = eps_sf dt / t_ff = c_x sqrt(delta) with
+  // t_ff = (pi/2) sqrt(a^3 / (omega_b delta)); gate arguments (delta - delta_c) k_rho and
+  // (t_c - T) k_t, k_rho = 1 / (w_rho delta_c), k_t = 1 / (w_t t_c); inv_tau = 1 / tau
+  double c_x, k_rho, k_t, inv_tau;
   int mode;
   uint32_t seed_lo, seed_hi, step;
   const uint4* mlp;   // packed closure network (dh_mlp.h): pi0 from the network; null: plain
@@ -143,12 +147,12 @@ void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4
 // block: partials[(v S + s) nb + block], nb = source_vjp_blocks(n)
 void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, double* partials,
                        const Batch& b);
-// adjoint of the closing pass with the plain source term (or none, src.mode 0): the source
-// at q_src, then the gas half kick at q_kick with g4 (lam_g = adjoint of g), in one pass;
-// partials as launch_source_vjp (zeros without source)
-void launch_source_kick_vjp(hipStream_t st, const float* q_src, const float* q_kick,
-                            const float4* g4, float* lam_q, float* lam_g, double* partials,
-                            const Batch& b);
+// adjoint of the closing pass with the plain source term (or none, src.mode 0) from the
+// state q_kick before the closing gas half kick with g4 (the kicked state is recomputed):
+// the source, then the kick (lam_g = adjoint of g), in one pass; partials as
+// launch_source_vjp (zeros without source)
+void launch_source_kick_vjp(hipStream_t st, const float* q_kick, const float4* g4,
+                            float* lam_q, float* lam_g, double* partials, const Batch& b);
 int source_vjp_blocks(int n);
 // FP64 block maxima of the CFL speed max_d (|U_d| + c_s)/a with a = a_cur[s]:
 // block_max[s][cfl_blocks(n)]

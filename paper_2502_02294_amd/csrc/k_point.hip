@@ -145,9 +145,6 @@ struct SrcCell {
 };
 
 __device__ __forceinline__ double sigmoid_(double y) { return 1.0 / (1.0 + exp(-y)); }
-__device__ __forceinline__ double log_sigmoid_(double y) {
-  return fmin(y, 0.0) - log1p(exp(-fabs(y)));
-}
 
 // The uniform of cell c for the draw of the given step.
 __device__ __forceinline__ double starform_uniform(long long c, const SourceArgs& a) {
@@ -198,15 +195,20 @@ __device__ __forceinline__ float draw_logit_estimate(const float q5[5], const So
                         static_cast<float>(a.efloor));
   const float temp = e * static_cast<float>(a.t_per_e);
   const float delta = rho * static_cast<float>(a.inv_rho_mean);
-  // t_ff = pi/2 sqrt(a^3 / (Omega_b delta)); x = eps dt / t_ff
-  const float c_ff = static_cast<float>(a.eps_sf * a.dt / 1.5707963267948966 *
-                                        sqrt(a.omega_b / (a.a * a.a * a.a)));
-  const float psf = one_minus_exp_neg(c_ff * sqrt_approx(delta));
+  // x = eps dt / t_ff = c_x sqrt(delta)
+  const float psf = one_minus_exp_neg(static_cast<float>(a.c_x) * sqrt_approx(delta));
   if (!(psf > 1e-30f)) return INFINITY;
-  const float y1 = (delta - static_cast<float>(a.delta_c)) *
-                   static_cast<float>(1.0 / (a.w_rho * a.delta_c));
-  const float y2 = (static_cast<float>(a.t_c) - temp) * static_cast<float>(1.0 / (a.w_t * a.t_c));
+  const float y1 = (delta - static_cast<float>(a.delta_c)) * static_cast<float>(a.k_rho);
+  const float y2 = (static_cast<float>(a.t_c) - temp) * static_cast<float>(a.k_t);
   return fast_logit_of_log(fast_log(psf) + fast_log_sigmoid(y1) + fast_log_sigmoid(y2));
+}
+
+// sigmoid(y) and log sigmoid(y) from one exponential: t = exp(-|y|),
+// sigmoid = 1 / (1 + t) (y >= 0) or t / (1 + t), log sigmoid = min(y, 0) - log1p(t)
+__device__ __forceinline__ void sigmoid_pair(double y, double& sig, double& log_sig) {
+  const double t = exp(-fabs(y));
+  sig = (y >= 0.0 ? 1.0 : t) / (1.0 + t);
+  log_sig = fmin(y, 0.0) - log1p(t);
 }
 
 __device__ SrcCell source_eval(const float q5[5], double u, const SourceArgs& a) {
@@ -229,26 +231,25 @@ __device__ SrcCell source_eval(const float q5[5], double u, const SourceArgs& a)
     s.pi0 = 0.0;
     s.z = 0.0;
     if (gate > 0.0) {   // the draw matters only where the thresholds are passed
-      const double tff = 1.5707963267948966 * sqrt(a.a * a.a * a.a / (a.omega_b * s.delta));
-      s.x = a.eps_sf * a.dt / tff;
+      s.x = a.c_x * sqrt(s.delta);
       s.psf = -expm1(-s.x);
       s.pi0 = s.psf;
       s.z = s.u > 1.0 - s.pi0 ? 1.0 : 0.0;
     }
     return s;
   }
-  const double tff = 1.5707963267948966 * sqrt(a.a * a.a * a.a / (a.omega_b * s.delta));
-  s.x = a.eps_sf * a.dt / tff;
+  // x = eps dt / t_ff, t_ff = (pi/2) sqrt(a^3 / (Omega_b delta))
+  s.x = a.c_x * sqrt(s.delta);
   s.psf = -expm1(-s.x);
-  const double y1 = (s.delta - a.delta_c) / (a.w_rho * a.delta_c);
-  const double y2 = (a.t_c - s.temp) / (a.w_t * a.t_c);
-  s.s1 = sigmoid_(y1);
-  s.s2 = sigmoid_(y2);
+  double ls1, ls2;
+  sigmoid_pair((s.delta - a.delta_c) * a.k_rho, s.s1, ls1);
+  sigmoid_pair((a.t_c - s.temp) * a.k_t, s.s2, ls2);
   s.pi0 = s.psf * s.s1 * s.s2;
-  const double logpi = log(s.psf) + log_sigmoid_(y1) + log_sigmoid_(y2);
+  const double logpi = log(s.psf) + ls1 + ls2;
   const double logit = logpi - log1p(-s.pi0);
-  const double noise = log(s.u) - log1p(-s.u);
-  s.z = sigmoid_((logit + noise) / a.tau);
+  // logit of u: 1 - u is exact for the 24-bit uniforms
+  const double noise = log(s.u / (1.0 - s.u));
+  s.z = sigmoid_((logit + noise) * a.inv_tau);
   return s;
 }
 
@@ -368,13 +369,14 @@ __device__ __forceinline__ void source_cell_vjp(const float q5[5], long long c,
 }
 
 // Adjoint of the closing pass of a step (plain source term): lam (in: adjoint after the
-// source, out: before the closing gas kick), with the state q_src before the source and
-// q_kick before the kick; lam_g = adjoint of the kick's g; partials of dL/d(eps_sf|delta_c).
-// One pass over the cells for the two pointwise operators.
+// source, out: before the closing gas kick), with the state q_kick before the kick;
+// lam_g = adjoint of the kick's g; partials of dL/d(eps_sf|delta_c).  The kicked state, the
+// source term's input, is recomputed in registers exactly as the closing pass made it (same
+// operands, same arithmetic), so one pass over the cells serves both operators.
 __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
-    const float* __restrict__ q_src, const float* __restrict__ q_kick,
-    const float4* __restrict__ g4, float* __restrict__ lam, float* __restrict__ lam_g,
-    double* partial, long long nc, const StepScal* __restrict__ tab) {
+    const float* __restrict__ q_kick, const float4* __restrict__ g4, float* __restrict__ lam,
+    float* __restrict__ lam_g, double* partial, long long nc,
+    const StepScal* __restrict__ tab) {
   const StepScal& sc = tab[blockIdx.y];
   if (!sc.active) {
     zero_partials<2>(partial);
@@ -382,7 +384,6 @@ __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
   }
   const SourceArgs& a = sc.src;
   const float h = sc.h;
-  q_src += blockIdx.y * 5 * nc;
   q_kick += blockIdx.y * 5 * nc;
   g4 += blockIdx.y * nc;
   lam += blockIdx.y * 5 * nc;
@@ -393,12 +394,18 @@ __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
     const long long c = base + r * kRedThreads + threadIdx.x;
     if (c >= nc) break;
     float q5[5], l5[5];
-    load_q(q_src, c, nc, q5);
+    load_q(q_kick, c, nc, q5);
     load_q(lam, c, nc, l5);
+    const float4 gv = g4[c];
+    const float m0[3] = {q5[1], q5[2], q5[3]};
+    float m[3] = {q5[1], q5[2], q5[3]};
+    kick_cell(q5[0], gv, h, m, q5[4]);
+    q5[1] = m[0];
+    q5[2] = m[1];
+    q5[3] = m[2];
     if (a.mode != 0) source_cell_vjp(q5, c, a, l5, acc);
-    const float m[3] = {q_kick[nc + c], q_kick[2 * nc + c], q_kick[3 * nc + c]};
     float lg[3];
-    kick_cell_vjp(q_kick[c], m, g4[c], h, l5, lg);
+    kick_cell_vjp(q5[0], m0, gv, h, l5, lg);
 #pragma unroll
     for (int k = 0; k < 5; ++k) lam[k * nc + c] = l5[k];
 #pragma unroll
@@ -929,13 +936,12 @@ void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, doub
   DH_LAUNCH_CHECK();
 }
 
-void launch_source_kick_vjp(hipStream_t st, const float* q_src, const float* q_kick,
-                            const float4* g4, float* lam_q, float* lam_g, double* partials,
-                            const Batch& b) {
+void launch_source_kick_vjp(hipStream_t st, const float* q_kick, const float4* g4,
+                            float* lam_q, float* lam_g, double* partials, const Batch& b) {
   if (!b.tab) throw ArgError("closing pass adjoint: step table required");
   const dim3 grid(source_vjp_blocks(b.n), b.S);
-  hipLaunchKernelGGL(source_kick_vjp_kernel, grid, dim3(kRedThreads), 0, st, q_src, q_kick, g4,
-                     lam_q, lam_g, partials, b.nc(), b.tab);
+  hipLaunchKernelGGL(source_kick_vjp_kernel, grid, dim3(kRedThreads), 0, st, q_kick, g4, lam_q,
+                     lam_g, partials, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
