@@ -121,8 +121,13 @@ struct dh_sim {
 
   // adjoint buffers
   float *lq = nullptr, *lq2 = nullptr, *lx = nullptr, *lp = nullptr,
-        *lphi = nullptr, *lphi2 = nullptr, *lg = nullptr, *ldelta = nullptr, *lpsi = nullptr,
-        *lcic = nullptr;
+        *lphi = nullptr, *lphi2 = nullptr, *lg = nullptr, *lg2 = nullptr, *ldelta = nullptr,
+        *lpsi = nullptr, *lcic = nullptr;
+  // adjoint of a step's opening gas kick left to the closing-pass adjoint of the step before
+  // (same cells, same g): the step's start state and table
+  bool open_pending = false;
+  const float* open_q0 = nullptr;
+  const StepScal* open_tab = nullptr;
   double* param_steps = nullptr;   // [cap][2 S] per-step dL/d(eps_sf, delta_c)
   int param_cap = 0;
 
@@ -656,7 +661,20 @@ void release_ckpt(dh_sim* s, Ckpt& c) {
 // here (factor h_dm = h of this step + h of the next, the latter 0 after a sample's last
 // step); this step's own opening kick is left to the previous step, or to
 // finish_first_kick after the first step.  A sample that sat the step out keeps its adjoints.
-void step_vjp(dh_sim* s, const TapeStep& T) {
+// defer_open: the step before is the next one to be processed (same tape): the opening gas
+// kick's adjoint may be left to its closing-pass adjoint (one pass over the cells).
+void opening_kick_vjp(dh_sim* s, const float* q0, const Batch& b) {
+  dh::launch_gas_kick_vjp(s->st, q0, s->g4b, s->lq, s->lg, b);
+  dh::launch_grad_vjp(s->st, s->lg, nullptr, s->lphi, b);
+}
+
+void flush_open_vjp(dh_sim* s) {
+  if (!s->open_pending) return;
+  opening_kick_vjp(s, s->open_q0, Batch{s->n, s->S, s->open_tab});
+  s->open_pending = false;
+}
+
+void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
   const long long nc = s->nc;
   const StepPlan& sp = T.plan;
   const Batch b = batch(s, tab_of(s, sp));
@@ -668,11 +686,19 @@ void step_vjp(dh_sim* s, const TapeStep& T) {
   // gradient the previous call left in g4b when every sample moved in both steps
   bool all = true;
   for (int i = 0; i < s->S; ++i) all = all && sp.smp[i].active;
-  if (!(all && s->g4b_phi0_of == sp.step + 1)) dh::launch_grad(st, T.phi1, s->g4b, b);
+  const bool reuse = all && s->g4b_phi0_of == sp.step + 1;
+  const bool fuse_open = s->open_pending && reuse && !closure;
+  if (!fuse_open) flush_open_vjp(s);   // with the next step's g, still in g4b
+  if (!reuse) dh::launch_grad(st, T.phi1, s->g4b, b);
   const int nb = dh::source_vjp_blocks(s->n);
   if (closure) {
     dh::launch_source_vjp(st, T.q[5], s->lq, s->red, b);
     dh::launch_gas_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, b);
+  } else if (fuse_open) {
+    dh::launch_source_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, s->red, b, s->open_q0, s->lg2,
+                               s->open_tab);
+    dh::launch_grad_vjp(st, s->lg2, nullptr, s->lphi, Batch{s->n, s->S, s->open_tab});
+    s->open_pending = false;
   } else {
     dh::launch_source_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, s->red, b);
   }
@@ -687,13 +713,14 @@ void step_vjp(dh_sim* s, const TapeStep& T) {
   tb.sval = s->bins.sval;
   dh::launch_gather_sorted(st, tb, s->lp, b);
   dh::launch_deposit_vec(st, tb, true, s->lg, b);
-  dh::launch_kick_vjp_pos(st, s->g4b, T.x1, s->lp, true, s->lx, b);
   dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi2, b);
   // Poisson (symmetric operator) and deposit at x1
   poisson(s, s->lphi2, s->ldelta, b);
   dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc, 5 * nc, nc, false, b);
-  // with the drift x1 = x0 + p_half dt / a_h^2: lambda_p += (dt / a_h^2) lambda_x
-  dh::launch_deposit_vjp_pos(st, s->ldelta, T.x1, static_cast<float>(s->m_dm), s->lx, s->lp, b);
+  // with the kicks' term at x1 (g4b still holds g_{n+1}) and the drift
+  // x1 = x0 + p_half dt / a_h^2: lambda_p += (dt / a_h^2) lambda_x
+  dh::launch_deposit_vjp_pos(st, s->ldelta, T.x1, static_cast<float>(s->m_dm), s->lx, s->lp,
+                             s->g4b, b);
   // sweeps in reverse
   for (int k = 2; k >= 0; --k) {
     dh::launch_sweep_vjp(st, T.q[1 + k], s->lq, s->lq2, b, sp.axes[k]);
@@ -702,8 +729,13 @@ void step_vjp(dh_sim* s, const TapeStep& T) {
   // opening gas kick with phi_n
   dh::launch_grad(st, T.phi0, s->g4b, b);
   s->g4b_phi0_of = all ? sp.step : -1;
-  dh::launch_gas_kick_vjp(st, T.q[0], s->g4b, s->lq, s->lg, b);
-  dh::launch_grad_vjp(st, s->lg, nullptr, s->lphi, b);
+  if (defer_open && all && !closure) {
+    s->open_pending = true;
+    s->open_q0 = T.q[0];
+    s->open_tab = tab_of(s, sp);
+  } else {
+    opening_kick_vjp(s, T.q[0], b);
+  }
 }
 
 // Adjoint of the opening dark-matter kick of the first step (x0, phi0 of its tape entry)
@@ -736,13 +768,13 @@ void ic_vjp(dh_sim* s, float* d_grad_white) {
   const double vfac = ai * ai * s->cosmo.E(ai) * s->cosmo.growth_rate(ai);
   dh::launch_ic_particles(st, s->psi, s->pos, s->fscratch, static_cast<float>(vfac), all);
   dh::launch_deposit_vjp_pos(st, s->ldelta, s->pos, static_cast<float>(s->m_dm), s->lx, nullptr,
-                             all);
+                             nullptr, all);
   // gas: rho = f_b CIC(x), m = rho p(q), Et = a^2 rho (e_init + |p/a|^2/2)
   dh::launch_fill(st, s->lpsi, 0.0f, 3 * nc * s->S);
   dh::launch_ic_gas_vjp(st, s->cic, s->psi, s->lq, static_cast<float>(s->f_b),
                         static_cast<float>(vfac), static_cast<float>(ai),
                         static_cast<float>(s->e_init), s->lcic, s->lpsi, all);
-  dh::launch_deposit_vjp_pos(st, s->lcic, s->pos, 1.0f, s->lx, nullptr, all);
+  dh::launch_deposit_vjp_pos(st, s->lcic, s->pos, 1.0f, s->lx, nullptr, nullptr, all);
   // x = q + psi, p = vfac psi
   dh::launch_axpy(st, s->lpsi, s->lx, 1.0f, 3 * nc, 3 * nc, 3 * nc, false, all);
   dh::launch_axpy(st, s->lpsi, s->lp, static_cast<float>(vfac), 3 * nc, 3 * nc, 3 * nc, false,
@@ -1215,6 +1247,7 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     const long long nc = s->nc, np = s->np;
     const int nsteps = s->fwd_steps;
     s->g4b_phi0_of = -1;
+    s->open_pending = false;
     const int K = s->cfg.ckpt_every;
     if (!s->lq) {
       s->lq = s->alloc<float>(5 * nc * S);
@@ -1224,6 +1257,7 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
       s->lphi = s->alloc<float>(nc * S);
       s->lphi2 = s->alloc<float>(nc * S);
       s->lg = s->alloc<float>(3 * nc * S);
+      s->lg2 = s->alloc<float>(3 * nc * S);
       s->ldelta = s->alloc<float>(nc * S);
       s->lpsi = s->alloc<float>(3 * nc * S);
       s->lcic = s->alloc<float>(nc * S);
@@ -1291,7 +1325,7 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
       // step of the segment are not needed, so its pending kick is dropped
       for (int k = s0; k < s1; ++k) do_step(s, s->fwd_plans[k], &s->tape[k - s0], true);
       drop_kick(s);
-      for (int k = s1 - 1; k >= s0; --k) step_vjp(s, s->tape[k - s0]);
+      for (int k = s1 - 1; k >= s0; --k) step_vjp(s, s->tape[k - s0], k > s0);
     }
     if (nsteps > 0) finish_first_kick(s, s->tape[0]);
     ic_vjp(s, d_grad_white);

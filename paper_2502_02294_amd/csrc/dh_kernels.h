@@ -99,9 +99,11 @@ void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom,
 void launch_kick_vjp_pos(hipStream_t st, const float4* g4, const float* pos,
                          const float* lam_p, bool merged, float* lam_x, const Batch& b);
 // adjoint of the deposit wrt positions: lam_x += mass sum_c lam_delta_c dw_c/dx; with lam_p
-// (table required), then the drift's adjoint lam_p += drift lam_x
+// (table required), first (with g4) the merged kicks' term of launch_kick_vjp_pos and last
+// the drift's adjoint lam_p += drift lam_x
 void launch_deposit_vjp_pos(hipStream_t st, const float* lam_delta, const float* pos,
-                            float mass, float* lam_x, float* lam_p, const Batch& b);
+                            float mass, float* lam_x, float* lam_p, const float4* g4,
+                            const Batch& b);
 // y[s] += a x[s] over `count` values per sample (strides ys, xs); a times the table's drift
 // factor if by_drift
 void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long count,
@@ -150,9 +152,13 @@ void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, doub
 // adjoint of the closing pass with the plain source term (or none, src.mode 0) from the
 // state q_kick before the closing gas half kick with g4 (the kicked state is recomputed):
 // the source, then the kick (lam_g = adjoint of g), in one pass; partials as
-// launch_source_vjp (zeros without source)
+// launch_source_vjp (zeros without source).  With q_open: first the adjoint of the next
+// step's opening gas kick (its start state q_open, table tab_open, the same g4; every sample
+// active in both steps), its adjoint of g into lam_g_open.
 void launch_source_kick_vjp(hipStream_t st, const float* q_kick, const float4* g4,
-                            float* lam_q, float* lam_g, double* partials, const Batch& b);
+                            float* lam_q, float* lam_g, double* partials, const Batch& b,
+                            const float* q_open = nullptr, float* lam_g_open = nullptr,
+                            const StepScal* tab_open = nullptr);
 int source_vjp_blocks(int n);
 // FP64 block maxima of the CFL speed max_d (|U_d| + c_s)/a with a = a_cur[s]:
 // block_max[s][cfl_blocks(n)]

@@ -589,6 +589,25 @@ __global__ void __launch_bounds__(256) kick_kernel(const float4* __restrict__ g4
   for (int d = 0; d < 3; ++d) mom[d * np + i] = fmaf(h, g[d], mom[d * np + i]);
 }
 
+// acc = sum_corners (dw/dx) (g_corner . lp): the kick's adjoint with respect to the position
+__device__ __forceinline__ void kick_pos_acc(const float4* __restrict__ g4, const Cic& w,
+                                             const float lp[3], int n, float acc[3]) {
+  acc[0] = acc[1] = acc[2] = 0.0f;
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        const float4 g = g4[corner(w, ox, oy, oz, n)];
+        const float gl = g.x * lp[0] + g.y * lp[1] + g.z * lp[2];
+        const float wx = wsel(w.w1[0], ox), wy = wsel(w.w1[1], oy), wz = wsel(w.w1[2], oz);
+        acc[0] += (ox ? 1.0f : -1.0f) * wy * wz * gl;
+        acc[1] += wx * (oy ? 1.0f : -1.0f) * wz * gl;
+        acc[2] += wx * wy * (oz ? 1.0f : -1.0f) * gl;
+      }
+}
+
 // lam_x += h * sum_corners (dw/dx) (g_corner . lam_p)
 __global__ void __launch_bounds__(256) kick_vjp_pos_kernel(const float4* __restrict__ g4,
                                                            const float* __restrict__ pos,
@@ -606,31 +625,21 @@ __global__ void __launch_bounds__(256) kick_vjp_pos_kernel(const float4* __restr
   lam_x += blockIdx.y * 3 * np;
   const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
   const float lp[3] = {lam_p[i], lam_p[np + i], lam_p[2 * np + i]};
-  float acc[3] = {0.0f, 0.0f, 0.0f};
+  float acc[3];
+  kick_pos_acc(g4, w, lp, n, acc);
 #pragma unroll
-  for (int oz = 0; oz < 2; ++oz)
-#pragma unroll
-    for (int oy = 0; oy < 2; ++oy)
-#pragma unroll
-      for (int ox = 0; ox < 2; ++ox) {
-        const float4 g = g4[corner(w, ox, oy, oz, n)];
-        const float gl = g.x * lp[0] + g.y * lp[1] + g.z * lp[2];
-        const float wx = wsel(w.w1[0], ox), wy = wsel(w.w1[1], oy), wz = wsel(w.w1[2], oz);
-        acc[0] += (ox ? 1.0f : -1.0f) * wy * wz * gl;
-        acc[1] += wx * (oy ? 1.0f : -1.0f) * wz * gl;
-        acc[2] += wx * wy * (oz ? 1.0f : -1.0f) * gl;
-      }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) lam_x[d * np + i] += h * acc[d];
+  for (int d = 0; d < 3; ++d) lam_x[d * np + i] = fmaf(h, acc[d], lam_x[d * np + i]);
 }
 
 // lam_x += mass * sum_corners lam_delta[corner] dw/dx
-// With lam_p: then lam_p += drift lam_x (the drift's adjoint, x1 = x0 + drift p), in the
-// same pass.
+// With lam_p: first, with g4, the merged dark-matter kicks' adjoint with respect to the
+// position (kick_vjp_pos_kernel, factor h_dm); last, lam_p += drift lam_x (the drift's
+// adjoint, x1 = x0 + drift p).  One pass, the roundings of the separate kernels.
 __global__ void __launch_bounds__(256) deposit_vjp_pos_kernel(const float* __restrict__ lam_delta,
                                                               const float* __restrict__ pos,
                                                               float mass, float* __restrict__ lam_x,
                                                               float* __restrict__ lam_p,
+                                                              const float4* __restrict__ g4,
                                                               int n, long long np,
                                                               const StepScal* __restrict__ tab) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -639,7 +648,21 @@ __global__ void __launch_bounds__(256) deposit_vjp_pos_kernel(const float* __res
   pos += blockIdx.y * 3 * np;
   lam_x += blockIdx.y * 3 * np;
   if (lam_p) lam_p += blockIdx.y * 3 * np;
+  if (g4) g4 += blockIdx.y * np;
   const Cic w = cic_of(pos[i], pos[np + i], pos[2 * np + i], n);
+  float lx0[3] = {lam_x[i], lam_x[np + i], lam_x[2 * np + i]};
+  float lp[3] = {0.0f, 0.0f, 0.0f};
+  if (lam_p) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lp[d] = lam_p[d * np + i];
+  }
+  if (g4) {
+    float ka[3];
+    kick_pos_acc(g4, w, lp, n, ka);
+    const float h = tab[blockIdx.y].h_dm;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lx0[d] = fmaf(h, ka[d], lx0[d]);
+  }
   float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int oz = 0; oz < 2; ++oz)
@@ -655,9 +678,9 @@ __global__ void __launch_bounds__(256) deposit_vjp_pos_kernel(const float* __res
       }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const float lx = fmaf(mass, acc[d], lam_x[d * np + i]);
+    const float lx = fmaf(mass, acc[d], lx0[d]);
     lam_x[d * np + i] = lx;
-    if (lam_p) lam_p[d * np + i] = fmaf(tab[blockIdx.y].drift, lx, lam_p[d * np + i]);
+    if (lam_p) lam_p[d * np + i] = fmaf(tab[blockIdx.y].drift, lx, lp[d]);
   }
 }
 
@@ -826,10 +849,11 @@ void launch_kick_vjp_pos(hipStream_t st, const float4* g4, const float* pos, con
 }
 
 void launch_deposit_vjp_pos(hipStream_t st, const float* lam_delta, const float* pos, float mass,
-                            float* lam_x, float* lam_p, const Batch& b) {
+                            float* lam_x, float* lam_p, const float4* g4, const Batch& b) {
   if (lam_p && !b.tab) throw ArgError("deposit adjoint: step table required for the drift");
+  if (g4 && !lam_p) throw ArgError("deposit adjoint: the kick term needs lam_p");
   hipLaunchKernelGGL(deposit_vjp_pos_kernel, per_sample(b.nc(), b), dim3(256), 0, st, lam_delta,
-                     pos, mass, lam_x, lam_p, b.n, b.nc(), b.tab);
+                     pos, mass, lam_x, lam_p, g4, b.n, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 

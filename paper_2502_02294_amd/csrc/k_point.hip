@@ -373,10 +373,15 @@ __device__ __forceinline__ void source_cell_vjp(const float q5[5], long long c,
 // lam_g = adjoint of the kick's g; partials of dL/d(eps_sf|delta_c).  The kicked state, the
 // source term's input, is recomputed in registers exactly as the closing pass made it (same
 // operands, same arithmetic), so one pass over the cells serves both operators.
+// OPEN: first the adjoint of the following step's opening gas kick (state q_open, factor of
+// tab_open, the same g: its phi_n is this step's phi_{n+1}), adjoint of g into lam_g_open;
+// every sample moves in both steps.
+template <bool OPEN>
 __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
     const float* __restrict__ q_kick, const float4* __restrict__ g4, float* __restrict__ lam,
-    float* __restrict__ lam_g, double* partial, long long nc,
-    const StepScal* __restrict__ tab) {
+    float* __restrict__ lam_g, double* partial, long long nc, const StepScal* __restrict__ tab,
+    const float* __restrict__ q_open, float* __restrict__ lam_g_open,
+    const StepScal* __restrict__ tab_open) {
   const StepScal& sc = tab[blockIdx.y];
   if (!sc.active) {
     zero_partials<2>(partial);
@@ -388,6 +393,12 @@ __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
   g4 += blockIdx.y * nc;
   lam += blockIdx.y * 5 * nc;
   lam_g += blockIdx.y * 3 * nc;
+  float h_open = 0.0f;
+  if (OPEN) {
+    q_open += blockIdx.y * 5 * nc;
+    lam_g_open += blockIdx.y * 3 * nc;
+    h_open = tab_open[blockIdx.y].h;
+  }
   double acc[2] = {0.0, 0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   for (int r = 0; r < kRedPer; ++r) {
@@ -397,6 +408,13 @@ __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
     load_q(q_kick, c, nc, q5);
     load_q(lam, c, nc, l5);
     const float4 gv = g4[c];
+    if (OPEN) {
+      const float mo[3] = {q_open[nc + c], q_open[2 * nc + c], q_open[3 * nc + c]};
+      float lgo[3];
+      kick_cell_vjp(q_open[c], mo, gv, h_open, l5, lgo);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) lam_g_open[d * nc + c] = lgo[d];
+    }
     const float m0[3] = {q5[1], q5[2], q5[3]};
     float m[3] = {q5[1], q5[2], q5[3]};
     kick_cell(q5[0], gv, h, m, q5[4]);
@@ -937,11 +955,18 @@ void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, doub
 }
 
 void launch_source_kick_vjp(hipStream_t st, const float* q_kick, const float4* g4,
-                            float* lam_q, float* lam_g, double* partials, const Batch& b) {
+                            float* lam_q, float* lam_g, double* partials, const Batch& b,
+                            const float* q_open, float* lam_g_open, const StepScal* tab_open) {
   if (!b.tab) throw ArgError("closing pass adjoint: step table required");
   const dim3 grid(source_vjp_blocks(b.n), b.S);
-  hipLaunchKernelGGL(source_kick_vjp_kernel, grid, dim3(kRedThreads), 0, st, q_kick, g4, lam_q,
-                     lam_g, partials, b.nc(), b.tab);
+  if (q_open) {
+    if (!lam_g_open || !tab_open) throw ArgError("closing pass adjoint: opening kick operands");
+    hipLaunchKernelGGL(source_kick_vjp_kernel<true>, grid, dim3(kRedThreads), 0, st, q_kick, g4,
+                       lam_q, lam_g, partials, b.nc(), b.tab, q_open, lam_g_open, tab_open);
+  } else {
+    hipLaunchKernelGGL(source_kick_vjp_kernel<false>, grid, dim3(kRedThreads), 0, st, q_kick, g4,
+                       lam_q, lam_g, partials, b.nc(), b.tab, nullptr, nullptr, nullptr);
+  }
   DH_LAUNCH_CHECK();
 }
 
