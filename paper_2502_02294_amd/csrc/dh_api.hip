@@ -57,6 +57,7 @@ struct TapeStep {
   float *x0, *x1;             // particle positions at the start and after the drift
   float *phi0, *phi1;
   uint32_t *start, *sorted;   // the step's sort of x1 (bin starts, ids in bin order)
+  float4* spos;               // x1 in that bin order
   StepPlan plan;
 };
 
@@ -439,6 +440,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
     // former buffers
     std::swap(s->bins.start, tp->start);
     std::swap(s->bins.sorted, tp->sorted);
+    std::swap(s->bins.spos, tp->spos);
     dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, s->star, closure ? tp->q[5] : nullptr,
                           s->cfg.gamma, s->cfl_red, b, closure);
   } else {
@@ -606,6 +608,7 @@ void alloc_tape_entry(dh_sim* s, TapeStep& t) {
   t.phi1 = s->alloc<float>(s->nc * S);
   t.start = s->alloc<uint32_t>(s->nc * S + 1);
   t.sorted = s->alloc<uint32_t>(s->np * S);
+  t.spos = s->alloc<float4>(s->np * S);
 }
 
 void save_ckpt(dh_sim* s, Ckpt& c) {
@@ -704,13 +707,11 @@ void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
   }
   if (source)
     dh::launch_reduce_sum(st, s->red, nb, nb, 2 * s->S, s->param_steps + 2LL * s->S * sp.slot);
-  // x1 in bin order from the sort the recomputed step kept, then lambda_p in the same order
+  // x1 in bin order as the recomputed step's sort left it, then lambda_p in the same order
   dh::Bins tb = s->bins;
   tb.start = T.start;
   tb.sorted = T.sorted;
-  tb.sval = tb.spos;
-  dh::launch_gather_sorted(st, tb, T.x1, b);
-  tb.sval = s->bins.sval;
+  tb.spos = T.spos;
   dh::launch_gather_sorted(st, tb, s->lp, b);
   dh::launch_deposit_vec(st, tb, true, s->lg, b);
   dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi2, b);
