@@ -143,6 +143,7 @@ struct dh_sim {
 
   // reverse mode
   std::vector<Ckpt> ckpts;
+  Ckpt keep{};   // the state set aside during the reverse pass
   std::vector<TapeStep> tape;
   std::vector<StepPlan> fwd_plans;   // plans of the last dh_forward, in order
   bool have_forward = false, have_loss = false;
@@ -576,23 +577,33 @@ void commit_plan(dh_sim* s, const StepPlan& sp) {
   }
 }
 
-// Plans and takes one step of all samples; *moved = false when no sample had a step left.
-int step_once(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan* out, bool* moved,
-              bool defer) {
+// Checks the handle and plans the next step of all samples (plan_step).
+int prepare_step(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan& sp, bool* any) {
   if (!s->initialised) return fail(s, DH_E_STATE, "no initial state");
   if (s->cfg.closure == DH_CLOSURE_MLP && !s->mlp_ready)
     return fail(s, DH_E_STATE, "closure network weights not set (dh_set_closure)");
   if (!s->phi_valid) refresh_potential(s);
-  StepPlan sp;
-  bool any = false;
-  int rc = plan_step(s, t_end, stop_at_replay_end, sp, &any);
-  if (rc) return rc;
-  *moved = any;
-  if (!any) return DH_OK;
+  return plan_step(s, t_end, stop_at_replay_end, sp, any);
+}
+
+// Takes a planned step (at least one sample moves).
+void take_step(dh_sim* s, StepPlan& sp, bool defer) {
   sp.slot = s->nslots++;
   upload_plan(s, sp);
   do_step(s, sp, nullptr, defer);
   commit_plan(s, sp);
+}
+
+// Plans and takes one step of all samples; *moved = false when no sample had a step left.
+int step_once(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan* out, bool* moved,
+              bool defer) {
+  StepPlan sp;
+  bool any = false;
+  int rc = prepare_step(s, t_end, stop_at_replay_end, sp, &any);
+  if (rc) return rc;
+  *moved = any;
+  if (!any) return DH_OK;
+  take_step(s, sp, defer);
   if (out) *out = sp;
   return DH_OK;
 }
@@ -647,13 +658,43 @@ void load_ckpt(dh_sim* s, const Ckpt& c) {
   state_changed(s);
 }
 
-void release_ckpt(dh_sim* s, Ckpt& c) {
-  s->release(c.q);
-  s->release(c.pos);
-  s->release(c.mom);
-  s->release(c.star);
-  s->release(c.phi);
-  c.q = c.pos = c.mom = c.star = c.phi = nullptr;
+// Moves the state buffers aside without copying (the reverse pass then works in a spare set,
+// allocated once) and back again afterwards.
+void stash_state(dh_sim* s) {
+  flush_kick(s);
+  Ckpt& c = s->keep;
+  const long long S = s->S;
+  if (!c.q) {
+    c.q = s->alloc<float>(5 * s->nc * S);
+    c.pos = s->alloc<float>(3 * s->np * S);
+    c.mom = s->alloc<float>(3 * s->np * S);
+    c.star = s->alloc<float>(s->nc * S);
+    c.phi = s->alloc<float>(s->nc * S);
+  }
+  std::swap(s->q, c.q);
+  std::swap(s->pos, c.pos);
+  std::swap(s->mom, c.mom);
+  std::swap(s->star, c.star);
+  std::swap(s->phi, c.phi);
+  c.t = s->t;
+  c.a = s->a;
+  c.step = s->step;
+}
+
+void unstash_state(dh_sim* s) {
+  Ckpt& c = s->keep;
+  drop_kick(s);
+  std::swap(s->q, c.q);
+  std::swap(s->pos, c.pos);
+  std::swap(s->mom, c.mom);
+  std::swap(s->star, c.star);
+  std::swap(s->phi, c.phi);
+  s->t = c.t;
+  s->a = c.a;
+  s->step = c.step;
+  dh::launch_grad(s->st, s->phi, s->g4, batch(s, nullptr));
+  s->phi_valid = true;
+  state_changed(s);
 }
 
 // Adjoint of one step.  In: lq, lx, lp, lphi = adjoints of the state after the step (lphi is
@@ -1195,18 +1236,20 @@ int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_
     int count = 0;
     s->fwd_plans.clear();
     for (;;) {
-      if (count % K == 0) {
-        if (nck == s->ckpts.size()) s->ckpts.push_back(Ckpt{});
-        save_ckpt(s, s->ckpts[nck++]);
-      }
       StepPlan sp;
-      bool moved = false;
-      int rc = step_once(s, t_end, true, &sp, &moved, true);
+      bool any = false;
+      int rc = prepare_step(s, t_end, true, sp, &any);
       if (rc) {
         flush_kick(s);
         return rc;
       }
-      if (!moved) break;
+      if (!any) break;
+      // a checkpoint at the start of every K-th step (none after the last step)
+      if (count % K == 0) {
+        if (nck == s->ckpts.size()) s->ckpts.push_back(Ckpt{});
+        save_ckpt(s, s->ckpts[nck++]);
+      }
+      take_step(s, sp, true);
       s->fwd_plans.push_back(sp);
       ++count;
     }
@@ -1313,9 +1356,8 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
       s->tape.push_back(TapeStep{});
       alloc_tape_entry(s, s->tape.back());
     }
-    // keep the forward's final state to restore it afterwards
-    Ckpt final_state{};
-    save_ckpt(s, final_state);
+    // set the forward's final state aside to restore it afterwards
+    stash_state(s);
     dh::launch_fill(s->st, reinterpret_cast<float*>(s->param_steps), 0.0f,
                     4LL * S * s->param_cap);
     for (int g = nseg - 1; g >= 0; --g) {
@@ -1331,8 +1373,7 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     if (nsteps > 0) finish_first_kick(s, s->tape[0]);
     ic_vjp(s, d_grad_white);
     // restore the final state of the forward run
-    load_ckpt(s, final_state);
-    release_ckpt(s, final_state);
+    unstash_state(s);
     // parameter gradients: fixed-order host sum of the per-step FP64 partials
     std::vector<double> ps(2 * static_cast<size_t>(S) * (nsteps > 0 ? nsteps : 1));
     if (nsteps > 0)
