@@ -94,44 +94,61 @@ __device__ __forceinline__ float2 tw_full(const float2* tw, int m, int n) {
   return m < h ? w : make_float2(-w.x, -w.y);
 }
 
+// The transpose of a line transform through this line's exchange buffer ex (n floats): the
+// writer thread q puts v[i] (i < NW) at [i WS + q], the reader thread q takes v[j] (j < NR)
+// from [q RS + j]; real parts first, then imaginary parts, so the buffer is half the size
+// of a complex one (more blocks per CU).  A caller that writes ex again needs a barrier first.
+template <int NW, int WS, int NR, int RS>
+__device__ __forceinline__ void exchange(float2 (&v)[kMaxR], float* ex, int q, bool writer,
+                                         bool reader) {
+  float re[kMaxR];
+  if (writer)
+#pragma unroll
+    for (int i = 0; i < NW; ++i) ex[i * WS + q] = v[i].x;
+  __syncthreads();
+  if (reader)
+#pragma unroll
+    for (int j = 0; j < NR; ++j) re[j] = ex[q * RS + j];
+  __syncthreads();
+  if (writer)
+#pragma unroll
+    for (int i = 0; i < NW; ++i) ex[i * WS + q] = v[i].y;
+  __syncthreads();
+  if (reader)
+#pragma unroll
+    for (int j = 0; j < NR; ++j) v[j] = make_float2(re[j], ex[q * RS + j]);
+}
+
 // Forward line transform: D_x (thread q < N2 of the line) -> D_k (thread q < N1).
-// ex: this line's exchange buffer (n complex), tw: twiddle half table in LDS.
+// ex: this line's exchange buffer (n floats), tw: twiddle half table in LDS.
 template <int N1, int N2>
-__device__ __forceinline__ void line_forward(float2 (&v)[kMaxR], float2* ex, const float2* tw,
+__device__ __forceinline__ void line_forward(float2 (&v)[kMaxR], float* ex, const float2* tw,
                                              int q, bool in_x, bool in_k) {
   constexpr int n = N1 * N2;
-  if (in_x) {   // q = j2: DFT over j1, then W_n^(j2 k1), store at [k1 * N2 + j2]
+  if (in_x) {   // q = j2: DFT over j1, then W_n^(j2 k1), to [k1 * N2 + j2]
     dft_reg<N1, false>(v);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) ex[k1 * N2 + q] = cmul(v[k1], tw_full(tw, q * k1, n));
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmul(v[k1], tw_full(tw, q * k1, n));
   }
-  __syncthreads();
-  if (in_k) {   // q = k1: DFT over j2 gives X[k1 + N1 k2]
-#pragma unroll
-    for (int j2 = 0; j2 < N2; ++j2) v[j2] = ex[q * N2 + j2];
-    dft_reg<N2, false>(v);
-  }
+  exchange<N1, N2, N2, N2>(v, ex, q, in_x, in_k);
+  if (in_k) dft_reg<N2, false>(v);   // q = k1: DFT over j2 gives X[k1 + N1 k2]
 }
 
 // Inverse line transform: D_k (thread q < N1) -> D_x (thread q < N2), unnormalised.
 template <int N1, int N2>
-__device__ __forceinline__ void line_inverse(float2 (&v)[kMaxR], float2* ex, const float2* tw,
+__device__ __forceinline__ void line_inverse(float2 (&v)[kMaxR], float* ex, const float2* tw,
                                              int q, bool in_x, bool in_k) {
   constexpr int n = N1 * N2;
-  if (in_k) {   // q = k1: inverse DFT over k2 gives index a; times W_n^(-a k1); store [a * N1 + k1]
+  if (in_k) {   // q = k1: inverse DFT over k2 gives index a; times W_n^(-a k1); to [a * N1 + k1]
     dft_reg<N2, true>(v);
 #pragma unroll
     for (int a = 0; a < N2; ++a) {
       const float2 w = tw_full(tw, a * q, n);
-      ex[a * N1 + q] = cmul(v[a], make_float2(w.x, -w.y));
+      v[a] = cmul(v[a], make_float2(w.x, -w.y));
     }
   }
-  __syncthreads();
-  if (in_x) {   // q = a: inverse DFT over k1 gives x[a + N2 b]
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) v[k1] = ex[q * N1 + k1];
-    dft_reg<N1, true>(v);
-  }
+  exchange<N2, N1, N1, N1>(v, ex, q, in_k, in_x);
+  if (in_x) dft_reg<N1, true>(v);   // q = a: inverse DFT over k1 gives x[a + N2 b]
 }
 
 __device__ __forceinline__ void load_tw(float2* sh_tw, const float2* tw, int n) {
@@ -157,7 +174,7 @@ __global__ void __launch_bounds__(kFftThreads) x_r2c_kernel(const float* __restr
                                                             long long in_stride) {
   using L = Lines<N1, N2>;
   constexpr int n = L::n, nh = n / 2 + 1;
-  __shared__ float2 EX[L::tk * L::ps];
+  __shared__ float EX[L::tk * L::ps];
   __shared__ float2 TW[n / 2];
   const long long row0 = static_cast<long long>(blockIdx.x) * L::tk;
   const long long nn = static_cast<long long>(n) * n;
@@ -191,7 +208,7 @@ __global__ void __launch_bounds__(kFftThreads) x_c2r_kernel(const float2* __rest
                                                             long long out_stride) {
   using L = Lines<N1, N2>;
   constexpr int n = L::n, nh = n / 2 + 1;
-  __shared__ float2 EX[L::tk * L::ps];
+  __shared__ float EX[L::tk * L::ps];
   __shared__ float2 TW[n / 2];
   const long long row0 = static_cast<long long>(blockIdx.x) * L::tk;
   const long long nn = static_cast<long long>(n) * n;
@@ -265,6 +282,14 @@ __device__ __forceinline__ float2 apply_op(const OpArgs& o, int kx, int ky, int 
   return make_float2(-v.y * ff, v.x * ff);
 }
 
+// Workgroups go to the 8 XCDs (each with its own L2) round robin.  Consecutive line groups
+// of a pass share cache lines (a spectrum row of nh = n/2 + 1 complex values is not line
+// aligned), so each XCD takes one contiguous range of groups: block b -> group
+// (b mod 8) nb/8 + b/8 when nb is a multiple of 8 (a bijection), else b.
+__device__ __forceinline__ int xcd_group(int b, int nb) {
+  return (nb & 7) ? b : (b & 7) * (nb >> 3) + (b >> 3);
+}
+
 // Line pass along AX (1 = y, 2 = z) over tk consecutive lines of sample blockIdx.y.  Line
 // l = fixed * nh + kx (fixed = z for AX = 1, ky for AX = 2); thread t: line t % tk, q = t / tk,
 // so consecutive lanes take consecutive kx.  flags: 1 forward, 2 operator, 4 inverse, 8
@@ -278,7 +303,7 @@ __global__ void __launch_bounds__(kFftThreads) pencil_kernel(const float2* in, f
                                                              const StepScal* __restrict__ tab) {
   using L = Lines<N1, N2>;
   constexpr int n = L::n, nh = n / 2 + 1;
-  __shared__ float2 EX[L::tk * L::ps];
+  __shared__ float EX[L::tk * L::ps];
   __shared__ float2 TW[n / 2];
   if (!sample_active(tab, blockIdx.y)) return;
   if (tab && op.op == kOpGreen) op.green = tab[blockIdx.y].green;
@@ -287,13 +312,13 @@ __global__ void __launch_bounds__(kFftThreads) pencil_kernel(const float2* in, f
   out += blockIdx.y * slab;
   load_tw(TW, tw, n);
   const int li = threadIdx.x % L::tk, q = threadIdx.x / L::tk;
-  const int line = blockIdx.x * L::tk + li;
+  const int line = xcd_group(blockIdx.x, gridDim.x) * L::tk + li;
   const bool valid = line < n * nh;
   const int fixed = line / nh, kx = line - fixed * nh;
   const long long stride = AX == 1 ? nh : static_cast<long long>(n) * nh;
   const long long base = AX == 1 ? static_cast<long long>(fixed) * n * nh + kx
                                  : static_cast<long long>(fixed) * nh + kx;
-  float2* ex = EX + li * L::ps;
+  float* ex = EX + li * L::ps;
   float2 v[kMaxR];
   const bool in_x = valid && q < N2, in_k = valid && q < N1;
   if (flags & 1) {
