@@ -54,7 +54,10 @@ struct TapeStep {
   float* q[6];      // Q0 start, Q1 after opening kick (sweep-1 input), Q2, Q3 sweep inputs,
                     // Q4 after sweeps, Q5 after closing kick (source input; kept only for
                     // the learned closure, the plain source's adjoint recomputes it)
-  float *x0, *x1;             // particle positions at the start and after the drift
+  float* x0;                  // particle positions at the start
+  const float* x1;            // after the drift: not stored (the positions do not change
+                              // after the drift, so x1 is the next step's x0, or the state's
+                              // positions after a segment's last step); set by the reverse pass
   float *phi0, *phi1;
   uint32_t *start, *sorted;   // the step's sort of x1 (bin starts, ids in bin order)
   float4* spos;               // x1 in that bin order
@@ -431,7 +434,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
   if (tp) {
     // the kick, the sweeps and the closing pass write their results straight into the tape
     dh::launch_gas_kick(s->st, tp->q[0], tp->q[1], s->g4, b);
-    dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, tp->x1,
+    dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, nullptr,
                           prev, b);
     for (int k = 0; k < 3; ++k) dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
     dh::launch_sort(s->st, s->bins, s->pos, b);
@@ -614,7 +617,7 @@ void alloc_tape_entry(dh_sim* s, TapeStep& t) {
   for (int k = 0; k < 6; ++k)
     t.q[k] = k < 5 || closure ? s->alloc<float>(5 * s->nc * S) : nullptr;
   t.x0 = s->alloc<float>(3 * s->np * S);
-  t.x1 = s->alloc<float>(3 * s->np * S);
+  t.x1 = nullptr;
   t.phi0 = s->alloc<float>(s->nc * S);
   t.phi1 = s->alloc<float>(s->nc * S);
   t.start = s->alloc<uint32_t>(s->nc * S + 1);
@@ -1368,7 +1371,11 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
       // step of the segment are not needed, so its pending kick is dropped
       for (int k = s0; k < s1; ++k) do_step(s, s->fwd_plans[k], &s->tape[k - s0], true);
       drop_kick(s);
-      for (int k = s1 - 1; k >= s0; --k) step_vjp(s, s->tape[k - s0], k > s0);
+      for (int k = s1 - 1; k >= s0; --k) {
+        TapeStep& T = s->tape[k - s0];
+        T.x1 = k + 1 < s1 ? s->tape[k + 1 - s0].x0 : s->pos;
+        step_vjp(s, T, k > s0);
+      }
     }
     if (nsteps > 0) finish_first_kick(s, s->tape[0]);
     ic_vjp(s, d_grad_white);
