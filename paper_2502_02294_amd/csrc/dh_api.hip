@@ -58,7 +58,9 @@ struct TapeStep {
   const float* x1;            // after the drift: not stored (the positions do not change
                               // after the drift, so x1 is the next step's x0, or the state's
                               // positions after a segment's last step); set by the reverse pass
-  float *phi0, *phi1;
+  float* phi0;
+  const float* phi1;          // not stored either: the next step's phi0, or the state's phi
+                              // after a segment's last step; set by the reverse pass
   uint32_t *start, *sorted;   // the step's sort of x1 (bin starts, ids in bin order)
   float4* spos;               // x1 in that bin order
   StepPlan plan;
@@ -439,7 +441,6 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
     for (int k = 0; k < 3; ++k) dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
     dh::launch_sort(s->st, s->bins, s->pos, b);
     potential_from_bins(s, tp->q[4], s->phi, s->g4, b);
-    copy_d2d(s, tp->phi1, s->phi, nc * s->S);
     // the tape keeps this sort of x1 for the reverse pass; the next sort writes the tape's
     // former buffers
     std::swap(s->bins.start, tp->start);
@@ -619,7 +620,7 @@ void alloc_tape_entry(dh_sim* s, TapeStep& t) {
   t.x0 = s->alloc<float>(3 * s->np * S);
   t.x1 = nullptr;
   t.phi0 = s->alloc<float>(s->nc * S);
-  t.phi1 = s->alloc<float>(s->nc * S);
+  t.phi1 = nullptr;
   t.start = s->alloc<uint32_t>(s->nc * S + 1);
   t.sorted = s->alloc<uint32_t>(s->np * S);
   t.spos = s->alloc<float4>(s->np * S);
@@ -1374,6 +1375,7 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
       for (int k = s1 - 1; k >= s0; --k) {
         TapeStep& T = s->tape[k - s0];
         T.x1 = k + 1 < s1 ? s->tape[k + 1 - s0].x0 : s->pos;
+        T.phi1 = k + 1 < s1 ? s->tape[k + 1 - s0].phi0 : s->phi;
         step_vjp(s, T, k > s0);
       }
     }
