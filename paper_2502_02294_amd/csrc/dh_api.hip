@@ -446,8 +446,10 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
     std::swap(s->bins.start, tp->start);
     std::swap(s->bins.sorted, tp->sorted);
     std::swap(s->bins.spos, tp->spos);
-    dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, s->star, closure ? tp->q[5] : nullptr,
-                          s->cfg.gamma, s->cfl_red, b, closure);
+    // the recomputation needs neither the star field nor the CFL maxima (plain source)
+    dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, closure ? s->star : nullptr,
+                          closure ? tp->q[5] : nullptr, s->cfg.gamma,
+                          closure ? s->cfl_red : nullptr, b, closure);
   } else {
     // opening half kicks with g_n, drift with a(t + dt/2)
     dh::launch_gas_kick(s->st, s->q, s->q, s->g4, b);
@@ -484,8 +486,9 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
   }
   s->step = sp.step + 1;
   s->speed_known = false;
-  // the closing pass left the CFL maxima of every sample that moved (zeros for the others)
-  s->cfl_partials = all;
+  // the closing pass left the CFL maxima of every sample that moved (zeros for the others),
+  // except in the reverse pass's recomputation
+  s->cfl_partials = all && !tp;
 }
 
 void refresh_potential(dh_sim* s) {

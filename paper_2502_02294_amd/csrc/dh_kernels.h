@@ -141,7 +141,8 @@ void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4
 // closing pass of a step, from q_in (may equal q) into q: gas half kick with g4, optional
 // copy of the kicked state to q_kicked (tape), source term (if src.mode != 0; with the
 // learned closure if `closure`), FP64 block maxima of the CFL speed of the result at src.a
-// into block_max[S][cfl_blocks(n)]
+// into block_max[S][cfl_blocks(n)].  star and block_max both null (plain source only): the
+// star field and the CFL maxima are skipped (the reverse pass's recomputation)
 void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4* g4,
                        float* star, float* q_kicked, double gamma, double* block_max,
                        const Batch& b, bool closure);

@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(256) gas_kick_vjp_kernel(const float* __restri
 // Evaluated in FP64 from the FP32 state (the kernel is memory bound, and the relaxed draw
 // sigma(x / tau) amplifies rounding of its argument by 1/tau).
 struct SrcCell {
-  double rho, delta, e, eraw, temp, x, psf, s1, s2, pi0, z, u;
+  double rho, ir, delta, e, eraw, temp, x, psf, s1, s2, pi0, z, u;   // ir = 1 / rho
   bool floored;
 };
 
@@ -214,7 +214,8 @@ __device__ __forceinline__ void sigmoid_pair(double y, double& sig, double& log_
 __device__ SrcCell source_eval(const float q5[5], double u, const SourceArgs& a) {
   SrcCell s;
   s.rho = q5[0];
-  const double ir = 1.0 / s.rho;
+  s.ir = 1.0 / s.rho;
+  const double ir = s.ir;
   const double ia = 1.0 / a.a;
   const double u0 = q5[1] * ia * ir, u1 = q5[2] * ia * ir, u2 = q5[3] * ia * ir;
   s.eraw = q5[4] * ia * ia * ir - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
@@ -275,14 +276,16 @@ __device__ __forceinline__ double cell_speed(const float q5[5], double a, double
 }
 
 // Closing pass of a step over kRedPer cells per thread: gas half kick, optional tape copy,
-// source term, CFL block maximum of the result.
+// source term, CFL block maximum of the result.  !FULL (the reverse pass's recomputation):
+// no star field and no CFL maxima, which only the forward run needs.
+template <bool FULL>
 __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
     const float* q_in, float* q, const float4* __restrict__ g4, float* __restrict__ star,
     float* __restrict__ q_kicked, double gg1, double* partial, long long nc,
     const StepScal* __restrict__ tab) {
   const StepScal& sc = tab[blockIdx.y];
   if (!sc.active) {
-    zero_partials<1>(partial);
+    if (FULL) zero_partials<1>(partial);
     return;
   }
   const float h = sc.h;
@@ -291,7 +294,7 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
   q += blockIdx.y * 5 * nc;
   if (q_kicked) q_kicked += blockIdx.y * 5 * nc;
   g4 += blockIdx.y * nc;
-  star += blockIdx.y * nc;
+  if (FULL) star += blockIdx.y * nc;
   double vmax[1] = {0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   for (int r = 0; r < kRedPer; ++r) {
@@ -315,15 +318,15 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
         const SrcCell s = source_eval(q5, u, a);
         if (s.z != 0.0) {
           q5[4] = static_cast<float>(q5[4] + a.a * a.a * s.rho * s.z * a.e0_code);
-          star[c] = static_cast<float>(star[c] + s.z);
+          if (FULL) star[c] = static_cast<float>(star[c] + s.z);
         }
       }
     }
 #pragma unroll
     for (int k = (q == q_in ? 1 : 0); k < 5; ++k) q[k * nc + c] = q5[k];
-    vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
+    if (FULL) vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
   }
-  block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
+  if (FULL) block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
 }
 
 // Adjoint of the source term at one cell (state q5 before it): l5 from the adjoint after the
@@ -342,16 +345,16 @@ __device__ __forceinline__ void source_cell_vjp(const float q5[5], long long c,
   // Et' = Et + K rho z
   double lr = l5[0] + le * K * s.z;
   if (a.mode != 1 && le != 0.0) {
-    const double dz = s.z * (1.0 - s.z) / a.tau / (1.0 - s.pi0);   // dz / dln(pi0)
+    const double dz = s.z * (1.0 - s.z) * a.inv_tau / (1.0 - s.pi0);   // dz / dln(pi0)
     const double coef = le * K * s.rho * dz;
-    // dln p_sf / dx = 1 / expm1(x);  x ~ sqrt(rho)
-    const double dlp_dx = 1.0 / expm1(s.x);
-    const double dlnpi_drho_sf = dlp_dx * s.x * 0.5 / s.rho;
-    const double dlnpi_drho_s1 = (1.0 - s.s1) * a.inv_rho_mean / (a.w_rho * a.delta_c);
+    // dln p_sf / dx = 1 / expm1(x) = (1 - p_sf) / p_sf;  x ~ sqrt(rho)
+    const double dlp_dx = (1.0 - s.psf) / s.psf;
+    const double ir = s.ir, ia = 1.0 / a.a;
+    const double dlnpi_drho_sf = dlp_dx * s.x * 0.5 * ir;
+    const double dlnpi_drho_s1 = (1.0 - s.s1) * a.inv_rho_mean * a.k_rho;
     // s2 through T(e)
-    const double dlnpi_dT = -(1.0 - s.s2) / (a.w_t * a.t_c);
+    const double dlnpi_dT = -(1.0 - s.s2) * a.k_t;
     const double dT = s.floored ? 0.0 : a.t_per_e;
-    const double ir = 1.0 / s.rho, ia = 1.0 / a.a;
     double u[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) u[d] = q5[1 + d] * ia * ir;
@@ -929,13 +932,18 @@ void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4
                        float* star, float* q_kicked, double gamma, double* block_max,
                        const Batch& b, bool closure) {
   if (!b.tab) throw ArgError("closing pass: step table required");
+  if ((star == nullptr) != (block_max == nullptr) || (closure && !star))
+    throw ArgError("closing pass: star field and CFL maxima go together (both for the closure)");
   const dim3 grid(sum_blocks(b.nc()), b.S);
   if (closure)
     hipLaunchKernelGGL(close_step_mlp_kernel, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
                        q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab);
-  else
-    hipLaunchKernelGGL(close_step_kernel, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
+  else if (star)
+    hipLaunchKernelGGL(close_step_kernel<true>, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
                        q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab);
+  else
+    hipLaunchKernelGGL(close_step_kernel<false>, grid, dim3(kRedThreads), 0, st, q_in, q, g4,
+                       star, q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab);
   DH_LAUNCH_CHECK();
 }
 
