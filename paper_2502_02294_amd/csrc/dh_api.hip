@@ -63,6 +63,9 @@ struct TapeStep {
                               // after a segment's last step; set by the reverse pass
   uint32_t *start, *sorted;   // the step's sort of x1 (bin starts, ids in bin order)
   float4* spos;               // x1 in that bin order
+  // the sort the reverse pass uses: the buffers above, or the forward's stored one
+  uint32_t *vstart, *vsorted;
+  float4* vspos;
   StepPlan plan;
 };
 
@@ -70,6 +73,16 @@ struct Ckpt {
   float *q, *pos, *mom, *star, *phi;
   std::vector<double> t, a;
   int step;
+};
+
+// What a forward step computed that its recomputation in the reverse pass would compute
+// again, bit for bit: the sort of the post-drift positions (bin starts, ids, positions in
+// bin order) and the end-of-step potential.  Kept per step while memory allows.
+struct StepStore {
+  uint32_t* start = nullptr;
+  uint32_t* sorted = nullptr;
+  float4* spos = nullptr;
+  float* phi = nullptr;
 };
 
 }  // namespace
@@ -149,6 +162,10 @@ struct dh_sim {
   // reverse mode
   std::vector<Ckpt> ckpts;
   Ckpt keep{};   // the state set aside during the reverse pass
+  // per-step results of the last dh_forward: steps [0, store_valid) are held in store;
+  // store_limit = how many steps this forward may keep (memory budget)
+  std::vector<StepStore> store;
+  int store_valid = 0, store_limit = 0;
   std::vector<TapeStep> tape;
   std::vector<StepPlan> fwd_plans;   // plans of the last dh_forward, in order
   bool have_forward = false, have_loss = false;
@@ -349,6 +366,77 @@ void drop_kick(dh_sim* s) {
   s->kick_pending = false;
 }
 
+long long store_step_bytes(const dh_sim* s) {
+  const long long S = s->S;
+  return (s->nc * S + 1) * 4 + s->np * S * (4 + 16) + s->nc * S * 4;
+}
+
+// Device memory the first reverse pass still has to allocate (tape entries, adjoint buffers,
+// the spare state set).
+long long reverse_pass_bytes(const dh_sim* s) {
+  const long long S = s->S, nc = s->nc * S, np = s->np * S;
+  const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
+  const long long entry = (closure ? 6 : 5) * 5 * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 +
+                          np * 4 + np * 16;
+  long long need = 0;
+  const long long k = s->cfg.ckpt_every;
+  if (static_cast<long long>(s->tape.size()) < k)
+    need += (k - static_cast<long long>(s->tape.size())) * entry;
+  if (!s->lq) need += 29 * nc * 4;
+  if (!s->keep.q) need += 5 * nc * 4 + 6 * np * 4 + 2 * nc * 4;
+  return need;
+}
+
+// How many forward steps may be stored: what is free after the reverse pass's own buffers
+// and a margin of 4 GiB (entries allocated earlier are reused).
+int store_budget(dh_sim* s) {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    return static_cast<int>(s->store.size());
+  }
+  const long long margin = 4LL << 30;
+  const long long avail = static_cast<long long>(free_b) - reverse_pass_bytes(s) - margin;
+  const long long more = avail > 0 ? avail / store_step_bytes(s) : 0;
+  return static_cast<int>(std::min<long long>(s->store.size() + more, 1 << 20));
+}
+
+// Keeps forward step k's sort (the bins trade buffers with the store: no copy) and potential.
+// Returns false (and keeps nothing more in this forward) when the memory is not there.
+bool keep_step(dh_sim* s, int k) {
+  if (k >= s->store_limit || k != s->store_valid) return false;
+  if (k == static_cast<int>(s->store.size())) {
+    const long long S = s->S;
+    StepStore e;
+    void* p[4] = {nullptr, nullptr, nullptr, nullptr};
+    const size_t bytes[4] = {static_cast<size_t>(s->nc * S + 1) * 4,
+                             static_cast<size_t>(s->np * S) * 4,
+                             static_cast<size_t>(s->np * S) * 16,
+                             static_cast<size_t>(s->nc * S) * 4};
+    for (int i = 0; i < 4; ++i) {
+      if (hipMalloc(&p[i], bytes[i]) != hipSuccess) {
+        (void)hipGetLastError();
+        for (int j = 0; j < i; ++j) (void)hipFree(p[j]);
+        s->store_limit = k;
+        return false;
+      }
+      s->allocs.push_back(p[i]);
+    }
+    e.start = static_cast<uint32_t*>(p[0]);
+    e.sorted = static_cast<uint32_t*>(p[1]);
+    e.spos = static_cast<float4*>(p[2]);
+    e.phi = static_cast<float*>(p[3]);
+    s->store.push_back(e);
+  }
+  StepStore& e = s->store[k];
+  std::swap(s->bins.start, e.start);
+  std::swap(s->bins.sorted, e.sorted);
+  std::swap(s->bins.spos, e.spos);
+  copy_d2d(s, e.phi, s->phi, s->nc * s->S);
+  s->store_valid = k + 1;
+  return true;
+}
+
 // bins of the particle positions pos (all samples of b)
 void sort_particles(dh_sim* s, const float* pos, const Batch& b) {
   dh::launch_keys(s->st, pos, s->bins.key, b);
@@ -408,7 +496,9 @@ bool all_finite(const std::vector<double>& v) {
 
 // One step of the method on the handle state.  With a tape entry, keeps its intermediates.
 // defer: leave the closing dark-matter kick to the next step's kick-drift pass.
-void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
+// store_k >= 0: step store_k of a forward run (no tape: keep its sort and potential if the
+// budget allows; with a tape: take them from the store when it holds them).
+void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_k) {
   const long long nc = s->nc, np = s->np;
   if (!defer) flush_kick(s);
   const bool prev = s->kick_pending;
@@ -439,13 +529,26 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
     dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, nullptr,
                           prev, b);
     for (int k = 0; k < 3; ++k) dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
-    dh::launch_sort(s->st, s->bins, s->pos, b);
-    potential_from_bins(s, tp->q[4], s->phi, s->g4, b);
-    // the tape keeps this sort of x1 for the reverse pass; the next sort writes the tape's
-    // former buffers
-    std::swap(s->bins.start, tp->start);
-    std::swap(s->bins.sorted, tp->sorted);
-    std::swap(s->bins.spos, tp->spos);
+    if (store_k >= 0 && store_k < s->store_valid) {
+      // the forward kept this step's sort and potential: no sort, deposit or Poisson solve
+      const StepStore& e = s->store[store_k];
+      copy_d2d(s, s->phi, e.phi, nc * s->S);
+      dh::launch_grad(s->st, s->phi, s->g4, b);
+      tp->vstart = e.start;
+      tp->vsorted = e.sorted;
+      tp->vspos = e.spos;
+    } else {
+      dh::launch_sort(s->st, s->bins, s->pos, b);
+      potential_from_bins(s, tp->q[4], s->phi, s->g4, b);
+      // the tape keeps this sort of x1 for the reverse pass; the next sort writes the tape's
+      // former buffers
+      std::swap(s->bins.start, tp->start);
+      std::swap(s->bins.sorted, tp->sorted);
+      std::swap(s->bins.spos, tp->spos);
+      tp->vstart = tp->start;
+      tp->vsorted = tp->sorted;
+      tp->vspos = tp->spos;
+    }
     // the recomputation needs neither the star field nor the CFL maxima (plain source)
     dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, closure ? s->star : nullptr,
                           closure ? tp->q[5] : nullptr, s->cfg.gamma,
@@ -463,6 +566,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer) {
     // Poisson at a(t + dt) from gas + DM (keys were written by the drift)
     dh::launch_sort(s->st, s->bins, s->pos, b);
     potential_from_bins(s, s->q, s->phi, s->g4, b);
+    if (store_k >= 0) keep_step(s, store_k);
     // closing gas half kick with g_{n+1}, source term and the CFL maxima: one pass
     dh::launch_close_step(s->st, s->q, s->q, s->g4, s->star, nullptr, s->cfg.gamma, s->cfl_red, b,
                           closure);
@@ -594,10 +698,10 @@ int prepare_step(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan& sp,
 }
 
 // Takes a planned step (at least one sample moves).
-void take_step(dh_sim* s, StepPlan& sp, bool defer) {
+void take_step(dh_sim* s, StepPlan& sp, bool defer, int store_k = -1) {
   sp.slot = s->nslots++;
   upload_plan(s, sp);
-  do_step(s, sp, nullptr, defer);
+  do_step(s, sp, nullptr, defer, store_k);
   commit_plan(s, sp);
 }
 
@@ -757,9 +861,9 @@ void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
     dh::launch_reduce_sum(st, s->red, nb, nb, 2 * s->S, s->param_steps + 2LL * s->S * sp.slot);
   // x1 in bin order as the recomputed step's sort left it, then lambda_p in the same order
   dh::Bins tb = s->bins;
-  tb.start = T.start;
-  tb.sorted = T.sorted;
-  tb.spos = T.spos;
+  tb.start = T.vstart;
+  tb.sorted = T.vsorted;
+  tb.spos = T.vspos;
   dh::launch_gather_sorted(st, tb, s->lp, b);
   dh::launch_deposit_vec(st, tb, true, s->lg, b);
   dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi2, b);
@@ -1242,6 +1346,8 @@ int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_
     size_t nck = 0;
     int count = 0;
     s->fwd_plans.clear();
+    s->store_valid = 0;
+    s->store_limit = store_budget(s);
     for (;;) {
       StepPlan sp;
       bool any = false;
@@ -1256,7 +1362,7 @@ int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_
         if (nck == s->ckpts.size()) s->ckpts.push_back(Ckpt{});
         save_ckpt(s, s->ckpts[nck++]);
       }
-      take_step(s, sp, true);
+      take_step(s, sp, true, count);
       s->fwd_plans.push_back(sp);
       ++count;
     }
@@ -1373,7 +1479,7 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
       // the recomputed trajectory is the forward's bit for bit (the forward also deferred
       // its kicks and applied them before each checkpoint); the momenta after the last
       // step of the segment are not needed, so its pending kick is dropped
-      for (int k = s0; k < s1; ++k) do_step(s, s->fwd_plans[k], &s->tape[k - s0], true);
+      for (int k = s0; k < s1; ++k) do_step(s, s->fwd_plans[k], &s->tape[k - s0], true, k);
       drop_kick(s);
       for (int k = s1 - 1; k >= s0; --k) {
         TapeStep& T = s->tape[k - s0];
