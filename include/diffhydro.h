@@ -168,6 +168,12 @@ int dh_get_sample_times(const dh_sim* sim, double* a, double* t);
  * cfg.ckpt_every steps (replaying each sample's schedule if one was set, else recording
  * it); *nsteps_out = number of lockstep steps. */
 int dh_forward(dh_sim* sim, const float* d_white, double a_final, int32_t* nsteps_out);
+/* How many steps of a dh_forward keep their particle sort and end-of-step potential for
+ * the reverse pass, which then skips recomputing them (the results are the same bit for
+ * bit).  max_steps < 0 (the default): as many as device memory allows, after the reverse
+ * pass's own buffers and a 4 GiB margin (about 28 bytes per cell and step); 0: none.
+ * Takes effect at the next dh_forward. */
+int dh_set_store_limit(dh_sim* sim, int32_t max_steps);
 /* Loss L = mean over cells of (F - F_target)^2 with F = exp(-A (rho/rho_mean)^beta) on the
  * current state; FP64 reduction.  d_target[n^3] device (per sample); loss_out: one value
  * per sample. */

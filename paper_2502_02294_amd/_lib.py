@@ -72,6 +72,7 @@ _SIGNATURES = {
     "dh_step": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
     "dh_run_to": (I, [P, D, ctypes.POINTER(I)]),
     "dh_run_steps": (I, [P, I, ctypes.POINTER(I)]),
+    "dh_set_store_limit": (I, [P, I]),
     "dh_set_schedule": (I, [P, ctypes.POINTER(D), I]),
     "dh_get_schedule": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
     "dh_set_sample_schedule": (I, [P, I, ctypes.POINTER(D), I]),

@@ -166,6 +166,7 @@ struct dh_sim {
   // store_limit = how many steps this forward may keep (memory budget)
   std::vector<StepStore> store;
   int store_valid = 0, store_limit = 0;
+  int store_max = -1;   // caller's cap on stored steps (< 0: none)
   std::vector<TapeStep> tape;
   std::vector<StepPlan> fwd_plans;   // plans of the last dh_forward, in order
   bool have_forward = false, have_loss = false;
@@ -1337,6 +1338,12 @@ int dh_set_time(dh_sim* s, double a, int32_t step) {
   return DH_OK;
 }
 
+int dh_set_store_limit(dh_sim* s, int32_t max_steps) {
+  if (!s) return DH_E_INVAL;
+  s->store_max = max_steps < 0 ? -1 : max_steps;
+  return DH_OK;
+}
+
 int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_out) {
   if (!s || !d_white || !(a_final > s->cfg.a_init)) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
@@ -1348,6 +1355,7 @@ int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_
     s->fwd_plans.clear();
     s->store_valid = 0;
     s->store_limit = store_budget(s);
+    if (s->store_max >= 0) s->store_limit = std::min(s->store_limit, s->store_max);
     for (;;) {
       StepPlan sp;
       bool any = false;

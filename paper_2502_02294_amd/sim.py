@@ -213,6 +213,10 @@ class Sim:
         self._stream()
         self._check(lib().dh_set_time(self._h, a, step))
 
+    def set_store_limit(self, max_steps):
+        """Cap on forward steps whose sort and potential are kept for backward (-1: memory)."""
+        self._check(lib().dh_set_store_limit(self._h, int(max_steps)))
+
     def forward(self, white, a_final):
         self._stream()
         k = ctypes.c_int32()

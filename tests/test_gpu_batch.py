@@ -138,6 +138,39 @@ def test_batch_gradient_equals_single_runs(dhp):
         assert gpb[i] == gp, (i, gpb[i], gp)
 
 
+@pytest.mark.parametrize("S", [1, 3])
+def test_reverse_pass_with_and_without_stored_steps(dhp, S):
+    """The forward keeps each step's particle sort and potential for the reverse pass (as
+    memory allows); the recomputation takes them instead of computing them again.  All,
+    some or none kept: the same gradients bit for bit (with S = 3 the samples end after
+    different numbers of steps)."""
+    n, box = 16, 4.0
+    white = np.stack([si.white_noise(n, seed=90 + i) for i in range(S)])
+    target = (0.2 + 0.7 * np.random.default_rng(5).random((S, n, n, n))).astype(np.float32)
+    outs = []
+    for limit in (-1, 0, 2):
+        print(f"reverse pass, S = {S}, store limit {limit}", flush=True)
+        if S == 1:
+            b = _single(dhp, n, box, 0, a_init=0.05, ckpt_every=3)
+            b.set_schedule(REPLAY[2])
+        else:
+            b = _batch(dhp, n, box, S, a_init=0.05, ckpt_every=3)
+            for i, dts in REPLAY.items():
+                b.set_sample_schedule(i, dts)
+        b.set_store_limit(limit)
+        w = to_gpu(white if S > 1 else white[0])
+        t = to_gpu(target if S > 1 else target[0])
+        k = b.forward(w, 0.08)
+        assert k >= 4, k   # two checkpoint segments or more
+        b.loss(t)
+        gw, gp = b.backward()
+        outs.append((gw.clone(), gp, b.get("q").clone()))
+        b.close()
+    for gw, gp, q in outs[1:]:
+        assert torch.equal(gw, outs[0][0]) and gp == outs[0][1]
+        assert torch.equal(q, outs[0][2])   # the forward's final state is restored
+
+
 def test_batch_sample_gradient_matches_oracle_autograd(dhp):
     n, box, S = 16, 4.0, 2
     white = np.stack([si.white_noise(n, seed=70 + i) for i in range(S)])
