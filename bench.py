@@ -102,10 +102,25 @@ def sweep_valu_insts():
     return {ax: float(v["valu_insts_per_launch"]) for ax, v in doc["per_axis"].items()}
 
 
+def time_fwd_bwd(torch, s, white, sched, target, steps):
+    """Seconds of one forward + loss + reverse pass over the schedule, after an untimed one."""
+    for timed in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_schedule(sched)
+        k = s.forward(white, 1.0)
+        s.loss(target)
+        s.backward()
+        torch.cuda.synchronize()
+        assert k == steps
+    return time.perf_counter() - t0
+
+
 def time_steps(torch, s, white, steps, warmup):
-    """(forward-only seconds, forward-with-checkpoints + loss + reverse seconds) of `steps`
-    steps from the initial conditions of `white`, after `warmup` untimed steps / one untimed
-    pass of the full path."""
+    """(forward-only seconds, forward + loss + reverse seconds with what device memory lets
+    the forward keep, the same with every checkpoint segment recomputed, the schedule, the
+    steps the forward taped) of `steps` steps from the initial conditions of `white`, after
+    `warmup` untimed steps / one untimed pass of the full path."""
     s.init_from_noise(white)
     s.run_steps(warmup)
     torch.cuda.synchronize()
@@ -117,20 +132,12 @@ def time_steps(torch, s, white, steps, warmup):
     s.run_steps(steps)
     sched = s.get_schedule()
     target = s.get("flux").clone()
-    s.set_schedule(sched)
-    s.forward(white, 1.0)
-    s.loss(target)
-    s.backward()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.set_schedule(sched)
-    k = s.forward(white, 1.0)
-    s.loss(target)
-    s.backward()
-    torch.cuda.synchronize()
-    t_fb = time.perf_counter() - t0
-    assert k == steps
-    return t_fwd, t_fb, sched
+    t_fb = time_fwd_bwd(torch, s, white, sched, target, steps)
+    taped = s.store_info()
+    s.set_store_limit(0)
+    t_fb_recompute = time_fwd_bwd(torch, s, white, sched, target, steps)
+    s.set_store_limit(-1)
+    return t_fwd, t_fb, t_fb_recompute, sched, taped
 
 
 def mlp_comparison(torch, dhp, white, n, box, steps, warmup, samples):
@@ -158,7 +165,7 @@ def mlp_comparison(torch, dhp, white, n, box, steps, warmup, samples):
         s = dhp.Sim(cfg, prm)
         if clo:
             s.set_closure(theta)
-        t_fwd, t_fb, _ = time_steps(torch, s, white, steps, warmup)
+        t_fwd, t_fb, _, _, _ = time_steps(torch, s, white, steps, warmup)
         rates[name] = (n ** 3 * steps / t_fwd, n ** 3 * steps / t_fb)
         s.close()
         log(f"bench: {name} source term: forward {t_fwd * 1e3 / steps:.2f} ms/step, "
@@ -314,9 +321,11 @@ def main():
     white = torch.from_numpy(si.white_noise(n, 6)).cuda()
     log(f"bench: n={n} steps={args.steps} warmup={args.warmup}")
 
-    t_fwd, t_fb, sched = time_steps(torch, s, white, args.steps, args.warmup)
+    t_fwd, t_fb, t_fb_rc, sched, taped = time_steps(torch, s, white, args.steps, args.warmup)
     log(f"bench: forward {args.steps} steps {t_fwd * 1e3:.1f} ms")
-    log(f"bench: forward+backward {args.steps} steps {t_fb * 1e3:.1f} ms")
+    log(f"bench: forward+backward {args.steps} steps {t_fb * 1e3:.1f} ms "
+        f"({taped[0]} taped by the forward, {taped[1]} with a kept sort); every segment "
+        f"recomputed {t_fb_rc * 1e3:.1f} ms")
 
     # dominant kernel: the hydro sweep (three per step, three adjoint sweeps in the reverse
     # pass), bound by vector ALU issue: 236 FP32 operations and 40 bytes per cell and launch
@@ -353,7 +362,14 @@ def main():
         "config": {"workload": f"{n}^3 cells + {n}^3 DM particles, {BOX * n / N:g} Mpc/h box, "
                                "BBKS Gaussian random field at a=0.01, relaxed stochastic star "
                                "formation, checkpointed forward + reverse pass",
-                   "n": n, "box_mpc_h": BOX * n / N, "ckpt_every": int(cfg.ckpt_every)},
+                   "n": n, "box_mpc_h": BOX * n / N, "ckpt_every": int(cfg.ckpt_every),
+                   "reverse_data": "capacity-chosen: the forward taped "
+                                   f"{taped[0]} of {args.steps} steps, kept the sort of "
+                                   f"{taped[1]} more; the rest recomputed from checkpoints"},
+        "fwd_bwd_recompute_all": {"value": nc * args.steps / t_fb_rc,
+                                  "ms_per_step": t_fb_rc / args.steps * 1e3,
+                                  "what": "the same with every checkpoint segment recomputed "
+                                          "(nothing kept by the forward)"},
         "fwd_cell_updates_per_s": nc * args.steps / t_fwd,
         "fwd_ms_per_step": t_fwd / args.steps * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,

@@ -168,12 +168,19 @@ int dh_get_sample_times(const dh_sim* sim, double* a, double* t);
  * cfg.ckpt_every steps (replaying each sample's schedule if one was set, else recording
  * it); *nsteps_out = number of lockstep steps. */
 int dh_forward(dh_sim* sim, const float* d_white, double a_final, int32_t* nsteps_out);
-/* How many steps of a dh_forward keep their particle sort and end-of-step potential for
- * the reverse pass, which then skips recomputing them (the results are the same bit for
- * bit).  max_steps < 0 (the default): as many as device memory allows, after the reverse
- * pass's own buffers and a 4 GiB margin (about 28 bytes per cell and step); 0: none.
+/* How many steps of a dh_forward keep data for the reverse pass, which then recomputes less
+ * (the results are the same bit for bit): first whole checkpoint segments keep their full
+ * tape (the reverse pass recomputes nothing there; about 140 bytes per cell and step), then
+ * further steps keep their particle sort and end-of-step potential (its recomputation skips
+ * the sort, the deposit and the Poisson solve; about 28 bytes per cell and step).
+ * max_steps < 0 (the default): as many as device memory allows after the reverse pass's own
+ * buffers and a 4 GiB margin; 0: none (every segment is recomputed from its checkpoint).
  * Takes effect at the next dh_forward. */
 int dh_set_store_limit(dh_sim* sim, int32_t max_steps);
+/* What the last dh_forward kept: *taped = steps on its own tape (the first ones, whole
+ * checkpoint segments or all), *sorted = further steps with a kept sort and potential.
+ * Either pointer may be NULL. */
+int dh_get_store_info(const dh_sim* sim, int32_t* taped, int32_t* sorted);
 /* Loss L = mean over cells of (F - F_target)^2 with F = exp(-A (rho/rho_mean)^beta) on the
  * current state; FP64 reduction.  d_target[n^3] device (per sample); loss_out: one value
  * per sample. */

@@ -73,6 +73,7 @@ _SIGNATURES = {
     "dh_run_to": (I, [P, D, ctypes.POINTER(I)]),
     "dh_run_steps": (I, [P, I, ctypes.POINTER(I)]),
     "dh_set_store_limit": (I, [P, I]),
+    "dh_get_store_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
     "dh_set_schedule": (I, [P, ctypes.POINTER(D), I]),
     "dh_get_schedule": (I, [P, ctypes.POINTER(D), I, ctypes.POINTER(I)]),
     "dh_set_sample_schedule": (I, [P, I, ctypes.POINTER(D), I]),

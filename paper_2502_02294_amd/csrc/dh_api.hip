@@ -167,6 +167,11 @@ struct dh_sim {
   std::vector<StepStore> store;
   int store_valid = 0, store_limit = 0;
   int store_max = -1;   // caller's cap on stored steps (< 0: none)
+  // the forward's own tape of its first steps [0, taped) (whole checkpoint segments, or the
+  // whole run): the reverse pass recomputes nothing there.  tape_limit = the budget of this
+  // forward (a multiple of ckpt_every); store entries are then those of steps tape_limit + j.
+  std::vector<TapeStep> ftape;
+  int taped = 0, tape_limit = 0;
   std::vector<TapeStep> tape;
   std::vector<StepPlan> fwd_plans;   // plans of the last dh_forward, in order
   bool have_forward = false, have_loss = false;
@@ -388,22 +393,43 @@ long long reverse_pass_bytes(const dh_sim* s) {
   return need;
 }
 
-// How many forward steps may be stored: what is free after the reverse pass's own buffers
-// and a margin of 4 GiB (entries allocated earlier are reused).
-int store_budget(dh_sim* s) {
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
-    (void)hipGetLastError();
-    return static_cast<int>(s->store.size());
-  }
-  const long long margin = 4LL << 30;
-  const long long avail = static_cast<long long>(free_b) - reverse_pass_bytes(s) - margin;
-  const long long more = avail > 0 ? avail / store_step_bytes(s) : 0;
-  return static_cast<int>(std::min<long long>(s->store.size() + more, 1 << 20));
+long long tape_entry_bytes(const dh_sim* s) {
+  const long long S = s->S, nc = s->nc * S, np = s->np * S;
+  const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
+  return (closure ? 6 : 5) * 5 * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 + np * 4 +
+         np * 16;
 }
 
-// Keeps forward step k's sort (the bins trade buffers with the store: no copy) and potential.
-// Returns false (and keeps nothing more in this forward) when the memory is not there.
+// What the next forward may keep for the reverse pass, from what the device has free after
+// the reverse pass's own buffers and a margin of 4 GiB (entries allocated earlier are
+// reused), within the caller's cap: first the full tape of whole checkpoint segments, then
+// the sort and potential of further steps.
+void plan_storage(dh_sim* s) {
+  size_t free_b = 0, total_b = 0;
+  long long avail = 0;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+    avail = static_cast<long long>(free_b) - reverse_pass_bytes(s) - (4LL << 30);
+  else
+    (void)hipGetLastError();
+  if (avail < 0) avail = 0;
+  const long long K = s->cfg.ckpt_every;
+  const long long cap = s->store_max >= 0 ? s->store_max : (1LL << 20);
+  const long long entry = tape_entry_bytes(s), sstep = store_step_bytes(s);
+  const long long have_t = static_cast<long long>(s->ftape.size());
+  long long tl = std::min(cap, have_t + avail / entry);
+  tl -= tl % K;
+  const long long new_t = std::max(0LL, tl - have_t) * entry;
+  const long long sl = std::min(cap - tl, static_cast<long long>(s->store.size()) +
+                                              std::max(0LL, avail - new_t) / sstep);
+  s->tape_limit = static_cast<int>(tl);
+  s->store_limit = static_cast<int>(std::max(0LL, sl));
+  s->store_valid = 0;
+  s->taped = 0;
+}
+
+// Keeps the sort (the bins trade buffers with the store: no copy) and potential of the
+// forward step with store index k (step tape_limit + k).  Returns false (and keeps nothing
+// more in this forward) when the memory is not there.
 bool keep_step(dh_sim* s, int k) {
   if (k >= s->store_limit || k != s->store_valid) return false;
   if (k == static_cast<int>(s->store.size())) {
@@ -497,9 +523,11 @@ bool all_finite(const std::vector<double>& v) {
 
 // One step of the method on the handle state.  With a tape entry, keeps its intermediates.
 // defer: leave the closing dark-matter kick to the next step's kick-drift pass.
-// store_k >= 0: step store_k of a forward run (no tape: keep its sort and potential if the
-// budget allows; with a tape: take them from the store when it holds them).
-void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_k) {
+// store_k >= 0: store index of a forward step (no tape: keep its sort and potential if the
+// budget allows; recomputing: take them from the store when it holds them).  recompute: the
+// reverse pass's recomputation into a tape (else a tape entry records a forward step).
+void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_k,
+             bool recompute) {
   const long long nc = s->nc, np = s->np;
   if (!defer) flush_kick(s);
   const bool prev = s->kick_pending;
@@ -530,7 +558,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
     dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, nullptr,
                           prev, b);
     for (int k = 0; k < 3; ++k) dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
-    if (store_k >= 0 && store_k < s->store_valid) {
+    if (recompute && store_k >= 0 && store_k < s->store_valid) {
       // the forward kept this step's sort and potential: no sort, deposit or Poisson solve
       const StepStore& e = s->store[store_k];
       copy_d2d(s, s->phi, e.phi, nc * s->S);
@@ -551,9 +579,10 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
       tp->vspos = tp->spos;
     }
     // the recomputation needs neither the star field nor the CFL maxima (plain source)
-    dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, closure ? s->star : nullptr,
+    const bool full = !recompute || closure;
+    dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, full ? s->star : nullptr,
                           closure ? tp->q[5] : nullptr, s->cfg.gamma,
-                          closure ? s->cfl_red : nullptr, b, closure);
+                          full ? s->cfl_red : nullptr, b, closure);
   } else {
     // opening half kicks with g_n, drift with a(t + dt/2)
     dh::launch_gas_kick(s->st, s->q, s->q, s->g4, b);
@@ -593,7 +622,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
   s->speed_known = false;
   // the closing pass left the CFL maxima of every sample that moved (zeros for the others),
   // except in the reverse pass's recomputation
-  s->cfl_partials = all && !tp;
+  s->cfl_partials = all && !recompute;
 }
 
 void refresh_potential(dh_sim* s) {
@@ -699,10 +728,11 @@ int prepare_step(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan& sp,
 }
 
 // Takes a planned step (at least one sample moves).
-void take_step(dh_sim* s, StepPlan& sp, bool defer, int store_k = -1) {
+void take_step(dh_sim* s, StepPlan& sp, bool defer, int store_k = -1,
+               TapeStep* tp = nullptr) {
   sp.slot = s->nslots++;
   upload_plan(s, sp);
-  do_step(s, sp, nullptr, defer, store_k);
+  do_step(s, sp, tp, defer, store_k, false);
   commit_plan(s, sp);
 }
 
@@ -1344,18 +1374,22 @@ int dh_set_store_limit(dh_sim* s, int32_t max_steps) {
   return DH_OK;
 }
 
+int dh_get_store_info(const dh_sim* s, int32_t* taped, int32_t* sorted) {
+  if (!s) return DH_E_INVAL;
+  if (taped) *taped = s->taped;
+  if (sorted) *sorted = s->store_valid;
+  return DH_OK;
+}
+
 int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_out) {
   if (!s || !d_white || !(a_final > s->cfg.a_init)) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
     initial_conditions(s, d_white);
     const double t_end = s->cosmo.t_of_a(a_final);
     const int K = s->cfg.ckpt_every;
-    size_t nck = 0;
     int count = 0;
     s->fwd_plans.clear();
-    s->store_valid = 0;
-    s->store_limit = store_budget(s);
-    if (s->store_max >= 0) s->store_limit = std::min(s->store_limit, s->store_max);
+    plan_storage(s);
     for (;;) {
       StepPlan sp;
       bool any = false;
@@ -1365,12 +1399,23 @@ int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_
         return rc;
       }
       if (!any) break;
-      // a checkpoint at the start of every K-th step (none after the last step)
-      if (count % K == 0) {
-        if (nck == s->ckpts.size()) s->ckpts.push_back(Ckpt{});
-        save_ckpt(s, s->ckpts[nck++]);
+      if (count < s->tape_limit) {
+        // recorded into the forward's own tape (no checkpoint needed for these segments)
+        while (static_cast<int>(s->ftape.size()) <= count) {
+          s->ftape.push_back(TapeStep{});
+          alloc_tape_entry(s, s->ftape.back());
+        }
+        take_step(s, sp, true, -1, &s->ftape[count]);
+        s->taped = count + 1;
+      } else {
+        // a checkpoint at the start of every K-th step (none after the last step)
+        if (count % K == 0) {
+          const size_t g = static_cast<size_t>(count / K);
+          if (s->ckpts.size() <= g) s->ckpts.resize(g + 1);
+          save_ckpt(s, s->ckpts[g]);
+        }
+        take_step(s, sp, true, count - s->tape_limit);
       }
-      take_step(s, sp, true, count);
       s->fwd_plans.push_back(sp);
       ++count;
     }
@@ -1472,7 +1517,8 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     }
     // segments in reverse
     const int nseg = (nsteps + K - 1) / K;
-    const size_t want = static_cast<size_t>(std::min(K, nsteps));
+    // the recomputation's tape, if some segment is not on the forward's own tape
+    const size_t want = s->taped < nsteps ? static_cast<size_t>(std::min(K, nsteps)) : 0;
     while (s->tape.size() < want) {
       s->tape.push_back(TapeStep{});
       alloc_tape_entry(s, s->tape.back());
@@ -1482,12 +1528,33 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     dh::launch_fill(s->st, reinterpret_cast<float*>(s->param_steps), 0.0f,
                     4LL * S * s->param_cap);
     for (int g = nseg - 1; g >= 0; --g) {
-      load_ckpt(s, s->ckpts[g]);
       const int s0 = g * K, s1 = std::min(nsteps, s0 + K);
+      if (s1 <= s->taped) {
+        // recorded by the forward: x1 and phi1 of a step are the next step's x0 and phi0,
+        // or, after the recorded steps, those of the next checkpoint or the final state
+        for (int k = s1 - 1; k >= s0; --k) {
+          TapeStep& T = s->ftape[k];
+          if (k + 1 < s->taped) {
+            T.x1 = s->ftape[k + 1].x0;
+            T.phi1 = s->ftape[k + 1].phi0;
+          } else if (k + 1 == nsteps) {
+            T.x1 = s->keep.pos;
+            T.phi1 = s->keep.phi;
+          } else {
+            T.x1 = s->ckpts[(k + 1) / K].pos;
+            T.phi1 = s->ckpts[(k + 1) / K].phi;
+          }
+          step_vjp(s, T, k > s0);
+        }
+        continue;
+      }
+      load_ckpt(s, s->ckpts[g]);
       // the recomputed trajectory is the forward's bit for bit (the forward also deferred
       // its kicks and applied them before each checkpoint); the momenta after the last
       // step of the segment are not needed, so its pending kick is dropped
-      for (int k = s0; k < s1; ++k) do_step(s, s->fwd_plans[k], &s->tape[k - s0], true, k);
+      for (int k = s0; k < s1; ++k)
+        do_step(s, s->fwd_plans[k], &s->tape[k - s0], true,
+                k >= s->tape_limit ? k - s->tape_limit : -1, true);
       drop_kick(s);
       for (int k = s1 - 1; k >= s0; --k) {
         TapeStep& T = s->tape[k - s0];
@@ -1496,7 +1563,7 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
         step_vjp(s, T, k > s0);
       }
     }
-    if (nsteps > 0) finish_first_kick(s, s->tape[0]);
+    if (nsteps > 0) finish_first_kick(s, s->taped > 0 ? s->ftape[0] : s->tape[0]);
     ic_vjp(s, d_grad_white);
     // restore the final state of the forward run
     unstash_state(s);

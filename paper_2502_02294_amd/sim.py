@@ -217,6 +217,12 @@ class Sim:
         """Cap on forward steps whose sort and potential are kept for backward (-1: memory)."""
         self._check(lib().dh_set_store_limit(self._h, int(max_steps)))
 
+    def store_info(self):
+        """(steps on the last forward's own tape, further steps with a kept sort)."""
+        t, k = ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib().dh_get_store_info(self._h, ctypes.byref(t), ctypes.byref(k)))
+        return t.value, k.value
+
     def forward(self, white, a_final):
         self._stream()
         k = ctypes.c_int32()

@@ -140,15 +140,16 @@ def test_batch_gradient_equals_single_runs(dhp):
 
 @pytest.mark.parametrize("S", [1, 3])
 def test_reverse_pass_with_and_without_stored_steps(dhp, S):
-    """The forward keeps each step's particle sort and potential for the reverse pass (as
-    memory allows); the recomputation takes them instead of computing them again.  All,
-    some or none kept: the same gradients bit for bit (with S = 3 the samples end after
-    different numbers of steps)."""
+    """The forward keeps data for the reverse pass as memory allows: the full tape of whole
+    checkpoint segments (no recomputation there), then the particle sort and potential of
+    further steps (their recomputation takes them).  Everything taped (-1), nothing (0), two
+    steps' sorts (2), one taped segment of three steps and one step's sort (4): the same
+    gradients bit for bit (with S = 3 the samples end after different numbers of steps)."""
     n, box = 16, 4.0
     white = np.stack([si.white_noise(n, seed=90 + i) for i in range(S)])
     target = (0.2 + 0.7 * np.random.default_rng(5).random((S, n, n, n))).astype(np.float32)
     outs = []
-    for limit in (-1, 0, 2):
+    for limit in (-1, 0, 2, 4):
         print(f"reverse pass, S = {S}, store limit {limit}", flush=True)
         if S == 1:
             b = _single(dhp, n, box, 0, a_init=0.05, ckpt_every=3)
