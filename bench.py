@@ -242,25 +242,25 @@ def batch_comparison(torch, dhp, si, samples):
     b.close()
     log(f"bench: batch of {samples}: {k} lockstep steps, per-sample {min(steps)}..{max(steps)}, "
         f"fwd+bwd {t_batch:.2f} s")
-    # the same samples one at a time
+    # the same samples one at a time, each after an untimed pass of its own (as the batch:
+    # the device buffers of a handle are allocated by its first pass)
     t_seq = 0.0
     seq_steps = []
-    for i in range(-1, samples):               # i = -1: untimed warm-up of sample 0
-        j = max(i, 0)
+    for i in range(samples):
         s = dhp.Sim(dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=2, ckpt_every=K,
-                                       sf_seed=102 + j),
-                    dhp.default_params(eps_sf=float(eps[j]), delta_c=float(dcs[j])))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.forward(white[j].contiguous(), a_final)
-        s.loss(target[j].contiguous())
-        s.backward()
-        torch.cuda.synchronize()
-        if i >= 0:
-            t_seq += time.perf_counter() - t0
-            seq_steps.append(len(s.get_schedule()))
-            if i % 8 == 7:
-                log(f"bench: sequential samples {i + 1}/{samples}, {t_seq:.2f} s")
+                                       sf_seed=102 + i),
+                    dhp.default_params(eps_sf=float(eps[i]), delta_c=float(dcs[i])))
+        for timed in (False, True):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.forward(white[i].contiguous(), a_final)
+            s.loss(target[i].contiguous())
+            s.backward()
+            torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        seq_steps.append(len(s.get_schedule()))
+        if i % 8 == 7:
+            log(f"bench: sequential samples {i + 1}/{samples}, {t_seq:.2f} s")
         s.close()
     assert seq_steps == steps
     log(f"bench: the same {samples} samples one after another: {t_seq:.2f} s")
