@@ -28,8 +28,8 @@ Modules
   sim        configuration, state, the full time step, run-to-scale-factor and the loss
   riemann    exact Riemann solver for the Sod shock tube (test reference, Toro's method)
 
-Every reading of a passage the paper leaves open is listed in DESIGN.md with its reason;
-the functions cite the section or equation they follow.
+Where the paper leaves a passage open, the function that takes a reading of it says so in
+its docstring; the functions cite the section or equation they follow.
 """
 
 from . import cosmology, philox, hydro, gravity, subgrid, ics, sim, riemann  # noqa: F401

@@ -6,8 +6,9 @@ Particle variables are the comoving position x [cells] and p = a u, so dx/dt = p
 dp/dt = g.  The peculiar potential obeys lap(phi) = (3 Om / 2a) delta_m, delta_m the total
 (gas + dark matter) overdensity with mean matter density 1 per cell.
 
-Mesh conventions (readings listed in the design doc): the mesh is the gas grid; CIC uses cell
-centres, i0 = floor(x - 1/2), w1 = x - 1/2 - i0; the same weights deposit and read out;
+Mesh conventions (readings of Sec. 2.2, which names CIC and an FFT Poisson solve only): the
+mesh is the gas grid; CIC uses cell centres, i0 = floor(x - 1/2), w1 = x - 1/2 - i0; the
+same weights deposit and read out;
 the Green's function is -1/k^2 with continuous k = 2 pi n / N, k = 0 set to zero; no CIC
 deconvolution; g on the mesh by the two-point central difference.
 """

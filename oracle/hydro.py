@@ -9,7 +9,8 @@ Fluxes along direction d (eq. cont, eq. momentum, eq. ev with gamma = 5/3):
     F_mj  = rho U_d U_j + p delta_jd        (pressure in the momentum flux: conservative form)
     F_E   = a U_d (rho E + p)
 The internal-energy source S_e is not applied: the energy variable is the total energy,
-whose flux already carries the pdV work (reading listed in the design doc).
+whose flux already carries the pdV work (a reading: the paper lists S_e beside a total-
+energy equation whose flux has the pressure work).
 
 Units: length in cells (Delta x = 1), time in 1/H0, velocity in cells*H0.
 Arrays are indexed [component, z, y, x] (x fastest); axis d = 0, 1, 2 means x, y, z.
@@ -61,7 +62,7 @@ def van_leer(x, y, eps=LIMITER_EPS):
 
     phi(x, y) = (x y + |x y|) / (x + y + eps sgn(x+y)), sgn(0) = +1: equal to
     2xy/(x+y+eps sgn) when x and y share a sign and 0 otherwise, so it is never 0/0
-    (reading listed in the design doc)."""
+    (a reading: the paper's form 2xy/(x+y+eps) leaves opposite signs and x + y < 0 open)."""
     s = x + y
     sg = torch.where(s >= 0, torch.ones_like(s), -torch.ones_like(s))
     xy = x * y

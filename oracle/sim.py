@@ -1,6 +1,7 @@
 """Configuration, state and the full time step of the oracle.
 
-One step from t_n to t_n + dt (operator order; readings listed in the design doc):
+One step from t_n to t_n + dt (operator order; the order of the kicks, drift, sweeps and
+source is a reading of Sec. 2.2-2.4, which state the operators but not one sequence):
   1. dt from the CFL condition (eq. dt) and a cap on dln a, or the next entry of a given
      schedule (a predefined schedule is what the paper differentiates through, Sec. 2.3.3);
   2. opening half kicks with g_n = -grad(phi_n): gas (source S_g) and dark matter;
