@@ -619,45 +619,46 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
 #pragma unroll
     for (int k = 0; k < 5; ++k) stage[wave][lane][k] = valid ? xin[k] : 0.0f;
     __syncthreads();
-    mlp::f4 o[4];
-    mlp::forward<4>(fr, bias, stage_operands<4>(stage[wave], lane), o, nullptr, nullptr, lane);
-    if (g == 0) {
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        stage[wave][16 * ct + cl][5] = o[ct][0];
-        stage[wave][16 * ct + cl][6] = o[ct][1];
-      }
-    }
-    __syncthreads();
-    // dL/do of this cell
-    double le = 0.0, z = 0.0, go0 = 0.0, go1 = 0.0;
-    if (valid) {
-      const float o0 = stage[wave][lane][5], o1 = stage[wave][lane][6];
-      const float lg = closure_logit_estimate(o0, o1, a);
-      const double u = screened_out(lg, kMaxLogitU, a) ? 0.5 : starform_uniform(c, a);
-      le = lam[4 * nc + c];
-      if (!screened_out(lg, kMaxLogitU, a) && !screened_out(lg, logit_u_of(u), a)) {
-        const ClosureDraw d = closure_draw(o0, o1, u, a);
-        z = d.z;
-        if (a.mode != 1 && le != 0.0) {
-          const double dz = d.z * (1.0 - d.z) / a.tau / (1.0 - d.pi0);   // dz / dln(pi0)
-          const double coef = le * K * q5[0] * dz;
-          go0 = coef * d.x / expm1(d.x);                // dln p_sf / do0
-          go1 = o1 < 0.0f ? coef : 0.0;                  // dln gate / do1
-        }
-      }
-    }
-    __syncthreads();
-    stage[wave][lane][5] = static_cast<float>(go0);
-    stage[wave][lane][6] = static_cast<float>(go1);
-    __syncthreads();
-    // backward in two halves of 32 cells (the forward is recomputed with its derivatives)
+    // per half of 32 cells: the forward with its derivatives, dL/do of those cells (their
+    // lanes), the backward; the network runs forward once per cell
+    double le = 0.0, z = 0.0;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const float (*sh)[kStage] = stage[wave] + 32 * half;
       mlp::f4 oh[2], go[2], dx[2];
       mlp::Act<2> sd[3];
       mlp::forward<2>(fr, bias, stage_operands<2>(sh, lane), oh, sd, nullptr, lane);
+      if (g == 0) {
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          stage[wave][32 * half + 16 * ct + cl][5] = oh[ct][0];
+          stage[wave][32 * half + 16 * ct + cl][6] = oh[ct][1];
+        }
+      }
+      __syncthreads();
+      if ((lane >> 5) == half) {
+        // dL/do of this lane's cell; the lane reads and then overwrites its own slots
+        double go0 = 0.0, go1 = 0.0;
+        if (valid) {
+          const float o0 = stage[wave][lane][5], o1 = stage[wave][lane][6];
+          const float lg = closure_logit_estimate(o0, o1, a);
+          const double u = screened_out(lg, kMaxLogitU, a) ? 0.5 : starform_uniform(c, a);
+          le = lam[4 * nc + c];
+          if (!screened_out(lg, kMaxLogitU, a) && !screened_out(lg, logit_u_of(u), a)) {
+            const ClosureDraw d = closure_draw(o0, o1, u, a);
+            z = d.z;
+            if (a.mode != 1 && le != 0.0) {
+              const double dz = d.z * (1.0 - d.z) / a.tau / (1.0 - d.pi0);   // dz / dln(pi0)
+              const double coef = le * K * q5[0] * dz;
+              go0 = coef * d.x / expm1(d.x);                // dln p_sf / do0
+              go1 = o1 < 0.0f ? coef : 0.0;                  // dln gate / do1
+            }
+          }
+        }
+        stage[wave][lane][5] = static_cast<float>(go0);
+        stage[wave][lane][6] = static_cast<float>(go1);
+      }
+      __syncthreads();
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
         go[ct] = mlp::f4{0.0f, 0.0f, 0.0f, 0.0f};
