@@ -163,6 +163,9 @@ def test_reverse_pass_with_and_without_stored_steps(dhp, S):
         t = to_gpu(target if S > 1 else target[0])
         k = b.forward(w, 0.08)
         assert k >= 4, k   # two checkpoint segments or more
+        # what the forward kept: whole segments of 3 steps taped first, then sorts
+        expect = {-1: (k, 0), 0: (0, 0), 2: (0, 2), 4: (3, 1)}[limit]
+        assert b.store_info() == expect, (limit, b.store_info())
         b.loss(t)
         gw, gp = b.backward()
         outs.append((gw.clone(), gp, b.get("q").clone()))
