@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -443,7 +444,7 @@ bool keep_step(dh_sim* s, int k) {
     for (int i = 0; i < 4; ++i) {
       if (hipMalloc(&p[i], bytes[i]) != hipSuccess) {
         (void)hipGetLastError();
-        for (int j = 0; j < i; ++j) (void)hipFree(p[j]);
+        for (int j = 0; j < i; ++j) s->release(p[j]);
         s->store_limit = k;
         return false;
       }
@@ -762,6 +763,20 @@ void alloc_tape_entry(dh_sim* s, TapeStep& t) {
   t.start = s->alloc<uint32_t>(s->nc * S + 1);
   t.sorted = s->alloc<uint32_t>(s->np * S);
   t.spos = s->alloc<float4>(s->np * S);
+}
+
+// alloc_tape_entry that gives the memory back and returns false when it is not there
+bool try_alloc_tape_entry(dh_sim* s, TapeStep& t) {
+  const size_t mark = s->allocs.size();
+  try {
+    alloc_tape_entry(s, t);
+    return true;
+  } catch (const std::bad_alloc&) {
+    (void)hipGetLastError();
+    while (s->allocs.size() > mark) s->release(s->allocs.back());
+    t = TapeStep{};
+    return false;
+  }
 }
 
 void save_ckpt(dh_sim* s, Ckpt& c) {
@@ -1399,12 +1414,21 @@ int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_
         return rc;
       }
       if (!any) break;
+      if (count < s->tape_limit && count % K == 0) {
+        // a segment's tape entries at its start; if the memory is not there after all, this
+        // segment and the following ones take checkpoints instead
+        const int need = std::min(count + K, s->tape_limit);
+        while (static_cast<int>(s->ftape.size()) < need) {
+          s->ftape.push_back(TapeStep{});
+          if (!try_alloc_tape_entry(s, s->ftape.back())) {
+            s->ftape.pop_back();
+            s->tape_limit = count;
+            break;
+          }
+        }
+      }
       if (count < s->tape_limit) {
         // recorded into the forward's own tape (no checkpoint needed for these segments)
-        while (static_cast<int>(s->ftape.size()) <= count) {
-          s->ftape.push_back(TapeStep{});
-          alloc_tape_entry(s, s->ftape.back());
-        }
         take_step(s, sp, true, -1, &s->ftape[count]);
         s->taped = count + 1;
       } else {
