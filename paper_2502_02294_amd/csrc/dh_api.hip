@@ -554,11 +554,12 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
   }
   const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
   if (tp) {
-    // the kick, the sweeps and the closing pass write their results straight into the tape
-    dh::launch_gas_kick(s->st, tp->q[0], tp->q[1], s->g4, b);
+    // the sweeps (the first one also applies the opening gas kick and keeps the kicked state
+    // in Q1) and the closing pass write their results straight into the tape
     dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, nullptr,
                           prev, b);
-    for (int k = 0; k < 3; ++k) dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
+    dh::launch_sweep(s->st, tp->q[0], tp->q[2], b, sp.axes[0], s->g4, tp->q[1]);
+    for (int k = 1; k < 3; ++k) dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
     if (recompute && store_k >= 0 && store_k < s->store_valid) {
       // the forward kept this step's sort and potential: no sort, deposit or Poisson solve
       const StepStore& e = s->store[store_k];
@@ -585,13 +586,13 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
                           closure ? tp->q[5] : nullptr, s->cfg.gamma,
                           full ? s->cfl_red : nullptr, b, closure);
   } else {
-    // opening half kicks with g_n, drift with a(t + dt/2)
-    dh::launch_gas_kick(s->st, s->q, s->q, s->g4, b);
+    // opening half kicks with g_n (the gas one inside the first sweep), drift with
+    // a(t + dt/2)
     dh::launch_kick_drift(s->st, s->g4, s->pos, s->pos, s->mom, s->bins.key, nullptr, nullptr,
                           prev, b);
     // sweeps in the Strang order of the step (a sample that sits out is copied along)
     for (int k = 0; k < 3; ++k) {
-      dh::launch_sweep(s->st, s->q, s->q2, b, sp.axes[k]);
+      dh::launch_sweep(s->st, s->q, s->q2, b, sp.axes[k], k == 0 ? s->g4 : nullptr);
       std::swap(s->q, s->q2);
     }
     // Poisson at a(t + dt) from gas + DM (keys were written by the drift)

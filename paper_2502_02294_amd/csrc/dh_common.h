@@ -46,6 +46,24 @@ inline unsigned blocks_for(long long work, int threads) {
 __device__ __forceinline__ float rcp_approx(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrt_approx(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Gravity source of the gas over a half kick h (operator split): m' = m + rho g h,
+// Et' = Et + h g . (m + m')/2, so the internal energy is unchanged.  One function for every
+// kernel that applies or recomputes it, with every rounding spelled out (explicit FMAs, no
+// contraction left to the compiler), so they all round alike wherever it is inlined.
+__device__ __forceinline__ void kick_cell(float rho, const float4 g4, float h, float m[3],
+                                          float& et) {
+  const float g[3] = {g4.x, g4.y, g4.z};
+  float de = 0.0f;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float m0 = m[d];
+    const float m1 = fmaf(__fmul_rn(rho, g[d]), h, m0);
+    m[d] = m1;
+    de = fmaf(__fmul_rn(0.5f, __fadd_rn(m0, m1)), g[d], de);
+  }
+  et = fmaf(de, h, et);
+}
+
 struct HydroK {
   float a, ia, ia2;   // scale factor, 1/a, 1/a^2
   float gm1, gg1;     // gamma-1, gamma*(gamma-1)

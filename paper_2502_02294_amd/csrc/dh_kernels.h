@@ -47,7 +47,10 @@ __device__ __forceinline__ bool sample_active(const StepScal* tab, int smp) {
 }
 
 // ---- hydro (k_hydro.hip): one sweep with dt, h1, h2 of the table (tab required)
-void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis);
+// With g4 (the first sweep of a step): the opening gas half kick (the table's h) is applied
+// to each cell as it is loaded, and with `kicked` the kicked state is also stored there.
+void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis,
+                  const float4* g4 = nullptr, float* kicked = nullptr);
 // adjoint of one sweep: lam_in = (dU'/dU)^T lam_out at U = qin (not in place)
 void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
                       const Batch& b, int axis);
@@ -133,9 +136,7 @@ void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* t
                   bool forward_first, bool inverse_after, bool accumulate, const Batch& b);
 
 // ---- pointwise / reductions (k_point.hip)
-// q_out = q_in after the half kick h (q_out may equal q_in)
-void launch_gas_kick(hipStream_t st, const float* q_in, float* q_out, const float4* g4,
-                     const Batch& b);
+// (the opening gas half kick is applied inside the first sweep of a step: launch_sweep)
 void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4, float* lam_q,
                          float* lam_g, const Batch& b);
 // closing pass of a step, from q_in (may equal q) into q: gas half kick with g4, optional

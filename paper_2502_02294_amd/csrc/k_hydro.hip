@@ -63,10 +63,15 @@ __device__ __forceinline__ void face_l_coef(float f0, float fp1, float fp2, floa
 
 // ------------------------------------------------------------------------------- forward x
 // Whole rows in LDS, one cell per thread; the limited stage-2 flux is formed once per face.
+// KICK (the first sweep of a step): the opening gas half kick with g4 and the table's h is
+// applied to each cell as it is loaded, and the kicked state goes to `kicked` if given.
+template <bool KICK>
 __global__ void __launch_bounds__(kRowThreads) sweep_x_kernel(const float* __restrict__ qin,
                                                               float* __restrict__ qout, int n,
                                                               long long nc,
-                                                              const StepScal* __restrict__ tab) {
+                                                              const StepScal* __restrict__ tab,
+                                                              const float4* __restrict__ g4,
+                                                              float* __restrict__ kicked) {
   __shared__ float FR[5][kRowCells];
   __shared__ float FL[5][kRowCells];
   const long long base = static_cast<long long>(blockIdx.x) * kRowCells;
@@ -87,6 +92,17 @@ __global__ void __launch_bounds__(kRowThreads) sweep_x_kernel(const float* __res
   float u[5], fr[5], fl[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) u[c] = qin[c * nc + base + j];
+  if (KICK) {
+    float m[3] = {u[1], u[2], u[3]};
+    kick_cell(u[0], g4[blockIdx.y * nc + base + j], sc.h, m, u[4]);
+    u[1] = m[0];
+    u[2] = m[1];
+    u[3] = m[2];
+    if (kicked) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) kicked[(blockIdx.y * 5 + c) * nc + base + j] = u[c];
+    }
+  }
   split_flux<0>(u, h1, fr, fl);
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
@@ -148,6 +164,11 @@ struct WalkPtr {
   float* __restrict__ o[5];
   unsigned base, stride;   // in bytes
   int n;
+  // opening gas kick on load (first sweep of a step): g of the sample's cells, the half kick,
+  // and where the kicked state goes
+  const char* g4;
+  float* k[5];
+  float h;
   // byte offset of cell k of the column (periodic)
   __device__ __forceinline__ unsigned at(int k) const {
     return base + static_cast<unsigned>(k & (n - 1)) * stride;
@@ -160,18 +181,40 @@ struct WalkPtr {
   }
 };
 
-template <int D, int I, int STAGE>
+// U of cell kk of the column into u, with the opening kick when KICK; KEEP stores the kicked
+// state of every cell the walk loads: a halo cell is also loaded, and stored with the same
+// value, by the walk of the neighbouring segment.  (A store limited to the segment's own
+// cells needs a branch, which splits the visit's code and changes how the compiler fuses the
+// sweep's multiply-adds.)
+template <bool KICK, bool KEEP>
+__device__ __forceinline__ void walk_load(const WalkPtr& p, int kk, float (&u)[5]) {
+  const unsigned off = p.at(kk);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) u[c] = p.ld(c, off);
+  if (KICK) {
+    // the float4 of cell i is at byte 16 i, i.e. 4 times the byte offset of its float
+    const float4 g = *reinterpret_cast<const float4*>(p.g4 + 4ull * off);
+    float m[3] = {u[1], u[2], u[3]};
+    kick_cell(u[0], g, p.h, m, u[4]);
+    u[1] = m[0];
+    u[2] = m[1];
+    u[3] = m[2];
+    if (KEEP) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c)
+        *reinterpret_cast<float*>(reinterpret_cast<char*>(p.k[c]) + off) = u[c];
+    }
+  }
+}
+
+template <int D, int I, int STAGE, bool KICK, bool KEEP>
 __device__ __forceinline__ void walk_fwd_visit(WalkFwd<D>& w, const WalkPtr& p, int k,
                                                const HydroK& h1, const HydroK& h2, float dt,
                                                float hdt) {
   constexpr int s0 = I & 7, s1 = (I + 7) & 7, s3 = (I + 5) & 7, sa = (I + kAhead) & 7;
   constexpr int t0 = I & 3, t1 = (I + 3) & 3, t2 = (I + 2) & 3, t3 = (I + 1) & 3;
   constexpr int p0 = I & 1, p1 = (I + 1) & 1;
-  {
-    const unsigned off = p.at(k + kAhead);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) w.u[sa][c] = p.ld(c, off);
-  }
+  walk_load<KICK, KEEP>(p, k + kAhead, w.u[sa]);
   float l1[5];
   split_flux<D>(w.u[s0], h1, w.r1[p0], l1);
   if (STAGE < 1) return;
@@ -202,11 +245,13 @@ __device__ __forceinline__ void walk_fwd_visit(WalkFwd<D>& w, const WalkPtr& p, 
   for (int c = 0; c < 5; ++c) p.st(c, off, w.u[s3][c] - dt * (w.f2[p0][c] - w.f2[p1][c]));
 }
 
-template <int D>
+template <int D, bool KICK, bool KEEP>
 __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict__ qin,
                                                          float* __restrict__ qout, int n,
                                                          long long nc, int seg_len, int nseg,
-                                                         const StepScal* __restrict__ tab) {
+                                                         const StepScal* __restrict__ tab,
+                                                         const float4* __restrict__ g4,
+                                                         float* __restrict__ kicked) {
   const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<long long>(n) * n * nseg) return;
   const int x = static_cast<int>(t % n);
@@ -223,7 +268,10 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
   for (int c = 0; c < 5; ++c) {
     p.q[c] = qin + (blockIdx.y * 5 + c) * nc;
     p.o[c] = qout + (blockIdx.y * 5 + c) * nc;
+    p.k[c] = KEEP ? kicked + (blockIdx.y * 5 + c) * nc : nullptr;
   }
+  p.g4 = KICK ? reinterpret_cast<const char*>(g4 + blockIdx.y * nc) : nullptr;
+  p.h = sc.h;
   if (!sc.active) {
     for (int i = 0; i < seg_len; ++i) {
       const unsigned off = p.at(s + i);
@@ -237,28 +285,24 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
   const float hdt = 0.5f * dt;
   WalkFwd<D> w;
 #pragma unroll
-  for (int j = 0; j < kAhead; ++j) {
-    const unsigned off = p.at(s - 3 + j);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) w.u[j][c] = p.ld(c, off);
-  }
+  for (int j = 0; j < kAhead; ++j) walk_load<KICK, KEEP>(p, s - 3 + j, w.u[j]);
   // visits 0..5 fill the pipeline; from visit 6 on every visit writes a cell
-  walk_fwd_visit<D, 0, 0>(w, p, s - 3, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 1, 1>(w, p, s - 2, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 2, 2>(w, p, s - 1, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 3, 2>(w, p, s, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 4, 2>(w, p, s + 1, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 5, 3>(w, p, s + 2, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 0, 0, KICK, KEEP>(w, p, s - 3, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 1, 1, KICK, KEEP>(w, p, s - 2, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 2, 2, KICK, KEEP>(w, p, s - 1, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 3, 2, KICK, KEEP>(w, p, s, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 4, 2, KICK, KEEP>(w, p, s + 1, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 5, 3, KICK, KEEP>(w, p, s + 2, h1, h2, dt, hdt);
   // seg_len is a multiple of 8: visits 6 + 8m .. 13 + 8m have ring phases 6, 7, 0, .., 5
   for (int k = s + 3; k < s + 3 + seg_len; k += 8) {
-    walk_fwd_visit<D, 6, 4>(w, p, k, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 7, 4>(w, p, k + 1, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 0, 4>(w, p, k + 2, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 1, 4>(w, p, k + 3, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 2, 4>(w, p, k + 4, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 3, 4>(w, p, k + 5, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 4, 4>(w, p, k + 6, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 5, 4>(w, p, k + 7, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 6, 4, KICK, KEEP>(w, p, k, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 7, 4, KICK, KEEP>(w, p, k + 1, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 0, 4, KICK, KEEP>(w, p, k + 2, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 1, 4, KICK, KEEP>(w, p, k + 3, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 2, 4, KICK, KEEP>(w, p, k + 4, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 3, 4, KICK, KEEP>(w, p, k + 5, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 4, 4, KICK, KEEP>(w, p, k + 6, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 5, 4, KICK, KEEP>(w, p, k + 7, h1, h2, dt, hdt);
   }
 }
 
@@ -581,25 +625,40 @@ int pick_segment(int n) { return n >= 64 ? 64 : n; }
 
 }  // namespace
 
-void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis) {
+void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis,
+                  const float4* g4, float* kicked) {
   const int n = b.n;
   const long long nc = b.nc();
   if (!b.tab) throw ArgError("sweep: step table required");
+  if (kicked && !g4) throw ArgError("sweep: the kicked state needs the kick's field");
+  if (kicked && (kicked == qin || kicked == qout)) throw ArgError("sweep: kicked state aliases");
   if (axis == 0) {
     if (qin == qout) throw ArgError("sweep_x: in-place not supported");
-    hipLaunchKernelGGL(sweep_x_kernel, dim3(static_cast<unsigned>(nc / kRowCells), b.S),
-                       dim3(kRowThreads), 0, st, qin, qout, n, nc, b.tab);
+    const dim3 grid(static_cast<unsigned>(nc / kRowCells), b.S);
+    if (g4)
+      hipLaunchKernelGGL(sweep_x_kernel<true>, grid, dim3(kRowThreads), 0, st, qin, qout, n, nc,
+                         b.tab, g4, kicked);
+    else
+      hipLaunchKernelGGL(sweep_x_kernel<false>, grid, dim3(kRowThreads), 0, st, qin, qout, n, nc,
+                         b.tab, nullptr, nullptr);
   } else {
     const int seg = pick_segment(n);
     const int nseg = n / seg;
     const long long threads = static_cast<long long>(n) * n * nseg;
     const dim3 grid(blocks_for(threads, 256), b.S);
-    if (axis == 1)
-      hipLaunchKernelGGL(sweep_walk_kernel<1>, grid, dim3(256), 0, st, qin, qout, n, nc, seg,
-                         nseg, b.tab);
-    else
-      hipLaunchKernelGGL(sweep_walk_kernel<2>, grid, dim3(256), 0, st, qin, qout, n, nc, seg,
-                         nseg, b.tab);
+#define DH_WALK(D, KICK, KEEP)                                                                 \
+  hipLaunchKernelGGL((sweep_walk_kernel<D, KICK, KEEP>), grid, dim3(256), 0, st, qin, qout, n, \
+                     nc, seg, nseg, b.tab, g4, kicked)
+    if (axis == 1) {
+      if (kicked) DH_WALK(1, true, true);
+      else if (g4) DH_WALK(1, true, false);
+      else DH_WALK(1, false, false);
+    } else {
+      if (kicked) DH_WALK(2, true, true);
+      else if (g4) DH_WALK(2, true, false);
+      else DH_WALK(2, false, false);
+    }
+#undef DH_WALK
   }
   DH_LAUNCH_CHECK();
 }

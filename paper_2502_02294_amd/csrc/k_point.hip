@@ -56,41 +56,7 @@ __device__ __forceinline__ void zero_partials(double* partial) {
 }
 
 // ------------------------------------------------------------------------- gas kick
-// m' = m + rho g h ; Et' = Et + h g . (m + m')/2   (internal energy unchanged)
-__device__ __forceinline__ void kick_cell(float rho, const float4 g4, float h, float m[3],
-                                          float& et) {
-  const float g[3] = {g4.x, g4.y, g4.z};
-  float de = 0.0f;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const float m0 = m[d];
-    const float m1 = m0 + rho * g[d] * h;
-    m[d] = m1;
-    de += 0.5f * (m0 + m1) * g[d];
-  }
-  et += de * h;
-}
-
-__global__ void __launch_bounds__(256) gas_kick_kernel(const float* q_in, float* q,
-                                                       const float4* __restrict__ g4,
-                                                       long long nc,
-                                                       const StepScal* __restrict__ tab) {
-  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const StepScal& sc = tab[blockIdx.y];
-  if (c >= nc || !sc.active) return;
-  const float h = sc.h;
-  q_in += blockIdx.y * 5 * nc;
-  q += blockIdx.y * 5 * nc;
-  g4 += blockIdx.y * nc;
-  float m[3] = {q_in[nc + c], q_in[2 * nc + c], q_in[3 * nc + c]};
-  float et = q_in[4 * nc + c];
-  const float rho = q_in[c];
-  kick_cell(rho, g4[c], h, m, et);
-  if (q != q_in) q[c] = rho;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) q[(1 + d) * nc + c] = m[d];
-  q[4 * nc + c] = et;
-}
+// (kick_cell, the kick of one cell, is shared with the first sweep of a step: dh_common.h)
 
 // adjoint of kick_cell at one cell: l5 (adjoint after the kick) becomes the adjoint before
 // it (the energy component is unchanged); lg = adjoint of g
@@ -911,14 +877,6 @@ __global__ void fill_kernel(float* p, float v, long long count) {
 }
 
 }  // namespace
-
-void launch_gas_kick(hipStream_t st, const float* q_in, float* q_out, const float4* g4,
-                     const Batch& b) {
-  if (!b.tab) throw ArgError("gas kick: step table required");
-  hipLaunchKernelGGL(gas_kick_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st, q_in,
-                     q_out, g4, b.nc(), b.tab);
-  DH_LAUNCH_CHECK();
-}
 
 void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4, float* lam_q,
                          float* lam_g, const Batch& b) {
