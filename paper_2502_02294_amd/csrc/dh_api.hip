@@ -899,7 +899,6 @@ void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
   } else if (fuse_open) {
     dh::launch_source_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, s->red, b, s->open_q0, s->lg2,
                                s->open_tab);
-    dh::launch_grad_vjp(st, s->lg2, nullptr, s->lphi, Batch{s->n, s->S, s->open_tab});
     s->open_pending = false;
   } else {
     dh::launch_source_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, s->red, b);
@@ -913,7 +912,11 @@ void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
   tb.spos = T.vspos;
   dh::launch_gather_sorted(st, tb, s->lp, b);
   dh::launch_deposit_vec(st, tb, true, s->lg, b);
-  dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi2, b);
+  // lambda_phi_{n+1}: with the next step's opening kick taken above, its g adjoint (lg2) first
+  if (fuse_open)
+    dh::launch_grad_vjp2(st, s->lg2, s->lg, s->lphi2, b);
+  else
+    dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi2, b);
   // Poisson (symmetric operator) and deposit at x1
   poisson(s, s->lphi2, s->ldelta, b);
   dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc, 5 * nc, nc, false, b);

@@ -114,6 +114,10 @@ void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long co
 // lam_phi = (adjoint of the central-difference gradient) lam_g + lam_phi_in
 void launch_grad_vjp(hipStream_t st, const float* lam_g, const float* lam_phi_in, float* lam_phi,
                      const Batch& b);
+// lam_phi = the launch above for lam_g0 alone (lam_phi_in null), then for lam_g with that as
+// lam_phi_in, in one pass (the same roundings)
+void launch_grad_vjp2(hipStream_t st, const float* lam_g0, const float* lam_g, float* lam_phi,
+                      const Batch& b);
 
 // ---- FFT and spectral operators (k_fft.hip)
 enum SpecOp { kOpGreen = 0, kOpIcDisp = 1, kOpIcDispT = 2 };

@@ -693,11 +693,15 @@ __global__ void axpy_kernel(float* __restrict__ y, const float* __restrict__ x, 
   y[blockIdx.y * ys + i] = fmaf(f, x[blockIdx.y * xs + i], y[blockIdx.y * ys + i]);
 }
 
-// lam_phi[c] = lam_phi_in[c] + sum_d (lam_g_d[c + e_d] - lam_g_d[c - e_d]) / 2
+// lam_phi[c] = lam_phi_in[c] + sum_d (lam_g_d[c + e_d] - lam_g_d[c - e_d]) / 2.
+// FIRST: the terms of a first field lam_g0 come before those of lam_g, starting from 0 (the
+// value the launch for lam_g0 alone would have passed in as lam_phi_in, rounded alike).
+template <bool FIRST>
 __global__ void __launch_bounds__(256) grad_vjp_kernel(const float* __restrict__ lam_g,
                                                        const float* __restrict__ lam_phi_in,
                                                        float* __restrict__ lam_phi, int n, int lgn,
-                                                       const StepScal* __restrict__ tab) {
+                                                       const StepScal* __restrict__ tab,
+                                                       const float* __restrict__ lam_g0) {
   const unsigned c = blockIdx.x * blockDim.x + threadIdx.x;
   const unsigned nc = 1u << (3 * lgn);
   if (c >= nc || !sample_active(tab, blockIdx.y)) return;
@@ -710,6 +714,15 @@ __global__ void __launch_bounds__(256) grad_vjp_kernel(const float* __restrict__
   const float* ly = lam_g + nc;
   const float* lz = lam_g + 2 * static_cast<long long>(nc);
   float v = lam_phi_in ? lam_phi_in[c] : 0.0f;
+  if (FIRST) {
+    lam_g0 += static_cast<long long>(blockIdx.y) * 3 * nc;
+    const float* mx = lam_g0;
+    const float* my = lam_g0 + nc;
+    const float* mz = lam_g0 + 2 * static_cast<long long>(nc);
+    v += 0.5f * (mx[gi.at(ix + 1, iy, iz)] - mx[gi.at(ix - 1, iy, iz)]);
+    v += 0.5f * (my[gi.at(ix, iy + 1, iz)] - my[gi.at(ix, iy - 1, iz)]);
+    v += 0.5f * (mz[gi.at(ix, iy, iz + 1)] - mz[gi.at(ix, iy, iz - 1)]);
+  }
   v += 0.5f * (lx[gi.at(ix + 1, iy, iz)] - lx[gi.at(ix - 1, iy, iz)]);
   v += 0.5f * (ly[gi.at(ix, iy + 1, iz)] - ly[gi.at(ix, iy - 1, iz)]);
   v += 0.5f * (lz[gi.at(ix, iy, iz + 1)] - lz[gi.at(ix, iy, iz - 1)]);
@@ -867,8 +880,15 @@ void launch_axpy(hipStream_t st, float* y, const float* x, float a, long long co
 
 void launch_grad_vjp(hipStream_t st, const float* lam_g, const float* lam_phi_in, float* lam_phi,
                      const Batch& b) {
-  hipLaunchKernelGGL(grad_vjp_kernel, per_sample(b.nc(), b), dim3(256), 0, st, lam_g, lam_phi_in,
-                     lam_phi, b.n, log2_ll(b.n), b.tab);
+  hipLaunchKernelGGL(grad_vjp_kernel<false>, per_sample(b.nc(), b), dim3(256), 0, st, lam_g,
+                     lam_phi_in, lam_phi, b.n, log2_ll(b.n), b.tab, nullptr);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_grad_vjp2(hipStream_t st, const float* lam_g0, const float* lam_g, float* lam_phi,
+                      const Batch& b) {
+  hipLaunchKernelGGL(grad_vjp_kernel<true>, per_sample(b.nc(), b), dim3(256), 0, st, lam_g,
+                     nullptr, lam_phi, b.n, log2_ll(b.n), b.tab, lam_g0);
   DH_LAUNCH_CHECK();
 }
 
