@@ -51,7 +51,8 @@ enum {
     DH_E_OOM = -2,        /* device or host allocation failed */
     DH_E_HIP = -3,        /* a HIP runtime call failed */
     DH_E_NONFINITE = -4,  /* non-finite or non-positive density found in the state */
-    DH_E_SCHEDULE = -5,   /* a replayed schedule is exhausted or violates the dt rule */
+    DH_E_SCHEDULE = -5,   /* a replayed schedule entry is not a positive finite dt, or a
+                             replayed step exceeds the Courant number cfg.cfl_forward */
     DH_E_STATE = -6       /* call out of order (e.g. backward before forward) */
 };
 
@@ -81,6 +82,9 @@ typedef struct dh_config {
     int32_t ckpt_every;  /* checkpoint interval in steps for dh_forward/dh_backward (>=1)  */
     int32_t closure;     /* DH_CLOSURE_*; MLP needs subgrid != OFF and dh_set_closure()    */
     int32_t batch;       /* samples in the handle (>= 1); n^3 * batch <= 2^31              */
+    double cfl_forward;  /* largest Courant number a replayed step may reach on the state it
+                            is applied to (C_forward of Sec. 2.3.3; default 1.5 cfl); 0: no
+                            check                                                         */
 } dh_config;
 
 /* Model parameters (double).  A, beta: flux observable F = exp(-A Delta^beta) of the loss;
@@ -142,7 +146,17 @@ int dh_run_steps(dh_sim* sim, int32_t nsteps, int32_t* nsteps_out);
 
 /* Predefined schedule (Sec. 2.3.3).  set: the next steps take dts[0..n) in order (then the
  * CFL again); n = 0 clears it.  get: the dt of every step since the last init, at most
- * cap values, total count in *n_out. */
+ * cap values, total count in *n_out.
+ * A replayed entry is clipped, like a CFL step, so as not to pass the end of a dh_run_to or
+ * dh_forward.  Accuracy check of a replay (Sec. 2.3.3): a schedule recorded on a fiducial
+ * run at Courant number C_fid = cfg.cfl is valid for another run as long as each replayed
+ * dt_fid stays within C_forward / C_fid of the step dt_sol = C_fid / v that eq. dt gives on
+ * that run's own state (v = max over cells and axes of (|U_d| + c_s)/a), i.e. dt_fid v <=
+ * C_forward.  (The paper prints the ratio the other way up, C_fid / C_forward < 1, which a
+ * replay of the fiducial run on itself, ratio 1, would already violate.)  The calls that
+ * take steps check every replayed step of the call against cfg.cfl_forward and return
+ * DH_E_SCHEDULE when one exceeds it; the steps are still taken (the state is that of the
+ * whole call), and a dh_forward that fails the check cannot be followed by dh_backward. */
 int dh_set_schedule(dh_sim* sim, const double* dts, int32_t n);
 int dh_get_schedule(const dh_sim* sim, double* dts, int32_t cap, int32_t* n_out);
 /* The same for one sample of a batch (dh_set_schedule sets every sample's; dh_get_schedule

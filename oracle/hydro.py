@@ -40,43 +40,72 @@ def primitives(q, a, gamma, e_floor):
     return u, p, cs
 
 
-def flux_and_speed(q, a, d, gamma, e_floor):
+def flux_and_speed(q, a, d, gamma, e_floor, sign_ud=None):
     """Cell-centred flux F along d and the freezing speed c = (|U_d| + c_s)/a (Sec. 2.3.1).
 
     The 1/a in c is the comoving signal speed in cells per unit time: the continuity flux is
-    rho U/a, so the characteristic speeds of this system are (U_d +- c_s)/a."""
+    rho U/a, so the characteristic speeds of this system are (U_d +- c_s)/a.
+    sign_ud (optional, +-1 per cell) fixes the side of the kink of |U_d| (|U_d| = sign U_d);
+    only derivative checks at a kink use it."""
     rho = q[0]
     u, p, cs = primitives(q, a, gamma, e_floor)
     ud = u[d]
     mom = [rho * ud * u[j] + (p if j == d else 0.0) for j in range(3)]
     f = torch.stack([rho * ud / a] + mom + [a * ud * (q[4] / (a * a) + p)])
-    c = (ud.abs() + cs) / a
+    c = ((ud.abs() if sign_ud is None else sign_ud * ud) + cs) / a
     return f, c
 
 
 LIMITER_EPS = 1e-20
 
 
-def van_leer(x, y, eps=LIMITER_EPS):
+def van_leer(x, y, eps=LIMITER_EPS, take=None):
     """Harmonic-mean (van Leer) flux limiter with a small guard epsilon (Sec. 2.3.2).
 
     phi(x, y) = (x y + |x y|) / (x + y + eps sgn(x+y)), sgn(0) = +1: equal to
     2xy/(x+y+eps sgn) when x and y share a sign and 0 otherwise, so it is never 0/0
-    (a reading: the paper's form 2xy/(x+y+eps) leaves opposite signs and x + y < 0 open)."""
+    (a reading: the paper's form 2xy/(x+y+eps) leaves opposite signs and x + y < 0 open).
+    take (optional boolean per element) fixes the branch, 2xy/(x+y+eps sgn) where true and
+    0 where false, in place of the test x y > 0; only derivative checks at the kink x y = 0
+    use it."""
     s = x + y
     sg = torch.where(s >= 0, torch.ones_like(s), -torch.ones_like(s))
     xy = x * y
-    return (xy + xy.abs()) / (s + eps * sg)
+    if take is None:
+        return (xy + xy.abs()) / (s + eps * sg)
+    return torch.where(take, 2.0 * xy / (s + eps * sg), torch.zeros_like(xy))
 
 
-def split_fluxes(q, a, d, gamma, e_floor):
+def split_fluxes(q, a, d, gamma, e_floor, sign_ud=None):
     """Right- and left-moving fluxes F^R = c Q^R, F^L = c Q^L of the relaxation system with
     Q^R = (Q + F/c)/2 and Q^L = (Q - F/c)/2, so that F = F^R - F^L (Sec. 2.3.1)."""
-    f, c = flux_and_speed(q, a, d, gamma, e_floor)
+    f, c = flux_and_speed(q, a, d, gamma, e_floor, sign_ud)
     return 0.5 * (c * q + f), 0.5 * (c * q - f)
 
 
-def sweep(q, d, dt, a_stage1, a_stage2, gamma, e_floor, eps=LIMITER_EPS):
+def sweep_kinks(q, d, dt, a_stage1, a_stage2, gamma, e_floor):
+    """The quantities whose signs decide the non-smooth choices of sweep(): U_d at each
+    stage (the kink of |U_d|) and the two slopes of every limited face and component,
+    right-moving (x_r, y_r) and left-moving (x_l, y_l).  Returned as a dict of tensors, with
+    the scale each is compared against (for telling which lie within rounding of a kink)."""
+    with torch.no_grad():
+        u1 = primitives(q, a_stage1, gamma, e_floor)[0][d]
+        fr, fl = split_fluxes(q, a_stage1, d, gamma, e_floor)
+        f1 = fr - shift(fl, d, 1)
+        qh = q - 0.5 * dt * (f1 - shift(f1, d, -1))
+        u2 = primitives(qh, a_stage2, gamma, e_floor)[0][d]
+        fr, fl = split_fluxes(qh, a_stage2, d, gamma, e_floor)
+        fr_m1, fr_p1 = shift(fr, d, -1), shift(fr, d, 1)
+        fl_p1, fl_p2 = shift(fl, d, 1), shift(fl, d, 2)
+        return {"u1": (u1, primitives(q, a_stage1, gamma, e_floor)[0].abs().sum(0)),
+                "u2": (u2, primitives(qh, a_stage2, gamma, e_floor)[0].abs().sum(0)),
+                "x_r": (fr - fr_m1, fr.abs() + fr_m1.abs()),
+                "y_r": (fr_p1 - fr, fr_p1.abs() + fr.abs()),
+                "x_l": (fl_p1 - fl, fl_p1.abs() + fl.abs()),
+                "y_l": (fl_p2 - fl_p1, fl_p2.abs() + fl_p1.abs())}
+
+
+def sweep(q, d, dt, a_stage1, a_stage2, gamma, e_floor, eps=LIMITER_EPS, branches=None):
     """One dimensional relaxing-TVD sweep of the whole grid along axis d over a full dt.
 
     Stage 1 (eq. TVD_halfstep): first-order upwind interface fluxes
@@ -87,16 +116,24 @@ def sweep(q, d, dt, a_stage1, a_stage2, gamma, e_floor, eps=LIMITER_EPS):
         F^L_{n+1/2} = F^L_{n+1} - phi((F^L_{n+1} - F^L_n)/2, (F^L_{n+2} - F^L_{n+1})/2)
     and Q^{new}_n = Q_n - dt (F_{n+1/2} - F_{n-1/2}).  The freezing speed is recomputed at
     each stage; stage 1 uses a(t_n), stage 2 a(t_n + dt/2).
+
+    branches (optional, for derivative checks at the kinks only): a dict that fixes the
+    side of each non-smooth choice instead of deciding it from the values, with entries
+    "sign1", "sign2" (the sign taken for |U_d| at each stage, +-1 per cell) and "take_r",
+    "take_l" (the limiter branch of each face and component of the right- and left-moving
+    waves, see van_leer).  Missing entries are decided from the values as usual.
     """
-    fr, fl = split_fluxes(q, a_stage1, d, gamma, e_floor)
+    br = branches or {}
+    fr, fl = split_fluxes(q, a_stage1, d, gamma, e_floor, br.get("sign1"))
     f1 = fr - shift(fl, d, 1)
     qh = q - 0.5 * dt * (f1 - shift(f1, d, -1))
 
-    fr, fl = split_fluxes(qh, a_stage2, d, gamma, e_floor)
+    fr, fl = split_fluxes(qh, a_stage2, d, gamma, e_floor, br.get("sign2"))
     fr_m1, fr_p1 = shift(fr, d, -1), shift(fr, d, 1)
     fl_p1, fl_p2 = shift(fl, d, 1), shift(fl, d, 2)
-    fr_face = fr + van_leer(0.5 * (fr - fr_m1), 0.5 * (fr_p1 - fr), eps)
-    fl_face = fl_p1 - van_leer(0.5 * (fl_p1 - fl), 0.5 * (fl_p2 - fl_p1), eps)
+    fr_face = fr + van_leer(0.5 * (fr - fr_m1), 0.5 * (fr_p1 - fr), eps, br.get("take_r"))
+    fl_face = fl_p1 - van_leer(0.5 * (fl_p1 - fl), 0.5 * (fl_p2 - fl_p1), eps,
+                               br.get("take_l"))
     f2 = fr_face - fl_face
     return q - dt * (f2 - shift(f2, d, -1))
 

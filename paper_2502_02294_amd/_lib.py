@@ -28,7 +28,7 @@ class Config(ctypes.Structure):
                 ("dlna_max", ctypes.c_double), ("t_floor", ctypes.c_double),
                 ("subgrid", ctypes.c_int32), ("tau", ctypes.c_double), ("sf_seed", ctypes.c_uint64),
                 ("ckpt_every", ctypes.c_int32), ("closure", ctypes.c_int32),
-                ("batch", ctypes.c_int32)]
+                ("batch", ctypes.c_int32), ("cfl_forward", ctypes.c_double)]
 
 
 class Params(ctypes.Structure):

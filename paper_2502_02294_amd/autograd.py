@@ -12,6 +12,8 @@ class DiffHydroFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, white, theta, sim, a_final):
+        if sim.S != 1:
+            raise ValueError("DiffHydroFn takes a single-sample handle (config.batch = 1)")
         eps_sf, delta_c = [float(v) for v in theta.detach().cpu()]
         sim.set_params(eps_sf=eps_sf, delta_c=delta_c)
         sim.forward(white.detach().contiguous(), float(a_final))

@@ -40,6 +40,7 @@ constexpr double kProtonMass = 1.67262192369e-27;  // kg
 struct Plan {        // one sample's part of a step
   double t0, dt, a0, ah, a1;
   bool active;
+  bool replayed;     // dt is an entry of a replayed schedule
 };
 
 struct StepPlan {    // one global step of all samples
@@ -130,6 +131,12 @@ struct dh_sim {
 
   // per-step tables: slot k holds the S entries of the k-th step since the last init
   StepScal* tabs = nullptr;
+  // replay check (Sec. 2.3.3): CFL speed of the state each replayed step started from
+  // (device [tab_cap][S]), which (slot, sample) pairs were replayed, and the first slot not
+  // yet checked
+  double* speed_log = nullptr;
+  std::vector<double> replayed;   // [tab_cap][S]: the replayed dt, 0 for a CFL step
+  int checked_slots = 0;
   StepScal* htabs = nullptr;   // pinned mirror
   int tab_cap = 0;
   int nslots = 0;
@@ -289,6 +296,7 @@ void ensure_tab_slots(dh_sim* s, int slots) {
   const int cap = std::max(slots, 2 * s->tab_cap + 64);
   sync(s);
   StepScal* d = s->alloc<StepScal>(static_cast<long long>(cap) * s->S);
+  double* sl = s->alloc<double>(static_cast<long long>(cap) * s->S);
   void* hp = nullptr;
   DH_HIP(hipHostMalloc(&hp, static_cast<size_t>(cap) * s->S * sizeof(StepScal),
                        hipHostMallocDefault));
@@ -296,11 +304,16 @@ void ensure_tab_slots(dh_sim* s, int slots) {
   if (s->tabs) {
     const size_t bytes = static_cast<size_t>(s->tab_cap) * s->S * sizeof(StepScal);
     DH_HIP(hipMemcpy(d, s->tabs, bytes, hipMemcpyDeviceToDevice));
+    DH_HIP(hipMemcpy(sl, s->speed_log, static_cast<size_t>(s->tab_cap) * s->S * sizeof(double),
+                     hipMemcpyDeviceToDevice));
     std::memcpy(h, s->htabs, bytes);
     s->release(s->tabs);
+    s->release(s->speed_log);
     (void)hipHostFree(s->htabs);
   }
   s->tabs = d;
+  s->speed_log = sl;
+  s->replayed.resize(static_cast<size_t>(cap) * s->S, 0.0);
   s->htabs = h;
   s->tab_cap = cap;
 }
@@ -640,6 +653,8 @@ void reset_clock(dh_sim* s) {
   std::fill(s->a.begin(), s->a.end(), ai);
   s->step = 0;
   s->nslots = 0;
+  s->checked_slots = 0;
+  std::fill(s->replayed.begin(), s->replayed.end(), 0.0);
   for (auto& r : s->recorded) r.clear();
   std::fill(s->replay_pos.begin(), s->replay_pos.end(), 0);
 }
@@ -690,10 +705,13 @@ int plan_step(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan& sp, bo
     p.active = false;
     if (t_end > 0.0 && s->t[i] >= t_end * (1.0 - 1e-12)) continue;
     double dt;
+    p.replayed = false;
     if (s->replay_pos[i] < s->replay[i].size()) {
       dt = s->replay[i][s->replay_pos[i]];
       if (!(dt > 0.0) || !std::isfinite(dt))
         return fail(s, DH_E_SCHEDULE, "schedule entry is not a positive finite dt");
+      if (t_end > 0.0 && s->t[i] + dt > t_end) dt = t_end - s->t[i];
+      p.replayed = true;
     } else {
       if (stop_at_replay_end && !s->replay[i].empty()) continue;
       if (!speeds) speeds = &current_speed(s);
@@ -729,11 +747,65 @@ int prepare_step(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan& sp,
   return plan_step(s, t_end, stop_at_replay_end, sp, any);
 }
 
+// CFL speed of the current state of every sample into the speed log of a replayed step's
+// slot (device to device: the run does not wait for it; check_replay reads the log).
+void log_replay_speed(dh_sim* s, const StepPlan& sp) {
+  bool any = false;
+  for (int i = 0; i < s->S; ++i) {
+    const Plan& p = sp.smp[i];
+    s->replayed[static_cast<size_t>(sp.slot) * s->S + i] = p.active && p.replayed ? p.dt : 0.0;
+    any = any || (p.active && p.replayed);
+  }
+  if (!any || !(s->cfg.cfl_forward > 0.0)) return;
+  const int nb = dh::cfl_blocks(s->n);
+  if (!s->cfl_partials) {
+    sync(s);
+    std::memcpy(s->host_out, s->a.data(), s->S * sizeof(double));
+    DH_HIP(hipMemcpyAsync(s->d_acur, s->host_out, s->S * sizeof(double), hipMemcpyHostToDevice,
+                          s->st));
+    dh::launch_cfl_partial(s->st, s->q, s->d_acur, s->cfg.gamma, s->e_floor, s->cfl_red,
+                           batch(s, nullptr));
+    s->cfl_partials = true;
+  }
+  dh::launch_reduce_max(s->st, s->cfl_red, nb, nb, s->S,
+                        s->speed_log + static_cast<size_t>(sp.slot) * s->S);
+}
+
+// Accuracy check of the replayed steps taken since the last check (Sec. 2.3.3): each
+// replayed dt times the CFL speed of the state it was applied to, its Courant number on
+// that state, may not exceed cfg.cfl_forward.
+int check_replay(dh_sim* s) {
+  const int from = s->checked_slots, to = s->nslots;
+  s->checked_slots = to;
+  if (!(s->cfg.cfl_forward > 0.0) || to <= from) return DH_OK;
+  const size_t S = static_cast<size_t>(s->S);
+  bool any = false;
+  for (size_t k = from * S; k < to * S; ++k) any = any || s->replayed[k] > 0.0;
+  if (!any) return DH_OK;
+  std::vector<double> v((to - from) * S);
+  DH_HIP(hipMemcpyAsync(v.data(), s->speed_log + from * S, v.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, s->st));
+  sync(s);
+  for (int k = from; k < to; ++k)
+    for (size_t i = 0; i < S; ++i) {
+      const double dt = s->replayed[k * S + i];
+      if (!(dt > 0.0)) continue;
+      const double c = dt * v[(k - from) * S + i];
+      if (!(c <= s->cfg.cfl_forward * (1.0 + 1e-9)))
+        return fail(s, DH_E_SCHEDULE,
+                    "replayed step " + std::to_string(k) + " of sample " + std::to_string(i) +
+                        " has Courant number " + std::to_string(c) + " > cfl_forward " +
+                        std::to_string(s->cfg.cfl_forward) + " on this run's state");
+    }
+  return DH_OK;
+}
+
 // Takes a planned step (at least one sample moves).
 void take_step(dh_sim* s, StepPlan& sp, bool defer, int store_k = -1,
                TapeStep* tp = nullptr) {
   sp.slot = s->nslots++;
   upload_plan(s, sp);
+  log_replay_speed(s, sp);
   do_step(s, sp, tp, defer, store_k, false);
   commit_plan(s, sp);
 }
@@ -1028,6 +1100,7 @@ void dh_config_default(dh_config* c) {
   c->ckpt_every = 16;
   c->closure = DH_CLOSURE_PLAIN;
   c->batch = 1;
+  c->cfl_forward = 1.5 * c->cfl;
 }
 
 void dh_params_default(dh_params* p) {
@@ -1052,6 +1125,7 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
   if (!(cfg->omega_m > 0 && cfg->omega_m < 1 && cfg->omega_b > 0 && cfg->omega_b < cfg->omega_m &&
         cfg->box > 0 && cfg->a_init > 0 && cfg->a_init < 1 && cfg->cfl > 0 && cfg->dlna_max > 0 &&
         cfg->gamma > 1 && cfg->tau > 0 && cfg->ckpt_every >= 1 && cfg->subgrid >= 0 &&
+        cfg->cfl_forward >= 0 &&
         cfg->subgrid <= 2 && cfg->t_floor > 0 && cfg->t_init > 0 && cfg->sigma8 > 0 &&
         (cfg->closure == DH_CLOSURE_PLAIN ||
          (cfg->closure == DH_CLOSURE_MLP && cfg->subgrid != DH_SUBGRID_OFF))))
@@ -1214,6 +1288,8 @@ int dh_step(dh_sim* s, double* dt_out, double* a_out) {
     int rc = step_once(s, -1.0, false, &sp, &moved, false);
     if (rc) return rc;
     s->have_forward = false;
+    rc = check_replay(s);
+    if (rc) return rc;
     if (!all_finite(current_speed(s)))   // also validates the new state
       return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
     if (dt_out) *dt_out = moved ? sp.smp[0].dt : 0.0;
@@ -1237,7 +1313,8 @@ int dh_run_to(dh_sim* s, double a_final, int32_t* nsteps_out) {
     flush_kick(s);
     s->have_forward = false;
     if (nsteps_out) *nsteps_out = count;
-    return rc;
+    if (rc) return rc;
+    return check_replay(s);
   });
 }
 
@@ -1255,6 +1332,8 @@ int dh_run_steps(dh_sim* s, int32_t nsteps, int32_t* nsteps_out) {
     flush_kick(s);
     s->have_forward = false;
     if (nsteps_out) *nsteps_out = count;
+    if (rc) return rc;
+    rc = check_replay(s);
     if (rc) return rc;
     if (!all_finite(current_speed(s)))   // also validates the new state
       return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
@@ -1403,6 +1482,7 @@ int dh_get_store_info(const dh_sim* s, int32_t* taped, int32_t* sorted) {
 int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_out) {
   if (!s || !d_white || !(a_final > s->cfg.a_init)) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
+    s->have_forward = false;
     initial_conditions(s, d_white);
     const double t_end = s->cosmo.t_of_a(a_final);
     const int K = s->cfg.ckpt_every;
@@ -1448,6 +1528,9 @@ int dh_forward(dh_sim* s, const float* d_white, double a_final, int32_t* nsteps_
       ++count;
     }
     flush_kick(s);
+    if (nsteps_out) *nsteps_out = count;
+    int rc = check_replay(s);
+    if (rc) return rc;
     if (!all_finite(current_speed(s)))
       return fail(s, DH_E_NONFINITE, "state has a non-finite value or a non-positive density");
     s->fwd_steps = count;

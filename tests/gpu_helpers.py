@@ -4,7 +4,7 @@ and the library's float32 buffers, and error measures."""
 import numpy as np
 import torch
 
-from oracle import sim as osim
+from oracle import cosmology, gravity, hydro, ics, sim as osim
 
 
 def rel_l2(a, b):
@@ -61,3 +61,180 @@ def gpu_params(p):
     from paper_2502_02294_amd import default_params
     return default_params(A=p.A, beta=p.beta, eps_sf=p.eps_sf, delta_c=p.delta_c, t_c=p.t_c,
                           e0=p.e0, w_rho=p.w_rho, w_t=p.w_t)
+
+
+def initial_state_fp32_cells(white, ocfg):
+    """The oracle's initial state with the CIC cell of every particle decided on its float32
+    position, as the GPU decides it: the values of x are rounded to float32, the gradient
+    passes through the rounding.  The lattice puts every particle on a CIC kink (a cell
+    centre), so a displacement within float32 rounding of zero picks the neighbouring cell
+    differently in float32 and float64; a 64^3 field has a few such particles, and each moves
+    the exact gradient by ~1e-3."""
+    n = ocfg.n
+    a = ocfg.a_init
+    psi = ics.za_displacement(ics.linear_density(white, ocfg), n)
+    psi_p = psi.reshape(3, -1)
+    x = torch.remainder(ics.lattice(n) + psi_p, float(n))
+    x = x + (round32(x) - x).detach()
+    vfac = a * a * cosmology.hubble_e(a, ocfg.omega_m) * cosmology.growth_rate(a, ocfg.omega_m)
+    p = vfac * psi_p
+    rho = ocfg.f_b * gravity.cic_deposit(x, 1.0, n)
+    mom = rho * (vfac * psi)
+    u = mom / (a * rho)
+    etot = a * a * rho * (ocfg.e_init + 0.5 * (u * u).sum(0))
+    return osim.state_from_qxp(torch.cat([rho[None], mom, etot[None]]), x, p, ocfg)
+
+
+# ---------------------------------------------------------------- sweep adjoint at kinks
+
+def _kink_choices(k, rel):
+    """FP64 decisions of the sweep's non-smooth choices, and those lying within `rel` of
+    their kink: list of (entry, element index)."""
+    u1, su1 = k["u1"]
+    u2, su2 = k["u2"]
+    one = lambda v: torch.where(v >= 0, torch.ones_like(v), -torch.ones_like(v))
+    br = {"sign1": one(u1), "sign2": one(u2),
+          "take_r": k["x_r"][0] * k["y_r"][0] > 0, "take_l": k["x_l"][0] * k["y_l"][0] > 0}
+    amb = []
+    for name, (v, sc) in (("sign1", k["u1"]), ("sign2", k["u2"])):
+        amb += [(name, tuple(i)) for i in (v.abs() <= rel * sc).nonzero().tolist()]
+    for name, xk, yk in (("take_r", "x_r", "y_r"), ("take_l", "x_l", "y_l")):
+        (x, sx), (y, sy) = k[xk], k[yk]
+        m = (x.abs() <= rel * sx) | (y.abs() <= rel * sy)
+        amb += [(name, tuple(i)) for i in m.nonzero().tolist()]
+    return br, amb
+
+
+def _flipped(br, items):
+    out = {key: v.clone() for key, v in br.items()}
+    for name, idx in items:
+        if name.startswith("sign"):
+            out[name][idx] = -out[name][idx]
+        else:
+            out[name][idx] = ~out[name][idx]
+    return out
+
+
+def hydro_kinks(q, axis, dt, a1, a2, gamma, e_floor):
+    return hydro.sweep_kinks(q, axis, dt, a1, a2, gamma, e_floor)
+
+
+def line_of(q, axis, i, j):
+    """The line along `axis` through the two other indices (i, j) (in z, y, x order without
+    the axis) of a [c][z][y][x] field, shaped so that a sweep along the same axis acts on it."""
+    if axis == 0:
+        return q[:, i:i + 1, j:j + 1, :]
+    if axis == 1:
+        return q[:, i:i + 1, :, j:j + 1]
+    return q[:, :, i:i + 1, j:j + 1]
+
+
+def kink_lines(q64, axis, dt, a1, a2, gamma, e_floor, rel=1e-5):
+    """The lines along `axis` (as (i, j) of line_of) holding a non-smooth choice of the sweep
+    within `rel` of its kink."""
+    _, amb = _kink_choices(hydro_kinks(q64, axis, dt, a1, a2, gamma, e_floor), rel)
+    out = set()
+    for _, idx in amb:
+        zyx = list(idx[-3:])
+        del zyx[2 - axis]
+        out.add(tuple(zyx))
+    return sorted(out)
+
+
+def _stack_dim(axis, ndim):
+    """Dimension along which lines along `axis` are stacked (a transverse one) in a tensor of
+    ndim dimensions ending in z, y, x."""
+    return ndim - 2 if axis == 0 else ndim - 1
+
+
+def _batched_vjp(lines_q, lines_lam, lines_br, axis, dt, a1, a2, gamma, e_floor):
+    """Adjoints of one sweep of many independent lines (lists of [5, ...] line tensors and
+    branch dicts), evaluated as one stacked field: a sweep acts on each line on its own."""
+    dq = _stack_dim(axis, 4)
+    q = torch.cat(lines_q, dim=dq).detach().requires_grad_(True)
+    lam = torch.cat(lines_lam, dim=dq)
+    br = {}
+    for key in lines_br[0]:
+        v = lines_br[0][key]
+        br[key] = torch.cat([b[key] for b in lines_br], dim=_stack_dim(axis, v.dim()))
+    y = hydro.sweep(q, axis, dt, a1, a2, gamma, e_floor, branches=br)
+    (g,) = torch.autograd.grad(y, q, lam)
+    return torch.split(g, 1, dim=dq)
+
+
+def sweep_vjp_on_gpu_branches(q, lam, gpu, axis, dt, a1, a2, gamma, e_floor, rel=1e-5,
+                              window=6):
+    """The oracle's adjoint of one sweep (float32 numpy inputs q, lam [5][z][y][x]; a whole
+    field or single lines) with every non-smooth choice that lies within `rel` of its kink
+    (a limiter slope or U_d within rounding of zero, where float32 and float64 may take
+    different sides) set to the side whose exact derivative the GPU's adjoint `gpu` follows.
+    Both sides give exact one-sided derivatives of the sweep; every other choice is the
+    oracle's own.  A sweep acts on each line along `axis` by itself, so only lines holding
+    such a choice are recomputed; on a line, choices within `window` cells of each other are
+    decided together (every combination, on the cells they reach), groups further apart
+    independently.  Returns (adjoint, lines recomputed, choices near a kink)."""
+    q64 = torch.from_numpy(q).double().requires_grad_(True)
+    lam64 = torch.from_numpy(lam).double()
+    y = hydro.sweep(q64, axis, dt, a1, a2, gamma, e_floor)
+    (ref,) = torch.autograd.grad(y, q64, lam64)
+    ref = ref.numpy().copy()
+    qd = torch.from_numpy(q).double()
+    lines = kink_lines(qd, axis, dt, a1, a2, gamma, e_floor, rel)
+    if not lines:
+        return ref, 0, 0
+    pos = lambda item: item[1][-1 - axis]
+    n = q.shape[-1 - axis]
+    gpu = np.asarray(gpu, dtype=np.float64)
+    # per line: base decisions and groups of choices near a kink
+    info = []
+    for i, j in lines:
+        ql = line_of(qd, axis, i, j)
+        br, amb = _kink_choices(hydro_kinks(ql, axis, dt, a1, a2, gamma, e_floor), rel)
+        amb.sort(key=pos)
+        groups, cur = [], [amb[0]]
+        for it in amb[1:]:
+            if pos(it) - pos(cur[-1]) <= window:
+                cur.append(it)
+            else:
+                groups.append(cur)
+                cur = [it]
+        groups.append(cur)
+        if len(groups) > 1 and pos(groups[0][0]) + n - pos(groups[-1][-1]) <= window:
+            groups[0] = groups.pop() + groups[0]   # periodic line: the ends touch
+        for grp in groups:
+            if len(grp) > 10:
+                raise AssertionError(f"{len(grp)} choices near kinks within {window} cells")
+        info.append((ql, line_of(lam64, axis, i, j), line_of(gpu, axis, i, j), br, amb, groups))
+    # every combination of every group, all lines in one stacked evaluation
+    cand = []
+    for li, (ql, ll, gl, br, amb, groups) in enumerate(info):
+        for gi, grp in enumerate(groups):
+            for mask in range(1 << len(grp)):
+                flips = [grp[t] for t in range(len(grp)) if mask >> t & 1]
+                cand.append((li, gi, flips, _flipped(br, flips)))
+    nsel = len(gpu.shape) - 1 - axis
+    best = {}
+    for k0 in range(0, len(cand), 512):
+        chunk = cand[k0:k0 + 512]
+        outs = _batched_vjp([info[c[0]][0] for c in chunk], [info[c[0]][1] for c in chunk],
+                            [c[3] for c in chunk], axis, dt, a1, a2, gamma, e_floor)
+        for (li, gi, flips, _), g in zip(chunk, outs):
+            grp = info[li][5][gi]
+            cells = sorted({(pos(it) + o) % n for it in grp for o in range(-window, window + 1)})
+            sel = [slice(None)] * g.dim()
+            sel[nsel] = cells
+            err = float(np.abs(g.numpy()[tuple(sel)] - info[li][2][tuple(sel)]).max())
+            if (li, gi) not in best or err < best[(li, gi)][0]:
+                best[(li, gi)] = (err, flips)
+    finals = []
+    for li, (ql, ll, gl, br, amb, groups) in enumerate(info):
+        flips = [it for gi in range(len(groups)) for it in best[(li, gi)][1]]
+        finals.append(_flipped(br, flips))
+    total = 0
+    for k0 in range(0, len(info), 512):
+        outs = _batched_vjp([x[0] for x in info[k0:k0 + 512]], [x[1] for x in info[k0:k0 + 512]],
+                            finals[k0:k0 + 512], axis, dt, a1, a2, gamma, e_floor)
+        for (i, j), x, g in zip(lines[k0:k0 + 512], info[k0:k0 + 512], outs):
+            line_of(ref, axis, i, j)[...] = g.numpy()
+            total += len(x[4])
+    return ref, len(lines), total

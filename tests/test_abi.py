@@ -47,12 +47,12 @@ def test_struct_layouts_match_c(tmp_path):
 #include <stddef.h>
 #include "{HEADER}"
 int main(void) {{
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dh_config), sizeof(dh_params),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dh_config), sizeof(dh_params),
          offsetof(dh_config, subgrid), offsetof(dh_config, sf_seed),
          offsetof(dh_config, ckpt_every), offsetof(dh_params, w_t),
          offsetof(dh_config, closure), sizeof(dh_mlp_train_opts),
          offsetof(dh_mlp_train_opts, lr), sizeof(dh_mlp_sample_opts),
-         offsetof(dh_mlp_sample_opts, dc_hi));
+         offsetof(dh_mlp_sample_opts, dc_hi), offsetof(dh_config, cfl_forward));
   return 0;
 }}
 """)
@@ -63,7 +63,7 @@ int main(void) {{
     C, P, T, S = _lib.Config, _lib.Params, _lib.MlpTrainOpts, _lib.MlpSampleOpts
     want = [ctypes.sizeof(C), ctypes.sizeof(P), C.subgrid.offset, C.sf_seed.offset,
             C.ckpt_every.offset, P.w_t.offset, C.closure.offset, ctypes.sizeof(T), T.lr.offset,
-            ctypes.sizeof(S), S.dc_hi.offset]
+            ctypes.sizeof(S), S.dc_hi.offset, C.cfl_forward.offset]
     assert got == want
 
 
@@ -74,6 +74,7 @@ def test_defaults_and_error_strings_without_gpu():
     c = _lib.Config()
     lib.dh_config_default(ctypes.byref(c))
     assert (c.n, c.box, c.cfl, c.dlna_max, c.tau, c.ckpt_every) == (32, 10.0, 0.4, 0.04, 0.1, 16)
+    assert abs(c.cfl_forward - 0.6) < 1e-15
     p = _lib.Params()
     lib.dh_params_default(ctypes.byref(p))
     assert (p.A, p.beta, p.eps_sf, p.delta_c) == (0.3, 1.6, 0.02, 100.0)
@@ -86,6 +87,9 @@ def test_defaults_and_error_strings_without_gpu():
     assert lib.dh_create(ctypes.byref(bad), ctypes.byref(h)) == -1
     bad.n = 32
     bad.omega_b = 0.5
+    assert lib.dh_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+    bad.omega_b = 0.05
+    bad.cfl_forward = -1.0
     assert lib.dh_create(ctypes.byref(bad), ctypes.byref(h)) == -1
     assert lib.dh_step(None, None, None) == -1
 

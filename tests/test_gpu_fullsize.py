@@ -17,9 +17,9 @@ import pytest
 import torch
 
 import synth_inputs as si
-from gpu_helpers import displacement_err, gpu_config, gpu_params, rel_l2, to_gpu, to_np
+from gpu_helpers import (displacement_err, gpu_config, gpu_params, rel_l2,
+                         sweep_vjp_on_gpu_branches, to_gpu, to_np)
 from oracle import gravity, hydro, ics, sim as osim, subgrid
-from test_gpu_parity import _nonsmooth_cells
 
 pytestmark = pytest.mark.gpu
 torch.set_default_dtype(torch.float64)
@@ -76,6 +76,9 @@ def test_sweep_256_sampled_lines(dhp, axis):
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_sweep_vjp_256_sampled_lines(dhp, axis):
+    """Every cell of the sampled lines against the oracle's exact derivative of the line,
+    taken, where a limiter slope or U_d lies within rounding of its kink, on the side the GPU
+    took (both sides are exact one-sided derivatives)."""
     _say(f"sweep adjoint 256^3 axis {axis}")
     ocfg = osim.default_config(n=N)
     s = dhp.Sim(gpu_config(ocfg), gpu_params(osim.Params()))
@@ -83,25 +86,23 @@ def test_sweep_vjp_256_sampled_lines(dhp, axis):
     q = si.smooth_gas_state(N, a0, seed=50 + axis, energy=0.6)
     lam = si.random_field((5, N, N, N), seed=60 + axis)
     out = to_np(s.stage_sweep_vjp(to_gpu(q), to_gpu(lam), axis, dt, a0, ah))
-    qt, lt = torch.from_numpy(q), torch.from_numpy(lam)
-    kept = []
-    for i, j in LINES:
-        ql = _line(qt, axis, i, j).double().requires_grad_(True)
-        y = hydro.sweep(ql, axis, dt, a0, ah, ocfg.gamma, ocfg.e_floor)
-        (g,) = torch.autograd.grad(y, ql, _line(lt, axis, i, j).double())
-        g = g.numpy()
-        got = _line(out, axis, i, j)
-        # float32 and float64 can take different branches of the limiter where a slope is
-        # within rounding of zero: those cells (and 4 neighbours) are left out, as in the
-        # small-size adjoint test (on the smoother 256^3 field about one cell in ten)
-        skip = _nonsmooth_cells(_line(q, axis, i, j), axis, dt, a0, ah, ocfg)
-        keep = ~skip
-        kept.append(keep.mean())
+    # the sampled lines side by side: one field of independent lines along the axis
+    d = 2 if axis == 0 else 3
+    stack = lambda f: np.concatenate([_line(f, axis, i, j) for i, j in LINES], axis=d)
+    got = stack(out)
+    ref, nl, kinks = sweep_vjp_on_gpu_branches(stack(q), stack(lam), got, axis, dt, a0, ah,
+                                               ocfg.gamma, ocfg.e_floor)
+    _say(f"  {kinks} choices near a kink on {nl} of {len(LINES)} lines")
+    assert np.isfinite(got).all()
+    for k in range(len(LINES)):
+        sl = [slice(None)] * 4
+        sl[d] = slice(k, k + 1)
+        gk, rk = got[tuple(sl)], ref[tuple(sl)]
         for c in range(5):
-            err = rel_l2(got[c][keep], g[c][keep])
-            assert err < LINE_VJP_TOL, (i, j, c, err)
-        assert np.isfinite(got).all()
-    assert float(np.mean(kept)) > 0.75, kept
+            err = rel_l2(gk[c], rk[c])
+            assert err < LINE_VJP_TOL, (LINES[k], c, err)
+            elem = np.abs(gk[c] - rk[c]).max() / np.abs(rk[c]).max()
+            assert elem < 1e-3, (LINES[k], c, elem)
     s.close()
 
 
@@ -137,34 +138,68 @@ def test_poisson_256(dhp):
     s.close()
 
 
-def test_bench_step_256_matches_oracle(dhp):
-    """One step of the bench workload from its initial conditions (white-noise seed 6)."""
-    _say("bench step 256^3: oracle initial conditions")
+def _step_256(dhp, prm, label):
+    """One step of the 256^3 / 40 Mpc/h workload from its initial conditions (white-noise
+    seed 6) on the GPU and in the oracle, with the star-formation parameters prm; the
+    relative L2 of every field, and every element within 10 times the bar of its field's
+    largest value."""
+    _say(f"{label} 256^3: oracle initial conditions")
     ocfg = osim.default_config(n=N, box=40.0, a_init=0.01, subgrid=subgrid.MODE_RELAXED)
     w = si.white_noise(N, 6)
     st = osim.initial_state(torch.from_numpy(w).double(), ocfg)
     dt = osim.cfl_dt(st, ocfg)
-    _say("bench step 256^3: GPU step")
-    s = dhp.Sim(gpu_config(ocfg), gpu_params(osim.Params()))
+    _say(f"{label} 256^3: GPU step")
+    s = dhp.Sim(gpu_config(ocfg), gpu_params(prm))
     s.init_from_noise(to_gpu(w))
     s.set_schedule([dt])
     s.step()
-    _say("bench step 256^3: oracle step")
+    _say(f"{label} 256^3: oracle step")
     with torch.no_grad():
-        ref = osim.step(st, ocfg, osim.Params(), dt)
+        ref = osim.step(st, ocfg, prm, dt)
     q = to_np(s.get("q"))
-    errs = {f"q{c}": rel_l2(q[c], ref.q[c].numpy()) for c in range(5)}
-    errs["mom"] = rel_l2(to_np(s.get("mom")), ref.p.numpy())
-    errs["phi"] = rel_l2(to_np(s.get("phi")), ref.phi.numpy())
+    fields = {f"q{c}": (q[c], ref.q[c].numpy()) for c in range(5)}
+    fields["mom"] = (to_np(s.get("mom")), ref.p.numpy())
+    fields["phi"] = (to_np(s.get("phi")), ref.phi.numpy())
+    fields["star"] = (to_np(s.get("star")), ref.star.numpy())
+    errs = {k: rel_l2(g, r) for k, (g, r) in fields.items()}
+    elem = {k: float(np.abs(g - r).max() / max(np.abs(r).max(), 1e-30))
+            for k, (g, r) in fields.items()}
     lat = ics.lattice(N).numpy()
-    scale = np.linalg.norm(((ref.x.numpy() - lat) + N / 2) % N - N / 2)
-    errs["pos"] = displacement_err(to_np(s.get("pos")), ref.x.numpy(), N, scale)
-    _say(f"bench step 256^3: {errs}")
+    disp = ((ref.x.numpy() - lat) + N / 2) % N - N / 2
+    scale = np.linalg.norm(disp)
+    got_x = to_np(s.get("pos"))
+    errs["pos"] = displacement_err(got_x, ref.x.numpy(), N, scale)
+    elem["pos"] = float(np.abs((got_x - ref.x.numpy() + N / 2) % N - N / 2).max()
+                        / np.abs(disp).max())
+    stars = float(ref.star.sum())
+    _say(f"{label} 256^3: stars {stars:.4g}; rel-L2 / per-element "
+         + str({k: f"{errs[k]:.2e}/{elem[k]:.2e}" for k in errs}))
     # positions are absolute float32 coordinates up to 256, resolved to 2^-16: rounding alone
     # leaves an error of about 2^-16 / sqrt(12) per coordinate, which the displacement norm
-    # (sub-cell at a = 0.01) turns into a relative error of a few 1e-6 .. 1e-5
+    # (sub-cell at a = 0.01) turns into a relative error of a few 1e-6 .. 1e-5; per element,
+    # one rounding of a coordinate (2^-16 at 256) against the largest displacement
     pos_floor = 2.0 ** -16 * math.sqrt(3 * N ** 3 / 12.0) / scale
     tol = {k: (max(STEP_TOL, 4 * pos_floor) if k == "pos" else STEP_TOL) for k in errs}
+    etol = {k: 10 * tol[k] for k in errs}
+    etol["pos"] = max(10 * STEP_TOL, 2 * 2.0 ** -16 / np.abs(disp).max())
+    if stars == 0.0:
+        del errs["star"], elem["star"]
     bad = {k: (v, tol[k]) for k, v in errs.items() if not v < tol[k]}
     assert not bad, bad
+    bad = {k: (v, etol[k]) for k, v in elem.items() if not v < etol[k]}
+    assert not bad, ("per element", bad)
     s.close()
+    return stars
+
+
+def test_bench_step_256_matches_oracle(dhp):
+    """One step of the bench workload (default star-formation thresholds, which no cell of
+    the early field reaches)."""
+    _step_256(dhp, osim.Params(), "bench step")
+
+
+def test_step_256_with_active_source_term_matches_oracle(dhp):
+    """The same step with thresholds the early field does reach (Delta_c = 1, T_c = 1e6 K,
+    eps_sf = 5): the FP64 source term acts in many cells."""
+    stars = _step_256(dhp, osim.Params(delta_c=1.0, t_c=1e6, eps_sf=5.0), "active source")
+    assert stars > 1000.0

@@ -3,11 +3,18 @@ the FP64 oracle of oracle.mlp: inference, input gradients and the objective's we
 gradient, the training set, training, one simulation step and the reverse pass with the
 closure, and what the trained network gains over running without the source term.
 
-Tolerances.  The GPU rounds every operand of the network's matrix products, forward and
-backward, to bfloat16 (unit roundoff 2^-9 = 2e-3) and accumulates in FP32.  The oracle
-evaluated with the same roundings (forward(..., bf16=True)) agrees up to FP32 accumulation
-and rare values whose FP32 and FP64 results round to neighbouring bfloat16 values: 1e-3
-relative L2 for outputs, 5e-3 for gradients.  Against the unrounded network: 3e-2."""
+Tolerances.  The reference is the network in FP64 (oracle.mlp.forward with bf16=False).
+The GPU multiplies bfloat16 operands (unit roundoff u = 2^-9 = 2e-3) with FP32 sums, so it
+differs from the FP64 network by a few u per layer: on the test inputs the oracle's own
+bfloat16 model of that arithmetic (bf16=True: every operand of the forward and backward
+matrix products rounded) lies 1e-3 from the FP64 network in the outputs, 7e-3 in the input
+gradient, 1e-3 in the weight gradient (5e-3 for the smallest block), 1.5e-3 in a closure
+step's energy and star field.  The FP64 bars are about four times those: FP64_FWD = 5e-3,
+FP64_VJP = 3e-2, FP64_WGRAD = 5e-3 (2e-2 per block), FP64_STEP = 1e-2.  A parameter
+gradient that sums per-cell terms of both signs is held to 5e-2 of the sum of their
+magnitudes.  As a second, tighter check the GPU is also compared with the bfloat16 model,
+which it follows up to FP32 accumulation and rare values whose FP32 and FP64 results round
+to neighbouring bfloat16 values: 1e-3 relative L2 for outputs, 5e-3 for gradients."""
 
 import numpy as np
 import pytest
@@ -21,9 +28,13 @@ from oracle import mlp as omlp, sim as osim, subgrid
 pytestmark = pytest.mark.gpu
 torch.set_default_dtype(torch.float64)
 
-FWD_TOL = 1e-3
+FWD_TOL = 1e-3          # against the bfloat16 model
 BWD_TOL = 5e-3
-FP64_TOL = 3e-2
+FP64_FWD = 5e-3         # against the FP64 network
+FP64_VJP = 3e-2
+FP64_WGRAD = 5e-3
+FP64_STEP = 1e-2
+FP64_PARAM = 5e-2
 
 
 @pytest.fixture(scope="module")
@@ -50,8 +61,10 @@ def test_eval_matches_oracle(dhp, count):
     th = _theta(net)
     ref16 = omlp.forward(th, torch.from_numpy(x).double(), bf16=True).numpy()
     ref64 = omlp.forward(th, torch.from_numpy(x).double()).numpy()
+    assert rel_l2(out, ref64) < FP64_FWD, rel_l2(out, ref64)
     assert rel_l2(out, ref16) < FWD_TOL, rel_l2(out, ref16)
-    assert rel_l2(out, ref64) < FP64_TOL, rel_l2(out, ref64)
+    # per element: within a few bfloat16 roundings of the output scale
+    assert np.abs(out - ref64).max() < 2e-2 * np.abs(ref64).max()
 
 
 def test_weights_round_trip(dhp):
@@ -74,10 +87,14 @@ def test_vjp_matches_oracle_autograd(dhp):
     x = _inputs(count, seed=11)
     gout = np.random.default_rng(12).normal(size=(2, count)).astype(np.float32)
     gx = to_np(net.vjp(to_gpu(x), to_gpu(gout)))
-    xt = torch.from_numpy(x).double().requires_grad_(True)
-    o = omlp.forward(_theta(net), xt, bf16=True)
-    ref, = torch.autograd.grad(o, xt, grad_outputs=torch.from_numpy(gout).double())
-    assert rel_l2(gx, ref.numpy()) < BWD_TOL, rel_l2(gx, ref.numpy())
+    refs = {}
+    for bf16 in (False, True):
+        xt = torch.from_numpy(x).double().requires_grad_(True)
+        o = omlp.forward(_theta(net), xt, bf16=bf16)
+        refs[bf16], = torch.autograd.grad(o, xt, grad_outputs=torch.from_numpy(gout).double())
+    ref64, ref16 = refs[False].numpy(), refs[True].numpy()
+    assert rel_l2(gx, ref64) < FP64_VJP, rel_l2(gx, ref64)
+    assert rel_l2(gx, ref16) < BWD_TOL, rel_l2(gx, ref16)
 
 
 @pytest.mark.parametrize("count", [100, 3000])
@@ -86,16 +103,23 @@ def test_weight_gradient_matches_oracle_autograd(dhp, count):
     x = _inputs(count, seed=13)
     y = np.random.default_rng(14).normal(0.0, 3.0, (2, count)).astype(np.float32)
     loss, g = net.grad(to_gpu(x), to_gpu(y))
-    th = _theta(net).requires_grad_(True)
-    L = omlp.loss(th, torch.from_numpy(x).double(), torch.from_numpy(y).double(), bf16=True)
-    ref, = torch.autograd.grad(L, th)
-    assert abs(loss - float(L)) < 1e-4 * float(L)
-    assert rel_l2(g, ref.numpy()) < BWD_TOL, rel_l2(g, ref.numpy())
+    refs, losses = {}, {}
+    for bf16 in (False, True):
+        th = _theta(net).requires_grad_(True)
+        L = omlp.loss(th, torch.from_numpy(x).double(), torch.from_numpy(y).double(), bf16=bf16)
+        refs[bf16], = torch.autograd.grad(L, th)
+        losses[bf16] = float(L)
+    ref64, ref16 = refs[False].numpy(), refs[True].numpy()
+    assert abs(loss - losses[False]) < FP64_FWD * losses[False]
+    assert abs(loss - losses[True]) < 1e-4 * losses[True]
+    assert rel_l2(g, ref64) < FP64_WGRAD, rel_l2(g, ref64)
+    assert rel_l2(g, ref16) < BWD_TOL, rel_l2(g, ref16)
     # every parameter block (W1, b1, ..., b4) is right, not only the largest
     k = 0
     for s in omlp.SHAPES:
         m = int(np.prod(s))
-        assert rel_l2(g[k:k + m], ref.numpy()[k:k + m]) < 2 * BWD_TOL, (s, k)
+        assert rel_l2(g[k:k + m], ref64[k:k + m]) < 4 * FP64_WGRAD, (s, k)
+        assert rel_l2(g[k:k + m], ref16[k:k + m]) < 2 * BWD_TOL, (s, k)
         k += m
 
 
@@ -144,8 +168,8 @@ def test_training_fits_the_source_term(dhp):
     assert np.median(err) < 0.04 and np.mean(err) < 0.06, (np.median(err), np.mean(err))
 
 
-def _closure_config(ocfg, theta, **kw):
-    return replace(ocfg, closure_theta=theta, closure_bf16=True, **kw)
+def _closure_config(ocfg, theta, bf16=False, **kw):
+    return replace(ocfg, closure_theta=theta, closure_bf16=bf16, **kw)
 
 
 def test_closure_step_matches_oracle(dhp):
@@ -156,55 +180,74 @@ def test_closure_step_matches_oracle(dhp):
     st = rounded_state(st)
     net = dhp.Mlp(seed=8)
     theta = net.weights().astype(np.float64)
-    ocfg = _closure_config(osim.default_config(n=n, box=10.0, subgrid=subgrid.MODE_RELAXED),
-                           theta)
+    ocfg0 = osim.default_config(n=n, box=10.0, subgrid=subgrid.MODE_RELAXED)
     prm = osim.Params()
-    s = dhp.Sim(gpu_config(ocfg, closure=1), gpu_params(prm))
+    s = dhp.Sim(gpu_config(ocfg0, closure=1), gpu_params(prm))
     s.set_closure(theta)
     load_state(s, st)
-    dt = osim.cfl_dt(st, ocfg)
+    dt = osim.cfl_dt(st, ocfg0)
     s.set_schedule([dt])
     s.step()
-    ref = osim.step(st, ocfg, prm, dt)
     star = to_np(s.get("star"))
-    assert float(ref.star.sum()) > 10.0
     q = to_np(s.get("q"))
-    for c in range(5):
-        assert rel_l2(q[c], ref.q[c].numpy()) < 1e-4, (c, rel_l2(q[c], ref.q[c].numpy()))
-    assert rel_l2(star, ref.star.numpy()) < FWD_TOL, rel_l2(star, ref.star.numpy())
+    for bf16, tol_q, tol_star in ((False, FP64_STEP, FP64_STEP), (True, 1e-4, FWD_TOL)):
+        ref = osim.step(st, _closure_config(ocfg0, theta, bf16=bf16), prm, dt)
+        assert float(ref.star.sum()) > 10.0
+        for c in range(5):
+            assert rel_l2(q[c], ref.q[c].numpy()) < tol_q, (bf16, c, rel_l2(q[c], ref.q[c].numpy()))
+        assert rel_l2(star, ref.star.numpy()) < tol_star, (bf16, rel_l2(star, ref.star.numpy()))
+
+
+def _closure_oracle_gradient(ocfg, prm, w, target, sched):
+    """Oracle autograd of the flux loss: (loss, dL/dwhite, dL/d(A, beta, eps_sf, delta_c),
+    sums over cells of |per-cell terms| of dL/d(eps_sf, delta_c)).  The two star-formation
+    parameters enter as per-cell copies, so that their gradient's per-cell terms are seen."""
+    n = ocfg.n
+    w64 = torch.from_numpy(w).double().requires_grad_(True)
+    th = torch.tensor([prm.A, prm.beta], requires_grad=True)
+    ef = torch.full((n, n, n), prm.eps_sf, requires_grad=True)
+    dc = torch.full((n, n, n), prm.delta_c, requires_grad=True)
+    p2 = osim.Params(A=th[0], beta=th[1], eps_sf=ef, delta_c=dc)
+    st = osim.initial_state(w64, ocfg)
+    st, _ = osim.run(st, ocfg, p2, schedule=sched)
+    assert float(st.star.sum()) > 1.0
+    loss = osim.loss(st, torch.from_numpy(target).double(), ocfg, th[0], th[1])
+    gw, gab, ge, gd = torch.autograd.grad(loss, (w64, th, ef, dc))
+    gp = np.array([float(gab[0]), float(gab[1]), float(ge.sum()), float(gd.sum())])
+    mag = np.array([abs(gp[0]), abs(gp[1]), float(ge.abs().sum()), float(gd.abs().sum())])
+    return float(loss), gw.numpy(), gp, mag
 
 
 def test_closure_gradient_matches_oracle_autograd(dhp):
     n = 16
     net = dhp.Mlp(seed=9)
     theta = net.weights().astype(np.float64)
-    ocfg = _closure_config(osim.default_config(n=n, box=4.0, subgrid=subgrid.MODE_RELAXED,
-                                               a_init=0.05), theta)
+    ocfg0 = osim.default_config(n=n, box=4.0, subgrid=subgrid.MODE_RELAXED, a_init=0.05)
     prm = osim.Params(eps_sf=0.025, delta_c=80.0)
     w = si.white_noise(n, seed=22)
     target = (0.2 + 0.7 * np.random.default_rng(2).random((n, n, n))).astype(np.float32)
     nsteps = 3
+    ocfg = _closure_config(ocfg0, theta)
     st0 = osim.initial_state(torch.from_numpy(w).double(), ocfg)
     _, sched = osim.run(st0, ocfg, prm, nsteps=nsteps)
-    w64 = torch.from_numpy(w).double().requires_grad_(True)
-    th = torch.tensor([prm.A, prm.beta, prm.eps_sf, prm.delta_c], requires_grad=True)
-    p2 = osim.Params(A=th[0], beta=th[1], eps_sf=th[2], delta_c=th[3])
-    st = osim.initial_state(w64, ocfg)
-    st, _ = osim.run(st, ocfg, p2, schedule=sched)
-    assert float(st.star.sum()) > 1.0
-    loss = osim.loss(st, torch.from_numpy(target).double(), ocfg, th[0], th[1])
-    gw_ref, gp_ref = torch.autograd.grad(loss, (w64, th))
     s = dhp.Sim(gpu_config(ocfg, closure=1, ckpt_every=2), gpu_params(prm))
     s.set_closure(theta)
     s.set_schedule(sched)
     assert s.forward(to_gpu(w), 1.0) == nsteps
     lval = s.loss(to_gpu(target))
-    assert abs(lval - float(loss)) < 1e-4 * float(loss)
     gw, gp = s.backward()
-    assert rel_l2(to_np(gw), gw_ref.numpy()) < 1e-2, rel_l2(to_np(gw), gw_ref.numpy())
-    for i in range(4):
-        tol = 1e-3 if i < 2 else BWD_TOL
-        assert abs(gp[i] - float(gp_ref[i])) < tol * abs(float(gp_ref[i])) + 1e-12, (i, gp, gp_ref)
+    gw = to_np(gw)
+    gp = np.array(gp)
+    # the FP64 network, then the bfloat16 model of the GPU's arithmetic
+    for bf16, tol_w, tol_sf in ((False, 1e-2, FP64_PARAM), (True, 1e-2, BWD_TOL)):
+        L, gw_ref, gp_ref, mag = _closure_oracle_gradient(_closure_config(ocfg0, theta, bf16),
+                                                          prm, w, target, sched)
+        assert abs(lval - L) < 1e-4 * L, (bf16, lval, L)
+        assert rel_l2(gw, gw_ref) < tol_w, (bf16, rel_l2(gw, gw_ref))
+        for i in range(2):     # A, beta act on the final state only
+            assert abs(gp[i] - gp_ref[i]) < 1e-3 * mag[i] + 1e-12, (bf16, i, gp, gp_ref)
+        for i in (2, 3):
+            assert abs(gp[i] - gp_ref[i]) < tol_sf * mag[i] + 1e-12, (bf16, i, gp, gp_ref, mag)
 
 
 def test_trained_closure_gains_over_no_source_term(dhp):

@@ -10,8 +10,9 @@ import pytest
 import torch
 
 import synth_inputs as si
-from gpu_helpers import (displacement_err, gpu_config, gpu_params, load_state, rel_l2,
-                         round32, rounded_state, to_gpu, to_np)
+from gpu_helpers import (displacement_err, gpu_config, gpu_params, initial_state_fp32_cells,
+                         load_state, rel_l2, round32, rounded_state, sweep_vjp_on_gpu_branches,
+                         to_gpu, to_np)
 from oracle import cosmology, gravity, hydro, ics, sim as osim, subgrid
 
 pytestmark = pytest.mark.gpu
@@ -46,50 +47,32 @@ def test_sweep_matches_oracle(dhp, n, axis):
         assert rel_l2(out[c], ref[c]) < STEP_TOL, (c, rel_l2(out[c], ref[c]))
 
 
-def _nonsmooth_cells(q, axis, dt, a0, ah, ocfg, rel=1e-5, reach=4):
-    """Cells whose adjoint depends on a non-smooth point that float32 rounding can move:
-    a limiter slope of a stage-2 split flux, or a sweep-direction momentum, within `rel` of
-    zero relative to its neighbours.  FP32 and FP64 may take different branches there."""
-    with torch.no_grad():
-        qt = torch.from_numpy(q).double()
-        fr, fl = hydro.split_fluxes(qt, a0, axis, ocfg.gamma, ocfg.e_floor)
-        f1 = fr - hydro.shift(fl, axis, 1)
-        qh = qt - 0.5 * dt * (f1 - hydro.shift(f1, axis, -1))
-        fr, fl = hydro.split_fluxes(qh, ah, axis, ocfg.gamma, ocfg.e_floor)
-        frm, flp = hydro.shift(fr, axis, -1), hydro.shift(fl, axis, 1)
-        amb = ((fr - frm).abs() <= rel * (fr.abs() + frm.abs())).any(0)
-        amb |= ((flp - fl).abs() <= rel * (fl.abs() + flp.abs())).any(0)
-        for st in (qt, qh):
-            m = st[1 + axis].abs()
-            amb |= m <= rel * st[1:4].abs().sum(0)
-        mask = amb.clone()
-        for k in range(1, reach + 1):
-            mask |= hydro.shift(amb, axis, k) | hydro.shift(amb, axis, -k)
-    return mask.numpy()
+# per element, an adjoint cell against the field's largest: float32 sums of about sixty
+# products whose terms reach ten times the result
+VJP_ELEM_TOL = 1e-3
 
 
 @pytest.mark.parametrize("n", [32, 128])
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_sweep_vjp_matches_oracle_autograd(dhp, n, axis):
+    """The sweep adjoint against the oracle's exact derivative over every cell.  Where a
+    non-smooth choice of the sweep (a limiter slope or U_d) lies within rounding of its kink,
+    float32 and float64 may take different sides; there the oracle's derivative is taken on
+    the side the GPU took (both sides are exact one-sided derivatives)."""
     ocfg = osim.default_config(n=n)
     s = _sim(dhp, ocfg)
     a0, ah, dt = 0.3, 0.31, 0.04
     q = si.smooth_gas_state(n, a0, seed=20 + axis, energy=0.6)
     lam = si.random_field((5, n, n, n), seed=30 + axis)
     out = to_np(s.stage_sweep_vjp(to_gpu(q), to_gpu(lam), axis, dt, a0, ah))
-    q64 = torch.from_numpy(q).double().requires_grad_(True)
-    y = hydro.sweep(q64, axis, dt, a0, ah, ocfg.gamma, ocfg.e_floor)
-    (ref,) = torch.autograd.grad(y, q64, torch.from_numpy(lam).double())
-    ref = ref.numpy()
-    skip = _nonsmooth_cells(q, axis, dt, a0, ah, ocfg)
-    assert skip.mean() < 0.03
-    keep = ~skip
+    ref, lines, kinks = sweep_vjp_on_gpu_branches(q, lam, out, axis, dt, a0, ah, ocfg.gamma,
+                                                  ocfg.e_floor)
+    print(f"{n}^3 axis {axis}: {kinks} choices near a kink on {lines} lines")
     for c in range(5):
-        err = rel_l2(out[c][keep], ref[c][keep])
-        assert err < STEP_TOL, (c, err, skip.mean())
-    # where a branch may differ, the adjoint is still finite and of the same scale
-    assert np.isfinite(out).all()
-    assert np.abs(out[:, skip]).max(initial=0.0) <= 10 * np.abs(ref).max()
+        err = rel_l2(out[c], ref[c])
+        assert err < STEP_TOL, (c, err)
+        elem = np.abs(out[c] - ref[c]).max() / np.abs(ref[c]).max()
+        assert elem < VJP_ELEM_TOL, (c, elem)
 
 
 def test_sweep_handles_cold_gas_floor(dhp):
@@ -191,21 +174,42 @@ def test_readout_matches_oracle(dhp):
 
 # ---------------------------------------------------------------- initial conditions
 
+# per element, a field's largest difference against its largest value: ten times the
+# relative L2 bars (a cell may sit where rounding differences concentrate, e.g. on a
+# steep gradient)
+ELEM_STEP = 1e-4
+ELEM_RUN = 1e-2
+
+
 def _compare_state(s, st, n, tol, fields=("q", "mom", "phi")):
-    errs = {}
+    """Relative L2 of every field below tol, and every element within 10 tol of the field's
+    largest value (positions: displacements, within 10 tol of the largest displacement)."""
+    errs, elem = {}, {}
+
+    def check(name, got, ref):
+        errs[name] = rel_l2(got, ref)
+        elem[name] = float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30))
+
     if "q" in fields:
         q = to_np(s.get("q"))
         for c in range(5):
-            errs[f"q{c}"] = rel_l2(q[c], st.q[c].numpy())
+            check(f"q{c}", q[c], st.q[c].numpy())
     if "mom" in fields:
-        errs["mom"] = rel_l2(to_np(s.get("mom")), st.p.numpy())
+        check("mom", to_np(s.get("mom")), st.p.numpy())
     if "phi" in fields:
-        errs["phi"] = rel_l2(to_np(s.get("phi")), st.phi.numpy())
+        check("phi", to_np(s.get("phi")), st.phi.numpy())
     lat = ics.lattice(n).numpy()
-    scale = np.linalg.norm(((st.x.numpy() - lat) + n / 2) % n - n / 2) + 1e-30
-    errs["pos"] = displacement_err(to_np(s.get("pos")), st.x.numpy(), n, scale)
+    disp = ((st.x.numpy() - lat) + n / 2) % n - n / 2
+    scale = np.linalg.norm(disp) + 1e-30
+    got_x = to_np(s.get("pos"))
+    errs["pos"] = displacement_err(got_x, st.x.numpy(), n, scale)
+    dpos = np.abs((got_x - st.x.numpy() + n / 2) % n - n / 2)
+    elem["pos"] = float(dpos.max() / (np.abs(disp).max() + 1e-30))
+    print({k: f"{errs[k]:.2e}/{elem[k]:.2e}" for k in errs})
     bad = {k: v for k, v in errs.items() if not v < tol}
     assert not bad, bad
+    bad = {k: v for k, v in elem.items() if not v < 10 * tol}
+    assert not bad, ("per element", bad)
     return errs
 
 
@@ -274,11 +278,25 @@ def test_single_step_with_star_formation(dhp, mode):
                                                                 ocfg.e_floor, ocfg.t_per_e).numpy()) < STEP_TOL
     else:
         # hard draws: identical except where the uniform sits within float32 rounding of
-        # the threshold 1 - pi0
+        # the threshold 1 - pi0; there the other draw is as valid, and the cell differs by
+        # one star and by exactly the supernova energy a^2 rho E0
         differ = star != ref.star.numpy()
         assert differ.sum() <= 2
-        if differ.sum() == 0:
-            _compare_state(s, ref, n, STEP_TOL)
+        keep = ~differ
+        q = to_np(s.get("q"))
+        for c in range(5):
+            r = ref.q[c].numpy()
+            assert rel_l2(q[c][keep], r[keep]) < STEP_TOL, (c, rel_l2(q[c][keep], r[keep]))
+            assert np.abs(q[c][keep] - r[keep]).max() < ELEM_STEP * np.abs(r).max(), c
+        if differ.any():
+            dz = star[differ] - ref.star.numpy()[differ]
+            assert np.all(np.abs(dz) == 1.0)
+            e0_code = prm.e0 * 1e6 / ocfg.vel_unit ** 2
+            inj = ref.a ** 2 * ref.q[0].numpy()[differ] * e0_code
+            de = q[4][differ] - ref.q[4].numpy()[differ]
+            assert np.allclose(de, dz * inj, rtol=1e-4), (de, dz * inj)
+        others = ["mom", "phi"]
+        _compare_state(s, ref, n, STEP_TOL, fields=others)
 
 
 def test_ten_step_run_matches_oracle(dhp):
@@ -327,28 +345,6 @@ def test_conservation_sums(dhp):
 
 # ---------------------------------------------------------------- gradients
 
-def _initial_state_fp32_cells(white, ocfg):
-    """The oracle's initial state with the CIC cell of every particle decided on its float32
-    position, as the GPU decides it: the values of x are rounded to float32, the gradient
-    passes through the rounding.  The lattice puts every particle on a CIC kink (a cell
-    centre), so a displacement within float32 rounding of zero picks the neighbouring cell
-    differently in float32 and float64; a 64^3 field has a few such particles, and each moves
-    the exact gradient by ~1e-3."""
-    n = ocfg.n
-    a = ocfg.a_init
-    psi = ics.za_displacement(ics.linear_density(white, ocfg), n)
-    psi_p = psi.reshape(3, -1)
-    x = torch.remainder(ics.lattice(n) + psi_p, float(n))
-    x = x + (round32(x) - x).detach()
-    vfac = a * a * cosmology.hubble_e(a, ocfg.omega_m) * cosmology.growth_rate(a, ocfg.omega_m)
-    p = vfac * psi_p
-    rho = ocfg.f_b * gravity.cic_deposit(x, 1.0, n)
-    mom = rho * (vfac * psi)
-    u = mom / (a * rho)
-    etot = a * a * rho * (ocfg.e_init + 0.5 * (u * u).sum(0))
-    return osim.state_from_qxp(torch.cat([rho[None], mom, etot[None]]), x, p, ocfg)
-
-
 @pytest.mark.parametrize("n,box,a_init,nsteps,ckpt", [(16, 4.0, 0.05, 4, 3), (64, 10.0, 0.01, 2, 1)])
 def test_gradient_matches_oracle_autograd(dhp, n, box, a_init, nsteps, ckpt):
     # 16^3: star formation active in most cells; 64^3: the launch shapes of larger grids
@@ -364,7 +360,7 @@ def test_gradient_matches_oracle_autograd(dhp, n, box, a_init, nsteps, ckpt):
     w64 = torch.from_numpy(w).double().requires_grad_(True)
     th = torch.tensor([prm.A, prm.beta, prm.eps_sf, prm.delta_c], requires_grad=True)
     p2 = osim.Params(A=th[0], beta=th[1], eps_sf=th[2], delta_c=th[3], t_c=prm.t_c)
-    st = _initial_state_fp32_cells(w64, ocfg)
+    st = initial_state_fp32_cells(w64, ocfg)
     st, _ = osim.run(st, ocfg, p2, schedule=sched)
     loss = osim.loss(st, torch.from_numpy(target).double(), ocfg, th[0], th[1])
     gw_ref, gp_ref = torch.autograd.grad(loss, (w64, th))

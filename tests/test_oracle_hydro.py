@@ -147,3 +147,31 @@ def test_strang_cycle_order():
     names = ["".join("XYZ"[d] for d in hydro.strang_axes(s)) for s in range(6)]
     assert "".join(names) == "XYZZYXZXYYXZYZXXZY"
     assert hydro.strang_axes(6) == hydro.strang_axes(0)
+
+
+def test_sweep_with_fixed_branches():
+    """The optional fixed choices of sweep() (used by derivative checks at kinks): with its
+    own decisions the sweep is unchanged; a flipped limiter branch or |U_d| sign changes the
+    value only by what that branch contributes at the point, which vanishes at the kink."""
+    a, dt = 0.3, 0.04
+    q = _random_state(8, a, 5)
+    k = hydro.sweep_kinks(q, 1, dt, a, a, 5 / 3, 1e-6)
+    one = lambda v: torch.where(v >= 0, torch.ones_like(v), -torch.ones_like(v))
+    br = {"sign1": one(k["u1"][0]), "sign2": one(k["u2"][0]),
+          "take_r": k["x_r"][0] * k["y_r"][0] > 0, "take_l": k["x_l"][0] * k["y_l"][0] > 0}
+    base = hydro.sweep(q, 1, dt, a, a, 5 / 3, 1e-6)
+    assert torch.allclose(hydro.sweep(q, 1, dt, a, a, 5 / 3, 1e-6, branches=br), base,
+                          rtol=0, atol=1e-15)
+    # every limiter branch switched on where the slopes disagree in sign: the flux gains the
+    # harmonic mean of opposite-signed slopes, a change of the value
+    br2 = dict(br, take_r=torch.ones_like(br["take_r"]))
+    assert not torch.allclose(hydro.sweep(q, 1, dt, a, a, 5 / 3, 1e-6, branches=br2), base)
+    # at an exact kink (a zero slope), either branch gives the same value
+    x = torch.tensor([0.0, 0.3, -0.2])
+    y = torch.tensor([0.7, 0.0, 0.0])
+    assert torch.equal(hydro.van_leer(x, y, take=torch.tensor([True, True, True])),
+                       hydro.van_leer(x, y, take=torch.tensor([False, False, False])))
+    # |U_d| with the sign fixed to that of U_d is |U_d|
+    f0, c0 = hydro.flux_and_speed(q, a, 2, 5 / 3, 1e-6)
+    f1, c1 = hydro.flux_and_speed(q, a, 2, 5 / 3, 1e-6, sign_ud=one(q[3]))
+    assert torch.equal(f0, f1) and torch.allclose(c0, c1, rtol=1e-15, atol=0)
