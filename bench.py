@@ -1,12 +1,13 @@
 """Benchmark of the MI355X path: cell-updates/s of the full time step (forward with
 checkpoints plus the reverse pass) at 256^3 cells + 256^3 dark-matter particles, the
-forward-only rate, the roofline of the dominant kernel (the hydro sweep, bound by vector ALU
-issue; its HBM fraction beside it), the FP64 CPU oracle
-timed on this host, the learned star-formation closure against the plain source term
-(its training, its step rates, and the distance of its final fields from the plain run's),
-and the batched parameter sampler (64 samples of 64^3 with their own seeds, star-formation
-parameters and step counts, forward + reverse in shared launches) against running the same
-samples one after another.
+forward-only rate, the same over a whole run a = 0.01 -> 0.29, the HBM roofline of the
+dominant kernel (the hydro sweep adjoint) and of the whole step (algorithmic bytes per
+cell-step recounted from the kernels), the error of the first step against the FP64 oracle,
+the oracle itself timed on this host's cores, the learned star-formation closure against
+the plain source term (its training, its step rates, and the distance of its final fields
+from the plain run's), and the batched parameter sampler (64 samples of 64^3 with their own
+seeds, star-formation parameters and step counts, forward + reverse in shared launches)
+against running the same samples one after another.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -23,12 +24,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed FP32 instructions (this build emits none): 256 CUs x 4 SIMDs
-# x 16 lanes x 2 flops (FMA) x 2.4 GHz
-VALU_FP32_PEAK_TFLOPS = 78.6432
-VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4   # wave64 VALU instructions per second (4 cycles each)
+FP32_VECTOR_PEAK_TFLOPS = 157.3      # MI355X published FP32 vector peak
 SWEEP_FLOPS_PER_CELL = 236           # FP32 operations of one sweep per cell (FMA = 2)
 SWEEP_BYTES_PER_CELL = 40            # read Q, write Q
+SWEEP_VJP_BYTES_PER_CELL = 60        # read Q, read lambda_out, write lambda_in
+# Algorithmic HBM bytes per cell (one particle per cell) of one step, recounted from the
+# kernels a step launches: every array a kernel must read or write, once.
+FWD_BYTES = [
+    ("kick+drift: x, p read and written, key written, g4 read", 68),
+    ("first sweep with the opening gas kick: Q read and written, g4 read", 56),
+    ("second and third sweeps: Q read and written", 80),
+    ("sort: histogram 8, scan 8, scatter 12, bin sort 8, gather of x 32", 68),
+    ("deposit: bin starts, sorted x, rho_gas read, delta written", 28),
+    ("FFT Poisson: r2c, y, z with Green's function, y, c2r passes", 64),
+    ("gradient: phi read, g4 written", 20),
+    ("closing pass: Q read and written, g4 read, star read and written", 64),
+]
+TAPE_BYTES = 20      # the forward's copy of the kicked state for the reverse pass
+REV_BYTES = [
+    ("source, closing-kick and next opening-kick adjoints", 120),
+    ("gather of lambda_p into bin order", 32),
+    ("vector deposit of the kick adjoint", 60),
+    ("gradient adjoint (two fields)", 28),
+    ("FFT Poisson of the potential adjoint", 64),
+    ("density adjoint added to lambda_rho", 12),
+    ("position adjoint of kicks, deposit and drift", 80),
+    ("three sweep adjoints", 180),
+    ("gradient of the step's start potential", 20),
+]
+MODEL_FWD_BYTES = 340                # the byte model the >= 50% target is stated in
+MODEL_FWD_BWD_BYTES = 1180
 N = 256
 BOX = 40.0           # Mpc/h: cell size 0.156 Mpc/h, as the 128^3 / 20 Mpc/h box
 A_INIT = 0.01
@@ -70,9 +95,9 @@ def time_stage(torch, fn, reps):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
-def sweep_counter_record(name):
-    """A record of rocprofv3 counters of the 256^3 sweep launches (profiles/<name>), or None
-    when the sweep sources have changed since the counters were taken."""
+def counter_record(name):
+    """A record of rocprofv3 counters of 256^3 launches (profiles/<name>), or None when the
+    kernel sources it names have changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
@@ -85,21 +110,6 @@ def sweep_counter_record(name):
             if hashlib.sha256(fh.read()).hexdigest() != digest:
                 return None
     return doc
-
-
-def sweep_traffic_bytes():
-    """Measured HBM bytes per sweep launch at 256^3 (two counter passes, calibrated by
-    streaming kernels of known size), or None."""
-    doc = sweep_counter_record("sweep_256_traffic.json")
-    return float(doc["traffic_bytes_per_launch"]) if doc else None
-
-
-def sweep_valu_insts():
-    """Measured VALU wave instructions per sweep launch at 256^3 by axis, or None."""
-    doc = sweep_counter_record("sweep_256_valu.json")
-    if not doc:
-        return None
-    return {ax: float(v["valu_insts_per_launch"]) for ax, v in doc["per_axis"].items()}
 
 
 def time_fwd_bwd(torch, s, white, sched, target, steps):
@@ -284,23 +294,127 @@ def batch_comparison(torch, dhp, si, samples):
     }
 
 
-def cpu_baseline(n, box):
-    """The FP64 oracle on this host's cores: one forward step at the same size."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_fwd_bwd_rate(n, box, threads, min_seconds):
+    """Cell-updates/s of forward + reverse steps of the FP64 oracle (the step, the flux loss,
+    torch.autograd back to the step's gas, particles and potential and to the parameters) at
+    n^3 on `threads` host threads: one untimed step (the first touch of its memory), then
+    timed steps until min_seconds have passed.  Returns (rate, timed steps, seconds)."""
     import torch
     import synth_inputs as si
     from oracle import sim as osim, subgrid
-    torch.set_default_dtype(torch.float64)
+    torch.set_num_threads(threads)
     cfg = osim.default_config(n=n, box=box, a_init=A_INIT, subgrid=subgrid.MODE_RELAXED)
-    st = osim.initial_state(torch.from_numpy(si.white_noise(n, 6)).double(), cfg)
-    dt = osim.cfl_dt(st, cfg)
-    t0 = time.perf_counter()
+    w = torch.from_numpy(si.white_noise(n, 6)).double()
+    target = torch.from_numpy(si.white_noise(n, 7)).double().abs() * 0.1 + 0.5
     with torch.no_grad():
-        osim.step(st, cfg, osim.Params(), dt)
+        st0 = osim.initial_state(w, cfg)
+        dt = osim.cfl_dt(st0, cfg)
+
+    def one():
+        th = torch.tensor([0.3, 1.6, 0.02, 100.0], dtype=torch.float64, requires_grad=True)
+        prm = osim.Params(A=th[0], beta=th[1], eps_sf=th[2], delta_c=th[3])
+        leaves = [v.clone().requires_grad_(True) for v in (st0.q, st0.x, st0.p, st0.phi)]
+        st = osim.State(q=leaves[0], x=leaves[1], p=leaves[2], star=st0.star, phi=leaves[3],
+                        t=st0.t, a=st0.a, step=st0.step)
+        out = osim.step(st, cfg, prm, dt)
+        L = osim.loss(out, target, cfg, th[0], th[1])
+        torch.autograd.grad(L, leaves + [th])
+
+    one()
+    k, t0 = 0, time.perf_counter()
+    while k < 2 or time.perf_counter() - t0 < min_seconds:
+        one()
+        k += 1
     el = time.perf_counter() - t0
-    return {"value": n ** 3 / el, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"one forward step (relaxed star formation) of the FP64 oracle at {n}^3 "
-                      f"from the same initial conditions; {el:.1f} s"}
+    return n ** 3 * k / el, k, el
+
+
+def cpu_baseline(n, box, gpu_first_step):
+    """The FP64 oracle on this host's cores.  The headline sample: one forward + reverse step
+    at 128^3 on all threads; beside it the same at 64^3 on one thread, and one forward step at
+    the benchmarked size, which also gives the error of the GPU's first step against it."""
+    import torch
+    import synth_inputs as si
+    from oracle import sim as osim, subgrid
+    threads = torch.get_num_threads()
+    n_fb = min(n, 64)
+    v_all, k_all, el_all = oracle_fwd_bwd_rate(n_fb, box * n_fb / n, threads, 6.0)
+    log(f"bench: oracle fwd+bwd {n_fb}^3 on {threads} threads: {k_all} steps {el_all:.1f} s")
+    v_one, k_one, el_one = oracle_fwd_bwd_rate(n_fb, box * n_fb / n, 1, 6.0)
+    log(f"bench: oracle fwd+bwd {n_fb}^3 on 1 thread: {k_one} steps {el_one:.1f} s")
+    torch.set_num_threads(threads)
+    cfg = osim.default_config(n=n, box=box, a_init=A_INIT, subgrid=subgrid.MODE_RELAXED)
+    with torch.no_grad():
+        st = osim.initial_state(torch.from_numpy(si.white_noise(n, 6)).double(), cfg)
+        dt = osim.cfl_dt(st, cfg)
+        t0 = time.perf_counter()
+        ref = osim.step(st, cfg, osim.Params(), dt)
+        el = time.perf_counter() - t0
+    log(f"bench: oracle forward step {n}^3 {el:.1f} s")
+    errors = None
+    if gpu_first_step is not None:
+        got, gpu_dt = gpu_first_step
+        errors = {"dt_rel": abs(gpu_dt - dt) / dt}
+        refs = {f"q{c}": ref.q[c].numpy() for c in range(5)}
+        refs.update(mom=ref.p.numpy(), phi=ref.phi.numpy(), star=ref.star.numpy())
+        for k, r in refs.items():
+            g = got[k]
+            nr = float(np.linalg.norm(r))
+            errors[k] = float(np.linalg.norm(g - r) / (nr if nr > 0 else 1.0))
+    return {"value": v_all, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"forward + reverse steps (relaxed star formation, flux loss, "
+                      f"torch.autograd) of the FP64 oracle at {n_fb}^3 ({box * n_fb / n:g} "
+                      f"Mpc/h, the benchmark's cell size) from a = {A_INIT}: {k_all} timed "
+                      f"steps, {el_all:.1f} s on {threads} threads, after one untimed step",
+            "cpu_model": cpu_model(),
+            "one_core": {"value": v_one, "cores": 1,
+                         "sample": f"the same on 1 thread: {k_one} steps, {el_one:.1f} s"},
+            "forward_step": {"value": n ** 3 / el, "cores": threads,
+                             "sample": f"one forward step at {n}^3, {el:.1f} s"}}, errors
+
+
+def gpu_first_step(torch, dhp, white, n, box):
+    """The fields after the first CFL step of the benchmark workload on the GPU (for its error
+    against the oracle's step), and the step's dt."""
+    cfg = dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=2)
+    s = dhp.Sim(cfg)
+    s.init_from_noise(white)
+    dt, _ = s.step()
+    q = s.get("q").double().cpu().numpy()
+    out = {f"q{c}": q[c] for c in range(5)}
+    out.update(mom=s.get("mom").double().cpu().numpy(), phi=s.get("phi").double().cpu().numpy(),
+               star=s.get("star").double().cpu().numpy())
+    s.close()
+    return out, dt
+
+
+def full_run(torch, s, white, a_final=0.29):
+    """Forward + loss + reverse over a whole run from a = 0.01 to a_final with CFL steps
+    (checkpoints every cfg.ckpt_every steps, the reverse pass's data chosen by the free device
+    memory); timed after an untimed pass.  Returns (seconds, steps, (taped, sorted))."""
+    s.init_from_noise(white)
+    s.run_to(a_final)
+    target = s.get("flux").clone()
+    s.set_schedule([])
+    for timed in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = s.forward(white, a_final)
+        s.loss(target)
+        s.backward()
+        torch.cuda.synchronize()
+    return time.perf_counter() - t0, k, s.store_info()
 
 
 def main():
@@ -315,7 +429,8 @@ def main():
 
     n = args.n
     nc = n ** 3
-    cfg = dhp.default_config(n=n, box=BOX * n / N, a_init=A_INIT, subgrid=2,
+    box = BOX * n / N
+    cfg = dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=2,
                              ckpt_every=max(1, args.steps))
     s = dhp.Sim(cfg)
     white = torch.from_numpy(si.white_noise(n, 6)).cuda()
@@ -327,28 +442,48 @@ def main():
         f"({taped[0]} taped by the forward, {taped[1]} with a kept sort); every segment "
         f"recomputed {t_fb_rc * 1e3:.1f} ms")
 
-    # dominant kernel: the hydro sweep (three per step, three adjoint sweeps in the reverse
-    # pass), bound by vector ALU issue: 236 FP32 operations and 40 bytes per cell and launch
+    # dominant kernel of the forward + reverse step: the sweep adjoint (three launches per
+    # step, about a fifth of the step), 60 algorithmic bytes per cell and launch; beside it
+    # the forward sweep, 40 bytes and 236 FP32 operations per cell and launch
     q = s.get("q")
+    lam = torch.randn_like(q)
     a, _, _ = s.time()
-    sweep_t = {}
+    vjp_t, sweep_t = {}, {}
     for axis in (0, 1, 2):
+        vjp_t[axis] = time_stage(torch, lambda: s.stage_sweep_vjp(q, lam, axis, sched[0], a, a),
+                                 args.kernel_reps)
         sweep_t[axis] = time_stage(torch, lambda: s.stage_sweep(q, axis, sched[0], a, a),
                                    args.kernel_reps)
+    t_vjp = sum(vjp_t.values()) / 3.0
     t_sweep = sum(sweep_t.values()) / 3.0
-    flops_per_launch = SWEEP_FLOPS_PER_CELL * nc
-    achieved = flops_per_launch / t_sweep / 1e12
-    bytes_per_launch = SWEEP_BYTES_PER_CELL * nc
-    hbm_achieved = bytes_per_launch / t_sweep / 1e9
-    measured = sweep_traffic_bytes() if n == N else None
-    traffic = measured / t_sweep / 1e9 if measured else None
-    valu = sweep_valu_insts() if n == N else None
-    issue_frac = (sum(valu[ax] / sweep_t[i] for i, ax in enumerate("xyz")) / 3.0 / VALU_ISSUE_PEAK
-                  if valu else None)
+    vjp_bytes = SWEEP_VJP_BYTES_PER_CELL * nc
+    vjp_gbs = vjp_bytes / t_vjp / 1e9
+    rec = counter_record("sweep_vjp_256_traffic.json") if n == N else None
+    traffic = float(rec["traffic_bytes_per_launch"]) if rec else None
+    sweep_gbs = SWEEP_BYTES_PER_CELL * nc / t_sweep / 1e9
+    sweep_tflops = SWEEP_FLOPS_PER_CELL * nc / t_sweep / 1e12
+
+    # whole run a = 0.01 -> 0.29 at the benchmarked size
+    cfg_run = dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=2, ckpt_every=16)
+    s_run = dhp.Sim(cfg_run)
+    t_run, k_run, taped_run = full_run(torch, s_run, white)
+    s_run.close()
+    log(f"bench: whole run a = {A_INIT} -> 0.29: {k_run} steps, fwd+bwd {t_run:.2f} s "
+        f"({taped_run[0]} taped, {taped_run[1]} with a kept sort)")
+    first = gpu_first_step(torch, dhp, white, n, box) if not args.no_cpu_baseline else None
+
+    fwd_b = sum(b for _, b in FWD_BYTES)
+    rev_b = sum(b for _, b in REV_BYTES)
+    fb_b = fwd_b + TAPE_BYTES + rev_b
+    rate_fwd = nc * args.steps / t_fwd
+    rate_fb = nc * args.steps / t_fb
+
+    def frac(bytes_per_cell, rate):
+        return bytes_per_cell * rate / (HBM_PEAK_GBS * 1e9)
 
     out = {
         "metric": "cell-updates/s fwd+bwd at 256^3 (forward with checkpoints + reverse pass)",
-        "value": nc * args.steps / t_fb,
+        "value": rate_fb,
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -359,10 +494,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{n}^3 cells + {n}^3 DM particles, {BOX * n / N:g} Mpc/h box, "
+        "config": {"workload": f"{n}^3 cells + {n}^3 DM particles, {box:g} Mpc/h box, "
                                "BBKS Gaussian random field at a=0.01, relaxed stochastic star "
-                               "formation, checkpointed forward + reverse pass",
-                   "n": n, "box_mpc_h": BOX * n / N, "ckpt_every": int(cfg.ckpt_every),
+                               "formation, checkpointed forward + flux loss + reverse pass",
+                   "n": n, "box_mpc_h": box, "ckpt_every": int(cfg.ckpt_every),
                    "reverse_data": "capacity-chosen: the forward taped "
                                    f"{taped[0]} of {args.steps} steps, kept the sort of "
                                    f"{taped[1]} more; the rest recomputed from checkpoints"},
@@ -370,31 +505,53 @@ def main():
                                   "ms_per_step": t_fb_rc / args.steps * 1e3,
                                   "what": "the same with every checkpoint segment recomputed "
                                           "(nothing kept by the forward)"},
-        "fwd_cell_updates_per_s": nc * args.steps / t_fwd,
+        "fwd_cell_updates_per_s": rate_fwd,
         "fwd_ms_per_step": t_fwd / args.steps * 1e3,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / VALU_FP32_PEAK_TFLOPS,
-                     "traffic": traffic, "traffic_unit": "GB/s",
-                     "kernel": "hydro sweep (x, y, z mean)",
-                     "algorithmic_flops_per_launch": flops_per_launch,
-                     "valu_issue_frac": issue_frac,
-                     "hbm": {"achieved": hbm_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": hbm_achieved / HBM_PEAK_GBS,
-                             "algorithmic_bytes_per_launch": bytes_per_launch,
-                             "traffic_bytes_per_launch": measured},
-                     "ms_per_launch": {str(k_): v * 1e3 for k_, v in sweep_t.items()}},
+        "full_run": {"what": f"whole run a = {A_INIT} -> 0.29 with CFL steps, checkpoint every "
+                             "16 steps, forward + flux loss + reverse pass",
+                     "steps": k_run, "seconds": t_run, "ms_per_step": t_run / k_run * 1e3,
+                     "cell_updates_per_s": nc * k_run / t_run,
+                     "taped_steps": taped_run[0], "sorted_steps": taped_run[1]},
+        "roofline": {"bound": "hbm", "achieved": vjp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": vjp_gbs / HBM_PEAK_GBS,
+                     "traffic": traffic / t_vjp / 1e9 if traffic else None,
+                     "kernel": "hydro sweep adjoint (x, y, z launches, mean)",
+                     "algorithmic_bytes_per_launch": vjp_bytes,
+                     "traffic_bytes_per_launch": traffic,
+                     "ms_per_launch": {str(k_): v * 1e3 for k_, v in vjp_t.items()}},
+        "forward_sweep": {"bound": "hbm", "achieved": sweep_gbs, "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": sweep_gbs / HBM_PEAK_GBS,
+                          "algorithmic_bytes_per_launch": SWEEP_BYTES_PER_CELL * nc,
+                          "alu_tflops": sweep_tflops,
+                          "alu_frac": sweep_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                          "ms_per_launch": {str(k_): v * 1e3 for k_, v in sweep_t.items()}},
+        "step_roofline": {
+            "peak_gbs": HBM_PEAK_GBS,
+            "forward": {"bytes_per_cell_step_recount": fwd_b,
+                        "frac_recount": frac(fwd_b, rate_fwd),
+                        "bytes_per_cell_step_model": MODEL_FWD_BYTES,
+                        "frac_model": frac(MODEL_FWD_BYTES, rate_fwd)},
+            "fwd_bwd": {"bytes_per_cell_step_recount": fb_b,
+                        "frac_recount": frac(fb_b, rate_fb),
+                        "bytes_per_cell_step_model": MODEL_FWD_BWD_BYTES,
+                        "frac_model": frac(MODEL_FWD_BWD_BYTES, rate_fb)},
+            "recount": {"forward": dict(FWD_BYTES), "tape": TAPE_BYTES,
+                        "reverse": dict(REV_BYTES)}},
     }
     s.close()
     if not args.no_mlp:
         log("bench: learned closure vs plain source term")
-        out["mlp_closure"] = mlp_comparison(torch, dhp, white, n, BOX * n / N, args.steps,
+        out["mlp_closure"] = mlp_comparison(torch, dhp, white, n, box, args.steps,
                                             args.warmup, args.mlp_samples)
     if not args.no_batch:
         log("bench: batched parameter sampler vs one sample at a time")
         out["batched_sampler"] = batch_comparison(torch, dhp, si, args.batch_samples)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(n, BOX * n / N)
+        out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(n, box, first)
+        out["error_vs_oracle_what"] = ("relative L2 of every field after the first CFL step of "
+                                       "the benchmark workload, GPU (FP32) against the FP64 "
+                                       "oracle from the same white noise")
     print(json.dumps(out), flush=True)
 
 

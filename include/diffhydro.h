@@ -64,6 +64,14 @@ enum { DH_SUBGRID_OFF = 0, DH_SUBGRID_HARD = 1, DH_SUBGRID_RELAXED = 2 };
  * the same in both. */
 enum { DH_CLOSURE_PLAIN = 0, DH_CLOSURE_MLP = 1 };
 
+/* Kick and drift factors of the dark matter's kick-drift-kick step: the leapfrog in t (kicks
+ * dt/2, drift dt / a(t+dt/2)^2), or the growth-factor factors of FastPM that the paper's
+ * particle mesh uses (Sec. 2.2), exact for the linear growing mode: with D the growth factor,
+ * G = a^2 dD/dt and F = dG/dt = (3 Om / 2a) D, opening kick (G(a_half) - G(a0)) / F(a0),
+ * drift (D(a1) - D(a0)) / G(a_half), closing kick (G(a1) - G(a_half)) / F(a1).  The gas
+ * kicks are dt/2 in both. */
+enum { DH_KDK_PLAIN = 0, DH_KDK_FASTPM = 1 };
+
 /* Run configuration.  dh_config_default() fills the values of the paper's workloads. */
 typedef struct dh_config {
     int32_t n;           /* cells per side; power of two, 16..256                        */
@@ -85,6 +93,7 @@ typedef struct dh_config {
     double cfl_forward;  /* largest Courant number a replayed step may reach on the state it
                             is applied to (C_forward of Sec. 2.3.3; default 1.5 cfl); 0: no
                             check                                                         */
+    int32_t kdk;         /* DH_KDK_*: the dark matter's step factors                        */
 } dh_config;
 
 /* Model parameters (double).  A, beta: flux observable F = exp(-A Delta^beta) of the loss;

@@ -53,6 +53,38 @@ def growth_rate(a, om):
     return -1.5 * om / (a ** 3 * e2) + 2.5 * om / (a * a * e2 * growth_unnormalised(a, om))
 
 
+def growth_momentum(a, om):
+    """G(a) = a^2 dD/dt for t in 1/H0: with dD/dt = (dD/da) a E(a) and f = dlnD/dlna this is
+    a^2 E(a) f(a) D(a).  For the linear growing mode x = q + D Psi_0 the momentum p = a^2 dx/dt
+    of the particle step (eq. dm_hamil) is G Psi_0."""
+    return a * a * hubble_e(a, om) * growth_rate(a, om) * growth(a, om)
+
+
+def growth_force(a, om):
+    """F(a) = dG/dt = (3 Om / 2a) D(a): the growth equation of linear theory,
+    d(a^2 dD/dt)/dt = (3/2) Om D / a (t in 1/H0).  For the growing mode the particle force
+    g = -grad phi with lap phi = (3 Om / 2a) delta (Sec. 2.2) is F Psi_0."""
+    return 1.5 * om * growth(a, om) / a
+
+
+def fastpm_factors(a0, a_half, a1, om):
+    """Kick and drift factors of one kick-drift-kick step from a0 to a1 through a_half that
+    are exact for the linear growing mode (the modified KDK of FastPM, which the paper uses
+    for its particle mesh, Sec. 2.2).  With p = G Psi_0, g = F Psi_0 and x - q = D Psi_0 along
+    that mode, the opening half kick with g(a0), the drift with p(a_half) and the closing half
+    kick with g(a1) reproduce the mode exactly when
+        opening kick  K0 = (G(a_half) - G(a0)) / F(a0),
+        drift         Dr = (D(a1) - D(a0)) / G(a_half),
+        closing kick  K1 = (G(a1) - G(a_half)) / F(a1);
+    the plain leapfrog in t uses dt/2, dt / a_half^2 and dt/2 (their limit for small dt).
+    Returns (K0, Dr, K1)."""
+    g0, gh, g1 = (growth_momentum(a, om) for a in (a0, a_half, a1))
+    k0 = (gh - g0) / growth_force(a0, om)
+    dr = (growth(a1, om) - growth(a0, om)) / gh
+    k1 = (g1 - gh) / growth_force(a1, om)
+    return k0, dr, k1
+
+
 def bbks_transfer(q, log=math.log):
     """BBKS (Bardeen et al. 1986) transfer function of q = k / (Om h) with k in h/Mpc.
     Works on floats, or on tensors with log=torch.log (q > 0)."""

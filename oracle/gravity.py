@@ -103,6 +103,11 @@ def dm_kick(p, x, g, h):
     return p + cic_readout(g, x) * h
 
 
+def dm_drift_by(x, p, factor, n):
+    """x += p * factor, wrapped into the periodic box [0, n)."""
+    return torch.remainder(x + p * factor, float(n))
+
+
 def dm_drift(x, p, dt, a_mid, n):
     """x += p dt / a_mid^2 (midpoint rule for dx/dt = p/a^2), periodic wrap to [0, n)."""
     return torch.remainder(x + p * (dt / (a_mid * a_mid)), float(n))

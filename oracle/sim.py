@@ -5,7 +5,8 @@ source is a reading of Sec. 2.2-2.4, which state the operators but not one seque
   1. dt from the CFL condition (eq. dt) and a cap on dln a, or the next entry of a given
      schedule (a predefined schedule is what the paper differentiates through, Sec. 2.3.3);
   2. opening half kicks with g_n = -grad(phi_n): gas (source S_g) and dark matter;
-  3. dark-matter drift with a(t_n + dt/2);
+  3. dark-matter drift with a(t_n + dt/2) (the dark matter's kick and drift factors are
+     those of the leapfrog in t, or FastPM's growth-factor factors: dm_factors);
   4. three relaxing-TVD sweeps in the Strang order of this step;
   5. CIC deposit of gas + dark matter and the FFT Poisson solve at a(t_n+dt) -> phi_{n+1};
   6. closing half kicks with g_{n+1}: gas and dark matter;
@@ -45,6 +46,7 @@ class Config:
     sf_seed: int = 102
     closure_theta: object = None  # flat network parameters (oracle.mlp), None: plain source
     closure_bf16: bool = True     # round the network's product operands to bfloat16
+    kdk: int = 0                  # dark-matter step factors: KDK_PLAIN or KDK_FASTPM
 
     # derived quantities (filled by finish())
     amp: float = 0.0
@@ -63,6 +65,18 @@ class Config:
         c.e_init = c.t_init / c.t_per_e
         c.e_floor = c.t_floor / c.t_per_e
         return c
+
+
+KDK_PLAIN, KDK_FASTPM = 0, 1
+
+
+def dm_factors(cfg, a0, a_half, a1, dt):
+    """(opening kick, drift, closing kick) factors of the dark matter over one step: the plain
+    leapfrog in t (dt/2, dt / a_half^2, dt/2), or the growth-factor factors of FastPM
+    (cosmology.fastpm_factors).  The gas kicks are dt/2 in both."""
+    if cfg.kdk == KDK_FASTPM:
+        return cosmology.fastpm_factors(a0, a_half, a1, cfg.omega_m)
+    return 0.5 * dt, dt / (a_half * a_half), 0.5 * dt
 
 
 @dataclass
@@ -125,10 +139,12 @@ def step(state, cfg, prm, dt):
     a1 = cosmology.a_of_time(state.t + dt, om)
     h = 0.5 * dt
 
+    k_open, drift, k_close = dm_factors(cfg, a0, a_half, a1, dt)
+
     g = gravity.grad_central(state.phi)
     q = gravity.gas_kick(state.q, g, h)
-    p = gravity.dm_kick(state.p, state.x, g, h)
-    x = gravity.dm_drift(state.x, p, dt, a_half, n)
+    p = gravity.dm_kick(state.p, state.x, g, k_open)
+    x = gravity.dm_drift_by(state.x, p, drift, n)
 
     for d in hydro.strang_axes(state.step):
         q = hydro.sweep(q, d, dt, a0, a_half, cfg.gamma, cfg.e_floor)
@@ -136,7 +152,7 @@ def step(state, cfg, prm, dt):
     phi = potential(q, x, a1, cfg)
     g = gravity.grad_central(phi)
     q = gravity.gas_kick(q, g, h)
-    p = gravity.dm_kick(p, x, g, h)
+    p = gravity.dm_kick(p, x, g, k_close)
 
     star = state.star
     if cfg.subgrid != subgrid.MODE_OFF:

@@ -16,6 +16,7 @@ ERRORS = {-1: "DH_E_INVAL", -2: "DH_E_OOM", -3: "DH_E_HIP", -4: "DH_E_NONFINITE"
 
 SUBGRID_OFF, SUBGRID_HARD, SUBGRID_RELAXED = 0, 1, 2
 CLOSURE_PLAIN, CLOSURE_MLP = 0, 1
+KDK_PLAIN, KDK_FASTPM = 0, 1
 MLP_NPARAMS = 8834
 FIELD_Q, FIELD_RHO, FIELD_POS, FIELD_MOM, FIELD_STAR, FIELD_PHI, FIELD_TEMP, FIELD_FLUX = range(8)
 
@@ -28,7 +29,8 @@ class Config(ctypes.Structure):
                 ("dlna_max", ctypes.c_double), ("t_floor", ctypes.c_double),
                 ("subgrid", ctypes.c_int32), ("tau", ctypes.c_double), ("sf_seed", ctypes.c_uint64),
                 ("ckpt_every", ctypes.c_int32), ("closure", ctypes.c_int32),
-                ("batch", ctypes.c_int32), ("cfl_forward", ctypes.c_double)]
+                ("batch", ctypes.c_int32), ("cfl_forward", ctypes.c_double),
+                ("kdk", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):

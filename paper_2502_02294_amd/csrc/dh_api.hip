@@ -97,6 +97,7 @@ struct dh_sim {
   long long nc = 0, np = 0, nck = 0;
   hipStream_t st = nullptr;
   dh::Cosmo cosmo{};
+  dh::HeathTable heath;            // growth integral for the per-step FastPM factors
   double amp = 0, f_b = 0, vel_unit = 0, t_per_e = 0, e_init = 0, e_floor = 0, m_dm = 0;
 
   // state (S samples stacked)
@@ -281,11 +282,20 @@ StepScal entry_of(const dh_sim* s, int smp, const Plan& p, int step) {
   if (!p.active) return e;
   e.dt = static_cast<float>(p.dt);
   e.h = static_cast<float>(0.5 * p.dt);
-  e.drift = static_cast<float>(p.dt / (p.ah * p.ah));
+  if (s->cfg.kdk == DH_KDK_FASTPM) {
+    double k0, dr, k1;
+    dh::fastpm_factors(s->cosmo, s->heath, p.a0, p.ah, p.a1, &k0, &dr, &k1);
+    e.h_open = static_cast<float>(k0);
+    e.drift = static_cast<float>(dr);
+    e.h_close = static_cast<float>(k1);
+  } else {
+    e.h_open = e.h_close = e.h;
+    e.drift = static_cast<float>(p.dt / (p.ah * p.ah));
+  }
   e.h1 = hydro_at(s, p.a0);
   e.h2 = hydro_at(s, p.ah);
   e.green = green_at(s, p.a1);
-  e.h_dm = e.h;
+  e.h_dm = e.h_close;
   e.h_prev = s->kick_due[smp];
   return e;
 }
@@ -370,7 +380,7 @@ void flush_kick(dh_sim* s) {
   for (int i = 0; i < s->S; ++i) {
     StepScal e{};
     e.active = s->kick_due[i] != 0.0f ? 1 : 0;
-    e.h = s->kick_due[i];
+    e.h_close = s->kick_due[i];
     s->hstage[i] = e;
   }
   DH_HIP(hipMemcpyAsync(s->cur_tab, s->hstage, static_cast<size_t>(s->S) * sizeof(StepScal),
@@ -627,7 +637,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
       continue;
     }
     if (defer) {
-      s->kick_due[i] = static_cast<float>(0.5 * p.dt);
+      s->kick_due[i] = s->htabs[static_cast<size_t>(sp.slot) * s->S + i].h_close;
       s->kick_pending = true;
     }
     s->t[i] = p.t0 + p.dt;
@@ -1101,6 +1111,7 @@ void dh_config_default(dh_config* c) {
   c->closure = DH_CLOSURE_PLAIN;
   c->batch = 1;
   c->cfl_forward = 1.5 * c->cfl;
+  c->kdk = DH_KDK_PLAIN;
 }
 
 void dh_params_default(dh_params* p) {
@@ -1125,7 +1136,7 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
   if (!(cfg->omega_m > 0 && cfg->omega_m < 1 && cfg->omega_b > 0 && cfg->omega_b < cfg->omega_m &&
         cfg->box > 0 && cfg->a_init > 0 && cfg->a_init < 1 && cfg->cfl > 0 && cfg->dlna_max > 0 &&
         cfg->gamma > 1 && cfg->tau > 0 && cfg->ckpt_every >= 1 && cfg->subgrid >= 0 &&
-        cfg->cfl_forward >= 0 &&
+        cfg->cfl_forward >= 0 && (cfg->kdk == DH_KDK_PLAIN || cfg->kdk == DH_KDK_FASTPM) &&
         cfg->subgrid <= 2 && cfg->t_floor > 0 && cfg->t_init > 0 && cfg->sigma8 > 0 &&
         (cfg->closure == DH_CLOSURE_PLAIN ||
          (cfg->closure == DH_CLOSURE_MLP && cfg->subgrid != DH_SUBGRID_OFF))))
@@ -1142,6 +1153,7 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
     s->nck = static_cast<long long>(n) * n * (n / 2 + 1);
     s->cosmo.om = cfg->omega_m;
     s->cosmo.ol = 1.0 - cfg->omega_m;
+    if (cfg->kdk == DH_KDK_FASTPM) s->heath.build(s->cosmo, 4.0, 4096);
     s->amp = dh::spectrum_amplitude(cfg->omega_m, cfg->h, cfg->n_s, cfg->sigma8);
     s->f_b = cfg->omega_b / cfg->omega_m;
     s->m_dm = 1.0 - s->f_b;
@@ -1589,16 +1601,17 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
       s->param_cap = nsteps + 2;
       s->param_steps = s->alloc<double>(2LL * S * s->param_cap);
     }
-    // dark-matter kick factors of the reverse pass: h of the step plus h of the same
-    // sample's next step (0 after its last)
+    // dark-matter kick factors of the reverse pass: the step's closing kick plus the same
+    // sample's next opening kick (0 after its last step)
     for (int k = 0; k < nsteps; ++k) {
       const StepPlan& sp = s->fwd_plans[k];
       StepScal* h = s->htabs + static_cast<size_t>(sp.slot) * S;
       for (int i = 0; i < S; ++i) {
         if (!sp.smp[i].active) continue;
         const bool next = k + 1 < nsteps && s->fwd_plans[k + 1].smp[i].active;
-        const double hn = next ? 0.5 * s->fwd_plans[k + 1].smp[i].dt : 0.0;
-        h[i].h_dm = static_cast<float>(0.5 * sp.smp[i].dt + hn);
+        const float hn =
+            next ? s->htabs[static_cast<size_t>(s->fwd_plans[k + 1].slot) * S + i].h_open : 0.0f;
+        h[i].h_dm = h[i].h_close + hn;
       }
     }
     if (nsteps > 0)

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cmath>
+#include <vector>
 
 namespace dh {
 
@@ -38,6 +39,69 @@ struct Cosmo {
     return -1.5 * om / (a * a * a * e2) + 2.5 * om / (a * a * e2 * growth_u(a));
   }
 };
+
+// The Heath integral I(a) = int_0^a da' / (a' E(a'))^3 tabulated on s = sqrt(a) (a smooth
+// integrand in s), with cubic Hermite interpolation from the exact derivative
+// dI/ds = 2 s / (s^2 E(s^2))^3: for the per-step growth functions of the FastPM factors,
+// which would otherwise need a fresh quadrature at every step.
+struct HeathTable {
+  double hs = 0.0;
+  std::vector<double> I, dI;
+  void build(const Cosmo& c, double a_max, int m = 2048) {
+    const double smax = std::sqrt(a_max);
+    hs = smax / m;
+    auto f = [&](double s) {
+      if (s == 0.0) return 0.0;
+      const double ap = s * s;
+      const double x = ap * c.E(ap);
+      return 2.0 * s / (x * x * x);
+    };
+    I.assign(m + 1, 0.0);
+    dI.assign(m + 1, 0.0);
+    for (int k = 0; k <= m; ++k) {
+      dI[k] = f(k * hs);
+      if (k == 0) continue;
+      const int sub = 16;   // Simpson over [s_{k-1}, s_k]
+      const double h = hs / sub, s0 = (k - 1) * hs;
+      double acc = f(s0) + f(s0 + hs);
+      for (int i = 1; i < sub; ++i) acc += (i & 1 ? 4.0 : 2.0) * f(s0 + i * h);
+      I[k] = I[k - 1] + acc * h / 3.0;
+    }
+  }
+  bool covers(double a) const {
+    return !I.empty() && a >= 0.0 && std::sqrt(a) <= hs * (static_cast<double>(I.size()) - 1);
+  }
+  double operator()(double a) const {
+    const double s = std::sqrt(a);
+    const int m = static_cast<int>(I.size()) - 1;
+    int k = static_cast<int>(s / hs);
+    if (k >= m) k = m - 1;
+    const double t = s / hs - k, t2 = t * t, t3 = t2 * t;
+    return (2 * t3 - 3 * t2 + 1) * I[k] + (t3 - 2 * t2 + t) * hs * dI[k] +
+           (-2 * t3 + 3 * t2) * I[k + 1] + (t3 - t2) * hs * dI[k + 1];
+  }
+};
+
+// Kick and drift factors of one kick-drift-kick step a0 -> a_half -> a1 that are exact for
+// the linear growing mode (the modified KDK of FastPM): with the growth factor D, the
+// momentum function G = a^2 dD/dt = a^2 E f D and the force function F = dG/dt = (3 Om / 2a) D
+// (the linear growth equation), opening kick (G(a_half) - G(a0)) / F(a0), drift
+// (D(a1) - D(a0)) / G(a_half), closing kick (G(a1) - G(a_half)) / F(a1).  The normalisation
+// of D cancels; D_u = (5 Om / 2) E I from the table.
+inline void fastpm_factors(const Cosmo& c, const HeathTable& T, double a0, double ah, double a1,
+                           double* k_open, double* drift, double* k_close) {
+  auto du = [&](double a) { return 2.5 * c.om * c.E(a) * (T.covers(a) ? T(a) : c.heath(a)); };
+  auto gm = [&](double a) {
+    const double e2 = c.E(a) * c.E(a), d = du(a);
+    const double f = -1.5 * c.om / (a * a * a * e2) + 2.5 * c.om / (a * a * e2 * d);
+    return a * a * c.E(a) * f * d;
+  };
+  auto fo = [&](double a) { return 1.5 * c.om * du(a) / a; };
+  const double g0 = gm(a0), gh = gm(ah), g1 = gm(a1);
+  *k_open = (gh - g0) / fo(a0);
+  *drift = (du(a1) - du(a0)) / gh;
+  *k_close = (g1 - gh) / fo(a1);
+}
 
 inline double bbks(double q) {
   return std::log(1.0 + 2.34 * q) / (2.34 * q) *

@@ -28,10 +28,12 @@ struct SourceArgs {   // FP64: the source term is evaluated in double precision
 struct StepScal {
   SourceArgs src;     // source term at a(t+dt)
   HydroK h1, h2;      // sweep stages at a(t) and a(t+dt/2)
-  float dt, h;        // step length, half kick
-  float drift;        // dt / a(t+dt/2)^2
+  float dt, h;        // step length, half kick of the gas (dt/2)
+  float h_open;       // opening dark-matter kick factor (dt/2, or FastPM's growth-factor one)
+  float h_close;      // closing dark-matter kick factor (likewise)
+  float drift;        // dark-matter drift factor: dt / a(t+dt/2)^2, or FastPM's
   float green;        // Poisson: -(3 Om / 2 a(t+dt)) / N^3
-  float h_dm;         // reverse pass: dark-matter kick factor of this step and the next
+  float h_dm;         // reverse pass: closing dark-matter kick of this step + opening of the next
   float h_prev;       // closing dark-matter kick of the sample's previous step, when deferred
   int active;
 };
@@ -81,7 +83,8 @@ void launch_gather_sorted(hipStream_t st, const Bins& bins, const float* v, cons
 // rho_gas + s * rho_stride: 5 n^3 for the density row of Q) may be null (then 0)
 void launch_deposit(hipStream_t st, const Bins& bins, const float* rho_gas,
                     long long rho_stride, float m_dm, float offset, float* out, const Batch& b);
-// out_accum[3][nc] += scale * CIC deposit of bins.sval, scale = h (merged: h_dm) of the table
+// out_accum[3][nc] += scale * CIC deposit of bins.sval, scale = h_open (merged: h_dm) of the
+// table
 void launch_deposit_vec(hipStream_t st, const Bins& bins, bool merged, float* out_accum,
                         const Batch& b);
 // g4 = (-grad phi, 0) by two-point central differences
@@ -89,16 +92,16 @@ void launch_grad(hipStream_t st, const float* phi, float4* g4, const Batch& b);
 // g at particles: out[3][np] = CIC read-out of g4
 void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float* out,
                       const Batch& b);
-// opening kick (h) + drift (drift) + keys: positions read from pos_in and written to pos
+// opening kick (h_open) + drift (drift) + keys: positions read from pos_in and written to pos
 // (the same array for an update in place); optional copies of the new momenta and positions.
 // prev: first the previous step's closing kick (h_prev of the table), as launch_kick would
 void launch_kick_drift(hipStream_t st, const float4* g4, const float* pos_in, float* pos,
                        float* mom, uint32_t* key, float* mom_copy, float* pos_copy, bool prev,
                        const Batch& b);
-// closing kick p += h g(x)
+// closing kick p += h_close g(x)
 void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom, const Batch& b);
 // adjoint of p' = p + k g(x) with respect to x: lam_x += k sum_c dw/dx (g_c . lam_p'), with
-// k = h (merged: h_dm) of the table
+// k = h_open (merged: h_dm) of the table
 void launch_kick_vjp_pos(hipStream_t st, const float4* g4, const float* pos,
                          const float* lam_p, bool merged, float* lam_x, const Batch& b);
 // adjoint of the deposit wrt positions: lam_x += mass sum_c lam_delta_c dw_c/dx; with lam_p

@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __rest
   __shared__ float W[8 * T::NB];
   const StepScal& sc = tab[blockIdx.y];
   if (!sc.active) return;
-  const float scale = merged ? sc.h_dm : sc.h;
+  const float scale = merged ? sc.h_dm : sc.h_open;
   const long long nc = static_cast<long long>(n) * n * n;
   start += blockIdx.y * nc;
   out += blockIdx.y * 3 * nc;
@@ -550,7 +550,7 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
     }
     return;
   }
-  const float h = sc.h, drift_fac = sc.drift, hp = prev ? sc.h_prev : 0.0f;
+  const float h = sc.h_open, drift_fac = sc.drift, hp = prev ? sc.h_prev : 0.0f;
   float x[3] = {pos_in[i], pos_in[np + i], pos_in[2 * np + i]};
   const Cic w = cic_of(x[0], x[1], x[2], n);
   float g[3];
@@ -578,7 +578,7 @@ __global__ void __launch_bounds__(256) kick_kernel(const float4* __restrict__ g4
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const StepScal& sc = tab[blockIdx.y];
   if (i >= np || !sc.active) return;
-  const float h = sc.h;
+  const float h = sc.h_close;
   g4 += blockIdx.y * np;
   pos += blockIdx.y * 3 * np;
   mom += blockIdx.y * 3 * np;
@@ -618,7 +618,7 @@ __global__ void __launch_bounds__(256) kick_vjp_pos_kernel(const float4* __restr
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const StepScal& sc = tab[blockIdx.y];
   if (i >= np || !sc.active) return;
-  const float h = merged ? sc.h_dm : sc.h;
+  const float h = merged ? sc.h_dm : sc.h_open;
   g4 += blockIdx.y * np;
   pos += blockIdx.y * 3 * np;
   lam_p += blockIdx.y * 3 * np;

@@ -233,11 +233,12 @@ __device__ __forceinline__ double cell_speed(const float q5[5], double a, double
   const double ia = 1.0 / a;
   const double iar = ia / rho;
   const double u0 = q5[1] * iar, u1 = q5[2] * iar, u2 = q5[3] * iar;
-  double e = q5[4] * ia * iar - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
-  e = fmax(e, efloor);
-  const double cs = sqrt(gg1 * e);
+  const double e_raw = q5[4] * ia * iar - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+  const double cs = sqrt(gg1 * fmax(e_raw, efloor));
   double sp = (fmax(fabs(u0), fmax(fabs(u1), fabs(u2))) + cs) * ia;
-  if (!(rho > 0.0) || !isfinite(sp)) sp = INFINITY;
+  // every component enters e_raw, so a NaN or infinity anywhere in the cell shows there
+  // (fmax and the floor would drop a NaN)
+  if (!(rho > 0.0) || !isfinite(e_raw) || !isfinite(sp)) sp = INFINITY;
   return sp;
 }
 

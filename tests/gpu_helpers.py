@@ -54,7 +54,7 @@ def gpu_config(ocfg, **kw):
                           h=ocfg.h, sigma8=ocfg.sigma8, n_s=ocfg.n_s, gamma=ocfg.gamma, mu=ocfg.mu,
                           a_init=ocfg.a_init, t_init=ocfg.t_init, cfl=ocfg.cfl,
                           dlna_max=ocfg.dlna_max, t_floor=ocfg.t_floor, subgrid=ocfg.subgrid,
-                          tau=ocfg.tau, sf_seed=ocfg.sf_seed, **kw)
+                          tau=ocfg.tau, sf_seed=ocfg.sf_seed, kdk=ocfg.kdk, **kw)
 
 
 def gpu_params(p):

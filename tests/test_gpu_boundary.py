@@ -144,7 +144,7 @@ def test_replayed_schedule_accuracy_check(dhp):
         s.forward(w, 1.0)
     assert e.value.code == -5
     with pytest.raises(DiffHydroError) as e:
-        s.backward(torch.zeros(n, n, n, device="cuda"))
+        s.backward(torch.zeros(n, n, n, dtype=torch.float32, device="cuda"))
     assert e.value.code == -6
     s.close()
     # one step at a time: the step that exceeds it reports it

@@ -243,10 +243,11 @@ def _evolved_oracle_state(n, box, a_target, seed, **cfgkw):
     return ocfg, rounded_state(st)
 
 
-@pytest.mark.parametrize("a_target", [0.01, 0.12])
-def test_single_step_matches_oracle(dhp, a_target):
+@pytest.mark.parametrize("a_target,kdk", [(0.01, 0), (0.12, 0), (0.12, 1)])
+def test_single_step_matches_oracle(dhp, a_target, kdk):
+    """One step from an evolved state; kdk 1: the dark matter with FastPM's factors."""
     n = 32
-    ocfg, st = _evolved_oracle_state(n, 10.0, a_target, seed=2)
+    ocfg, st = _evolved_oracle_state(n, 10.0, a_target, seed=2, kdk=kdk)
     s = _sim(dhp, ocfg)
     load_state(s, st)
     dt = osim.cfl_dt(st, ocfg)
@@ -345,12 +346,16 @@ def test_conservation_sums(dhp):
 
 # ---------------------------------------------------------------- gradients
 
-@pytest.mark.parametrize("n,box,a_init,nsteps,ckpt", [(16, 4.0, 0.05, 4, 3), (64, 10.0, 0.01, 2, 1)])
-def test_gradient_matches_oracle_autograd(dhp, n, box, a_init, nsteps, ckpt):
-    # 16^3: star formation active in most cells; 64^3: the launch shapes of larger grids
-    # (whole-segment walks, 8 x 8 FFT lines, tiled deposits), two checkpoint segments
-    print(f"gradient vs oracle autograd, {n}^3, {nsteps} steps", flush=True)
-    ocfg = osim.default_config(n=n, box=box, subgrid=subgrid.MODE_RELAXED, a_init=a_init)
+@pytest.mark.parametrize("n,box,a_init,nsteps,ckpt,kdk", [(16, 4.0, 0.05, 4, 3, 0),
+                                                        (16, 4.0, 0.05, 4, 3, 1),
+                                                        (64, 10.0, 0.01, 2, 1, 0)])
+def test_gradient_matches_oracle_autograd(dhp, n, box, a_init, nsteps, ckpt, kdk):
+    # 16^3: star formation active in most cells (with the leapfrog's and FastPM's dark-matter
+    # factors); 64^3: the launch shapes of larger grids (whole-segment walks, 8 x 8 FFT
+    # lines, tiled deposits), two checkpoint segments
+    print(f"gradient vs oracle autograd, {n}^3, {nsteps} steps, kdk {kdk}", flush=True)
+    ocfg = osim.default_config(n=n, box=box, subgrid=subgrid.MODE_RELAXED, a_init=a_init,
+                               kdk=kdk)
     prm = osim.Params(delta_c=1.05, t_c=1e6, eps_sf=0.5)
     w = si.white_noise(n, seed=21)
     target = (0.2 + 0.7 * np.random.default_rng(1).random((n, n, n))).astype(np.float32)

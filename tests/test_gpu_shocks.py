@@ -131,11 +131,11 @@ def test_sod_tube_matches_oracle_and_exact_solution(dhp, axis, a):
 
 
 def test_sedov_blast_matches_oracle_and_radius(dhp):
-    """A point explosion in a cold uniform medium (48^3, gamma = 5/3, a = 1): three sweeps per
+    """A point explosion in a cold uniform medium (64^3, gamma = 5/3, a = 1): three sweeps per
     step in the Strang order, the oracle's CFL steps replayed on the GPU; the final fields
     against the oracle's, one step from an identical mid-run state, and the GPU's shock
     radius against r = 1.15 (E t^2 / rho)^(1/5) within 2 cells, angular scatter < 1 cell."""
-    n, rsh, tf, g = 48, 10.0, 10.0, 5.0 / 3.0
+    n, rsh, tf, g = 64, 10.0, 10.0, 5.0 / 3.0
     print(f"Sedov {n}^3", flush=True)
     # an energy floor far below the cold medium's e = 1e-6, the same on both sides
     ocfg = osim.default_config(n=n, gamma=g, t_floor=1e-10)
