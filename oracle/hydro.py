@@ -65,15 +65,18 @@ def van_leer(x, y, eps=LIMITER_EPS, take=None):
     phi(x, y) = (x y + |x y|) / (x + y + eps sgn(x+y)), sgn(0) = +1: equal to
     2xy/(x+y+eps sgn) when x and y share a sign and 0 otherwise, so it is never 0/0
     (a reading: the paper's form 2xy/(x+y+eps) leaves opposite signs and x + y < 0 open).
-    take (optional boolean per element) fixes the branch, 2xy/(x+y+eps sgn) where true and
-    0 where false, in place of the test x y > 0; only derivative checks at the kink x y = 0
+    take (optional, per element: a boolean or a weight 0, 1/2 or 1) fixes the branch in place
+    of the test x y > 0: w 2xy/(x+y+eps sgn) with w = 1 (true) or 0 (false).  w = 1/2 is the
+    mean of the two sides, whose derivative is that of the |x y| form itself at x y = 0 exactly
+    (where |.| has the derivative sign(0) = 0).  Only derivative checks at the kink x y = 0
     use it."""
     s = x + y
     sg = torch.where(s >= 0, torch.ones_like(s), -torch.ones_like(s))
     xy = x * y
     if take is None:
         return (xy + xy.abs()) / (s + eps * sg)
-    return torch.where(take, 2.0 * xy / (s + eps * sg), torch.zeros_like(xy))
+    w = take.to(xy.dtype)
+    return torch.where(w > 0, w * (2.0 * xy / (s + eps * sg)), torch.zeros_like(xy))
 
 
 def split_fluxes(q, a, d, gamma, e_floor, sign_ud=None):

@@ -1,6 +1,9 @@
 """Helpers shared by the GPU parity tests: conversions between the oracle's float64 state
 and the library's float32 buffers, and error measures."""
 
+import itertools
+import math
+
 import numpy as np
 import torch
 
@@ -87,31 +90,38 @@ def initial_state_fp32_cells(white, ocfg):
 
 # ---------------------------------------------------------------- sweep adjoint at kinks
 
+# a slope within this relative distance of zero may be rounded to exactly zero in float32,
+# where the adjoint takes the derivative of the |x y| form at x y = 0 (the half weight)
+EXACT_ZERO_REL = 2.0 ** -21
+
+
 def _kink_choices(k, rel):
     """FP64 decisions of the sweep's non-smooth choices, and those lying within `rel` of
-    their kink: list of (entry, element index)."""
+    their kink: list of (entry, element index, the sides to try).  A limiter branch is a
+    weight (0 or 1, or 1/2 for a slope that float32 may round to exactly zero)."""
     u1, su1 = k["u1"]
     u2, su2 = k["u2"]
     one = lambda v: torch.where(v >= 0, torch.ones_like(v), -torch.ones_like(v))
     br = {"sign1": one(u1), "sign2": one(u2),
-          "take_r": k["x_r"][0] * k["y_r"][0] > 0, "take_l": k["x_l"][0] * k["y_l"][0] > 0}
+          "take_r": (k["x_r"][0] * k["y_r"][0] > 0).double(),
+          "take_l": (k["x_l"][0] * k["y_l"][0] > 0).double()}
     amb = []
     for name, (v, sc) in (("sign1", k["u1"]), ("sign2", k["u2"])):
-        amb += [(name, tuple(i)) for i in (v.abs() <= rel * sc).nonzero().tolist()]
+        amb += [(name, tuple(i), (-1.0, 1.0)) for i in (v.abs() <= rel * sc).nonzero().tolist()]
     for name, xk, yk in (("take_r", "x_r", "y_r"), ("take_l", "x_l", "y_l")):
         (x, sx), (y, sy) = k[xk], k[yk]
         m = (x.abs() <= rel * sx) | (y.abs() <= rel * sy)
-        amb += [(name, tuple(i)) for i in m.nonzero().tolist()]
+        z = (x.abs() <= EXACT_ZERO_REL * sx) | (y.abs() <= EXACT_ZERO_REL * sy)
+        for i in m.nonzero().tolist():
+            amb.append((name, tuple(i), (0.0, 0.5, 1.0) if bool(z[tuple(i)]) else (0.0, 1.0)))
     return br, amb
 
 
 def _flipped(br, items):
+    """The branch dict with each (entry, index, side) of items set to that side."""
     out = {key: v.clone() for key, v in br.items()}
-    for name, idx in items:
-        if name.startswith("sign"):
-            out[name][idx] = -out[name][idx]
-        else:
-            out[name][idx] = ~out[name][idx]
+    for name, idx, side in items:
+        out[name][idx] = side
     return out
 
 
@@ -134,7 +144,7 @@ def kink_lines(q64, axis, dt, a1, a2, gamma, e_floor, rel=1e-5):
     within `rel` of its kink."""
     _, amb = _kink_choices(hydro_kinks(q64, axis, dt, a1, a2, gamma, e_floor), rel)
     out = set()
-    for _, idx in amb:
+    for _, idx, _ in amb:
         zyx = list(idx[-3:])
         del zyx[2 - axis]
         out.add(tuple(zyx))
@@ -168,8 +178,10 @@ def sweep_vjp_on_gpu_branches(q, lam, gpu, axis, dt, a1, a2, gamma, e_floor, rel
     field or single lines) with every non-smooth choice that lies within `rel` of its kink
     (a limiter slope or U_d within rounding of zero, where float32 and float64 may take
     different sides) set to the side whose exact derivative the GPU's adjoint `gpu` follows.
-    Both sides give exact one-sided derivatives of the sweep; every other choice is the
-    oracle's own.  A sweep acts on each line along `axis` by itself, so only lines holding
+    Both sides give exact one-sided derivatives of the sweep; a slope that float32 may round
+    to exactly zero also has the mean of the two (the derivative of the |x y| form of the
+    limiter at x y = 0, which the adjoint takes there); every other choice is the oracle's
+    own.  A sweep acts on each line along `axis` by itself, so only lines holding
     such a choice are recomputed; on a line, choices within `window` cells of each other are
     decided together (every combination, on the cells they reach), groups further apart
     independently.  Returns (adjoint, lines recomputed, choices near a kink)."""
@@ -202,15 +214,15 @@ def sweep_vjp_on_gpu_branches(q, lam, gpu, axis, dt, a1, a2, gamma, e_floor, rel
         if len(groups) > 1 and pos(groups[0][0]) + n - pos(groups[-1][-1]) <= window:
             groups[0] = groups.pop() + groups[0]   # periodic line: the ends touch
         for grp in groups:
-            if len(grp) > 10:
+            if math.prod(len(it[2]) for it in grp) > 1024:
                 raise AssertionError(f"{len(grp)} choices near kinks within {window} cells")
         info.append((ql, line_of(lam64, axis, i, j), line_of(gpu, axis, i, j), br, amb, groups))
     # every combination of every group, all lines in one stacked evaluation
     cand = []
     for li, (ql, ll, gl, br, amb, groups) in enumerate(info):
         for gi, grp in enumerate(groups):
-            for mask in range(1 << len(grp)):
-                flips = [grp[t] for t in range(len(grp)) if mask >> t & 1]
+            for sides in itertools.product(*[it[2] for it in grp]):
+                flips = [(it[0], it[1], sd) for it, sd in zip(grp, sides)]
                 cand.append((li, gi, flips, _flipped(br, flips)))
     nsel = len(gpu.shape) - 1 - axis
     best = {}

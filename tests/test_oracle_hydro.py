@@ -171,6 +171,19 @@ def test_sweep_with_fixed_branches():
     y = torch.tensor([0.7, 0.0, 0.0])
     assert torch.equal(hydro.van_leer(x, y, take=torch.tensor([True, True, True])),
                        hydro.van_leer(x, y, take=torch.tensor([False, False, False])))
+    # the half weight at an exact zero slope: the same value, and the derivative of the
+    # |x y| form there (sign(0) = 0), the mean of the two one-sided derivatives
+    x = torch.tensor([0.0, 0.3], requires_grad=True)
+    y = torch.tensor([0.7, 0.0], requires_grad=True)
+    grads = []
+    for take in (None, torch.tensor([0.5, 0.5]), torch.tensor([1.0, 1.0]),
+                 torch.tensor([0.0, 0.0])):
+        v = hydro.van_leer(x, y, take=take)
+        assert torch.equal(v.detach(), torch.zeros(2))
+        grads.append(torch.cat(torch.autograd.grad(v.sum(), (x, y))))
+    assert torch.allclose(grads[0], grads[1], rtol=0, atol=1e-15)
+    assert torch.allclose(grads[1], 0.5 * (grads[2] + grads[3]), rtol=0, atol=1e-15)
+    assert torch.allclose(grads[2], torch.tensor([2.0, 0.0, 0.0, 2.0]), rtol=0, atol=1e-12)
     # |U_d| with the sign fixed to that of U_d is |U_d|
     f0, c0 = hydro.flux_and_speed(q, a, 2, 5 / 3, 1e-6)
     f1, c1 = hydro.flux_and_speed(q, a, 2, 5 / 3, 1e-6, sign_ud=one(q[3]))
