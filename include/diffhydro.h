@@ -220,6 +220,22 @@ int dh_backward(dh_sim* sim, const float* d_grad_rho, float* d_grad_white, doubl
  * times p). */
 int dh_conservation(dh_sim* sim, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the sums of dh_conservation over caller
+ * buffers, without a handle.  d_q[batch][5][n^3] gas state, d_mom[batch][3][n^3] particle
+ * momenta p, m_dm the dark-matter particle mass; d_out[8 * batch] (device, FP64) receives
+ * per sample the 8 values of dh_conservation, bit for bit (the same kernels and summation
+ * order).  Enqueued on hip_stream (a hipStream_t or NULL); asynchronous: no allocation and
+ * no synchronisation, so it may be captured into a HIP graph.  The reduction's block
+ * partials live in a library-owned static device array of 512 KiB per device (each device
+ * that the library runs on holds it until the process ends), which limits n to 256:
+ * larger n, n < 1, batch < 1 or a null pointer return DH_E_INVAL, a failed device lookup
+ * DH_E_HIP; dh_last_error(NULL) then holds the message (per thread).  Every call on a device
+ * shares that array: calls that overlap on one device (different streams, or threads)
+ * race and must be ordered by the caller. */
+int dh_conservation_noalloc(const float* d_q, const float* d_mom, int32_t n, int32_t batch,
+                            double m_dm, double* d_out, void* hip_stream);
+
 /* Single stages on caller buffers (one sample's size), for verification of each kernel
  * against a reference.  They do not touch the handle's state.  All pointers are device
  * float32.
@@ -238,6 +254,8 @@ int dh_stage_poisson(dh_sim* sim, const float* d_delta, float* d_phi, double a);
 int dh_stage_deposit(dh_sim* sim, const float* d_rho_gas, const float* d_pos, float* d_delta);
 int dh_stage_readout(dh_sim* sim, const float* d_phi, const float* d_pos, float* d_g);
 
+/* Message of the last failed call on sim; with sim NULL, of the last failed handle-free
+ * call (dh_conservation_noalloc) on this thread. */
 const char* dh_last_error(const dh_sim* sim);
 const char* dh_strerror(int code);
 

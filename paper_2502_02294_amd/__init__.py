@@ -9,8 +9,8 @@ from ._lib import lib as _load
 
 _load()
 
-from .sim import Sim, default_config, default_params  # noqa: E402
+from .sim import Sim, conservation_noalloc, default_config, default_params  # noqa: E402
 from .autograd import DiffHydroFn  # noqa: E402
 from .mlp import Mlp  # noqa: E402
 
-__all__ = ["Sim", "default_config", "default_params", "DiffHydroFn"]
+__all__ = ["Sim", "conservation_noalloc", "default_config", "default_params", "DiffHydroFn"]

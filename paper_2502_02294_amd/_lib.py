@@ -90,6 +90,7 @@ _SIGNATURES = {
     "dh_loss": (I, [P, P, ctypes.POINTER(D)]),
     "dh_backward": (I, [P, P, P, ctypes.POINTER(D)]),
     "dh_conservation": (I, [P, ctypes.POINTER(D)]),
+    "dh_conservation_noalloc": (I, [P, P, I, I, D, P, P]),
     "dh_stage_sweep": (I, [P, P, P, I, D, D, D]),
     "dh_stage_sweep_vjp": (I, [P, P, P, P, I, D, D, D]),
     "dh_stage_poisson": (I, [P, P, P, D]),

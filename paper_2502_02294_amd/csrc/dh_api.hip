@@ -27,6 +27,8 @@
 #include "dh_kernels.h"
 #include "dh_mlp.h"
 
+const char* dh_noalloc_last_error_message();   // noalloc_api.hip
+
 namespace {
 
 using dh::ArgError;
@@ -1794,7 +1796,10 @@ int dh_stage_readout(dh_sim* s, const float* d_phi, const float* d_pos, float* d
   });
 }
 
-const char* dh_last_error(const dh_sim* s) { return s ? s->err.c_str() : "null handle"; }
+// handle-free calls (dh_conservation_noalloc) keep their last message per thread
+const char* dh_last_error(const dh_sim* s) {
+  return s ? s->err.c_str() : dh_noalloc_last_error_message();
+}
 const char* dh_strerror(int code) {
   switch (code) {
     case DH_OK: return "ok";

@@ -291,3 +291,20 @@ class Sim:
         self._check(lib().dh_stage_readout(self._h, _ptr(phi, numel=self.nc),
                                            _ptr(pos, numel=3 * self.nc), _ptr(out)))
         return out
+
+
+def conservation_noalloc(q, mom, n, m_dm, out, batch=1):
+    """dh_conservation_noalloc: the FP64 sums of Sim.conservation over caller tensors q
+    [batch][5][n^3] and mom [batch][3][n^3] (float32, device) into the caller's float64 device
+    tensor out [batch][8], on torch's current stream; the library allocates nothing."""
+    nc = n ** 3
+    if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+            and out.numel() == 8 * batch):
+        raise ValueError("out: expected a contiguous float64 CUDA tensor of 8 * batch values")
+    rc = lib().dh_conservation_noalloc(_ptr(q, numel=5 * nc * batch),
+                                       _ptr(mom, numel=3 * nc * batch), n, batch, m_dm,
+                                       ctypes.c_void_p(out.data_ptr()),
+                                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != _lib.DH_OK:
+        raise _lib.DiffHydroError(rc, lib().dh_last_error(None).decode())
+    return out
