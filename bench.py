@@ -66,33 +66,16 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--n", type=int, default=N)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--kernel-reps", type=int, default=20)
     p.add_argument("--no-mlp", action="store_true", help="skip the learned-closure comparison")
     p.add_argument("--mlp-samples", type=int, default=1 << 24)
     p.add_argument("--no-batch", action="store_true", help="skip the batched-sampler comparison")
     p.add_argument("--batch-samples", type=int, default=64)
+    p.add_argument("--no-full-run", action="store_true", help="skip the whole run a -> 0.29")
     return p.parse_args()
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
-
-
-def time_stage(torch, fn, reps):
-    """Average duration of one launch of fn() (HIP events on the current stream).  One
-    untimed launch is queued before the start event, so the timed launches follow each other
-    without the idle gap of the first launch after a synchronisation."""
-    fn()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    fn()
-    e0.record()
-    for _ in range(reps):
-        fn()
-    e1.record()
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps / 1e3
 
 
 def counter_record(name):
@@ -444,18 +427,21 @@ def main():
 
     # dominant kernel of the forward + reverse step: the sweep adjoint (three launches per
     # step, about a fifth of the step), 60 algorithmic bytes per cell and launch; beside it
-    # the forward sweep, 40 bytes and 236 FP32 operations per cell and launch
-    q = s.get("q")
-    lam = torch.randn_like(q)
-    a, _, _ = s.time()
-    vjp_t, sweep_t = {}, {}
-    for axis in (0, 1, 2):
-        vjp_t[axis] = time_stage(torch, lambda: s.stage_sweep_vjp(q, lam, axis, sched[0], a, a),
-                                 args.kernel_reps)
-        sweep_t[axis] = time_stage(torch, lambda: s.stage_sweep(q, axis, sched[0], a, a),
-                                   args.kernel_reps)
-    t_vjp = sum(vjp_t.values()) / 3.0
-    t_sweep = sum(sweep_t.values()) / 3.0
+    # the forward sweeps, 40 bytes and 236 FP32 operations per cell and launch.  Their
+    # launches inside one more forward + loss + reverse pass of the same steps are timed by
+    # the library with HIP events on the stream it launches them on.
+    from paper_2502_02294_amd import _lib as dhl
+    kt = {}
+    for fam in (dhl.KTIME_SWEEP_VJP, dhl.KTIME_SWEEP, dhl.KTIME_SWEEP_KICK):
+        s.set_kernel_timing(fam)
+        time_fwd_bwd(torch, s, white, sched, s.get("flux").clone(), args.steps)
+        kt[fam] = s.kernel_timing()
+        s.set_kernel_timing(-1)
+    (n_vjp, t_vjp), (n_sweep, t_sweep), (n_kick, t_kick) = (
+        kt[dhl.KTIME_SWEEP_VJP], kt[dhl.KTIME_SWEEP], kt[dhl.KTIME_SWEEP_KICK])
+    log(f"bench: in-step launches: sweep adjoint {n_vjp} x {t_vjp * 1e6:.1f} us, second/third "
+        f"sweeps {n_sweep} x {t_sweep * 1e6:.1f} us, kicking first sweep {n_kick} x "
+        f"{t_kick * 1e6:.1f} us")
     vjp_bytes = SWEEP_VJP_BYTES_PER_CELL * nc
     vjp_gbs = vjp_bytes / t_vjp / 1e9
     rec = counter_record("sweep_vjp_256_traffic.json") if n == N else None
@@ -464,12 +450,13 @@ def main():
     sweep_tflops = SWEEP_FLOPS_PER_CELL * nc / t_sweep / 1e12
 
     # whole run a = 0.01 -> 0.29 at the benchmarked size
-    cfg_run = dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=2, ckpt_every=16)
-    s_run = dhp.Sim(cfg_run)
-    t_run, k_run, taped_run = full_run(torch, s_run, white)
-    s_run.close()
-    log(f"bench: whole run a = {A_INIT} -> 0.29: {k_run} steps, fwd+bwd {t_run:.2f} s "
-        f"({taped_run[0]} taped, {taped_run[1]} with a kept sort)")
+    if not args.no_full_run:
+        cfg_run = dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=2, ckpt_every=16)
+        s_run = dhp.Sim(cfg_run)
+        t_run, k_run, taped_run = full_run(torch, s_run, white)
+        s_run.close()
+        log(f"bench: whole run a = {A_INIT} -> 0.29: {k_run} steps, fwd+bwd {t_run:.2f} s "
+            f"({taped_run[0]} taped, {taped_run[1]} with a kept sort)")
     first = gpu_first_step(torch, dhp, white, n, box) if not args.no_cpu_baseline else None
 
     fwd_b = sum(b for _, b in FWD_BYTES)
@@ -507,24 +494,30 @@ def main():
                                           "(nothing kept by the forward)"},
         "fwd_cell_updates_per_s": rate_fwd,
         "fwd_ms_per_step": t_fwd / args.steps * 1e3,
-        "full_run": {"what": f"whole run a = {A_INIT} -> 0.29 with CFL steps, checkpoint every "
-                             "16 steps, forward + flux loss + reverse pass",
-                     "steps": k_run, "seconds": t_run, "ms_per_step": t_run / k_run * 1e3,
-                     "cell_updates_per_s": nc * k_run / t_run,
-                     "taped_steps": taped_run[0], "sorted_steps": taped_run[1]},
+        "full_run": None if args.no_full_run else {
+            "what": f"whole run a = {A_INIT} -> 0.29 with CFL steps, checkpoint every 16 steps, "
+                    "forward + flux loss + reverse pass",
+            "steps": k_run, "seconds": t_run, "ms_per_step": t_run / k_run * 1e3,
+            "cell_updates_per_s": nc * k_run / t_run,
+            "taped_steps": taped_run[0], "sorted_steps": taped_run[1]},
         "roofline": {"bound": "hbm", "achieved": vjp_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": vjp_gbs / HBM_PEAK_GBS,
                      "traffic": traffic / t_vjp / 1e9 if traffic else None,
-                     "kernel": "hydro sweep adjoint (x, y, z launches, mean)",
+                     "kernel": "hydro sweep adjoint (sweep_x_vjp_kernel, "
+                               "sweep_walk_vjp_kernel<1>, <2>): mean of its launches inside "
+                               "a forward + reverse pass",
+                     "launches": n_vjp, "ms_per_launch": t_vjp * 1e3,
                      "algorithmic_bytes_per_launch": vjp_bytes,
-                     "traffic_bytes_per_launch": traffic,
-                     "ms_per_launch": {str(k_): v * 1e3 for k_, v in vjp_t.items()}},
+                     "traffic_bytes_per_launch": traffic},
         "forward_sweep": {"bound": "hbm", "achieved": sweep_gbs, "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": sweep_gbs / HBM_PEAK_GBS,
                           "algorithmic_bytes_per_launch": SWEEP_BYTES_PER_CELL * nc,
                           "alu_tflops": sweep_tflops,
                           "alu_frac": sweep_tflops / FP32_VECTOR_PEAK_TFLOPS,
-                          "ms_per_launch": {str(k_): v * 1e3 for k_, v in sweep_t.items()}},
+                          "kernel": "second and third hydro sweeps of a step (sweep_x_kernel"
+                                    "<false>, sweep_walk_kernel<1|2, false, ·>)",
+                          "launches": n_sweep, "ms_per_launch": t_sweep * 1e3,
+                          "kicking_first_sweep_ms_per_launch": t_kick * 1e3},
         "step_roofline": {
             "peak_gbs": HBM_PEAK_GBS,
             "forward": {"bytes_per_cell_step_recount": fwd_b,

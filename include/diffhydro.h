@@ -94,6 +94,16 @@ typedef struct dh_config {
                             is applied to (C_forward of Sec. 2.3.3; default 1.5 cfl); 0: no
                             check                                                         */
     int32_t kdk;         /* DH_KDK_*: the dark matter's step factors                        */
+    int32_t star_dm;     /* 1: the stars formed in each step are read out by CIC at the
+                            particles' end-of-step positions and added to the particles'
+                            auxiliary field DH_FIELD_STAR_DM (Sec. 2.4.1: new stars are
+                            associated with nearby dark matter; a diagnostic without effect on
+                            the evolution and without adjoint)                               */
+    int32_t sn_smooth;   /* 1: the supernova energy a^2 rho z E0 of a cell is spread over the
+                            cell and its 26 neighbours with weights w(ox) w(oy) w(oz),
+                            w(0) = 1/2, w(+-1) = 1/4 (periodic; the total is unchanged), the
+                            start of the Sedov-Taylor blast of Sec. 2.4.1 on the grid; 0: all
+                            of it into the cell.  Differentiated like the rest of the step   */
 } dh_config;
 
 /* Model parameters (double).  A, beta: flux observable F = exp(-A Delta^beta) of the loss;
@@ -105,10 +115,13 @@ typedef struct dh_params {
 } dh_params;
 
 /* Fields for dh_get_field / dh_set_field.  Sizes in floats: Q = 5 n^3, POS and MOM = 3 n^3,
- * the rest n^3.  TEMP (get only) is the gas temperature [K] from the floored energy. */
+ * the rest n^3.  TEMP (get only) is the gas temperature [K] from the floored energy.
+ * STAR_DM: the particles' auxiliary field of read-out stars, in particle order (needs
+ * cfg.star_dm; zeroed by the initial conditions). */
 typedef enum dh_field {
     DH_FIELD_Q = 0, DH_FIELD_RHO = 1, DH_FIELD_POS = 2, DH_FIELD_MOM = 3,
-    DH_FIELD_STAR = 4, DH_FIELD_PHI = 5, DH_FIELD_TEMP = 6, DH_FIELD_FLUX = 7
+    DH_FIELD_STAR = 4, DH_FIELD_PHI = 5, DH_FIELD_TEMP = 6, DH_FIELD_FLUX = 7,
+    DH_FIELD_STAR_DM = 8
 } dh_field;
 
 typedef struct dh_sim dh_sim;
@@ -214,6 +227,17 @@ int dh_loss(dh_sim* sim, const float* d_target, double* loss_out);
  * dL/d(A, beta, eps_sf, delta_c) (host, FP64, summed over steps in a fixed order).  The time
  * schedule is held fixed.  DH_E_STATE if no forward (or no loss, with NULL) precedes it. */
 int dh_backward(dh_sim* sim, const float* d_grad_rho, float* d_grad_white, double* grad_params);
+
+/* Kernel timing for measurement.  While a family is set, every launch of that kernel family
+ * made by the stepping calls and dh_backward (not the dh_stage_* calls) is bracketed by a
+ * pair of HIP events on the handle's stream: DH_KTIME_SWEEP_KICK the first hydro sweep of a
+ * step (with the opening gas kick), DH_KTIME_SWEEP the second and third sweeps,
+ * DH_KTIME_SWEEP_VJP the sweep adjoints; -1 stops timing.  Setting it discards earlier
+ * records.  dh_get_kernel_timing synchronises the stream and returns the number of timed
+ * launches since the last set or get and their mean duration [ms], then discards them. */
+enum { DH_KTIME_SWEEP_KICK = 0, DH_KTIME_SWEEP = 1, DH_KTIME_SWEEP_VJP = 2 };
+int dh_set_kernel_timing(dh_sim* sim, int32_t family);
+int dh_get_kernel_timing(dh_sim* sim, int32_t* count, double* mean_ms);
 
 /* FP64 sums over the current state, 8 values per sample: out[0] gas mass, out[1..3] gas
  * momentum a rho U, out[4] total gas energy a^2 rho E, out[5..7] dark-matter momentum (mass

@@ -177,21 +177,27 @@ def closure_inputs(q, a, *, rho_mean_gas, gamma, e_floor, t_per_e, eps_sf, delta
     return features(delta, temp, a, eps_sf, delta_c)
 
 
-def apply_with_outputs(q, star, a, dt, u, o, *, e0_code, tau, mode):
-    """Source update of Sec. 2.4 with pi0 taken from network outputs o (returns Q, star)."""
+def apply_with_outputs(q, star, a, dt, u, o, *, e0_code, tau, mode, with_draw=False,
+                       smooth=False):
+    """Source update of Sec. 2.4 with pi0 taken from network outputs o (returns Q, star, and
+    the draw z with_draw); smooth: the supernova energy spread as subgrid.smooth_injection."""
     pi0 = probability(o, dt)
     z = subgrid.draw(pi0, u, tau, mode)
-    e_new = q[4] + a * a * q[0] * z * e0_code
-    return torch.cat([q[:4], e_new[None]]), star + z
+    inj = a * a * q[0] * z * e0_code
+    e_new = q[4] + (subgrid.smooth_injection(inj) if smooth else inj)
+    out = (torch.cat([q[:4], e_new[None]]), star + z)
+    return out + (z,) if with_draw else out
 
 
 def apply_closure(q, star, a, dt, u, theta, *, rho_mean_gas, gamma, e_floor, t_per_e, e0_code,
-                  eps_sf, delta_c, tau, mode=subgrid.MODE_RELAXED, bf16=False):
-    """The source term with pi0 from the network (returns Q, star)."""
+                  eps_sf, delta_c, tau, mode=subgrid.MODE_RELAXED, bf16=False, with_draw=False,
+                  smooth=False):
+    """The source term with pi0 from the network (returns Q, star, and z with_draw)."""
     x = closure_inputs(q, a, rho_mean_gas=rho_mean_gas, gamma=gamma, e_floor=e_floor,
                        t_per_e=t_per_e, eps_sf=eps_sf, delta_c=delta_c)
     o = forward(theta, x, bf16=bf16)
-    return apply_with_outputs(q, star, a, dt, u, o, e0_code=e0_code, tau=tau, mode=mode)
+    return apply_with_outputs(q, star, a, dt, u, o, e0_code=e0_code, tau=tau, mode=mode,
+                              with_draw=with_draw, smooth=smooth)
 
 
 def init_params(seed):

@@ -11,7 +11,11 @@ source is a reading of Sec. 2.2-2.4, which state the operators but not one seque
   5. CIC deposit of gas + dark matter and the FFT Poisson solve at a(t_n+dt) -> phi_{n+1};
   6. closing half kicks with g_{n+1}: gas and dark matter;
   7. the star-formation source term with a(t_n+dt), or the learned closure standing in for
-     its probability (oracle.mlp) when the configuration carries network weights.
+     its probability (oracle.mlp) when the configuration carries network weights; optionally
+     with the supernova energy spread over neighbouring cells (subgrid.smooth_injection);
+  8. optionally, the stars formed in the step read out by CIC at the particles' positions
+     and added to the particles' auxiliary field (Sec. 2.4.1: the new stars are associated
+     with nearby dark-matter particles, a diagnostic that does not act on the evolution).
 The state carries phi so that each step solves Poisson once; phi of the initial state is
 solved from the initial particles and gas.
 """
@@ -47,6 +51,8 @@ class Config:
     closure_theta: object = None  # flat network parameters (oracle.mlp), None: plain source
     closure_bf16: bool = True     # round the network's product operands to bfloat16
     kdk: int = 0                  # dark-matter step factors: KDK_PLAIN or KDK_FASTPM
+    sn_smooth: bool = False       # supernova energy spread over the neighbouring cells
+    star_dm: bool = False         # keep the stars' read-out on the particles (State.aux)
 
     # derived quantities (filled by finish())
     amp: float = 0.0
@@ -101,6 +107,7 @@ class State:
     t: float
     a: float
     step: int
+    aux: object = None   # [n^3] stars read out on the particles (Config.star_dm), else None
 
 
 def potential(q, x, a, cfg):
@@ -155,23 +162,31 @@ def step(state, cfg, prm, dt):
     p = gravity.dm_kick(p, x, g, k_close)
 
     star = state.star
+    aux = state.aux
+    if cfg.star_dm and aux is None:
+        aux = torch.zeros(n ** 3, dtype=x.dtype)
     if cfg.subgrid != subgrid.MODE_OFF:
         u = torch.from_numpy(philox.starform_uniform(cfg.sf_seed, state.step, n))
         if cfg.closure_theta is not None:
             theta = torch.as_tensor(cfg.closure_theta, dtype=torch.float64)
-            q, star = mlp.apply_closure(
+            q, star, z = mlp.apply_closure(
                 q, star, a1, dt, u, theta, rho_mean_gas=cfg.f_b, gamma=cfg.gamma,
                 e_floor=cfg.e_floor, t_per_e=cfg.t_per_e,
                 e0_code=prm.e0 * 1e6 / cfg.vel_unit ** 2, eps_sf=prm.eps_sf,
-                delta_c=prm.delta_c, tau=cfg.tau, mode=cfg.subgrid, bf16=cfg.closure_bf16)
-            return State(q=q, x=x, p=p, star=star, phi=phi, t=state.t + dt, a=a1,
-                         step=state.step + 1)
-        q, star = subgrid.apply_source(
-            q, star, a1, dt, u, rho_mean_gas=cfg.f_b, omega_b=cfg.omega_b, gamma=cfg.gamma,
-            e_floor=cfg.e_floor, t_per_e=cfg.t_per_e, e0_code=prm.e0 * 1e6 / cfg.vel_unit ** 2,
-            eps_sf=prm.eps_sf, delta_c=prm.delta_c, t_c=prm.t_c, w_rho=prm.w_rho,
-            w_t=prm.w_t, tau=cfg.tau, mode=cfg.subgrid)
-    return State(q=q, x=x, p=p, star=star, phi=phi, t=state.t + dt, a=a1, step=state.step + 1)
+                delta_c=prm.delta_c, tau=cfg.tau, mode=cfg.subgrid, bf16=cfg.closure_bf16,
+                with_draw=True, smooth=cfg.sn_smooth)
+        else:
+            q, star, z = subgrid.apply_source(
+                q, star, a1, dt, u, rho_mean_gas=cfg.f_b, omega_b=cfg.omega_b,
+                gamma=cfg.gamma, e_floor=cfg.e_floor, t_per_e=cfg.t_per_e,
+                e0_code=prm.e0 * 1e6 / cfg.vel_unit ** 2, eps_sf=prm.eps_sf,
+                delta_c=prm.delta_c, t_c=prm.t_c, w_rho=prm.w_rho, w_t=prm.w_t, tau=cfg.tau,
+                mode=cfg.subgrid, smooth=cfg.sn_smooth, with_draw=True)
+        if cfg.star_dm:
+            # the step's new stars, read out at the particles' end-of-step positions
+            aux = aux + gravity.cic_readout(z, x)
+    return State(q=q, x=x, p=p, star=star, phi=phi, t=state.t + dt, a=a1, step=state.step + 1,
+                 aux=aux)
 
 
 def run(state, cfg, prm, *, a_final=None, nsteps=None, schedule=None):

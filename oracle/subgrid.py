@@ -16,6 +16,12 @@ Per cell and step:
 Effect of a formation event: the specific energy E0 is added in the cell,
 a^2 rho E += a^2 rho z E0, and the diagnostic star field gains z.  The gas mass is unchanged.
 E0 is given in (1000 km/s)^2.
+
+Smoothed injection (an option; Sec. 2.4.1 models the supernova heating as the start of a
+Sedov-Taylor blast in the surrounding gas, without fixing how the energy is placed): the
+energy a^2 rho z E0 of each cell is spread over that cell and its 26 neighbours with the
+weights w(ox) w(oy) w(oz), w(0) = 1/2, w(+-1) = 1/4, periodic.  The weights sum to one, so
+the total energy injected is that of the local form.
 """
 
 import math
@@ -65,14 +71,26 @@ def draw(pi0, u, tau, mode):
     return torch.sigmoid((logit + noise) / tau)
 
 
+def smooth_injection(s):
+    """The field s [n, n, n] spread over each cell and its 26 neighbours with the weights
+    w(ox) w(oy) w(oz), w(0) = 1/2, w(+-1) = 1/4 (periodic), one axis after the other."""
+    for d in range(3):
+        s = 0.5 * s + 0.25 * (torch.roll(s, 1, d) + torch.roll(s, -1, d))
+    return s
+
+
 def apply_source(q, star, a, dt, u, *, rho_mean_gas, omega_b, gamma, e_floor, t_per_e,
-                 e0_code, eps_sf, delta_c, t_c, w_rho, w_t, tau, mode):
-    """Returns (Q, star) after one step of the source term."""
+                 e0_code, eps_sf, delta_c, t_c, w_rho, w_t, tau, mode, smooth=False,
+                 with_draw=False):
+    """Returns (Q, star) after one step of the source term (and the draw z, with_draw).
+    smooth: the supernova energy is spread over the neighbouring cells (module docstring)."""
     rho = q[0]
     delta = rho / rho_mean_gas
     temp = temperature(q, a, gamma, e_floor, t_per_e)
     pi0 = formation_probability(delta, temp, a, dt, omega_b, eps_sf, delta_c, t_c,
                                 w_rho, w_t, mode)
     z = draw(pi0, u, tau, mode)
-    e_new = q[4] + a * a * rho * z * e0_code
-    return torch.cat([q[:4], e_new[None]]), star + z
+    inj = a * a * rho * z * e0_code
+    e_new = q[4] + (smooth_injection(inj) if smooth else inj)
+    out = (torch.cat([q[:4], e_new[None]]), star + z)
+    return out + (z,) if with_draw else out

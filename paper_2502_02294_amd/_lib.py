@@ -17,8 +17,10 @@ ERRORS = {-1: "DH_E_INVAL", -2: "DH_E_OOM", -3: "DH_E_HIP", -4: "DH_E_NONFINITE"
 SUBGRID_OFF, SUBGRID_HARD, SUBGRID_RELAXED = 0, 1, 2
 CLOSURE_PLAIN, CLOSURE_MLP = 0, 1
 KDK_PLAIN, KDK_FASTPM = 0, 1
+KTIME_SWEEP_KICK, KTIME_SWEEP, KTIME_SWEEP_VJP = 0, 1, 2
 MLP_NPARAMS = 8834
-FIELD_Q, FIELD_RHO, FIELD_POS, FIELD_MOM, FIELD_STAR, FIELD_PHI, FIELD_TEMP, FIELD_FLUX = range(8)
+(FIELD_Q, FIELD_RHO, FIELD_POS, FIELD_MOM, FIELD_STAR, FIELD_PHI, FIELD_TEMP, FIELD_FLUX,
+ FIELD_STAR_DM) = range(9)
 
 
 class Config(ctypes.Structure):
@@ -30,7 +32,8 @@ class Config(ctypes.Structure):
                 ("subgrid", ctypes.c_int32), ("tau", ctypes.c_double), ("sf_seed", ctypes.c_uint64),
                 ("ckpt_every", ctypes.c_int32), ("closure", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("cfl_forward", ctypes.c_double),
-                ("kdk", ctypes.c_int32)]
+                ("kdk", ctypes.c_int32), ("star_dm", ctypes.c_int32),
+                ("sn_smooth", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -89,6 +92,8 @@ _SIGNATURES = {
     "dh_forward": (I, [P, P, D, ctypes.POINTER(I)]),
     "dh_loss": (I, [P, P, ctypes.POINTER(D)]),
     "dh_backward": (I, [P, P, P, ctypes.POINTER(D)]),
+    "dh_set_kernel_timing": (I, [P, I]),
+    "dh_get_kernel_timing": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D)]),
     "dh_conservation": (I, [P, ctypes.POINTER(D)]),
     "dh_conservation_noalloc": (I, [P, P, I, I, D, P, P]),
     "dh_stage_sweep": (I, [P, P, P, I, D, D, D]),

@@ -108,6 +108,11 @@ struct dh_sim {
   int step = 0;                     // global step counter
   bool phi_valid = false, initialised = false;
 
+  // stars read out on the particles (cfg.star_dm): auxiliary field [S][np] and the step's
+  // draw per cell; smoothed injection (cfg.sn_smooth): the injected energy per cell (and the
+  // adjoint of it in the reverse pass)
+  float *aux = nullptr, *znew = nullptr, *sn_buf = nullptr;
+
   // scratch
   float *q2 = nullptr, *delta = nullptr, *cic = nullptr, *psi = nullptr, *fscratch = nullptr;
   float2 *spec = nullptr, *spec2 = nullptr, *tw = nullptr;
@@ -189,6 +194,12 @@ struct dh_sim {
   int fwd_steps = 0;
   float* loss_target = nullptr;
 
+  // kernel timing for measurement (dh_set_kernel_timing): the launches of one kernel family
+  // inside steps and reverse passes are bracketed by HIP event pairs on the handle's stream
+  int ktime_family = -1;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> kt_events;
+  size_t kt_used = 0;
+
   std::vector<void*> allocs;
   std::string err;
 
@@ -229,6 +240,27 @@ int guarded(dh_sim* s, F&& f) {
     return fail(s, DH_E_HIP, e.what());
   }
 }
+
+// Records an event pair around the launches made during its lifetime when the handle times
+// kernel family `fam` (see dh_set_kernel_timing); nothing otherwise.
+struct KernelTimer {
+  dh_sim* s;
+  std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
+  KernelTimer(dh_sim* sim, int fam) : s(sim) {
+    if (s->ktime_family != fam) return;
+    if (s->kt_used == s->kt_events.size()) {
+      std::pair<hipEvent_t, hipEvent_t> p{};
+      DH_HIP(hipEventCreate(&p.first));
+      DH_HIP(hipEventCreate(&p.second));
+      s->kt_events.push_back(p);
+    }
+    ev = &s->kt_events[s->kt_used++];
+    DH_HIP(hipEventRecord(ev->first, s->st));
+  }
+  ~KernelTimer() {
+    if (ev) (void)hipEventRecord(ev->second, s->st);
+  }
+};
 
 void copy_d2d(dh_sim* s, float* dst, const float* src, long long count) {
   DH_HIP(hipMemcpyAsync(dst, src, static_cast<size_t>(count) * sizeof(float),
@@ -547,6 +579,22 @@ bool all_finite(const std::vector<double>& v) {
   return true;
 }
 
+// Closing pass of a step from q_in (the state after the sweeps) into s->q: gas half kick,
+// source term (kicked state to q_kicked if given), star field and CFL maxima if `full`; then
+// the smoothed supernova injection (cfg.sn_smooth, with the CFL maxima) and, if `readout`,
+// the step's new stars read out on the particles (cfg.star_dm; spos, sorted: the sort of the
+// end-of-step positions).
+void close_pass(dh_sim* s, const float* q_in, float* q_kicked, bool full, bool readout,
+                const float4* spos, const uint32_t* sorted, const Batch& b, bool closure) {
+  const bool smooth = s->cfg.sn_smooth && s->cfg.subgrid != DH_SUBGRID_OFF;
+  const bool stars = readout && full && s->znew && s->cfg.subgrid != DH_SUBGRID_OFF;
+  dh::launch_close_step(s->st, q_in, s->q, s->g4, full ? s->star : nullptr, q_kicked,
+                        s->cfg.gamma, full && !smooth ? s->cfl_red : nullptr, b, closure,
+                        stars ? s->znew : nullptr, smooth ? s->sn_buf : nullptr);
+  if (smooth) dh::launch_sn_inject(s->st, s->sn_buf, s->q, s->cfg.gamma, full ? s->cfl_red : nullptr, b);
+  if (stars) dh::launch_star_readout(s->st, s->znew, spos, sorted, s->aux, b);
+}
+
 // One step of the method on the handle state.  With a tape entry, keeps its intermediates.
 // defer: leave the closing dark-matter kick to the next step's kick-drift pass.
 // store_k >= 0: store index of a forward step (no tape: keep its sort and potential if the
@@ -583,8 +631,14 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
     // in Q1) and the closing pass write their results straight into the tape
     dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, nullptr,
                           prev, b);
-    dh::launch_sweep(s->st, tp->q[0], tp->q[2], b, sp.axes[0], s->g4, tp->q[1]);
-    for (int k = 1; k < 3; ++k) dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
+    {
+      KernelTimer kt(s, DH_KTIME_SWEEP_KICK);
+      dh::launch_sweep(s->st, tp->q[0], tp->q[2], b, sp.axes[0], s->g4, tp->q[1]);
+    }
+    for (int k = 1; k < 3; ++k) {
+      KernelTimer kt(s, DH_KTIME_SWEEP);
+      dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
+    }
     if (recompute && store_k >= 0 && store_k < s->store_valid) {
       // the forward kept this step's sort and potential: no sort, deposit or Poisson solve
       const StepStore& e = s->store[store_k];
@@ -607,9 +661,8 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
     }
     // the recomputation needs neither the star field nor the CFL maxima (plain source)
     const bool full = !recompute || closure;
-    dh::launch_close_step(s->st, tp->q[4], s->q, s->g4, full ? s->star : nullptr,
-                          closure ? tp->q[5] : nullptr, s->cfg.gamma,
-                          full ? s->cfl_red : nullptr, b, closure);
+    close_pass(s, tp->q[4], closure ? tp->q[5] : nullptr, full, !recompute, tp->vspos,
+               tp->vsorted, b, closure);
   } else {
     // opening half kicks with g_n (the gas one inside the first sweep), drift with
     // a(t + dt/2)
@@ -617,16 +670,16 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
                           prev, b);
     // sweeps in the Strang order of the step (a sample that sits out is copied along)
     for (int k = 0; k < 3; ++k) {
+      KernelTimer kt(s, k == 0 ? DH_KTIME_SWEEP_KICK : DH_KTIME_SWEEP);
       dh::launch_sweep(s->st, s->q, s->q2, b, sp.axes[k], k == 0 ? s->g4 : nullptr);
       std::swap(s->q, s->q2);
     }
     // Poisson at a(t + dt) from gas + DM (keys were written by the drift)
     dh::launch_sort(s->st, s->bins, s->pos, b);
     potential_from_bins(s, s->q, s->phi, s->g4, b);
-    if (store_k >= 0) keep_step(s, store_k);
     // closing gas half kick with g_{n+1}, source term and the CFL maxima: one pass
-    dh::launch_close_step(s->st, s->q, s->q, s->g4, s->star, nullptr, s->cfg.gamma, s->cfl_red, b,
-                          closure);
+    close_pass(s, s->q, nullptr, true, true, s->bins.spos, s->bins.sorted, b, closure);
+    if (store_k >= 0) keep_step(s, store_k);
   }
   // closing dark-matter half kick with g_{n+1} (deferred: the factor the table holds)
   if (!defer) dh::launch_kick(s->st, s->g4, s->pos, s->mom, b);
@@ -694,6 +747,7 @@ void initial_conditions(dh_sim* s, const float* d_white) {
                     static_cast<float>(vfac), static_cast<float>(ai), static_cast<float>(s->e_init),
                     all);
   dh::launch_fill(s->st, s->star, 0.0f, s->nc * s->S);
+  if (s->aux) dh::launch_fill(s->st, s->aux, 0.0f, s->np * s->S);
   reset_clock(s);
   potential_from_bins(s, s->q, s->phi, s->g4, batch(s, state_table(s)));
   s->phi_valid = true;
@@ -977,15 +1031,24 @@ void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
   if (!fuse_open) flush_open_vjp(s);   // with the next step's g, still in g4b
   if (!reuse) dh::launch_grad(st, T.phi1, s->g4b, b);
   const int nb = dh::source_vjp_blocks(s->n);
+  // smoothed injection: the adjoint of each cell's injected energy is the smoothing of the
+  // energy adjoint (the weights are symmetric); the next step's opening gas kick leaves the
+  // energy adjoint unchanged, so it may be taken before the fused kernel applies that kick
+  const float* lam_inj = nullptr;
+  if (source && s->cfg.sn_smooth) {
+    dh::launch_smooth27(st, s->lq + 4 * nc, 5 * nc, s->sn_buf, b);
+    lam_inj = s->sn_buf;
+  }
   if (closure) {
-    dh::launch_source_vjp(st, T.q[5], s->lq, s->red, b);
+    dh::launch_source_vjp(st, T.q[5], s->lq, s->red, b, lam_inj);
     dh::launch_gas_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, b);
   } else if (fuse_open) {
     dh::launch_source_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, s->red, b, s->open_q0, s->lg2,
-                               s->open_tab);
+                               s->open_tab, lam_inj);
     s->open_pending = false;
   } else {
-    dh::launch_source_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, s->red, b);
+    dh::launch_source_kick_vjp(st, T.q[4], s->g4b, s->lq, s->lg, s->red, b, nullptr, nullptr,
+                               nullptr, lam_inj);
   }
   if (source)
     dh::launch_reduce_sum(st, s->red, nb, nb, 2 * s->S, s->param_steps + 2LL * s->S * sp.slot);
@@ -1010,7 +1073,10 @@ void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
                              s->g4b, b);
   // sweeps in reverse
   for (int k = 2; k >= 0; --k) {
-    dh::launch_sweep_vjp(st, T.q[1 + k], s->lq, s->lq2, b, sp.axes[k]);
+    {
+      KernelTimer kt(s, DH_KTIME_SWEEP_VJP);
+      dh::launch_sweep_vjp(st, T.q[1 + k], s->lq, s->lq2, b, sp.axes[k]);
+    }
     std::swap(s->lq, s->lq2);
   }
   // opening gas kick with phi_n
@@ -1114,6 +1180,8 @@ void dh_config_default(dh_config* c) {
   c->batch = 1;
   c->cfl_forward = 1.5 * c->cfl;
   c->kdk = DH_KDK_PLAIN;
+  c->star_dm = 0;
+  c->sn_smooth = 0;
 }
 
 void dh_params_default(dh_params* p) {
@@ -1140,6 +1208,7 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
         cfg->gamma > 1 && cfg->tau > 0 && cfg->ckpt_every >= 1 && cfg->subgrid >= 0 &&
         cfg->cfl_forward >= 0 && (cfg->kdk == DH_KDK_PLAIN || cfg->kdk == DH_KDK_FASTPM) &&
         cfg->subgrid <= 2 && cfg->t_floor > 0 && cfg->t_init > 0 && cfg->sigma8 > 0 &&
+        (cfg->star_dm == 0 || cfg->star_dm == 1) && (cfg->sn_smooth == 0 || cfg->sn_smooth == 1) &&
         (cfg->closure == DH_CLOSURE_PLAIN ||
          (cfg->closure == DH_CLOSURE_MLP && cfg->subgrid != DH_SUBGRID_OFF))))
     return DH_E_INVAL;
@@ -1176,6 +1245,12 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
     s->pos = s->alloc<float>(3 * np);
     s->mom = s->alloc<float>(3 * np);
     s->star = s->alloc<float>(nc);
+    if (cfg->star_dm) {
+      s->aux = s->alloc<float>(np);
+      s->znew = s->alloc<float>(nc);
+      DH_HIP(hipMemset(s->aux, 0, static_cast<size_t>(np) * sizeof(float)));
+    }
+    if (cfg->sn_smooth) s->sn_buf = s->alloc<float>(nc);
     s->phi = s->alloc<float>(nc);
     s->delta = s->alloc<float>(nc);
     s->cic = s->alloc<float>(nc);
@@ -1227,6 +1302,10 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
 int dh_destroy(dh_sim* s) {
   if (!s) return DH_OK;
   (void)hipDeviceSynchronize();
+  for (auto& e : s->kt_events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   for (void* p : s->allocs) (void)hipFree(p);
   if (s->host_out) (void)hipHostFree(s->host_out);
   if (s->hstage) (void)hipHostFree(s->hstage);
@@ -1397,6 +1476,10 @@ int dh_get_field(dh_sim* s, dh_field f, float* d_out) {
       case DH_FIELD_POS: copy_d2d(s, d_out, s->pos, 3 * s->np * S); break;
       case DH_FIELD_MOM: copy_d2d(s, d_out, s->mom, 3 * s->np * S); break;
       case DH_FIELD_STAR: copy_d2d(s, d_out, s->star, nc * S); break;
+      case DH_FIELD_STAR_DM:
+        if (!s->aux) return fail(s, DH_E_INVAL, "the star read-out needs cfg.star_dm");
+        copy_d2d(s, d_out, s->aux, s->np * S);
+        break;
       case DH_FIELD_PHI:
         if (!s->phi_valid) refresh_potential(s);
         copy_d2d(s, d_out, s->phi, nc * S);
@@ -1431,6 +1514,10 @@ int dh_set_field(dh_sim* s, dh_field f, const float* d_in) {
       case DH_FIELD_POS: copy_d2d(s, s->pos, d_in, 3 * s->np * S); s->phi_valid = false; break;
       case DH_FIELD_MOM: copy_d2d(s, s->mom, d_in, 3 * s->np * S); break;
       case DH_FIELD_STAR: copy_d2d(s, s->star, d_in, nc * S); break;
+      case DH_FIELD_STAR_DM:
+        if (!s->aux) return fail(s, DH_E_INVAL, "the star read-out needs cfg.star_dm");
+        copy_d2d(s, s->aux, d_in, s->np * S);
+        break;
       case DH_FIELD_PHI:
         copy_d2d(s, s->phi, d_in, nc * S);
         dh::launch_grad(s->st, s->phi, s->g4, batch(s, nullptr));
@@ -1712,6 +1799,30 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
       grad_params[4 * i + 2] = ge;
       grad_params[4 * i + 3] = gd;
     }
+    return DH_OK;
+  });
+}
+
+int dh_set_kernel_timing(dh_sim* s, int32_t family) {
+  if (!s || family < -1 || family > DH_KTIME_SWEEP_VJP) return DH_E_INVAL;
+  s->ktime_family = family;
+  s->kt_used = 0;
+  return DH_OK;
+}
+
+int dh_get_kernel_timing(dh_sim* s, int32_t* count, double* mean_ms) {
+  if (!s || !count || !mean_ms) return DH_E_INVAL;
+  return guarded(s, [&]() -> int {
+    sync(s);
+    double total = 0.0;
+    for (size_t i = 0; i < s->kt_used; ++i) {
+      float ms = 0.0f;
+      DH_HIP(hipEventElapsedTime(&ms, s->kt_events[i].first, s->kt_events[i].second));
+      total += ms;
+    }
+    *count = static_cast<int32_t>(s->kt_used);
+    *mean_ms = s->kt_used ? total / static_cast<double>(s->kt_used) : 0.0;
+    s->kt_used = 0;
     return DH_OK;
   });
 }

@@ -75,6 +75,10 @@ size_t scan_block_count(long long nbins);
 // entries of Bins::large for `total` particles (bins of more than 32 particles)
 long long large_bin_capacity(long long total);
 void launch_keys(hipStream_t st, const float* pos, uint32_t* key, const Batch& b);
+// aux[id] += CIC read-out of znew at each particle (bin order: spos, sorted of the positions
+// at the end of the step; samples that sit the step out are skipped)
+void launch_star_readout(hipStream_t st, const float* znew, const float4* spos,
+                         const uint32_t* sorted, float* aux, const Batch& b);
 // sort by bins.key (already computed for pos) and gather pos into bin order
 void launch_sort(hipStream_t st, const Bins& bins, const float* pos, const Batch& b);
 // bins.sval = v[3][np] (per sample) in bin order
@@ -150,14 +154,25 @@ void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4
 // copy of the kicked state to q_kicked (tape), source term (if src.mode != 0; with the
 // learned closure if `closure`), FP64 block maxima of the CFL speed of the result at src.a
 // into block_max[S][cfl_blocks(n)].  star and block_max both null (plain source only): the
-// star field and the CFL maxima are skipped (the reverse pass's recomputation)
+// star field and the CFL maxima are skipped (the reverse pass's recomputation).  znew: the
+// step's draw of every cell (0 where none; needs star).  sn_out: the supernova energy of
+// every cell goes there instead of into the cell (for launch_sn_inject; block_max null).
 void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4* g4,
                        float* star, float* q_kicked, double gamma, double* block_max,
-                       const Batch& b, bool closure);
+                       const Batch& b, bool closure, float* znew = nullptr,
+                       float* sn_out = nullptr);
+// smoothed supernova injection: a^2 rho E += the 27-cell smoothing of sn (weights 1/2, 1/4 per
+// axis), then the CFL block maxima as launch_close_step (block_max may be null)
+void launch_sn_inject(hipStream_t st, const float* sn, float* q, double gamma, double* block_max,
+                      const Batch& b);
+// out[s][n^3] = the same smoothing of in (sample stride in_stride): its adjoint
+void launch_smooth27(hipStream_t st, const float* in, long long in_stride, float* out,
+                     const Batch& b);
 // adjoint of the source term with the learned closure; dL/d(eps_sf, delta_c) partials per
-// block: partials[(v S + s) nb + block], nb = source_vjp_blocks(n)
+// block: partials[(v S + s) nb + block], nb = source_vjp_blocks(n).  lam_inj: adjoint of
+// each cell's injected energy when the injection is smoothed (null: the energy adjoint).
 void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, double* partials,
-                       const Batch& b);
+                       const Batch& b, const float* lam_inj = nullptr);
 // adjoint of the closing pass with the plain source term (or none, src.mode 0) from the
 // state q_kick before the closing gas half kick with g4 (the kicked state is recomputed):
 // the source, then the kick (lam_g = adjoint of g), in one pass; partials as
@@ -167,7 +182,7 @@ void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, doub
 void launch_source_kick_vjp(hipStream_t st, const float* q_kick, const float4* g4,
                             float* lam_q, float* lam_g, double* partials, const Batch& b,
                             const float* q_open = nullptr, float* lam_g_open = nullptr,
-                            const StepScal* tab_open = nullptr);
+                            const StepScal* tab_open = nullptr, const float* lam_inj = nullptr);
 int source_vjp_blocks(int n);
 // FP64 block maxima of the CFL speed max_d (|U_d| + c_s)/a with a = a_cur[s]:
 // block_max[s][cfl_blocks(n)]

@@ -508,6 +508,36 @@ __global__ void __launch_bounds__(256) readout_g_kernel(const float4* __restrict
   out[2 * np + i] = g[2];
 }
 
+// Stars formed in a step, associated with the dark matter (Sec. 2.4.1): each particle's
+// auxiliary field gains the CIC read-out of the step's new stars znew at its position.
+// Particles in bin order (spos, sorted: global ids, sample in the high bits), so that
+// neighbouring threads read neighbouring cells; samples that sit the step out are skipped.
+__global__ void __launch_bounds__(256) star_readout_kernel(const float* __restrict__ znew,
+                                                           const float4* __restrict__ spos,
+                                                           const uint32_t* __restrict__ sorted,
+                                                           float* __restrict__ aux, int n,
+                                                           long long total, int lnp,
+                                                           const StepScal* __restrict__ tab) {
+  const long long j = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= total) return;
+  const uint32_t id = sorted[j];
+  const long long smp = id >> lnp;
+  if (!sample_active(tab, static_cast<int>(smp))) return;
+  const float* zs = znew + (smp << lnp);   // n^3 cells = n^3 particles per sample
+  const float4 x = spos[j];
+  const Cic w = cic_of(x.x, x.y, x.z, n);
+  float v = 0.0f;
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox)
+        v = fmaf(wsel(w.w1[0], ox) * wsel(w.w1[1], oy) * wsel(w.w1[2], oz),
+                 zs[corner(w, ox, oy, oz, n)], v);
+  aux[id] += v;
+}
+
 __device__ __forceinline__ float wrap_pos(float x, float fn) {
   x -= fn * floorf(x / fn);
   if (x >= fn) x -= fn;
@@ -834,6 +864,15 @@ void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float*
                       const Batch& b) {
   hipLaunchKernelGGL(readout_g_kernel, per_sample(b.nc(), b), dim3(256), 0, st, g4, pos, out, b.n,
                      b.nc());
+  DH_LAUNCH_CHECK();
+}
+
+void launch_star_readout(hipStream_t st, const float* znew, const float4* spos,
+                         const uint32_t* sorted, float* aux, const Batch& b) {
+  if (!b.tab) throw ArgError("star read-out: step table required");
+  const long long total = b.nc() * b.S;
+  hipLaunchKernelGGL(star_readout_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, st, znew,
+                     spos, sorted, aux, b.n, total, log2_ll(b.nc()), b.tab);
   DH_LAUNCH_CHECK();
 }
 

@@ -244,15 +244,20 @@ __device__ __forceinline__ double cell_speed(const float q5[5], double a, double
 
 // Closing pass of a step over kRedPer cells per thread: gas half kick, optional tape copy,
 // source term, CFL block maximum of the result.  !FULL (the reverse pass's recomputation):
-// no star field and no CFL maxima, which only the forward run needs.
+// no star field and no CFL maxima, which only the forward run needs.  znew (optional): the
+// step's draw z of every cell (0 where no star forms), for the stars' read-out on the
+// particles.  sn_out (optional): the supernova energy a^2 rho z E0 of every cell is written
+// there (0 where none) instead of being added to the cell, for the smoothed injection; the
+// CFL maxima are then left to the injection pass (partial may be null).
 template <bool FULL>
 __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
     const float* q_in, float* q, const float4* __restrict__ g4, float* __restrict__ star,
     float* __restrict__ q_kicked, double gg1, double* partial, long long nc,
-    const StepScal* __restrict__ tab) {
+    const StepScal* __restrict__ tab, float* __restrict__ znew, float* __restrict__ sn_out) {
   const StepScal& sc = tab[blockIdx.y];
+  const bool do_max = FULL && partial != nullptr;
   if (!sc.active) {
-    if (FULL) zero_partials<1>(partial);
+    if (do_max) zero_partials<1>(partial);
     return;
   }
   const float h = sc.h;
@@ -262,6 +267,8 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
   if (q_kicked) q_kicked += blockIdx.y * 5 * nc;
   g4 += blockIdx.y * nc;
   if (FULL) star += blockIdx.y * nc;
+  if (znew) znew += blockIdx.y * nc;
+  if (sn_out) sn_out += blockIdx.y * nc;
   double vmax[1] = {0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   for (int r = 0; r < kRedPer; ++r) {
@@ -279,28 +286,110 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
       for (int k = 0; k < 5; ++k) q_kicked[k * nc + c] = q5[k];
     }
     const float lg = a.mode != 0 ? draw_logit_estimate(q5, a) : 0.0f;
+    float zc = 0.0f, inj = 0.0f;
     if (a.mode != 0 && !screened_out(lg, kMaxLogitU, a)) {
       const double u = starform_uniform(c, a);
       if (!screened_out(lg, logit_u_of(u), a)) {
         const SrcCell s = source_eval(q5, u, a);
         if (s.z != 0.0) {
-          q5[4] = static_cast<float>(q5[4] + a.a * a.a * s.rho * s.z * a.e0_code);
+          const double e_sn = a.a * a.a * s.rho * s.z * a.e0_code;
+          if (sn_out)
+            inj = static_cast<float>(e_sn);
+          else
+            q5[4] = static_cast<float>(q5[4] + e_sn);
           if (FULL) star[c] = static_cast<float>(star[c] + s.z);
+          zc = static_cast<float>(s.z);
         }
       }
     }
+    if (znew) znew[c] = zc;
+    if (sn_out) sn_out[c] = inj;
 #pragma unroll
     for (int k = (q == q_in ? 1 : 0); k < 5; ++k) q[k * nc + c] = q5[k];
-    if (FULL) vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
+    if (do_max) vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
   }
-  if (FULL) block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
+  if (do_max) block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
+}
+
+// Weighted sum of the 27 cells around (ix, iy, iz) of one sample's field f with the weights
+// w(ox) w(oy) w(oz), w(0) = 1/2, w(+-1) = 1/4 (periodic): the smoothing of the supernova
+// energy, and its transpose (the weights are symmetric).
+__device__ __forceinline__ float smooth27(const float* __restrict__ f, unsigned ix, unsigned iy,
+                                          unsigned iz, unsigned n1, int lgn) {
+  const unsigned xm = (ix - 1) & n1, xp = (ix + 1) & n1;
+  float acc = 0.0f;
+#pragma unroll
+  for (int oz = -1; oz <= 1; ++oz) {
+    const float wz = oz == 0 ? 0.5f : 0.25f;
+    float accy = 0.0f;
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy) {
+      const float wy = oy == 0 ? 0.5f : 0.25f;
+      const unsigned row = ((((iz + oz) & n1) << lgn) | ((iy + oy) & n1)) << lgn;
+      const float r = 0.5f * f[row | ix] + 0.25f * (f[row | xm] + f[row | xp]);
+      accy = fmaf(wy, r, accy);
+    }
+    acc = fmaf(wz, accy, acc);
+  }
+  return acc;
+}
+
+// Smoothed supernova injection of a step: a^2 rho E += smooth27(sn) per cell, then the CFL
+// block maximum of the result (partial may be null: none).
+__global__ void __launch_bounds__(kRedThreads) sn_inject_kernel(
+    const float* __restrict__ sn, float* __restrict__ q, double gg1, double* partial, int n,
+    int lgn, const StepScal* __restrict__ tab) {
+  const StepScal& sc = tab[blockIdx.y];
+  const long long nc = 1LL << (3 * lgn);
+  if (!sc.active) {
+    if (partial) zero_partials<1>(partial);
+    return;
+  }
+  const SourceArgs& a = sc.src;
+  sn += blockIdx.y * nc;
+  q += blockIdx.y * 5 * nc;
+  const unsigned n1 = static_cast<unsigned>(n - 1);
+  double vmax[1] = {0.0};
+  const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
+  for (int r = 0; r < kRedPer; ++r) {
+    const long long c = base + r * kRedThreads + threadIdx.x;
+    if (c >= nc) break;
+    const unsigned uc = static_cast<unsigned>(c);
+    const float add = smooth27(sn, uc & n1, (uc >> lgn) & n1, uc >> (2 * lgn), n1, lgn);
+    const float e4 = q[4 * nc + c] + add;
+    q[4 * nc + c] = e4;
+    if (partial) {
+      float q5[5];
+      load_q(q, c, nc, q5);
+      q5[4] = e4;
+      vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
+    }
+  }
+  if (partial) block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
+}
+
+// out = smooth27(in) per cell (in: a field of stride in_stride per sample, out: n^3 per
+// sample): the adjoint of the smoothed injection on the energy adjoint
+__global__ void __launch_bounds__(256) smooth27_kernel(const float* __restrict__ in,
+                                                       long long in_stride,
+                                                       float* __restrict__ out, int n, int lgn,
+                                                       const StepScal* __restrict__ tab) {
+  const unsigned c = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nc = 1u << (3 * lgn);
+  if (c >= nc || !tab[blockIdx.y].active) return;
+  in += blockIdx.y * in_stride;
+  out += static_cast<long long>(blockIdx.y) * nc;
+  const unsigned n1 = static_cast<unsigned>(n - 1);
+  out[c] = smooth27(in, c & n1, (c >> lgn) & n1, c >> (2 * lgn), n1, lgn);
 }
 
 // Adjoint of the source term at one cell (state q5 before it): l5 from the adjoint after the
 // source to the adjoint before; acc += dL/d(eps_sf, delta_c).  z and its derivatives are
 // below 1e-47 where the draw is screened out.
+// li: the adjoint of the cell's injected energy, l5[4] itself for the injection into the
+// cell, that of the smoothed injection otherwise.
 __device__ __forceinline__ void source_cell_vjp(const float q5[5], long long c,
-                                                const SourceArgs& a, float l5[5],
+                                                const SourceArgs& a, float l5[5], double li,
                                                 double acc[2]) {
   const float lg = draw_logit_estimate(q5, a);
   if (screened_out(lg, kMaxLogitU, a)) return;
@@ -309,11 +398,11 @@ __device__ __forceinline__ void source_cell_vjp(const float q5[5], long long c,
   const SrcCell s = source_eval(q5, u, a);
   const double le = l5[4];
   const double K = a.a * a.a * a.e0_code;
-  // Et' = Et + K rho z
-  double lr = l5[0] + le * K * s.z;
-  if (a.mode != 1 && le != 0.0) {
+  // Et' = Et + K rho z (into this cell, or spread by the smoothing)
+  double lr = l5[0] + li * K * s.z;
+  if (a.mode != 1 && li != 0.0) {
     const double dz = s.z * (1.0 - s.z) * a.inv_tau / (1.0 - s.pi0);   // dz / dln(pi0)
-    const double coef = le * K * s.rho * dz;
+    const double coef = li * K * s.rho * dz;
     // dln p_sf / dx = 1 / expm1(x) = (1 - p_sf) / p_sf;  x ~ sqrt(rho)
     const double dlp_dx = (1.0 - s.psf) / s.psf;
     const double ir = s.ir, ia = 1.0 / a.a;
@@ -346,12 +435,14 @@ __device__ __forceinline__ void source_cell_vjp(const float q5[5], long long c,
 // OPEN: first the adjoint of the following step's opening gas kick (state q_open, factor of
 // tab_open, the same g: its phi_n is this step's phi_{n+1}), adjoint of g into lam_g_open;
 // every sample moves in both steps.
+// lam_inj (optional): the adjoint of the injected energy of each cell when the injection is
+// smoothed (the smoothing of the energy adjoint).
 template <bool OPEN>
 __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
     const float* __restrict__ q_kick, const float4* __restrict__ g4, float* __restrict__ lam,
     float* __restrict__ lam_g, double* partial, long long nc, const StepScal* __restrict__ tab,
     const float* __restrict__ q_open, float* __restrict__ lam_g_open,
-    const StepScal* __restrict__ tab_open) {
+    const StepScal* __restrict__ tab_open, const float* __restrict__ lam_inj) {
   const StepScal& sc = tab[blockIdx.y];
   if (!sc.active) {
     zero_partials<2>(partial);
@@ -363,6 +454,7 @@ __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
   g4 += blockIdx.y * nc;
   lam += blockIdx.y * 5 * nc;
   lam_g += blockIdx.y * 3 * nc;
+  if (lam_inj) lam_inj += blockIdx.y * nc;
   float h_open = 0.0f;
   if (OPEN) {
     q_open += blockIdx.y * 5 * nc;
@@ -391,7 +483,7 @@ __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
     q5[1] = m[0];
     q5[2] = m[1];
     q5[3] = m[2];
-    if (a.mode != 0) source_cell_vjp(q5, c, a, l5, acc);
+    if (a.mode != 0) source_cell_vjp(q5, c, a, l5, lam_inj ? lam_inj[c] : l5[4], acc);
     float lg[3];
     kick_cell_vjp(q5[0], m0, gv, h, l5, lg);
 #pragma unroll
@@ -478,10 +570,10 @@ __device__ __forceinline__ float closure_logit_estimate(float o0, float o1, cons
 __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
     const float* q_in, float* q, const float4* __restrict__ g4, float* __restrict__ star,
     float* __restrict__ q_kicked, double gg1, double* partial, long long nc,
-    const StepScal* __restrict__ tab) {
+    const StepScal* __restrict__ tab, float* __restrict__ znew, float* __restrict__ sn_out) {
   const StepScal& sc = tab[blockIdx.y];
   if (!sc.active) {
-    zero_partials<1>(partial);
+    if (partial) zero_partials<1>(partial);
     return;
   }
   const float h = sc.h;
@@ -491,6 +583,8 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
   if (q_kicked) q_kicked += blockIdx.y * 5 * nc;
   g4 += blockIdx.y * nc;
   star += blockIdx.y * nc;
+  if (znew) znew += blockIdx.y * nc;
+  if (sn_out) sn_out += blockIdx.y * nc;
   __shared__ uint4 fr[mlp::kFrFwd * 64];
   __shared__ __attribute__((aligned(16))) float bias[mlp::kBias];
   __shared__ float stage[kRedThreads / 64][64][kStage];
@@ -536,27 +630,35 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
       const float o0 = stage[wave][lane][5], o1 = stage[wave][lane][6];
       const float lg = closure_logit_estimate(o0, o1, a);
       const double u = screened_out(lg, kMaxLogitU, a) ? 0.5 : starform_uniform(c, a);
+      float zc = 0.0f, inj = 0.0f;
       if (!screened_out(lg, kMaxLogitU, a) && !screened_out(lg, logit_u_of(u), a)) {
         const ClosureDraw d = closure_draw(o0, o1, u, a);
         if (d.z != 0.0) {
-          q5[4] = static_cast<float>(q5[4] + a.a * a.a * static_cast<double>(q5[0]) * d.z * a.e0_code);
+          const double e_sn = a.a * a.a * static_cast<double>(q5[0]) * d.z * a.e0_code;
+          if (sn_out)
+            inj = static_cast<float>(e_sn);
+          else
+            q5[4] = static_cast<float>(q5[4] + e_sn);
           star[c] = static_cast<float>(star[c] + d.z);
+          zc = static_cast<float>(d.z);
         }
       }
+      if (znew) znew[c] = zc;
+      if (sn_out) sn_out[c] = inj;
 #pragma unroll
       for (int k = (q == q_in ? 1 : 0); k < 5; ++k) q[k * nc + c] = q5[k];
-      vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
+      if (partial) vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
     }
     __syncthreads();
   }
-  block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
+  if (partial) block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
 }
 
 // Adjoint of the closure's source update at the kicked state q: lam (in: after, out:
 // before); partial[0|1][block] = dL/d(eps_sf | delta_c), which enter through the inputs.
 __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
     const float* __restrict__ q, float* __restrict__ lam, double* partial, long long nc,
-    const StepScal* __restrict__ tab) {
+    const StepScal* __restrict__ tab, const float* __restrict__ lam_inj) {
   const StepScal& sc = tab[blockIdx.y];
   if (!sc.active) {
     zero_partials<2>(partial);
@@ -565,6 +667,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
   const SourceArgs& a = sc.src;
   q += blockIdx.y * 5 * nc;
   lam += blockIdx.y * 5 * nc;
+  if (lam_inj) lam_inj += blockIdx.y * nc;
   __shared__ uint4 fr[mlp::kFrAll * 64];
   __shared__ __attribute__((aligned(16))) float bias[mlp::kBias];
   __shared__ float stage[kRedThreads / 64][64][kStage];
@@ -588,7 +691,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
     __syncthreads();
     // per half of 32 cells: the forward with its derivatives, dL/do of those cells (their
     // lanes), the backward; the network runs forward once per cell
-    double le = 0.0, z = 0.0;
+    double le = 0.0, li = 0.0, z = 0.0;   // adjoints of the energy and of the injection
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const float (*sh)[kStage] = stage[wave] + 32 * half;
@@ -611,12 +714,13 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
           const float lg = closure_logit_estimate(o0, o1, a);
           const double u = screened_out(lg, kMaxLogitU, a) ? 0.5 : starform_uniform(c, a);
           le = lam[4 * nc + c];
+          li = lam_inj ? lam_inj[c] : le;
           if (!screened_out(lg, kMaxLogitU, a) && !screened_out(lg, logit_u_of(u), a)) {
             const ClosureDraw d = closure_draw(o0, o1, u, a);
             z = d.z;
-            if (a.mode != 1 && le != 0.0) {
+            if (a.mode != 1 && li != 0.0) {
               const double dz = d.z * (1.0 - d.z) / a.tau / (1.0 - d.pi0);   // dz / dln(pi0)
-              const double coef = le * K * q5[0] * dz;
+              const double coef = li * K * q5[0] * dz;
               go0 = coef * d.x / expm1(d.x);                // dln p_sf / do0
               go1 = o1 < 0.0f ? coef : 0.0;                  // dln gate / do1
             }
@@ -658,7 +762,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
       for (int d = 0; d < 3; ++d) u[d] = q5[1 + d] * ia * ir;
       const double ke = 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
       const double ge = floored ? 0.0 : gx1 / (5.0 * e_raw);   // dL/de
-      lam[c] = static_cast<float>(lam[c] + le * K * z + gx0 / (5.0 * rho) + ge * (ke - e_raw) * ir);
+      lam[c] = static_cast<float>(lam[c] + li * K * z + gx0 / (5.0 * rho) + ge * (ke - e_raw) * ir);
 #pragma unroll
       for (int d = 0; d < 3; ++d)
         lam[(1 + d) * nc + c] = static_cast<float>(lam[(1 + d) * nc + c] + ge * (-u[d] * ia * ir));
@@ -890,20 +994,46 @@ void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4
 // The closure kernels are chosen per launch: every sample of a batch has the same closure.
 void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4* g4,
                        float* star, float* q_kicked, double gamma, double* block_max,
-                       const Batch& b, bool closure) {
+                       const Batch& b, bool closure, float* znew, float* sn_out) {
   if (!b.tab) throw ArgError("closing pass: step table required");
-  if ((star == nullptr) != (block_max == nullptr) || (closure && !star))
-    throw ArgError("closing pass: star field and CFL maxima go together (both for the closure)");
+  if ((star == nullptr && block_max != nullptr) || (closure && !star))
+    throw ArgError("closing pass: CFL maxima need the star field (so does the closure)");
+  if ((star == nullptr && znew != nullptr) || (block_max != nullptr && sn_out != nullptr))
+    throw ArgError("closing pass: new stars need the star field; a smoothed injection takes "
+                   "the CFL maxima to the injection pass");
   const dim3 grid(sum_blocks(b.nc()), b.S);
   if (closure)
     hipLaunchKernelGGL(close_step_mlp_kernel, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
-                       q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab);
+                       q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab, znew, sn_out);
   else if (star)
     hipLaunchKernelGGL(close_step_kernel<true>, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
-                       q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab);
+                       q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab, znew, sn_out);
   else
     hipLaunchKernelGGL(close_step_kernel<false>, grid, dim3(kRedThreads), 0, st, q_in, q, g4,
-                       star, q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab);
+                       star, q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab, znew,
+                       sn_out);
+  DH_LAUNCH_CHECK();
+}
+
+static int log2_int(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+void launch_sn_inject(hipStream_t st, const float* sn, float* q, double gamma, double* block_max,
+                      const Batch& b) {
+  if (!b.tab) throw ArgError("supernova injection: step table required");
+  hipLaunchKernelGGL(sn_inject_kernel, dim3(sum_blocks(b.nc()), b.S), dim3(kRedThreads), 0, st,
+                     sn, q, gamma * (gamma - 1.0), block_max, b.n, log2_int(b.n), b.tab);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_smooth27(hipStream_t st, const float* in, long long in_stride, float* out,
+                     const Batch& b) {
+  if (!b.tab) throw ArgError("smoothing: step table required");
+  hipLaunchKernelGGL(smooth27_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st, in,
+                     in_stride, out, b.n, log2_int(b.n), b.tab);
   DH_LAUNCH_CHECK();
 }
 
@@ -914,26 +1044,29 @@ int source_vjp_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n *
 int cfl_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n * n); }
 
 void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, double* partials,
-                       const Batch& b) {
+                       const Batch& b, const float* lam_inj) {
   if (!b.tab) throw ArgError("source adjoint: step table required");
   const dim3 grid(source_vjp_blocks(b.n), b.S);
   hipLaunchKernelGGL(source_vjp_mlp_kernel, grid, dim3(kRedThreads), 0, st, q_before, lam_q,
-                     partials, b.nc(), b.tab);
+                     partials, b.nc(), b.tab, lam_inj);
   DH_LAUNCH_CHECK();
 }
 
 void launch_source_kick_vjp(hipStream_t st, const float* q_kick, const float4* g4,
                             float* lam_q, float* lam_g, double* partials, const Batch& b,
-                            const float* q_open, float* lam_g_open, const StepScal* tab_open) {
+                            const float* q_open, float* lam_g_open, const StepScal* tab_open,
+                            const float* lam_inj) {
   if (!b.tab) throw ArgError("closing pass adjoint: step table required");
   const dim3 grid(source_vjp_blocks(b.n), b.S);
   if (q_open) {
     if (!lam_g_open || !tab_open) throw ArgError("closing pass adjoint: opening kick operands");
     hipLaunchKernelGGL(source_kick_vjp_kernel<true>, grid, dim3(kRedThreads), 0, st, q_kick, g4,
-                       lam_q, lam_g, partials, b.nc(), b.tab, q_open, lam_g_open, tab_open);
+                       lam_q, lam_g, partials, b.nc(), b.tab, q_open, lam_g_open, tab_open,
+                       lam_inj);
   } else {
     hipLaunchKernelGGL(source_kick_vjp_kernel<false>, grid, dim3(kRedThreads), 0, st, q_kick, g4,
-                       lam_q, lam_g, partials, b.nc(), b.tab, nullptr, nullptr, nullptr);
+                       lam_q, lam_g, partials, b.nc(), b.tab, nullptr, nullptr, nullptr,
+                       lam_inj);
   }
   DH_LAUNCH_CHECK();
 }

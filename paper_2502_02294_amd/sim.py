@@ -8,12 +8,12 @@ import torch
 
 from . import _lib
 from ._lib import (FIELD_FLUX, FIELD_MOM, FIELD_PHI, FIELD_POS, FIELD_Q, FIELD_RHO, FIELD_STAR,
-                   FIELD_TEMP, Config, Params, check, lib)
+                   FIELD_STAR_DM, FIELD_TEMP, Config, Params, check, lib)
 
 _FIELD_SHAPE = {FIELD_Q: (5,), FIELD_RHO: (), FIELD_POS: (3,), FIELD_MOM: (3,), FIELD_STAR: (),
-                FIELD_PHI: (), FIELD_TEMP: (), FIELD_FLUX: ()}
+                FIELD_PHI: (), FIELD_TEMP: (), FIELD_FLUX: (), FIELD_STAR_DM: ()}
 FIELDS = {"q": FIELD_Q, "rho": FIELD_RHO, "pos": FIELD_POS, "mom": FIELD_MOM, "star": FIELD_STAR,
-          "phi": FIELD_PHI, "temp": FIELD_TEMP, "flux": FIELD_FLUX}
+          "phi": FIELD_PHI, "temp": FIELD_TEMP, "flux": FIELD_FLUX, "star_dm": FIELD_STAR_DM}
 
 
 def default_config(**kw):
@@ -248,6 +248,18 @@ class Sim:
         self._check(lib().dh_backward(self._h, gr, _ptr(gw), gp))
         vals = list(gp)
         return gw, (vals if self.S == 1 else [vals[4 * i:4 * i + 4] for i in range(self.S)])
+
+    def set_kernel_timing(self, family):
+        """Time the launches of one kernel family (_lib.KTIME_*; -1 stops) inside steps and
+        reverse passes with HIP events on the handle's stream."""
+        self._check(lib().dh_set_kernel_timing(self._h, family))
+
+    def kernel_timing(self):
+        """(launches timed since the last call, their mean duration in seconds)."""
+        self._stream()
+        cnt, ms = ctypes.c_int32(), ctypes.c_double()
+        self._check(lib().dh_get_kernel_timing(self._h, ctypes.byref(cnt), ctypes.byref(ms)))
+        return cnt.value, ms.value * 1e-3
 
     def conservation(self):
         self._stream()

@@ -57,7 +57,8 @@ def gpu_config(ocfg, **kw):
                           h=ocfg.h, sigma8=ocfg.sigma8, n_s=ocfg.n_s, gamma=ocfg.gamma, mu=ocfg.mu,
                           a_init=ocfg.a_init, t_init=ocfg.t_init, cfl=ocfg.cfl,
                           dlna_max=ocfg.dlna_max, t_floor=ocfg.t_floor, subgrid=ocfg.subgrid,
-                          tau=ocfg.tau, sf_seed=ocfg.sf_seed, kdk=ocfg.kdk, **kw)
+                          tau=ocfg.tau, sf_seed=ocfg.sf_seed, kdk=ocfg.kdk,
+                          sn_smooth=int(ocfg.sn_smooth), star_dm=int(ocfg.star_dm), **kw)
 
 
 def gpu_params(p):
@@ -250,3 +251,23 @@ def sweep_vjp_on_gpu_branches(q, lam, gpu, axis, dt, a1, a2, gamma, e_floor, rel
             line_of(ref, axis, i, j)[...] = g.numpy()
             total += len(x[4])
     return ref, len(lines), total
+
+
+def closure_oracle_gradient(ocfg, prm, w, target, sched):
+    """Oracle autograd of the flux loss: (loss, dL/dwhite, dL/d(A, beta, eps_sf, delta_c),
+    sums over cells of |per-cell terms| of dL/d(eps_sf, delta_c)).  The two star-formation
+    parameters enter as per-cell copies, so that their gradient's per-cell terms are seen."""
+    n = ocfg.n
+    w64 = torch.from_numpy(w).double().requires_grad_(True)
+    th = torch.tensor([prm.A, prm.beta], requires_grad=True)
+    ef = torch.full((n, n, n), prm.eps_sf, requires_grad=True)
+    dc = torch.full((n, n, n), prm.delta_c, requires_grad=True)
+    p2 = osim.Params(A=th[0], beta=th[1], eps_sf=ef, delta_c=dc)
+    st = osim.initial_state(w64, ocfg)
+    st, _ = osim.run(st, ocfg, p2, schedule=sched)
+    assert float(st.star.sum()) > 1.0
+    loss = osim.loss(st, torch.from_numpy(target).double(), ocfg, th[0], th[1])
+    gw, gab, ge, gd = torch.autograd.grad(loss, (w64, th, ef, dc))
+    gp = np.array([float(gab[0]), float(gab[1]), float(ge.sum()), float(gd.sum())])
+    mag = np.array([abs(gp[0]), abs(gp[1]), float(ge.abs().sum()), float(gd.abs().sum())])
+    return float(loss), gw.numpy(), gp, mag

@@ -22,7 +22,8 @@ import torch
 from dataclasses import replace
 
 import synth_inputs as si
-from gpu_helpers import gpu_config, gpu_params, load_state, rel_l2, rounded_state, to_gpu, to_np
+from gpu_helpers import (closure_oracle_gradient, gpu_config, gpu_params, load_state, rel_l2,
+                         rounded_state, to_gpu, to_np)
 from oracle import mlp as omlp, sim as osim, subgrid
 
 pytestmark = pytest.mark.gpu
@@ -198,26 +199,6 @@ def test_closure_step_matches_oracle(dhp):
         assert rel_l2(star, ref.star.numpy()) < tol_star, (bf16, rel_l2(star, ref.star.numpy()))
 
 
-def _closure_oracle_gradient(ocfg, prm, w, target, sched):
-    """Oracle autograd of the flux loss: (loss, dL/dwhite, dL/d(A, beta, eps_sf, delta_c),
-    sums over cells of |per-cell terms| of dL/d(eps_sf, delta_c)).  The two star-formation
-    parameters enter as per-cell copies, so that their gradient's per-cell terms are seen."""
-    n = ocfg.n
-    w64 = torch.from_numpy(w).double().requires_grad_(True)
-    th = torch.tensor([prm.A, prm.beta], requires_grad=True)
-    ef = torch.full((n, n, n), prm.eps_sf, requires_grad=True)
-    dc = torch.full((n, n, n), prm.delta_c, requires_grad=True)
-    p2 = osim.Params(A=th[0], beta=th[1], eps_sf=ef, delta_c=dc)
-    st = osim.initial_state(w64, ocfg)
-    st, _ = osim.run(st, ocfg, p2, schedule=sched)
-    assert float(st.star.sum()) > 1.0
-    loss = osim.loss(st, torch.from_numpy(target).double(), ocfg, th[0], th[1])
-    gw, gab, ge, gd = torch.autograd.grad(loss, (w64, th, ef, dc))
-    gp = np.array([float(gab[0]), float(gab[1]), float(ge.sum()), float(gd.sum())])
-    mag = np.array([abs(gp[0]), abs(gp[1]), float(ge.abs().sum()), float(gd.abs().sum())])
-    return float(loss), gw.numpy(), gp, mag
-
-
 def test_closure_gradient_matches_oracle_autograd(dhp):
     n = 16
     net = dhp.Mlp(seed=9)
@@ -240,7 +221,7 @@ def test_closure_gradient_matches_oracle_autograd(dhp):
     gp = np.array(gp)
     # the FP64 network, then the bfloat16 model of the GPU's arithmetic
     for bf16, tol_w, tol_sf in ((False, 1e-2, FP64_PARAM), (True, 1e-2, BWD_TOL)):
-        L, gw_ref, gp_ref, mag = _closure_oracle_gradient(_closure_config(ocfg0, theta, bf16),
+        L, gw_ref, gp_ref, mag = closure_oracle_gradient(_closure_config(ocfg0, theta, bf16),
                                                           prm, w, target, sched)
         assert abs(lval - L) < 1e-4 * L, (bf16, lval, L)
         assert rel_l2(gw, gw_ref) < tol_w, (bf16, rel_l2(gw, gw_ref))
