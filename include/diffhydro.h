@@ -117,11 +117,13 @@ typedef struct dh_params {
 /* Fields for dh_get_field / dh_set_field.  Sizes in floats: Q = 5 n^3, POS and MOM = 3 n^3,
  * the rest n^3.  TEMP (get only) is the gas temperature [K] from the floored energy.
  * STAR_DM: the particles' auxiliary field of read-out stars, in particle order (needs
- * cfg.star_dm; zeroed by the initial conditions). */
+ * cfg.star_dm; zeroed by the initial conditions).  OBS_TEMP (get only): the observable of
+ * the field-level inference, O = (rho / rho_mean_gas) T [K], the gas-mass-weighted
+ * temperature (Sec. 3.2). */
 typedef enum dh_field {
     DH_FIELD_Q = 0, DH_FIELD_RHO = 1, DH_FIELD_POS = 2, DH_FIELD_MOM = 3,
     DH_FIELD_STAR = 4, DH_FIELD_PHI = 5, DH_FIELD_TEMP = 6, DH_FIELD_FLUX = 7,
-    DH_FIELD_STAR_DM = 8
+    DH_FIELD_STAR_DM = 8, DH_FIELD_OBS_TEMP = 9
 } dh_field;
 
 typedef struct dh_sim dh_sim;
@@ -221,11 +223,36 @@ int dh_get_store_info(const dh_sim* sim, int32_t* taped, int32_t* sorted);
  * current state; FP64 reduction.  d_target[n^3] device (per sample); loss_out: one value
  * per sample. */
 int dh_loss(dh_sim* sim, const float* d_target, double* loss_out);
+/* Observables of the paper's applications (Sec. 3) on the current state.
+ * Baryon power spectrum (the statistic of the parameter inference): with the overdensity
+ * delta_b = rho / rho_mean_gas - 1 and its unnormalised transform X_m over the n^3 integer
+ * wavenumber vectors m, P_b = (L^3 / n^6) sum_{m in bin b} |X_m|^2 / W_b [(Mpc/h)^3], where
+ * bin b = 0..nbins-1 holds the modes whose |m| rounds to b + 1 (no |m| is a half-integer)
+ * and W_b is their number; 1 <= nbins <= n/2.  pk_out[S][nbins] (host); k_out[nbins] the
+ * nominal wavenumbers 2 pi (b + 1) / L [h/Mpc] and nmodes_out[nbins] = W_b, either may be
+ * NULL.  FP64 sums in a fixed order (reproducible bit for bit). */
+int dh_power_spectrum(dh_sim* sim, int32_t nbins, double* pk_out, double* k_out,
+                      double* nmodes_out);
+/* Gaussian loss of a mock spectrum, L = 1/2 (P - P_obs)^T C^-1 (P - P_obs) with pk_obs
+ * [S][nbins] and the inverse covariance cinv [nbins][nbins] (host, row-major, shared by the
+ * samples; the paper estimates C from independent boxes); loss_out[S].  A following
+ * dh_backward(NULL) differentiates it (dL/dA = dL/dbeta = 0). */
+int dh_power_loss(dh_sim* sim, int32_t nbins, const double* pk_obs, const double* cinv,
+                  double* loss_out);
+/* Negative log-posterior of the field-level inference (Sec. 3.2):
+ * L = 1/2 sum_i (d_i - O_i)^2 / N_i + 1/2 sum_i w_i^2 with O of DH_FIELD_OBS_TEMP, the data
+ * d_data, pixel noise variances d_noise_var and the white noise d_white of the run (the
+ * initial phases, standard-normal prior), all device [S][n^3] (copied).  loss_out[S].  A
+ * following dh_backward(NULL) differentiates it, prior included. */
+int dh_fli_loss(dh_sim* sim, const float* d_data, const float* d_noise_var,
+                const float* d_white, double* loss_out);
+
 /* Reverse pass of the last dh_forward.  d_grad_rho: adjoint of the final gas density
- * (device n^3 per sample) or NULL for the gradient of the last dh_loss (each sample's own
- * loss).  Outputs: d_grad_white[n^3] per sample (device) and grad_params[4] per sample =
- * dL/d(A, beta, eps_sf, delta_c) (host, FP64, summed over steps in a fixed order).  The time
- * schedule is held fixed.  DH_E_STATE if no forward (or no loss, with NULL) precedes it. */
+ * (device n^3 per sample) or NULL for the gradient of the last loss call (dh_loss,
+ * dh_power_loss or dh_fli_loss; each sample's own loss).  Outputs: d_grad_white[n^3] per
+ * sample (device) and grad_params[4] per sample = dL/d(A, beta, eps_sf, delta_c) (host, FP64,
+ * summed over steps in a fixed order).  The time schedule is held fixed.  DH_E_STATE if no
+ * forward (or no loss, with NULL) precedes it. */
 int dh_backward(dh_sim* sim, const float* d_grad_rho, float* d_grad_white, double* grad_params);
 
 /* Kernel timing for measurement.  While a family is set, every launch of that kernel family

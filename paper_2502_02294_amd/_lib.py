@@ -20,7 +20,7 @@ KDK_PLAIN, KDK_FASTPM = 0, 1
 KTIME_SWEEP_KICK, KTIME_SWEEP, KTIME_SWEEP_VJP = 0, 1, 2
 MLP_NPARAMS = 8834
 (FIELD_Q, FIELD_RHO, FIELD_POS, FIELD_MOM, FIELD_STAR, FIELD_PHI, FIELD_TEMP, FIELD_FLUX,
- FIELD_STAR_DM) = range(9)
+ FIELD_STAR_DM, FIELD_OBS_TEMP) = range(10)
 
 
 class Config(ctypes.Structure):
@@ -92,6 +92,9 @@ _SIGNATURES = {
     "dh_forward": (I, [P, P, D, ctypes.POINTER(I)]),
     "dh_loss": (I, [P, P, ctypes.POINTER(D)]),
     "dh_backward": (I, [P, P, P, ctypes.POINTER(D)]),
+    "dh_power_spectrum": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]),
+    "dh_power_loss": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]),
+    "dh_fli_loss": (I, [P, P, P, P, ctypes.POINTER(D)]),
     "dh_set_kernel_timing": (I, [P, I]),
     "dh_get_kernel_timing": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D)]),
     "dh_conservation": (I, [P, ctypes.POINTER(D)]),

@@ -8,7 +8,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["k_hydro.hip", "k_pm.hip", "k_fft.hip", "k_point.hip", "k_mlp.hip", "dh_api.hip",
+SOURCES = ["k_hydro.hip", "k_pm.hip", "k_fft.hip", "k_point.hip", "k_mlp.hip", "k_observe.hip",
+           "dh_api.hip",
            "mlp_api.hip", "noalloc_api.hip"]
 LIB = os.path.join(HERE, "libdiffhydro.so")
 ARCH = os.environ.get("DH_OFFLOAD_ARCH", "gfx950")

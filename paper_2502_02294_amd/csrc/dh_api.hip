@@ -191,6 +191,21 @@ struct dh_sim {
   std::vector<TapeStep> tape;
   std::vector<StepPlan> fwd_plans;   // plans of the last dh_forward, in order
   bool have_forward = false, have_loss = false;
+  // which loss dh_backward(NULL) differentiates: the flux MSE (dh_loss), the Gaussian
+  // power-spectrum loss (dh_power_loss) or the field-level posterior (dh_fli_loss)
+  enum { kLossFlux = 0, kLossPower = 1, kLossFli = 2 };
+  int loss_kind = kLossFlux;
+  // power spectrum: block partials, bin counts of the last nbins, the loss's adjoint weights
+  double* pk_part = nullptr;
+  int pk_part_bins = 0;
+  std::vector<double> pk_counts;
+  int pk_counts_bins = 0;
+  std::vector<float> pk_g;       // [S][nbins] spectral weights of the adjoint
+  float* d_pk_g = nullptr;
+  int pk_loss_bins = 0;
+  // field-level posterior: data, noise variance and white noise (copies), [S][n^3] each
+  float *fli_data = nullptr, *fli_nvar = nullptr, *fli_white = nullptr;
+  double* fli_part = nullptr;
   int fwd_steps = 0;
   float* loss_target = nullptr;
 
@@ -758,6 +773,89 @@ void initial_conditions(dh_sim* s, const float* d_white) {
 // Plans the next step of every sample: the next schedule entry, or the CFL dt (eq. dt) with
 // the dln a cap, clipped to land on t_end (< 0: none).  A sample at t_end, or whose replayed
 // schedule is used up (with stop_at_replay_end), sits out.  *any = whether a sample moves.
+// the current scale factor of every sample into d_acur
+void upload_scale_factors(dh_sim* s) {
+  sync(s);
+  std::memcpy(s->host_out, s->a.data(), s->S * sizeof(double));
+  DH_HIP(hipMemcpyAsync(s->d_acur, s->host_out, s->S * sizeof(double), hipMemcpyHostToDevice,
+                        s->st));
+}
+
+// Mode counts W_b (full spectrum) of bins 1..nbins of the rounded |m|: host, exact, cached.
+const std::vector<double>& pk_counts(dh_sim* s, int nbins) {
+  if (s->pk_counts_bins == nbins) return s->pk_counts;
+  const int n = s->n;
+  std::vector<double> w(nbins, 0.0);
+  for (int kz = 0; kz < n; ++kz) {
+    const long long mz = kz <= n / 2 ? kz : kz - n;
+    for (int ky = 0; ky < n; ++ky) {
+      const long long my = ky <= n / 2 ? ky : ky - n;
+      for (int kx = 0; kx <= n / 2; ++kx) {
+        const long long m2 = static_cast<long long>(kx) * kx + my * my + mz * mz;
+        long long j = static_cast<long long>(std::sqrt(static_cast<double>(m2)) + 0.5);
+        if (4 * m2 >= (2 * j + 1) * (2 * j + 1)) ++j;
+        if (j > 0 && 4 * m2 < (2 * j - 1) * (2 * j - 1)) --j;
+        if (j >= 1 && j <= nbins) w[j - 1] += (kx == 0 || kx == n / 2) ? 1.0 : 2.0;
+      }
+    }
+  }
+  s->pk_counts = w;
+  s->pk_counts_bins = nbins;
+  return s->pk_counts;
+}
+
+// half spectrum of each sample's gas density into s->spec (forward, unnormalised)
+void density_spectrum(dh_sim* s, const Batch& b) {
+  dh::fft_forward_xy(s->st, s->q, s->spec, s->tw, b, 5 * s->nc);
+  dh::fft_zpass_forward(s->st, s->spec, s->spec, s->tw, b);
+}
+
+// power spectrum of the current gas overdensity: pk[s][b] (FP64, host)
+void power_spectrum(dh_sim* s, int nbins, std::vector<double>& pk) {
+  const int S = s->S;
+  const int nblk = dh::pk_blocks(s->n);
+  if (s->pk_part_bins < nbins) {
+    if (s->pk_part) s->release(s->pk_part);
+    s->pk_part = nullptr;
+    s->pk_part = s->alloc<double>(static_cast<long long>(S) * nbins * nblk);
+    s->pk_part_bins = nbins;
+  }
+  const Batch b = batch(s, nullptr);
+  density_spectrum(s, b);
+  dh::launch_pk_bin(s->st, s->spec, nbins, s->pk_part, b);
+  std::vector<double> sums(static_cast<size_t>(S) * nbins);
+  double* d_sums = s->red;   // S nbins <= 8 red_blocks S + 8 doubles
+  dh::launch_reduce_sum(s->st, s->pk_part, nblk, nblk, S * nbins, d_sums);
+  DH_HIP(hipMemcpyAsync(sums.data(), d_sums, sums.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        s->st));
+  sync(s);
+  const std::vector<double>& w = pk_counts(s, nbins);
+  const double n3 = static_cast<double>(s->nc);
+  // P_b = (L^3 / n^6) sum |X|^2 / W_b of delta = rho / rho_mean - 1 (X of rho / rho_mean: the
+  // mean only enters the mode m = 0, outside every bin)
+  const double c = s->cfg.box * s->cfg.box * s->cfg.box / (n3 * n3) / (s->f_b * s->f_b);
+  pk.assign(sums.size(), 0.0);
+  for (int i = 0; i < S; ++i)
+    for (int k = 0; k < nbins; ++k)
+      pk[static_cast<size_t>(i) * nbins + k] = c * sums[static_cast<size_t>(i) * nbins + k] / w[k];
+}
+
+// adjoint of the power-spectrum loss into lam_rho (component 0 of s->lq): with G_m = g_b c /
+// W_b, dL/drho_x = 2 sum_m G_m Re(X_m e^{i k_m x}), i.e. twice the unnormalised inverse
+// transform of G X
+void power_loss_vjp(dh_sim* s) {
+  const Batch b = batch(s, nullptr);
+  const int nbins = s->pk_loss_bins;
+  if (!s->d_pk_g) s->d_pk_g = s->alloc<float>(static_cast<long long>(s->S) * (s->n / 2));
+  DH_HIP(hipMemcpyAsync(s->d_pk_g, s->pk_g.data(), s->pk_g.size() * sizeof(float),
+                        hipMemcpyHostToDevice, s->st));
+  density_spectrum(s, b);
+  dh::launch_pk_scale(s->st, s->spec, s->d_pk_g, nbins, b);
+  dh::fft_zpass_inverse(s->st, s->spec, s->tw, b);
+  dh::fft_inverse_yx(s->st, s->spec, s->lq, s->tw, 2.0f, b, 5 * s->nc);
+  sync(s);   // pk_g is host memory read by the copy above
+}
+
 int plan_step(dh_sim* s, double t_end, bool stop_at_replay_end, StepPlan& sp, bool* any) {
   sp.step = s->step;
   for (int k = 0; k < 3; ++k) sp.axes[k] = kStrang[s->step % 6][k];
@@ -1480,6 +1578,11 @@ int dh_get_field(dh_sim* s, dh_field f, float* d_out) {
         if (!s->aux) return fail(s, DH_E_INVAL, "the star read-out needs cfg.star_dm");
         copy_d2d(s, d_out, s->aux, s->np * S);
         break;
+      case DH_FIELD_OBS_TEMP:
+        for (int i = 0; i < S; ++i)
+          dh::launch_fli_obs(s->st, s->q + 5 * nc * i, s->a[i], 1.0 / s->f_b, s->e_floor,
+                             s->t_per_e, d_out + nc * i, nc);
+        break;
       case DH_FIELD_PHI:
         if (!s->phi_valid) refresh_potential(s);
         copy_d2d(s, d_out, s->phi, nc * S);
@@ -1656,6 +1759,7 @@ int dh_loss(dh_sim* s, const float* d_target, double* loss_out) {
     if (!s->loss_target) s->loss_target = s->alloc<float>(s->nc * s->S);
     copy_d2d(s, s->loss_target, d_target, s->nc * s->S);
     s->have_loss = s->have_forward;
+    s->loss_kind = dh_sim::kLossFlux;
     return DH_OK;
   });
 }
@@ -1715,6 +1819,12 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     std::vector<double> gA(S, 0.0), gB(S, 0.0);
     if (d_grad_rho) {
       for (int i = 0; i < S; ++i) copy_d2d(s, s->lq + 5 * nc * i, d_grad_rho + nc * i, nc);
+    } else if (s->loss_kind == dh_sim::kLossPower) {
+      power_loss_vjp(s);
+    } else if (s->loss_kind == dh_sim::kLossFli) {
+      upload_scale_factors(s);
+      dh::launch_fli(s->st, s->q, s->fli_data, s->fli_nvar, s->fli_white, s->d_acur,
+                     1.0 / s->f_b, s->e_floor, s->t_per_e, nullptr, s->lq, batch(s, nullptr));
     } else {
       const int nb = s->red_blocks;
       dh::launch_loss_vjp(s->st, s->q, s->loss_target, s->prm.A, s->prm.beta,
@@ -1778,6 +1888,10 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     }
     if (nsteps > 0) finish_first_kick(s, s->taped > 0 ? s->ftape[0] : s->tape[0]);
     ic_vjp(s, d_grad_white);
+    // the field-level posterior's prior 1/2 |w|^2 adds w
+    if (!d_grad_rho && s->loss_kind == dh_sim::kLossFli)
+      dh::launch_axpy(s->st, d_grad_white, s->fli_white, 1.0f, nc, nc, nc, false,
+                      batch(s, nullptr));
     // restore the final state of the forward run
     unstash_state(s);
     // parameter gradients: fixed-order host sum of the per-step FP64 partials
@@ -1799,6 +1913,82 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
       grad_params[4 * i + 2] = ge;
       grad_params[4 * i + 3] = gd;
     }
+    return DH_OK;
+  });
+}
+
+int dh_power_spectrum(dh_sim* s, int32_t nbins, double* pk_out, double* k_out,
+                      double* nmodes_out) {
+  if (!s || !pk_out || nbins < 1 || nbins > s->n / 2) return DH_E_INVAL;
+  return guarded(s, [&]() -> int {
+    std::vector<double> pk;
+    power_spectrum(s, nbins, pk);
+    std::memcpy(pk_out, pk.data(), pk.size() * sizeof(double));
+    const std::vector<double>& w = pk_counts(s, nbins);
+    for (int k = 0; k < nbins; ++k) {
+      if (k_out) k_out[k] = 2.0 * M_PI * (k + 1) / s->cfg.box;
+      if (nmodes_out) nmodes_out[k] = w[k];
+    }
+    return DH_OK;
+  });
+}
+
+int dh_power_loss(dh_sim* s, int32_t nbins, const double* pk_obs, const double* cinv,
+                  double* loss_out) {
+  if (!s || !pk_obs || !cinv || !loss_out || nbins < 1 || nbins > s->n / 2) return DH_E_INVAL;
+  return guarded(s, [&]() -> int {
+    const int S = s->S;
+    std::vector<double> pk;
+    power_spectrum(s, nbins, pk);
+    const std::vector<double>& w = pk_counts(s, nbins);
+    const double n3 = static_cast<double>(s->nc);
+    const double c = s->cfg.box * s->cfg.box * s->cfg.box / (n3 * n3) / (s->f_b * s->f_b);
+    s->pk_g.assign(static_cast<size_t>(S) * nbins, 0.0f);
+    for (int i = 0; i < S; ++i) {
+      const double* p = pk.data() + static_cast<size_t>(i) * nbins;
+      const double* o = pk_obs + static_cast<size_t>(i) * nbins;
+      double L = 0.0;
+      for (int a = 0; a < nbins; ++a) {
+        double g = 0.0;   // (C^-1 (P - P_obs))_a
+        for (int k = 0; k < nbins; ++k) g += cinv[static_cast<size_t>(a) * nbins + k] * (p[k] - o[k]);
+        L += 0.5 * (p[a] - o[a]) * g;
+        s->pk_g[static_cast<size_t>(i) * nbins + a] = static_cast<float>(g * c / w[a]);
+      }
+      loss_out[i] = L;
+    }
+    s->pk_loss_bins = nbins;
+    s->have_loss = s->have_forward;
+    s->loss_kind = dh_sim::kLossPower;
+    return DH_OK;
+  });
+}
+
+int dh_fli_loss(dh_sim* s, const float* d_data, const float* d_noise_var, const float* d_white,
+                double* loss_out) {
+  if (!s || !d_data || !d_noise_var || !d_white || !loss_out) return DH_E_INVAL;
+  return guarded(s, [&]() -> int {
+    const int S = s->S;
+    const long long nc = s->nc;
+    if (!s->fli_data) {
+      s->fli_data = s->alloc<float>(nc * S);
+      s->fli_nvar = s->alloc<float>(nc * S);
+      s->fli_white = s->alloc<float>(nc * S);
+      s->fli_part = s->alloc<double>(static_cast<long long>(dh::fli_blocks(nc)) * S);
+    }
+    copy_d2d(s, s->fli_data, d_data, nc * S);
+    copy_d2d(s, s->fli_nvar, d_noise_var, nc * S);
+    copy_d2d(s, s->fli_white, d_white, nc * S);
+    upload_scale_factors(s);
+    const int nb = dh::fli_blocks(nc);
+    dh::launch_fli(s->st, s->q, s->fli_data, s->fli_nvar, s->fli_white, s->d_acur, 1.0 / s->f_b,
+                   s->e_floor, s->t_per_e, s->fli_part, nullptr, batch(s, nullptr));
+    dh::launch_reduce_sum(s->st, s->fli_part, nb, nb, S, s->red_out);
+    DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, S * sizeof(double), hipMemcpyDeviceToHost,
+                          s->st));
+    sync(s);
+    for (int i = 0; i < S; ++i) loss_out[i] = s->host_out[i];
+    s->have_loss = s->have_forward;
+    s->loss_kind = dh_sim::kLossFli;
     return DH_OK;
   });
 }

@@ -146,6 +146,23 @@ void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* t
                   bool transpose, double amp, double om_h, double n_s, double kphys,
                   bool forward_first, bool inverse_after, bool accumulate, const Batch& b);
 
+// ---- observables of Sec. 3 (k_observe.hip)
+// per-block sums of w |X|^2 by bin of the rounded |m| (bins 1..nbins) of a half spectrum
+// [S][n][n][n/2+1]: partial[(s nbins + b) pk_blocks(n) + block]
+int pk_blocks(int n);
+void launch_pk_bin(hipStream_t st, const float2* spec, int nbins, double* partial, const Batch& b);
+// spec[s][m] *= g[s][bin(m) - 1] (0 outside bins 1..nbins)
+void launch_pk_scale(hipStream_t st, float2* spec, const float* g, int nbins, const Batch& b);
+// field-level loss 1/2 sum (d - O)^2 / N + 1/2 sum w^2, O = rho irm T(e): per-block partials
+// partial[s fli_blocks(nc) + block] (partial may be null) and, with lam, dL/dQ of the data
+// term into lam[s][5][nc]; a_cur[s] the scale factor of each sample (device)
+int fli_blocks(long long nc);
+void launch_fli(hipStream_t st, const float* q, const float* data, const float* nvar,
+                const float* white, const double* a_cur, double irm, double efloor,
+                double t_per_e, double* partial, float* lam, const Batch& b);
+void launch_fli_obs(hipStream_t st, const float* q, double a, double irm, double efloor,
+                    double t_per_e, float* out, long long nc);
+
 // ---- pointwise / reductions (k_point.hip)
 // (the opening gas half kick is applied inside the first sweep of a step: launch_sweep)
 void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4, float* lam_q,

@@ -7,13 +7,15 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (FIELD_FLUX, FIELD_MOM, FIELD_PHI, FIELD_POS, FIELD_Q, FIELD_RHO, FIELD_STAR,
-                   FIELD_STAR_DM, FIELD_TEMP, Config, Params, check, lib)
+from ._lib import (FIELD_FLUX, FIELD_MOM, FIELD_OBS_TEMP, FIELD_PHI, FIELD_POS, FIELD_Q,
+                   FIELD_RHO, FIELD_STAR, FIELD_STAR_DM, FIELD_TEMP, Config, Params, check, lib)
 
 _FIELD_SHAPE = {FIELD_Q: (5,), FIELD_RHO: (), FIELD_POS: (3,), FIELD_MOM: (3,), FIELD_STAR: (),
-                FIELD_PHI: (), FIELD_TEMP: (), FIELD_FLUX: (), FIELD_STAR_DM: ()}
+                FIELD_PHI: (), FIELD_TEMP: (), FIELD_FLUX: (), FIELD_STAR_DM: (),
+                FIELD_OBS_TEMP: ()}
 FIELDS = {"q": FIELD_Q, "rho": FIELD_RHO, "pos": FIELD_POS, "mom": FIELD_MOM, "star": FIELD_STAR,
-          "phi": FIELD_PHI, "temp": FIELD_TEMP, "flux": FIELD_FLUX, "star_dm": FIELD_STAR_DM}
+          "phi": FIELD_PHI, "temp": FIELD_TEMP, "flux": FIELD_FLUX, "star_dm": FIELD_STAR_DM,
+          "obs_temp": FIELD_OBS_TEMP}
 
 
 def default_config(**kw):
@@ -248,6 +250,41 @@ class Sim:
         self._check(lib().dh_backward(self._h, gr, _ptr(gw), gp))
         vals = list(gp)
         return gw, (vals if self.S == 1 else [vals[4 * i:4 * i + 4] for i in range(self.S)])
+
+    def power_spectrum(self, nbins):
+        """(P [S][nbins] or [nbins], k [nbins] in h/Mpc, mode counts [nbins]) of the gas
+        overdensity (dh_power_spectrum)."""
+        self._stream()
+        pk = (ctypes.c_double * (self.S * nbins))()
+        kk = (ctypes.c_double * nbins)()
+        nm = (ctypes.c_double * nbins)()
+        self._check(lib().dh_power_spectrum(self._h, nbins, pk, kk, nm))
+        vals = list(pk)
+        out = vals if self.S == 1 else [vals[i * nbins:(i + 1) * nbins] for i in range(self.S)]
+        return out, list(kk), list(nm)
+
+    def power_loss(self, pk_obs, cinv):
+        """Gaussian loss of the spectrum against pk_obs ([nbins] or [S][nbins]) with inverse
+        covariance cinv [nbins][nbins] (dh_power_loss); per-sample losses for S > 1."""
+        self._stream()
+        import numpy as np
+        obs = np.asarray(pk_obs, dtype=np.float64).reshape(-1)
+        nbins = obs.size // self.S
+        ci = np.ascontiguousarray(np.asarray(cinv, dtype=np.float64).reshape(nbins, nbins))
+        out = (ctypes.c_double * self.S)()
+        self._check(lib().dh_power_loss(
+            self._h, nbins, obs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            ci.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out))
+        return out[0] if self.S == 1 else list(out)
+
+    def fli_loss(self, data, noise_var, white):
+        """Field-level negative log-posterior (dh_fli_loss); device float32 tensors."""
+        self._stream()
+        out = (ctypes.c_double * self.S)()
+        m = self.S * self.nc
+        self._check(lib().dh_fli_loss(self._h, _ptr(data, numel=m), _ptr(noise_var, numel=m),
+                                      _ptr(white, numel=m), out))
+        return out[0] if self.S == 1 else list(out)
 
     def set_kernel_timing(self, family):
         """Time the launches of one kernel family (_lib.KTIME_*; -1 stops) inside steps and
