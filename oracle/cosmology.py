@@ -92,6 +92,50 @@ def bbks_transfer(q, log=math.log):
             * (1.0 + 3.89 * q + (16.1 * q) ** 2 + (5.46 * q) ** 3 + (6.71 * q) ** 4) ** -0.25)
 
 
+def eh_nowiggle_transfer(k, om, ob, h, tcmb=2.7255, log=math.log, sqrt=math.sqrt):
+    """Eisenstein & Hu (1998, Sec. 4.2) fitting formula without the baryon oscillations, the
+    transfer function family the paper sets its initial conditions with (Sec. 2.1).  k in
+    h/Mpc.  With theta = T_cmb / 2.7 K, w_m = Om h^2, w_b = Ob h^2, f_b = Ob / Om:
+        s       = 44.5 ln(9.83 / w_m) / sqrt(1 + 10 w_b^(3/4))  [Mpc]   (sound horizon fit)
+        alpha   = 1 - 0.328 ln(431 w_m) f_b + 0.38 ln(22.3 w_m) f_b^2
+        Gamma   = Om h (alpha + (1 - alpha) / (1 + (0.43 k h s)^4))
+        q       = k theta^2 / Gamma
+        T       = L / (L + C q^2),  L = ln(2 e + 1.8 q),  C = 14.2 + 731 / (1 + 62.5 q).
+    Works on floats, or on tensors with log=torch.log, sqrt=torch.sqrt (k > 0)."""
+    theta2 = (tcmb / 2.7) ** 2
+    wm, wb, fb = om * h * h, ob * h * h, ob / om
+    s = 44.5 * math.log(9.83 / wm) / math.sqrt(1.0 + 10.0 * wb ** 0.75)
+    alpha = 1.0 - 0.328 * math.log(431.0 * wm) * fb + 0.38 * math.log(22.3 * wm) * fb * fb
+    gamma = om * h * (alpha + (1.0 - alpha) / (1.0 + (0.43 * k * h * s) ** 4))
+    q = k * theta2 / gamma
+    big_l = log(2.0 * math.e + 1.8 * q)
+    big_c = 14.2 + 731.0 / (1.0 + 62.5 * q)
+    return big_l / (big_l + big_c * q * q)
+
+
+TRANSFER_BBKS, TRANSFER_EH = 0, 1
+
+
+def transfer(k, om, ob, h, kind, log=math.log, sqrt=math.sqrt):
+    """The matter transfer function of wavenumber k [h/Mpc]: BBKS of q = k / (Om h), or
+    Eisenstein & Hu without wiggles."""
+    if kind == TRANSFER_EH:
+        return eh_nowiggle_transfer(k, om, ob, h, log=log, sqrt=sqrt)
+    return bbks_transfer(k / (om * h), log=log)
+
+
+def omega_m_of_a(a, om):
+    """Omega_m(a) = Om a^-3 / E(a)^2."""
+    return om / (a ** 3 * hubble_e(a, om) ** 2)
+
+
+def lpt2_factors(a, om):
+    """Second-order LPT at scale factor a: (D2 / D1^2, f2) with the fits of Bouchet et al.
+    (1995), D2 = -(3/7) D1^2 Omega_m(a)^(-1/143) and f2 = dln D2 / dln a = 2 Omega_m(a)^(6/11)."""
+    w = omega_m_of_a(a, om)
+    return -3.0 / 7.0 * w ** (-1.0 / 143.0), 2.0 * w ** (6.0 / 11.0)
+
+
 def _tophat(x):
     if x < 1e-4:
         return 1.0 - x * x / 10.0
@@ -107,9 +151,9 @@ def sigma_r(pk, radius):
     return math.sqrt(val / (2.0 * math.pi ** 2))
 
 
-def spectrum_amplitude(om, h, n_s, sigma8):
-    """A such that P(k) = A k^n_s T(k/(Om h))^2 has sigma(8 Mpc/h) = sigma8 today."""
-    shape = lambda k: k ** n_s * bbks_transfer(k / (om * h)) ** 2 if k > 0 else 0.0
+def spectrum_amplitude(om, h, n_s, sigma8, kind=TRANSFER_BBKS, ob=0.05):
+    """A such that P(k) = A k^n_s T(k)^2 has sigma(8 Mpc/h) = sigma8 today."""
+    shape = lambda k: k ** n_s * transfer(k, om, ob, h, kind) ** 2 if k > 0 else 0.0
     s = sigma_r(shape, 8.0)
     return (sigma8 / s) ** 2
 

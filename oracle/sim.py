@@ -51,6 +51,8 @@ class Config:
     closure_theta: object = None  # flat network parameters (oracle.mlp), None: plain source
     closure_bf16: bool = True     # round the network's product operands to bfloat16
     kdk: int = 0                  # dark-matter step factors: KDK_PLAIN or KDK_FASTPM
+    lpt: int = 1                  # order of the initial displacements (1 Zel'dovich, 2 2LPT)
+    transfer: int = 0             # cosmology.TRANSFER_BBKS or TRANSFER_EH
     sn_smooth: bool = False       # supernova energy spread over the neighbouring cells
     star_dm: bool = False         # keep the stars' read-out on the particles (State.aux)
 
@@ -64,7 +66,8 @@ class Config:
 
     def finish(self):
         c = replace(self)
-        c.amp = cosmology.spectrum_amplitude(c.omega_m, c.h, c.n_s, c.sigma8)
+        c.amp = cosmology.spectrum_amplitude(c.omega_m, c.h, c.n_s, c.sigma8, c.transfer,
+                                             c.omega_b)
         c.f_b = c.omega_b / c.omega_m
         c.vel_unit = 100.0 * c.box / c.n
         c.t_per_e = subgrid.kelvin_per_code_energy(c.gamma, c.mu, c.vel_unit)

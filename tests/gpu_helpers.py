@@ -76,14 +76,21 @@ def initial_state_fp32_cells(white, ocfg):
     the exact gradient by ~1e-3."""
     n = ocfg.n
     a = ocfg.a_init
-    psi = ics.za_displacement(ics.linear_density(white, ocfg), n)
+    dk = ics.linear_density(white, ocfg)
+    psi = ics.za_displacement(dk, n)
+    vfac = a * a * cosmology.hubble_e(a, ocfg.omega_m) * cosmology.growth_rate(a, ocfg.omega_m)
+    vel = vfac * psi
+    if ocfg.lpt == 2:
+        psi2 = ics.lpt2_displacement(dk, n, a, ocfg.omega_m)
+        _, f2 = cosmology.lpt2_factors(a, ocfg.omega_m)
+        vel = vel + a * a * cosmology.hubble_e(a, ocfg.omega_m) * f2 * psi2
+        psi = psi + psi2
     psi_p = psi.reshape(3, -1)
     x = torch.remainder(ics.lattice(n) + psi_p, float(n))
     x = x + (round32(x) - x).detach()
-    vfac = a * a * cosmology.hubble_e(a, ocfg.omega_m) * cosmology.growth_rate(a, ocfg.omega_m)
-    p = vfac * psi_p
+    p = vel.reshape(3, -1)
     rho = ocfg.f_b * gravity.cic_deposit(x, 1.0, n)
-    mom = rho * (vfac * psi)
+    mom = rho * vel
     u = mom / (a * rho)
     etot = a * a * rho * (ocfg.e_init + 0.5 * (u * u).sum(0))
     return osim.state_from_qxp(torch.cat([rho[None], mom, etot[None]]), x, p, ocfg)
