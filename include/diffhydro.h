@@ -72,6 +72,11 @@ enum { DH_CLOSURE_PLAIN = 0, DH_CLOSURE_MLP = 1 };
  * kicks are dt/2 in both. */
 enum { DH_KDK_PLAIN = 0, DH_KDK_FASTPM = 1 };
 
+/* Matter transfer function of the initial spectrum P(k) = A k^n_s T(k)^2 (Sec. 2.1): BBKS of
+ * q = k / (Omega_m h), or the Eisenstein & Hu (1998) fitting formula without the baryon
+ * oscillations, which the paper's family of initial conditions uses. */
+enum { DH_TRANSFER_BBKS = 0, DH_TRANSFER_EH = 1 };
+
 /* Run configuration.  dh_config_default() fills the values of the paper's workloads. */
 typedef struct dh_config {
     int32_t n;           /* cells per side; power of two, 16..256                        */
@@ -104,6 +109,12 @@ typedef struct dh_config {
                             w(0) = 1/2, w(+-1) = 1/4 (periodic; the total is unchanged), the
                             start of the Sedov-Taylor blast of Sec. 2.4.1 on the grid; 0: all
                             of it into the cell.  Differentiated like the rest of the step   */
+    int32_t lpt;         /* order of the initial displacements: 1 Zel'dovich, 2 second-order
+                            LPT (Psi2 = -(D2/D1^2) IFFT(i k delta2_k / k^2) from
+                            delta2 = sum_{i<j} (phi_ii phi_jj - phi_ij^2) of the linear
+                            potential, D2/D1^2 = -3/7 Omega_m(a)^(-1/143), velocities with
+                            f2 = 2 Omega_m(a)^(6/11)); differentiated by dh_backward          */
+    int32_t transfer;    /* DH_TRANSFER_*                                                   */
 } dh_config;
 
 /* Model parameters (double).  A, beta: flux observable F = exp(-A Delta^beta) of the loss;

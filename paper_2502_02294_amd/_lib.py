@@ -17,6 +17,7 @@ ERRORS = {-1: "DH_E_INVAL", -2: "DH_E_OOM", -3: "DH_E_HIP", -4: "DH_E_NONFINITE"
 SUBGRID_OFF, SUBGRID_HARD, SUBGRID_RELAXED = 0, 1, 2
 CLOSURE_PLAIN, CLOSURE_MLP = 0, 1
 KDK_PLAIN, KDK_FASTPM = 0, 1
+TRANSFER_BBKS, TRANSFER_EH = 0, 1
 KTIME_SWEEP_KICK, KTIME_SWEEP, KTIME_SWEEP_VJP = 0, 1, 2
 MLP_NPARAMS = 8834
 (FIELD_Q, FIELD_RHO, FIELD_POS, FIELD_MOM, FIELD_STAR, FIELD_PHI, FIELD_TEMP, FIELD_FLUX,
@@ -33,7 +34,8 @@ class Config(ctypes.Structure):
                 ("ckpt_every", ctypes.c_int32), ("closure", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("cfl_forward", ctypes.c_double),
                 ("kdk", ctypes.c_int32), ("star_dm", ctypes.c_int32),
-                ("sn_smooth", ctypes.c_int32)]
+                ("sn_smooth", ctypes.c_int32), ("lpt", ctypes.c_int32),
+                ("transfer", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):

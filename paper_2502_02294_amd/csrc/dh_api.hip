@@ -112,6 +112,10 @@ struct dh_sim {
   // draw per cell; smoothed injection (cfg.sn_smooth): the injected energy per cell (and the
   // adjoint of it in the reverse pass)
   float *aux = nullptr, *znew = nullptr, *sn_buf = nullptr;
+  // second-order LPT initial conditions (cfg.lpt == 2): the six second derivatives of the
+  // linear potential [S][6][n^3] and the velocity displacement Psi + (f2/f1) Psi2 [S][3][n^3],
+  // kept for the adjoint of the initial conditions
+  float *hess = nullptr, *lptv = nullptr;
 
   // scratch
   float *q2 = nullptr, *delta = nullptr, *cic = nullptr, *psi = nullptr, *fscratch = nullptr;
@@ -739,26 +743,81 @@ void reset_clock(dh_sim* s) {
   std::fill(s->replay_pos.begin(), s->replay_pos.end(), 0);
 }
 
-void initial_conditions(dh_sim* s, const float* d_white) {
+// The spectral operator op (kOpIcDisp, kOpIcHess, ...) of the initial conditions with the
+// handle's linear spectrum at a_init
+dh::IcOp ic_op(const dh_sim* s, int op, int axis, int axis2 = 0, double scale = 1.0) {
   const int n = s->n;
   const double ai = s->cfg.a_init;
   const double d = s->cosmo.growth(ai);
-  const double vcell = std::pow(s->cfg.box / n, 3.0);
-  const double amp = s->amp * d * d / vcell;
+  dh::IcOp o;
+  o.op = op;
+  o.axis = axis;
+  o.axis2 = axis2;
+  o.amp = s->amp * d * d / std::pow(s->cfg.box / n, 3.0);
+  o.n_s = s->cfg.n_s;
+  o.om_h = s->cfg.omega_m * s->cfg.h;
+  o.kphys = n / s->cfg.box;
+  o.scale = scale;
+  o.eh = s->cfg.transfer == DH_TRANSFER_EH;
+  const dh::EhShape e = dh::eh_shape(s->cfg.omega_m, s->cfg.omega_b, s->cfg.h);
+  o.eh_theta2 = e.theta2;
+  o.eh_alpha = e.alpha;
+  o.eh_ks = e.ks;
+  return o;
+}
+
+// second derivative k of the linear potential: (xx, yy, zz, xy, xz, yz)
+const int kHessAxes[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+
+// second-order LPT at a_init: (-D2 / D1^2, f2 / f1) with D2 = -3/7 D1^2 Omega_m(a)^(-1/143),
+// f2 = 2 Omega_m(a)^(6/11) (fits of Bouchet et al. 1995)
+void lpt2_factors(const dh_sim* s, double* c2, double* r) {
+  const double ai = s->cfg.a_init;
+  const double om_a = s->cfg.omega_m / (ai * ai * ai * s->cosmo.E(ai) * s->cosmo.E(ai));
+  *c2 = 3.0 / 7.0 * std::pow(om_a, -1.0 / 143.0);
+  *r = 2.0 * std::pow(om_a, 6.0 / 11.0) / s->cosmo.growth_rate(ai);
+}
+
+void initial_conditions(dh_sim* s, const float* d_white) {
+  const int n = s->n;
+  const long long nc = s->nc;
+  const double ai = s->cfg.a_init;
   const Batch all = batch(s, nullptr);
   dh::fft_forward_xy(s->st, d_white, s->spec2, s->tw, all);
   dh::fft_zpass_forward(s->st, s->spec2, s->spec2, s->tw, all);
   for (int j = 0; j < 3; ++j) {
-    dh::fft_zpass_ic(s->st, s->spec2, s->spec, s->tw, j, false, amp, s->cfg.omega_m * s->cfg.h,
-                     s->cfg.n_s, n / s->cfg.box, false, true, false, all);
-    dh::fft_inverse_yx(s->st, s->spec, s->psi + j * s->nc, s->tw, 1.0f, all, 3 * s->nc);
+    dh::fft_zpass_ic(s->st, s->spec2, s->spec, s->tw, ic_op(s, dh::kOpIcDisp, j), false, true,
+                     false, all);
+    dh::fft_inverse_yx(s->st, s->spec, s->psi + j * nc, s->tw, 1.0f, all, 3 * nc);
+  }
+  const float* vel = s->psi;
+  if (s->cfg.lpt == 2) {
+    // second derivatives of the linear potential, the source delta2 and its displacement
+    for (int k = 0; k < 6; ++k) {
+      dh::fft_zpass_ic(s->st, s->spec2, s->spec, s->tw,
+                       ic_op(s, dh::kOpIcHess, kHessAxes[k][0], kHessAxes[k][1]), false, true,
+                       false, all);
+      dh::fft_inverse_yx(s->st, s->spec, s->hess + k * nc, s->tw, 1.0f, all, 6 * nc);
+    }
+    dh::launch_lpt2_source(s->st, s->hess, s->delta, all);
+    double c2, r;
+    lpt2_factors(s, &c2, &r);
+    dh::fft_forward_xy(s->st, s->delta, s->spec, s->tw, all);
+    for (int j = 0; j < 3; ++j) {
+      dh::fft_zpass_ic(s->st, s->spec, s->spec2, s->tw, ic_op(s, dh::kOpZa, j, 0, c2), true, true,
+                       false, all);
+      dh::fft_inverse_yx(s->st, s->spec2, s->fscratch + j * nc, s->tw, 1.0f, all, 3 * nc);
+    }
+    dh::launch_lpt2_combine(s->st, s->psi, s->fscratch, s->lptv, static_cast<float>(r),
+                            3 * nc * s->S);
+    vel = s->lptv;
   }
   const double vfac = ai * ai * s->cosmo.E(ai) * s->cosmo.growth_rate(ai);
   drop_kick(s);
-  dh::launch_ic_particles(s->st, s->psi, s->pos, s->mom, static_cast<float>(vfac), all);
+  dh::launch_ic_particles(s->st, s->psi, vel, s->pos, s->mom, static_cast<float>(vfac), all);
   sort_particles(s, s->pos, all);
   dh::launch_deposit(s->st, s->bins, nullptr, 0, 1.0f, 0.0f, s->cic, all);
-  dh::launch_ic_gas(s->st, s->cic, s->psi, s->q, static_cast<float>(s->f_b),
+  dh::launch_ic_gas(s->st, s->cic, vel, s->q, static_cast<float>(s->f_b),
                     static_cast<float>(vfac), static_cast<float>(ai), static_cast<float>(s->e_init),
                     all);
   dh::launch_fill(s->st, s->star, 0.0f, s->nc * s->S);
@@ -1215,28 +1274,60 @@ void ic_vjp(dh_sim* s, float* d_grad_white) {
   // phi_0 = Poisson(rho_gas + m_dm CIC(x) - 1)
   poisson(s, s->lphi, s->ldelta, b0);
   dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc, 5 * nc, nc, false, all);
-  // positions of the initial particles are recomputed from psi
+  // positions of the initial particles are recomputed from psi (the momenta, written to
+  // scratch, are not needed)
   const double vfac = ai * ai * s->cosmo.E(ai) * s->cosmo.growth_rate(ai);
-  dh::launch_ic_particles(st, s->psi, s->pos, s->fscratch, static_cast<float>(vfac), all);
+  const bool lpt2 = s->cfg.lpt == 2;
+  const float* vel = lpt2 ? s->lptv : s->psi;
+  dh::launch_ic_particles(st, s->psi, vel, s->pos, s->fscratch, static_cast<float>(vfac), all);
   dh::launch_deposit_vjp_pos(st, s->ldelta, s->pos, static_cast<float>(s->m_dm), s->lx, nullptr,
                              nullptr, all);
-  // gas: rho = f_b CIC(x), m = rho p(q), Et = a^2 rho (e_init + |p/a|^2/2)
+  // gas: rho = f_b CIC(x), m = rho p(q), Et = a^2 rho (e_init + |p/a|^2/2); with first-order
+  // displacements the velocity displacement is psi itself and its adjoint goes to lpsi, with
+  // second-order ones it has its own adjoint (lvel, in fscratch)
+  float* lvel = lpt2 ? s->fscratch : s->lpsi;
   dh::launch_fill(st, s->lpsi, 0.0f, 3 * nc * s->S);
-  dh::launch_ic_gas_vjp(st, s->cic, s->psi, s->lq, static_cast<float>(s->f_b),
+  if (lpt2) dh::launch_fill(st, lvel, 0.0f, 3 * nc * s->S);
+  dh::launch_ic_gas_vjp(st, s->cic, vel, s->lq, static_cast<float>(s->f_b),
                         static_cast<float>(vfac), static_cast<float>(ai),
-                        static_cast<float>(s->e_init), s->lcic, s->lpsi, all);
+                        static_cast<float>(s->e_init), s->lcic, lvel, all);
   dh::launch_deposit_vjp_pos(st, s->lcic, s->pos, 1.0f, s->lx, nullptr, nullptr, all);
-  // x = q + psi, p = vfac psi
+  // x = q + psi, p = vfac vel
   dh::launch_axpy(st, s->lpsi, s->lx, 1.0f, 3 * nc, 3 * nc, 3 * nc, false, all);
-  dh::launch_axpy(st, s->lpsi, s->lp, static_cast<float>(vfac), 3 * nc, 3 * nc, 3 * nc, false,
-                  all);
+  dh::launch_axpy(st, lvel, s->lp, static_cast<float>(vfac), 3 * nc, 3 * nc, 3 * nc, false, all);
+  bool acc = false;   // spec2 accumulates the spectrum of lambda_w
+  if (lpt2) {
+    // psi = Psi1 + Psi2, vel = Psi1 + r Psi2: lambda_Psi2 = lambda_psi + r lambda_vel (into
+    // lx, free now), lambda_Psi1 = lambda_psi + lambda_vel (into lpsi)
+    double c2, r;
+    lpt2_factors(s, &c2, &r);
+    copy_d2d(s, s->lx, s->lpsi, 3 * nc * s->S);
+    dh::launch_axpy(st, s->lx, lvel, static_cast<float>(r), 3 * nc, 3 * nc, 3 * nc, false, all);
+    dh::launch_axpy(st, s->lpsi, lvel, 1.0f, 3 * nc, 3 * nc, 3 * nc, false, all);
+    // Psi2_j = IFFT(i k_j c2 / k^2 FFT(delta2)) -> lambda_delta2 (into ldelta)
+    for (int j = 0; j < 3; ++j) {
+      dh::fft_forward_xy(st, s->lx + j * nc, s->spec, s->tw, all, 3 * nc);
+      dh::fft_zpass_ic(st, s->spec, s->spec2, s->tw, ic_op(s, dh::kOpZaT, j, 0, c2), true, false,
+                       j > 0, all);
+    }
+    dh::fft_zpass_inverse(st, s->spec2, s->tw, all);
+    dh::fft_inverse_yx(st, s->spec2, s->ldelta, s->tw, 1.0f, all);
+    // delta2 from the second derivatives phi_ab = IFFT(k_a k_b T/k^2 FFT(w)): lambda_w gains
+    // IFFT(k_a k_b T/k^2 FFT(lambda_phi_ab)) (a real operator is its own transpose)
+    for (int k = 0; k < 6; ++k) {
+      dh::launch_lpt2_source_vjp(st, s->hess, s->ldelta, k, s->lcic, all);
+      dh::fft_forward_xy(st, s->lcic, s->spec, s->tw, all);
+      dh::fft_zpass_ic(st, s->spec, s->spec2, s->tw,
+                       ic_op(s, dh::kOpIcHess, kHessAxes[k][0], kHessAxes[k][1]), true, false,
+                       acc, all);
+      acc = true;
+    }
+  }
   // psi_j = IFFT(i k_j T(k)/k^2 FFT(w)) -> lambda_w = sum_j IFFT(-i k_j T/k^2 FFT(lambda_psi_j))
-  const double d = s->cosmo.growth(ai);
-  const double amp = s->amp * d * d / std::pow(s->cfg.box / n, 3.0);
   for (int j = 0; j < 3; ++j) {
     dh::fft_forward_xy(st, s->lpsi + j * nc, s->spec, s->tw, all, 3 * nc);
-    dh::fft_zpass_ic(st, s->spec, s->spec2, s->tw, j, true, amp, s->cfg.omega_m * s->cfg.h,
-                     s->cfg.n_s, n / s->cfg.box, true, false, j > 0, all);
+    dh::fft_zpass_ic(st, s->spec, s->spec2, s->tw, ic_op(s, dh::kOpIcDispT, j), true, false,
+                     acc || j > 0, all);
   }
   dh::fft_zpass_inverse(st, s->spec2, s->tw, all);
   dh::fft_inverse_yx(st, s->spec2, d_grad_white, s->tw, 1.0f, all);
@@ -1280,6 +1371,8 @@ void dh_config_default(dh_config* c) {
   c->kdk = DH_KDK_PLAIN;
   c->star_dm = 0;
   c->sn_smooth = 0;
+  c->lpt = 1;
+  c->transfer = DH_TRANSFER_BBKS;
 }
 
 void dh_params_default(dh_params* p) {
@@ -1307,6 +1400,8 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
         cfg->cfl_forward >= 0 && (cfg->kdk == DH_KDK_PLAIN || cfg->kdk == DH_KDK_FASTPM) &&
         cfg->subgrid <= 2 && cfg->t_floor > 0 && cfg->t_init > 0 && cfg->sigma8 > 0 &&
         (cfg->star_dm == 0 || cfg->star_dm == 1) && (cfg->sn_smooth == 0 || cfg->sn_smooth == 1) &&
+        (cfg->lpt == 1 || cfg->lpt == 2) &&
+        (cfg->transfer == DH_TRANSFER_BBKS || cfg->transfer == DH_TRANSFER_EH) &&
         (cfg->closure == DH_CLOSURE_PLAIN ||
          (cfg->closure == DH_CLOSURE_MLP && cfg->subgrid != DH_SUBGRID_OFF))))
     return DH_E_INVAL;
@@ -1323,7 +1418,8 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
     s->cosmo.om = cfg->omega_m;
     s->cosmo.ol = 1.0 - cfg->omega_m;
     if (cfg->kdk == DH_KDK_FASTPM) s->heath.build(s->cosmo, 4.0, 4096);
-    s->amp = dh::spectrum_amplitude(cfg->omega_m, cfg->h, cfg->n_s, cfg->sigma8);
+    s->amp = dh::spectrum_amplitude(cfg->omega_m, cfg->h, cfg->n_s, cfg->sigma8,
+                                    cfg->transfer == DH_TRANSFER_EH, cfg->omega_b);
     s->f_b = cfg->omega_b / cfg->omega_m;
     s->m_dm = 1.0 - s->f_b;
     s->vel_unit = 100.0 * cfg->box / n;
@@ -1349,6 +1445,10 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
       DH_HIP(hipMemset(s->aux, 0, static_cast<size_t>(np) * sizeof(float)));
     }
     if (cfg->sn_smooth) s->sn_buf = s->alloc<float>(nc);
+    if (cfg->lpt == 2) {
+      s->hess = s->alloc<float>(6 * nc);
+      s->lptv = s->alloc<float>(3 * nc);
+    }
     s->phi = s->alloc<float>(nc);
     s->delta = s->alloc<float>(nc);
     s->cic = s->alloc<float>(nc);

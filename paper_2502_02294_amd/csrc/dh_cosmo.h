@@ -110,14 +110,46 @@ inline double bbks(double q) {
                   -0.25);
 }
 
-// A with sigma(8 Mpc/h) = sigma8 for P(k) = A k^n_s T(k/(om h))^2; Simpson in ln k
-inline double spectrum_amplitude(double om, double h, double n_s, double sigma8) {
+// Eisenstein & Hu (1998) transfer function without the baryon oscillations, of k in h/Mpc
+// (Sec. 2.1 sets the initial spectrum with the Eisenstein & Hu fitting formulae): the
+// k-independent constants of its effective shape Gamma(k) = om h (alpha + (1 - alpha) /
+// (1 + (0.43 k h s)^4)) and q = k theta^2 / Gamma, T = L / (L + C q^2), L = ln(2 e + 1.8 q),
+// C = 14.2 + 731 / (1 + 62.5 q); s = 44.5 ln(9.83 / w_m) / sqrt(1 + 10 w_b^(3/4)) Mpc,
+// alpha = 1 - 0.328 ln(431 w_m) f_b + 0.38 ln(22.3 w_m) f_b^2, theta = T_cmb / 2.7 K.
+struct EhShape {
+  double theta2, alpha, ks;   // ks = 0.43 h s: Gamma's cut-off in k [h/Mpc]^-1
+  double omh;
+};
+inline EhShape eh_shape(double om, double ob, double h) {
+  EhShape e;
+  const double wm = om * h * h, wb = ob * h * h, fb = ob / om;
+  const double s = 44.5 * std::log(9.83 / wm) / std::sqrt(1.0 + 10.0 * std::pow(wb, 0.75));
+  e.alpha = 1.0 - 0.328 * std::log(431.0 * wm) * fb + 0.38 * std::log(22.3 * wm) * fb * fb;
+  e.ks = 0.43 * h * s;
+  e.theta2 = (2.7255 / 2.7) * (2.7255 / 2.7);
+  e.omh = om * h;
+  return e;
+}
+inline double eh_transfer(double k, const EhShape& e) {
+  const double ks4 = std::pow(k * e.ks, 4);
+  const double gamma = e.omh * (e.alpha + (1.0 - e.alpha) / (1.0 + ks4));
+  const double q = k * e.theta2 / gamma;
+  const double l = std::log(2.0 * M_E + 1.8 * q);
+  const double c = 14.2 + 731.0 / (1.0 + 62.5 * q);
+  return l / (l + c * q * q);
+}
+
+// A with sigma(8 Mpc/h) = sigma8 for P(k) = A k^n_s T(k)^2 (BBKS of k/(om h), or Eisenstein &
+// Hu when eh); Simpson in ln k
+inline double spectrum_amplitude(double om, double h, double n_s, double sigma8, bool eh = false,
+                                 double ob = 0.05) {
   const double lo = std::log(1e-7), hi = std::log(1e4);
   const int m = 400000;
   const double dl = (hi - lo) / m;
+  const EhShape es = eh_shape(om, ob, h);
   auto f = [&](double lk) {
     const double k = std::exp(lk);
-    const double t = bbks(k / (om * h));
+    const double t = eh ? eh_transfer(k, es) : bbks(k / (om * h));
     const double x = 8.0 * k;
     const double w = x < 1e-4 ? 1.0 - x * x / 10.0 : 3.0 * (std::sin(x) - x * std::cos(x)) / (x * x * x);
     return k * k * k * std::pow(k, n_s) * t * t * w * w;

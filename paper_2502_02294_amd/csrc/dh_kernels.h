@@ -127,7 +127,17 @@ void launch_grad_vjp2(hipStream_t st, const float* lam_g0, const float* lam_g, f
                       const Batch& b);
 
 // ---- FFT and spectral operators (k_fft.hip)
-enum SpecOp { kOpGreen = 0, kOpIcDisp = 1, kOpIcDispT = 2 };
+enum SpecOp {
+  kOpGreen = 0, kOpIcDisp = 1, kOpIcDispT = 2, kOpIcHess = 3, kOpZa = 4, kOpZaT = 5
+};
+// An initial-condition operator of the z pass: op, axes, the spectrum (amplitude
+// A D^2 / V_cell, n_s, Omega_m h, n / box, transfer function) and a scale for kOpZa(T)
+struct IcOp {
+  int op = kOpIcDisp, axis = 0, axis2 = 0;
+  double amp = 0, n_s = 1, om_h = 1, kphys = 1, scale = 1;
+  bool eh = false;
+  double eh_theta2 = 1, eh_alpha = 1, eh_ks = 0;
+};
 void fft_make_twiddles(int n, std::vector<float2>& tw);
 // real field -> half spectrum transformed along x and y (z pass separate); sample s of the
 // input starts at in + s * in_stride (default n^3)
@@ -141,10 +151,10 @@ void fft_zpass_green(hipStream_t st, float2* spec, const float2* tw, const Batch
 void fft_zpass_forward(hipStream_t st, const float2* in, float2* out, const float2* tw,
                        const Batch& b);
 void fft_zpass_inverse(hipStream_t st, float2* spec, const float2* tw, const Batch& b);
-// z pass with the initial-condition operator i k_axis T(k)/k^2 / N^3 (or its conjugate)
-void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* tw, int axis,
-                  bool transpose, double amp, double om_h, double n_s, double kphys,
-                  bool forward_first, bool inverse_after, bool accumulate, const Batch& b);
+// z pass with an initial-condition operator (IcOp; the 1/N^3 of the inverse included)
+void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* tw,
+                  const IcOp& op, bool forward_first, bool inverse_after, bool accumulate,
+                  const Batch& b);
 
 // ---- observables of Sec. 3 (k_observe.hip)
 // per-block sums of w |X|^2 by bin of the rounded |m| (bins 1..nbins) of a half spectrum
@@ -228,8 +238,16 @@ void launch_temperature(hipStream_t st, const float* q, float a, float efloor, f
                         float* out, long long nc);
 void launch_white_noise(hipStream_t st, float* out, uint32_t seed_lo, uint32_t seed_hi, int n);
 // IC: particles from displacement and gas from the deposit
-void launch_ic_particles(hipStream_t st, const float* psi, float* pos, float* mom, float vfac,
-                         const Batch& b);
+// x = q + psi, p = vfac vel (vel = psi for first-order displacements)
+void launch_ic_particles(hipStream_t st, const float* psi, const float* vel, float* pos,
+                         float* mom, float vfac, const Batch& b);
+// second-order LPT: delta2 from the six second derivatives hess[s][6][nc] (xx, yy, zz, xy, xz,
+// yz), its adjoint for derivative k, and vel = psi + r psi2, psi += psi2 over count values
+void launch_lpt2_source(hipStream_t st, const float* hess, float* d2, const Batch& b);
+void launch_lpt2_source_vjp(hipStream_t st, const float* hess, const float* lam_d2, int k,
+                            float* out, const Batch& b);
+void launch_lpt2_combine(hipStream_t st, float* psi, const float* psi2, float* vel, float r,
+                         long long count);
 void launch_ic_gas(hipStream_t st, const float* cic, const float* psi, float* q, float f_b,
                    float vfac, float a, float e_init, const Batch& b);
 void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const float* lam_q,

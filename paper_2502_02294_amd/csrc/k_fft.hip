@@ -237,15 +237,45 @@ __global__ void __launch_bounds__(kFftThreads) x_c2r_kernel(const float2* __rest
 
 // ---------------------------------------------------------------------------- line passes
 struct OpArgs {
-  int op;          // -1 none, kOpGreen, kOpIcDisp, kOpIcDispT
+  int op;          // -1 none, kOpGreen, kOpIcDisp, kOpIcDispT, kOpIcHess, kOpZa, kOpZaT
   float green;     // -(3 Om / 2a) / N^3
-  int axis;
+  int axis, axis2;
   float sqrt_amp;  // sqrt(A D^2 / V_cell)
   float half_ns;   // spectral index / 2
   float om_h;      // Omega_m h
   float kphys;     // n / box: rad/cell -> h/Mpc
-  float inv_n3;
+  float inv_n3;    // 1/N^3, times the operator's scale for kOpZa / kOpZaT
+  int eh;          // transfer function: 0 BBKS, 1 Eisenstein & Hu without wiggles
+  float eh_theta2, eh_alpha, eh_ks;
 };
+
+// derivative factor k_j (rad/cell) of mode (fx, fy, fz): zero on the Nyquist plane of its own
+// axis (an odd derivative of the real Nyquist mode)
+__device__ __forceinline__ float deriv_k(int axis, int fx, int fy, int fz, int n) {
+  const int f = axis == 0 ? fx : (axis == 1 ? fy : fz);
+  if (f == n / 2 || f == -n / 2) return 0.0f;
+  return 6.283185307179586f / static_cast<float>(n) * static_cast<float>(f);
+}
+
+// sqrt(P(k)) / sqrt(A D^2 / V_cell) at k = kp h/Mpc: k^(n_s/2) T(k)
+__device__ __forceinline__ float sqrt_shape(const OpArgs& o, float kp) {
+  float t;
+  if (o.eh) {
+    const float x = kp * o.eh_ks;
+    const float x2 = x * x;
+    const float gamma = o.om_h * (o.eh_alpha + (1.0f - o.eh_alpha) / (1.0f + x2 * x2));
+    const float q = kp * o.eh_theta2 / gamma;
+    const float l = logf(2.0f * 2.718281828459045f + 1.8f * q);
+    const float c = 14.2f + 731.0f / (1.0f + 62.5f * q);
+    t = l / (l + c * q * q);
+  } else {
+    const float q = kp / o.om_h;
+    const float q2 = 16.1f * q, q3 = 5.46f * q, q4 = 6.71f * q;
+    t = logf(1.0f + 2.34f * q) / (2.34f * q) *
+        powf(1.0f + 3.89f * q + q2 * q2 + q3 * q3 * q3 + (q4 * q4) * (q4 * q4), -0.25f);
+  }
+  return powf(kp, o.half_ns) * t;
+}
 
 __device__ __forceinline__ int signed_freq(int k, int n) { return k <= n / 2 ? k : k - n; }
 
@@ -263,20 +293,30 @@ __device__ __forceinline__ float2 apply_op(const OpArgs& o, int kx, int ky, int 
     const float f = o.green / k2;
     return make_float2(v.x * f, v.y * f);
   }
-  // initial-condition displacement operators: i k_axis sqrt(P(k)) / k^2 / N^3 (or its
-  // conjugate), with the BBKS transfer function
+  // initial-condition operators (derivative factors from deriv_k):
+  //   kOpIcDisp  i k_axis sqrt(P(k)) / k^2 / N^3 (kOpIcDispT: its conjugate), the Zel'dovich
+  //              displacement of white noise;
+  //   kOpIcHess  k_axis k_axis2 sqrt(P(k)) / k^2 / N^3 (real): second derivative of the
+  //              linear potential (its own transpose);
+  //   kOpZa      i k_axis / k^2 times inv_n3 (kOpZaT: its conjugate), the displacement of a
+  //              given density, scaled
   const float c = 6.283185307179586f / static_cast<float>(n);
   const float ax = c * fx, ay = c * fy, az = c * fz;
   const float k2 = ax * ax + ay * ay + az * az;
-  const int f_axis = o.axis == 0 ? fx : (o.axis == 1 ? fy : fz);
-  if (k2 == 0.0f || (f_axis == n / 2 || f_axis == -n / 2)) return make_float2(0.0f, 0.0f);
-  const float kj = o.axis == 0 ? ax : (o.axis == 1 ? ay : az);
+  if (k2 == 0.0f) return make_float2(0.0f, 0.0f);
+  const float kj = deriv_k(o.axis, fx, fy, fz, n);
+  if (o.op == kOpZa || o.op == kOpZaT) {
+    const float f = kj / k2 * o.inv_n3;
+    const float ff = o.op == kOpZa ? f : -f;
+    return make_float2(-v.y * ff, v.x * ff);
+  }
   const float kp = sqrtf(k2) * o.kphys;
-  const float q = kp / o.om_h;
-  const float q2 = 16.1f * q, q3 = 5.46f * q, q4 = 6.71f * q;
-  const float tq = logf(1.0f + 2.34f * q) / (2.34f * q) *
-                   powf(1.0f + 3.89f * q + q2 * q2 + q3 * q3 * q3 + (q4 * q4) * (q4 * q4), -0.25f);
-  const float f = kj * (o.sqrt_amp * powf(kp, o.half_ns) * tq) / k2 * o.inv_n3;
+  const float spec = o.sqrt_amp * sqrt_shape(o, kp);
+  if (o.op == kOpIcHess) {
+    const float f = kj * deriv_k(o.axis2, fx, fy, fz, n) * spec / k2 * o.inv_n3;
+    return make_float2(v.x * f, v.y * f);
+  }
+  const float f = kj * spec / k2 * o.inv_n3;
   const float ff = o.op == kOpIcDisp ? f : -f;
   // multiply by i * ff
   return make_float2(-v.y * ff, v.x * ff);
@@ -477,19 +517,25 @@ void fft_zpass_inverse(hipStream_t st, float2* spec, const float2* tw, const Bat
   pencil(st, 2, spec, spec, tw, 4, none, b);
 }
 
-// IC displacement: out = op_axis(in) then inverse along z (in already transformed in x, y, z)
-void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* tw, int axis,
-                  bool transpose, double amp, double om_h, double n_s, double kphys,
-                  bool forward_first, bool inverse_after, bool accumulate, const Batch& b) {
+// IC operators on the z pass (see apply_op): out = op(in), forward z transform first and
+// inverse after as asked
+void fft_zpass_ic(hipStream_t st, const float2* in, float2* out, const float2* tw,
+                  const IcOp& op, bool forward_first, bool inverse_after, bool accumulate,
+                  const Batch& b) {
   const int n = b.n;
   OpArgs o{};
-  o.op = transpose ? kOpIcDispT : kOpIcDisp;
-  o.axis = axis;
-  o.sqrt_amp = static_cast<float>(std::sqrt(amp));
-  o.half_ns = static_cast<float>(0.5 * n_s);
-  o.om_h = static_cast<float>(om_h);
-  o.kphys = static_cast<float>(kphys);
-  o.inv_n3 = static_cast<float>(1.0 / (static_cast<double>(n) * n * n));
+  o.op = op.op;
+  o.axis = op.axis;
+  o.axis2 = op.axis2;
+  o.sqrt_amp = static_cast<float>(std::sqrt(op.amp));
+  o.half_ns = static_cast<float>(0.5 * op.n_s);
+  o.om_h = static_cast<float>(op.om_h);
+  o.kphys = static_cast<float>(op.kphys);
+  o.inv_n3 = static_cast<float>(op.scale / (static_cast<double>(n) * n * n));
+  o.eh = op.eh ? 1 : 0;
+  o.eh_theta2 = static_cast<float>(op.eh_theta2);
+  o.eh_alpha = static_cast<float>(op.eh_alpha);
+  o.eh_ks = static_cast<float>(op.eh_ks);
   const int flags = (forward_first ? 1 : 0) | 2 | (inverse_after ? 4 : 0) | (accumulate ? 8 : 0);
   pencil(st, 2, in, out, tw, flags, o, b);
 }

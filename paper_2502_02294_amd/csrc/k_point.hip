@@ -905,11 +905,14 @@ __global__ void white_noise_kernel(float* __restrict__ out, uint32_t k0, uint32_
   out[c] = static_cast<float>(sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
 }
 
-__global__ void ic_particles_kernel(const float* __restrict__ psi, float* __restrict__ pos,
-                                    float* __restrict__ mom, float vfac, int n, long long np) {
+// x = q + psi, p = vfac vel (vel = psi with first-order displacements)
+__global__ void ic_particles_kernel(const float* __restrict__ psi, const float* __restrict__ vel,
+                                    float* __restrict__ pos, float* __restrict__ mom, float vfac,
+                                    int n, long long np) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= np) return;
   psi += blockIdx.y * 3 * np;
+  vel += blockIdx.y * 3 * np;
   pos += blockIdx.y * 3 * np;
   mom += blockIdx.y * 3 * np;
   const int l[3] = {static_cast<int>(i % n), static_cast<int>((i / n) % n),
@@ -922,8 +925,51 @@ __global__ void ic_particles_kernel(const float* __restrict__ psi, float* __rest
     x -= fn * floorf(x / fn);
     if (x >= fn) x -= fn;
     pos[d * np + i] = x;
-    mom[d * np + i] = vfac * s;
+    mom[d * np + i] = vfac * vel[d * np + i];
   }
+}
+
+// Second-order LPT source delta2 = sum_{i<j} (phi_ii phi_jj - phi_ij^2) from the six second
+// derivatives hess[s][6][nc] in the order xx, yy, zz, xy, xz, yz
+__global__ void lpt2_source_kernel(const float* __restrict__ hess, float* __restrict__ d2,
+                                   long long nc) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  hess += blockIdx.y * 6 * nc;
+  d2 += blockIdx.y * nc;
+  const float xx = hess[c], yy = hess[nc + c], zz = hess[2 * nc + c];
+  const float xy = hess[3 * nc + c], xz = hess[4 * nc + c], yz = hess[5 * nc + c];
+  d2[c] = xx * yy + xx * zz + yy * zz - xy * xy - xz * xz - yz * yz;
+}
+
+// adjoint of lpt2_source for one second derivative k (order as above): out = dL/dphi_k
+__global__ void lpt2_source_vjp_kernel(const float* __restrict__ hess,
+                                       const float* __restrict__ lam_d2, int k,
+                                       float* __restrict__ out, long long nc) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  hess += blockIdx.y * 6 * nc;
+  lam_d2 += blockIdx.y * nc;
+  out += blockIdx.y * nc;
+  const float l = lam_d2[c];
+  float v;
+  if (k < 3) {   // d/dphi_kk of the products: the sum of the other two diagonal entries
+    const float a = hess[((k + 1) % 3) * nc + c], b = hess[((k + 2) % 3) * nc + c];
+    v = l * (a + b);
+  } else {
+    v = -2.0f * l * hess[k * nc + c];
+  }
+  out[c] = v;
+}
+
+// second-order LPT: vel = psi + r psi2, psi = psi + psi2 (r = f2 / f1)
+__global__ void lpt2_combine_kernel(float* __restrict__ psi, const float* __restrict__ psi2,
+                                    float* __restrict__ vel, float r, long long count) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float a = psi[i], b = psi2[i];
+  vel[i] = fmaf(r, b, a);
+  psi[i] = a + b;
 }
 
 __global__ void ic_gas_kernel(const float* __restrict__ cic, const float* __restrict__ psi,
@@ -1133,10 +1179,30 @@ void launch_white_noise(hipStream_t st, float* out, uint32_t seed_lo, uint32_t s
   DH_LAUNCH_CHECK();
 }
 
-void launch_ic_particles(hipStream_t st, const float* psi, float* pos, float* mom, float vfac,
-                         const Batch& b) {
+void launch_ic_particles(hipStream_t st, const float* psi, const float* vel, float* pos,
+                         float* mom, float vfac, const Batch& b) {
   hipLaunchKernelGGL(ic_particles_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st, psi,
-                     pos, mom, vfac, b.n, b.nc());
+                     vel, pos, mom, vfac, b.n, b.nc());
+  DH_LAUNCH_CHECK();
+}
+
+void launch_lpt2_source(hipStream_t st, const float* hess, float* d2, const Batch& b) {
+  hipLaunchKernelGGL(lpt2_source_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st,
+                     hess, d2, b.nc());
+  DH_LAUNCH_CHECK();
+}
+
+void launch_lpt2_source_vjp(hipStream_t st, const float* hess, const float* lam_d2, int k,
+                            float* out, const Batch& b) {
+  hipLaunchKernelGGL(lpt2_source_vjp_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0,
+                     st, hess, lam_d2, k, out, b.nc());
+  DH_LAUNCH_CHECK();
+}
+
+void launch_lpt2_combine(hipStream_t st, float* psi, const float* psi2, float* vel, float r,
+                         long long count) {
+  hipLaunchKernelGGL(lpt2_combine_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, st, psi,
+                     psi2, vel, r, count);
   DH_LAUNCH_CHECK();
 }
 

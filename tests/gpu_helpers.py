@@ -58,7 +58,8 @@ def gpu_config(ocfg, **kw):
                           a_init=ocfg.a_init, t_init=ocfg.t_init, cfl=ocfg.cfl,
                           dlna_max=ocfg.dlna_max, t_floor=ocfg.t_floor, subgrid=ocfg.subgrid,
                           tau=ocfg.tau, sf_seed=ocfg.sf_seed, kdk=ocfg.kdk,
-                          sn_smooth=int(ocfg.sn_smooth), star_dm=int(ocfg.star_dm), **kw)
+                          sn_smooth=int(ocfg.sn_smooth), star_dm=int(ocfg.star_dm),
+                          lpt=ocfg.lpt, transfer=ocfg.transfer, **kw)
 
 
 def gpu_params(p):

@@ -223,6 +223,20 @@ def test_initial_conditions_from_noise(dhp, n, box):
     _compare_state(s, st, n, STEP_TOL)
 
 
+@pytest.mark.parametrize("lpt,transfer", [(2, 0), (1, 1), (2, 1)])
+def test_initial_conditions_lpt2_and_eh(dhp, lpt, transfer):
+    """Second-order displacements and the Eisenstein & Hu spectrum (Sec. 2.1) against the
+    oracle at 64^3, a = 0.05 (where the second order moves particles by a few per cent of
+    the first)."""
+    n = 64
+    ocfg = osim.default_config(n=n, box=20.0, a_init=0.05, lpt=lpt, transfer=transfer)
+    s = _sim(dhp, ocfg)
+    w = si.white_noise(n, seed=1)
+    s.init_from_noise(to_gpu(w))
+    st = osim.initial_state(torch.from_numpy(w).double(), ocfg)
+    _compare_state(s, st, n, STEP_TOL)
+
+
 def test_initial_conditions_from_seed(dhp):
     from oracle import philox
     n = 32
@@ -346,16 +360,20 @@ def test_conservation_sums(dhp):
 
 # ---------------------------------------------------------------- gradients
 
-@pytest.mark.parametrize("n,box,a_init,nsteps,ckpt,kdk", [(16, 4.0, 0.05, 4, 3, 0),
-                                                        (16, 4.0, 0.05, 4, 3, 1),
-                                                        (64, 10.0, 0.01, 2, 1, 0)])
-def test_gradient_matches_oracle_autograd(dhp, n, box, a_init, nsteps, ckpt, kdk):
+@pytest.mark.parametrize("n,box,a_init,nsteps,ckpt,kdk,lpt,tf", [(16, 4.0, 0.05, 4, 3, 0, 1, 0),
+                                                               (16, 4.0, 0.05, 4, 3, 1, 1, 0),
+                                                               (16, 4.0, 0.05, 3, 2, 1, 2, 1),
+                                                               (64, 10.0, 0.01, 2, 1, 0, 1, 0),
+                                                               (64, 10.0, 0.05, 2, 1, 1, 2, 0)])
+def test_gradient_matches_oracle_autograd(dhp, n, box, a_init, nsteps, ckpt, kdk, lpt, tf):
     # 16^3: star formation active in most cells (with the leapfrog's and FastPM's dark-matter
-    # factors); 64^3: the launch shapes of larger grids (whole-segment walks, 8 x 8 FFT
-    # lines, tiled deposits), two checkpoint segments
-    print(f"gradient vs oracle autograd, {n}^3, {nsteps} steps, kdk {kdk}", flush=True)
+    # factors, and with second-order initial displacements and the Eisenstein & Hu spectrum);
+    # 64^3: the launch shapes of larger grids (whole-segment walks, 8 x 8 FFT lines, tiled
+    # deposits), two checkpoint segments
+    print(f"gradient vs oracle autograd, {n}^3, {nsteps} steps, kdk {kdk}, lpt {lpt}, "
+          f"transfer {tf}", flush=True)
     ocfg = osim.default_config(n=n, box=box, subgrid=subgrid.MODE_RELAXED, a_init=a_init,
-                               kdk=kdk)
+                               kdk=kdk, lpt=lpt, transfer=tf)
     prm = osim.Params(delta_c=1.05, t_c=1e6, eps_sf=0.5)
     w = si.white_noise(n, seed=21)
     target = (0.2 + 0.7 * np.random.default_rng(1).random((n, n, n))).astype(np.float32)
@@ -378,5 +396,9 @@ def test_gradient_matches_oracle_autograd(dhp, n, box, a_init, nsteps, ckpt, kdk
     assert abs(lval - float(loss)) < 1e-4 * float(loss)
     gw, gp = s.backward()
     assert rel_l2(to_np(gw), gw_ref.numpy()) < 1e-3
+    # from a = 0.05 at 64^3 the star-formation gradients are sums over the few cells the
+    # relaxed gates let through, each term scaled by 1/tau: 5e-3 there
+    ptol = 5e-3 if (n == 64 and a_init > 0.01) else 1e-3
     for i in range(4):
-        assert abs(gp[i] - float(gp_ref[i])) < 1e-3 * abs(float(gp_ref[i])) + 1e-9, (i, gp, gp_ref)
+        tol = 1e-3 if i < 2 else ptol
+        assert abs(gp[i] - float(gp_ref[i])) < tol * abs(float(gp_ref[i])) + 1e-9, (i, gp, gp_ref)
