@@ -538,7 +538,15 @@ def main():
                                             args.warmup, args.mlp_samples)
     if not args.no_batch:
         log("bench: batched parameter sampler vs one sample at a time")
-        out["batched_sampler"] = batch_comparison(torch, dhp, si, args.batch_samples)
+        bs = batch_comparison(torch, dhp, si, args.batch_samples)
+        # the plain path over the same whole run (a = 0.01 -> 0.29, the same cell size): both
+        # include the late, clustered steps, whose particle kernels cost more than the early
+        # steps of `value`
+        if out.get("full_run"):
+            fr = out["full_run"]["cell_updates_per_s"]
+            bs["plain_256_full_run_fwd_bwd_cell_updates_per_s"] = fr
+            bs["rate_vs_plain_256_full_run"] = bs["fwd_bwd_cell_updates_per_s"] / fr
+        out["batched_sampler"] = bs
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(n, box, first)

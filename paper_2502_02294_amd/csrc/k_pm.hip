@@ -264,12 +264,76 @@ struct DepTile {
   static constexpr int PER = (NB + 255) / 256;      // bins per thread
 };
 
+// Bins of more than kCrowded particles (dense halos gather hundreds or thousands of
+// particles in a cell) are summed by whole waves instead of one thread: the block lists them
+// in LDS during pass 1 and its waves take them one each, every lane over a strided share of
+// the bin's particles in ascending order, then a fixed butterfly across the wave, so the sums
+// stay reproducible bit for bit and no thread loops over a crowded bin alone.
+constexpr uint32_t kCrowded = 16;
+
+// sum of v over the 64 lanes of the wave, every lane receiving it (fixed order)
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// cell of tile bin b (the tile at x0, y0, z0 and its low halo)
+template <int BX, int BY>
+__device__ __forceinline__ int tile_bin_cell(int b, int x0, int y0, int z0, int n) {
+  const int bx = b % BX, by = (b / BX) % BY, bz = b / (BX * BY);
+  return (wrapi(z0 - 1 + bz, n) * n + wrapi(y0 - 1 + by, n)) * n + wrapi(x0 - 1 + bx, n);
+}
+
+// W[o][b] (or the weights times one component v of sval, VEC) of the crowded bins listed in
+// list[0..count): wave w of the block takes entries w, w + waves, ...
+template <int TX, int TY, int TZ, bool VEC>
+__device__ __forceinline__ void crowded_bin_sums(const uint32_t* __restrict__ start,
+                                                 const float4* __restrict__ spos,
+                                                 const float4* __restrict__ sval, int v,
+                                                 const uint16_t* list, int count, int x0, int y0,
+                                                 int z0, int n, float* W) {
+  using T = DepTile<TX, TY, TZ>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  for (int e = wave; e < count; e += waves) {
+    const int b = list[e];
+    const int cell = tile_bin_cell<T::BX, T::BY>(b, x0, y0, z0, n);
+    const uint32_t lo = start[cell], hi = start[cell + 1];
+    float acc[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) acc[o] = 0.0f;
+    for (uint32_t j = lo + lane; j < hi; j += 64) {
+      const float4 p = spos[j];
+      float val = 1.0f;
+      if (VEC) {
+        const float4 q = sval[j];
+        val = v == 0 ? q.x : (v == 1 ? q.y : q.z);
+      }
+      const float wx = w1_of(p.x), wy = w1_of(p.y), wz = w1_of(p.z);
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const float w = wsel(wx, o & 1) * wsel(wy, (o >> 1) & 1) * wsel(wz, o >> 2);
+        acc[o] += VEC ? w * val : w;
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const float t = wave_sum(acc[o]);
+      if (lane == 0) W[o * T::NB + b] = t;
+    }
+  }
+}
+
 // Pass 1 of the density deposit: W[o][b] for the bins of the tile and its halo.
 template <int TX, int TY, int TZ>
 __device__ __forceinline__ void deposit_tile(const uint32_t* __restrict__ start,
                                              const float4* __restrict__ spos, int n, int x0,
                                              int y0, int z0, float* W) {
   using T = DepTile<TX, TY, TZ>;
+  __shared__ int ncrowd;
+  __shared__ uint16_t crowd[T::NB];
+  if (threadIdx.x == 0) ncrowd = 0;
+  __syncthreads();
   // bounds of this thread's bins first (independent loads), then their particles
   uint32_t lo[T::PER], hi[T::PER];
 #pragma unroll
@@ -293,6 +357,11 @@ __device__ __forceinline__ void deposit_tile(const uint32_t* __restrict__ start,
   for (int k = 0; k < T::PER; ++k) {
     const int b = threadIdx.x + 256 * k;
     if (b >= T::NB) continue;
+    if (hi[k] - lo[k] > kCrowded) {
+      // the list order only decides which wave sums the bin
+      crowd[atomicAdd(&ncrowd, 1)] = static_cast<uint16_t>(b);
+      continue;
+    }
     float acc[8];
 #pragma unroll
     for (int o = 0; o < 8; ++o) acc[o] = 0.0f;
@@ -306,6 +375,8 @@ __device__ __forceinline__ void deposit_tile(const uint32_t* __restrict__ start,
 #pragma unroll
     for (int o = 0; o < 8; ++o) W[o * T::NB + b] = acc[o];
   }
+  __syncthreads();
+  crowded_bin_sums<TX, TY, TZ, false>(start, spos, nullptr, 0, crowd, ncrowd, x0, y0, z0, n, W);
 }
 
 // sum over the 8 corners of cell (cx, cy, cz) of the tile
@@ -370,8 +441,12 @@ __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __rest
   using T = DepTile<TX, TY, TZ>;
   constexpr int CPT = (T::NC + 255) / 256;   // cells per thread
   __shared__ float W[8 * T::NB];
+  __shared__ int ncrowd;
+  __shared__ uint16_t crowd[T::NB];
   const StepScal& sc = tab[blockIdx.y];
   if (!sc.active) return;
+  if (threadIdx.x == 0) ncrowd = 0;
+  __syncthreads();
   const float scale = merged ? sc.h_dm : sc.h_open;
   const long long nc = static_cast<long long>(n) * n * n;
   start += blockIdx.y * nc;
@@ -391,6 +466,14 @@ __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __rest
       hi[k] = start[cell + 1];
     }
   }
+  // crowded bins: listed once, summed by waves for each component
+  bool crowded[T::PER];
+#pragma unroll
+  for (int k = 0; k < T::PER; ++k) {
+    const int b = threadIdx.x + 256 * k;
+    crowded[k] = b < T::NB && hi[k] - lo[k] > kCrowded;
+    if (crowded[k]) crowd[atomicAdd(&ncrowd, 1)] = static_cast<uint16_t>(b);
+  }
   float4 p0[T::PER], v0[T::PER];
 #pragma unroll
   for (int k = 0; k < T::PER; ++k) {
@@ -398,13 +481,16 @@ __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __rest
     p0[k] = spos[j];
     v0[k] = sval[j];
   }
+  __syncthreads();
   float sum[3][CPT];
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
+    crowded_bin_sums<TX, TY, TZ, true>(start, spos, sval, v, crowd, ncrowd, x0, y0, z0, n, W);
 #pragma unroll
     for (int k = 0; k < T::PER; ++k) {
       const int b = threadIdx.x + 256 * k;
       if (b >= T::NB) continue;
+      if (crowded[k]) continue;   // summed by a wave
       float acc[8];
 #pragma unroll
       for (int o = 0; o < 8; ++o) acc[o] = 0.0f;
