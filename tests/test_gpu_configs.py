@@ -177,3 +177,53 @@ def test_gradient_128_full_run_is_consistent(dhp):
         _say(f"  {name}: finite difference {fd:.6e}, adjoint {gp[i]:.6e}")
         assert abs(fd - gp[i]) <= 1e-3 * abs(gp[i]) + 1e-6 * abs(l0) / h
     one.close()
+
+
+@pytest.mark.parametrize("n,box,a_final", [(32, 5.0, 0.29), (64, 10.0, 0.1)])
+def test_long_run_gradient_matches_oracle_autograd(dhp, n, box, a_final):
+    """Over whole runs (0.156 Mpc/h cells, CFL 0.4, no source term) the reverse pass is the
+    exact derivative of the discrete map: against the FP64 oracle's autograd over 89 steps to
+    a = 0.29 at 32^3 and 60 steps to a = 0.1 at 64^3 (the oracle's own central differences
+    along a random direction are printed beside it).  The map is piecewise smooth
+    (limiter, |U_d|, CIC cell crossings); float32 and float64 take different sides of the
+    kinks in a few cells per step, which over these runs moves the gradient by a few 1e-3
+    (5e-3 bar).  At 128^3 the float32 forward cannot resolve the derivative by finite
+    differences beyond a ~ 0.05: steps above its rounding noise (eps >= 1e-3) cross many
+    kinks, and the exact derivative grows quickly with a and with resolution."""
+    import torch as th
+    from gpu_helpers import gpu_config, gpu_params, initial_state_fp32_cells, rel_l2, to_np
+    from oracle import sim as osim
+    th.set_num_threads(16)
+    prm = osim.Params(eps_sf=0.03, delta_c=10.0, t_c=1e7)
+    ocfg = osim.default_config(n=n, box=box, a_init=0.01)
+    w = si.white_noise(n, 11)
+    tgt, sched = osim.run(osim.initial_state(th.from_numpy(si.white_noise(n, 12)).double(), ocfg),
+                          ocfg, prm, a_final=a_final)
+    target = osim.flux_observable(tgt.q[0], ocfg.f_b, prm.A, prm.beta).detach()
+    _, sched = osim.run(osim.initial_state(th.from_numpy(w).double(), ocfg), ocfg, prm,
+                        a_final=a_final)
+    _say(f"long-run gradient {n}^3 to a = {a_final}: {len(sched)} steps, oracle autograd")
+    w64 = th.from_numpy(w).double().requires_grad_(True)
+    st, _ = osim.run(initial_state_fp32_cells(w64, ocfg), ocfg, prm, schedule=sched)
+    L = osim.loss(st, target, ocfg, prm.A, prm.beta)
+    (gref,) = th.autograd.grad(L, w64)
+    s = dhp.Sim(gpu_config(ocfg, ckpt_every=16), gpu_params(prm))
+    s.set_schedule(sched)
+    s.forward(to_gpu(w), 1.0)
+    lval = s.loss(to_gpu(target.numpy()))
+    gw, _ = s.backward()
+    g = to_np(gw)
+    err = rel_l2(g, gref.numpy())
+    _say(f"long-run gradient {n}^3: loss {lval:.6e} / {float(L.detach()):.6e}, rel-L2 {err:.2e}")
+    assert abs(lval - float(L.detach())) < 1e-4 * float(L.detach())
+    assert err < 5e-3
+    # the oracle's finite differences converge to its exact derivative along a direction
+    v = th.from_numpy(np.random.default_rng(13).standard_normal((n, n, n)))
+    eps = 1e-6
+    with th.no_grad():
+        lp, lm = (osim.loss(osim.run(osim.initial_state(th.from_numpy(w).double() + sg * eps * v,
+                                                        ocfg), ocfg, prm, schedule=sched)[0],
+                            target, ocfg, prm.A, prm.beta) for sg in (1.0, -1.0))
+    fd = float(lp - lm) / (2 * eps)
+    ad = float((gref * v).sum())
+    _say(f"  oracle: finite difference {fd:.6e}, autograd {ad:.6e}; GPU {float((th.from_numpy(g) * v).sum()):.6e}")
