@@ -537,6 +537,16 @@ __device__ __forceinline__ mlp::Act<NCT> stage_operands(const float (*stage)[kSt
   return in;
 }
 
+// Each wave of the closure kernels owns its 64 cells' slots of the LDS stage and exchanges
+// values only among its own lanes, so the waves synchronise on their own: the fences order
+// the wave's LDS writes before its later reads, and the waves of a block run independently
+// (one wave's matrix products overlap another's scalar work).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 struct ClosureDraw {
   double x, psf, pi0, z, lgate;
 };
@@ -589,6 +599,7 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
   __shared__ __attribute__((aligned(16))) float bias[mlp::kBias];
   __shared__ float stage[kRedThreads / 64][64][kStage];
   mlp::load_packed(a.mlp, mlp::kFrFwd, fr, bias);
+  __syncthreads();   // the weights; from here on every wave works on its own cells
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, cl = lane & 15;
   double vmax[1] = {0.0};
@@ -615,7 +626,7 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
     closure_inputs(q5, a, xin, e_raw, floored);
 #pragma unroll
     for (int k = 0; k < 5; ++k) stage[wave][lane][k] = valid ? xin[k] : 0.0f;
-    __syncthreads();
+    wave_sync();
     mlp::f4 o[4];
     mlp::forward<4>(fr, bias, stage_operands<4>(stage[wave], lane), o, nullptr, nullptr, lane);
     if (g == 0) {
@@ -625,7 +636,7 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
         stage[wave][16 * ct + cl][6] = o[ct][1];
       }
     }
-    __syncthreads();
+    wave_sync();
     if (valid) {
       const float o0 = stage[wave][lane][5], o1 = stage[wave][lane][6];
       const float lg = closure_logit_estimate(o0, o1, a);
@@ -649,7 +660,7 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
       for (int k = (q == q_in ? 1 : 0); k < 5; ++k) q[k * nc + c] = q5[k];
       if (partial) vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
     }
-    __syncthreads();
+    wave_sync();
   }
   if (partial) block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
 }
@@ -672,6 +683,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
   __shared__ __attribute__((aligned(16))) float bias[mlp::kBias];
   __shared__ float stage[kRedThreads / 64][64][kStage];
   mlp::load_packed(a.mlp, mlp::kFrAll, fr, bias);
+  __syncthreads();   // the weights; from here on every wave works on its own cells
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, cl = lane & 15;
   const double K = a.a * a.a * a.e0_code;
@@ -688,7 +700,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
     closure_inputs(q5, a, xin, e_raw, floored);
 #pragma unroll
     for (int k = 0; k < 5; ++k) stage[wave][lane][k] = valid ? xin[k] : 0.0f;
-    __syncthreads();
+    wave_sync();
     // per half of 32 cells: the forward with its derivatives, dL/do of those cells (their
     // lanes), the backward; the network runs forward once per cell
     double le = 0.0, li = 0.0, z = 0.0;   // adjoints of the energy and of the injection
@@ -705,7 +717,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
           stage[wave][32 * half + 16 * ct + cl][6] = oh[ct][1];
         }
       }
-      __syncthreads();
+      wave_sync();
       if ((lane >> 5) == half) {
         // dL/do of this lane's cell; the lane reads and then overwrites its own slots
         double go0 = 0.0, go1 = 0.0;
@@ -729,7 +741,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
         stage[wave][lane][5] = static_cast<float>(go0);
         stage[wave][lane][6] = static_cast<float>(go1);
       }
-      __syncthreads();
+      wave_sync();
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
         go[ct] = mlp::f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -739,7 +751,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
         }
       }
       mlp::backward<2>(fr, sd, go, dx, nullptr, lane);
-      __syncthreads();
+      wave_sync();
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
         float* cellst = stage[wave][32 * half + 16 * ct + cl];
@@ -750,7 +762,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
           cellst[4] = dx[ct][0];
         }
       }
-      __syncthreads();
+      wave_sync();
     }
     if (valid) {
       // Et' = Et + K rho z; inputs x0 = (ln Delta - 4.6)/5, x1 = (ln T - 10.4)/5 with T ~ e
@@ -770,7 +782,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
       acc[0] += stage[wave][lane][3] / 0.02;
       acc[1] += stage[wave][lane][4] / 100.0;
     }
-    __syncthreads();
+    wave_sync();
   }
   block_reduce_store<2, false>(acc, sample_partials(partial), partial_stride());
 }
