@@ -90,12 +90,13 @@ def total_overdensity(rho_gas, x, dm_mass, n):
 def gas_kick(q, g, h):
     """Gravity source S_g of eq. conservation over a time h, in operator-split form:
     m += rho g h;  a^2 rho E += m_bar . g h with m_bar the mean of m before and after,
-    which leaves the internal energy a^2 rho e unchanged."""
+    which leaves the internal energy a^2 rho e unchanged (and with it the entropy of a
+    dual-energy state, passed through)."""
     rho = q[0]
     m_old = q[1:4]
     m_new = m_old + rho * g * h
     e_new = q[4] + (0.5 * (m_old + m_new) * g).sum(0) * h
-    return torch.cat([rho[None], m_new, e_new[None]])
+    return torch.cat([rho[None], m_new, e_new[None], q[5:]])
 
 
 def dm_kick(p, x, g, h):

@@ -12,6 +12,19 @@ The internal-energy source S_e is not applied: the energy variable is the total 
 whose flux already carries the pdV work (a reading: the paper lists S_e beside a total-
 energy equation whose flux has the pressure work).
 
+Dual energy (an option; Sec. 2.3 names the dual-energy formalism as the extension of its
+single-energy scheme without fixing one): a sixth conserved component S = (a^2 rho e)
+rho^(1-gamma), the entropy variable, is advected with the flux S U_d / a.  With gamma = 5/3,
+S / rho = a^2 e rho^(1-gamma) is a function of the proper entropy p_prop / rho_prop^gamma alone,
+so it is carried unchanged by the flow wherever the flow is adiabatic.  The equation of state
+takes the specific internal energy from the total energy, e_E = E - U^2/2, where
+e_E > eta1 E, and from the entropy, e_S = S rho^(gamma-2) / a^2, elsewhere (kinetic energy
+dominating: e_E is then a small difference of large numbers); at the end of each step S is
+reset from the total energy where e_E >= eta2 E, so shocks, which raise the entropy, feed it.
+The selection and synchronisation rule and eta1 = 1e-3, eta2 = 0.1 are those of Bryan et al.
+(1995); the entropy in place of an internal-energy equation follows Ryu et al. (1993), and
+needs no pdV source term.
+
 Units: length in cells (Delta x = 1), time in 1/H0, velocity in cells*H0.
 Arrays are indexed [component, z, y, x] (x fastest); axis d = 0, 1, 2 means x, y, z.
 """
@@ -24,16 +37,55 @@ def shift(f, d, s):
     return torch.roll(f, shifts=-s, dims=f.dim() - 1 - d)
 
 
+DUAL_ETA1 = 1e-3   # below this fraction of E, e comes from the entropy
+DUAL_ETA2 = 0.1    # at or above it, the entropy is reset from the total energy
+
+
+def entropy_energy(q, a, gamma):
+    """e_S = S rho^(gamma-2) / a^2: the specific internal energy held by the entropy S."""
+    return q[5] * q[0] ** (gamma - 2.0) / (a * a)
+
+
+def internal_energy(q, a, gamma):
+    """(e, U): the specific internal energy before the floor and the peculiar velocity.
+    Single energy (five components): e = E - U^2/2.  Dual energy (six): that where it
+    exceeds eta1 E, else e_S (module docstring)."""
+    rho = q[0]
+    u = q[1:4] / (a * rho)
+    big_e = q[4] / (a * a * rho)
+    e = big_e - 0.5 * (u * u).sum(0)
+    if q.shape[0] > 5:
+        e = torch.where(e > DUAL_ETA1 * big_e, e, entropy_energy(q, a, gamma))
+    return e, u
+
+
+def entropy_of_total(q, gamma):
+    """S = (a^2 rho E - |a rho U|^2 / (2 rho)) rho^(1-gamma): the entropy variable of the
+    internal energy that the total energy holds."""
+    rho = q[0]
+    return (q[4] - 0.5 * (q[1:4] * q[1:4]).sum(0) / rho) * rho ** (1.0 - gamma)
+
+
+def dual_sync(q, a, gamma):
+    """End-of-step synchronisation of the dual-energy state: S from the total energy where
+    e_E >= eta2 E, unchanged elsewhere."""
+    rho = q[0]
+    u = q[1:4] / (a * rho)
+    big_e = q[4] / (a * a * rho)
+    e = big_e - 0.5 * (u * u).sum(0)
+    s = torch.where(e >= DUAL_ETA2 * big_e, entropy_of_total(q, gamma), q[5])
+    return torch.cat([q[:5], s[None]])
+
+
 def primitives(q, a, gamma, e_floor):
     """Velocity, pressure and sound speed from Q at scale factor a.
 
-    The specific internal energy e = E - U^2/2 is floored at e_floor only inside the
+    The specific internal energy e (internal_energy) is floored at e_floor only inside the
     equation of state (pressure, sound speed); the stored total energy is never changed,
     so the conservation form is untouched.  p = (gamma-1) rho e, c_s = sqrt(gamma p/rho).
     """
     rho = q[0]
-    u = q[1:4] / (a * rho)
-    e = q[4] / (a * a * rho) - 0.5 * (u * u).sum(0)
+    e, u = internal_energy(q, a, gamma)
     e_eff = torch.clamp(e, min=e_floor)
     p = (gamma - 1.0) * rho * e_eff
     cs = torch.sqrt(gamma * p / rho)
@@ -51,7 +103,8 @@ def flux_and_speed(q, a, d, gamma, e_floor, sign_ud=None):
     u, p, cs = primitives(q, a, gamma, e_floor)
     ud = u[d]
     mom = [rho * ud * u[j] + (p if j == d else 0.0) for j in range(3)]
-    f = torch.stack([rho * ud / a] + mom + [a * ud * (q[4] / (a * a) + p)])
+    extra = [q[5] * ud / a] if q.shape[0] > 5 else []
+    f = torch.stack([rho * ud / a] + mom + [a * ud * (q[4] / (a * a) + p)] + extra)
     c = ((ud.abs() if sign_ud is None else sign_ud * ud) + cs) / a
     return f, c
 

@@ -111,7 +111,11 @@ def state_from_displacement(psi, cfg, psi2=None):
     mom = rho * vel
     u = mom / (a * rho)
     etot = a * a * rho * (cfg.e_init + 0.5 * (u * u).sum(0))
-    q = torch.cat([rho[None], mom, etot[None]])
+    # dual energy: the entropy variable of the initial internal energy, a^2 rho e_init
+    # rho^(1-gamma)
+    extra = ([(a * a * cfg.e_init * rho ** (2.0 - cfg.gamma))[None]]
+             if getattr(cfg, "dual_energy", False) else [])
+    q = torch.cat([rho[None], mom, etot[None]] + extra)
     return q, x, p
 
 

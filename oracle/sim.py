@@ -15,7 +15,9 @@ source is a reading of Sec. 2.2-2.4, which state the operators but not one seque
      with the supernova energy spread over neighbouring cells (subgrid.smooth_injection);
   8. optionally, the stars formed in the step read out by CIC at the particles' positions
      and added to the particles' auxiliary field (Sec. 2.4.1: the new stars are associated
-     with nearby dark-matter particles, a diagnostic that does not act on the evolution).
+     with nearby dark-matter particles, a diagnostic that does not act on the evolution);
+  9. with the dual-energy formalism, the entropy reset from the total energy where the
+     internal energy is a large enough part of it (hydro.dual_sync).
 The state carries phi so that each step solves Poisson once; phi of the initial state is
 solved from the initial particles and gas.
 """
@@ -55,6 +57,7 @@ class Config:
     transfer: int = 0             # cosmology.TRANSFER_BBKS or TRANSFER_EH
     sn_smooth: bool = False       # supernova energy spread over the neighbouring cells
     star_dm: bool = False         # keep the stars' read-out on the particles (State.aux)
+    dual_energy: bool = False     # carry the entropy variable S as a sixth gas component
 
     # derived quantities (filled by finish())
     amp: float = 0.0
@@ -102,7 +105,7 @@ class Params:
 
 @dataclass
 class State:
-    q: torch.Tensor      # [5, n, n, n]
+    q: torch.Tensor      # [5, n, n, n], or [6, n, n, n] with the entropy (dual energy)
     x: torch.Tensor      # [3, n^3]
     p: torch.Tensor      # [3, n^3]
     star: torch.Tensor   # [n, n, n]
@@ -188,6 +191,8 @@ def step(state, cfg, prm, dt):
         if cfg.star_dm:
             # the step's new stars, read out at the particles' end-of-step positions
             aux = aux + gravity.cic_readout(z, x)
+    if cfg.dual_energy:
+        q = hydro.dual_sync(q, a1, cfg.gamma)
     return State(q=q, x=x, p=p, star=star, phi=phi, t=state.t + dt, a=a1, step=state.step + 1,
                  aux=aux)
 

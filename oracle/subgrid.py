@@ -15,6 +15,8 @@ Per cell and step:
   the tau -> 0 limit of the relaxed one.
 Effect of a formation event: the specific energy E0 is added in the cell,
 a^2 rho E += a^2 rho z E0, and the diagnostic star field gains z.  The gas mass is unchanged.
+In a dual-energy state the entropy variable gains the same internal energy,
+S += a^2 rho z E0 rho^(1-gamma).
 E0 is given in (1000 km/s)^2.
 
 Smoothed injection (an option; Sec. 2.4.1 models the supernova heating as the start of a
@@ -28,6 +30,8 @@ import math
 
 import torch
 
+from . import hydro
+
 K_BOLTZMANN = 1.380649e-23      # J / K
 M_PROTON = 1.67262192369e-27    # kg
 
@@ -40,10 +44,9 @@ def kelvin_per_code_energy(gamma, mu, vel_unit_kms):
 
 
 def temperature(q, a, gamma, e_floor, t_per_e):
-    """Gas temperature [K] from the floored specific internal energy."""
-    rho = q[0]
-    u = q[1:4] / (a * rho)
-    e = q[4] / (a * a * rho) - 0.5 * (u * u).sum(0)
+    """Gas temperature [K] from the floored specific internal energy (of the total energy,
+    or the dual-energy selection: hydro.internal_energy)."""
+    e, _ = hydro.internal_energy(q, a, gamma)
     return torch.clamp(e, min=e_floor) * t_per_e
 
 
@@ -91,6 +94,10 @@ def apply_source(q, star, a, dt, u, *, rho_mean_gas, omega_b, gamma, e_floor, t_
                                 w_rho, w_t, mode)
     z = draw(pi0, u, tau, mode)
     inj = a * a * rho * z * e0_code
-    e_new = q[4] + (smooth_injection(inj) if smooth else inj)
-    out = (torch.cat([q[:4], e_new[None]]), star + z)
+    add = smooth_injection(inj) if smooth else inj
+    e_new = q[4] + add
+    # a dual-energy state: the entropy variable of the added internal energy, in the cell
+    # that receives it
+    extra = [q[5] + add * rho ** (1.0 - gamma)] if q.shape[0] > 5 else []
+    out = (torch.stack([q[0], q[1], q[2], q[3], e_new] + extra), star + z)
     return out + (z,) if with_draw else out
