@@ -115,6 +115,15 @@ typedef struct dh_config {
                             potential, D2/D1^2 = -3/7 Omega_m(a)^(-1/143), velocities with
                             f2 = 2 Omega_m(a)^(6/11)); differentiated by dh_backward          */
     int32_t transfer;    /* DH_TRANSFER_*                                                   */
+    int32_t dual_energy; /* 1: the dual-energy formalism, the extension of the single-energy
+                            scheme named in Sec. 2.3: a sixth gas component S = (a^2 rho e)
+                            rho^(1-gamma), the entropy variable, advected with the flux
+                            S U_d / a; the EOS takes e = E - U^2/2 where that exceeds
+                            1e-3 E and S rho^(gamma-2) / a^2 elsewhere, and at the end of
+                            each step S is reset from the total energy where E - U^2/2 >=
+                            0.1 E (Bryan et al. 1995 with the entropy of Ryu et al. 1993).
+                            Differentiated by dh_backward.  Not with closure = MLP or
+                            sn_smooth = 1 (DH_E_INVAL)                                      */
 } dh_config;
 
 /* Model parameters (double).  A, beta: flux observable F = exp(-A Delta^beta) of the loss;
@@ -125,8 +134,10 @@ typedef struct dh_params {
     double A, beta, eps_sf, delta_c, t_c, e0, w_rho, w_t;
 } dh_params;
 
-/* Fields for dh_get_field / dh_set_field.  Sizes in floats: Q = 5 n^3, POS and MOM = 3 n^3,
- * the rest n^3.  TEMP (get only) is the gas temperature [K] from the floored energy.
+/* Fields for dh_get_field / dh_set_field.  Sizes in floats: Q = 5 n^3 (6 n^3 with
+ * cfg.dual_energy: the entropy S is the sixth component), POS and MOM = 3 n^3, the rest n^3.
+ * TEMP (get only) is the gas temperature [K] from the floored energy (the dual-energy
+ * selection where cfg.dual_energy).
  * STAR_DM: the particles' auxiliary field of read-out stars, in particle order (needs
  * cfg.star_dm; zeroed by the initial conditions).  OBS_TEMP (get only): the observable of
  * the field-level inference, O = (rho / rho_mean_gas) T [K], the gas-mass-weighted
@@ -302,7 +313,8 @@ int dh_conservation_noalloc(const float* d_q, const float* d_mom, int32_t n, int
  * against a reference.  They do not touch the handle's state.  All pointers are device
  * float32.
  *  sweep:    q_out = one relaxing-TVD sweep of q_in along axis (0 x, 1 y, 2 z) over dt,
- *            with scale factors a_stage1, a_stage2 (Sec. 2.3.1-2.3.2).
+ *            with scale factors a_stage1, a_stage2 (Sec. 2.3.1-2.3.2); q holds the handle's
+ *            gas components (5 n^3 floats, 6 n^3 with cfg.dual_energy).
  *  sweep_vjp: lam_in = (d sweep / d q_in)^T lam_out at q_in.
  *  poisson:  phi = solution of lap(phi) = (3 Om / 2a) delta (Green's function -1/k^2).
  *  deposit:  delta = rho_gas + m_dm CIC(pos) - 1 (cell-sorted, deterministic).

@@ -35,7 +35,8 @@ class Config(ctypes.Structure):
                 ("batch", ctypes.c_int32), ("cfl_forward", ctypes.c_double),
                 ("kdk", ctypes.c_int32), ("star_dm", ctypes.c_int32),
                 ("sn_smooth", ctypes.c_int32), ("lpt", ctypes.c_int32),
-                ("transfer", ctypes.c_int32)]
+                ("transfer", ctypes.c_int32),
+                ("dual_energy", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):

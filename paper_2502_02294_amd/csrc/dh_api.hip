@@ -96,6 +96,7 @@ struct dh_sim {
   dh_params prm;                    // shared parameters (loss: A, beta)
   std::vector<dh_params> sprm;      // per-sample parameters of the source term
   int n = 0, S = 1;
+  int nq = 5;   // gas components per cell: 6 with the dual-energy entropy
   long long nc = 0, np = 0, nck = 0;
   hipStream_t st = nullptr;
   dh::Cosmo cosmo{};
@@ -293,7 +294,7 @@ dh::HydroK hydro_at(const dh_sim* s, double a) {
 
 void sync(dh_sim* s) { DH_HIP(hipStreamSynchronize(s->st)); }
 
-Batch batch(const dh_sim* s, const StepScal* tab) { return Batch{s->n, s->S, tab}; }
+Batch batch(const dh_sim* s, const StepScal* tab) { return Batch{s->n, s->S, tab, s->nq}; }
 
 float green_at(const dh_sim* s, double a) {
   return static_cast<float>(-(1.5 * s->cfg.omega_m / a) / static_cast<double>(s->nc));
@@ -307,6 +308,7 @@ dh::SourceArgs source_args(const dh_sim* s, int smp, double a1, double dt, int s
   a.inv_rho_mean = 1.0 / s->f_b;
   a.omega_b = s->cfg.omega_b;
   a.efloor = s->e_floor;
+  a.gamma = s->cfg.gamma;
   a.t_per_e = s->t_per_e;
   a.e0_code = p.e0 * 1e6 / (s->vel_unit * s->vel_unit);
   a.eps_sf = p.eps_sf;
@@ -438,7 +440,7 @@ void flush_kick(dh_sim* s) {
   }
   DH_HIP(hipMemcpyAsync(s->cur_tab, s->hstage, static_cast<size_t>(s->S) * sizeof(StepScal),
                         hipMemcpyHostToDevice, s->st));
-  dh::launch_kick(s->st, s->g4, s->pos, s->mom, Batch{s->n, s->S, s->cur_tab});
+  dh::launch_kick(s->st, s->g4, s->pos, s->mom, Batch{s->n, s->S, s->cur_tab, s->nq});
   std::fill(s->kick_due.begin(), s->kick_due.end(), 0.0f);
   s->kick_pending = false;
 }
@@ -459,21 +461,21 @@ long long store_step_bytes(const dh_sim* s) {
 long long reverse_pass_bytes(const dh_sim* s) {
   const long long S = s->S, nc = s->nc * S, np = s->np * S;
   const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
-  const long long entry = (closure ? 6 : 5) * 5 * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 +
+  const long long entry = (closure ? 6 : 5) * s->nq * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 +
                           np * 4 + np * 16;
   long long need = 0;
   const long long k = s->cfg.ckpt_every;
   if (static_cast<long long>(s->tape.size()) < k)
     need += (k - static_cast<long long>(s->tape.size())) * entry;
-  if (!s->lq) need += 29 * nc * 4;
-  if (!s->keep.q) need += 5 * nc * 4 + 6 * np * 4 + 2 * nc * 4;
+  if (!s->lq) need += (29 + 2 * (s->nq - 5)) * nc * 4;
+  if (!s->keep.q) need += s->nq * nc * 4 + 6 * np * 4 + 2 * nc * 4;
   return need;
 }
 
 long long tape_entry_bytes(const dh_sim* s) {
   const long long S = s->S, nc = s->nc * S, np = s->np * S;
   const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
-  return (closure ? 6 : 5) * 5 * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 + np * 4 +
+  return (closure ? 6 : 5) * s->nq * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 + np * 4 +
          np * 16;
 }
 
@@ -558,7 +560,7 @@ void poisson(dh_sim* s, const float* delta, float* phi_out, const Batch& b) {
 // particle positions already built
 void potential_from_bins(dh_sim* s, const float* rho_gas, float* phi_out, float4* g4_out,
                          const Batch& b) {
-  dh::launch_deposit(s->st, s->bins, rho_gas, 5 * s->nc, static_cast<float>(s->m_dm), -1.0f,
+  dh::launch_deposit(s->st, s->bins, rho_gas, s->nq * s->nc, static_cast<float>(s->m_dm), -1.0f,
                      s->delta, b);
   poisson(s, s->delta, phi_out, b);
   dh::launch_grad(s->st, phi_out, g4_out, b);
@@ -639,7 +641,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
       std::swap(s->phi, tp->phi0);
       pos_in = tp->x0;
     } else {
-      copy_d2d(s, tp->q[0], s->q, 5 * nc * s->S);
+      copy_d2d(s, tp->q[0], s->q, s->nq * nc * s->S);
       copy_d2d(s, tp->x0, s->pos, 3 * np * s->S);
       copy_d2d(s, tp->phi0, s->phi, nc * s->S);
     }
@@ -819,7 +821,7 @@ void initial_conditions(dh_sim* s, const float* d_white) {
   dh::launch_deposit(s->st, s->bins, nullptr, 0, 1.0f, 0.0f, s->cic, all);
   dh::launch_ic_gas(s->st, s->cic, vel, s->q, static_cast<float>(s->f_b),
                     static_cast<float>(vfac), static_cast<float>(ai), static_cast<float>(s->e_init),
-                    all);
+                    s->cfg.gamma, all);
   dh::launch_fill(s->st, s->star, 0.0f, s->nc * s->S);
   if (s->aux) dh::launch_fill(s->st, s->aux, 0.0f, s->np * s->S);
   reset_clock(s);
@@ -865,7 +867,7 @@ const std::vector<double>& pk_counts(dh_sim* s, int nbins) {
 
 // half spectrum of each sample's gas density into s->spec (forward, unnormalised)
 void density_spectrum(dh_sim* s, const Batch& b) {
-  dh::fft_forward_xy(s->st, s->q, s->spec, s->tw, b, 5 * s->nc);
+  dh::fft_forward_xy(s->st, s->q, s->spec, s->tw, b, s->nq * s->nc);
   dh::fft_zpass_forward(s->st, s->spec, s->spec, s->tw, b);
 }
 
@@ -911,7 +913,7 @@ void power_loss_vjp(dh_sim* s) {
   density_spectrum(s, b);
   dh::launch_pk_scale(s->st, s->spec, s->d_pk_g, nbins, b);
   dh::fft_zpass_inverse(s->st, s->spec, s->tw, b);
-  dh::fft_inverse_yx(s->st, s->spec, s->lq, s->tw, 2.0f, b, 5 * s->nc);
+  dh::fft_inverse_yx(s->st, s->spec, s->lq, s->tw, 2.0f, b, s->nq * s->nc);
   sync(s);   // pk_g is host memory read by the copy above
 }
 
@@ -1051,7 +1053,7 @@ void alloc_tape_entry(dh_sim* s, TapeStep& t) {
   const long long S = s->S;
   const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
   for (int k = 0; k < 6; ++k)
-    t.q[k] = k < 5 || closure ? s->alloc<float>(5 * s->nc * S) : nullptr;
+    t.q[k] = k < 5 || closure ? s->alloc<float>(s->nq * s->nc * S) : nullptr;
   t.x0 = s->alloc<float>(3 * s->np * S);
   t.x1 = nullptr;
   t.phi0 = s->alloc<float>(s->nc * S);
@@ -1079,13 +1081,13 @@ void save_ckpt(dh_sim* s, Ckpt& c) {
   const long long S = s->S;
   flush_kick(s);
   if (!c.q) {
-    c.q = s->alloc<float>(5 * s->nc * S);
+    c.q = s->alloc<float>(s->nq * s->nc * S);
     c.pos = s->alloc<float>(3 * s->np * S);
     c.mom = s->alloc<float>(3 * s->np * S);
     c.star = s->alloc<float>(s->nc * S);
     c.phi = s->alloc<float>(s->nc * S);
   }
-  copy_d2d(s, c.q, s->q, 5 * s->nc * S);
+  copy_d2d(s, c.q, s->q, s->nq * s->nc * S);
   copy_d2d(s, c.pos, s->pos, 3 * s->np * S);
   copy_d2d(s, c.mom, s->mom, 3 * s->np * S);
   copy_d2d(s, c.star, s->star, s->nc * S);
@@ -1098,7 +1100,7 @@ void save_ckpt(dh_sim* s, Ckpt& c) {
 void load_ckpt(dh_sim* s, const Ckpt& c) {
   const long long S = s->S;
   drop_kick(s);
-  copy_d2d(s, s->q, c.q, 5 * s->nc * S);
+  copy_d2d(s, s->q, c.q, s->nq * s->nc * S);
   copy_d2d(s, s->pos, c.pos, 3 * s->np * S);
   copy_d2d(s, s->mom, c.mom, 3 * s->np * S);
   copy_d2d(s, s->star, c.star, s->nc * S);
@@ -1118,7 +1120,7 @@ void stash_state(dh_sim* s) {
   Ckpt& c = s->keep;
   const long long S = s->S;
   if (!c.q) {
-    c.q = s->alloc<float>(5 * s->nc * S);
+    c.q = s->alloc<float>(s->nq * s->nc * S);
     c.pos = s->alloc<float>(3 * s->np * S);
     c.mom = s->alloc<float>(3 * s->np * S);
     c.star = s->alloc<float>(s->nc * S);
@@ -1167,7 +1169,7 @@ void opening_kick_vjp(dh_sim* s, const float* q0, const Batch& b) {
 
 void flush_open_vjp(dh_sim* s) {
   if (!s->open_pending) return;
-  opening_kick_vjp(s, s->open_q0, Batch{s->n, s->S, s->open_tab});
+  opening_kick_vjp(s, s->open_q0, Batch{s->n, s->S, s->open_tab, s->nq});
   s->open_pending = false;
 }
 
@@ -1193,7 +1195,7 @@ void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
   // energy adjoint unchanged, so it may be taken before the fused kernel applies that kick
   const float* lam_inj = nullptr;
   if (source && s->cfg.sn_smooth) {
-    dh::launch_smooth27(st, s->lq + 4 * nc, 5 * nc, s->sn_buf, b);
+    dh::launch_smooth27(st, s->lq + 4 * nc, s->nq * nc, s->sn_buf, b);
     lam_inj = s->sn_buf;
   }
   if (closure) {
@@ -1223,7 +1225,7 @@ void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
     dh::launch_grad_vjp(st, s->lg, s->lphi, s->lphi2, b);
   // Poisson (symmetric operator) and deposit at x1
   poisson(s, s->lphi2, s->ldelta, b);
-  dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc, 5 * nc, nc, false, b);
+  dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc, s->nq * nc, nc, false, b);
   // with the kicks' term at x1 (g4b still holds g_{n+1}) and the drift
   // x1 = x0 + p_half dt / a_h^2: lambda_p += (dt / a_h^2) lambda_x
   dh::launch_deposit_vjp_pos(st, s->ldelta, T.x1, static_cast<float>(s->m_dm), s->lx, s->lp,
@@ -1273,7 +1275,7 @@ void ic_vjp(dh_sim* s, float* d_grad_white) {
   const Batch b0 = batch(s, state_table(s));
   // phi_0 = Poisson(rho_gas + m_dm CIC(x) - 1)
   poisson(s, s->lphi, s->ldelta, b0);
-  dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc, 5 * nc, nc, false, all);
+  dh::launch_axpy(st, s->lq, s->ldelta, 1.0f, nc, s->nq * nc, nc, false, all);
   // positions of the initial particles are recomputed from psi (the momenta, written to
   // scratch, are not needed)
   const double vfac = ai * ai * s->cosmo.E(ai) * s->cosmo.growth_rate(ai);
@@ -1290,7 +1292,7 @@ void ic_vjp(dh_sim* s, float* d_grad_white) {
   if (lpt2) dh::launch_fill(st, lvel, 0.0f, 3 * nc * s->S);
   dh::launch_ic_gas_vjp(st, s->cic, vel, s->lq, static_cast<float>(s->f_b),
                         static_cast<float>(vfac), static_cast<float>(ai),
-                        static_cast<float>(s->e_init), s->lcic, lvel, all);
+                        static_cast<float>(s->e_init), s->cfg.gamma, s->lcic, lvel, all);
   dh::launch_deposit_vjp_pos(st, s->lcic, s->pos, 1.0f, s->lx, nullptr, nullptr, all);
   // x = q + psi, p = vfac vel
   dh::launch_axpy(st, s->lpsi, s->lx, 1.0f, 3 * nc, 3 * nc, 3 * nc, false, all);
@@ -1373,6 +1375,7 @@ void dh_config_default(dh_config* c) {
   c->sn_smooth = 0;
   c->lpt = 1;
   c->transfer = DH_TRANSFER_BBKS;
+  c->dual_energy = 0;
 }
 
 void dh_params_default(dh_params* p) {
@@ -1402,6 +1405,8 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
         (cfg->star_dm == 0 || cfg->star_dm == 1) && (cfg->sn_smooth == 0 || cfg->sn_smooth == 1) &&
         (cfg->lpt == 1 || cfg->lpt == 2) &&
         (cfg->transfer == DH_TRANSFER_BBKS || cfg->transfer == DH_TRANSFER_EH) &&
+        (cfg->dual_energy == 0 ||
+         (cfg->dual_energy == 1 && cfg->closure == DH_CLOSURE_PLAIN && cfg->sn_smooth == 0)) &&
         (cfg->closure == DH_CLOSURE_PLAIN ||
          (cfg->closure == DH_CLOSURE_MLP && cfg->subgrid != DH_SUBGRID_OFF))))
     return DH_E_INVAL;
@@ -1412,6 +1417,7 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
     s->sprm.assign(S, s->prm);
     s->n = n;
     s->S = S;
+    s->nq = cfg->dual_energy ? 6 : 5;
     s->nc = static_cast<long long>(n) * n * n;
     s->np = s->nc;
     s->nck = static_cast<long long>(n) * n * (n / 2 + 1);
@@ -1434,8 +1440,8 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
     s->replay_pos.assign(S, 0);
     s->kick_due.assign(S, 0.0f);
     const long long nc = s->nc * S, np = s->np * S;
-    s->q = s->alloc<float>(5 * nc);
-    s->q2 = s->alloc<float>(5 * nc);
+    s->q = s->alloc<float>(s->nq * nc);
+    s->q2 = s->alloc<float>(s->nq * nc);
     s->pos = s->alloc<float>(3 * np);
     s->mom = s->alloc<float>(3 * np);
     s->star = s->alloc<float>(nc);
@@ -1667,9 +1673,9 @@ int dh_get_field(dh_sim* s, dh_field f, float* d_out) {
   return guarded(s, [&]() -> int {
     const long long nc = s->nc, S = s->S;
     switch (f) {
-      case DH_FIELD_Q: copy_d2d(s, d_out, s->q, 5 * nc * S); break;
+      case DH_FIELD_Q: copy_d2d(s, d_out, s->q, s->nq * nc * S); break;
       case DH_FIELD_RHO:
-        for (int i = 0; i < S; ++i) copy_d2d(s, d_out + nc * i, s->q + 5 * nc * i, nc);
+        for (int i = 0; i < S; ++i) copy_d2d(s, d_out + nc * i, s->q + s->nq * nc * i, nc);
         break;
       case DH_FIELD_POS: copy_d2d(s, d_out, s->pos, 3 * s->np * S); break;
       case DH_FIELD_MOM: copy_d2d(s, d_out, s->mom, 3 * s->np * S); break;
@@ -1680,8 +1686,8 @@ int dh_get_field(dh_sim* s, dh_field f, float* d_out) {
         break;
       case DH_FIELD_OBS_TEMP:
         for (int i = 0; i < S; ++i)
-          dh::launch_fli_obs(s->st, s->q + 5 * nc * i, s->a[i], 1.0 / s->f_b, s->e_floor,
-                             s->t_per_e, d_out + nc * i, nc);
+          dh::launch_fli_obs(s->st, s->q + s->nq * nc * i, s->a[i], 1.0 / s->f_b, s->e_floor,
+                             s->t_per_e, d_out + nc * i, nc, s->nq, s->cfg.gamma);
         break;
       case DH_FIELD_PHI:
         if (!s->phi_valid) refresh_potential(s);
@@ -1689,13 +1695,13 @@ int dh_get_field(dh_sim* s, dh_field f, float* d_out) {
         break;
       case DH_FIELD_TEMP:
         for (int i = 0; i < S; ++i)
-          dh::launch_temperature(s->st, s->q + 5 * nc * i, static_cast<float>(s->a[i]),
+          dh::launch_temperature(s->st, s->q + s->nq * nc * i, static_cast<float>(s->a[i]),
                                  static_cast<float>(s->e_floor), static_cast<float>(s->t_per_e),
-                                 d_out + nc * i, nc);
+                                 d_out + nc * i, nc, s->nq, s->cfg.gamma);
         break;
       case DH_FIELD_FLUX:
         for (int i = 0; i < S; ++i)
-          dh::launch_flux_field(s->st, s->q + 5 * nc * i, s->prm.A, s->prm.beta,
+          dh::launch_flux_field(s->st, s->q + s->nq * nc * i, s->prm.A, s->prm.beta,
                                 static_cast<float>(1.0 / s->f_b), d_out + nc * i, nc);
         break;
       default: return fail(s, DH_E_INVAL, "unknown field");
@@ -1709,9 +1715,9 @@ int dh_set_field(dh_sim* s, dh_field f, const float* d_in) {
   return guarded(s, [&]() -> int {
     const long long nc = s->nc, S = s->S;
     switch (f) {
-      case DH_FIELD_Q: copy_d2d(s, s->q, d_in, 5 * nc * S); s->phi_valid = false; break;
+      case DH_FIELD_Q: copy_d2d(s, s->q, d_in, s->nq * nc * S); s->phi_valid = false; break;
       case DH_FIELD_RHO:
-        for (int i = 0; i < S; ++i) copy_d2d(s, s->q + 5 * nc * i, d_in + nc * i, nc);
+        for (int i = 0; i < S; ++i) copy_d2d(s, s->q + s->nq * nc * i, d_in + nc * i, nc);
         s->phi_valid = false;
         break;
       case DH_FIELD_POS: copy_d2d(s, s->pos, d_in, 3 * s->np * S); s->phi_valid = false; break;
@@ -1876,8 +1882,8 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
     s->open_pending = false;
     const int K = s->cfg.ckpt_every;
     if (!s->lq) {
-      s->lq = s->alloc<float>(5 * nc * S);
-      s->lq2 = s->alloc<float>(5 * nc * S);
+      s->lq = s->alloc<float>(s->nq * nc * S);
+      s->lq2 = s->alloc<float>(s->nq * nc * S);
       s->lx = s->alloc<float>(3 * np * S);
       s->lp = s->alloc<float>(3 * np * S);
       s->lphi = s->alloc<float>(nc * S);
@@ -1912,19 +1918,20 @@ int dh_backward(dh_sim* s, const float* d_grad_rho, float* d_grad_white, double*
                             static_cast<size_t>(s->fwd_plans.back().slot + 1) * S * sizeof(StepScal),
                             hipMemcpyHostToDevice, s->st));
     // final state adjoint
-    dh::launch_fill(s->st, s->lq, 0.0f, 5 * nc * S);
+    dh::launch_fill(s->st, s->lq, 0.0f, s->nq * nc * S);
     dh::launch_fill(s->st, s->lx, 0.0f, 3 * np * S);
     dh::launch_fill(s->st, s->lp, 0.0f, 3 * np * S);
     dh::launch_fill(s->st, s->lphi, 0.0f, nc * S);
     std::vector<double> gA(S, 0.0), gB(S, 0.0);
     if (d_grad_rho) {
-      for (int i = 0; i < S; ++i) copy_d2d(s, s->lq + 5 * nc * i, d_grad_rho + nc * i, nc);
+      for (int i = 0; i < S; ++i) copy_d2d(s, s->lq + s->nq * nc * i, d_grad_rho + nc * i, nc);
     } else if (s->loss_kind == dh_sim::kLossPower) {
       power_loss_vjp(s);
     } else if (s->loss_kind == dh_sim::kLossFli) {
       upload_scale_factors(s);
       dh::launch_fli(s->st, s->q, s->fli_data, s->fli_nvar, s->fli_white, s->d_acur,
-                     1.0 / s->f_b, s->e_floor, s->t_per_e, nullptr, s->lq, batch(s, nullptr));
+                     1.0 / s->f_b, s->e_floor, s->t_per_e, s->cfg.gamma, nullptr, s->lq,
+                     batch(s, nullptr));
     } else {
       const int nb = s->red_blocks;
       dh::launch_loss_vjp(s->st, s->q, s->loss_target, s->prm.A, s->prm.beta,
@@ -2081,7 +2088,7 @@ int dh_fli_loss(dh_sim* s, const float* d_data, const float* d_noise_var, const 
     upload_scale_factors(s);
     const int nb = dh::fli_blocks(nc);
     dh::launch_fli(s->st, s->q, s->fli_data, s->fli_nvar, s->fli_white, s->d_acur, 1.0 / s->f_b,
-                   s->e_floor, s->t_per_e, s->fli_part, nullptr, batch(s, nullptr));
+                   s->e_floor, s->t_per_e, s->cfg.gamma, s->fli_part, nullptr, batch(s, nullptr));
     dh::launch_reduce_sum(s->st, s->fli_part, nb, nb, S, s->red_out);
     DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, S * sizeof(double), hipMemcpyDeviceToHost,
                           s->st));
@@ -2122,7 +2129,7 @@ int dh_conservation(dh_sim* s, double* out) {
   return guarded(s, [&]() -> int {
     const int nb = s->red_blocks;
     for (int i = 0; i < s->S; ++i) {
-      dh::launch_conservation_partial(s->st, s->q + 5 * s->nc * i, s->mom + 3 * s->np * i, s->red,
+      dh::launch_conservation_partial(s->st, s->q + s->nq * s->nc * i, s->mom + 3 * s->np * i, s->red,
                                       nb, s->nc);
       dh::launch_reduce_sum(s->st, s->red, nb, nb, 8, s->red_out);
       DH_HIP(hipMemcpyAsync(s->host_out, s->red_out, 8 * sizeof(double), hipMemcpyDeviceToHost,
@@ -2144,7 +2151,7 @@ int dh_stage_sweep(dh_sim* s, const float* d_q_in, float* d_q_out, int32_t axis,
     e.dt = static_cast<float>(dt);
     e.h1 = hydro_at(s, a1);
     e.h2 = hydro_at(s, a2);
-    dh::launch_sweep(s->st, d_q_in, d_q_out, Batch{s->n, 1, stage_table(s, e)}, axis);
+    dh::launch_sweep(s->st, d_q_in, d_q_out, Batch{s->n, 1, stage_table(s, e), s->nq}, axis);
     return DH_OK;
   });
 }
@@ -2158,7 +2165,7 @@ int dh_stage_sweep_vjp(dh_sim* s, const float* d_q_in, const float* d_lam_out, f
     e.dt = static_cast<float>(dt);
     e.h1 = hydro_at(s, a1);
     e.h2 = hydro_at(s, a2);
-    dh::launch_sweep_vjp(s->st, d_q_in, d_lam_out, d_lam_in, Batch{s->n, 1, stage_table(s, e)},
+    dh::launch_sweep_vjp(s->st, d_q_in, d_lam_out, d_lam_in, Batch{s->n, 1, stage_table(s, e), s->nq},
                          axis);
     return DH_OK;
   });
@@ -2170,7 +2177,7 @@ int dh_stage_poisson(dh_sim* s, const float* d_delta, float* d_phi, double a) {
     StepScal e{};
     e.active = 1;
     e.green = green_at(s, a);
-    poisson(s, d_delta, d_phi, Batch{s->n, 1, stage_table(s, e)});
+    poisson(s, d_delta, d_phi, Batch{s->n, 1, stage_table(s, e), s->nq});
     return DH_OK;
   });
 }
@@ -2178,7 +2185,7 @@ int dh_stage_poisson(dh_sim* s, const float* d_delta, float* d_phi, double a) {
 int dh_stage_deposit(dh_sim* s, const float* d_rho_gas, const float* d_pos, float* d_delta) {
   if (!s || !d_rho_gas || !d_pos || !d_delta) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
-    const Batch one{s->n, 1, nullptr};
+    const Batch one{s->n, 1, nullptr, s->nq};
     sort_particles(s, d_pos, one);
     dh::launch_deposit(s->st, s->bins, d_rho_gas, s->nc, static_cast<float>(s->m_dm), -1.0f,
                        d_delta, one);
@@ -2189,7 +2196,7 @@ int dh_stage_deposit(dh_sim* s, const float* d_rho_gas, const float* d_pos, floa
 int dh_stage_readout(dh_sim* s, const float* d_phi, const float* d_pos, float* d_g) {
   if (!s || !d_phi || !d_pos || !d_g) return DH_E_INVAL;
   return guarded(s, [&]() -> int {
-    const Batch one{s->n, 1, nullptr};
+    const Batch one{s->n, 1, nullptr, s->nq};
     dh::launch_grad(s->st, d_phi, s->g4b, one);
     s->g4b_phi0_of = -1;
     dh::launch_readout_g(s->st, s->g4b, d_pos, d_g, one);

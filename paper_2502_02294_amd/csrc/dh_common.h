@@ -37,6 +37,10 @@ inline unsigned blocks_for(long long work, int threads) {
 //   p = (gamma-1) rho e, c_s = sqrt(gamma (gamma-1) e), freezing speed c = (|U_d| + c_s)/a,
 //   F = (rho U_d / a, rho U_d U + p e_d, a U_d (Et/a^2 + p)),
 //   F^R = (c Q + F)/2, F^L = (c Q - F)/2.
+// Dual energy (NQ = 6): a sixth component S = (a^2 rho e) rho^(1-gamma), the entropy
+// variable, with the flux S U_d / a; the EOS takes e = Et/(a^2 rho) - U^2/2 where that
+// exceeds eta1 Et/(a^2 rho), else e_S = S rho^(gamma-2) / a^2 (the selection of Bryan et al.
+// 1995 with the entropy form of Ryu et al. 1993).
 // ---------------------------------------------------------------------------------------
 // Reciprocal and square root on the hardware's approximate units (v_rcp_f32, v_sqrt_f32:
 // within 1 ulp).  The hydro kernels take these in place of the correctly rounded division
@@ -64,10 +68,31 @@ __device__ __forceinline__ void kick_cell(float rho, const float4 g4, float h, f
   et = fmaf(de, h, et);
 }
 
+// Dual energy: below kDualEta1 of E the internal energy comes from the entropy; at the end of
+// a step the entropy is reset from the total energy where e_E >= kDualEta2 E.
+constexpr float kDualEta1 = 1e-3f;
+constexpr float kDualEta2 = 0.1f;
+
+// The dual-energy tests of one cell state Q (FP32, written on Q so that they need no a:
+// a^2 rho e_E = Et - |m|^2 / (2 rho)).  Every kernel outside the sweeps that needs the
+// selection takes it from here, so a cell's screening, its source term and its adjoint agree.
+//   dual_total_branch: the EOS takes e_E (e_E > kDualEta1 E);
+//   dual_sync_branch: the end-of-step reset of S from the total energy (e_E >= kDualEta2 E).
+__device__ __forceinline__ float dual_internal(const float* q) {
+  return q[4] - 0.5f * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+}
+__device__ __forceinline__ bool dual_total_branch(const float* q) {
+  return dual_internal(q) > kDualEta1 * q[4];
+}
+__device__ __forceinline__ bool dual_sync_branch(const float* q) {
+  return dual_internal(q) >= kDualEta2 * q[4];
+}
+
 struct HydroK {
   float a, ia, ia2;   // scale factor, 1/a, 1/a^2
   float gm1, gg1;     // gamma-1, gamma*(gamma-1)
   float efloor;
+  float gm2;          // gamma-2 (the entropy's internal energy, dual energy only)
 };
 
 __host__ __device__ inline HydroK make_hydro(float a, float gamma, float efloor) {
@@ -78,17 +103,31 @@ __host__ __device__ inline HydroK make_hydro(float a, float gamma, float efloor)
   k.gm1 = gamma - 1.0f;
   k.gg1 = gamma * (gamma - 1.0f);
   k.efloor = efloor;
+  k.gm2 = gamma - 2.0f;
   return k;
 }
 
-template <int D>
-__device__ __forceinline__ void split_flux(const float q[5], const HydroK& h, float fr[5],
-                                           float fl[5]) {
+// x^y for x > 0 on the hardware's base-2 exponential and logarithm (v_exp_f32, v_log_f32:
+// about one ulp each, so a relative error of a few ulp times |y log2 x|)
+__device__ __forceinline__ float pow_approx(float x, float y) {
+  return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x));
+}
+
+template <int D, int NQ = 5>
+__device__ __forceinline__ void split_flux(const float* q, const HydroK& h, float* fr,
+                                           float* fl) {
   const float rho = q[0];
   const float ir = rcp_approx(rho);
   const float u0 = q[1] * h.ia * ir, u1 = q[2] * h.ia * ir, u2 = q[3] * h.ia * ir;
   const float ke = 0.5f * (u0 * u0 + u1 * u1 + u2 * u2);
-  float e = q[4] * h.ia2 * ir - ke;
+  float e;
+  if (NQ == 6) {
+    const float big = q[4] * h.ia2 * ir;
+    const float e_tot = big - ke;
+    e = e_tot > kDualEta1 * big ? e_tot : q[5] * h.ia2 * pow_approx(rho, h.gm2);
+  } else {
+    e = q[4] * h.ia2 * ir - ke;
+  }
   e = fmaxf(e, h.efloor);
   const float p = h.gm1 * rho * e;
   const float cs = sqrt_approx(h.gg1 * e);
@@ -105,23 +144,37 @@ __device__ __forceinline__ void split_flux(const float q[5], const HydroK& h, fl
     fr[k] = 0.5f * (c * q[k] + f[k]);
     fl[k] = 0.5f * (c * q[k] - f[k]);
   }
+  if (NQ == 6) {
+    const float f5 = q[5] * ud * h.ia;
+    fr[5] = 0.5f * (c * q[5] + f5);
+    fl[5] = 0.5f * (c * q[5] - f5);
+  }
 }
 
 // Vector-Jacobian product of the split fluxes at q: given the adjoints gR = dL/dF^R and
-// gL = dL/dF^L (5 each), returns dL/dq = (dF^R/dq)^T gR + (dF^L/dq)^T gL
+// gL = dL/dF^L (NQ each), returns dL/dq = (dF^R/dq)^T gR + (dF^L/dq)^T gL
 //   = 1/2 [ c s + (dc/dq)(q . s) + (dF/dq)^T d ],  s = gR + gL, d = gR - gL.
-// Derivatives are those of the floored EOS (zero through e where the floor is active) and
-// of |U_d| with sign(0) = 0.
-template <int D>
-__device__ __forceinline__ void split_flux_vjp(const float q[5], const HydroK& h,
-                                               const float s[5], const float dv[5],
-                                               float out[5]) {
+// Derivatives are those of the floored EOS (zero through e where the floor is active), of
+// the branch of the dual-energy selection that the state takes, and of |U_d| with
+// sign(0) = 0.
+template <int D, int NQ = 5>
+__device__ __forceinline__ void split_flux_vjp(const float* q, const HydroK& h, const float* s,
+                                               const float* dv, float* out) {
   const float rho = q[0];
   const float ir = rcp_approx(rho);
   const float iar = h.ia * ir;
   const float u[3] = {q[1] * iar, q[2] * iar, q[3] * iar};
   const float ke = 0.5f * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-  const float eraw = q[4] * h.ia2 * ir - ke;
+  float eraw, tot = 1.0f, rs = 0.0f;   // tot: the total energy's branch; rs = rho^(gamma-2)
+  if (NQ == 6) {
+    const float big = q[4] * h.ia2 * ir;
+    const float e_tot = big - ke;
+    tot = e_tot > kDualEta1 * big ? 1.0f : 0.0f;
+    rs = pow_approx(rho, h.gm2);
+    eraw = tot > 0.0f ? e_tot : q[5] * h.ia2 * rs;
+  } else {
+    eraw = q[4] * h.ia2 * ir - ke;
+  }
   // 0 where the floor is active (its derivative), 1 elsewhere; every term is computed and
   // masked, so the function has no branches
   const float live = eraw < h.efloor ? 0.0f : 1.0f;
@@ -133,13 +186,16 @@ __device__ __forceinline__ void split_flux_vjp(const float q[5], const HydroK& h
   const float sgn = md > 0.0f ? 1.0f : (md < 0.0f ? -1.0f : 0.0f);
   const float c = (fabsf(ud) + cs) * h.ia;
 
-  // derivatives of e (zero when floored)
-  const float er = live * (ke - e) * ir;
-  const float liar = -live * iar;
+  // derivatives of e (zero when floored); the entropy's branch: e = S rho^(gamma-2) / a^2
+  const float lt = live * tot;
+  float er = lt * (ke - e) * ir;
+  if (NQ == 6) er += live * (1.0f - tot) * h.gm2 * e * ir;
+  const float liar = -lt * iar;
   float em[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) em[k] = liar * u[k];
-  const float eE = live * h.ia2 * ir;
+  const float eE = lt * h.ia2 * ir;
+  const float eS = NQ == 6 ? live * (1.0f - tot) * h.ia2 * rs : 0.0f;
   // pressure derivatives
   const float pr = h.gm1 * (e + rho * er);
   float pm[3];
@@ -154,14 +210,21 @@ __device__ __forceinline__ void split_flux_vjp(const float q[5], const HydroK& h
   for (int k = 0; k < 3; ++k) cm[k] = h.ia * ((k == D ? sgn * iar : 0.0f) + cse * em[k]);
   const float cE = h.ia * cse * eE;
 
-  const float qs = q[0] * s[0] + q[1] * s[1] + q[2] * s[2] + q[3] * s[3] + q[4] * s[4];
+  float qs = q[0] * s[0] + q[1] * s[1] + q[2] * s[2] + q[3] * s[3] + q[4] * s[4];
+  if (NQ == 6) qs += q[5] * s[5];
   // (dF/dq)^T dv
   const float H = (q[4] * h.ia2 + p) * ir;
   const float vu = dv[1] * u[0] + dv[2] * u[1] + dv[3] * u[2];
   const float W = dv[1 + D] + dv[4] * h.a * ud;
   float jt[5];
   jt[0] = -ud * vu + pr * W - dv[4] * h.a * ud * H;
-  const float diag = dv[0] * h.ia2 + h.ia * vu + dv[4] * H;
+  float diag = dv[0] * h.ia2 + h.ia * vu + dv[4] * H;
+  if (NQ == 6) {
+    // F_S = S U_d / a
+    const float fs = dv[5] * q[5] * h.ia;
+    jt[0] -= fs * ud * ir;
+    diag += fs * iar;
+  }
 #pragma unroll
   for (int k = 0; k < 3; ++k) jt[1 + k] = (k == D ? diag : 0.0f) + ud * h.ia * dv[1 + k] + pm[k] * W;
   jt[4] = pE * W + dv[4] * h.a * ud * h.ia2;
@@ -169,6 +232,11 @@ __device__ __forceinline__ void split_flux_vjp(const float q[5], const HydroK& h
   const float dc[5] = {cr, cm[0], cm[1], cm[2], cE};
 #pragma unroll
   for (int k = 0; k < 5; ++k) out[k] = 0.5f * (c * s[k] + dc[k] * qs + jt[k]);
+  if (NQ == 6) {
+    const float pS = h.gm1 * rho * eS;
+    const float cS = h.ia * cse * eS;
+    out[5] = 0.5f * (c * s[5] + cS * qs + pS * W + dv[5] * ud * h.ia);
+  }
 }
 
 // van Leer limiter (Sec. 2.3.2): phi(x, y) = (x y + |x y|) / (x + y + eps sgn(x+y)),

@@ -16,6 +16,7 @@ namespace dh {
 // step).  tab == nullptr: every sample active, no step scalars used.
 struct SourceArgs {   // FP64: the source term is evaluated in double precision
   double a, dt, inv_rho_mean, omega_b, efloor, t_per_e, e0_code;
+  double gamma;       // adiabatic index (the dual-energy entropy's powers of rho)
   double eps_sf, delta_c, t_c, w_rho, w_t, tau;
   // per-step constants: x = eps_sf dt / t_ff = c_x sqrt(delta) with
   // t_ff = (pi/2) sqrt(a^3 / (omega_b delta)); gate arguments (delta - delta_c) k_rho and
@@ -41,7 +42,9 @@ struct Batch {
   int n;                 // cells per side of one sample
   int S;                 // samples
   const StepScal* tab;   // device table [S] or null
+  int nq = 5;            // gas components per cell: 5, or 6 with the dual-energy entropy
   long long nc() const { return static_cast<long long>(n) * n * n; }
+  long long qs() const { return nq * nc(); }   // floats of one sample's gas state
 };
 
 __device__ __forceinline__ bool sample_active(const StepScal* tab, int smp) {
@@ -165,13 +168,13 @@ void launch_pk_bin(hipStream_t st, const float2* spec, int nbins, double* partia
 void launch_pk_scale(hipStream_t st, float2* spec, const float* g, int nbins, const Batch& b);
 // field-level loss 1/2 sum (d - O)^2 / N + 1/2 sum w^2, O = rho irm T(e): per-block partials
 // partial[s fli_blocks(nc) + block] (partial may be null) and, with lam, dL/dQ of the data
-// term into lam[s][5][nc]; a_cur[s] the scale factor of each sample (device)
+// term into lam[s][nq][nc]; a_cur[s] the scale factor of each sample (device)
 int fli_blocks(long long nc);
 void launch_fli(hipStream_t st, const float* q, const float* data, const float* nvar,
                 const float* white, const double* a_cur, double irm, double efloor,
-                double t_per_e, double* partial, float* lam, const Batch& b);
+                double t_per_e, double gamma, double* partial, float* lam, const Batch& b);
 void launch_fli_obs(hipStream_t st, const float* q, double a, double irm, double efloor,
-                    double t_per_e, float* out, long long nc);
+                    double t_per_e, float* out, long long nc, int nq, double gamma);
 
 // ---- pointwise / reductions (k_point.hip)
 // (the opening gas half kick is applied inside the first sweep of a step: launch_sweep)
@@ -234,8 +237,9 @@ void launch_loss_vjp(hipStream_t st, const float* rho, const float* target, doub
                      float inv_rho_mean, float* lam_rho, double* partial, const Batch& b);
 void launch_flux_field(hipStream_t st, const float* rho, double A, double beta,
                        float inv_rho_mean, float* out, long long nc);
+// T of one sample's state q (nq components; 6: the dual-energy selection)
 void launch_temperature(hipStream_t st, const float* q, float a, float efloor, float t_per_e,
-                        float* out, long long nc);
+                        float* out, long long nc, int nq, double gamma);
 void launch_white_noise(hipStream_t st, float* out, uint32_t seed_lo, uint32_t seed_hi, int n);
 // IC: particles from displacement and gas from the deposit
 // x = q + psi, p = vfac vel (vel = psi for first-order displacements)
@@ -248,10 +252,11 @@ void launch_lpt2_source_vjp(hipStream_t st, const float* hess, const float* lam_
                             float* out, const Batch& b);
 void launch_lpt2_combine(hipStream_t st, float* psi, const float* psi2, float* vel, float r,
                          long long count);
+// (b.nq = 6: also the dual-energy entropy of e_init)
 void launch_ic_gas(hipStream_t st, const float* cic, const float* psi, float* q, float f_b,
-                   float vfac, float a, float e_init, const Batch& b);
+                   float vfac, float a, float e_init, double gamma, const Batch& b);
 void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const float* lam_q,
-                       float f_b, float vfac, float a, float e_init, float* lam_cic,
+                       float f_b, float vfac, float a, float e_init, double gamma, float* lam_cic,
                        float* lam_psi, const Batch& b);
 void launch_fill(hipStream_t st, float* p, float v, long long count);
 

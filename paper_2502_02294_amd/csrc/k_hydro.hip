@@ -32,12 +32,13 @@ constexpr int kRowThreads = kRowCells;
 __device__ __forceinline__ int wrap(int j, int n) { return j & (n - 1); }
 
 // out = in over the cells [base, base + count) of all five components (inactive samples)
+template <int NQ>
 __device__ __forceinline__ void copy_block(const float* __restrict__ in, float* __restrict__ out,
                                            long long nc, long long base, int count, int tid,
                                            int threads) {
   for (int i = tid; i < count; i += threads)
 #pragma unroll
-    for (int c = 0; c < 5; ++c) out[c * nc + base + i] = in[c * nc + base + i];
+    for (int c = 0; c < NQ; ++c) out[c * nc + base + i] = in[c * nc + base + i];
 }
 
 // coefficients of the limited right-moving face flux FRf_m = F_m + phi((F_m - F_{m-1})/2,
@@ -65,22 +66,22 @@ __device__ __forceinline__ void face_l_coef(float f0, float fp1, float fp2, floa
 // Whole rows in LDS, one cell per thread; the limited stage-2 flux is formed once per face.
 // KICK (the first sweep of a step): the opening gas half kick with g4 and the table's h is
 // applied to each cell as it is loaded, and the kicked state goes to `kicked` if given.
-template <bool KICK>
+template <bool KICK, int NQ>
 __global__ void __launch_bounds__(kRowThreads) sweep_x_kernel(const float* __restrict__ qin,
                                                               float* __restrict__ qout, int n,
                                                               long long nc,
                                                               const StepScal* __restrict__ tab,
                                                               const float4* __restrict__ g4,
                                                               float* __restrict__ kicked) {
-  __shared__ float FR[5][kRowCells];
-  __shared__ float FL[5][kRowCells];
+  __shared__ float FR[NQ][kRowCells];
+  __shared__ float FL[NQ][kRowCells];
   const long long base = static_cast<long long>(blockIdx.x) * kRowCells;
   const int j = threadIdx.x;
   const StepScal& sc = tab[blockIdx.y];
-  qin += blockIdx.y * 5 * nc;
-  qout += blockIdx.y * 5 * nc;
+  qin += blockIdx.y * NQ * nc;
+  qout += blockIdx.y * NQ * nc;
   if (!sc.active) {
-    copy_block(qin, qout, nc, base, kRowCells, j, kRowThreads);
+    copy_block<NQ>(qin, qout, nc, base, kRowCells, j, kRowThreads);
     return;
   }
   const float dt = sc.dt;
@@ -89,9 +90,9 @@ __global__ void __launch_bounds__(kRowThreads) sweep_x_kernel(const float* __res
   const int row0 = j - (j & (n - 1)), col = j & (n - 1);
   const int jm = row0 + wrap(col - 1, n), jp = row0 + wrap(col + 1, n);
   const int jpp = row0 + wrap(col + 2, n);
-  float u[5], fr[5], fl[5];
+  float u[NQ], fr[NQ], fl[NQ];
 #pragma unroll
-  for (int c = 0; c < 5; ++c) u[c] = qin[c * nc + base + j];
+  for (int c = 0; c < NQ; ++c) u[c] = qin[c * nc + base + j];
   if (KICK) {
     float m[3] = {u[1], u[2], u[3]};
     kick_cell(u[0], g4[blockIdx.y * nc + base + j], sc.h, m, u[4]);
@@ -100,41 +101,41 @@ __global__ void __launch_bounds__(kRowThreads) sweep_x_kernel(const float* __res
     u[3] = m[2];
     if (kicked) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) kicked[(blockIdx.y * 5 + c) * nc + base + j] = u[c];
+      for (int c = 0; c < NQ; ++c) kicked[(blockIdx.y * NQ + c) * nc + base + j] = u[c];
     }
   }
-  split_flux<0>(u, h1, fr, fl);
+  split_flux<0, NQ>(u, h1, fr, fl);
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 0; c < NQ; ++c) {
     FR[c][j] = fr[c];
     FL[c][j] = fl[c];
   }
   __syncthreads();
-  float qh[5];
+  float qh[NQ];
 #pragma unroll
-  for (int c = 0; c < 5; ++c)
+  for (int c = 0; c < NQ; ++c)
     qh[c] = u[c] - hdt * ((fr[c] - FL[c][jp]) - (FR[c][jm] - fl[c]));
-  split_flux<0>(qh, h2, fr, fl);
+  split_flux<0, NQ>(qh, h2, fr, fl);
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 0; c < NQ; ++c) {
     FR[c][j] = fr[c];
     FL[c][j] = fl[c];
   }
   __syncthreads();
-  float f2[5];   // limited stage-2 flux of face j+1/2
+  float f2[NQ];   // limited stage-2 flux of face j+1/2
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 0; c < NQ; ++c) {
     const float rm1 = FR[c][jm], r0 = fr[c], rp1 = FR[c][jp];
     const float l0 = fl[c], lp1 = FL[c][jp], lp2 = FL[c][jpp];
     f2[c] = (r0 + van_leer_half(r0 - rm1, rp1 - r0)) - (lp1 - van_leer_half(lp1 - l0, lp2 - lp1));
   }
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < 5; ++c) FR[c][j] = f2[c];
+  for (int c = 0; c < NQ; ++c) FR[c][j] = f2[c];
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < 5; ++c) qout[c * nc + base + j] = u[c] - dt * (f2[c] - FR[c][jm]);
+  for (int c = 0; c < NQ; ++c) qout[c * nc + base + j] = u[c] - dt * (f2[c] - FR[c][jm]);
 }
 
 // ---------------------------------------------------------------------- forward y / z walk
@@ -144,30 +145,31 @@ __global__ void __launch_bounds__(kRowThreads) sweep_x_kernel(const float* __res
 // k+kAhead, splits U_k, forms the stage-1 face k-1/2, the half step and stage-2 split of cell
 // k-1, the limited stage-2 face (k-3)+1/2 and the update of cell k-3.  Every carried quantity
 // sits in a ring indexed by the visit number, so with the visits unrolled eight at a time all
-// ring slots are compile-time registers and nothing is shifted.  Offsets within one sample are
-// 32-bit (at most 5 * 256^3 floats).
+// ring slots are compile-time registers and nothing is shifted.  Offsets within one component
+// of a sample are 32-bit (at most 256^3 floats).
 constexpr int kAhead = 4;   // cells loaded ahead of the one being split
 
-template <int D>
+template <int D, int NQ>
 struct WalkFwd {
-  float u[8][5];             // U of cell k - j in slot (i - j) & 7 (j = -kAhead .. 3)
-  float r1[2][5];            // stage-1 F^R of cell k - j in slot (i - j) & 1
-  float f1[2][5];            // stage-1 face flux (k - j) - 1/2 in slot (i - j) & 1
-  float r2[4][5], l2[4][5];  // stage-2 split of cell k - 1 - j in slot (i - j) & 3
-  float f2[2][5];            // limited stage-2 face (k - 3 - j) + 1/2 in slot (i - j) & 1
-  float dr[2][5], dl[2][5];  // upper slopes of face (k - 3 - j) + 1/2 in slot (i - j) & 1: the
+  float u[8][NQ];             // U of cell k - j in slot (i - j) & 7 (j = -kAhead .. 3)
+  float r1[2][NQ];            // stage-1 F^R of cell k - j in slot (i - j) & 1
+  float f1[2][NQ];            // stage-1 face flux (k - j) - 1/2 in slot (i - j) & 1
+  float r2[4][NQ], l2[4][NQ];  // stage-2 split of cell k - 1 - j in slot (i - j) & 3
+  float f2[2][NQ];            // limited stage-2 face (k - 3 - j) + 1/2 in slot (i - j) & 1
+  float dr[2][NQ], dl[2][NQ];  // upper slopes of face (k - 3 - j) + 1/2 in slot (i - j) & 1: the
                              // lower slopes of the next face
 };
 
+template <int NQ>
 struct WalkPtr {
-  const float* __restrict__ q[5];
-  float* __restrict__ o[5];
+  const float* __restrict__ q[NQ];
+  float* __restrict__ o[NQ];
   unsigned base, stride;   // in bytes
   int n;
   // opening gas kick on load (first sweep of a step): g of the sample's cells, the half kick,
   // and where the kicked state goes
   const char* g4;
-  float* k[5];
+  float* k[NQ];
   float h;
   // byte offset of cell k of the column (periodic)
   __device__ __forceinline__ unsigned at(int k) const {
@@ -186,11 +188,11 @@ struct WalkPtr {
 // value, by the walk of the neighbouring segment.  (A store limited to the segment's own
 // cells needs a branch, which splits the visit's code and changes how the compiler fuses the
 // sweep's multiply-adds.)
-template <bool KICK, bool KEEP>
-__device__ __forceinline__ void walk_load(const WalkPtr& p, int kk, float (&u)[5]) {
+template <bool KICK, bool KEEP, int NQ>
+__device__ __forceinline__ void walk_load(const WalkPtr<NQ>& p, int kk, float (&u)[NQ]) {
   const unsigned off = p.at(kk);
 #pragma unroll
-  for (int c = 0; c < 5; ++c) u[c] = p.ld(c, off);
+  for (int c = 0; c < NQ; ++c) u[c] = p.ld(c, off);
   if (KICK) {
     // the float4 of cell i is at byte 16 i, i.e. 4 times the byte offset of its float
     const float4 g = *reinterpret_cast<const float4*>(p.g4 + 4ull * off);
@@ -201,35 +203,35 @@ __device__ __forceinline__ void walk_load(const WalkPtr& p, int kk, float (&u)[5
     u[3] = m[2];
     if (KEEP) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c)
+      for (int c = 0; c < NQ; ++c)
         *reinterpret_cast<float*>(reinterpret_cast<char*>(p.k[c]) + off) = u[c];
     }
   }
 }
 
-template <int D, int I, int STAGE, bool KICK, bool KEEP>
-__device__ __forceinline__ void walk_fwd_visit(WalkFwd<D>& w, const WalkPtr& p, int k,
+template <int D, int I, int STAGE, bool KICK, bool KEEP, int NQ>
+__device__ __forceinline__ void walk_fwd_visit(WalkFwd<D, NQ>& w, const WalkPtr<NQ>& p, int k,
                                                const HydroK& h1, const HydroK& h2, float dt,
                                                float hdt) {
   constexpr int s0 = I & 7, s1 = (I + 7) & 7, s3 = (I + 5) & 7, sa = (I + kAhead) & 7;
   constexpr int t0 = I & 3, t1 = (I + 3) & 3, t2 = (I + 2) & 3, t3 = (I + 1) & 3;
   constexpr int p0 = I & 1, p1 = (I + 1) & 1;
-  walk_load<KICK, KEEP>(p, k + kAhead, w.u[sa]);
-  float l1[5];
-  split_flux<D>(w.u[s0], h1, w.r1[p0], l1);
+  walk_load<KICK, KEEP, NQ>(p, k + kAhead, w.u[sa]);
+  float l1[NQ];
+  split_flux<D, NQ>(w.u[s0], h1, w.r1[p0], l1);
   if (STAGE < 1) return;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) w.f1[p0][c] = w.r1[p1][c] - l1[c];   // face k-1/2
+  for (int c = 0; c < NQ; ++c) w.f1[p0][c] = w.r1[p1][c] - l1[c];   // face k-1/2
   if (STAGE < 2) return;
-  float qh[5];   // half step of cell k-1 from faces (k-1) -+ 1/2
+  float qh[NQ];   // half step of cell k-1 from faces (k-1) -+ 1/2
 #pragma unroll
-  for (int c = 0; c < 5; ++c) qh[c] = w.u[s1][c] - hdt * (w.f1[p0][c] - w.f1[p1][c]);
-  split_flux<D>(qh, h2, w.r2[t0], w.l2[t0]);
+  for (int c = 0; c < NQ; ++c) qh[c] = w.u[s1][c] - hdt * (w.f1[p0][c] - w.f1[p1][c]);
+  split_flux<D, NQ>(qh, h2, w.r2[t0], w.l2[t0]);
   if (STAGE < 3) return;
   // face (k-3)+1/2: F^R at cells k-4, k-3, k-2 (slots t3, t2, t1), F^L at k-3, k-2, k-1; the
   // lower slopes are the previous face's upper ones
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 0; c < NQ; ++c) {
     const float r0 = w.r2[t2][c], lp = w.l2[t1][c];
     const float sr = STAGE == 3 ? r0 - w.r2[t3][c] : w.dr[p1][c];
     const float sl = STAGE == 3 ? lp - w.l2[t2][c] : w.dl[p1][c];
@@ -242,10 +244,10 @@ __device__ __forceinline__ void walk_fwd_visit(WalkFwd<D>& w, const WalkPtr& p, 
   if (STAGE < 4) return;
   const unsigned off = p.at(k - 3);
 #pragma unroll
-  for (int c = 0; c < 5; ++c) p.st(c, off, w.u[s3][c] - dt * (w.f2[p0][c] - w.f2[p1][c]));
+  for (int c = 0; c < NQ; ++c) p.st(c, off, w.u[s3][c] - dt * (w.f2[p0][c] - w.f2[p1][c]));
 }
 
-template <int D, bool KICK, bool KEEP>
+template <int D, bool KICK, bool KEEP, int NQ>
 __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict__ qin,
                                                          float* __restrict__ qout, int n,
                                                          long long nc, int seg_len, int nseg,
@@ -257,7 +259,7 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
   const int x = static_cast<int>(t % n);
   const int other = static_cast<int>((t / n) % n);
   const int seg = static_cast<int>(t / (static_cast<long long>(n) * n));
-  WalkPtr p;
+  WalkPtr<NQ> p;
   p.n = n;
   p.base = 4u * (D == 1 ? static_cast<unsigned>(other) * n * n + x
                         : static_cast<unsigned>(other) * n + x);
@@ -265,10 +267,10 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
   const int s = seg * seg_len;
   const StepScal& sc = tab[blockIdx.y];
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    p.q[c] = qin + (blockIdx.y * 5 + c) * nc;
-    p.o[c] = qout + (blockIdx.y * 5 + c) * nc;
-    p.k[c] = KEEP ? kicked + (blockIdx.y * 5 + c) * nc : nullptr;
+  for (int c = 0; c < NQ; ++c) {
+    p.q[c] = qin + (blockIdx.y * NQ + c) * nc;
+    p.o[c] = qout + (blockIdx.y * NQ + c) * nc;
+    p.k[c] = KEEP ? kicked + (blockIdx.y * NQ + c) * nc : nullptr;
   }
   p.g4 = KICK ? reinterpret_cast<const char*>(g4 + blockIdx.y * nc) : nullptr;
   p.h = sc.h;
@@ -276,33 +278,33 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
     for (int i = 0; i < seg_len; ++i) {
       const unsigned off = p.at(s + i);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) p.st(c, off, p.ld(c, off));
+      for (int c = 0; c < NQ; ++c) p.st(c, off, p.ld(c, off));
     }
     return;
   }
   const float dt = sc.dt;
   const HydroK h1 = sc.h1, h2 = sc.h2;
   const float hdt = 0.5f * dt;
-  WalkFwd<D> w;
+  WalkFwd<D, NQ> w;
 #pragma unroll
-  for (int j = 0; j < kAhead; ++j) walk_load<KICK, KEEP>(p, s - 3 + j, w.u[j]);
+  for (int j = 0; j < kAhead; ++j) walk_load<KICK, KEEP, NQ>(p, s - 3 + j, w.u[j]);
   // visits 0..5 fill the pipeline; from visit 6 on every visit writes a cell
-  walk_fwd_visit<D, 0, 0, KICK, KEEP>(w, p, s - 3, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 1, 1, KICK, KEEP>(w, p, s - 2, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 2, 2, KICK, KEEP>(w, p, s - 1, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 3, 2, KICK, KEEP>(w, p, s, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 4, 2, KICK, KEEP>(w, p, s + 1, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 5, 3, KICK, KEEP>(w, p, s + 2, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 0, 0, KICK, KEEP, NQ>(w, p, s - 3, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 1, 1, KICK, KEEP, NQ>(w, p, s - 2, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 2, 2, KICK, KEEP, NQ>(w, p, s - 1, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 3, 2, KICK, KEEP, NQ>(w, p, s, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 4, 2, KICK, KEEP, NQ>(w, p, s + 1, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 5, 3, KICK, KEEP, NQ>(w, p, s + 2, h1, h2, dt, hdt);
   // seg_len is a multiple of 8: visits 6 + 8m .. 13 + 8m have ring phases 6, 7, 0, .., 5
   for (int k = s + 3; k < s + 3 + seg_len; k += 8) {
-    walk_fwd_visit<D, 6, 4, KICK, KEEP>(w, p, k, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 7, 4, KICK, KEEP>(w, p, k + 1, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 0, 4, KICK, KEEP>(w, p, k + 2, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 1, 4, KICK, KEEP>(w, p, k + 3, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 2, 4, KICK, KEEP>(w, p, k + 4, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 3, 4, KICK, KEEP>(w, p, k + 5, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 4, 4, KICK, KEEP>(w, p, k + 6, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 5, 4, KICK, KEEP>(w, p, k + 7, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 6, 4, KICK, KEEP, NQ>(w, p, k, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 7, 4, KICK, KEEP, NQ>(w, p, k + 1, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 0, 4, KICK, KEEP, NQ>(w, p, k + 2, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 1, 4, KICK, KEEP, NQ>(w, p, k + 3, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 2, 4, KICK, KEEP, NQ>(w, p, k + 4, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 3, 4, KICK, KEEP, NQ>(w, p, k + 5, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 4, 4, KICK, KEEP, NQ>(w, p, k + 6, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 5, 4, KICK, KEEP, NQ>(w, p, k + 7, h1, h2, dt, hdt);
   }
 }
 
@@ -316,18 +318,19 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
 //   4. lambda_h = split VJP at Uh of the gathered adjoints.
 //   5. stage-1 transpose: lambda = lambda' + lambda_h + split VJP at U of (G1_j, -G1_{j-1}),
 //      G1_m = -dt/2 (lambda_h_m - lambda_h_{m+1}).
+template <int NQ>
 __global__ void __launch_bounds__(kRowThreads) sweep_x_vjp_kernel(
     const float* __restrict__ qin, const float* __restrict__ lam_out, float* __restrict__ lam_in,
     int n, long long nc, const StepScal* __restrict__ tab) {
-  __shared__ float S[5][5][kRowCells];
+  __shared__ float S[5][NQ][kRowCells];
   const long long base = static_cast<long long>(blockIdx.x) * kRowCells;
   const int j = threadIdx.x;
   const StepScal& sc = tab[blockIdx.y];
-  qin += blockIdx.y * 5 * nc;
-  lam_out += blockIdx.y * 5 * nc;
-  lam_in += blockIdx.y * 5 * nc;
+  qin += blockIdx.y * NQ * nc;
+  lam_out += blockIdx.y * NQ * nc;
+  lam_in += blockIdx.y * NQ * nc;
   if (!sc.active) {
-    copy_block(lam_out, lam_in, nc, base, kRowCells, j, kRowThreads);
+    copy_block<NQ>(lam_out, lam_in, nc, base, kRowCells, j, kRowThreads);
     return;
   }
   const float dt = sc.dt;
@@ -336,41 +339,41 @@ __global__ void __launch_bounds__(kRowThreads) sweep_x_vjp_kernel(
   const int row0 = j - (j & (n - 1)), col = j & (n - 1);
   const int jm = row0 + wrap(col - 1, n), jmm = row0 + wrap(col - 2, n);
   const int jp = row0 + wrap(col + 1, n), jpp = row0 + wrap(col + 2, n);
-  float u[5], lm[5];
+  float u[NQ], lm[NQ];
   {  // 1. S[0] = lambda', S[1] = F^R(U), S[2] = F^L(U)
-    float fr[5], fl[5];
+    float fr[NQ], fl[NQ];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < NQ; ++c) {
       u[c] = qin[c * nc + base + j];
       lm[c] = lam_out[c * nc + base + j];
     }
-    split_flux<0>(u, h1, fr, fl);
+    split_flux<0, NQ>(u, h1, fr, fl);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < NQ; ++c) {
       S[0][c][j] = lm[c];
       S[1][c][j] = fr[c];
       S[2][c][j] = fl[c];
     }
   }
   __syncthreads();
-  float qh[5];
+  float qh[NQ];
   {  // 2. S[3] = F^R(Uh), S[4] = F^L(Uh)
-    float fr[5], fl[5];
+    float fr[NQ], fl[NQ];
 #pragma unroll
-    for (int c = 0; c < 5; ++c)
+    for (int c = 0; c < NQ; ++c)
       qh[c] = u[c] - hdt * ((S[1][c][j] - S[2][c][jp]) - (S[1][c][jm] - S[2][c][j]));
-    split_flux<0>(qh, h2, fr, fl);
+    split_flux<0, NQ>(qh, h2, fr, fl);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < NQ; ++c) {
       S[3][c][j] = fr[c];
       S[4][c][j] = fl[c];
     }
   }
   __syncthreads();
   // 3. face m = j; S[1], S[2] are free since step 2
-  float gr[5], gl[5], xl1[5], xl2[5];
+  float gr[NQ], gl[NQ], xl1[NQ], xl2[NQ];
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 0; c < NQ; ++c) {
     const float g = -dt * (S[0][c][j] - S[0][c][jp]);
     float a0, a1, a2, b0, b1, b2;
     face_r_coef(S[3][c][jm], S[3][c][j], S[3][c][jp], a0, a1, a2);
@@ -384,37 +387,37 @@ __global__ void __launch_bounds__(kRowThreads) sweep_x_vjp_kernel(
   }
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 0; c < NQ; ++c) {
     S[3][c][j] = xl1[c];
     S[4][c][j] = xl2[c];
   }
   __syncthreads();
   {  // 4. lambda_h into S[0]
-    float sv[5], dv[5];
+    float sv[NQ], dv[NQ];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < NQ; ++c) {
       const float gR = gr[c] + S[2][c][jm] + S[1][c][jp];
       const float gL = gl[c] + S[3][c][jm] + S[4][c][jmm];
       sv[c] = gR + gL;
       dv[c] = gR - gL;
     }
-    split_flux_vjp<0>(qh, h2, sv, dv, gr);
+    split_flux_vjp<0, NQ>(qh, h2, sv, dv, gr);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) S[0][c][j] = gr[c];
+    for (int c = 0; c < NQ; ++c) S[0][c][j] = gr[c];
   }
   __syncthreads();
   {  // 5. stage-1 transpose
-    float sv[5], dv[5], out[5];
+    float sv[NQ], dv[NQ], out[NQ];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < NQ; ++c) {
       const float gp = -hdt * (gr[c] - S[0][c][jp]);
       const float gm = -hdt * (S[0][c][jm] - gr[c]);
       sv[c] = gp - gm;
       dv[c] = gp + gm;
     }
-    split_flux_vjp<0>(u, h1, sv, dv, out);
+    split_flux_vjp<0, NQ>(u, h1, sv, dv, out);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) lam_in[c * nc + base + j] = lm[c] + gr[c] + out[c];
+    for (int c = 0; c < NQ; ++c) lam_in[c * nc + base + j] = lm[c] + gr[c] + out[c];
   }
 }
 
@@ -432,16 +435,17 @@ __global__ void __launch_bounds__(kRowThreads) sweep_x_vjp_kernel(
 constexpr int kAheadU = 2;   // U loaded this many cells ahead of the newest one
 constexpr int kAheadL = 1;   // lambda' likewise
 
+template <int NQ>
 struct WalkVjp {
-  float u[8][5];             // U of cell k - j in slot (i - j) & 7
-  float lm[8][5];            // lambda' of cell k - j in slot (i - j) & 7
-  float r1[2][5];            // stage-1 F^R of cell k - j in slot (i - j) & 1
-  float f1[2][5];            // F1 of face (k - j) - 1/2 in slot (i - j) & 1
-  float uh[4][5];            // Uh of cell k - 1 - j in slot (i - j) & 3
-  float r2[4][5], l2[4][5];  // stage-2 split of cell k - 1 - j in slot (i - j) & 3
-  float gr[4][5], gl[4][5];  // adjoints of F^R, F^L of cell k - 1 - j in slot (i - j) & 3
-  float lh[2][5];            // lambda_h of cell k - 3 - j in slot (i - j) & 1
-  float g1[2][5];            // G1 of face (k - 4 - j) + 1/2 in slot (i - j) & 1
+  float u[8][NQ];             // U of cell k - j in slot (i - j) & 7
+  float lm[8][NQ];            // lambda' of cell k - j in slot (i - j) & 7
+  float r1[2][NQ];            // stage-1 F^R of cell k - j in slot (i - j) & 1
+  float f1[2][NQ];            // F1 of face (k - j) - 1/2 in slot (i - j) & 1
+  float uh[4][NQ];            // Uh of cell k - 1 - j in slot (i - j) & 3
+  float r2[4][NQ], l2[4][NQ];  // stage-2 split of cell k - 1 - j in slot (i - j) & 3
+  float gr[4][NQ], gl[4][NQ];  // adjoints of F^R, F^L of cell k - 1 - j in slot (i - j) & 3
+  float lh[2][NQ];            // lambda_h of cell k - 3 - j in slot (i - j) & 1
+  float g1[2][NQ];            // G1 of face (k - 4 - j) + 1/2 in slot (i - j) & 1
 };
 
 // Returns x unchanged through an empty asm statement, so that the compiler cannot reuse
@@ -451,10 +455,11 @@ __device__ __forceinline__ float opaque(float x) {
   return x;
 }
 
+template <int NQ>
 struct WalkVjpPtr {
-  const float* __restrict__ q[5];
-  const float* __restrict__ l[5];
-  float* __restrict__ o[5];
+  const float* __restrict__ q[NQ];
+  const float* __restrict__ l[NQ];
+  float* __restrict__ o[NQ];
   unsigned base, stride;   // in bytes
   int n;
   __device__ __forceinline__ unsigned at(int k) const {
@@ -470,8 +475,8 @@ struct WalkVjpPtr {
 
 // STAGE: 0 split only, 1 + F1, 2 + half step and stage-2 split, 3 + first faces (every
 // adjoint assigned), 4 + faces, 5 + lambda_h, 6 + G1, 7 + output
-template <int D, int I, int STAGE>
-__device__ __forceinline__ void walk_vjp_visit(WalkVjp& w, const WalkVjpPtr& p, int k,
+template <int D, int I, int STAGE, int NQ>
+__device__ __forceinline__ void walk_vjp_visit(WalkVjp<NQ>& w, const WalkVjpPtr<NQ>& p, int k,
                                                const HydroK& h1, const HydroK& h2, float dt,
                                                float hdt) {
   constexpr int u0 = I & 7, u1 = (I + 7) & 7, u4 = (I + 4) & 7;
@@ -484,24 +489,24 @@ __device__ __forceinline__ void walk_vjp_visit(WalkVjp& w, const WalkVjpPtr& p, 
   {
     const unsigned offu = p.at(k + kAheadU), offl = p.at(k + kAheadL);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      w.u[ua][c] = WalkVjpPtr::ld(p.q[c], offu);
-      w.lm[la][c] = WalkVjpPtr::ld(p.l[c], offl);
+    for (int c = 0; c < NQ; ++c) {
+      w.u[ua][c] = WalkVjpPtr<NQ>::ld(p.q[c], offu);
+      w.lm[la][c] = WalkVjpPtr<NQ>::ld(p.l[c], offl);
     }
   }
-  float l1[5];
-  split_flux<D>(w.u[u0], h1, w.r1[p0], l1);
+  float l1[NQ];
+  split_flux<D, NQ>(w.u[u0], h1, w.r1[p0], l1);
   if (STAGE < 1) return;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) w.f1[p0][c] = w.r1[p1][c] - l1[c];
+  for (int c = 0; c < NQ; ++c) w.f1[p0][c] = w.r1[p1][c] - l1[c];
   if (STAGE < 2) return;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) w.uh[t0][c] = w.u[u1][c] - hdt * (w.f1[p0][c] - w.f1[p1][c]);
-  split_flux<D>(w.uh[t0], h2, w.r2[t0], w.l2[t0]);
+  for (int c = 0; c < NQ; ++c) w.uh[t0][c] = w.u[u1][c] - hdt * (w.f1[p0][c] - w.f1[p1][c]);
+  split_flux<D, NQ>(w.uh[t0], h2, w.r2[t0], w.l2[t0]);
   if (STAGE < 3) return;
   // R face k-2 (F^R at k-3, k-2, k-1), L face k-3 (F^L at k-3, k-2, k-1)
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
+  for (int c = 0; c < NQ; ++c) {
     float a0, a1, a2;
     face_r_coef(w.r2[t2][c], w.r2[t1][c], w.r2[t0][c], a0, a1, a2);
     const float gR = -dt * (w.lm[l2s][c] - w.lm[l1s][c]);
@@ -524,35 +529,35 @@ __device__ __forceinline__ void walk_vjp_visit(WalkVjp& w, const WalkVjpPtr& p, 
   }
   if (STAGE < 5) return;
   {  // lambda_h of cell k-3
-    float sv[5], dv[5], q[5];
+    float sv[NQ], dv[NQ], q[NQ];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < NQ; ++c) {
       sv[c] = w.gr[t2][c] + w.gl[t2][c];
       dv[c] = w.gr[t2][c] - w.gl[t2][c];
       q[c] = opaque(w.uh[t2][c]);
     }
-    split_flux_vjp<D>(q, h2, sv, dv, w.lh[p0]);
+    split_flux_vjp<D, NQ>(q, h2, sv, dv, w.lh[p0]);
   }
   if (STAGE < 6) return;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) w.g1[p0][c] = -hdt * (w.lh[p1][c] - w.lh[p0][c]);   // face k-4+1/2
+  for (int c = 0; c < NQ; ++c) w.g1[p0][c] = -hdt * (w.lh[p1][c] - w.lh[p0][c]);   // face k-4+1/2
   if (STAGE < 7) return;
   {  // lambda of cell k-4
-    float sv[5], dv[5], out[5], q[5];
+    float sv[NQ], dv[NQ], out[NQ], q[NQ];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < NQ; ++c) {
       sv[c] = w.g1[p0][c] - w.g1[p1][c];
       dv[c] = w.g1[p0][c] + w.g1[p1][c];
       q[c] = opaque(w.u[u4][c]);
     }
-    split_flux_vjp<D>(q, h1, sv, dv, out);
+    split_flux_vjp<D, NQ>(q, h1, sv, dv, out);
     const unsigned off = p.at(k - 4);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) p.st(c, off, w.lm[u4][c] + w.lh[p1][c] + out[c]);
+    for (int c = 0; c < NQ; ++c) p.st(c, off, w.lm[u4][c] + w.lh[p1][c] + out[c]);
   }
 }
 
-template <int D>
+template <int D, int NQ>
 __global__ void __launch_bounds__(256) sweep_walk_vjp_kernel(const float* __restrict__ qin,
                                                              const float* __restrict__ lam_out,
                                                              float* __restrict__ lam_in, int n,
@@ -563,7 +568,7 @@ __global__ void __launch_bounds__(256) sweep_walk_vjp_kernel(const float* __rest
   const int x = static_cast<int>(t % n);
   const int other = static_cast<int>((t / n) % n);
   const int seg = static_cast<int>(t / (static_cast<long long>(n) * n));
-  WalkVjpPtr p;
+  WalkVjpPtr<NQ> p;
   p.n = n;
   p.base = 4u * (D == 1 ? static_cast<unsigned>(other) * n * n + x
                         : static_cast<unsigned>(other) * n + x);
@@ -571,53 +576,53 @@ __global__ void __launch_bounds__(256) sweep_walk_vjp_kernel(const float* __rest
   const int s = seg * seg_len;
   const StepScal& sc = tab[blockIdx.y];
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    p.q[c] = qin + (blockIdx.y * 5 + c) * nc;
-    p.l[c] = lam_out + (blockIdx.y * 5 + c) * nc;
-    p.o[c] = lam_in + (blockIdx.y * 5 + c) * nc;
+  for (int c = 0; c < NQ; ++c) {
+    p.q[c] = qin + (blockIdx.y * NQ + c) * nc;
+    p.l[c] = lam_out + (blockIdx.y * NQ + c) * nc;
+    p.o[c] = lam_in + (blockIdx.y * NQ + c) * nc;
   }
   if (!sc.active) {
     for (int i = 0; i < seg_len; ++i) {
       const unsigned off = p.at(s + i);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) p.st(c, off, WalkVjpPtr::ld(p.l[c], off));
+      for (int c = 0; c < NQ; ++c) p.st(c, off, WalkVjpPtr<NQ>::ld(p.l[c], off));
     }
     return;
   }
   const float dt = sc.dt;
   const HydroK h1 = sc.h1, h2 = sc.h2;
   const float hdt = 0.5f * dt;
-  WalkVjp w;
+  WalkVjp<NQ> w;
 #pragma unroll
   for (int j = 0; j < kAheadU; ++j) {
     const unsigned off = p.at(s - 4 + j);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) w.u[j][c] = WalkVjpPtr::ld(p.q[c], off);
+    for (int c = 0; c < NQ; ++c) w.u[j][c] = WalkVjpPtr<NQ>::ld(p.q[c], off);
   }
 #pragma unroll
   for (int j = 0; j < kAheadL; ++j) {
     const unsigned off = p.at(s - 4 + j);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) w.lm[j][c] = WalkVjpPtr::ld(p.l[c], off);
+    for (int c = 0; c < NQ; ++c) w.lm[j][c] = WalkVjpPtr<NQ>::ld(p.l[c], off);
   }
-  walk_vjp_visit<D, 0, 0>(w, p, s - 4, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 1, 1>(w, p, s - 3, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 2, 2>(w, p, s - 2, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 3, 2>(w, p, s - 1, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 4, 3>(w, p, s, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 5, 4>(w, p, s + 1, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 6, 5>(w, p, s + 2, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 7, 6>(w, p, s + 3, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 0, 0, NQ>(w, p, s - 4, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 1, 1, NQ>(w, p, s - 3, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 2, 2, NQ>(w, p, s - 2, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 3, 2, NQ>(w, p, s - 1, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 4, 3, NQ>(w, p, s, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 5, 4, NQ>(w, p, s + 1, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 6, 5, NQ>(w, p, s + 2, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 7, 6, NQ>(w, p, s + 3, h1, h2, dt, hdt);
   // seg_len is a multiple of 8: visits 8 + 8m .. 15 + 8m have ring phases 0 .. 7
   for (int k = s + 4; k < s + 4 + seg_len; k += 8) {
-    walk_vjp_visit<D, 0, 7>(w, p, k, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 1, 7>(w, p, k + 1, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 2, 7>(w, p, k + 2, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 3, 7>(w, p, k + 3, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 4, 7>(w, p, k + 4, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 5, 7>(w, p, k + 5, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 6, 7>(w, p, k + 6, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 7, 7>(w, p, k + 7, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 0, 7, NQ>(w, p, k, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 1, 7, NQ>(w, p, k + 1, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 2, 7, NQ>(w, p, k + 2, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 3, 7, NQ>(w, p, k + 3, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 4, 7, NQ>(w, p, k + 4, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 5, 7, NQ>(w, p, k + 5, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 6, 7, NQ>(w, p, k + 6, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 7, 7, NQ>(w, p, k + 7, h1, h2, dt, hdt);
   }
 }
 
@@ -625,30 +630,29 @@ int pick_segment(int n) { return n >= 64 ? 64 : n; }
 
 }  // namespace
 
-void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis,
-                  const float4* g4, float* kicked) {
+namespace {
+
+template <int NQ>
+void sweep_nq(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis,
+              const float4* g4, float* kicked) {
   const int n = b.n;
   const long long nc = b.nc();
-  if (!b.tab) throw ArgError("sweep: step table required");
-  if (kicked && !g4) throw ArgError("sweep: the kicked state needs the kick's field");
-  if (kicked && (kicked == qin || kicked == qout)) throw ArgError("sweep: kicked state aliases");
   if (axis == 0) {
-    if (qin == qout) throw ArgError("sweep_x: in-place not supported");
     const dim3 grid(static_cast<unsigned>(nc / kRowCells), b.S);
     if (g4)
-      hipLaunchKernelGGL(sweep_x_kernel<true>, grid, dim3(kRowThreads), 0, st, qin, qout, n, nc,
-                         b.tab, g4, kicked);
+      hipLaunchKernelGGL((sweep_x_kernel<true, NQ>), grid, dim3(kRowThreads), 0, st, qin, qout, n,
+                         nc, b.tab, g4, kicked);
     else
-      hipLaunchKernelGGL(sweep_x_kernel<false>, grid, dim3(kRowThreads), 0, st, qin, qout, n, nc,
-                         b.tab, nullptr, nullptr);
+      hipLaunchKernelGGL((sweep_x_kernel<false, NQ>), grid, dim3(kRowThreads), 0, st, qin, qout,
+                         n, nc, b.tab, nullptr, nullptr);
   } else {
     const int seg = pick_segment(n);
     const int nseg = n / seg;
     const long long threads = static_cast<long long>(n) * n * nseg;
     const dim3 grid(blocks_for(threads, 256), b.S);
-#define DH_WALK(D, KICK, KEEP)                                                                 \
-  hipLaunchKernelGGL((sweep_walk_kernel<D, KICK, KEEP>), grid, dim3(256), 0, st, qin, qout, n, \
-                     nc, seg, nseg, b.tab, g4, kicked)
+#define DH_WALK(D, KICK, KEEP)                                                               \
+  hipLaunchKernelGGL((sweep_walk_kernel<D, KICK, KEEP, NQ>), grid, dim3(256), 0, st, qin, qout, \
+                     n, nc, seg, nseg, b.tab, g4, kicked)
     if (axis == 1) {
       if (kicked) DH_WALK(1, true, true);
       else if (g4) DH_WALK(1, true, false);
@@ -660,17 +664,15 @@ void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b,
     }
 #undef DH_WALK
   }
-  DH_LAUNCH_CHECK();
 }
 
-void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
-                      const Batch& b, int axis) {
+template <int NQ>
+void sweep_vjp_nq(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
+                  const Batch& b, int axis) {
   const int n = b.n;
   const long long nc = b.nc();
-  if (!b.tab) throw ArgError("sweep adjoint: step table required");
-  if (qin == lam_in || lam_out == lam_in) throw ArgError("sweep adjoint: in-place not supported");
   if (axis == 0) {
-    hipLaunchKernelGGL(sweep_x_vjp_kernel, dim3(static_cast<unsigned>(nc / kRowCells), b.S),
+    hipLaunchKernelGGL((sweep_x_vjp_kernel<NQ>), dim3(static_cast<unsigned>(nc / kRowCells), b.S),
                        dim3(kRowThreads), 0, st, qin, lam_out, lam_in, n, nc, b.tab);
   } else {
     const int seg = pick_segment(n);
@@ -678,12 +680,37 @@ void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, fl
     const long long threads = static_cast<long long>(n) * n * nseg;
     const dim3 grid(blocks_for(threads, 256), b.S);
     if (axis == 1)
-      hipLaunchKernelGGL(sweep_walk_vjp_kernel<1>, grid, dim3(256), 0, st, qin, lam_out, lam_in,
-                         n, nc, seg, nseg, b.tab);
+      hipLaunchKernelGGL((sweep_walk_vjp_kernel<1, NQ>), grid, dim3(256), 0, st, qin, lam_out,
+                         lam_in, n, nc, seg, nseg, b.tab);
     else
-      hipLaunchKernelGGL(sweep_walk_vjp_kernel<2>, grid, dim3(256), 0, st, qin, lam_out, lam_in,
-                         n, nc, seg, nseg, b.tab);
+      hipLaunchKernelGGL((sweep_walk_vjp_kernel<2, NQ>), grid, dim3(256), 0, st, qin, lam_out,
+                         lam_in, n, nc, seg, nseg, b.tab);
   }
+}
+
+}  // namespace
+
+void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis,
+                  const float4* g4, float* kicked) {
+  if (!b.tab) throw ArgError("sweep: step table required");
+  if (kicked && !g4) throw ArgError("sweep: the kicked state needs the kick's field");
+  if (kicked && (kicked == qin || kicked == qout)) throw ArgError("sweep: kicked state aliases");
+  if (axis == 0 && qin == qout) throw ArgError("sweep_x: in-place not supported");
+  if (b.nq == 6)
+    sweep_nq<6>(st, qin, qout, b, axis, g4, kicked);
+  else
+    sweep_nq<5>(st, qin, qout, b, axis, g4, kicked);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
+                      const Batch& b, int axis) {
+  if (!b.tab) throw ArgError("sweep adjoint: step table required");
+  if (qin == lam_in || lam_out == lam_in) throw ArgError("sweep adjoint: in-place not supported");
+  if (b.nq == 6)
+    sweep_vjp_nq<6>(st, qin, lam_out, lam_in, b, axis);
+  else
+    sweep_vjp_nq<5>(st, qin, lam_out, lam_in, b, axis);
   DH_LAUNCH_CHECK();
 }
 

@@ -8,7 +8,8 @@
 // spectrum is reproducible bit for bit.
 //
 // Field-level inference: observable O = (rho / rho_mean_gas) T, loss
-// 1/2 sum (d - O)^2 / N + 1/2 sum w^2 over the cells and white-noise values w.
+// 1/2 sum (d - O)^2 / N + 1/2 sum w^2 over the cells and white-noise values w.  T follows the
+// dual-energy selection of dh_common.h for a state with the entropy (NQ = 6).
 #include <cmath>
 
 #include "dh_kernels.h"
@@ -92,18 +93,40 @@ __global__ void __launch_bounds__(256) pk_scale_kernel(float2* __restrict__ spec
 
 // observable O of one cell (FP64) and its partial derivatives in Q
 struct ObsCell {
-  double o, d[5];
+  double o, d[6];
 };
 
+template <int NQ = 5>
 __device__ __forceinline__ ObsCell obs_cell(const float* q, long long c, long long nc, double a,
-                                            double irm, double efloor, double t_per_e) {
+                                            double irm, double efloor, double t_per_e,
+                                            double gamma = 0.0) {
   const double rho = q[c], ir = 1.0 / rho, ia2 = 1.0 / (a * a);
   const double m0 = q[nc + c], m1 = q[2 * nc + c], m2 = q[3 * nc + c], et = q[4 * nc + c];
   const double msq = m0 * m0 + m1 * m1 + m2 * m2;
   // rho e = Et / a^2 - |m|^2 / (2 a^2 rho)
   const double e = et * ia2 * ir - 0.5 * msq * ia2 * ir * ir;
   ObsCell r;
+  r.d[5] = 0.0;
   const double k = irm * t_per_e;
+  if (NQ == 6) {
+    const float v[5] = {q[c], q[nc + c], q[2 * nc + c], q[3 * nc + c], q[4 * nc + c]};
+    if (!dual_total_branch(v)) {
+      // rho e = S rho^(gamma-1) / a^2
+      const double sv = q[5 * nc + c], rg = pow(rho, gamma - 1.0);
+      const double es = sv * ia2 * rg * ir;
+      if (es >= efloor) {
+        r.o = k * sv * ia2 * rg;
+        r.d[0] = k * (gamma - 1.0) * sv * ia2 * rg * ir;
+        r.d[1] = r.d[2] = r.d[3] = r.d[4] = 0.0;
+        r.d[5] = k * ia2 * rg;
+      } else {
+        r.o = k * rho * efloor;
+        r.d[0] = k * efloor;
+        r.d[1] = r.d[2] = r.d[3] = r.d[4] = 0.0;
+      }
+      return r;
+    }
+  }
   if (e >= efloor) {
     r.o = k * (et * ia2 - 0.5 * msq * ia2 * ir);
     r.d[0] = k * 0.5 * msq * ia2 * ir * ir;
@@ -132,23 +155,25 @@ __device__ void obs_block_store(double v, double* out) {
 
 // partial[s nblk + block]: sum of 1/2 (d - O)^2 / N + 1/2 w^2 over the block's cells; with
 // lam (the adjoint pass) lam[s][5][nc] = dL/dQ of the data term
+template <int NQ>
 __global__ void __launch_bounds__(kObsThreads) fli_kernel(
     const float* __restrict__ q, const float* __restrict__ data, const float* __restrict__ nvar,
     const float* __restrict__ white, const double* __restrict__ a_cur, double irm, double efloor,
-    double t_per_e, long long nc, double* __restrict__ partial, float* __restrict__ lam) {
+    double t_per_e, double gamma, long long nc, double* __restrict__ partial,
+    float* __restrict__ lam) {
   const int smp = blockIdx.y;
-  q += smp * 5 * nc;
+  q += smp * NQ * nc;
   data += smp * nc;
   nvar += smp * nc;
   white += smp * nc;
-  if (lam) lam += smp * 5 * nc;
+  if (lam) lam += smp * NQ * nc;
   const double a = a_cur[smp];
   double acc = 0.0;
   const long long base = static_cast<long long>(blockIdx.x) * kObsThreads * kObsPer;
   for (int r = 0; r < kObsPer; ++r) {
     const long long c = base + r * kObsThreads + threadIdx.x;
     if (c >= nc) break;
-    const ObsCell oc = obs_cell(q, c, nc, a, irm, efloor, t_per_e);
+    const ObsCell oc = obs_cell<NQ>(q, c, nc, a, irm, efloor, t_per_e, gamma);
     const double resid = static_cast<double>(data[c]) - oc.o;
     const double inv = 1.0 / static_cast<double>(nvar[c]);
     const double w = white[c];
@@ -156,18 +181,20 @@ __global__ void __launch_bounds__(kObsThreads) fli_kernel(
     if (lam) {
       const double g = -resid * inv;   // dL/dO
 #pragma unroll
-      for (int k = 0; k < 5; ++k) lam[k * nc + c] = static_cast<float>(g * oc.d[k]);
+      for (int k = 0; k < NQ; ++k) lam[k * nc + c] = static_cast<float>(g * oc.d[k]);
     }
   }
   if (partial) obs_block_store(acc, partial + static_cast<long long>(smp) * gridDim.x);
 }
 
+template <int NQ>
 __global__ void __launch_bounds__(256) fli_obs_kernel(const float* __restrict__ q, double a,
                                                       double irm, double efloor, double t_per_e,
-                                                      long long nc, float* __restrict__ out) {
+                                                      double gamma, long long nc,
+                                                      float* __restrict__ out) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nc) return;
-  out[c] = static_cast<float>(obs_cell(q, c, nc, a, irm, efloor, t_per_e).o);
+  out[c] = static_cast<float>(obs_cell<NQ>(q, c, nc, a, irm, efloor, t_per_e, gamma).o);
 }
 
 }  // namespace
@@ -199,16 +226,25 @@ int fli_blocks(long long nc) {
 
 void launch_fli(hipStream_t st, const float* q, const float* data, const float* nvar,
                 const float* white, const double* a_cur, double irm, double efloor,
-                double t_per_e, double* partial, float* lam, const Batch& b) {
-  hipLaunchKernelGGL(fli_kernel, dim3(fli_blocks(b.nc()), b.S), dim3(kObsThreads), 0, st, q, data,
-                     nvar, white, a_cur, irm, efloor, t_per_e, b.nc(), partial, lam);
+                double t_per_e, double gamma, double* partial, float* lam, const Batch& b) {
+  const dim3 grid(fli_blocks(b.nc()), b.S);
+  if (b.nq == 6)
+    hipLaunchKernelGGL(fli_kernel<6>, grid, dim3(kObsThreads), 0, st, q, data, nvar, white, a_cur,
+                       irm, efloor, t_per_e, gamma, b.nc(), partial, lam);
+  else
+    hipLaunchKernelGGL(fli_kernel<5>, grid, dim3(kObsThreads), 0, st, q, data, nvar, white, a_cur,
+                       irm, efloor, t_per_e, gamma, b.nc(), partial, lam);
   DH_LAUNCH_CHECK();
 }
 
 void launch_fli_obs(hipStream_t st, const float* q, double a, double irm, double efloor,
-                    double t_per_e, float* out, long long nc) {
-  hipLaunchKernelGGL(fli_obs_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, a, irm,
-                     efloor, t_per_e, nc, out);
+                    double t_per_e, float* out, long long nc, int nq, double gamma) {
+  if (nq == 6)
+    hipLaunchKernelGGL(fli_obs_kernel<6>, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, a, irm,
+                       efloor, t_per_e, gamma, nc, out);
+  else
+    hipLaunchKernelGGL(fli_obs_kernel<5>, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, a, irm,
+                       efloor, t_per_e, gamma, nc, out);
   DH_LAUNCH_CHECK();
 }
 

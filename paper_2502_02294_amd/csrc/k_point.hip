@@ -81,13 +81,14 @@ __global__ void __launch_bounds__(256) gas_kick_vjp_kernel(const float* __restri
                                                            const float4* __restrict__ g4,
                                                            float* __restrict__ lam,
                                                            float* __restrict__ lam_g,
-                                                           long long nc,
+                                                           long long nc, int nq,
                                                            const StepScal* __restrict__ tab) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const StepScal& sc = tab[blockIdx.y];
   if (c >= nc || !sc.active) return;
-  q += blockIdx.y * 5 * nc;
-  lam += blockIdx.y * 5 * nc;
+  // the entropy of a dual-energy state passes the kick unchanged, and so does its adjoint
+  q += blockIdx.y * nq * nc;
+  lam += blockIdx.y * nq * nc;
   lam_g += blockIdx.y * 3 * nc;
   g4 += blockIdx.y * nc;
   const float m[3] = {q[nc + c], q[2 * nc + c], q[3 * nc + c]};
@@ -107,7 +108,9 @@ __global__ void __launch_bounds__(256) gas_kick_vjp_kernel(const float* __restri
 // sigma(x / tau) amplifies rounding of its argument by 1/tau).
 struct SrcCell {
   double rho, ir, delta, e, eraw, temp, x, psf, s1, s2, pi0, z, u;   // ir = 1 / rho
+  double rs;      // rho^(gamma-2) where e is the dual-energy entropy's (else unset)
   bool floored;
+  bool tot;       // e from the total energy (always, with five components)
 };
 
 __device__ __forceinline__ double sigmoid_(double y) { return 1.0 / (1.0 + exp(-y)); }
@@ -151,14 +154,17 @@ __device__ __forceinline__ float logit_u_of(double u) {
 }
 
 // FP32 estimate of log pi0 - log(1 - pi0) of the plain source term (relaxed mode only)
-__device__ __forceinline__ float draw_logit_estimate(const float q5[5], const SourceArgs& a) {
+template <int NQ = 5>
+__device__ __forceinline__ float draw_logit_estimate(const float* q5, const SourceArgs& a) {
   if (a.mode != 2) return INFINITY;
   const float rho = q5[0];
   const float ir = rcp_approx(rho), ia = static_cast<float>(1.0 / a.a);
   const float iar = ia * ir;
   const float u0 = q5[1] * iar, u1 = q5[2] * iar, u2 = q5[3] * iar;
-  const float e = fmaxf(q5[4] * ia * iar - 0.5f * (u0 * u0 + u1 * u1 + u2 * u2),
-                        static_cast<float>(a.efloor));
+  float e_raw = q5[4] * ia * iar - 0.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+  if (NQ == 6 && !dual_total_branch(q5))
+    e_raw = q5[5] * ia * ia * pow_approx(rho, static_cast<float>(a.gamma - 2.0));
+  const float e = fmaxf(e_raw, static_cast<float>(a.efloor));
   const float temp = e * static_cast<float>(a.t_per_e);
   const float delta = rho * static_cast<float>(a.inv_rho_mean);
   // x = eps dt / t_ff = c_x sqrt(delta)
@@ -177,7 +183,8 @@ __device__ __forceinline__ void sigmoid_pair(double y, double& sig, double& log_
   log_sig = fmin(y, 0.0) - log1p(t);
 }
 
-__device__ SrcCell source_eval(const float q5[5], double u, const SourceArgs& a) {
+template <int NQ = 5>
+__device__ SrcCell source_eval(const float* q5, double u, const SourceArgs& a) {
   SrcCell s;
   s.rho = q5[0];
   s.ir = 1.0 / s.rho;
@@ -185,6 +192,11 @@ __device__ SrcCell source_eval(const float q5[5], double u, const SourceArgs& a)
   const double ia = 1.0 / a.a;
   const double u0 = q5[1] * ia * ir, u1 = q5[2] * ia * ir, u2 = q5[3] * ia * ir;
   s.eraw = q5[4] * ia * ia * ir - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+  s.tot = NQ != 6 || dual_total_branch(q5);
+  if (!s.tot) {
+    s.rs = pow(s.rho, a.gamma - 2.0);
+    s.eraw = q5[5] * ia * ia * s.rs;
+  }
   s.floored = s.eraw < a.efloor;
   s.e = s.floored ? a.efloor : s.eraw;
   s.temp = s.e * a.t_per_e;
@@ -220,26 +232,41 @@ __device__ SrcCell source_eval(const float q5[5], double u, const SourceArgs& a)
   return s;
 }
 
+template <int NQ = 5>
 __device__ __forceinline__ void load_q(const float* __restrict__ q, long long c, long long nc,
-                                       float q5[5]) {
+                                       float* q5) {
 #pragma unroll
-  for (int k = 0; k < 5; ++k) q5[k] = q[k * nc + c];
+  for (int k = 0; k < NQ; ++k) q5[k] = q[k * nc + c];
 }
 
-// FP64 CFL speed of one cell: max_d (|U_d| + c_s) / a; +inf flags a broken state
-__device__ __forceinline__ double cell_speed(const float q5[5], double a, double gg1,
-                                             double efloor) {
+// FP64 CFL speed of one cell: max_d (|U_d| + c_s) / a; +inf flags a broken state.  With the
+// dual-energy entropy (NQ = 6, gm2 = gamma - 2) c_s takes the selected internal energy.
+template <int NQ = 5>
+__device__ __forceinline__ double cell_speed(const float* q5, double a, double gg1,
+                                             double efloor, float gm2 = 0.0f) {
   const double rho = q5[0];
   const double ia = 1.0 / a;
   const double iar = ia / rho;
   const double u0 = q5[1] * iar, u1 = q5[2] * iar, u2 = q5[3] * iar;
   const double e_raw = q5[4] * ia * iar - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
-  const double cs = sqrt(gg1 * fmax(e_raw, efloor));
+  double e_sel = e_raw;
+  if (NQ == 6 && !dual_total_branch(q5))
+    e_sel = q5[5] * ia * ia * static_cast<double>(pow_approx(q5[0], gm2));
+  const double cs = sqrt(gg1 * fmax(e_sel, efloor));
   double sp = (fmax(fabs(u0), fmax(fabs(u1), fabs(u2))) + cs) * ia;
-  // every component enters e_raw, so a NaN or infinity anywhere in the cell shows there
-  // (fmax and the floor would drop a NaN)
-  if (!(rho > 0.0) || !isfinite(e_raw) || !isfinite(sp)) sp = INFINITY;
+  // every component of the total energy enters e_raw, so a NaN or infinity anywhere in the
+  // cell shows there (fmax and the floor would drop a NaN); the entropy in e_sel
+  if (!(rho > 0.0) || !isfinite(e_raw) || !isfinite(sp) || (NQ == 6 && !isfinite(e_sel)))
+    sp = INFINITY;
   return sp;
+}
+
+// Dual energy at the end of the closing pass (NQ = 6): the entropy gains the internal energy
+// injected into the cell (e_sn, 0 if none), then is reset from the total energy where
+// dual_sync_branch holds.  r1g = rho^(1-gamma).
+__device__ __forceinline__ void dual_close(float* q, double e_sn, float r1g) {
+  if (e_sn != 0.0) q[5] = static_cast<float>(q[5] + e_sn * static_cast<double>(r1g));
+  if (dual_sync_branch(q)) q[5] = dual_internal(q) * r1g;
 }
 
 // Closing pass of a step over kRedPer cells per thread: gas half kick, optional tape copy,
@@ -249,7 +276,9 @@ __device__ __forceinline__ double cell_speed(const float q5[5], double a, double
 // particles.  sn_out (optional): the supernova energy a^2 rho z E0 of every cell is written
 // there (0 where none) instead of being added to the cell, for the smoothed injection; the
 // CFL maxima are then left to the injection pass (partial may be null).
-template <bool FULL>
+// NQ = 6 (dual energy): the entropy also takes the injected energy, then the end-of-step
+// reset (dual_close); there is no smoothed injection.
+template <bool FULL, int NQ>
 __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
     const float* q_in, float* q, const float4* __restrict__ g4, float* __restrict__ star,
     float* __restrict__ q_kicked, double gg1, double* partial, long long nc,
@@ -262,20 +291,21 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
   }
   const float h = sc.h;
   const SourceArgs& a = sc.src;
-  q_in += blockIdx.y * 5 * nc;
-  q += blockIdx.y * 5 * nc;
-  if (q_kicked) q_kicked += blockIdx.y * 5 * nc;
+  q_in += blockIdx.y * NQ * nc;
+  q += blockIdx.y * NQ * nc;
+  if (q_kicked) q_kicked += blockIdx.y * NQ * nc;
   g4 += blockIdx.y * nc;
   if (FULL) star += blockIdx.y * nc;
   if (znew) znew += blockIdx.y * nc;
   if (sn_out) sn_out += blockIdx.y * nc;
+  const float gm2 = static_cast<float>(a.gamma - 2.0), g1m = static_cast<float>(1.0 - a.gamma);
   double vmax[1] = {0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   for (int r = 0; r < kRedPer; ++r) {
     const long long c = base + r * kRedThreads + threadIdx.x;
     if (c >= nc) break;
-    float q5[5];
-    load_q(q_in, c, nc, q5);
+    float q5[NQ];
+    load_q<NQ>(q_in, c, nc, q5);
     float m[3] = {q5[1], q5[2], q5[3]};
     kick_cell(q5[0], g4[c], h, m, q5[4]);
     q5[1] = m[0];
@@ -283,30 +313,34 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
     q5[3] = m[2];
     if (q_kicked) {
 #pragma unroll
-      for (int k = 0; k < 5; ++k) q_kicked[k * nc + c] = q5[k];
+      for (int k = 0; k < NQ; ++k) q_kicked[k * nc + c] = q5[k];
     }
-    const float lg = a.mode != 0 ? draw_logit_estimate(q5, a) : 0.0f;
+    const float lg = a.mode != 0 ? draw_logit_estimate<NQ>(q5, a) : 0.0f;
     float zc = 0.0f, inj = 0.0f;
+    double e_add = 0.0;   // energy injected into this cell
     if (a.mode != 0 && !screened_out(lg, kMaxLogitU, a)) {
       const double u = starform_uniform(c, a);
       if (!screened_out(lg, logit_u_of(u), a)) {
-        const SrcCell s = source_eval(q5, u, a);
+        const SrcCell s = source_eval<NQ>(q5, u, a);
         if (s.z != 0.0) {
           const double e_sn = a.a * a.a * s.rho * s.z * a.e0_code;
-          if (sn_out)
+          if (sn_out) {
             inj = static_cast<float>(e_sn);
-          else
+          } else {
             q5[4] = static_cast<float>(q5[4] + e_sn);
+            e_add = e_sn;
+          }
           if (FULL) star[c] = static_cast<float>(star[c] + s.z);
           zc = static_cast<float>(s.z);
         }
       }
     }
+    if (NQ == 6) dual_close(q5, e_add, pow_approx(q5[0], g1m));
     if (znew) znew[c] = zc;
     if (sn_out) sn_out[c] = inj;
 #pragma unroll
-    for (int k = (q == q_in ? 1 : 0); k < 5; ++k) q[k * nc + c] = q5[k];
-    if (do_max) vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
+    for (int k = (q == q_in ? 1 : 0); k < NQ; ++k) q[k * nc + c] = q5[k];
+    if (do_max) vmax[0] = fmax(vmax[0], cell_speed<NQ>(q5, a.a, gg1, a.efloor, gm2));
   }
   if (do_max) block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
 }
@@ -387,15 +421,17 @@ __global__ void __launch_bounds__(256) smooth27_kernel(const float* __restrict__
 // source to the adjoint before; acc += dL/d(eps_sf, delta_c).  z and its derivatives are
 // below 1e-47 where the draw is screened out.
 // li: the adjoint of the cell's injected energy, l5[4] itself for the injection into the
-// cell, that of the smoothed injection otherwise.
-__device__ __forceinline__ void source_cell_vjp(const float q5[5], long long c,
-                                                const SourceArgs& a, float l5[5], double li,
+// cell, that of the smoothed injection otherwise (with the dual-energy entropy: also its
+// share through the entropy).  NQ = 6: T follows the selected internal energy.
+template <int NQ = 5>
+__device__ __forceinline__ void source_cell_vjp(const float* q5, long long c,
+                                                const SourceArgs& a, float* l5, double li,
                                                 double acc[2]) {
-  const float lg = draw_logit_estimate(q5, a);
+  const float lg = draw_logit_estimate<NQ>(q5, a);
   if (screened_out(lg, kMaxLogitU, a)) return;
   const double u = starform_uniform(c, a);
   if (screened_out(lg, logit_u_of(u), a)) return;
-  const SrcCell s = source_eval(q5, u, a);
+  const SrcCell s = source_eval<NQ>(q5, u, a);
   const double le = l5[4];
   const double K = a.a * a.a * a.e0_code;
   // Et' = Et + K rho z (into this cell, or spread by the smoothing)
@@ -411,6 +447,15 @@ __device__ __forceinline__ void source_cell_vjp(const float q5[5], long long c,
     // s2 through T(e)
     const double dlnpi_dT = -(1.0 - s.s2) * a.k_t;
     const double dT = s.floored ? 0.0 : a.t_per_e;
+    if (NQ == 6 && !s.tot) {
+      // e = S rho^(gamma-2) / a^2
+      lr += coef * (dlnpi_drho_sf + dlnpi_drho_s1 + dlnpi_dT * dT * (a.gamma - 2.0) * s.eraw * ir);
+      l5[5] = static_cast<float>(l5[5] + coef * dlnpi_dT * dT * (ia * ia * s.rs));
+      l5[0] = static_cast<float>(lr);
+      acc[0] += coef * (dlp_dx * s.x / a.eps_sf);
+      acc[1] += coef * ((1.0 - s.s1) * (-s.delta / (a.w_rho * a.delta_c * a.delta_c)));
+      return;
+    }
     double u[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) u[d] = q5[1 + d] * ia * ir;
@@ -427,6 +472,55 @@ __device__ __forceinline__ void source_cell_vjp(const float q5[5], long long c,
   l5[0] = static_cast<float>(lr);
 }
 
+// Adjoint of the source term and the end-of-step entropy update of a dual-energy cell
+// (dual_close) at the kicked state q: l from the adjoint after the closing pass to the adjoint
+// before the source term.  The draw and the injected energy are recomputed as the closing
+// pass made them.
+__device__ __forceinline__ void dual_close_vjp(const float* q, long long c, const SourceArgs& a,
+                                               float* l, double acc[2]) {
+  double e_sn = 0.0;
+  if (a.mode != 0) {
+    const float lg = draw_logit_estimate<6>(q, a);
+    if (!screened_out(lg, kMaxLogitU, a)) {
+      const double u = starform_uniform(c, a);
+      if (!screened_out(lg, logit_u_of(u), a)) {
+        const SrcCell s = source_eval<6>(q, u, a);
+        if (s.z != 0.0) e_sn = a.a * a.a * s.rho * s.z * a.e0_code;
+      }
+    }
+  }
+  const float r1g = pow_approx(q[0], static_cast<float>(1.0 - a.gamma));
+  float qp[6] = {q[0], q[1], q[2], q[3], q[4], q[5]};
+  if (e_sn != 0.0) {
+    qp[4] = static_cast<float>(q[4] + e_sn);
+    qp[5] = static_cast<float>(q[5] + e_sn * static_cast<double>(r1g));
+  }
+  double ls = l[5];
+  double lr = l[0], le = l[4];
+  double lm[3] = {l[1], l[2], l[3]};
+  if (dual_sync_branch(qp)) {
+    // S' = I r1g, I = Et - |m|^2 / (2 rho), r1g = rho^(1-gamma)
+    const double ir = 1.0 / static_cast<double>(qp[0]);
+    const double msq = static_cast<double>(qp[1]) * qp[1] + static_cast<double>(qp[2]) * qp[2] +
+                       static_cast<double>(qp[3]) * qp[3];
+    const double i_tot = qp[4] - 0.5 * msq * ir;
+    lr += ls * r1g * (0.5 * msq * ir * ir + (1.0 - a.gamma) * i_tot * ir);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lm[d] -= ls * r1g * qp[1 + d] * ir;
+    le += ls * r1g;
+    ls = 0.0;
+  }
+  l[1] = static_cast<float>(lm[0]);
+  l[2] = static_cast<float>(lm[1]);
+  l[3] = static_cast<float>(lm[2]);
+  l[5] = static_cast<float>(ls);
+  l[4] = static_cast<float>(le);
+  // the injection: Et' = Et + e_sn, S' = S + e_sn r1g, e_sn = a^2 rho z E0
+  if (e_sn != 0.0) lr += ls * e_sn * (1.0 - a.gamma) * r1g / static_cast<double>(q[0]);
+  l[0] = static_cast<float>(lr);
+  if (a.mode != 0) source_cell_vjp<6>(q, c, a, l, le + ls * r1g, acc);
+}
+
 // Adjoint of the closing pass of a step (plain source term): lam (in: adjoint after the
 // source, out: before the closing gas kick), with the state q_kick before the kick;
 // lam_g = adjoint of the kick's g; partials of dL/d(eps_sf|delta_c).  The kicked state, the
@@ -437,7 +531,7 @@ __device__ __forceinline__ void source_cell_vjp(const float q5[5], long long c,
 // every sample moves in both steps.
 // lam_inj (optional): the adjoint of the injected energy of each cell when the injection is
 // smoothed (the smoothing of the energy adjoint).
-template <bool OPEN>
+template <bool OPEN, int NQ>
 __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
     const float* __restrict__ q_kick, const float4* __restrict__ g4, float* __restrict__ lam,
     float* __restrict__ lam_g, double* partial, long long nc, const StepScal* __restrict__ tab,
@@ -450,14 +544,14 @@ __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
   }
   const SourceArgs& a = sc.src;
   const float h = sc.h;
-  q_kick += blockIdx.y * 5 * nc;
+  q_kick += blockIdx.y * NQ * nc;
   g4 += blockIdx.y * nc;
-  lam += blockIdx.y * 5 * nc;
+  lam += blockIdx.y * NQ * nc;
   lam_g += blockIdx.y * 3 * nc;
   if (lam_inj) lam_inj += blockIdx.y * nc;
   float h_open = 0.0f;
   if (OPEN) {
-    q_open += blockIdx.y * 5 * nc;
+    q_open += blockIdx.y * NQ * nc;
     lam_g_open += blockIdx.y * 3 * nc;
     h_open = tab_open[blockIdx.y].h;
   }
@@ -466,9 +560,9 @@ __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
   for (int r = 0; r < kRedPer; ++r) {
     const long long c = base + r * kRedThreads + threadIdx.x;
     if (c >= nc) break;
-    float q5[5], l5[5];
-    load_q(q_kick, c, nc, q5);
-    load_q(lam, c, nc, l5);
+    float q5[NQ], l5[NQ];
+    load_q<NQ>(q_kick, c, nc, q5);
+    load_q<NQ>(lam, c, nc, l5);
     const float4 gv = g4[c];
     if (OPEN) {
       const float mo[3] = {q_open[nc + c], q_open[2 * nc + c], q_open[3 * nc + c]};
@@ -483,11 +577,14 @@ __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
     q5[1] = m[0];
     q5[2] = m[1];
     q5[3] = m[2];
-    if (a.mode != 0) source_cell_vjp(q5, c, a, l5, lam_inj ? lam_inj[c] : l5[4], acc);
+    if (NQ == 6)
+      dual_close_vjp(q5, c, a, l5, acc);
+    else if (a.mode != 0)
+      source_cell_vjp(q5, c, a, l5, lam_inj ? lam_inj[c] : l5[4], acc);
     float lg[3];
     kick_cell_vjp(q5[0], m0, gv, h, l5, lg);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) lam[k * nc + c] = l5[k];
+    for (int k = 0; k < NQ; ++k) lam[k * nc + c] = l5[k];
 #pragma unroll
     for (int d = 0; d < 3; ++d) lam_g[d * nc + c] = lg[d];
   }
@@ -788,20 +885,22 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
 }
 
 // ------------------------------------------------------------------------- CFL
+template <int NQ>
 __global__ void __launch_bounds__(kRedThreads) cfl_partial_kernel(const float* __restrict__ q,
                                                                   const double* __restrict__ a_cur,
                                                                   double gg1, double efloor,
-                                                                  double* partial, long long nc) {
+                                                                  float gm2, double* partial,
+                                                                  long long nc) {
   const double a = a_cur[blockIdx.y];
-  q += blockIdx.y * 5 * nc;
+  q += blockIdx.y * NQ * nc;
   double v[1] = {0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   for (int r = 0; r < kRedPer; ++r) {
     const long long c = base + r * kRedThreads + threadIdx.x;
     if (c >= nc) break;
-    float q5[5];
-    load_q(q, c, nc, q5);
-    v[0] = fmax(v[0], cell_speed(q5, a, gg1, efloor));
+    float q5[NQ];
+    load_q<NQ>(q, c, nc, q5);
+    v[0] = fmax(v[0], cell_speed<NQ>(q5, a, gg1, efloor, gm2));
   }
   block_reduce_store<1, true>(v, sample_partials(partial), partial_stride());
 }
@@ -848,8 +947,9 @@ __global__ void __launch_bounds__(kRedThreads) conservation_kernel(const float* 
 __global__ void __launch_bounds__(kRedThreads) loss_kernel(const float* __restrict__ rho,
                                                            const float* __restrict__ target,
                                                            double A, double beta, double irm,
-                                                           double* partial, long long nc) {
-  rho += blockIdx.y * 5 * nc;   // density row of the sample's Q
+                                                           double* partial, long long nc,
+                                                           long long qs) {
+  rho += blockIdx.y * qs;   // density row of the sample's Q
   target += blockIdx.y * nc;
   double v[1] = {0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
@@ -868,10 +968,11 @@ __global__ void __launch_bounds__(kRedThreads) loss_vjp_kernel(const float* __re
                                                                const float* __restrict__ target,
                                                                double A, double beta, double irm,
                                                                float* __restrict__ lam_rho,
-                                                               double* partial, long long nc) {
-  rho += blockIdx.y * 5 * nc;
+                                                               double* partial, long long nc,
+                                                               long long qs) {
+  rho += blockIdx.y * qs;
   target += blockIdx.y * nc;
-  lam_rho += blockIdx.y * 5 * nc;
+  lam_rho += blockIdx.y * qs;
   double v[2] = {0.0, 0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
   const double w = 2.0 / static_cast<double>(nc);
@@ -896,13 +997,19 @@ __global__ void flux_kernel(const float* __restrict__ rho, double A, double beta
   out[c] = static_cast<float>(exp(-A * pow(rho[c] * irm, beta)));
 }
 
+// T of one sample's cells; nq = 6: the dual-energy selection (gm2 = gamma - 2)
 __global__ void temperature_kernel(const float* __restrict__ q, float a, float efloor,
-                                   float t_per_e, float* __restrict__ out, long long nc) {
+                                   float t_per_e, float* __restrict__ out, long long nc, int nq,
+                                   float gm2) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   const float rho = q[c], ia = 1.0f / a;
   const float u0 = q[nc + c] * ia / rho, u1 = q[2 * nc + c] * ia / rho, u2 = q[3 * nc + c] * ia / rho;
-  const float e = q[4 * nc + c] * ia * ia / rho - 0.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+  float e = q[4 * nc + c] * ia * ia / rho - 0.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+  if (nq == 6) {
+    const float v[5] = {rho, q[nc + c], q[2 * nc + c], q[3 * nc + c], q[4 * nc + c]};
+    if (!dual_total_branch(v)) e = q[5 * nc + c] * ia * ia * pow_approx(rho, gm2);
+  }
   out[c] = fmaxf(e, efloor) * t_per_e;
 }
 
@@ -984,14 +1091,15 @@ __global__ void lpt2_combine_kernel(float* __restrict__ psi, const float* __rest
   psi[i] = a + b;
 }
 
+// nq = 6: also the dual-energy entropy S = a^2 e_init rho^(2-gamma) (g2m = 2 - gamma)
 __global__ void ic_gas_kernel(const float* __restrict__ cic, const float* __restrict__ psi,
                               float* __restrict__ q, float f_b, float vfac, float a, float e_init,
-                              long long nc) {
+                              long long nc, int nq, float g2m) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   cic += blockIdx.y * nc;
   psi += blockIdx.y * 3 * nc;
-  q += blockIdx.y * 5 * nc;
+  q += blockIdx.y * nq * nc;
   const float rho = f_b * cic[c];
   q[c] = rho;
   float u2 = 0.0f;
@@ -1003,18 +1111,19 @@ __global__ void ic_gas_kernel(const float* __restrict__ cic, const float* __rest
     u2 += u * u;
   }
   q[4 * nc + c] = a * a * rho * (e_init + 0.5f * u2);
+  if (nq == 6) q[5 * nc + c] = a * a * e_init * pow_approx(rho, g2m);
 }
 
 // adjoint of ic_gas: lam_cic = f_b * lam_rho_total ; lam_psi += contributions
 __global__ void ic_gas_vjp_kernel(const float* __restrict__ cic, const float* __restrict__ psi,
                                   const float* __restrict__ lam, float f_b, float vfac, float a,
                                   float e_init, float* __restrict__ lam_cic,
-                                  float* __restrict__ lam_psi, long long nc) {
+                                  float* __restrict__ lam_psi, long long nc, int nq, float g2m) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   cic += blockIdx.y * nc;
   psi += blockIdx.y * 3 * nc;
-  lam += blockIdx.y * 5 * nc;
+  lam += blockIdx.y * nq * nc;
   lam_cic += blockIdx.y * nc;
   lam_psi += blockIdx.y * 3 * nc;
   const float rho = f_b * cic[c];
@@ -1031,6 +1140,8 @@ __global__ void ic_gas_vjp_kernel(const float* __restrict__ cic, const float* __
     lam_psi[d * nc + c] += vfac * (lm * rho + le * rho * p);
   }
   lr += le * (a * a * e_init + 0.5f * p2);
+  // S = a^2 e_init rho^(2-gamma): dS/drho = (2-gamma) a^2 e_init rho^(1-gamma)
+  if (nq == 6) lr += lam[5 * nc + c] * g2m * a * a * e_init * pow_approx(rho, g2m - 1.0f);
   lam_cic[c] = f_b * lr;
 }
 
@@ -1045,7 +1156,7 @@ void launch_gas_kick_vjp(hipStream_t st, const float* q_before, const float4* g4
                          float* lam_g, const Batch& b) {
   if (!b.tab) throw ArgError("gas kick adjoint: step table required");
   hipLaunchKernelGGL(gas_kick_vjp_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st,
-                     q_before, g4, lam_q, lam_g, b.nc(), b.tab);
+                     q_before, g4, lam_q, lam_g, b.nc(), b.nq, b.tab);
   DH_LAUNCH_CHECK();
 }
 
@@ -1059,17 +1170,25 @@ void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4
   if ((star == nullptr && znew != nullptr) || (block_max != nullptr && sn_out != nullptr))
     throw ArgError("closing pass: new stars need the star field; a smoothed injection takes "
                    "the CFL maxima to the injection pass");
+  if (b.nq == 6 && (closure || sn_out))
+    throw ArgError("closing pass: the dual-energy state has neither the learned closure nor the "
+                   "smoothed injection");
   const dim3 grid(sum_blocks(b.nc()), b.S);
+  const double gg1 = gamma * (gamma - 1.0);
+#define DH_CLOSE(FULL, NQ)                                                                      \
+  hipLaunchKernelGGL((close_step_kernel<FULL, NQ>), grid, dim3(kRedThreads), 0, st, q_in, q, g4, \
+                     star, q_kicked, gg1, block_max, b.nc(), b.tab, znew, sn_out)
   if (closure)
     hipLaunchKernelGGL(close_step_mlp_kernel, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
-                       q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab, znew, sn_out);
-  else if (star)
-    hipLaunchKernelGGL(close_step_kernel<true>, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
-                       q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab, znew, sn_out);
-  else
-    hipLaunchKernelGGL(close_step_kernel<false>, grid, dim3(kRedThreads), 0, st, q_in, q, g4,
-                       star, q_kicked, gamma * (gamma - 1.0), block_max, b.nc(), b.tab, znew,
-                       sn_out);
+                       q_kicked, gg1, block_max, b.nc(), b.tab, znew, sn_out);
+  else if (b.nq == 6) {
+    if (star) DH_CLOSE(true, 6);
+    else DH_CLOSE(false, 6);
+  } else {
+    if (star) DH_CLOSE(true, 5);
+    else DH_CLOSE(false, 5);
+  }
+#undef DH_CLOSE
   DH_LAUNCH_CHECK();
 }
 
@@ -1082,6 +1201,7 @@ static int log2_int(int v) {
 void launch_sn_inject(hipStream_t st, const float* sn, float* q, double gamma, double* block_max,
                       const Batch& b) {
   if (!b.tab) throw ArgError("supernova injection: step table required");
+  if (b.nq != 5) throw ArgError("supernova injection: not with the dual-energy state");
   hipLaunchKernelGGL(sn_inject_kernel, dim3(sum_blocks(b.nc()), b.S), dim3(kRedThreads), 0, st,
                      sn, q, gamma * (gamma - 1.0), block_max, b.n, log2_int(b.n), b.tab);
   DH_LAUNCH_CHECK();
@@ -1104,6 +1224,7 @@ int cfl_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n * n); }
 void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, double* partials,
                        const Batch& b, const float* lam_inj) {
   if (!b.tab) throw ArgError("source adjoint: step table required");
+  if (b.nq != 5) throw ArgError("closure adjoint: not with the dual-energy state");
   const dim3 grid(source_vjp_blocks(b.n), b.S);
   hipLaunchKernelGGL(source_vjp_mlp_kernel, grid, dim3(kRedThreads), 0, st, q_before, lam_q,
                      partials, b.nc(), b.tab, lam_inj);
@@ -1115,24 +1236,34 @@ void launch_source_kick_vjp(hipStream_t st, const float* q_kick, const float4* g
                             const float* q_open, float* lam_g_open, const StepScal* tab_open,
                             const float* lam_inj) {
   if (!b.tab) throw ArgError("closing pass adjoint: step table required");
+  if (q_open && (!lam_g_open || !tab_open))
+    throw ArgError("closing pass adjoint: opening kick operands");
+  if (b.nq == 6 && lam_inj) throw ArgError("closing pass adjoint: no smoothed dual-energy injection");
   const dim3 grid(source_vjp_blocks(b.n), b.S);
-  if (q_open) {
-    if (!lam_g_open || !tab_open) throw ArgError("closing pass adjoint: opening kick operands");
-    hipLaunchKernelGGL(source_kick_vjp_kernel<true>, grid, dim3(kRedThreads), 0, st, q_kick, g4,
-                       lam_q, lam_g, partials, b.nc(), b.tab, q_open, lam_g_open, tab_open,
-                       lam_inj);
+#define DH_SKV(OPEN, NQ)                                                                      \
+  hipLaunchKernelGGL((source_kick_vjp_kernel<OPEN, NQ>), grid, dim3(kRedThreads), 0, st, q_kick, \
+                     g4, lam_q, lam_g, partials, b.nc(), b.tab, q_open, lam_g_open, tab_open,    \
+                     lam_inj)
+  if (b.nq == 6) {
+    if (q_open) DH_SKV(true, 6);
+    else DH_SKV(false, 6);
   } else {
-    hipLaunchKernelGGL(source_kick_vjp_kernel<false>, grid, dim3(kRedThreads), 0, st, q_kick, g4,
-                       lam_q, lam_g, partials, b.nc(), b.tab, nullptr, nullptr, nullptr,
-                       lam_inj);
+    if (q_open) DH_SKV(true, 5);
+    else DH_SKV(false, 5);
   }
+#undef DH_SKV
   DH_LAUNCH_CHECK();
 }
 
 void launch_cfl_partial(hipStream_t st, const float* q, const double* a_cur, double gamma,
                         double efloor, double* block_max, const Batch& b) {
-  hipLaunchKernelGGL(cfl_partial_kernel, dim3(cfl_blocks(b.n), b.S), dim3(kRedThreads), 0, st, q,
-                     a_cur, gamma * (gamma - 1.0), efloor, block_max, b.nc());
+  const float gm2 = static_cast<float>(gamma - 2.0);
+  if (b.nq == 6)
+    hipLaunchKernelGGL(cfl_partial_kernel<6>, dim3(cfl_blocks(b.n), b.S), dim3(kRedThreads), 0, st,
+                       q, a_cur, gamma * (gamma - 1.0), efloor, gm2, block_max, b.nc());
+  else
+    hipLaunchKernelGGL(cfl_partial_kernel<5>, dim3(cfl_blocks(b.n), b.S), dim3(kRedThreads), 0, st,
+                       q, a_cur, gamma * (gamma - 1.0), efloor, gm2, block_max, b.nc());
   DH_LAUNCH_CHECK();
 }
 
@@ -1159,14 +1290,15 @@ void launch_conservation_partial(hipStream_t st, const float* q, const float* mo
 void launch_loss_partial(hipStream_t st, const float* rho, const float* target, double A,
                          double beta, float inv_rho_mean, double* partial, const Batch& b) {
   hipLaunchKernelGGL(loss_kernel, dim3(sum_blocks(b.nc()), b.S), dim3(kRedThreads), 0, st, rho,
-                     target, A, beta, static_cast<double>(inv_rho_mean), partial, b.nc());
+                     target, A, beta, static_cast<double>(inv_rho_mean), partial, b.nc(), b.qs());
   DH_LAUNCH_CHECK();
 }
 
 void launch_loss_vjp(hipStream_t st, const float* rho, const float* target, double A, double beta,
                      float inv_rho_mean, float* lam_rho, double* partial, const Batch& b) {
   hipLaunchKernelGGL(loss_vjp_kernel, dim3(sum_blocks(b.nc()), b.S), dim3(kRedThreads), 0, st, rho,
-                     target, A, beta, static_cast<double>(inv_rho_mean), lam_rho, partial, b.nc());
+                     target, A, beta, static_cast<double>(inv_rho_mean), lam_rho, partial, b.nc(),
+                     b.qs());
   DH_LAUNCH_CHECK();
 }
 
@@ -1178,9 +1310,9 @@ void launch_flux_field(hipStream_t st, const float* rho, double A, double beta, 
 }
 
 void launch_temperature(hipStream_t st, const float* q, float a, float efloor, float t_per_e,
-                        float* out, long long nc) {
+                        float* out, long long nc, int nq, double gamma) {
   hipLaunchKernelGGL(temperature_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, a, efloor,
-                     t_per_e, out, nc);
+                     t_per_e, out, nc, nq, static_cast<float>(gamma - 2.0));
   DH_LAUNCH_CHECK();
 }
 
@@ -1219,17 +1351,18 @@ void launch_lpt2_combine(hipStream_t st, float* psi, const float* psi2, float* v
 }
 
 void launch_ic_gas(hipStream_t st, const float* cic, const float* psi, float* q, float f_b,
-                   float vfac, float a, float e_init, const Batch& b) {
+                   float vfac, float a, float e_init, double gamma, const Batch& b) {
   hipLaunchKernelGGL(ic_gas_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st, cic, psi,
-                     q, f_b, vfac, a, e_init, b.nc());
+                     q, f_b, vfac, a, e_init, b.nc(), b.nq, static_cast<float>(2.0 - gamma));
   DH_LAUNCH_CHECK();
 }
 
 void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const float* lam_q,
-                       float f_b, float vfac, float a, float e_init, float* lam_cic,
+                       float f_b, float vfac, float a, float e_init, double gamma, float* lam_cic,
                        float* lam_psi, const Batch& b) {
   hipLaunchKernelGGL(ic_gas_vjp_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st, cic,
-                     psi, lam_q, f_b, vfac, a, e_init, lam_cic, lam_psi, b.nc());
+                     psi, lam_q, f_b, vfac, a, e_init, lam_cic, lam_psi, b.nc(), b.nq,
+                     static_cast<float>(2.0 - gamma));
   DH_LAUNCH_CHECK();
 }
 

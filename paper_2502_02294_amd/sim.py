@@ -64,6 +64,7 @@ class Sim:
         self.n = int(self.cfg.n)
         self.S = max(1, int(self.cfg.batch))
         self.nc = self.n ** 3
+        self.nq = 6 if self.cfg.dual_energy else 5   # gas components (dual energy: entropy)
         self._h = ctypes.c_void_p()
         torch.cuda.init()
         check(lib().dh_create(ctypes.byref(self.cfg), ctypes.byref(self._h)))
@@ -188,7 +189,8 @@ class Sim:
     def get(self, name):
         self._stream()
         f = FIELDS[name]
-        out = torch.empty(self._lead() + _FIELD_SHAPE[f] + (self.n, self.n, self.n),
+        shape = (self.nq,) if f == FIELD_Q else _FIELD_SHAPE[f]
+        out = torch.empty(self._lead() + shape + (self.n, self.n, self.n),
                           dtype=torch.float32, device="cuda")
         self._check(lib().dh_get_field(self._h, f, _ptr(out)))
         if f in (FIELD_POS, FIELD_MOM):
@@ -198,7 +200,8 @@ class Sim:
     def set(self, name, t):
         self._stream()
         f = FIELDS[name]
-        numel = self.S * self.nc * (5 if f == FIELD_Q else 3 if f in (FIELD_POS, FIELD_MOM) else 1)
+        numel = self.S * self.nc * (self.nq if f == FIELD_Q else
+                                    3 if f in (FIELD_POS, FIELD_MOM) else 1)
         self._check(lib().dh_set_field(self._h, f, _ptr(t.contiguous(), numel=numel)))
 
     def refresh_potential(self):
@@ -309,16 +312,16 @@ class Sim:
     def stage_sweep(self, q, axis, dt, a1, a2):
         self._stream()
         out = torch.empty_like(q)
-        self._check(lib().dh_stage_sweep(self._h, _ptr(q, numel=5 * self.nc), _ptr(out), axis, dt,
-                                         a1, a2))
+        self._check(lib().dh_stage_sweep(self._h, _ptr(q, numel=self.nq * self.nc), _ptr(out),
+                                         axis, dt, a1, a2))
         return out
 
     def stage_sweep_vjp(self, q, lam_out, axis, dt, a1, a2):
         self._stream()
         out = torch.empty_like(q)
-        self._check(lib().dh_stage_sweep_vjp(self._h, _ptr(q, numel=5 * self.nc),
-                                             _ptr(lam_out, numel=5 * self.nc), _ptr(out), axis,
-                                             dt, a1, a2))
+        self._check(lib().dh_stage_sweep_vjp(self._h, _ptr(q, numel=self.nq * self.nc),
+                                             _ptr(lam_out, numel=self.nq * self.nc), _ptr(out),
+                                             axis, dt, a1, a2))
         return out
 
     def stage_poisson(self, delta, a):

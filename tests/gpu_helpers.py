@@ -59,7 +59,8 @@ def gpu_config(ocfg, **kw):
                           dlna_max=ocfg.dlna_max, t_floor=ocfg.t_floor, subgrid=ocfg.subgrid,
                           tau=ocfg.tau, sf_seed=ocfg.sf_seed, kdk=ocfg.kdk,
                           sn_smooth=int(ocfg.sn_smooth), star_dm=int(ocfg.star_dm),
-                          lpt=ocfg.lpt, transfer=ocfg.transfer, **kw)
+                          lpt=ocfg.lpt, transfer=ocfg.transfer,
+                          dual_energy=int(ocfg.dual_energy), **kw)
 
 
 def gpu_params(p):
@@ -94,7 +95,9 @@ def initial_state_fp32_cells(white, ocfg):
     mom = rho * vel
     u = mom / (a * rho)
     etot = a * a * rho * (ocfg.e_init + 0.5 * (u * u).sum(0))
-    return osim.state_from_qxp(torch.cat([rho[None], mom, etot[None]]), x, p, ocfg)
+    extra = ([(a * a * ocfg.e_init * rho ** (2.0 - ocfg.gamma))[None]]
+             if ocfg.dual_energy else [])
+    return osim.state_from_qxp(torch.cat([rho[None], mom, etot[None]] + extra), x, p, ocfg)
 
 
 # ---------------------------------------------------------------- sweep adjoint at kinks

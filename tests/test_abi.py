@@ -47,7 +47,7 @@ def test_struct_layouts_match_c(tmp_path):
 #include <stddef.h>
 #include "{HEADER}"
 int main(void) {{
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dh_config), sizeof(dh_params),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dh_config), sizeof(dh_params),
          offsetof(dh_config, subgrid), offsetof(dh_config, sf_seed),
          offsetof(dh_config, ckpt_every), offsetof(dh_params, w_t),
          offsetof(dh_config, closure), sizeof(dh_mlp_train_opts),
@@ -55,7 +55,7 @@ int main(void) {{
          offsetof(dh_mlp_sample_opts, dc_hi), offsetof(dh_config, cfl_forward),
          offsetof(dh_config, kdk), offsetof(dh_config, star_dm),
          offsetof(dh_config, sn_smooth), offsetof(dh_config, lpt),
-         offsetof(dh_config, transfer));
+         offsetof(dh_config, transfer), offsetof(dh_config, dual_energy));
   return 0;
 }}
 """)
@@ -67,7 +67,8 @@ int main(void) {{
     want = [ctypes.sizeof(C), ctypes.sizeof(P), C.subgrid.offset, C.sf_seed.offset,
             C.ckpt_every.offset, P.w_t.offset, C.closure.offset, ctypes.sizeof(T), T.lr.offset,
             ctypes.sizeof(S), S.dc_hi.offset, C.cfl_forward.offset, C.kdk.offset,
-            C.star_dm.offset, C.sn_smooth.offset, C.lpt.offset, C.transfer.offset]
+            C.star_dm.offset, C.sn_smooth.offset, C.lpt.offset, C.transfer.offset,
+            C.dual_energy.offset]
     assert got == want
 
 
