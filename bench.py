@@ -164,14 +164,33 @@ def mlp_comparison(torch, dhp, white, n, box, steps, warmup, samples):
         log(f"bench: {name} source term: forward {t_fwd * 1e3 / steps:.2f} ms/step, "
             f"fwd+bwd {t_fb * 1e3 / steps:.2f} ms/step")
     finals = {}
-    for name, sub, clo in (("plain", 2, 0), ("mlp", 2, 1), ("off", 0, 0)):
-        s = dhp.Sim(dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=sub, closure=clo), prm)
+    # "nudged": the plain term with eps_sf changed by one part in a million, the distance a
+    # run keeps from itself under a perturbation far below any closure's error (the flow's
+    # own sensitivity: the floor of every distance below)
+    prm_nudged = dhp.default_params(eps_sf=0.03 * (1.0 + 1e-6), delta_c=10.0, t_c=1e7)
+    for name, sub, clo in (("plain", 2, 0), ("mlp", 2, 1), ("off", 0, 0), ("nudged", 2, 0)):
+        s = dhp.Sim(dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=sub, closure=clo),
+                    prm_nudged if name == "nudged" else prm)
         if clo:
             s.set_closure(theta)
         s.init_from_noise(white)
         k = s.run_to(0.29)
         finals[name] = (s.get("rho").double(), s.get("temp").double().log(),
                         float(s.get("star").double().sum()), k)
+        if name == "plain":
+            # the network against the plain term on every cell of the state the run reached:
+            # ln pi0 of a step of dt = 0.002 where the gates are open (o1 > -10)
+            xs, ys = s.closure_states()
+            o = net.eval(xs).double()
+            t = ys.double()
+            dt = 0.002
+            lp_net = torch.log(-torch.expm1(-torch.exp(o[0]) * dt)) + torch.clamp(o[1], max=0.0)
+            lp_ref = torch.log(-torch.expm1(-torch.exp(t[0]) * dt)) + t[1]
+            err = (lp_net - lp_ref).abs()[t[1] > -10.0]
+            lp_stats = {"cells": int(err.numel()), "median": float(err.median()),
+                        "mean": float(err.mean()),
+                        "p99": float(torch.quantile(err[:1 << 24].float(), 0.99))}
+            del xs, ys, o, t
         s.close()
 
     def rel(a, b):
@@ -194,7 +213,10 @@ def mlp_comparison(torch, dhp, white, n, box, steps, warmup, samples):
                      "rel_l2_lnT_vs_plain": rel(finals["mlp"][1], p[1]),
                      "no_source_rel_l2_rho_vs_plain": rel(finals["off"][0], p[0]),
                      "no_source_rel_l2_lnT_vs_plain": rel(finals["off"][1], p[1]),
-                     "stars_plain": p[2], "stars_mlp": finals["mlp"][2]},
+                     "nudged_rel_l2_rho_vs_plain": rel(finals["nudged"][0], p[0]),
+                     "nudged_rel_l2_lnT_vs_plain": rel(finals["nudged"][1], p[1]),
+                     "stars_plain": p[2], "stars_mlp": finals["mlp"][2],
+                     "abs_err_ln_pi0_on_run_states": lp_stats},
     }
 
 

@@ -394,6 +394,12 @@ int dh_mlp_get_weights(dh_mlp* net, float* h_theta);
 int dh_mlp_sample(dh_mlp* net, const dh_mlp_sample_opts* opts, double omega_b,
                   const dh_params* p, uint64_t seed, int64_t first, int64_t count, float* d_x,
                   float* d_y);
+/* Training and checking on the states a run visits: the network inputs d_x[5][S n^3] and
+ * the targets d_y[2][S n^3] (as dh_mlp_sample's) of every cell of the handle's current state
+ * (sample s at columns s n^3 ..), with its scale factor and parameters.  Caller-owned device
+ * buffers; asynchronous.  DH_E_INVAL for a dual-energy handle (the closure's temperature is
+ * that of the total energy). */
+int dh_closure_states(dh_sim* sim, float* d_x, float* d_y);
 /* d_out[2][count] = network(d_x). */
 int dh_mlp_eval(dh_mlp* net, const float* d_x, int64_t count, float* d_out);
 /* d_gx[5][count] = (d out / d x)^T d_gout[2][count] (BF16 rounding passed as identity). */

@@ -98,6 +98,7 @@ _SIGNATURES = {
     "dh_power_spectrum": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]),
     "dh_power_loss": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]),
     "dh_fli_loss": (I, [P, P, P, P, ctypes.POINTER(D)]),
+    "dh_closure_states": (I, [P, P, P]),
     "dh_set_kernel_timing": (I, [P, I]),
     "dh_get_kernel_timing": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D)]),
     "dh_conservation": (I, [P, ctypes.POINTER(D)]),

@@ -259,6 +259,10 @@ void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const
                        float f_b, float vfac, float a, float e_init, double gamma, float* lam_cic,
                        float* lam_psi, const Batch& b);
 void launch_fill(hipStream_t st, float* p, float v, long long count);
+// network inputs x[5][ld] and plain targets y[2][ld] of the nc cells of one sample's state q
+// (five components), at the scale factor and parameters of a
+void launch_closure_state(hipStream_t st, const float* q, const SourceArgs& a, float* x, float* y,
+                          long long nc, long long ld);
 
 // ---- learned closure network (k_mlp.hip; layout in dh_mlp.h)
 struct MlpSampleArgs {   // ranges of the training states (natural logs where named ln)

@@ -216,5 +216,20 @@ __device__ __forceinline__ void load_packed(const uint4* __restrict__ packed, in
   for (int i = threadIdx.x; i < kBias; i += blockDim.x) bias_lds[i] = b[i];
 }
 
+// Training targets of a cell state (FP64): o0 = ln(eps_sf / t_ff) with t_ff H0 =
+// (pi/2) sqrt(a^3 / (Omega_b Delta)), o1 = ln of the two relaxed threshold gates of Sec. 2.4,
+// sigmoid((Delta - Delta_c) / (w_rho Delta_c)) sigmoid((T_c - T) / (w_T T_c)), clipped at -30.
+__host__ __device__ inline void closure_targets(double delta, double temp, double lna,
+                                                double eps, double dc, double omega_b,
+                                                double t_c, double w_rho, double w_t,
+                                                double& o0, double& o1) {
+  o0 = log(eps) - log(1.5707963267948966) - 1.5 * lna + 0.5 * log(omega_b * delta);
+  const double y1 = (delta - dc) / (w_rho * dc);
+  const double y2 = (t_c - temp) / (w_t * t_c);
+  const double ls1 = fmin(y1, 0.0) - log1p(exp(-fabs(y1)));
+  const double ls2 = fmin(y2, 0.0) - log1p(exp(-fabs(y2)));
+  o1 = fmax(ls1 + ls2, -30.0);
+}
+
 }  // namespace mlp
 }  // namespace dh

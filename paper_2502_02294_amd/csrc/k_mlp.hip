@@ -100,14 +100,10 @@ __global__ void __launch_bounds__(256) sample_kernel(MlpSampleArgs p, float* __r
   x[2 * count + i] = static_cast<float>((lna + 3.0) / 1.5);
   x[3 * count + i] = static_cast<float>(eps / 0.02 - 1.0);
   x[4 * count + i] = static_cast<float>(dc / 100.0 - 1.0);
-  // o0 = ln(eps / t_ff), t_ff H0 = (pi/2) sqrt(a^3 / (Omega_b Delta))
-  const double o0 = log(eps) - log(1.5707963267948966) - 1.5 * lna + 0.5 * log(p.omega_b * delta);
-  const double y1 = (delta - dc) / (p.w_rho * dc);
-  const double y2 = (p.t_c - temp) / (p.w_t * p.t_c);
-  const double ls1 = fmin(y1, 0.0) - log1p(exp(-fabs(y1)));
-  const double ls2 = fmin(y2, 0.0) - log1p(exp(-fabs(y2)));
+  double o0, o1;
+  closure_targets(delta, temp, lna, eps, dc, p.omega_b, p.t_c, p.w_rho, p.w_t, o0, o1);
   y[i] = static_cast<float>(o0);
-  y[count + i] = static_cast<float>(fmax(ls1 + ls2, -30.0));
+  y[count + i] = static_cast<float>(o1);
 }
 
 // ------------------------------------------------------------------------- inference

@@ -614,6 +614,30 @@ __device__ __forceinline__ void closure_inputs(const float q5[5], const SourceAr
   x[4] = static_cast<float>(a.delta_c / 100.0 - 1.0);
 }
 
+// Network inputs x[5][ld] and the plain relaxed term's targets y[2][ld] (mlp::closure_targets)
+// of every cell of one sample's state: the closure trained and checked on the states a run
+// visits.
+__global__ void __launch_bounds__(256) closure_state_kernel(const float* __restrict__ q,
+                                                            SourceArgs a, float* __restrict__ x,
+                                                            float* __restrict__ y, long long nc,
+                                                            long long ld) {
+  const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  float q5[5], xin[5];
+  load_q(q, c, nc, q5);
+  double e_raw;
+  bool floored;
+  closure_inputs(q5, a, xin, e_raw, floored);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) x[k * ld + c] = xin[k];
+  const double e = floored ? a.efloor : e_raw;
+  double o0, o1;
+  mlp::closure_targets(q5[0] * a.inv_rho_mean, e * a.t_per_e, log(a.a), a.eps_sf, a.delta_c,
+                       a.omega_b, a.t_c, a.w_rho, a.w_t, o0, o1);
+  y[c] = static_cast<float>(o0);
+  y[ld + c] = static_cast<float>(o1);
+}
+
 // input operands of 16 NCT cells from the stage (slots 0..4 of each cell)
 template <int NCT>
 __device__ __forceinline__ mlp::Act<NCT> stage_operands(const float (*stage)[kStage], int lane) {
@@ -1363,6 +1387,13 @@ void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const
   hipLaunchKernelGGL(ic_gas_vjp_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st, cic,
                      psi, lam_q, f_b, vfac, a, e_init, lam_cic, lam_psi, b.nc(), b.nq,
                      static_cast<float>(2.0 - gamma));
+  DH_LAUNCH_CHECK();
+}
+
+void launch_closure_state(hipStream_t st, const float* q, const SourceArgs& a, float* x, float* y,
+                          long long nc, long long ld) {
+  hipLaunchKernelGGL(closure_state_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, a, x,
+                     y, nc, ld);
   DH_LAUNCH_CHECK();
 }
 

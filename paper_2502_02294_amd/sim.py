@@ -289,6 +289,16 @@ class Sim:
                                       _ptr(white, numel=m), out))
         return out[0] if self.S == 1 else list(out)
 
+    def closure_states(self):
+        """(x [5, S n^3], y [2, S n^3]): the closure network's inputs and the plain term's
+        targets for every cell of the current state (dh_closure_states)."""
+        self._stream()
+        m = self.S * self.nc
+        x = torch.empty(5, m, dtype=torch.float32, device="cuda")
+        y = torch.empty(2, m, dtype=torch.float32, device="cuda")
+        self._check(lib().dh_closure_states(self._h, _ptr(x), _ptr(y)))
+        return x, y
+
     def set_kernel_timing(self, family):
         """Time the launches of one kernel family (_lib.KTIME_*; -1 stops) inside steps and
         reverse passes with HIP events on the handle's stream."""

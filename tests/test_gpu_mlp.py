@@ -146,6 +146,28 @@ def test_training_set_is_the_plain_source_term(dhp):
     assert torch.equal(torch.cat([x1, x2], 1), xa) and torch.equal(torch.cat([y1, y2], 1), ya)
 
 
+def test_closure_states_are_the_plain_source_term(dhp):
+    """dh_closure_states on an evolved state: every cell's network inputs and plain targets
+    against the oracle's features and targets of the same cells."""
+    n = 32
+    ocfg = osim.default_config(n=n, box=10.0)
+    st = osim.initial_state(torch.from_numpy(si.white_noise(n, 3)).double(), ocfg)
+    st, _ = osim.run(st, ocfg, osim.Params(), a_final=0.1)
+    st = rounded_state(st)
+    prm = osim.Params(eps_sf=0.03, delta_c=10.0, t_c=1e7)
+    s = dhp.Sim(gpu_config(replace(ocfg, subgrid=subgrid.MODE_RELAXED)), gpu_params(prm))
+    load_state(s, st)
+    x, y = s.closure_states()
+    temp = subgrid.temperature(st.q, st.a, ocfg.gamma, ocfg.e_floor, ocfg.t_per_e)
+    delta = st.q[0] / ocfg.f_b
+    xr = omlp.features(delta, temp, st.a, prm.eps_sf, prm.delta_c).reshape(5, -1).numpy()
+    yr = omlp.targets(delta, temp, st.a, prm.eps_sf, prm.delta_c, omega_b=ocfg.omega_b,
+                      t_c=prm.t_c, w_rho=prm.w_rho, w_t=prm.w_t).reshape(2, -1).numpy()
+    assert np.abs(to_np(x) - xr).max() < 1e-5
+    assert np.abs(to_np(y) - yr).max() < 1e-4
+    assert (yr[1] > -10.0).mean() > 1e-3   # some cells have open gates
+
+
 def _train(dhp, steps=20000, count=1 << 21, seed=7, params=None, opts=None):
     net = dhp.Mlp(seed=1)
     x, y = net.sample(count, seed=seed, params=params, opts=opts)
