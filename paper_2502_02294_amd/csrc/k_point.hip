@@ -17,10 +17,12 @@ constexpr int kRedPer = 8;   // cells per thread in reduction kernels
 
 __device__ __forceinline__ int wrapi(int j, int n) { return j & (n - 1); }
 
-// block reduction of nv doubles per thread into out[v * stride + blockIdx.x]
+// block reduction of nv doubles per thread into out[v * stride + blockIdx.x], through the
+// LDS scratch sh (NV kRedThreads doubles; the caller synchronises before handing in memory
+// that other waves may still read)
 template <int NV, bool MAX>
-__device__ void block_reduce_store(double (&v)[NV], double* out, long long stride) {
-  __shared__ double sh[NV][kRedThreads];
+__device__ void block_reduce_in(double (*sh)[kRedThreads], double (&v)[NV], double* out,
+                                long long stride) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) sh[k][threadIdx.x] = v[k];
   __syncthreads();
@@ -37,6 +39,12 @@ __device__ void block_reduce_store(double (&v)[NV], double* out, long long strid
 #pragma unroll
     for (int k = 0; k < NV; ++k) out[k * stride + blockIdx.x] = sh[k][0];
   }
+}
+
+template <int NV, bool MAX>
+__device__ void block_reduce_store(double (&v)[NV], double* out, long long stride) {
+  __shared__ double sh[NV][kRedThreads];
+  block_reduce_in<NV, MAX>(sh, v, out, stride);
 }
 
 // Partials of a batched reduction: value v of block b of sample s at [(v S + s) nb + b]
@@ -718,7 +726,7 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
   if (sn_out) sn_out += blockIdx.y * nc;
   __shared__ uint4 fr[mlp::kFrFwd * 64];
   __shared__ __attribute__((aligned(16))) float bias[mlp::kBias];
-  __shared__ float stage[kRedThreads / 64][64][kStage];
+  __shared__ __attribute__((aligned(16))) float stage[kRedThreads / 64][64][kStage];
   mlp::load_packed(a.mlp, mlp::kFrFwd, fr, bias);
   __syncthreads();   // the weights; from here on every wave works on its own cells
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -783,12 +791,21 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
     }
     wave_sync();
   }
-  if (partial) block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
+  if (partial) {
+    // the stage, free once every wave is done, holds the reduction (no LDS of its own, so
+    // more blocks share a CU)
+    __syncthreads();
+    block_reduce_in<1, true>(reinterpret_cast<double (*)[kRedThreads]>(&stage[0][0][0]), vmax,
+                             sample_partials(partial), partial_stride());
+  }
 }
 
 // Adjoint of the closure's source update at the kicked state q: lam (in: after, out:
 // before); partial[0|1][block] = dL/d(eps_sf | delta_c), which enter through the inputs.
-__global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
+// Two waves per SIMD (256 registers a lane): the compiler keeps a few values in scratch, and
+// the kernel still runs ~30% faster at 256^3 than with every value in registers at one wave
+// per SIMD (342 registers); a third wave costs more in spills than it gains.
+__global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
     const float* __restrict__ q, float* __restrict__ lam, double* partial, long long nc,
     const StepScal* __restrict__ tab, const float* __restrict__ lam_inj) {
   const StepScal& sc = tab[blockIdx.y];
@@ -802,7 +819,7 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
   if (lam_inj) lam_inj += blockIdx.y * nc;
   __shared__ uint4 fr[mlp::kFrAll * 64];
   __shared__ __attribute__((aligned(16))) float bias[mlp::kBias];
-  __shared__ float stage[kRedThreads / 64][64][kStage];
+  __shared__ __attribute__((aligned(16))) float stage[kRedThreads / 64][64][kStage];
   mlp::load_packed(a.mlp, mlp::kFrAll, fr, bias);
   __syncthreads();   // the weights; from here on every wave works on its own cells
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -905,7 +922,12 @@ __global__ void __launch_bounds__(kRedThreads) source_vjp_mlp_kernel(
     }
     wave_sync();
   }
-  block_reduce_store<2, false>(acc, sample_partials(partial), partial_stride());
+  // the stage, free once every wave is done, holds the reduction: 54 KB of LDS per block, so
+  // three blocks (three waves per SIMD) share a CU
+  static_assert(sizeof(stage) >= 2 * kRedThreads * sizeof(double), "stage too small");
+  __syncthreads();
+  block_reduce_in<2, false>(reinterpret_cast<double (*)[kRedThreads]>(&stage[0][0][0]), acc,
+                            sample_partials(partial), partial_stride());
 }
 
 // ------------------------------------------------------------------------- CFL
