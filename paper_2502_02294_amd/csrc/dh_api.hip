@@ -650,8 +650,9 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
   if (tp) {
     // the sweeps (the first one also applies the opening gas kick and keeps the kicked state
     // in Q1) and the closing pass write their results straight into the tape
+    const bool kept = recompute && store_k >= 0 && store_k < s->store_valid;
     dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, nullptr,
-                          prev, b);
+                          prev, b, kept ? nullptr : &s->bins);
     {
       KernelTimer kt(s, DH_KTIME_SWEEP_KICK);
       dh::launch_sweep(s->st, tp->q[0], tp->q[2], b, sp.axes[0], s->g4, tp->q[1]);
@@ -660,7 +661,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
       KernelTimer kt(s, DH_KTIME_SWEEP);
       dh::launch_sweep(s->st, tp->q[1 + k], tp->q[2 + k], b, sp.axes[k]);
     }
-    if (recompute && store_k >= 0 && store_k < s->store_valid) {
+    if (kept) {
       // the forward kept this step's sort and potential: no sort, deposit or Poisson solve
       const StepStore& e = s->store[store_k];
       copy_d2d(s, s->phi, e.phi, nc * s->S);
@@ -669,7 +670,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
       tp->vsorted = e.sorted;
       tp->vspos = e.spos;
     } else {
-      dh::launch_sort(s->st, s->bins, s->pos, b);
+      dh::launch_sort(s->st, s->bins, s->pos, b, true);
       potential_from_bins(s, tp->q[4], s->phi, s->g4, b);
       // the tape keeps this sort of x1 for the reverse pass; the next sort writes the tape's
       // former buffers
@@ -688,15 +689,15 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
     // opening half kicks with g_n (the gas one inside the first sweep), drift with
     // a(t + dt/2)
     dh::launch_kick_drift(s->st, s->g4, s->pos, s->pos, s->mom, s->bins.key, nullptr, nullptr,
-                          prev, b);
+                          prev, b, &s->bins);
     // sweeps in the Strang order of the step (a sample that sits out is copied along)
     for (int k = 0; k < 3; ++k) {
       KernelTimer kt(s, k == 0 ? DH_KTIME_SWEEP_KICK : DH_KTIME_SWEEP);
       dh::launch_sweep(s->st, s->q, s->q2, b, sp.axes[k], k == 0 ? s->g4 : nullptr);
       std::swap(s->q, s->q2);
     }
-    // Poisson at a(t + dt) from gas + DM (keys were written by the drift)
-    dh::launch_sort(s->st, s->bins, s->pos, b);
+    // Poisson at a(t + dt) from gas + DM (keys and their histogram were made by the drift)
+    dh::launch_sort(s->st, s->bins, s->pos, b, true);
     potential_from_bins(s, s->q, s->phi, s->g4, b);
     // closing gas half kick with g_{n+1}, source term and the CFL maxima: one pass
     close_pass(s, s->q, nullptr, true, true, s->bins.spos, s->bins.sorted, b, closure);

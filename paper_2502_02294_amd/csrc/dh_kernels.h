@@ -82,8 +82,10 @@ void launch_keys(hipStream_t st, const float* pos, uint32_t* key, const Batch& b
 // at the end of the step; samples that sit the step out are skipped)
 void launch_star_readout(hipStream_t st, const float* znew, const float4* spos,
                          const uint32_t* sorted, float* aux, const Batch& b);
-// sort by bins.key (already computed for pos) and gather pos into bin order
-void launch_sort(hipStream_t st, const Bins& bins, const float* pos, const Batch& b);
+// sort by bins.key (already computed for pos) and gather pos into bin order; counted: the
+// histogram was made by launch_kick_drift (count_into)
+void launch_sort(hipStream_t st, const Bins& bins, const float* pos, const Batch& b,
+                 bool counted = false);
 // bins.sval = v[3][np] (per sample) in bin order
 void launch_gather_sorted(hipStream_t st, const Bins& bins, const float* v, const Batch& b);
 // out = rho_gas + m_dm * CIC(sorted positions) + offset; rho_gas (sample s at
@@ -101,10 +103,12 @@ void launch_readout_g(hipStream_t st, const float4* g4, const float* pos, float*
                       const Batch& b);
 // opening kick (h_open) + drift (drift) + keys: positions read from pos_in and written to pos
 // (the same array for an update in place); optional copies of the new momenta and positions.
-// prev: first the previous step's closing kick (h_prev of the table), as launch_kick would
+// prev: first the previous step's closing kick (h_prev of the table), as launch_kick would.
+// count_into (optional, key == count_into->key): also the histogram of the following
+// launch_sort(..., counted = true) (count zeroed here, arrival ranks)
 void launch_kick_drift(hipStream_t st, const float4* g4, const float* pos_in, float* pos,
                        float* mom, uint32_t* key, float* mom_copy, float* pos_copy, bool prev,
-                       const Batch& b);
+                       const Batch& b, const Bins* count_into = nullptr);
 // closing kick p += h_close g(x)
 void launch_kick(hipStream_t st, const float4* g4, const float* pos, float* mom, const Batch& b);
 // adjoint of p' = p + k g(x) with respect to x: lam_x += k sum_c dw/dx (g_c . lam_p'), with

@@ -161,7 +161,9 @@ __global__ void scatter_kernel(const uint32_t* __restrict__ key, const uint32_t*
 // The atomics above fix each bin's size but not the order inside it; sorting each bin's ids
 // ascending makes the layout a pure function of the keys.  A thread sorts a bin of up to
 // kSmallBin ids by insertion; larger bins (dense halos gather thousands of particles in a
-// cell) go to a list that bin_sort_large_kernel sorts one workgroup per bin.
+// cell) go to a list that bin_sort_large_kernel sorts one workgroup per bin.  (Moving the
+// positions along with the ids, in place of the gather pass after the sort, was slower: the
+// scattered 16-byte writes cost more than the gather's scattered reads.)
 constexpr uint32_t kSmallBin = 32;
 constexpr int kLdsSort = 16384;   // ids a workgroup sorts in LDS (64 KB)
 
@@ -642,7 +644,9 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
                                                          float* __restrict__ mom_copy,
                                                          float* __restrict__ pos_copy, int n,
                                                          long long np, int prev,
-                                                         const StepScal* __restrict__ tab) {
+                                                         const StepScal* __restrict__ tab,
+                                                         uint32_t* count,
+                                                         uint32_t* __restrict__ rank) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const StepScal& sc = tab[blockIdx.y];
   if (i >= np) return;
@@ -654,7 +658,10 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
   key += smp * np;
   if (mom_copy) mom_copy += smp * 3 * np;
   if (pos_copy) pos_copy += smp * 3 * np;
+  if (count) rank += smp * np;
   if (!sc.active) {
+    // the sort's histogram counts the sample's particles under the keys they have
+    if (count) rank[i] = atomicAdd(&count[key[i]], 1u);
     // a sample that sits the step out keeps its particles; the copies (the tape of the
     // reverse pass, which sorts them again) receive them unchanged
 #pragma unroll
@@ -684,7 +691,10 @@ __global__ void __launch_bounds__(256) kick_drift_kernel(const float4* __restric
     if (pos_copy) pos_copy[d * np + i] = x[d];
   }
   const Cic w2 = cic_of(x[0], x[1], x[2], n);
-  key[i] = bin_of(w2, n, smp, np);
+  const uint32_t k = bin_of(w2, n, smp, np);
+  key[i] = k;
+  // the sort's histogram (count zeroed beforehand): the arrival rank of the particle in its bin
+  if (count) rank[i] = atomicAdd(&count[k], 1u);
 }
 
 __global__ void __launch_bounds__(256) kick_kernel(const float4* __restrict__ g4,
@@ -868,14 +878,17 @@ void launch_keys(hipStream_t st, const float* pos, uint32_t* key, const Batch& b
   DH_LAUNCH_CHECK();
 }
 
-void launch_sort(hipStream_t st, const Bins& bins, const float* pos, const Batch& b) {
+void launch_sort(hipStream_t st, const Bins& bins, const float* pos, const Batch& b,
+                 bool counted) {
   const long long nbins = b.nc() * b.S, total = nbins;
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(nbins, 256)), dim3(256), 0, st, bins.count,
-                     0u, nbins);
-  DH_LAUNCH_CHECK();
-  hipLaunchKernelGGL(hist_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, st, bins.key,
-                     bins.count, bins.rank, total);
-  DH_LAUNCH_CHECK();
+  if (!counted) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(nbins, 256)), dim3(256), 0, st,
+                       bins.count, 0u, nbins);
+    DH_LAUNCH_CHECK();
+    hipLaunchKernelGGL(hist_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, st, bins.key,
+                       bins.count, bins.rank, total);
+    DH_LAUNCH_CHECK();
+  }
   const int nb = static_cast<int>(scan_block_count(nbins));
   hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kScanThreads), 0, st, bins.count,
                      bins.block_sums, nbins);
@@ -964,10 +977,19 @@ void launch_star_readout(hipStream_t st, const float* znew, const float4* spos,
 
 void launch_kick_drift(hipStream_t st, const float4* g4, const float* pos_in, float* pos,
                        float* mom, uint32_t* key, float* mom_copy, float* pos_copy, bool prev,
-                       const Batch& b) {
+                       const Batch& b, const Bins* count_into) {
   if (!b.tab) throw ArgError("kick_drift: step table required");
+  if (count_into && key != count_into->key) throw ArgError("kick_drift: keys of another sort");
+  uint32_t* count = count_into ? count_into->count : nullptr;
+  uint32_t* rank = count_into ? count_into->rank : nullptr;
+  if (count) {
+    const long long nbins = b.nc() * b.S;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(nbins, 256)), dim3(256), 0, st, count, 0u,
+                       nbins);
+    DH_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(kick_drift_kernel, per_sample(b.nc(), b), dim3(256), 0, st, g4, pos_in, pos,
-                     mom, key, mom_copy, pos_copy, b.n, b.nc(), prev ? 1 : 0, b.tab);
+                     mom, key, mom_copy, pos_copy, b.n, b.nc(), prev ? 1 : 0, b.tab, count, rank);
   DH_LAUNCH_CHECK();
 }
 
