@@ -71,6 +71,7 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip the batched-sampler comparison")
     p.add_argument("--batch-samples", type=int, default=64)
     p.add_argument("--no-full-run", action="store_true", help="skip the whole run a -> 0.29")
+    p.add_argument("--no-dual", action="store_true", help="skip the dual-energy timing")
     return p.parse_args()
 
 
@@ -554,6 +555,19 @@ def main():
                         "reverse": dict(REV_BYTES)}},
     }
     s.close()
+    if not args.no_dual:
+        # the dual-energy formalism (entropy as a sixth gas component) on the same steps
+        cfg_d = dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=2,
+                                   ckpt_every=max(1, args.steps), dual_energy=1)
+        s_d = dhp.Sim(cfg_d)
+        td_fwd, td_fb, _, _, _ = time_steps(torch, s_d, white, args.steps, args.warmup)
+        s_d.close()
+        log(f"bench: dual energy: forward {td_fwd * 1e3 / args.steps:.2f} ms/step, fwd+bwd "
+            f"{td_fb * 1e3 / args.steps:.2f} ms/step")
+        out["dual_energy"] = {"fwd_ms_per_step": td_fwd / args.steps * 1e3,
+                              "fwd_bwd_ms_per_step": td_fb / args.steps * 1e3,
+                              "fwd_time_ratio_vs_plain": td_fwd / t_fwd,
+                              "fwd_bwd_time_ratio_vs_plain": td_fb / t_fb}
     if not args.no_mlp:
         log("bench: learned closure vs plain source term")
         out["mlp_closure"] = mlp_comparison(torch, dhp, white, n, box, args.steps,
