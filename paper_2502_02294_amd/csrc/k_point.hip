@@ -247,25 +247,28 @@ __device__ __forceinline__ void load_q(const float* __restrict__ q, long long c,
   for (int k = 0; k < NQ; ++k) q5[k] = q[k * nc + c];
 }
 
-// FP64 CFL speed of one cell: max_d (|U_d| + c_s) / a; +inf flags a broken state.  With the
-// dual-energy entropy (NQ = 6, gm2 = gamma - 2) c_s takes the selected internal energy.
+// CFL speed of one cell, max_d (|U_d| + c_s) / a, for the FP64 block maxima: evaluated in FP32
+// on the hardware reciprocal and square root (a few ulp, so the step's dt moves by ~1e-7 of
+// itself against an FP64 evaluation; the maxima, their reduction and dt stay FP64); +inf
+// flags a broken state.  With the dual-energy entropy (NQ = 6, gm2 = gamma - 2) c_s takes the
+// selected internal energy.
 template <int NQ = 5>
 __device__ __forceinline__ double cell_speed(const float* q5, double a, double gg1,
                                              double efloor, float gm2 = 0.0f) {
-  const double rho = q5[0];
-  const double ia = 1.0 / a;
-  const double iar = ia / rho;
-  const double u0 = q5[1] * iar, u1 = q5[2] * iar, u2 = q5[3] * iar;
-  const double e_raw = q5[4] * ia * iar - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
-  double e_sel = e_raw;
-  if (NQ == 6 && !dual_total_branch(q5))
-    e_sel = q5[5] * ia * ia * static_cast<double>(pow_approx(q5[0], gm2));
-  const double cs = sqrt(gg1 * fmax(e_sel, efloor));
-  double sp = (fmax(fabs(u0), fmax(fabs(u1), fabs(u2))) + cs) * ia;
+  const float rho = q5[0];
+  const float ia = static_cast<float>(1.0 / a);
+  const float iar = ia * rcp_approx(rho);
+  const float u0 = q5[1] * iar, u1 = q5[2] * iar, u2 = q5[3] * iar;
+  const float e_raw = q5[4] * ia * iar - 0.5f * (u0 * u0 + u1 * u1 + u2 * u2);
+  float e_sel = e_raw;
+  if (NQ == 6 && !dual_total_branch(q5)) e_sel = q5[5] * ia * ia * pow_approx(rho, gm2);
+  const float cs =
+      sqrt_approx(static_cast<float>(gg1) * fmaxf(e_sel, static_cast<float>(efloor)));
+  const float sp = (fmaxf(fabsf(u0), fmaxf(fabsf(u1), fabsf(u2))) + cs) * ia;
   // every component of the total energy enters e_raw, so a NaN or infinity anywhere in the
-  // cell shows there (fmax and the floor would drop a NaN); the entropy in e_sel
-  if (!(rho > 0.0) || !isfinite(e_raw) || !isfinite(sp) || (NQ == 6 && !isfinite(e_sel)))
-    sp = INFINITY;
+  // cell shows there (fmaxf and the floor would drop a NaN); the entropy in e_sel
+  if (!(rho > 0.0f) || !isfinite(e_raw) || !isfinite(sp) || (NQ == 6 && !isfinite(e_sel)))
+    return INFINITY;
   return sp;
 }
 
@@ -615,8 +618,10 @@ __device__ __forceinline__ void closure_inputs(const float q5[5], const SourceAr
   e_raw = q5[4] * ia * ia * ir - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
   floored = e_raw < a.efloor;
   const double e = floored ? a.efloor : e_raw;
-  x[0] = static_cast<float>((log(rho * a.inv_rho_mean) - 4.6) / 5.0);
-  x[1] = static_cast<float>((log(e * a.t_per_e) - 10.4) / 5.0);
+  // the logarithms on the hardware's (FP32, ~1e-7 absolute): the network sees its inputs as
+  // bfloat16 numbers, whose resolution is 4e-3
+  x[0] = (fast_log(static_cast<float>(rho * a.inv_rho_mean)) - 4.6f) * 0.2f;
+  x[1] = (fast_log(static_cast<float>(e * a.t_per_e)) - 10.4f) * 0.2f;
   x[2] = static_cast<float>((log(a.a) + 3.0) / 1.5);
   x[3] = static_cast<float>(a.eps_sf / 0.02 - 1.0);
   x[4] = static_cast<float>(a.delta_c / 100.0 - 1.0);
