@@ -266,8 +266,9 @@ __device__ __forceinline__ double cell_speed(const float* q5, double a, double g
       sqrt_approx(static_cast<float>(gg1) * fmaxf(e_sel, static_cast<float>(efloor)));
   const float sp = (fmaxf(fabsf(u0), fmaxf(fabsf(u1), fabsf(u2))) + cs) * ia;
   // every component of the total energy enters e_raw, so a NaN or infinity anywhere in the
-  // cell shows there (fmaxf and the floor would drop a NaN); the entropy in e_sel
-  if (!(rho > 0.0f) || !isfinite(e_raw) || !isfinite(sp) || (NQ == 6 && !isfinite(e_sel)))
+  // cell shows there (fmaxf and the floor would drop a NaN); the entropy is checked by itself
+  // (a cell on the total energy's branch does not use it)
+  if (!(rho > 0.0f) || !isfinite(e_raw) || !isfinite(sp) || (NQ == 6 && !isfinite(q5[5])))
     return INFINITY;
   return sp;
 }

@@ -310,3 +310,41 @@ def test_dual_batch_equals_single_runs(dhp):
     assert qb.shape == (S, 6, n, n, n)
     for i in range(S):
         assert torch.equal(qb[i], singles[i]), i
+
+
+def test_dual_combinations_and_errors(dhp):
+    """What the dual-energy state does not combine with returns DH_E_INVAL; a non-finite
+    entropy is reported like any broken state (DH_E_NONFINITE) before the step is taken."""
+    from paper_2502_02294_amd._lib import DiffHydroError
+    n = 16
+    for kw in ({"closure": 1, "subgrid": 2}, {"sn_smooth": 1, "subgrid": 2}):
+        with pytest.raises(DiffHydroError) as e:
+            dhp.Sim(dhp.default_config(n=n, box=4.0, dual_energy=1, **kw))
+        assert e.value.code == -1
+    s = dhp.Sim(dhp.default_config(n=n, box=4.0, dual_energy=1, subgrid=2))
+    s.init_from_noise(to_gpu(si.white_noise(n, seed=36)))
+    with pytest.raises(DiffHydroError) as e:
+        s.closure_states()
+    assert e.value.code == -1
+    q = s.get("q").clone()
+    assert q.shape == (6, n, n, n)
+    q[5, 1, 2, 3] = float("nan")
+    s.set("q", q)
+    a0 = s.time()[0]
+    with pytest.raises(DiffHydroError) as e:
+        s.step()
+    assert e.value.code == -4
+    assert s.time()[0] == a0
+
+
+def test_dual_power_spectrum_is_that_of_the_density(dhp):
+    """The spectrum reads the density row of the six-component state: from the same white
+    noise, a dual-energy handle and a plain one give the same spectrum bit for bit."""
+    n = 32
+    w = to_gpu(si.white_noise(n, seed=37))
+    out = []
+    for dual in (0, 1):
+        s = dhp.Sim(dhp.default_config(n=n, box=10.0, dual_energy=dual))
+        s.init_from_noise(w)
+        out.append(s.power_spectrum(8))
+    assert np.array_equal(np.asarray(out[0][0]), np.asarray(out[1][0]))
