@@ -433,7 +433,10 @@ __global__ void __launch_bounds__(256) deposit_kernel(const uint32_t* __restrict
 
 // Vector deposit: the three components go through the same 8-corner LDS table one after the
 // other (a third of the LDS of a 24-sum table, so twice as many blocks per CU); the first
-// particle of each bin stays in registers across the three passes.
+// particle of each bin stays in registers across the three passes.  (Reading the vector field
+// through the bins' particle ids, one component per pass, instead of gathering it into bin
+// order first, took 660 us against 432 + 104 us at 256^3: the dependent loads of every pass
+// and halo bin cost more than the gather.)
 template <int TX, int TY, int TZ>
 __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __restrict__ start,
                                                           const float4* __restrict__ spos,
