@@ -48,6 +48,18 @@ __device__ __forceinline__ float w1_of(float x) {
 
 __device__ __forceinline__ float wsel(float w1, int o) { return o ? w1 : 1.0f - w1; }
 
+// acc[o] += val prod_d (o_d ? w1_d : 1 - w1_d), o = ox + 2 oy + 4 oz: the products are formed
+// from z outwards, wx_o (wy_o (wz_o val)), so the 8 corners share their y-z factors (the
+// vector deposit; the density deposit keeps its products (wx wy) wz, for which the compiler
+// already shares the x-y factors: the shared form issues no fewer instructions there).
+__device__ __forceinline__ void add_corners(float wx, float wy, float wz, float val,
+                                            float (&acc)[8]) {
+  const float z0 = (1.0f - wz) * val, z1 = wz * val;
+  const float yz[4] = {(1.0f - wy) * z0, wy * z0, (1.0f - wy) * z1, wy * z1};
+#pragma unroll
+  for (int o = 0; o < 8; ++o) acc[o] = fmaf(wsel(wx, o & 1), yz[o >> 1], acc[o]);
+}
+
 // bin of particle i of sample s: s n^3 + CIC base cell
 __device__ __forceinline__ uint32_t bin_of(const Cic& c, int n, int smp, long long nc) {
   return static_cast<uint32_t>(smp * nc + (c.i0[2] * n + c.i0[1]) * n + c.i0[0]);
@@ -74,21 +86,36 @@ __global__ void hist_kernel(const uint32_t* __restrict__ key, uint32_t* count,
   rank[i] = atomicAdd(&count[key[i]], 1u);
 }
 
-// Block-local exclusive scan over kScanThreads values in LDS.
-__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const uint32_t add = t >= off ? sh[t - off] : 0u;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
+// Scans of the bin counts: 32-bit integer sums, so the grouping does not change a result.
+static_assert(kScanThreads == 256, "the block scans below assume four waves");
+
+// inclusive scan over the 64 lanes of a wave
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
   }
-  total = sh[kScanThreads - 1];
-  const uint32_t incl = sh[t];
+  return v;
+}
+
+// Block-wide exclusive scan over kScanThreads values; sh holds the four wave totals.
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
+  const uint32_t inc = wave_inclusive_scan(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) sh[w] = inc;
   __syncthreads();
-  return incl - v;
+  uint32_t below = 0;
+  total = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t t = sh[k];
+    below += k < w ? t : 0u;
+    total += t;
+  }
+  __syncthreads();   // sh is free again on return
+  return below + inc - v;
 }
 
 // tile element e lives at LDS word e + e / kScanPer (padding breaks the 16-word stride)
@@ -96,27 +123,51 @@ __device__ __forceinline__ int tile_slot(int e) { return e + e / kScanPer; }
 
 __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ block_sums, long long count) {
-  __shared__ uint32_t sh[kScanThreads];
+  __shared__ uint32_t sh[4];
   const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
   uint32_t s = 0;
-  for (int k = 0; k < kScanPer; ++k) {   // coalesced: consecutive threads, consecutive words
-    const long long e = base + k * kScanThreads + threadIdx.x;
-    if (e < count) s += in[e];
+  if (base + kScanTile <= count) {
+    // whole tile: 16-byte loads, consecutive threads on consecutive vectors
+    const uint4* in4 = reinterpret_cast<const uint4*>(in + base);
+#pragma unroll
+    for (int k = 0; k < kScanPer / 4; ++k) {
+      const uint4 v = in4[k * kScanThreads + threadIdx.x];
+      s += v.x + v.y + v.z + v.w;
+    }
+  } else {
+    for (int k = 0; k < kScanPer; ++k) {
+      const long long e = base + k * kScanThreads + threadIdx.x;
+      if (e < count) s += in[e];
+    }
   }
-  uint32_t total;
-  block_exclusive_scan(s, sh, total);
-  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// Exclusive scan of the nb block sums in place, one workgroup: each thread takes kScanPer
+// consecutive sums per round of kScanTile.
 __global__ void __launch_bounds__(kScanThreads) scan_block_sums_kernel(uint32_t* sums, int nb) {
-  __shared__ uint32_t sh[kScanThreads];
+  __shared__ uint32_t sh[4];
   uint32_t carry = 0;
-  for (int b0 = 0; b0 < nb; b0 += kScanThreads) {
-    const int i = b0 + threadIdx.x;
-    const uint32_t v = i < nb ? sums[i] : 0u;
+  for (int b0 = 0; b0 < nb; b0 += kScanTile) {
+    const int i0 = b0 + threadIdx.x * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      v[k] = i0 + k < nb ? sums[i0 + k] : 0u;
+      s += v[k];
+    }
     uint32_t total;
-    const uint32_t ex = block_exclusive_scan(v, sh, total);
-    if (i < nb) sums[i] = carry + ex;
+    uint32_t run = carry + block_exclusive_scan(s, sh, total);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      if (i0 + k < nb) sums[i0 + k] = run;
+      run += v[k];
+    }
     carry += total;
   }
 }
@@ -125,7 +176,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_final_kernel(
     const uint32_t* __restrict__ in, const uint32_t* __restrict__ block_off,
     uint32_t* __restrict__ out, long long count) {
   __shared__ uint32_t tile[kScanTile + kScanTile / kScanPer];
-  __shared__ uint32_t sh[kScanThreads];
+  __shared__ uint32_t sh[4];
   const long long base = static_cast<long long>(blockIdx.x) * kScanTile;
   for (int k = 0; k < kScanPer; ++k) {
     const int e = k * kScanThreads + threadIdx.x;
@@ -432,11 +483,11 @@ __global__ void __launch_bounds__(256) deposit_kernel(const uint32_t* __restrict
 }
 
 // Vector deposit: the three components go through the same 8-corner LDS table one after the
-// other (a third of the LDS of a 24-sum table, so twice as many blocks per CU); the first
-// particle of each bin stays in registers across the three passes.  (Reading the vector field
-// through the bins' particle ids, one component per pass, instead of gathering it into bin
-// order first, took 660 us against 432 + 104 us at 256^3: the dependent loads of every pass
-// and halo bin cost more than the gather.)
+// other (a third of the LDS of a 24-sum table, so twice as many blocks per CU); the CIC
+// weights of the first particle of each bin stay in registers across the three passes.
+// (Reading the vector field through the bins' particle ids, one component per pass, instead
+// of gathering it into bin order first, took 660 us against 432 + 104 us at 256^3: the
+// dependent loads of every pass and halo bin cost more than the gather.)
 template <int TX, int TY, int TZ>
 __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __restrict__ start,
                                                           const float4* __restrict__ spos,
@@ -479,11 +530,15 @@ __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __rest
     crowded[k] = b < T::NB && hi[k] - lo[k] > kCrowded;
     if (crowded[k]) crowd[atomicAdd(&ncrowd, 1)] = static_cast<uint16_t>(b);
   }
-  float4 p0[T::PER], v0[T::PER];
+  float w0[T::PER][3];   // CIC weights of the first particle of each bin
+  float4 v0[T::PER];
 #pragma unroll
   for (int k = 0; k < T::PER; ++k) {
     const uint32_t j = lo[k] < hi[k] ? lo[k] : 0u;
-    p0[k] = spos[j];
+    const float4 p = spos[j];
+    w0[k][0] = w1_of(p.x);
+    w0[k][1] = w1_of(p.y);
+    w0[k][2] = w1_of(p.z);
     v0[k] = sval[j];
   }
   __syncthreads();
@@ -499,14 +554,15 @@ __global__ void __launch_bounds__(256) deposit_vec_kernel(const uint32_t* __rest
       float acc[8];
 #pragma unroll
       for (int o = 0; o < 8; ++o) acc[o] = 0.0f;
-      for (uint32_t j = lo[k]; j < hi[k]; ++j) {
-        const float4 p = j == lo[k] ? p0[k] : spos[j];
-        const float4 q = j == lo[k] ? v0[k] : sval[j];
+      if (lo[k] < hi[k]) {
+        const float val = v == 0 ? v0[k].x : (v == 1 ? v0[k].y : v0[k].z);
+        add_corners(w0[k][0], w0[k][1], w0[k][2], val, acc);
+      }
+      for (uint32_t j = lo[k] + 1; j < hi[k]; ++j) {
+        const float4 p = spos[j];
+        const float4 q = sval[j];
         const float val = v == 0 ? q.x : (v == 1 ? q.y : q.z);
-        const float wx = w1_of(p.x), wy = w1_of(p.y), wz = w1_of(p.z);
-#pragma unroll
-        for (int o = 0; o < 8; ++o)
-          acc[o] += wsel(wx, o & 1) * wsel(wy, (o >> 1) & 1) * wsel(wz, o >> 2) * val;
+        add_corners(w1_of(p.x), w1_of(p.y), w1_of(p.z), val, acc);
       }
 #pragma unroll
       for (int o = 0; o < 8; ++o) W[o * T::NB + b] = acc[o];
