@@ -164,6 +164,21 @@ def mlp_comparison(torch, dhp, white, n, box, steps, warmup, samples):
         s.close()
         log(f"bench: {name} source term: forward {t_fwd * 1e3 / steps:.2f} ms/step, "
             f"fwd+bwd {t_fb * 1e3 / steps:.2f} ms/step")
+    # the same pair over the whole run a = 0.01 -> 0.29 (CFL steps, checkpoints every 16
+    # steps): the late steps have more cells where stars can form, and the closure's adjoint
+    # skips the network's backward only for groups of 32 cells where none can
+    whole = {}
+    for name, clo in (("plain", 0), ("mlp", 1)):
+        cfg = dhp.default_config(n=n, box=box, a_init=A_INIT, subgrid=2, closure=clo,
+                                 ckpt_every=16)
+        s = dhp.Sim(cfg, prm)
+        if clo:
+            s.set_closure(theta)
+        sec, k, _ = full_run(torch, s, white)
+        whole[name] = (sec, k)
+        s.close()
+        log(f"bench: {name} source term, whole run: {k} steps, forward + reverse "
+            f"{sec * 1e3 / k:.2f} ms/step")
     finals = {}
     # "nudged": the plain term with eps_sf changed by one part in a million, the distance a
     # run keeps from itself under a perturbation far below any closure's error (the flow's
@@ -205,6 +220,14 @@ def mlp_comparison(torch, dhp, white, n, box, steps, warmup, samples):
         "plain_fwd_bwd_cell_updates_per_s": rates["plain"][1],
         "fwd_time_ratio_vs_plain": rates["plain"][0] / rates["mlp"][0],
         "fwd_bwd_time_ratio_vs_plain": rates["plain"][1] / rates["mlp"][1],
+        "whole_run": {"what": f"forward + loss + reverse over a = {A_INIT} -> 0.29 with CFL "
+                              "steps, checkpoints every 16 steps",
+                      "steps_plain": whole["plain"][1], "steps_mlp": whole["mlp"][1],
+                      "plain_ms_per_step": whole["plain"][0] * 1e3 / whole["plain"][1],
+                      "mlp_ms_per_step": whole["mlp"][0] * 1e3 / whole["mlp"][1],
+                      "fwd_bwd_time_ratio_vs_plain":
+                          (whole["mlp"][0] / whole["mlp"][1]) /
+                          (whole["plain"][0] / whole["plain"][1])},
         "train": {"samples": samples, "steps": int(opts.steps), "batch": int(opts.batch),
                   "seconds": t_train, "objective_start": float(np.mean(hist[:10])),
                   "objective_end": float(np.mean(hist[-100:]))},

@@ -845,15 +845,16 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
 #pragma unroll
     for (int k = 0; k < 5; ++k) stage[wave][lane][k] = valid ? xin[k] : 0.0f;
     wave_sync();
-    // per half of 32 cells: the forward with its derivatives, dL/do of those cells (their
-    // lanes), the backward; the network runs forward once per cell
+    // per half of 32 cells: the forward, dL/do of those cells (their lanes), then, if any of
+    // them is nonzero, the forward again with its derivatives and the backward.  Where every
+    // cell of the half is screened out (dL/do = 0) the backward would return exact zeros and
+    // is skipped: its input gradients are set to zero instead.
     double le = 0.0, li = 0.0, z = 0.0;   // adjoints of the energy and of the injection
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const float (*sh)[kStage] = stage[wave] + 32 * half;
       mlp::f4 oh[2], go[2], dx[2];
-      mlp::Act<2> sd[3];
-      mlp::forward<2>(fr, bias, stage_operands<2>(sh, lane), oh, sd, nullptr, lane);
+      mlp::forward<2>(fr, bias, stage_operands<2>(sh, lane), oh, nullptr, nullptr, lane);
       if (g == 0) {
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
@@ -885,26 +886,36 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
         stage[wave][lane][5] = static_cast<float>(go0);
         stage[wave][lane][6] = static_cast<float>(go1);
       }
+      // wave-uniform: does a cell of this half have a nonzero dL/do (as stored, FP32)?
+      const bool own = (lane >> 5) == half;
+      const bool live = __any(own && (stage[wave][lane][5] != 0.0f || stage[wave][lane][6] != 0.0f));
       wave_sync();
+      if (live) {
+        mlp::Act<2> sd[3];
+        mlp::forward<2>(fr, bias, stage_operands<2>(sh, lane), oh, sd, nullptr, lane);
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        go[ct] = mlp::f4{0.0f, 0.0f, 0.0f, 0.0f};
-        if (g == 0) {
-          go[ct][0] = sh[16 * ct + cl][5];
-          go[ct][1] = sh[16 * ct + cl][6];
+        for (int ct = 0; ct < 2; ++ct) {
+          go[ct] = mlp::f4{0.0f, 0.0f, 0.0f, 0.0f};
+          if (g == 0) {
+            go[ct][0] = sh[16 * ct + cl][5];
+            go[ct][1] = sh[16 * ct + cl][6];
+          }
         }
-      }
-      mlp::backward<2>(fr, sd, go, dx, nullptr, lane);
-      wave_sync();
+        mlp::backward<2>(fr, sd, go, dx, nullptr, lane);
+        wave_sync();
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        float* cellst = stage[wave][32 * half + 16 * ct + cl];
-        if (g == 0) {
+        for (int ct = 0; ct < 2; ++ct) {
+          float* cellst = stage[wave][32 * half + 16 * ct + cl];
+          if (g == 0) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) cellst[k] = dx[ct][k];
-        } else if (g == 1) {
-          cellst[4] = dx[ct][0];
+            for (int k = 0; k < 4; ++k) cellst[k] = dx[ct][k];
+          } else if (g == 1) {
+            cellst[4] = dx[ct][0];
+          }
         }
+      } else if (own) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) stage[wave][lane][k] = 0.0f;
       }
       wave_sync();
     }
