@@ -210,22 +210,48 @@ __global__ void scatter_kernel(const uint32_t* __restrict__ key, const uint32_t*
 }
 
 // The atomics above fix each bin's size but not the order inside it; sorting each bin's ids
-// ascending makes the layout a pure function of the keys.  A thread sorts a bin of up to
-// kSmallBin ids by insertion; larger bins (dense halos gather thousands of particles in a
+// ascending makes the layout a pure function of the keys.  A thread sorts a bin of up to 8
+// ids with a sorting network in registers, of up to kSmallBin ids by insertion; larger bins (dense halos gather thousands of particles in a
 // cell) go to a list that bin_sort_large_kernel sorts one workgroup per bin.  (Moving the
 // positions along with the ids, in place of the gather pass after the sort, was slower: the
 // scattered 16-byte writes cost more than the gather's scattered reads.)
 constexpr uint32_t kSmallBin = 32;
 constexpr int kLdsSort = 16384;   // ids a workgroup sorts in LDS (64 KB)
 
+// Batcher's odd-even merge network for 8 keys (19 compare-exchanges)
+__device__ __forceinline__ void sort8(uint32_t (&v)[8]) {
+  constexpr int kNet[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6},
+                               {5, 7}, {1, 2}, {5, 6}, {0, 4}, {1, 5}, {2, 6}, {3, 7},
+                               {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    const uint32_t a = v[kNet[k][0]], b = v[kNet[k][1]];
+    v[kNet[k][0]] = min(a, b);
+    v[kNet[k][1]] = max(a, b);
+  }
+}
+
 __global__ void bin_sort_kernel(const uint32_t* __restrict__ start, uint32_t* sorted,
                                 long long nbins, uint32_t* __restrict__ large) {
   const long long b = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (b >= nbins) return;
   const uint32_t lo = start[b], hi = start[b + 1];
-  if (hi - lo > kSmallBin) {
+  const uint32_t cnt = hi - lo;
+  if (cnt > kSmallBin) {
     // large[0] counts the entries large[1..]; the list order does not affect the result
     large[1 + atomicAdd(&large[0], 1u)] = static_cast<uint32_t>(b);
+    return;
+  }
+  if (cnt < 2) return;
+  if (cnt <= 8) {
+    // independent loads, a sorting network in registers (the padding sorts last)
+    uint32_t v[8];
+#pragma unroll
+    for (uint32_t i = 0; i < 8; ++i) v[i] = i < cnt ? sorted[lo + i] : 0xFFFFFFFFu;
+    sort8(v);
+#pragma unroll
+    for (uint32_t i = 0; i < 8; ++i)
+      if (i < cnt) sorted[lo + i] = v[i];
     return;
   }
   for (uint32_t i = lo + 1; i < hi; ++i) {
