@@ -28,6 +28,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3      # MI355X published FP32 vector peak
 SWEEP_FLOPS_PER_CELL = 236           # FP32 operations of one sweep per cell (FMA = 2)
 SWEEP_BYTES_PER_CELL = 40            # read Q, write Q
 SWEEP_VJP_BYTES_PER_CELL = 60        # read Q, read lambda_out, write lambda_in
+SWEEP_VJP_KICK_BYTES_PER_CELL = 16   # the first of a step's three also reads g4 (the kick)
 # Algorithmic HBM bytes per cell (one particle per cell) of one step, recounted from the
 # kernels a step launches: every array a kernel must read or write, once.
 FWD_BYTES = [
@@ -40,7 +41,6 @@ FWD_BYTES = [
     ("gradient: phi read, g4 written", 20),
     ("closing pass: Q read and written, g4 read, star read and written", 64),
 ]
-TAPE_BYTES = 20      # the forward's copy of the kicked state for the reverse pass
 REV_BYTES = [
     ("source, closing-kick and next opening-kick adjoints", 120),
     ("gather of lambda_p into bin order", 32),
@@ -49,7 +49,7 @@ REV_BYTES = [
     ("FFT Poisson of the potential adjoint", 64),
     ("density adjoint added to lambda_rho", 12),
     ("position adjoint of kicks, deposit and drift", 80),
-    ("three sweep adjoints", 180),
+    ("three sweep adjoints (the first re-applies the opening kick: g4 read)", 196),
     ("gradient of the step's start potential", 20),
 ]
 MODEL_FWD_BYTES = 340                # the byte model the >= 50% target is stated in
@@ -472,7 +472,8 @@ def main():
         f"recomputed {t_fb_rc * 1e3:.1f} ms")
 
     # dominant kernel of the forward + reverse step: the sweep adjoint (three launches per
-    # step, about a fifth of the step), 60 algorithmic bytes per cell and launch; beside it
+    # step, about a fifth of the step), 60 algorithmic bytes per cell and launch (76 for the
+    # first, which reads g4 to re-apply the opening kick); beside it
     # the forward sweeps, 40 bytes and 236 FP32 operations per cell and launch.  Their
     # launches inside one more forward + loss + reverse pass of the same steps are timed by
     # the library with HIP events on the stream it launches them on.
@@ -488,7 +489,8 @@ def main():
     log(f"bench: in-step launches: sweep adjoint {n_vjp} x {t_vjp * 1e6:.1f} us, second/third "
         f"sweeps {n_sweep} x {t_sweep * 1e6:.1f} us, kicking first sweep {n_kick} x "
         f"{t_kick * 1e6:.1f} us")
-    vjp_bytes = SWEEP_VJP_BYTES_PER_CELL * nc
+    # mean over a step's three launches
+    vjp_bytes = (SWEEP_VJP_BYTES_PER_CELL + SWEEP_VJP_KICK_BYTES_PER_CELL / 3.0) * nc
     vjp_gbs = vjp_bytes / t_vjp / 1e9
     rec = counter_record("sweep_vjp_256_traffic.json") if n == N else None
     traffic = float(rec["traffic_bytes_per_launch"]) if rec else None
@@ -507,7 +509,7 @@ def main():
 
     fwd_b = sum(b for _, b in FWD_BYTES)
     rev_b = sum(b for _, b in REV_BYTES)
-    fb_b = fwd_b + TAPE_BYTES + rev_b
+    fb_b = fwd_b + rev_b
     rate_fwd = nc * args.steps / t_fwd
     rate_fb = nc * args.steps / t_fb
 
@@ -574,8 +576,7 @@ def main():
                         "frac_recount": frac(fb_b, rate_fb),
                         "bytes_per_cell_step_model": MODEL_FWD_BWD_BYTES,
                         "frac_model": frac(MODEL_FWD_BWD_BYTES, rate_fb)},
-            "recount": {"forward": dict(FWD_BYTES), "tape": TAPE_BYTES,
-                        "reverse": dict(REV_BYTES)}},
+            "recount": {"forward": dict(FWD_BYTES), "reverse": dict(REV_BYTES)}},
     }
     s.close()
     if not args.no_dual:

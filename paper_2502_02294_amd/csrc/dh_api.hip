@@ -55,9 +55,10 @@ struct StepPlan {    // one global step of all samples
 const int kStrang[6][3] = {{0, 1, 2}, {2, 1, 0}, {2, 0, 1}, {1, 0, 2}, {1, 2, 0}, {0, 2, 1}};
 
 struct TapeStep {
-  float* q[6];      // Q0 start, Q1 after opening kick (sweep-1 input), Q2, Q3 sweep inputs,
-                    // Q4 after sweeps, Q5 after closing kick (source input; kept only for
-                    // the learned closure, the plain source's adjoint recomputes it)
+  float* q[6];      // Q0 start, Q1 not stored (the sweep-1 input, Q0 after the opening gas
+                    // kick, which the first sweep's adjoint applies again), Q2, Q3 sweep
+                    // inputs, Q4 after sweeps, Q5 after closing kick (source input; kept only
+                    // for the learned closure, the plain source's adjoint recomputes it)
   float* x0;                  // particle positions at the start
   const float* x1;            // after the drift: not stored (the positions do not change
                               // after the drift, so x1 is the next step's x0, or the state's
@@ -461,7 +462,7 @@ long long store_step_bytes(const dh_sim* s) {
 long long reverse_pass_bytes(const dh_sim* s) {
   const long long S = s->S, nc = s->nc * S, np = s->np * S;
   const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
-  const long long entry = (closure ? 6 : 5) * s->nq * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 +
+  const long long entry = (closure ? 5 : 4) * s->nq * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 +
                           np * 4 + np * 16;
   long long need = 0;
   const long long k = s->cfg.ckpt_every;
@@ -475,7 +476,7 @@ long long reverse_pass_bytes(const dh_sim* s) {
 long long tape_entry_bytes(const dh_sim* s) {
   const long long S = s->S, nc = s->nc * S, np = s->np * S;
   const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
-  return (closure ? 6 : 5) * s->nq * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 + np * 4 +
+  return (closure ? 5 : 4) * s->nq * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 + np * 4 +
          np * 16;
 }
 
@@ -648,14 +649,14 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
   }
   const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
   if (tp) {
-    // the sweeps (the first one also applies the opening gas kick and keeps the kicked state
-    // in Q1) and the closing pass write their results straight into the tape
+    // the sweeps (the first one also applies the opening gas kick) and the closing pass write
+    // their results straight into the tape
     const bool kept = recompute && store_k >= 0 && store_k < s->store_valid;
     dh::launch_kick_drift(s->st, s->g4, pos_in, s->pos, s->mom, s->bins.key, nullptr, nullptr,
                           prev, b, kept ? nullptr : &s->bins);
     {
       KernelTimer kt(s, DH_KTIME_SWEEP_KICK);
-      dh::launch_sweep(s->st, tp->q[0], tp->q[2], b, sp.axes[0], s->g4, tp->q[1]);
+      dh::launch_sweep(s->st, tp->q[0], tp->q[2], b, sp.axes[0], s->g4);
     }
     for (int k = 1; k < 3; ++k) {
       KernelTimer kt(s, DH_KTIME_SWEEP);
@@ -1054,7 +1055,7 @@ void alloc_tape_entry(dh_sim* s, TapeStep& t) {
   const long long S = s->S;
   const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
   for (int k = 0; k < 6; ++k)
-    t.q[k] = k < 5 || closure ? s->alloc<float>(s->nq * s->nc * S) : nullptr;
+    t.q[k] = k != 1 && (k < 5 || closure) ? s->alloc<float>(s->nq * s->nc * S) : nullptr;
   t.x0 = s->alloc<float>(3 * s->np * S);
   t.x1 = nullptr;
   t.phi0 = s->alloc<float>(s->nc * S);
@@ -1231,17 +1232,21 @@ void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
   // x1 = x0 + p_half dt / a_h^2: lambda_p += (dt / a_h^2) lambda_x
   dh::launch_deposit_vjp_pos(st, s->ldelta, T.x1, static_cast<float>(s->m_dm), s->lx, s->lp,
                              s->g4b, b);
+  // g_n from phi_n: the first sweep's input is Q0 after the opening gas kick with it
+  dh::launch_grad(st, T.phi0, s->g4b, b);
+  s->g4b_phi0_of = all ? sp.step : -1;
   // sweeps in reverse
   for (int k = 2; k >= 0; --k) {
     {
       KernelTimer kt(s, DH_KTIME_SWEEP_VJP);
-      dh::launch_sweep_vjp(st, T.q[1 + k], s->lq, s->lq2, b, sp.axes[k]);
+      if (k > 0)
+        dh::launch_sweep_vjp(st, T.q[1 + k], s->lq, s->lq2, b, sp.axes[k]);
+      else
+        dh::launch_sweep_vjp(st, T.q[0], s->lq, s->lq2, b, sp.axes[0], s->g4b);
     }
     std::swap(s->lq, s->lq2);
   }
-  // opening gas kick with phi_n
-  dh::launch_grad(st, T.phi0, s->g4b, b);
-  s->g4b_phi0_of = all ? sp.step : -1;
+  // opening gas kick with g_n
   if (defer_open && all && !closure) {
     s->open_pending = true;
     s->open_q0 = T.q[0];

@@ -53,12 +53,13 @@ __device__ __forceinline__ bool sample_active(const StepScal* tab, int smp) {
 
 // ---- hydro (k_hydro.hip): one sweep with dt, h1, h2 of the table (tab required)
 // With g4 (the first sweep of a step): the opening gas half kick (the table's h) is applied
-// to each cell as it is loaded, and with `kicked` the kicked state is also stored there.
+// to each cell as it is loaded.
 void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis,
-                  const float4* g4 = nullptr, float* kicked = nullptr);
-// adjoint of one sweep: lam_in = (dU'/dU)^T lam_out at U = qin (not in place)
+                  const float4* g4 = nullptr);
+// adjoint of one sweep: lam_in = (dU'/dU)^T lam_out at U = qin (not in place); with g4 (the
+// first sweep of a step) U is qin after the opening gas half kick, applied again on load
 void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
-                      const Batch& b, int axis);
+                      const Batch& b, int axis, const float4* g4 = nullptr);
 
 // ---- particle mesh (k_pm.hip)
 // Keys are global bins: sample * n^3 + CIC base cell, so one counting sort orders the

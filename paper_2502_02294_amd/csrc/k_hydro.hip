@@ -65,14 +65,14 @@ __device__ __forceinline__ void face_l_coef(float f0, float fp1, float fp2, floa
 // ------------------------------------------------------------------------------- forward x
 // Whole rows in LDS, one cell per thread; the limited stage-2 flux is formed once per face.
 // KICK (the first sweep of a step): the opening gas half kick with g4 and the table's h is
-// applied to each cell as it is loaded, and the kicked state goes to `kicked` if given.
+// applied to each cell as it is loaded (the reverse pass applies it again, so the kicked state
+// is not stored).
 template <bool KICK, int NQ>
 __global__ void __launch_bounds__(kRowThreads) sweep_x_kernel(const float* __restrict__ qin,
                                                               float* __restrict__ qout, int n,
                                                               long long nc,
                                                               const StepScal* __restrict__ tab,
-                                                              const float4* __restrict__ g4,
-                                                              float* __restrict__ kicked) {
+                                                              const float4* __restrict__ g4) {
   __shared__ float FR[NQ][kRowCells];
   __shared__ float FL[NQ][kRowCells];
   const long long base = static_cast<long long>(blockIdx.x) * kRowCells;
@@ -99,10 +99,6 @@ __global__ void __launch_bounds__(kRowThreads) sweep_x_kernel(const float* __res
     u[1] = m[0];
     u[2] = m[1];
     u[3] = m[2];
-    if (kicked) {
-#pragma unroll
-      for (int c = 0; c < NQ; ++c) kicked[(blockIdx.y * NQ + c) * nc + base + j] = u[c];
-    }
   }
   split_flux<0, NQ>(u, h1, fr, fl);
 #pragma unroll
@@ -149,6 +145,18 @@ __global__ void __launch_bounds__(kRowThreads) sweep_x_kernel(const float* __res
 // of a sample are 32-bit (at most 256^3 floats).
 constexpr int kAhead = 4;   // cells loaded ahead of the one being split
 
+// The opening gas kick applied to a loaded state in place (the first sweep of a step).  The
+// walks load g two (forward) or one (adjoint) visits before a cell is first used and kick it
+// then: kicking on load would make a visit wait for the loads of the cells ahead.
+template <int NQ>
+__device__ __forceinline__ void kick_loaded(float (&u)[NQ], const float (&g)[3], float h) {
+  float m[3] = {u[1], u[2], u[3]};
+  kick_cell(u[0], make_float4(g[0], g[1], g[2], 0.0f), h, m, u[4]);
+  u[1] = m[0];
+  u[2] = m[1];
+  u[3] = m[2];
+}
+
 template <int D, int NQ>
 struct WalkFwd {
   float u[8][NQ];             // U of cell k - j in slot (i - j) & 7 (j = -kAhead .. 3)
@@ -158,6 +166,7 @@ struct WalkFwd {
   float f2[2][NQ];            // limited stage-2 face (k - 3 - j) + 1/2 in slot (i - j) & 1
   float dr[2][NQ], dl[2][NQ];  // upper slopes of face (k - 3 - j) + 1/2 in slot (i - j) & 1: the
                              // lower slopes of the next face
+  float g[4][3];              // first sweep: g of cell k + 2 - j in slot (i + 2 - j) & 3
 };
 
 template <int NQ>
@@ -166,10 +175,8 @@ struct WalkPtr {
   float* __restrict__ o[NQ];
   unsigned base, stride;   // in bytes
   int n;
-  // opening gas kick on load (first sweep of a step): g of the sample's cells, the half kick,
-  // and where the kicked state goes
+  // opening gas kick on load (first sweep of a step): g of the sample's cells, the half kick
   const char* g4;
-  float* k[NQ];
   float h;
   // byte offset of cell k of the column (periodic)
   __device__ __forceinline__ unsigned at(int k) const {
@@ -183,40 +190,37 @@ struct WalkPtr {
   }
 };
 
-// U of cell kk of the column into u, with the opening kick when KICK; KEEP stores the kicked
-// state of every cell the walk loads: a halo cell is also loaded, and stored with the same
-// value, by the walk of the neighbouring segment.  (A store limited to the segment's own
-// cells needs a branch, which splits the visit's code and changes how the compiler fuses the
-// sweep's multiply-adds.)
-template <bool KICK, bool KEEP, int NQ>
+// U of cell kk of the column into u
+template <int NQ>
 __device__ __forceinline__ void walk_load(const WalkPtr<NQ>& p, int kk, float (&u)[NQ]) {
   const unsigned off = p.at(kk);
 #pragma unroll
   for (int c = 0; c < NQ; ++c) u[c] = p.ld(c, off);
-  if (KICK) {
-    // the float4 of cell i is at byte 16 i, i.e. 4 times the byte offset of its float
-    const float4 g = *reinterpret_cast<const float4*>(p.g4 + 4ull * off);
-    float m[3] = {u[1], u[2], u[3]};
-    kick_cell(u[0], g, p.h, m, u[4]);
-    u[1] = m[0];
-    u[2] = m[1];
-    u[3] = m[2];
-    if (KEEP) {
-#pragma unroll
-      for (int c = 0; c < NQ; ++c)
-        *reinterpret_cast<float*>(reinterpret_cast<char*>(p.k[c]) + off) = u[c];
-    }
-  }
 }
 
-template <int D, int I, int STAGE, bool KICK, bool KEEP, int NQ>
+// g of cell kk of the column (the float4 of cell i is at byte 16 i, i.e. 4 times the byte
+// offset of its float)
+template <int NQ>
+__device__ __forceinline__ void walk_load_g(const WalkPtr<NQ>& p, int kk, float (&g)[3]) {
+  const float4 v = *reinterpret_cast<const float4*>(p.g4 + 4ull * p.at(kk));
+  g[0] = v.x;
+  g[1] = v.y;
+  g[2] = v.z;
+}
+
+template <int D, int I, int STAGE, bool KICK, int NQ>
 __device__ __forceinline__ void walk_fwd_visit(WalkFwd<D, NQ>& w, const WalkPtr<NQ>& p, int k,
                                                const HydroK& h1, const HydroK& h2, float dt,
                                                float hdt) {
   constexpr int s0 = I & 7, s1 = (I + 7) & 7, s3 = (I + 5) & 7, sa = (I + kAhead) & 7;
   constexpr int t0 = I & 3, t1 = (I + 3) & 3, t2 = (I + 2) & 3, t3 = (I + 1) & 3;
   constexpr int p0 = I & 1, p1 = (I + 1) & 1;
-  walk_load<KICK, KEEP, NQ>(p, k + kAhead, w.u[sa]);
+  walk_load<NQ>(p, k + kAhead, w.u[sa]);
+  if (KICK) {
+    // g two visits ahead; cell k, first used now, takes the opening kick
+    walk_load_g<NQ>(p, k + 2, w.g[(I + 2) & 3]);
+    kick_loaded(w.u[s0], w.g[I & 3], p.h);
+  }
   float l1[NQ];
   split_flux<D, NQ>(w.u[s0], h1, w.r1[p0], l1);
   if (STAGE < 1) return;
@@ -247,13 +251,12 @@ __device__ __forceinline__ void walk_fwd_visit(WalkFwd<D, NQ>& w, const WalkPtr<
   for (int c = 0; c < NQ; ++c) p.st(c, off, w.u[s3][c] - dt * (w.f2[p0][c] - w.f2[p1][c]));
 }
 
-template <int D, bool KICK, bool KEEP, int NQ>
+template <int D, bool KICK, int NQ>
 __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict__ qin,
                                                          float* __restrict__ qout, int n,
                                                          long long nc, int seg_len, int nseg,
                                                          const StepScal* __restrict__ tab,
-                                                         const float4* __restrict__ g4,
-                                                         float* __restrict__ kicked) {
+                                                         const float4* __restrict__ g4) {
   const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<long long>(n) * n * nseg) return;
   const int x = static_cast<int>(t % n);
@@ -270,7 +273,6 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
   for (int c = 0; c < NQ; ++c) {
     p.q[c] = qin + (blockIdx.y * NQ + c) * nc;
     p.o[c] = qout + (blockIdx.y * NQ + c) * nc;
-    p.k[c] = KEEP ? kicked + (blockIdx.y * NQ + c) * nc : nullptr;
   }
   p.g4 = KICK ? reinterpret_cast<const char*>(g4 + blockIdx.y * nc) : nullptr;
   p.h = sc.h;
@@ -287,24 +289,28 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
   const float hdt = 0.5f * dt;
   WalkFwd<D, NQ> w;
 #pragma unroll
-  for (int j = 0; j < kAhead; ++j) walk_load<KICK, KEEP, NQ>(p, s - 3 + j, w.u[j]);
+  for (int j = 0; j < kAhead; ++j) walk_load<NQ>(p, s - 3 + j, w.u[j]);
+  if (KICK) {
+    walk_load_g<NQ>(p, s - 3, w.g[0]);
+    walk_load_g<NQ>(p, s - 2, w.g[1]);
+  }
   // visits 0..5 fill the pipeline; from visit 6 on every visit writes a cell
-  walk_fwd_visit<D, 0, 0, KICK, KEEP, NQ>(w, p, s - 3, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 1, 1, KICK, KEEP, NQ>(w, p, s - 2, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 2, 2, KICK, KEEP, NQ>(w, p, s - 1, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 3, 2, KICK, KEEP, NQ>(w, p, s, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 4, 2, KICK, KEEP, NQ>(w, p, s + 1, h1, h2, dt, hdt);
-  walk_fwd_visit<D, 5, 3, KICK, KEEP, NQ>(w, p, s + 2, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 0, 0, KICK, NQ>(w, p, s - 3, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 1, 1, KICK, NQ>(w, p, s - 2, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 2, 2, KICK, NQ>(w, p, s - 1, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 3, 2, KICK, NQ>(w, p, s, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 4, 2, KICK, NQ>(w, p, s + 1, h1, h2, dt, hdt);
+  walk_fwd_visit<D, 5, 3, KICK, NQ>(w, p, s + 2, h1, h2, dt, hdt);
   // seg_len is a multiple of 8: visits 6 + 8m .. 13 + 8m have ring phases 6, 7, 0, .., 5
   for (int k = s + 3; k < s + 3 + seg_len; k += 8) {
-    walk_fwd_visit<D, 6, 4, KICK, KEEP, NQ>(w, p, k, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 7, 4, KICK, KEEP, NQ>(w, p, k + 1, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 0, 4, KICK, KEEP, NQ>(w, p, k + 2, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 1, 4, KICK, KEEP, NQ>(w, p, k + 3, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 2, 4, KICK, KEEP, NQ>(w, p, k + 4, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 3, 4, KICK, KEEP, NQ>(w, p, k + 5, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 4, 4, KICK, KEEP, NQ>(w, p, k + 6, h1, h2, dt, hdt);
-    walk_fwd_visit<D, 5, 4, KICK, KEEP, NQ>(w, p, k + 7, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 6, 4, KICK, NQ>(w, p, k, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 7, 4, KICK, NQ>(w, p, k + 1, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 0, 4, KICK, NQ>(w, p, k + 2, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 1, 4, KICK, NQ>(w, p, k + 3, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 2, 4, KICK, NQ>(w, p, k + 4, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 3, 4, KICK, NQ>(w, p, k + 5, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 4, 4, KICK, NQ>(w, p, k + 6, h1, h2, dt, hdt);
+    walk_fwd_visit<D, 5, 4, KICK, NQ>(w, p, k + 7, h1, h2, dt, hdt);
   }
 }
 
@@ -318,10 +324,12 @@ __global__ void __launch_bounds__(256) sweep_walk_kernel(const float* __restrict
 //   4. lambda_h = split VJP at Uh of the gathered adjoints.
 //   5. stage-1 transpose: lambda = lambda' + lambda_h + split VJP at U of (G1_j, -G1_{j-1}),
 //      G1_m = -dt/2 (lambda_h_m - lambda_h_{m+1}).
-template <int NQ>
+// KICK: the adjoint of the first sweep of a step; qin is the state before the opening gas
+// kick, which the load applies again (as the forward sweep did).
+template <bool KICK, int NQ>
 __global__ void __launch_bounds__(kRowThreads) sweep_x_vjp_kernel(
     const float* __restrict__ qin, const float* __restrict__ lam_out, float* __restrict__ lam_in,
-    int n, long long nc, const StepScal* __restrict__ tab) {
+    int n, long long nc, const StepScal* __restrict__ tab, const float4* __restrict__ g4) {
   __shared__ float S[5][NQ][kRowCells];
   const long long base = static_cast<long long>(blockIdx.x) * kRowCells;
   const int j = threadIdx.x;
@@ -346,6 +354,13 @@ __global__ void __launch_bounds__(kRowThreads) sweep_x_vjp_kernel(
     for (int c = 0; c < NQ; ++c) {
       u[c] = qin[c * nc + base + j];
       lm[c] = lam_out[c * nc + base + j];
+    }
+    if (KICK) {
+      float m[3] = {u[1], u[2], u[3]};
+      kick_cell(u[0], g4[blockIdx.y * nc + base + j], sc.h, m, u[4]);
+      u[1] = m[0];
+      u[2] = m[1];
+      u[3] = m[2];
     }
     split_flux<0, NQ>(u, h1, fr, fl);
 #pragma unroll
@@ -446,6 +461,7 @@ struct WalkVjp {
   float gr[4][NQ], gl[4][NQ];  // adjoints of F^R, F^L of cell k - 1 - j in slot (i - j) & 3
   float lh[2][NQ];            // lambda_h of cell k - 3 - j in slot (i - j) & 1
   float g1[2][NQ];            // G1 of face (k - 4 - j) + 1/2 in slot (i - j) & 1
+  float g[2][3];              // first sweep: g of cell k + 1 - j in slot (i + 1 - j) & 1
 };
 
 // Returns x unchanged through an empty asm statement, so that the compiler cannot reuse
@@ -462,6 +478,10 @@ struct WalkVjpPtr {
   float* __restrict__ o[NQ];
   unsigned base, stride;   // in bytes
   int n;
+  // adjoint of the first sweep of a step: q is the state before the opening gas kick, which
+  // every load applies again (g of the sample's cells, the half kick)
+  const char* g4;
+  float h;
   __device__ __forceinline__ unsigned at(int k) const {
     return base + static_cast<unsigned>(k & (n - 1)) * stride;
   }
@@ -471,11 +491,19 @@ struct WalkVjpPtr {
   __device__ __forceinline__ void st(int c, unsigned off, float v) const {
     *reinterpret_cast<float*>(reinterpret_cast<char*>(o[c]) + off) = v;
   }
+  // g of the cell at byte offset off (its float4 is at byte 16 off / 4)
+  __device__ __forceinline__ void load_g(unsigned off, float (&g)[3]) const {
+    const float4 v = *reinterpret_cast<const float4*>(g4 + 4ull * off);
+    g[0] = v.x;
+    g[1] = v.y;
+    g[2] = v.z;
+  }
 };
+
 
 // STAGE: 0 split only, 1 + F1, 2 + half step and stage-2 split, 3 + first faces (every
 // adjoint assigned), 4 + faces, 5 + lambda_h, 6 + G1, 7 + output
-template <int D, int I, int STAGE, int NQ>
+template <int D, int I, int STAGE, bool KICK, int NQ>
 __device__ __forceinline__ void walk_vjp_visit(WalkVjp<NQ>& w, const WalkVjpPtr<NQ>& p, int k,
                                                const HydroK& h1, const HydroK& h2, float dt,
                                                float hdt) {
@@ -493,7 +521,9 @@ __device__ __forceinline__ void walk_vjp_visit(WalkVjp<NQ>& w, const WalkVjpPtr<
       w.u[ua][c] = WalkVjpPtr<NQ>::ld(p.q[c], offu);
       w.lm[la][c] = WalkVjpPtr<NQ>::ld(p.l[c], offl);
     }
+    if (KICK) p.load_g(p.at(k + 1), w.g[(I + 1) & 1]);
   }
+  if (KICK) kick_loaded(w.u[u0], w.g[I & 1], p.h);
   float l1[NQ];
   split_flux<D, NQ>(w.u[u0], h1, w.r1[p0], l1);
   if (STAGE < 1) return;
@@ -557,12 +587,13 @@ __device__ __forceinline__ void walk_vjp_visit(WalkVjp<NQ>& w, const WalkVjpPtr<
   }
 }
 
-template <int D, int NQ>
+template <int D, bool KICK, int NQ>
 __global__ void __launch_bounds__(256) sweep_walk_vjp_kernel(const float* __restrict__ qin,
                                                              const float* __restrict__ lam_out,
                                                              float* __restrict__ lam_in, int n,
                                                              long long nc, int seg_len, int nseg,
-                                                             const StepScal* __restrict__ tab) {
+                                                             const StepScal* __restrict__ tab,
+                                                             const float4* __restrict__ g4) {
   const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= static_cast<long long>(n) * n * nseg) return;
   const int x = static_cast<int>(t % n);
@@ -581,6 +612,8 @@ __global__ void __launch_bounds__(256) sweep_walk_vjp_kernel(const float* __rest
     p.l[c] = lam_out + (blockIdx.y * NQ + c) * nc;
     p.o[c] = lam_in + (blockIdx.y * NQ + c) * nc;
   }
+  p.g4 = KICK ? reinterpret_cast<const char*>(g4 + blockIdx.y * nc) : nullptr;
+  p.h = sc.h;
   if (!sc.active) {
     for (int i = 0; i < seg_len; ++i) {
       const unsigned off = p.at(s + i);
@@ -599,30 +632,31 @@ __global__ void __launch_bounds__(256) sweep_walk_vjp_kernel(const float* __rest
 #pragma unroll
     for (int c = 0; c < NQ; ++c) w.u[j][c] = WalkVjpPtr<NQ>::ld(p.q[c], off);
   }
+  if (KICK) p.load_g(p.at(s - 4), w.g[0]);
 #pragma unroll
   for (int j = 0; j < kAheadL; ++j) {
     const unsigned off = p.at(s - 4 + j);
 #pragma unroll
     for (int c = 0; c < NQ; ++c) w.lm[j][c] = WalkVjpPtr<NQ>::ld(p.l[c], off);
   }
-  walk_vjp_visit<D, 0, 0, NQ>(w, p, s - 4, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 1, 1, NQ>(w, p, s - 3, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 2, 2, NQ>(w, p, s - 2, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 3, 2, NQ>(w, p, s - 1, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 4, 3, NQ>(w, p, s, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 5, 4, NQ>(w, p, s + 1, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 6, 5, NQ>(w, p, s + 2, h1, h2, dt, hdt);
-  walk_vjp_visit<D, 7, 6, NQ>(w, p, s + 3, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 0, 0, KICK, NQ>(w, p, s - 4, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 1, 1, KICK, NQ>(w, p, s - 3, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 2, 2, KICK, NQ>(w, p, s - 2, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 3, 2, KICK, NQ>(w, p, s - 1, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 4, 3, KICK, NQ>(w, p, s, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 5, 4, KICK, NQ>(w, p, s + 1, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 6, 5, KICK, NQ>(w, p, s + 2, h1, h2, dt, hdt);
+  walk_vjp_visit<D, 7, 6, KICK, NQ>(w, p, s + 3, h1, h2, dt, hdt);
   // seg_len is a multiple of 8: visits 8 + 8m .. 15 + 8m have ring phases 0 .. 7
   for (int k = s + 4; k < s + 4 + seg_len; k += 8) {
-    walk_vjp_visit<D, 0, 7, NQ>(w, p, k, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 1, 7, NQ>(w, p, k + 1, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 2, 7, NQ>(w, p, k + 2, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 3, 7, NQ>(w, p, k + 3, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 4, 7, NQ>(w, p, k + 4, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 5, 7, NQ>(w, p, k + 5, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 6, 7, NQ>(w, p, k + 6, h1, h2, dt, hdt);
-    walk_vjp_visit<D, 7, 7, NQ>(w, p, k + 7, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 0, 7, KICK, NQ>(w, p, k, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 1, 7, KICK, NQ>(w, p, k + 1, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 2, 7, KICK, NQ>(w, p, k + 2, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 3, 7, KICK, NQ>(w, p, k + 3, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 4, 7, KICK, NQ>(w, p, k + 4, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 5, 7, KICK, NQ>(w, p, k + 5, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 6, 7, KICK, NQ>(w, p, k + 6, h1, h2, dt, hdt);
+    walk_vjp_visit<D, 7, 7, KICK, NQ>(w, p, k + 7, h1, h2, dt, hdt);
   }
 }
 
@@ -634,33 +668,31 @@ namespace {
 
 template <int NQ>
 void sweep_nq(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis,
-              const float4* g4, float* kicked) {
+              const float4* g4) {
   const int n = b.n;
   const long long nc = b.nc();
   if (axis == 0) {
     const dim3 grid(static_cast<unsigned>(nc / kRowCells), b.S);
     if (g4)
       hipLaunchKernelGGL((sweep_x_kernel<true, NQ>), grid, dim3(kRowThreads), 0, st, qin, qout, n,
-                         nc, b.tab, g4, kicked);
+                         nc, b.tab, g4);
     else
       hipLaunchKernelGGL((sweep_x_kernel<false, NQ>), grid, dim3(kRowThreads), 0, st, qin, qout,
-                         n, nc, b.tab, nullptr, nullptr);
+                         n, nc, b.tab, nullptr);
   } else {
     const int seg = pick_segment(n);
     const int nseg = n / seg;
     const long long threads = static_cast<long long>(n) * n * nseg;
     const dim3 grid(blocks_for(threads, 256), b.S);
-#define DH_WALK(D, KICK, KEEP)                                                               \
-  hipLaunchKernelGGL((sweep_walk_kernel<D, KICK, KEEP, NQ>), grid, dim3(256), 0, st, qin, qout, \
-                     n, nc, seg, nseg, b.tab, g4, kicked)
+#define DH_WALK(D, KICK)                                                                     \
+  hipLaunchKernelGGL((sweep_walk_kernel<D, KICK, NQ>), grid, dim3(256), 0, st, qin, qout, n, nc, \
+                     seg, nseg, b.tab, g4)
     if (axis == 1) {
-      if (kicked) DH_WALK(1, true, true);
-      else if (g4) DH_WALK(1, true, false);
-      else DH_WALK(1, false, false);
+      if (g4) DH_WALK(1, true);
+      else DH_WALK(1, false);
     } else {
-      if (kicked) DH_WALK(2, true, true);
-      else if (g4) DH_WALK(2, true, false);
-      else DH_WALK(2, false, false);
+      if (g4) DH_WALK(2, true);
+      else DH_WALK(2, false);
     }
 #undef DH_WALK
   }
@@ -668,49 +700,57 @@ void sweep_nq(hipStream_t st, const float* qin, float* qout, const Batch& b, int
 
 template <int NQ>
 void sweep_vjp_nq(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
-                  const Batch& b, int axis) {
+                  const Batch& b, int axis, const float4* g4) {
   const int n = b.n;
   const long long nc = b.nc();
   if (axis == 0) {
-    hipLaunchKernelGGL((sweep_x_vjp_kernel<NQ>), dim3(static_cast<unsigned>(nc / kRowCells), b.S),
-                       dim3(kRowThreads), 0, st, qin, lam_out, lam_in, n, nc, b.tab);
+    const dim3 grid(static_cast<unsigned>(nc / kRowCells), b.S);
+    if (g4)
+      hipLaunchKernelGGL((sweep_x_vjp_kernel<true, NQ>), grid, dim3(kRowThreads), 0, st, qin,
+                         lam_out, lam_in, n, nc, b.tab, g4);
+    else
+      hipLaunchKernelGGL((sweep_x_vjp_kernel<false, NQ>), grid, dim3(kRowThreads), 0, st, qin,
+                         lam_out, lam_in, n, nc, b.tab, nullptr);
   } else {
     const int seg = pick_segment(n);
     const int nseg = n / seg;
     const long long threads = static_cast<long long>(n) * n * nseg;
     const dim3 grid(blocks_for(threads, 256), b.S);
-    if (axis == 1)
-      hipLaunchKernelGGL((sweep_walk_vjp_kernel<1, NQ>), grid, dim3(256), 0, st, qin, lam_out,
-                         lam_in, n, nc, seg, nseg, b.tab);
-    else
-      hipLaunchKernelGGL((sweep_walk_vjp_kernel<2, NQ>), grid, dim3(256), 0, st, qin, lam_out,
-                         lam_in, n, nc, seg, nseg, b.tab);
+#define DH_WALK_VJP(D, KICK)                                                                  \
+  hipLaunchKernelGGL((sweep_walk_vjp_kernel<D, KICK, NQ>), grid, dim3(256), 0, st, qin, lam_out, \
+                     lam_in, n, nc, seg, nseg, b.tab, g4)
+    if (axis == 1) {
+      if (g4) DH_WALK_VJP(1, true);
+      else DH_WALK_VJP(1, false);
+    } else {
+      if (g4) DH_WALK_VJP(2, true);
+      else DH_WALK_VJP(2, false);
+    }
+#undef DH_WALK_VJP
   }
 }
 
 }  // namespace
 
 void launch_sweep(hipStream_t st, const float* qin, float* qout, const Batch& b, int axis,
-                  const float4* g4, float* kicked) {
+                  const float4* g4) {
   if (!b.tab) throw ArgError("sweep: step table required");
-  if (kicked && !g4) throw ArgError("sweep: the kicked state needs the kick's field");
-  if (kicked && (kicked == qin || kicked == qout)) throw ArgError("sweep: kicked state aliases");
   if (axis == 0 && qin == qout) throw ArgError("sweep_x: in-place not supported");
   if (b.nq == 6)
-    sweep_nq<6>(st, qin, qout, b, axis, g4, kicked);
+    sweep_nq<6>(st, qin, qout, b, axis, g4);
   else
-    sweep_nq<5>(st, qin, qout, b, axis, g4, kicked);
+    sweep_nq<5>(st, qin, qout, b, axis, g4);
   DH_LAUNCH_CHECK();
 }
 
 void launch_sweep_vjp(hipStream_t st, const float* qin, const float* lam_out, float* lam_in,
-                      const Batch& b, int axis) {
+                      const Batch& b, int axis, const float4* g4) {
   if (!b.tab) throw ArgError("sweep adjoint: step table required");
   if (qin == lam_in || lam_out == lam_in) throw ArgError("sweep adjoint: in-place not supported");
   if (b.nq == 6)
-    sweep_vjp_nq<6>(st, qin, lam_out, lam_in, b, axis);
+    sweep_vjp_nq<6>(st, qin, lam_out, lam_in, b, axis, g4);
   else
-    sweep_vjp_nq<5>(st, qin, lam_out, lam_in, b, axis);
+    sweep_vjp_nq<5>(st, qin, lam_out, lam_in, b, axis, g4);
   DH_LAUNCH_CHECK();
 }
 
