@@ -850,6 +850,7 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
     // cell of the half is screened out (dL/do = 0) the backward would return exact zeros and
     // is skipped: its input gradients are set to zero instead.
     double le = 0.0, li = 0.0, z = 0.0;   // adjoints of the energy and of the injection
+    bool loaded = false;                   // le and li read
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const float (*sh)[kStage] = stage[wave] + 32 * half;
@@ -870,9 +871,10 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
           const float o0 = stage[wave][lane][5], o1 = stage[wave][lane][6];
           const float lg = closure_logit_estimate(o0, o1, a);
           const double u = screened_out(lg, kMaxLogitU, a) ? 0.5 : starform_uniform(c, a);
-          le = lam[4 * nc + c];
-          li = lam_inj ? lam_inj[c] : le;
           if (!screened_out(lg, kMaxLogitU, a) && !screened_out(lg, logit_u_of(u), a)) {
+            le = lam[4 * nc + c];
+            li = lam_inj ? lam_inj[c] : le;
+            loaded = true;
             const ClosureDraw d = closure_draw(o0, o1, u, a);
             z = d.z;
             if (a.mode != 1 && li != 0.0) {
@@ -919,10 +921,15 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
       }
       wave_sync();
     }
-    if (valid) {
+    const double gx0 = stage[wave][lane][0], gx1 = stage[wave][lane][1];
+    // a cell with no draw (z = 0, so dL/do = 0) and no input gradient keeps its adjoint
+    if (valid && (z != 0.0 || gx0 != 0.0 || gx1 != 0.0)) {
+      if (!loaded) {
+        le = lam[4 * nc + c];
+        li = lam_inj ? lam_inj[c] : le;
+      }
       // Et' = Et + K rho z; inputs x0 = (ln Delta - 4.6)/5, x1 = (ln T - 10.4)/5 with T ~ e
       const double rho = q5[0];
-      const double gx0 = stage[wave][lane][0], gx1 = stage[wave][lane][1];
       const double ir = 1.0 / rho, ia = 1.0 / a.a;
       double u[3];
 #pragma unroll
@@ -934,6 +941,8 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
       for (int d = 0; d < 3; ++d)
         lam[(1 + d) * nc + c] = static_cast<float>(lam[(1 + d) * nc + c] + ge * (-u[d] * ia * ir));
       lam[4 * nc + c] = static_cast<float>(le + ge * (ia * ia * ir));
+    }
+    if (valid) {
       acc[0] += stage[wave][lane][3] / 0.02;
       acc[1] += stage[wave][lane][4] / 100.0;
     }
