@@ -264,10 +264,11 @@ __device__ __forceinline__ void van_leer_half_d(float a, float b, float& da, flo
   const float s = a + b;
   const float id = rcp_approx(s + __builtin_copysignf(2.0f * kLimEps, s));
   const float hb = b * id, ha = a * id;
-  const float pa = hb * hb, pb = ha * ha;
-  const float za = ab < 0.0f ? 0.0f : 0.5f * hb, zb = ab < 0.0f ? 0.0f : 0.5f * ha;
-  da = ab > 0.0f ? pa : za;
-  db = ab > 0.0f ? pb : zb;
+  // da = hb * (hb, 1/2 or 0 as a b > 0, = 0 or < 0), db likewise with ha: one product each
+  // (a zero may come out as -0)
+  const float k = ab < 0.0f ? 0.0f : 0.5f;
+  da = hb * (ab > 0.0f ? hb : k);
+  db = ha * (ab > 0.0f ? ha : k);
 }
 
 // ---------------------------------------------------------------------------------------
