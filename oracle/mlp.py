@@ -178,14 +178,17 @@ def closure_inputs(q, a, *, rho_mean_gas, gamma, e_floor, t_per_e, eps_sf, delta
 
 
 def apply_with_outputs(q, star, a, dt, u, o, *, e0_code, tau, mode, with_draw=False,
-                       smooth=False):
+                       smooth=False, gamma=None):
     """Source update of Sec. 2.4 with pi0 taken from network outputs o (returns Q, star, and
-    the draw z with_draw); smooth: the supernova energy spread as subgrid.smooth_injection."""
+    the draw z with_draw); smooth: the supernova energy spread as subgrid.smooth_injection.
+    A six-component (dual-energy) state also takes the injected energy into its entropy, as
+    the plain source term does (subgrid.apply_source)."""
     pi0 = probability(o, dt)
     z = subgrid.draw(pi0, u, tau, mode)
     inj = a * a * q[0] * z * e0_code
-    e_new = q[4] + (subgrid.smooth_injection(inj) if smooth else inj)
-    out = (torch.cat([q[:4], e_new[None]]), star + z)
+    add = subgrid.smooth_injection(inj) if smooth else inj
+    extra = [q[5] + add * q[0] ** (1.0 - gamma)] if q.shape[0] > 5 else []
+    out = (torch.stack([q[0], q[1], q[2], q[3], q[4] + add] + extra), star + z)
     return out + (z,) if with_draw else out
 
 
@@ -197,7 +200,7 @@ def apply_closure(q, star, a, dt, u, theta, *, rho_mean_gas, gamma, e_floor, t_p
                        t_per_e=t_per_e, eps_sf=eps_sf, delta_c=delta_c)
     o = forward(theta, x, bf16=bf16)
     return apply_with_outputs(q, star, a, dt, u, o, e0_code=e0_code, tau=tau, mode=mode,
-                              with_draw=with_draw, smooth=smooth)
+                              with_draw=with_draw, smooth=smooth, gamma=gamma)
 
 
 def init_params(seed):

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import mlp, philox, sim, subgrid
+from oracle import hydro, mlp, philox, sim, subgrid
 
 torch.set_default_dtype(torch.float64)
 
@@ -189,10 +189,13 @@ def test_probability_matches_plain_source_factors():
     assert torch.allclose(pi_net, pi_plain, rtol=1e-12)
 
 
-def test_exact_outputs_reduce_closure_to_plain_source():
+@pytest.mark.parametrize("dual, smooth", [(False, False), (True, False), (True, True)])
+def test_exact_outputs_reduce_closure_to_plain_source(dual, smooth):
     """With o = targets, the closure's update is the plain relaxed source term.  Where the
     gate is clipped (below e^-30), both draws are below e^-130 (the logistic noise of a 24-bit
-    uniform stays within +-17), which the star-field tolerance absorbs."""
+    uniform stays within +-17), which the star-field tolerance absorbs.  With a dual-energy
+    state (a quarter of the cells so cold against their bulk motion that the entropy gives
+    their temperature) the entropy takes the injected energy alike, also when it is smoothed."""
     cfg = sim.default_config(n=8, box=2.0, subgrid=subgrid.MODE_RELAXED)
     prm = sim.Params(eps_sf=0.5, delta_c=2.0, t_c=1e5)
     rng = np.random.default_rng(2)
@@ -204,6 +207,15 @@ def test_exact_outputs_reduce_closure_to_plain_source():
     e = temp / cfg.t_per_e
     et = a * a * rho * (e + 0.5 * ((mom / (a * rho)) ** 2).sum(0))
     q = torch.cat([rho[None], mom, et[None]])
+    if dual:
+        s_var = a * a * e * rho ** (2.0 - cfg.gamma)   # the entropy of the true internal energy
+        cold = torch.from_numpy(rng.random((n, n, n)) < 0.25)
+        # these cells' total energy holds an internal energy of 1e-4 of their kinetic energy,
+        # below the 1e-3 of the total at which the entropy takes over
+        ke = 0.5 * ((mom / (a * rho)) ** 2).sum(0)
+        et = torch.where(cold, a * a * rho * ke * (1.0 + 1e-4), et)
+        q = torch.cat([rho[None], mom, et[None], s_var[None]])
+        assert bool(((hydro.internal_energy(q, a, cfg.gamma)[0] - e).abs() < 1e-9 * e)[cold].all())
     star = torch.zeros(n, n, n)
     u = torch.from_numpy(philox.starform_uniform(cfg.sf_seed, 3, n))
     dt = 0.02
@@ -212,12 +224,13 @@ def test_exact_outputs_reduce_closure_to_plain_source():
         q, star, a, dt, u, rho_mean_gas=cfg.f_b, omega_b=cfg.omega_b, gamma=cfg.gamma,
         e_floor=cfg.e_floor, t_per_e=cfg.t_per_e, e0_code=e0, eps_sf=prm.eps_sf,
         delta_c=prm.delta_c, t_c=prm.t_c, w_rho=prm.w_rho, w_t=prm.w_t, tau=cfg.tau,
-        mode=cfg.subgrid)
+        mode=cfg.subgrid, smooth=smooth)
     tgt = mlp.targets(q[0] / cfg.f_b, subgrid.temperature(q, a, cfg.gamma, cfg.e_floor, cfg.t_per_e),
                       a, prm.eps_sf, prm.delta_c, omega_b=cfg.omega_b, t_c=prm.t_c,
                       w_rho=prm.w_rho, w_t=prm.w_t)
     got_q, got_s = mlp.apply_with_outputs(q, star, a, dt, u, tgt, e0_code=e0, tau=cfg.tau,
-                                          mode=cfg.subgrid)
+                                          mode=cfg.subgrid, smooth=smooth, gamma=cfg.gamma)
+    assert got_q.shape[0] == q.shape[0]
     assert float(ref_s.sum()) > 1.0   # stars do form in this state
     assert torch.allclose(got_q, ref_q, rtol=1e-12, atol=0)
     assert torch.allclose(got_s, ref_s, rtol=1e-10, atol=1e-50)
