@@ -122,7 +122,8 @@ typedef struct dh_config {
                             1e-3 E and S rho^(gamma-2) / a^2 elsewhere, and at the end of
                             each step S is reset from the total energy where E - U^2/2 >=
                             0.1 E (Bryan et al. 1995 with the entropy of Ryu et al. 1993).
-                            Differentiated by dh_backward.  Not with closure = MLP or
+                            Differentiated by dh_backward, also with closure = MLP (the
+                            network's T from the selected internal energy).  Not with
                             sn_smooth = 1 (DH_E_INVAL)                                      */
 } dh_config;
 

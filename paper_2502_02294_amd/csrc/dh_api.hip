@@ -1412,7 +1412,7 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
         (cfg->lpt == 1 || cfg->lpt == 2) &&
         (cfg->transfer == DH_TRANSFER_BBKS || cfg->transfer == DH_TRANSFER_EH) &&
         (cfg->dual_energy == 0 ||
-         (cfg->dual_energy == 1 && cfg->closure == DH_CLOSURE_PLAIN && cfg->sn_smooth == 0)) &&
+         (cfg->dual_energy == 1 && cfg->sn_smooth == 0)) &&
         (cfg->closure == DH_CLOSURE_PLAIN ||
          (cfg->closure == DH_CLOSURE_MLP && cfg->subgrid != DH_SUBGRID_OFF))))
     return DH_E_INVAL;

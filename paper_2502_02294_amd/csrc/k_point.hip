@@ -610,13 +610,18 @@ __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
 // consecutive cells; the per-cell inputs and outputs pass through LDS.
 constexpr int kStage = 8;   // floats per cell in the LDS stage
 
-// network inputs of one cell (FP64 from the FP32 state, then FP32)
-__device__ __forceinline__ void closure_inputs(const float q5[5], const SourceArgs& a,
-                                               float x[5], double& e_raw, bool& floored) {
+// network inputs of one cell (FP64 from the FP32 state, then FP32); NQ = 6: T of the
+// internal energy the dual-energy selection takes (tot: that of the total energy), as the
+// plain source term (source_eval)
+template <int NQ = 5>
+__device__ __forceinline__ void closure_inputs(const float* q5, const SourceArgs& a, float x[5],
+                                               double& e_raw, bool& floored, bool& tot) {
   const double rho = q5[0];
   const double ir = 1.0 / rho, ia = 1.0 / a.a;
   const double u0 = q5[1] * ia * ir, u1 = q5[2] * ia * ir, u2 = q5[3] * ia * ir;
   e_raw = q5[4] * ia * ia * ir - 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+  tot = NQ != 6 || dual_total_branch(q5);
+  if (!tot) e_raw = q5[5] * ia * ia * pow(rho, a.gamma - 2.0);
   floored = e_raw < a.efloor;
   const double e = floored ? a.efloor : e_raw;
   // the logarithms on the hardware's (FP32, ~1e-7 absolute): the network sees its inputs as
@@ -640,8 +645,8 @@ __global__ void __launch_bounds__(256) closure_state_kernel(const float* __restr
   float q5[5], xin[5];
   load_q(q, c, nc, q5);
   double e_raw;
-  bool floored;
-  closure_inputs(q5, a, xin, e_raw, floored);
+  bool floored, tot;
+  closure_inputs(q5, a, xin, e_raw, floored, tot);
 #pragma unroll
   for (int k = 0; k < 5; ++k) x[k * ld + c] = xin[k];
   const double e = floored ? a.efloor : e_raw;
@@ -712,6 +717,9 @@ __device__ __forceinline__ float closure_logit_estimate(float o0, float o1, cons
 }
 
 // Closing pass with the learned closure (same cells per block as close_step_kernel).
+// NQ = 6 (dual energy): T from the selected internal energy, the entropy takes the injected
+// energy and the end-of-step reset (dual_close); no smoothed injection.
+template <int NQ>
 __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
     const float* q_in, float* q, const float4* __restrict__ g4, float* __restrict__ star,
     float* __restrict__ q_kicked, double gg1, double* partial, long long nc,
@@ -723,9 +731,10 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
   }
   const float h = sc.h;
   const SourceArgs& a = sc.src;
-  q_in += blockIdx.y * 5 * nc;
-  q += blockIdx.y * 5 * nc;
-  if (q_kicked) q_kicked += blockIdx.y * 5 * nc;
+  q_in += blockIdx.y * NQ * nc;
+  q += blockIdx.y * NQ * nc;
+  if (q_kicked) q_kicked += blockIdx.y * NQ * nc;
+  const float gm2 = static_cast<float>(a.gamma - 2.0), g1m = static_cast<float>(1.0 - a.gamma);
   g4 += blockIdx.y * nc;
   star += blockIdx.y * nc;
   if (znew) znew += blockIdx.y * nc;
@@ -742,9 +751,11 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
   for (int r = 0; r < kRedPer; ++r) {
     const long long c = base + r * kRedThreads + threadIdx.x;
     const bool valid = c < nc;
-    float q5[5] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+    float q5[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) q5[k] = k == 0 || k >= 4 ? 1.0f : 0.0f;
     if (valid) {
-      load_q(q_in, c, nc, q5);
+      load_q<NQ>(q_in, c, nc, q5);
       float m[3] = {q5[1], q5[2], q5[3]};
       kick_cell(q5[0], g4[c], h, m, q5[4]);
       q5[1] = m[0];
@@ -752,13 +763,13 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
       q5[3] = m[2];
       if (q_kicked) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) q_kicked[k * nc + c] = q5[k];
+        for (int k = 0; k < NQ; ++k) q_kicked[k * nc + c] = q5[k];
       }
     }
     float xin[5];
     double e_raw;
-    bool floored;
-    closure_inputs(q5, a, xin, e_raw, floored);
+    bool floored, tot;
+    closure_inputs<NQ>(q5, a, xin, e_raw, floored, tot);
 #pragma unroll
     for (int k = 0; k < 5; ++k) stage[wave][lane][k] = valid ? xin[k] : 0.0f;
     wave_sync();
@@ -777,23 +788,27 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
       const float lg = closure_logit_estimate(o0, o1, a);
       const double u = screened_out(lg, kMaxLogitU, a) ? 0.5 : starform_uniform(c, a);
       float zc = 0.0f, inj = 0.0f;
+      double e_add = 0.0;   // energy injected into this cell
       if (!screened_out(lg, kMaxLogitU, a) && !screened_out(lg, logit_u_of(u), a)) {
         const ClosureDraw d = closure_draw(o0, o1, u, a);
         if (d.z != 0.0) {
           const double e_sn = a.a * a.a * static_cast<double>(q5[0]) * d.z * a.e0_code;
-          if (sn_out)
+          if (sn_out) {
             inj = static_cast<float>(e_sn);
-          else
+          } else {
             q5[4] = static_cast<float>(q5[4] + e_sn);
+            e_add = e_sn;
+          }
           star[c] = static_cast<float>(star[c] + d.z);
           zc = static_cast<float>(d.z);
         }
       }
+      if (NQ == 6) dual_close(q5, e_add, pow_approx(q5[0], g1m));
       if (znew) znew[c] = zc;
       if (sn_out) sn_out[c] = inj;
 #pragma unroll
-      for (int k = (q == q_in ? 1 : 0); k < 5; ++k) q[k * nc + c] = q5[k];
-      if (partial) vmax[0] = fmax(vmax[0], cell_speed(q5, a.a, gg1, a.efloor));
+      for (int k = (q == q_in ? 1 : 0); k < NQ; ++k) q[k * nc + c] = q5[k];
+      if (partial) vmax[0] = fmax(vmax[0], cell_speed<NQ>(q5, a.a, gg1, a.efloor, gm2));
     }
     wave_sync();
   }
@@ -811,6 +826,10 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
 // Two waves per SIMD (256 registers a lane): the compiler keeps a few values in scratch, and
 // the kernel still runs ~30% faster at 256^3 than with every value in registers at one wave
 // per SIMD (342 registers); a third wave costs more in spills than it gains.
+// NQ = 6 (dual energy): first the adjoints of the end-of-step entropy reset and of the
+// entropy's share of the injection (as dual_close_vjp), then the closure's; T of the
+// internal energy the selection takes.
+template <int NQ>
 __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
     const float* __restrict__ q, float* __restrict__ lam, double* partial, long long nc,
     const StepScal* __restrict__ tab, const float* __restrict__ lam_inj) {
@@ -820,9 +839,10 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
     return;
   }
   const SourceArgs& a = sc.src;
-  q += blockIdx.y * 5 * nc;
-  lam += blockIdx.y * 5 * nc;
+  q += blockIdx.y * NQ * nc;
+  lam += blockIdx.y * NQ * nc;
   if (lam_inj) lam_inj += blockIdx.y * nc;
+  const float g1m = static_cast<float>(1.0 - a.gamma);
   __shared__ uint4 fr[mlp::kFrAll * 64];
   __shared__ __attribute__((aligned(16))) float bias[mlp::kBias];
   __shared__ __attribute__((aligned(16))) float stage[kRedThreads / 64][64][kStage];
@@ -836,12 +856,14 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
   for (int r = 0; r < kRedPer; ++r) {
     const long long c = base + r * kRedThreads + threadIdx.x;
     const bool valid = c < nc;
-    float q5[5] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
-    if (valid) load_q(q, c, nc, q5);
+    float q5[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) q5[k] = k == 0 || k >= 4 ? 1.0f : 0.0f;
+    if (valid) load_q<NQ>(q, c, nc, q5);
     float xin[5];
     double e_raw;
-    bool floored;
-    closure_inputs(q5, a, xin, e_raw, floored);
+    bool floored, tot;
+    closure_inputs<NQ>(q5, a, xin, e_raw, floored, tot);
 #pragma unroll
     for (int k = 0; k < 5; ++k) stage[wave][lane][k] = valid ? xin[k] : 0.0f;
     wave_sync();
@@ -851,6 +873,7 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
     // is skipped: its input gradients are set to zero instead.
     double le = 0.0, li = 0.0, z = 0.0;   // adjoints of the energy and of the injection
     bool loaded = false;                   // le and li read
+    float l6[6];                           // NQ = 6: the cell's adjoint after the entropy's
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const float (*sh)[kStage] = stage[wave] + 32 * half;
@@ -871,12 +894,52 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
           const float o0 = stage[wave][lane][5], o1 = stage[wave][lane][6];
           const float lg = closure_logit_estimate(o0, o1, a);
           const double u = screened_out(lg, kMaxLogitU, a) ? 0.5 : starform_uniform(c, a);
-          if (!screened_out(lg, kMaxLogitU, a) && !screened_out(lg, logit_u_of(u), a)) {
-            le = lam[4 * nc + c];
-            li = lam_inj ? lam_inj[c] : le;
-            loaded = true;
-            const ClosureDraw d = closure_draw(o0, o1, u, a);
+          const bool drawn = !screened_out(lg, kMaxLogitU, a) && !screened_out(lg, logit_u_of(u), a);
+          ClosureDraw d{};
+          if (drawn) {
+            d = closure_draw(o0, o1, u, a);
             z = d.z;
+          }
+          if (NQ == 6) {
+            // the reset at the state after the injection, then the entropy's share of it
+            const double e_sn = K * q5[0] * z;
+            const float r1g = pow_approx(q5[0], g1m);
+            float qp[NQ];
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) qp[k] = q5[k];
+            if (e_sn != 0.0) {
+              qp[4] = static_cast<float>(q5[4] + e_sn);
+              qp[5] = static_cast<float>(q5[5] + e_sn * static_cast<double>(r1g));
+            }
+            double lc[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) lc[k] = lam[k * nc + c];
+            if (dual_sync_branch(qp)) {
+              // S' = I r1g, I = Et - |m|^2 / (2 rho)
+              const double ir = 1.0 / static_cast<double>(qp[0]);
+              const double msq = static_cast<double>(qp[1]) * qp[1] +
+                                 static_cast<double>(qp[2]) * qp[2] +
+                                 static_cast<double>(qp[3]) * qp[3];
+              const double i_tot = qp[4] - 0.5 * msq * ir;
+              lc[0] += lc[5] * r1g * (0.5 * msq * ir * ir + (1.0 - a.gamma) * i_tot * ir);
+#pragma unroll
+              for (int dd = 0; dd < 3; ++dd) lc[1 + dd] -= lc[5] * r1g * qp[1 + dd] * ir;
+              lc[4] += lc[5] * r1g;
+              lc[5] = 0.0;
+            }
+            if (e_sn != 0.0) lc[0] += lc[5] * e_sn * (1.0 - a.gamma) * r1g / static_cast<double>(q5[0]);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) l6[k] = static_cast<float>(lc[k]);
+            le = l6[4];
+            li = le + static_cast<double>(l6[5]) * r1g;
+            loaded = true;
+          }
+          if (drawn) {
+            if (NQ != 6) {
+              le = lam[4 * nc + c];
+              li = lam_inj ? lam_inj[c] : le;
+              loaded = true;
+            }
             if (a.mode != 1 && li != 0.0) {
               const double dz = d.z * (1.0 - d.z) / a.tau / (1.0 - d.pi0);   // dz / dln(pi0)
               const double coef = li * K * q5[0] * dz;
@@ -922,8 +985,35 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
       wave_sync();
     }
     const double gx0 = stage[wave][lane][0], gx1 = stage[wave][lane][1];
-    // a cell with no draw (z = 0, so dL/do = 0) and no input gradient keeps its adjoint
-    if (valid && (z != 0.0 || gx0 != 0.0 || gx1 != 0.0)) {
+    if (NQ == 6) {
+      if (valid) {
+        // Et' = Et + K rho z; x0 = (ln Delta - 4.6)/5, x1 = (ln T - 10.4)/5 with T ~ e of the
+        // selected branch: e_E (rho, m, Et) or e_S = S rho^(gamma-2) / a^2 (rho, S)
+        const double rho = q5[0];
+        const double ir = 1.0 / rho, ia = 1.0 / a.a;
+        const double ge = floored ? 0.0 : gx1 / (5.0 * e_raw);   // dL/de
+        double l[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) l[k] = l6[k];
+        l[0] += li * K * z + gx0 / (5.0 * rho);
+        if (tot) {
+          double u[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) u[d] = q5[1 + d] * ia * ir;
+          const double ke = 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+          l[0] += ge * (ke - e_raw) * ir;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) l[1 + d] += ge * (-u[d] * ia * ir);
+          l[4] += ge * (ia * ia * ir);
+        } else {
+          l[0] += ge * (a.gamma - 2.0) * e_raw * ir;
+          l[5] += ge * ia * ia * pow(rho, a.gamma - 2.0);
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) lam[k * nc + c] = static_cast<float>(l[k]);
+      }
+    } else if (valid && (z != 0.0 || gx0 != 0.0 || gx1 != 0.0)) {
+      // a cell with no draw (z = 0, so dL/do = 0) and no input gradient keeps its adjoint
       if (!loaded) {
         le = lam[4 * nc + c];
         li = lam_inj ? lam_inj[c] : le;
@@ -1242,16 +1332,18 @@ void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4
   if ((star == nullptr && znew != nullptr) || (block_max != nullptr && sn_out != nullptr))
     throw ArgError("closing pass: new stars need the star field; a smoothed injection takes "
                    "the CFL maxima to the injection pass");
-  if (b.nq == 6 && (closure || sn_out))
-    throw ArgError("closing pass: the dual-energy state has neither the learned closure nor the "
-                   "smoothed injection");
+  if (b.nq == 6 && sn_out)
+    throw ArgError("closing pass: the dual-energy state has no smoothed injection");
   const dim3 grid(sum_blocks(b.nc()), b.S);
   const double gg1 = gamma * (gamma - 1.0);
 #define DH_CLOSE(FULL, NQ)                                                                      \
   hipLaunchKernelGGL((close_step_kernel<FULL, NQ>), grid, dim3(kRedThreads), 0, st, q_in, q, g4, \
                      star, q_kicked, gg1, block_max, b.nc(), b.tab, znew, sn_out)
-  if (closure)
-    hipLaunchKernelGGL(close_step_mlp_kernel, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
+  if (closure && b.nq == 6)
+    hipLaunchKernelGGL(close_step_mlp_kernel<6>, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
+                       q_kicked, gg1, block_max, b.nc(), b.tab, znew, sn_out);
+  else if (closure)
+    hipLaunchKernelGGL(close_step_mlp_kernel<5>, grid, dim3(kRedThreads), 0, st, q_in, q, g4, star,
                        q_kicked, gg1, block_max, b.nc(), b.tab, znew, sn_out);
   else if (b.nq == 6) {
     if (star) DH_CLOSE(true, 6);
@@ -1296,10 +1388,15 @@ int cfl_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n * n); }
 void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, double* partials,
                        const Batch& b, const float* lam_inj) {
   if (!b.tab) throw ArgError("source adjoint: step table required");
-  if (b.nq != 5) throw ArgError("closure adjoint: not with the dual-energy state");
+  if (b.nq == 6 && lam_inj)
+    throw ArgError("closure adjoint: the dual-energy state has no smoothed injection");
   const dim3 grid(source_vjp_blocks(b.n), b.S);
-  hipLaunchKernelGGL(source_vjp_mlp_kernel, grid, dim3(kRedThreads), 0, st, q_before, lam_q,
-                     partials, b.nc(), b.tab, lam_inj);
+  if (b.nq == 6)
+    hipLaunchKernelGGL(source_vjp_mlp_kernel<6>, grid, dim3(kRedThreads), 0, st, q_before, lam_q,
+                       partials, b.nc(), b.tab, lam_inj);
+  else
+    hipLaunchKernelGGL(source_vjp_mlp_kernel<5>, grid, dim3(kRedThreads), 0, st, q_before, lam_q,
+                       partials, b.nc(), b.tab, lam_inj);
   DH_LAUNCH_CHECK();
 }
 

@@ -11,8 +11,11 @@ import pytest
 import torch
 
 import synth_inputs as si
-from gpu_helpers import (gpu_config, gpu_params, initial_state_fp32_cells, load_state, rel_l2,
-                         rounded_state, sweep_vjp_on_gpu_branches, to_gpu, to_np)
+from dataclasses import replace
+
+from gpu_helpers import (closure_oracle_gradient, gpu_config, gpu_params,
+                         initial_state_fp32_cells, load_state, rel_l2, rounded_state,
+                         sweep_vjp_on_gpu_branches, to_gpu, to_np)
 from oracle import hydro, sim as osim, subgrid
 
 pytestmark = pytest.mark.gpu
@@ -313,11 +316,12 @@ def test_dual_batch_equals_single_runs(dhp):
 
 
 def test_dual_combinations_and_errors(dhp):
-    """What the dual-energy state does not combine with returns DH_E_INVAL; a non-finite
-    entropy is reported like any broken state (DH_E_NONFINITE) before the step is taken."""
+    """What the dual-energy state does not combine with (the smoothed injection) returns
+    DH_E_INVAL; a non-finite entropy is reported like any broken state (DH_E_NONFINITE) before
+    the step is taken."""
     from paper_2502_02294_amd._lib import DiffHydroError
     n = 16
-    for kw in ({"closure": 1, "subgrid": 2}, {"sn_smooth": 1, "subgrid": 2}):
+    for kw in ({"sn_smooth": 1, "subgrid": 2}, {"sn_smooth": 1, "subgrid": 2, "closure": 1}):
         with pytest.raises(DiffHydroError) as e:
             dhp.Sim(dhp.default_config(n=n, box=4.0, dual_energy=1, **kw))
         assert e.value.code == -1
@@ -348,3 +352,75 @@ def test_dual_power_spectrum_is_that_of_the_density(dhp):
         s.init_from_noise(w)
         out.append(s.power_spectrum(8))
     assert np.array_equal(np.asarray(out[0][0]), np.asarray(out[1][0]))
+
+
+def test_dual_closure_step_matches_oracle(dhp):
+    """One step with the learned closure from a dual-energy state (a fifth to two fifths of
+    the cells taking the entropy's internal energy, which then also sets the network's T),
+    against the oracle's FP64 network and its bfloat16 model (bars as in test_gpu_mlp.py:
+    1e-2 and 1e-4 for the gas, 1e-2 and 1e-3 for the star field)."""
+    n = 32
+    ocfg = osim.default_config(n=n, box=10.0, dual_energy=True)
+    st = osim.initial_state(torch.from_numpy(si.white_noise(n, 2)).double(), ocfg)
+    st, _ = osim.run(st, ocfg, osim.Params(), a_final=0.12)
+    st = rounded_state(st)
+    assert 0.2 < _branch_fraction(st.q, st.a) < 0.4
+    net = dhp.Mlp(seed=8)
+    theta = net.weights().astype(np.float64)
+    ocfg = replace(ocfg, subgrid=subgrid.MODE_RELAXED)
+    prm = osim.Params()
+    s = dhp.Sim(gpu_config(ocfg, closure=1), gpu_params(prm))
+    s.set_closure(theta)
+    load_state(s, st)
+    dt = osim.cfl_dt(st, ocfg)
+    s.set_schedule([dt])
+    s.step()
+    q = to_np(s.get("q"))
+    star = to_np(s.get("star"))
+    assert q.shape[0] == 6
+    for bf16, tol_q, tol_star in ((False, 1e-2, 1e-2), (True, 1e-4, 1e-3)):
+        ref = osim.step(st, replace(ocfg, closure_theta=theta, closure_bf16=bf16), prm, dt)
+        assert float(ref.star.sum()) > 10.0
+        errs = [rel_l2(q[c], ref.q[c].numpy()) for c in range(6)]
+        print(bf16, [f"{e:.1e}" for e in errs], f"star {rel_l2(star, ref.star.numpy()):.1e}")
+        assert max(errs) < tol_q, (bf16, errs)
+        assert rel_l2(star, ref.star.numpy()) < tol_star, bf16
+
+
+def test_dual_closure_gradient_matches_oracle_autograd(dhp):
+    """Gradients of the flux loss through three steps at 16^3 with the learned closure on the
+    dual-energy state (a few percent of the cells taking the entropy's internal energy at the
+    end, most of the rest reset from the total energy every step), against oracle autograd
+    with the FP64 network and with its bfloat16 model (bars as in test_gpu_mlp.py)."""
+    n, nsteps = 16, 3
+    net = dhp.Mlp(seed=9)
+    theta = net.weights().astype(np.float64)
+    ocfg0 = osim.default_config(n=n, box=4.0, subgrid=subgrid.MODE_RELAXED, a_init=0.05,
+                                dual_energy=True)
+    prm = osim.Params(eps_sf=0.025, delta_c=80.0)
+    w = si.white_noise(n, seed=21)
+    target = (0.2 + 0.7 * np.random.default_rng(2).random((n, n, n))).astype(np.float32)
+    ocfg = replace(ocfg0, closure_theta=theta, closure_bf16=False)
+    st0 = osim.initial_state(torch.from_numpy(w).double(), ocfg)
+    st1, sched = osim.run(st0, ocfg, prm, nsteps=nsteps)
+    frac = _branch_fraction(st1.q, st1.a)
+    print(f"entropy branch in {frac:.2f} of the cells at the end")
+    assert frac > 0.02
+    s = dhp.Sim(gpu_config(ocfg, closure=1, ckpt_every=2), gpu_params(prm))
+    s.set_closure(theta)
+    s.set_schedule(sched)
+    assert s.forward(to_gpu(w), 1.0) == nsteps
+    lval = s.loss(to_gpu(target))
+    gw, gp = s.backward()
+    gw = to_np(gw)
+    gp = np.array(gp)
+    for bf16, tol_w, tol_sf in ((False, 1e-2, 5e-2), (True, 1e-2, 5e-3)):
+        L, gw_ref, gp_ref, mag = closure_oracle_gradient(
+            replace(ocfg0, closure_theta=theta, closure_bf16=bf16), prm, w, target, sched)
+        print(bf16, f"gw rel-L2 {rel_l2(gw, gw_ref):.2e}", gp, gp_ref)
+        assert abs(lval - L) < 1e-4 * L, (bf16, lval, L)
+        assert rel_l2(gw, gw_ref) < tol_w, (bf16, rel_l2(gw, gw_ref))
+        for i in range(2):
+            assert abs(gp[i] - gp_ref[i]) < 1e-3 * mag[i] + 1e-12, (bf16, i, gp, gp_ref)
+        for i in (2, 3):
+            assert abs(gp[i] - gp_ref[i]) < tol_sf * mag[i] + 1e-12, (bf16, i, gp, gp_ref, mag)
