@@ -398,8 +398,8 @@ int dh_mlp_sample(dh_mlp* net, const dh_mlp_sample_opts* opts, double omega_b,
 /* Training and checking on the states a run visits: the network inputs d_x[5][S n^3] and
  * the targets d_y[2][S n^3] (as dh_mlp_sample's) of every cell of the handle's current state
  * (sample s at columns s n^3 ..), with its scale factor and parameters.  Caller-owned device
- * buffers; asynchronous.  DH_E_INVAL for a dual-energy handle (the closure's temperature is
- * that of the total energy). */
+ * buffers; asynchronous.  With the dual-energy state, T is that of the selected internal
+ * energy (as the closure and the plain source term take it). */
 int dh_closure_states(dh_sim* sim, float* d_x, float* d_y);
 /* d_out[2][count] = network(d_x). */
 int dh_mlp_eval(dh_mlp* net, const float* d_x, int64_t count, float* d_out);

@@ -2078,12 +2078,11 @@ int dh_power_loss(dh_sim* s, int32_t nbins, const double* pk_obs, const double* 
 
 int dh_closure_states(dh_sim* s, float* d_x, float* d_y) {
   if (!s || !d_x || !d_y) return DH_E_INVAL;
-  if (s->nq != 5) return fail(s, DH_E_INVAL, "closure states: not with the dual-energy state");
   return guarded(s, [&]() -> int {
     const long long ld = s->nc * s->S;
     for (int i = 0; i < s->S; ++i)
       dh::launch_closure_state(s->st, s->q + s->nq * s->nc * i, source_args(s, i, s->a[i], 0.0, 0),
-                               d_x + s->nc * i, d_y + s->nc * i, s->nc, ld);
+                               d_x + s->nc * i, d_y + s->nc * i, s->nc, ld, s->nq);
     return DH_OK;
   });
 }

@@ -265,9 +265,9 @@ void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const
                        float* lam_psi, const Batch& b);
 void launch_fill(hipStream_t st, float* p, float v, long long count);
 // network inputs x[5][ld] and plain targets y[2][ld] of the nc cells of one sample's state q
-// (five components), at the scale factor and parameters of a
+// (nq components), at the scale factor and parameters of a
 void launch_closure_state(hipStream_t st, const float* q, const SourceArgs& a, float* x, float* y,
-                          long long nc, long long ld);
+                          long long nc, long long ld, int nq);
 
 // ---- learned closure network (k_mlp.hip; layout in dh_mlp.h)
 struct MlpSampleArgs {   // ranges of the training states (natural logs where named ln)

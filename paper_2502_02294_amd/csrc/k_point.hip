@@ -635,18 +635,19 @@ __device__ __forceinline__ void closure_inputs(const float* q5, const SourceArgs
 
 // Network inputs x[5][ld] and the plain relaxed term's targets y[2][ld] (mlp::closure_targets)
 // of every cell of one sample's state: the closure trained and checked on the states a run
-// visits.
+// visits.  NQ = 6: T of the selected internal energy.
+template <int NQ>
 __global__ void __launch_bounds__(256) closure_state_kernel(const float* __restrict__ q,
                                                             SourceArgs a, float* __restrict__ x,
                                                             float* __restrict__ y, long long nc,
                                                             long long ld) {
   const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= nc) return;
-  float q5[5], xin[5];
-  load_q(q, c, nc, q5);
+  float q5[NQ], xin[5];
+  load_q<NQ>(q, c, nc, q5);
   double e_raw;
   bool floored, tot;
-  closure_inputs(q5, a, xin, e_raw, floored, tot);
+  closure_inputs<NQ>(q5, a, xin, e_raw, floored, tot);
 #pragma unroll
   for (int k = 0; k < 5; ++k) x[k * ld + c] = xin[k];
   const double e = floored ? a.efloor : e_raw;
@@ -1536,9 +1537,13 @@ void launch_ic_gas_vjp(hipStream_t st, const float* cic, const float* psi, const
 }
 
 void launch_closure_state(hipStream_t st, const float* q, const SourceArgs& a, float* x, float* y,
-                          long long nc, long long ld) {
-  hipLaunchKernelGGL(closure_state_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, a, x,
-                     y, nc, ld);
+                          long long nc, long long ld, int nq) {
+  if (nq == 6)
+    hipLaunchKernelGGL(closure_state_kernel<6>, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, a,
+                       x, y, nc, ld);
+  else
+    hipLaunchKernelGGL(closure_state_kernel<5>, dim3(blocks_for(nc, 256)), dim3(256), 0, st, q, a,
+                       x, y, nc, ld);
   DH_LAUNCH_CHECK();
 }
 
