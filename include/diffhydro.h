@@ -123,8 +123,9 @@ typedef struct dh_config {
                             each step S is reset from the total energy where E - U^2/2 >=
                             0.1 E (Bryan et al. 1995 with the entropy of Ryu et al. 1993).
                             Differentiated by dh_backward, also with closure = MLP (the
-                            network's T from the selected internal energy).  Not with
-                            sn_smooth = 1 (DH_E_INVAL)                                      */
+                            network's T from the selected internal energy) and sn_smooth = 1
+                            (the entropy takes its share of the smoothed energy before the
+                            reset; a taped step keeps the injection field, 4 B per cell) */
 } dh_config;
 
 /* Model parameters (double).  A, beta: flux observable F = exp(-A Delta^beta) of the loss;

@@ -68,6 +68,8 @@ struct TapeStep {
                               // after a segment's last step; set by the reverse pass
   uint32_t *start, *sorted;   // the step's sort of x1 (bin starts, ids in bin order)
   float4* spos;               // x1 in that bin order
+  float* sn;                  // dual energy with the smoothed injection: the step's per-cell
+                              // injected energy before the smoothing (else null)
   // the sort the reverse pass uses: the buffers above, or the forward's stored one
   uint32_t *vstart, *vsorted;
   float4* vspos;
@@ -114,6 +116,7 @@ struct dh_sim {
   // draw per cell; smoothed injection (cfg.sn_smooth): the injected energy per cell (and the
   // adjoint of it in the reverse pass)
   float *aux = nullptr, *znew = nullptr, *sn_buf = nullptr;
+  float* sn_buf2 = nullptr;   // dual energy with the smoothed injection: the injection's adjoint
   // second-order LPT initial conditions (cfg.lpt == 2): the six second derivatives of the
   // linear potential [S][6][n^3] and the velocity displacement Psi + (f2/f1) Psi2 [S][3][n^3],
   // kept for the adjoint of the initial conditions
@@ -457,13 +460,23 @@ long long store_step_bytes(const dh_sim* s) {
   return (s->nc * S + 1) * 4 + s->np * S * (4 + 16) + s->nc * S * 4;
 }
 
+// the dual-energy state with the smoothed injection (its tape keeps the injection field)
+bool dual_smooth(const dh_sim* s) {
+  return s->nq == 6 && s->cfg.sn_smooth && s->cfg.subgrid != DH_SUBGRID_OFF;
+}
+
+long long tape_entry_bytes(const dh_sim* s) {
+  const long long S = s->S, nc = s->nc * S, np = s->np * S;
+  const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
+  return (closure ? 5 : 4) * s->nq * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 + np * 4 +
+         np * 16 + (dual_smooth(s) ? nc * 4 : 0);
+}
+
 // Device memory the first reverse pass still has to allocate (tape entries, adjoint buffers,
 // the spare state set).
 long long reverse_pass_bytes(const dh_sim* s) {
   const long long S = s->S, nc = s->nc * S, np = s->np * S;
-  const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
-  const long long entry = (closure ? 5 : 4) * s->nq * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 +
-                          np * 4 + np * 16;
+  const long long entry = tape_entry_bytes(s);
   long long need = 0;
   const long long k = s->cfg.ckpt_every;
   if (static_cast<long long>(s->tape.size()) < k)
@@ -471,13 +484,6 @@ long long reverse_pass_bytes(const dh_sim* s) {
   if (!s->lq) need += (29 + 2 * (s->nq - 5)) * nc * 4;
   if (!s->keep.q) need += s->nq * nc * 4 + 6 * np * 4 + 2 * nc * 4;
   return need;
-}
-
-long long tape_entry_bytes(const dh_sim* s) {
-  const long long S = s->S, nc = s->nc * S, np = s->np * S;
-  const bool closure = s->cfg.closure == DH_CLOSURE_MLP && s->cfg.subgrid != DH_SUBGRID_OFF;
-  return (closure ? 5 : 4) * s->nq * nc * 4 + 3 * np * 4 + nc * 4 + (nc + 1) * 4 + np * 4 +
-         np * 16;
 }
 
 // What the next forward may keep for the reverse pass, from what the device has free after
@@ -607,13 +613,15 @@ bool all_finite(const std::vector<double>& v) {
 // the step's new stars read out on the particles (cfg.star_dm; spos, sorted: the sort of the
 // end-of-step positions).
 void close_pass(dh_sim* s, const float* q_in, float* q_kicked, bool full, bool readout,
-                const float4* spos, const uint32_t* sorted, const Batch& b, bool closure) {
+                const float4* spos, const uint32_t* sorted, const Batch& b, bool closure,
+                float* sn = nullptr) {
   const bool smooth = s->cfg.sn_smooth && s->cfg.subgrid != DH_SUBGRID_OFF;
   const bool stars = readout && full && s->znew && s->cfg.subgrid != DH_SUBGRID_OFF;
+  float* snb = sn ? sn : s->sn_buf;   // a tape keeps the injection field where it has room
   dh::launch_close_step(s->st, q_in, s->q, s->g4, full ? s->star : nullptr, q_kicked,
                         s->cfg.gamma, full && !smooth ? s->cfl_red : nullptr, b, closure,
-                        stars ? s->znew : nullptr, smooth ? s->sn_buf : nullptr);
-  if (smooth) dh::launch_sn_inject(s->st, s->sn_buf, s->q, s->cfg.gamma, full ? s->cfl_red : nullptr, b);
+                        stars ? s->znew : nullptr, smooth ? snb : nullptr);
+  if (smooth) dh::launch_sn_inject(s->st, snb, s->q, s->cfg.gamma, full ? s->cfl_red : nullptr, b);
   if (stars) dh::launch_star_readout(s->st, s->znew, spos, sorted, s->aux, b);
 }
 
@@ -685,7 +693,7 @@ void do_step(dh_sim* s, const StepPlan& sp, TapeStep* tp, bool defer, int store_
     // the recomputation needs neither the star field nor the CFL maxima (plain source)
     const bool full = !recompute || closure;
     close_pass(s, tp->q[4], closure ? tp->q[5] : nullptr, full, !recompute, tp->vspos,
-               tp->vsorted, b, closure);
+               tp->vsorted, b, closure, tp->sn);
   } else {
     // opening half kicks with g_n (the gas one inside the first sweep), drift with
     // a(t + dt/2)
@@ -1063,6 +1071,7 @@ void alloc_tape_entry(dh_sim* s, TapeStep& t) {
   t.start = s->alloc<uint32_t>(s->nc * S + 1);
   t.sorted = s->alloc<uint32_t>(s->np * S);
   t.spos = s->alloc<float4>(s->np * S);
+  t.sn = dual_smooth(s) ? s->alloc<float>(s->nc * S) : nullptr;
 }
 
 // alloc_tape_entry that gives the memory back and returns false when it is not there
@@ -1188,7 +1197,9 @@ void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
   bool all = true;
   for (int i = 0; i < s->S; ++i) all = all && sp.smp[i].active;
   const bool reuse = all && s->g4b_phi0_of == sp.step + 1;
-  const bool fuse_open = s->open_pending && reuse && !closure;
+  // with the dual-energy state and the smoothed injection the reset's adjoint below needs the
+  // next step's opening kick taken first: not fused
+  const bool fuse_open = s->open_pending && reuse && !closure && !dual_smooth(s);
   if (!fuse_open) flush_open_vjp(s);   // with the next step's g, still in g4b
   if (!reuse) dh::launch_grad(st, T.phi1, s->g4b, b);
   const int nb = dh::source_vjp_blocks(s->n);
@@ -1196,7 +1207,12 @@ void step_vjp(dh_sim* s, const TapeStep& T, bool defer_open) {
   // energy adjoint (the weights are symmetric); the next step's opening gas kick leaves the
   // energy adjoint unchanged, so it may be taken before the fused kernel applies that kick
   const float* lam_inj = nullptr;
-  if (source && s->cfg.sn_smooth) {
+  if (source && s->cfg.sn_smooth && s->nq == 6) {
+    // dual energy: the reset after the injection and the entropy's share of it first
+    dh::launch_inject_sync_vjp(st, T.q[4], s->g4b, T.sn, s->lq, s->sn_buf2, b);
+    dh::launch_smooth27(st, s->sn_buf2, nc, s->sn_buf, b);
+    lam_inj = s->sn_buf;
+  } else if (source && s->cfg.sn_smooth) {
     dh::launch_smooth27(st, s->lq + 4 * nc, s->nq * nc, s->sn_buf, b);
     lam_inj = s->sn_buf;
   }
@@ -1412,7 +1428,7 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
         (cfg->lpt == 1 || cfg->lpt == 2) &&
         (cfg->transfer == DH_TRANSFER_BBKS || cfg->transfer == DH_TRANSFER_EH) &&
         (cfg->dual_energy == 0 ||
-         (cfg->dual_energy == 1 && cfg->sn_smooth == 0)) &&
+         cfg->dual_energy == 1) &&
         (cfg->closure == DH_CLOSURE_PLAIN ||
          (cfg->closure == DH_CLOSURE_MLP && cfg->subgrid != DH_SUBGRID_OFF))))
     return DH_E_INVAL;
@@ -1457,6 +1473,7 @@ int dh_create(const dh_config* cfg, dh_sim** out) {
       DH_HIP(hipMemset(s->aux, 0, static_cast<size_t>(np) * sizeof(float)));
     }
     if (cfg->sn_smooth) s->sn_buf = s->alloc<float>(nc);
+    if (cfg->sn_smooth && cfg->dual_energy) s->sn_buf2 = s->alloc<float>(nc);
     if (cfg->lpt == 2) {
       s->hess = s->alloc<float>(6 * nc);
       s->lptv = s->alloc<float>(3 * nc);

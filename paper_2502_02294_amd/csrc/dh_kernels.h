@@ -197,12 +197,18 @@ void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4
                        const Batch& b, bool closure, float* znew = nullptr,
                        float* sn_out = nullptr);
 // smoothed supernova injection: a^2 rho E += the 27-cell smoothing of sn (weights 1/2, 1/4 per
-// axis), then the CFL block maxima as launch_close_step (block_max may be null)
+// axis), then the CFL block maxima as launch_close_step (block_max may be null); with the
+// dual-energy state the entropy takes its share and the end-of-step reset follows
 void launch_sn_inject(hipStream_t st, const float* sn, float* q, double gamma, double* block_max,
                       const Batch& b);
 // out[s][n^3] = the same smoothing of in (sample stride in_stride): its adjoint
 void launch_smooth27(hipStream_t st, const float* in, long long in_stride, float* out,
                      const Batch& b);
+// dual-energy state: adjoint of the smoothed injection and the reset after it, at q4 (the state
+// after the sweeps) with the closing gas kick (g4) and the step's injection field sn; lam
+// updated in place, lam_add[s][n^3] = adjoint of each cell's smoothed energy
+void launch_inject_sync_vjp(hipStream_t st, const float* q4, const float4* g4, const float* sn,
+                            float* lam, float* lam_add, const Batch& b);
 // adjoint of the source term with the learned closure; dL/d(eps_sf, delta_c) partials per
 // block: partials[(v S + s) nb + block], nb = source_vjp_blocks(n).  lam_inj: adjoint of
 // each cell's injected energy when the injection is smoothed (null: the energy adjoint).

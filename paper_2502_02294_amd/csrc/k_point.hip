@@ -289,7 +289,7 @@ __device__ __forceinline__ void dual_close(float* q, double e_sn, float r1g) {
 // there (0 where none) instead of being added to the cell, for the smoothed injection; the
 // CFL maxima are then left to the injection pass (partial may be null).
 // NQ = 6 (dual energy): the entropy also takes the injected energy, then the end-of-step
-// reset (dual_close); there is no smoothed injection.
+// reset (dual_close); with the smoothed injection both follow in the injection pass.
 template <bool FULL, int NQ>
 __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
     const float* q_in, float* q, const float4* __restrict__ g4, float* __restrict__ star,
@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(kRedThreads) close_step_kernel(
         }
       }
     }
-    if (NQ == 6) dual_close(q5, e_add, pow_approx(q5[0], g1m));
+    if (NQ == 6 && !sn_out) dual_close(q5, e_add, pow_approx(q5[0], g1m));
     if (znew) znew[c] = zc;
     if (sn_out) sn_out[c] = inj;
 #pragma unroll
@@ -381,7 +381,9 @@ __device__ __forceinline__ float smooth27(const float* __restrict__ f, unsigned 
 }
 
 // Smoothed supernova injection of a step: a^2 rho E += smooth27(sn) per cell, then the CFL
-// block maximum of the result (partial may be null: none).
+// block maximum of the result (partial may be null: none).  NQ = 6: the entropy takes
+// smooth27(sn) rho^(1-gamma) and the end-of-step reset (dual_close).
+template <int NQ>
 __global__ void __launch_bounds__(kRedThreads) sn_inject_kernel(
     const float* __restrict__ sn, float* __restrict__ q, double gg1, double* partial, int n,
     int lgn, const StepScal* __restrict__ tab) {
@@ -393,7 +395,8 @@ __global__ void __launch_bounds__(kRedThreads) sn_inject_kernel(
   }
   const SourceArgs& a = sc.src;
   sn += blockIdx.y * nc;
-  q += blockIdx.y * 5 * nc;
+  q += blockIdx.y * NQ * nc;
+  const float gm2 = static_cast<float>(a.gamma - 2.0), g1m = static_cast<float>(1.0 - a.gamma);
   const unsigned n1 = static_cast<unsigned>(n - 1);
   double vmax[1] = {0.0};
   const long long base = static_cast<long long>(blockIdx.x) * kRedThreads * kRedPer;
@@ -402,6 +405,16 @@ __global__ void __launch_bounds__(kRedThreads) sn_inject_kernel(
     if (c >= nc) break;
     const unsigned uc = static_cast<unsigned>(c);
     const float add = smooth27(sn, uc & n1, (uc >> lgn) & n1, uc >> (2 * lgn), n1, lgn);
+    if (NQ == 6) {
+      float q6[NQ];
+      load_q<NQ>(q, c, nc, q6);
+      q6[4] = q6[4] + add;
+      dual_close(q6, add, pow_approx(q6[0], g1m));
+      q[4 * nc + c] = q6[4];
+      q[5 * nc + c] = q6[5];
+      if (partial) vmax[0] = fmax(vmax[0], cell_speed<NQ>(q6, a.a, gg1, a.efloor, gm2));
+      continue;
+    }
     const float e4 = q[4 * nc + c] + add;
     q[4 * nc + c] = e4;
     if (partial) {
@@ -412,6 +425,61 @@ __global__ void __launch_bounds__(kRedThreads) sn_inject_kernel(
     }
   }
   if (partial) block_reduce_store<1, true>(vmax, sample_partials(partial), partial_stride());
+}
+
+// Adjoint of the smoothed injection into a dual-energy state and of the end-of-step reset
+// after it (sn_inject_kernel<6>), at the state the injection pass saw: q4 (the state after the
+// sweeps) with the closing gas kick (g4, the table's h) applied as the closing pass applied it
+// (where the injection is smoothed the source term leaves the cell's state unchanged), plus
+// add = smooth27(sn).  lam: in, the adjoint after the reset; out, that after the closing pass's
+// source term.  lam_add: the adjoint of each cell's smoothed energy.
+__global__ void __launch_bounds__(256) inject_sync_vjp_kernel(
+    const float* __restrict__ q4, const float4* __restrict__ g4, const float* __restrict__ sn,
+    float* __restrict__ lam, float* __restrict__ lam_add, int n, int lgn,
+    const StepScal* __restrict__ tab) {
+  const unsigned c = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nc = 1u << (3 * lgn);
+  const StepScal& sc = tab[blockIdx.y];
+  if (c >= nc || !sc.active) return;
+  const SourceArgs& a = sc.src;
+  const long long off = static_cast<long long>(blockIdx.y) * nc;
+  q4 += 6 * off;
+  g4 += off;
+  sn += off;
+  lam += 6 * off;
+  lam_add += off;
+  float q[6];
+  load_q<6>(q4, c, nc, q);
+  float m[3] = {q[1], q[2], q[3]};
+  kick_cell(q[0], g4[c], sc.h, m, q[4]);
+  q[1] = m[0];
+  q[2] = m[1];
+  q[3] = m[2];
+  const unsigned n1 = static_cast<unsigned>(n - 1);
+  const float add = smooth27(sn, c & n1, (c >> lgn) & n1, c >> (2 * lgn), n1, lgn);
+  const float r1g = pow_approx(q[0], static_cast<float>(1.0 - a.gamma));
+  float qp[6] = {q[0], q[1], q[2], q[3], q[4] + add, q[5]};
+  if (add != 0.0f) qp[5] = static_cast<float>(q[5] + static_cast<double>(add) * r1g);
+  double l[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) l[k] = lam[k * nc + c];
+  if (dual_sync_branch(qp)) {
+    // S' = I r1g, I = Et - |m|^2 / (2 rho)
+    const double ir = 1.0 / static_cast<double>(qp[0]);
+    const double msq = static_cast<double>(qp[1]) * qp[1] + static_cast<double>(qp[2]) * qp[2] +
+                       static_cast<double>(qp[3]) * qp[3];
+    const double i_tot = qp[4] - 0.5 * msq * ir;
+    l[0] += l[5] * r1g * (0.5 * msq * ir * ir + (1.0 - a.gamma) * i_tot * ir);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) l[1 + d] -= l[5] * r1g * qp[1 + d] * ir;
+    l[4] += l[5] * r1g;
+    l[5] = 0.0;
+  }
+  // Et' = Et + add, S' = S + add rho^(1-gamma)
+  if (add != 0.0f) l[0] += l[5] * add * (1.0 - a.gamma) * r1g / static_cast<double>(q[0]);
+  lam_add[c] = static_cast<float>(l[4] + l[5] * r1g);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) lam[k * nc + c] = static_cast<float>(l[k]);
 }
 
 // out = smooth27(in) per cell (in: a field of stride in_stride per sample, out: n^3 per
@@ -589,10 +657,10 @@ __global__ void __launch_bounds__(kRedThreads) source_kick_vjp_kernel(
     q5[1] = m[0];
     q5[2] = m[1];
     q5[3] = m[2];
-    if (NQ == 6)
+    if (NQ == 6 && !lam_inj)
       dual_close_vjp(q5, c, a, l5, acc);
     else if (a.mode != 0)
-      source_cell_vjp(q5, c, a, l5, lam_inj ? lam_inj[c] : l5[4], acc);
+      source_cell_vjp<NQ>(q5, c, a, l5, lam_inj ? lam_inj[c] : l5[4], acc);
     float lg[3];
     kick_cell_vjp(q5[0], m0, gv, h, l5, lg);
 #pragma unroll
@@ -719,7 +787,8 @@ __device__ __forceinline__ float closure_logit_estimate(float o0, float o1, cons
 
 // Closing pass with the learned closure (same cells per block as close_step_kernel).
 // NQ = 6 (dual energy): T from the selected internal energy, the entropy takes the injected
-// energy and the end-of-step reset (dual_close); no smoothed injection.
+// energy and the end-of-step reset (dual_close; with the smoothed injection, in the injection
+// pass).
 template <int NQ>
 __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
     const float* q_in, float* q, const float4* __restrict__ g4, float* __restrict__ star,
@@ -804,7 +873,7 @@ __global__ void __launch_bounds__(kRedThreads) close_step_mlp_kernel(
           zc = static_cast<float>(d.z);
         }
       }
-      if (NQ == 6) dual_close(q5, e_add, pow_approx(q5[0], g1m));
+      if (NQ == 6 && !sn_out) dual_close(q5, e_add, pow_approx(q5[0], g1m));
       if (znew) znew[c] = zc;
       if (sn_out) sn_out[c] = inj;
 #pragma unroll
@@ -901,7 +970,14 @@ __global__ void __launch_bounds__(kRedThreads, 2) source_vjp_mlp_kernel(
             d = closure_draw(o0, o1, u, a);
             z = d.z;
           }
-          if (NQ == 6) {
+          if (NQ == 6 && lam_inj) {
+            // smoothed injection: its adjoint and the reset's were taken before
+#pragma unroll
+            for (int k = 0; k < 6; ++k) l6[k] = lam[k * nc + c];
+            le = l6[4];
+            li = lam_inj[c];
+            loaded = true;
+          } else if (NQ == 6) {
             // the reset at the state after the injection, then the entropy's share of it
             const double e_sn = K * q5[0] * z;
             const float r1g = pow_approx(q5[0], g1m);
@@ -1333,8 +1409,6 @@ void launch_close_step(hipStream_t st, const float* q_in, float* q, const float4
   if ((star == nullptr && znew != nullptr) || (block_max != nullptr && sn_out != nullptr))
     throw ArgError("closing pass: new stars need the star field; a smoothed injection takes "
                    "the CFL maxima to the injection pass");
-  if (b.nq == 6 && sn_out)
-    throw ArgError("closing pass: the dual-energy state has no smoothed injection");
   const dim3 grid(sum_blocks(b.nc()), b.S);
   const double gg1 = gamma * (gamma - 1.0);
 #define DH_CLOSE(FULL, NQ)                                                                      \
@@ -1366,9 +1440,21 @@ static int log2_int(int v) {
 void launch_sn_inject(hipStream_t st, const float* sn, float* q, double gamma, double* block_max,
                       const Batch& b) {
   if (!b.tab) throw ArgError("supernova injection: step table required");
-  if (b.nq != 5) throw ArgError("supernova injection: not with the dual-energy state");
-  hipLaunchKernelGGL(sn_inject_kernel, dim3(sum_blocks(b.nc()), b.S), dim3(kRedThreads), 0, st,
-                     sn, q, gamma * (gamma - 1.0), block_max, b.n, log2_int(b.n), b.tab);
+  if (b.nq == 6)
+    hipLaunchKernelGGL(sn_inject_kernel<6>, dim3(sum_blocks(b.nc()), b.S), dim3(kRedThreads), 0,
+                       st, sn, q, gamma * (gamma - 1.0), block_max, b.n, log2_int(b.n), b.tab);
+  else
+    hipLaunchKernelGGL(sn_inject_kernel<5>, dim3(sum_blocks(b.nc()), b.S), dim3(kRedThreads), 0,
+                       st, sn, q, gamma * (gamma - 1.0), block_max, b.n, log2_int(b.n), b.tab);
+  DH_LAUNCH_CHECK();
+}
+
+void launch_inject_sync_vjp(hipStream_t st, const float* q4, const float4* g4, const float* sn,
+                            float* lam, float* lam_add, const Batch& b) {
+  if (!b.tab) throw ArgError("injection adjoint: step table required");
+  if (b.nq != 6) throw ArgError("injection adjoint: dual-energy state only");
+  hipLaunchKernelGGL(inject_sync_vjp_kernel, dim3(blocks_for(b.nc(), 256), b.S), dim3(256), 0, st,
+                     q4, g4, sn, lam, lam_add, b.n, log2_int(b.n), b.tab);
   DH_LAUNCH_CHECK();
 }
 
@@ -1389,8 +1475,6 @@ int cfl_blocks(int n) { return sum_blocks(static_cast<long long>(n) * n * n); }
 void launch_source_vjp(hipStream_t st, const float* q_before, float* lam_q, double* partials,
                        const Batch& b, const float* lam_inj) {
   if (!b.tab) throw ArgError("source adjoint: step table required");
-  if (b.nq == 6 && lam_inj)
-    throw ArgError("closure adjoint: the dual-energy state has no smoothed injection");
   const dim3 grid(source_vjp_blocks(b.n), b.S);
   if (b.nq == 6)
     hipLaunchKernelGGL(source_vjp_mlp_kernel<6>, grid, dim3(kRedThreads), 0, st, q_before, lam_q,
@@ -1408,7 +1492,6 @@ void launch_source_kick_vjp(hipStream_t st, const float* q_kick, const float4* g
   if (!b.tab) throw ArgError("closing pass adjoint: step table required");
   if (q_open && (!lam_g_open || !tab_open))
     throw ArgError("closing pass adjoint: opening kick operands");
-  if (b.nq == 6 && lam_inj) throw ArgError("closing pass adjoint: no smoothed dual-energy injection");
   const dim3 grid(source_vjp_blocks(b.n), b.S);
 #define DH_SKV(OPEN, NQ)                                                                      \
   hipLaunchKernelGGL((source_kick_vjp_kernel<OPEN, NQ>), grid, dim3(kRedThreads), 0, st, q_kick, \

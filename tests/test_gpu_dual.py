@@ -167,11 +167,14 @@ def test_dual_single_step_matches_oracle(dhp):
     _compare_q(s, ref.q, STEP_TOL, ref.a, t_ref=t_ref, t_tol=1e-4, t_cell=1e-3, t_frac=2e-3)
 
 
-def test_dual_run_with_star_formation_matches_oracle(dhp):
+@pytest.mark.parametrize("smooth", [False, True])
+def test_dual_run_with_star_formation_matches_oracle(dhp, smooth):
     """Twenty steps from the initial conditions with relaxed star formation (low thresholds,
-    so that heating and the entropy's share of it act), then the temperature cell by cell."""
+    so that heating and the entropy's share of it act; with smooth, the injection spread over
+    27 cells before the reset), then the temperature cell by cell."""
     n = 32
-    ocfg = osim.default_config(n=n, box=10.0, dual_energy=True, subgrid=subgrid.MODE_RELAXED)
+    ocfg = osim.default_config(n=n, box=10.0, dual_energy=True, subgrid=subgrid.MODE_RELAXED,
+                               sn_smooth=smooth)
     prm = osim.Params(delta_c=2.0, t_c=1e6, eps_sf=0.5)
     w = si.white_noise(n, seed=3)
     s = _sim(dhp, ocfg, prm)
@@ -227,12 +230,14 @@ def test_cold_supersonic_flow_temperature(dhp, dual):
         assert dev > 1e-2
 
 
-def test_dual_gradient_matches_oracle_autograd(dhp):
+@pytest.mark.parametrize("smooth", [False, True])
+def test_dual_gradient_matches_oracle_autograd(dhp, smooth):
     """Gradients of the flux loss through four steps at 16^3 (two checkpoint segments) with
-    relaxed star formation, a third of the cells taking the entropy's internal energy."""
+    relaxed star formation, some of the cells taking the entropy's internal energy; with
+    smooth, the injection spread over 27 cells before the reset."""
     n, nsteps = 16, 4
     ocfg = osim.default_config(n=n, box=4.0, subgrid=subgrid.MODE_RELAXED, a_init=0.05,
-                               dual_energy=True)
+                               dual_energy=True, sn_smooth=smooth)
     prm = osim.Params(delta_c=1.05, t_c=1e6, eps_sf=0.5)
     w = si.white_noise(n, seed=21)
     target = (0.2 + 0.7 * np.random.default_rng(1).random((n, n, n))).astype(np.float32)
@@ -240,7 +245,7 @@ def test_dual_gradient_matches_oracle_autograd(dhp):
     st1, sched = osim.run(st0, ocfg, prm, nsteps=nsteps)
     frac = _branch_fraction(st1.q, st1.a)
     print(f"entropy branch in {frac:.2f} of the cells at the end")
-    assert frac > 0.05
+    assert frac > 0.02   # both branches of the selection act
     w64 = torch.from_numpy(w).double().requires_grad_(True)
     th = torch.tensor([prm.A, prm.beta, prm.eps_sf, prm.delta_c], requires_grad=True)
     p2 = osim.Params(A=th[0], beta=th[1], eps_sf=th[2], delta_c=th[3], t_c=prm.t_c)
@@ -315,16 +320,11 @@ def test_dual_batch_equals_single_runs(dhp):
         assert torch.equal(qb[i], singles[i]), i
 
 
-def test_dual_combinations_and_errors(dhp):
-    """What the dual-energy state does not combine with (the smoothed injection) returns
-    DH_E_INVAL; a non-finite entropy is reported like any broken state (DH_E_NONFINITE) before
-    the step is taken."""
+def test_dual_nonfinite_entropy_is_reported(dhp):
+    """A non-finite entropy is reported like any broken state (DH_E_NONFINITE) before the
+    step is taken."""
     from paper_2502_02294_amd._lib import DiffHydroError
     n = 16
-    for kw in ({"sn_smooth": 1, "subgrid": 2}, {"sn_smooth": 1, "subgrid": 2, "closure": 1}):
-        with pytest.raises(DiffHydroError) as e:
-            dhp.Sim(dhp.default_config(n=n, box=4.0, dual_energy=1, **kw))
-        assert e.value.code == -1
     s = dhp.Sim(dhp.default_config(n=n, box=4.0, dual_energy=1, subgrid=2))
     s.init_from_noise(to_gpu(si.white_noise(n, seed=36)))
     q = s.get("q").clone()
@@ -384,7 +384,8 @@ def test_dual_closure_step_matches_oracle(dhp):
         assert rel_l2(star, ref.star.numpy()) < tol_star, bf16
 
 
-def test_dual_closure_gradient_matches_oracle_autograd(dhp):
+@pytest.mark.parametrize("smooth", [False, True])
+def test_dual_closure_gradient_matches_oracle_autograd(dhp, smooth):
     """Gradients of the flux loss through three steps at 16^3 with the learned closure on the
     dual-energy state (a few percent of the cells taking the entropy's internal energy at the
     end, most of the rest reset from the total energy every step), against oracle autograd
@@ -393,7 +394,7 @@ def test_dual_closure_gradient_matches_oracle_autograd(dhp):
     net = dhp.Mlp(seed=9)
     theta = net.weights().astype(np.float64)
     ocfg0 = osim.default_config(n=n, box=4.0, subgrid=subgrid.MODE_RELAXED, a_init=0.05,
-                                dual_energy=True)
+                                dual_energy=True, sn_smooth=smooth)
     prm = osim.Params(eps_sf=0.025, delta_c=80.0)
     w = si.white_noise(n, seed=21)
     target = (0.2 + 0.7 * np.random.default_rng(2).random((n, n, n))).astype(np.float32)
